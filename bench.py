@@ -1,0 +1,205 @@
+"""Benchmark: Mindlin + Boussinesq operator application on one MI355X.
+
+One step = one fused application strain = grad_s M[t] + grad_s N[C : eps_p]
+(every kernel of the operator path: forward x/y transforms of the 6 plastic
+strain components and of the 3 traction components, the per-mode depth
+pass, inverse y/x transforms of the 6 strain components) on the
+operator-only float64 workload 256 x 256 x 64 (lz = 0.25 L, nu = 0.3, E = 1,
+seeded Gaussian eigenstrain filtered by |k|^-2 in-plane and exp(-z/0.1 L) in
+depth, traction filtered the same way).  Inputs are resident in HBM before
+the timed region.
+
+Prints one JSON line (see the design notes for the field definitions):
+value = voxel-updates/s = nx ny nz / time per application; ``roofline`` for
+the slowest stage with its algorithmic bytes per launch and the launch time
+measured by HIP events on the library stream during the timed steps;
+``cpu_baseline`` = the FP64 oracle timed on the host cores on a sample of
+modes of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "operator-only fp64 256x256x64 (Mindlin+Boussinesq fused strain)"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nx", type=int, default=256)
+    ap.add_argument("--ny", type=int, default=256)
+    ap.add_argument("--nz", type=int, default=64)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-modes", type=int, default=768,
+                    help="modes of the oracle sample for the CPU baseline")
+    return ap.parse_args()
+
+
+def stage_bytes(nx, ny, nz, csize=16, rsize=8):
+    """Algorithmic (compulsory) bytes per launch of each stage."""
+    kxh = nx // 2 + 1
+    nm = kxh * ny
+    V = nx * ny * nz
+    p6 = 6 * nz
+    return {
+        "x_fwd": 6 * V * rsize + p6 * nm * csize,
+        "y_fwd": 2 * p6 * nm * csize,
+        "x_fwd_t": 3 * nx * ny * rsize + 3 * nm * csize,
+        "y_fwd_t": 2 * 3 * nm * csize,
+        "depth": p6 * nm * csize + 3 * nm * csize + p6 * nm * csize,
+        "y_inv": 2 * p6 * nm * csize,
+        "x_inv": p6 * nm * csize + 6 * V * rsize,
+    }
+
+
+KERNEL_OF_STAGE = {"x_fwd": "k_x_r2c", "y_fwd": "k_y_fwd", "x_fwd_t": "k_x_r2c", "y_fwd_t": "k_y_fwd",
+                   "depth": "k_depth", "y_inv": "k_y_inv", "x_inv": "k_x_c2r"}
+SOURCE_OF_STAGE = {"x_fwd": "fft.hip", "y_fwd": "fft.hip", "x_fwd_t": "fft.hip", "y_fwd_t": "fft.hip",
+                   "depth": "depth.hip", "y_inv": "fft.hip", "x_inv": "fft.hip"}
+
+
+def source_sha(name):
+    p = os.path.join(ROOT, "paper_1811_11558_amd", "csrc", name)
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(stage, nx, ny, nz, precision):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        rec = json.load(f)
+    key = "%s/%dx%dx%d/%s" % (stage, nx, ny, nz, precision)
+    r = rec.get(key)
+    if not r or r.get("source_sha") != source_sha(SOURCE_OF_STAGE[stage]):
+        return None
+    return r["bytes_per_launch"]
+
+
+def cpu_baseline(g, eps, t, nmodes_sample):
+    """The oracle, as it stands, on a sample of the in-plane modes."""
+    from oracle import operators as ora
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    nx, ny, nz = g["nx"], g["ny"], g["nz"]
+    rng = np.random.default_rng(0)
+    allm = [(ky, kx) for ky in range(ny) for kx in range(nx)]
+    pick = rng.choice(len(allm), size=min(nmodes_sample, len(allm)), replace=False)
+    modes = [allm[i] for i in sorted(pick)]
+    t0 = time.perf_counter()
+    ora.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes)
+    dt = time.perf_counter() - t0
+    t_full = dt * len(allm) / len(modes)
+    return {"value": nx * ny * nz / t_full, "unit": "voxel-updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "%d of %d in-plane modes of the same %dx%dx%d fused application (dense O(nz^2) "
+                      "depth sums per mode, full-field forward DFT included), %.1f s, extrapolated "
+                      "linearly to all modes" % (len(modes), len(allm), nx, ny, nz, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+              "(requested --gpus %d)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1811_11558_amd import Context
+    from synth import filtered_eigenstrain, filtered_traction, grid_dict
+
+    g = grid_dict(a.nx, a.ny, a.nz, 1.0, 1.0, 0.25)
+    eps_np = filtered_eigenstrain(g, seed=0, decay=0.1, max_abs=1e-3)
+    t_np = filtered_traction(g, seed=1000, max_abs=1e-2)
+    dev = torch.device("cuda:0")
+    eps = torch.from_numpy(eps_np).to(dev)
+    trac = torch.from_numpy(t_np).to(dev)
+    strain = torch.empty(eps.shape, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    ctx = Context(g, 1.0, 0.3, precision=a.precision, stream=stream)
+    out = {"strain": strain}
+    for _ in range(a.warmup):
+        ctx.operator_apply(eps, trac, out=out)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.stage_times()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        evs[i][0].record(stream)
+        ctx.operator_apply(eps, trac, out=out)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stage_times()
+    ctx.set_timing(False)
+    per = np.array([s.elapsed_time(e) for s, e in evs])
+    ms_per_step = 1e3 * wall / a.steps
+    V = a.nx * a.ny * a.nz
+    value = V / (ms_per_step * 1e-3)
+
+    csize = 16 if a.precision == "fp64" else 8
+    sb = stage_bytes(a.nx, a.ny, a.nz, csize=csize)
+    stages = {}
+    for k, (ms, n) in st.items():
+        if n:
+            avg = ms / n
+            stages[k] = {"avg_ms": round(avg, 5), "launches": n,
+                         "GBps": round(sb[k] / (avg * 1e-3) / 1e9, 1)}
+    dom = max(stages, key=lambda k: stages[k]["avg_ms"])
+    avg_s = stages[dom]["avg_ms"] * 1e-3
+    achieved = sb[dom] / avg_s / 1e9
+    traffic = measured_traffic(dom, a.nx, a.ny, a.nz, a.precision)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": KERNEL_OF_STAGE[dom], "stage": dom, "algorithmic_bytes": sb[dom],
+            "avg_launch_ms": stages[dom]["avg_ms"]}
+    total_alg = sum(sb[k] for k in stages)
+    res = {
+        "metric": "Mindlin+Boussinesq voxel-updates/s",
+        "value": value,
+        "unit": "voxel-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD if (a.nx, a.ny, a.nz, a.precision) == (256, 256, 64, "fp64") else
+                   "operator %dx%dx%d %s" % (a.nx, a.ny, a.nz, a.precision),
+                   "nx": a.nx, "ny": a.ny, "nz": a.nz, "lz": 0.25, "nu": 0.3, "precision": a.precision},
+        "p50_ms": float(np.percentile(per, 50)),
+        "p99_ms": float(np.percentile(per, 99)),
+        "operator_hbm_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "stages": stages,
+        "roofline": roof,
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(g, eps_np, t_np, a.cpu_modes)
+    ctx.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

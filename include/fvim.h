@@ -1,0 +1,226 @@
+/*
+ * fvim.h -- C ABI of the MI355X (gfx950) implementation of the Fourier-
+ * accelerated volume integral method for elastoplastic contact
+ * (Frerot, Bonnet, Molinari, Anciaux, arXiv 1811.11558).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Geometry (Sec. 1, eqn periodic_cell; Sec. 3.1): a horizontally periodic
+ * half-space cell lx x ly, depth axis z = x3 pointing INTO the body, outward
+ * surface normal n = -e3.  In-plane grid x = (j lx/nx, i ly/ny); nz depth
+ * nodes z_k = k lz/(nz-1) (both ends included).  nx and ny must be powers of
+ * two in [4, 4096]; 2 <= nz <= 512.
+ *
+ * Field layout: every field pointer is a DEVICE pointer to contiguous
+ * float64 memory owned by the caller, x fastest:
+ *   scalar  [nz][ny][nx]
+ *   tensor  [6][nz][ny][nx]   symmetric, order (11,22,33,23,13,12), tensor
+ *                             (not engineering) shear components
+ *   vector  [3][nz][ny][nx]
+ *   surface [ny][nx]          surface vector [3][ny][nx]
+ * Tractions are forces per unit area exerted ON the body at its surface
+ * (traction vector T = sigma . n of eqn traction); the contact pressure is
+ * p = T . e3 >= 0.
+ *
+ * Execution: calls are asynchronous on the context's HIP stream unless
+ * stated "blocking".  No call keeps a caller pointer after it returns.
+ * Outputs must not alias inputs (return_map may write sigma_np1 over
+ * sigma_n).  A context is used by one host thread at a time; different
+ * contexts may run concurrently on different streams.
+ *
+ * Errors: every int-returning call returns FVIM_OK (0) or a negative
+ * FVIM_E* code; on error the outputs are unspecified and no state passed by
+ * the caller is modified.  fvim_last_error() gives a thread-local message.
+ */
+#ifndef FVIM_H
+#define FVIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FVIM_OK = 0,
+  FVIM_EINVAL = -1,   /* bad argument: sizes, NULL where required, NaN input */
+  FVIM_ENOMEM = -2,   /* device allocation failed                          */
+  FVIM_EHIP = -3,     /* a HIP runtime call failed                          */
+  FVIM_ENOCONV = -4,  /* an iterative solve hit its iteration limit         */
+  FVIM_ENODEV = -5    /* no usable gfx950 device                            */
+};
+
+/* Arithmetic of the operator kernels.  FVIM_FP64: everything in float64.
+ * FVIM_FP32_REFINED: FFTs, kernel evaluation and depth recurrences in
+ * float32; boundary fields, residuals, reductions, the load constraint and
+ * the plastic-multiplier update stay float64. */
+enum { FVIM_FP64 = 0, FVIM_FP32_REFINED = 1 };
+
+/* Mean-traction (k = 0) part of the Boussinesq operator (Remark on the
+ * fundamental mode): INCLUDE adds the laterally uniform strain of the mean
+ * surface traction, EXCLUDE drops it.  The k = 0 Mindlin response is always
+ * included (it is the exact laterally uniform solution). */
+enum { FVIM_K0_INCLUDE = 0, FVIM_K0_EXCLUDE = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;
+  double lx, ly, lz;
+} fvim_grid;
+
+/* Isotropic elasticity E, nu and linear isotropic hardening
+ * f_h(e_p) = sigma_y0 + E_h e_p (Sec. 4.1). */
+typedef struct {
+  double E, nu, sigma_y0, E_h;
+} fvim_material;
+
+typedef struct fvim_ctx fvim_ctx;
+
+/* Create a context: checks the grid, builds FFT twiddle tables and
+ * allocates the device workspace lazily on first use.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Blocking. */
+int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision,
+                int k0_policy, void* hip_stream, fvim_ctx** out);
+void fvim_destroy(fvim_ctx* ctx);
+/* Replace the stream used by later calls on this context. */
+int fvim_set_stream(fvim_ctx* ctx, void* hip_stream);
+/* Device bytes a context of this grid holds at most (workspace for the
+ * fused operator with every output, plus solver state if asked).  Used by
+ * admission control. */
+size_t fvim_footprint_bytes(const fvim_grid* grid, int precision, int with_solver_state);
+const char* fvim_last_error(void);
+/* Library version string. */
+const char* fvim_version(void);
+
+/*
+ * Mindlin operator N (eqn operators, eqn N:conv; Sec. 2.1-2.3, Sec. 3):
+ * given the plastic strain eps_p (tensor field), the displacement u = N[C:eps_p]
+ * of the traction-free half-space, evaluated per in-plane Fourier mode
+ * (Thm 1) with the depth integrals of the P1-interpolated eigenstress done
+ * exactly (eqns full_discrete_convolution, int_g0, int_g1), including the
+ * local jump term (eqn jump).  Outputs (any may be NULL):
+ *   strain  = sym grad u                         tensor
+ *   stress  = C : (strain - eps_p)               tensor
+ *   disp    = u (mean of each layer set to 0)     vector
+ *   surf_u3 = u . e3 at z = 0                     surface
+ * Asynchronous.
+ */
+int mindlin_apply(fvim_ctx* ctx, const double* eps_p, double* strain, double* stress,
+                  double* disp, double* surf_u3);
+
+/*
+ * Boussinesq-Cerruti operator M (eqn operators, eqn M:conv, eqn B:fourier):
+ * the field of the half-space loaded by the surface traction t ([3][ny][nx]).
+ * Outputs as for mindlin_apply, with stress = C : strain.  The k = 0 mode
+ * follows the context's k0 policy.  Asynchronous.
+ */
+int boussinesq_apply(fvim_ctx* ctx, const double* traction, double* strain, double* stress,
+                     double* disp, double* surf_u3);
+
+/*
+ * Both operators in one pass: u = M[t] + N[C:eps_p] (eqn operators,
+ * eqn total_strain_n).  Either input may be NULL (treated as zero).  This is
+ * the operator application inside the plasticity residual.  Asynchronous.
+ */
+int fvim_operator_apply(fvim_ctx* ctx, const double* eps_p, const double* traction,
+                        double* strain, double* stress, double* disp, double* surf_u3);
+
+/*
+ * J2 return mapping with linear isotropic hardening (Sec. 4.1), backward
+ * Euler radial return, pointwise over V = nx*ny*nz voxels:
+ *   sigma_tr = sigma_n + C : d_eps;  s = dev sigma_tr;  f = sqrt(3/2)|s| -
+ *   (sigma_y0 + E_h ep_n);  if f > 0:  d_ep = f / (3 mu + E_h),
+ *   d_eps_p = (3 d_ep / (2 sqrt(3/2)|s|)) s,  else 0;
+ *   sigma_np1 = sigma_tr - 2 mu d_eps_p.
+ * d_eps, sigma_n, d_eps_p, sigma_np1: tensor fields; ep_n, d_ep: scalar
+ * fields.  sigma_np1 may be NULL or equal to sigma_n.  Asynchronous.
+ */
+int return_map(fvim_ctx* ctx, const double* d_eps, const double* sigma_n, const double* ep_n,
+               double* d_eps_p, double* d_ep, double* sigma_np1);
+
+typedef struct {
+  int iters;
+  double rel_change;      /* last dA * sum |p_k - p_(k-1)| / W                 */
+  double kkt_residual;    /* max(|gap| on the contact set, -min gap) / max|h|  */
+  double contact_fraction;
+  double mean_gap;        /* rigid approach (mean of u3 - h on the contact set) */
+} fvim_contact_info;
+
+/*
+ * Frictionless normal contact of the elastic half-space with the rigid
+ * surface h ([ny][nx], measured along +e3) under total load W (eqn
+ * total_pressure), as the Kalker dual minimisation solved by the
+ * Polonsky-Keer projected conjugate gradient (Sec. 5.1).  The compliance is
+ * u3 = M[p] . e3 at z = 0: 2 / (E* |q|) per mode, mode 0 dropped.
+ * p ([ny][nx]) is read as a warm start (all zero -> uniform W / area) and
+ * overwritten with the solution; gap (may be NULL) receives u3 - h - mean
+ * gap.  Stops when dA * sum |dp| / W < tol or max_iter is reached
+ * (FVIM_ENOCONV; p then holds the last iterate).  Blocking; info on host.
+ */
+int contact_solve(fvim_ctx* ctx, const double* h, double W, double tol, int max_iter,
+                  double* p, double* gap, fvim_contact_info* info);
+
+/* Elastoplastic state S_n kept between load steps (Sec. 4.2, Alg. 1):
+ * device pointers, caller-owned.  eps_p, sigma: tensor fields; ep: scalar
+ * field; traction: surface vector [3][ny][nx]; u3p: surface residual
+ * displacement [ny][nx] accumulated over the steps. */
+typedef struct {
+  double* eps_p;
+  double* ep;
+  double* sigma;
+  double* traction;
+  double* u3p;
+} fvim_state;
+
+typedef struct {
+  double tol_outer;    /* Alg. 1 epsilon_tol on |dU3p - dU3p_prev| / |H0|   */
+  double relax;        /* Alg. 1 lambda in ]0, 1]                            */
+  double tol_plastic;  /* DF-SANE: |R| <= tol * max(|R0|, |grad_s M[dT]|)   */
+  double tol_contact;  /* contact_solve tol                                  */
+  int max_outer, max_plastic, max_contact;
+  int solver;          /* 0 = DF-SANE (Sec. 4.3), 1 = Picard fixed point     */
+  int literal_alg1;    /* 1: the relaxed update is overwritten as printed    */
+} fvim_ep_opts;
+
+typedef struct {
+  int outer_iters, plastic_iters, contact_iters, r_evals;
+  double outer_err, plastic_res, kkt;
+} fvim_ep_info;
+
+/*
+ * Algorithm 1 (alternating contact / plasticity coupling, Sec. 5.2) over
+ * n_steps cumulative loads W_steps (host array).  Per step: contact on the
+ * modified surface h - U3p (Remark rem:modified_contact), the incremental
+ * plasticity fixed point R[d_eps] = 0 (eqn incremental_strain) solved by
+ * DF-SANE or Picard, the surface residual displacement of N[C:d_eps_p],
+ * relaxation, until the outer error is below tol_outer; then the state is
+ * updated in place.  info: host array of n_steps records.  Blocking.
+ */
+int elastoplastic_solve(fvim_ctx* ctx, const double* h, const double* W_steps, int n_steps,
+                        const fvim_ep_opts* opts, fvim_state* state, fvim_ep_info* info);
+
+/*
+ * Stage timing (profiling aid).  With timing on, every operator application
+ * records a HIP event before and after each kernel launch on the context
+ * stream.  fvim_stage_times synchronises the stream, adds the elapsed time of
+ * each stage over all applications since the last call into ms[stage] and
+ * the number of launches into count[stage] (arrays of FVIM_NSTAGES, host
+ * memory, caller-owned), then clears the record.  Stages:
+ */
+enum {
+  FVIM_STAGE_XFWD = 0,   /* x transform of the eigenstrain planes        */
+  FVIM_STAGE_YFWD = 1,   /* y transform of the eigenstrain planes        */
+  FVIM_STAGE_XFWD_T = 2, /* x transform of the traction planes           */
+  FVIM_STAGE_YFWD_T = 3, /* y transform of the traction planes           */
+  FVIM_STAGE_DEPTH = 4,  /* per-mode depth pass                          */
+  FVIM_STAGE_YINV = 5,   /* inverse y transform of the output planes     */
+  FVIM_STAGE_XINV = 6,   /* inverse x transform of the output planes     */
+  FVIM_NSTAGES = 7
+};
+int fvim_set_timing(fvim_ctx* ctx, int on);
+int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVIM_H */

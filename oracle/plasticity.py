@@ -1,0 +1,77 @@
+"""J2 plasticity and the incremental volume-integral fixed point (oracle).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+* ``return_map``: von Mises yield f_y(sigma) = sqrt(3/2)|s| (Sec. 4.1) with
+  linear isotropic hardening f_h(e_p) = sigma_y + E_h e_p, associated flow
+  d eps_p = (3 d e_p / (2 f_y)) s.  The paper gives the model, not the
+  integration algorithm; this is the backward-Euler radial return, exact for
+  linear hardening: trial stress, then if f = f_y(sigma_tr) - f_h(e_p_n) > 0
+  the consistency condition f_y(sigma_tr) - 3 mu d_ep = f_h(e_p_n + d_ep)
+  gives d_ep = f / (3 mu + E_h) along the trial deviator.
+* ``residual``: R[d_eps] = d_eps - grad_s M[dT] - grad_s N[C : d_eps_p(d_eps; S_n)]
+  (eqn incremental_strain and the residual that follows it).
+* ``dfsane``: the spectral-residual iteration of Sec. 4.3
+  (d = -alpha sigma R, sigma = |s|^2 / <y, s>) with the nonmonotone line
+  search of La Cruz, Martinez and Raydan (2006), which the paper defers to.
+
+Norms and inner products are trapezoid-in-depth weighted Frobenius sums over
+the grid (off-diagonal stored components count twice).
+"""
+import numpy as np
+
+from . import elastic
+from . import operators
+
+
+def return_map(d_eps, sigma_n, ep_n, E, nu, sigma_y0, E_h):
+    """Pointwise radial return.  d_eps, sigma_n: (6, ...); ep_n: (...).
+
+    Returns (d_eps_p, d_ep, sigma_np1) with the same shapes."""
+    lam, mu = elastic.lame(E, nu)
+    d_eps = np.asarray(d_eps, dtype=float)
+    sig_tr = np.asarray(sigma_n, dtype=float) + elastic.hooke(d_eps, E, nu)
+    mean = (sig_tr[0] + sig_tr[1] + sig_tr[2]) / 3.0
+    s = sig_tr.copy()
+    s[0] -= mean
+    s[1] -= mean
+    s[2] -= mean
+    w = elastic.VOIGT_WEIGHT.reshape((6,) + (1,) * (s.ndim - 1))
+    seq = np.sqrt(1.5 * np.sum(w * s * s, axis=0))
+    f = seq - (sigma_y0 + E_h * np.asarray(ep_n, dtype=float))
+    flow = f > 0.0
+    d_ep = np.where(flow, f / (3.0 * mu + E_h), 0.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        fac = np.where(flow, 1.5 * d_ep / seq, 0.0)
+    d_eps_p = fac * s
+    sigma_np1 = sig_tr - 2.0 * mu * d_eps_p
+    return d_eps_p, d_ep, sigma_np1
+
+
+def von_mises(sigma):
+    """f_y(sigma) = sqrt(3/2) |dev sigma| for stored components on axis 0."""
+    mean = (sigma[0] + sigma[1] + sigma[2]) / 3.0
+    s = np.array(sigma, dtype=float)
+    s[0] -= mean
+    s[1] -= mean
+    s[2] -= mean
+    w = elastic.VOIGT_WEIGHT.reshape((6,) + (1,) * (s.ndim - 1))
+    return np.sqrt(1.5 * np.sum(w * s * s, axis=0))
+
+
+def depth_weights(nz, lz):
+    """Trapezoid weights of the depth nodes."""
+    h = lz / (nz - 1)
+    w = np.full(nz, h)
+    w[0] = w[-1] = 0.5 * h
+    return w
+
+
+def inner(a, b, grid):
+    """<a, b>: Frobenius over stored components, trapezoid in depth,
+    cell area per in-plane point."""
+    nz = grid['nz']
+    wz = depth_weights(nz, grid['lz'])
+    da = grid['lx'] * grid['ly'] / (grid['nx'] * grid['ny'])
+    wc = elastic.VOIGT_WEIGHT[:, None, None, None]
+    return float(np.sum(wc * wz[None, :, None, None] * a * b) * da)

@@ -1,0 +1,302 @@
+"""ctypes binding of libfvim.so (argument marshalling only).
+
+Every function below checks the torch tensors it is given (device, dtype,
+contiguity, shape) and forwards raw device pointers to the C ABI declared in
+``include/fvim.h``; all arithmetic happens in the HIP kernels.  There is no
+fallback: if the library is missing or the tensors are not on a HIP device,
+the call raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfvim.so")
+
+FVIM_OK, FVIM_EINVAL, FVIM_ENOMEM, FVIM_EHIP, FVIM_ENOCONV, FVIM_ENODEV = 0, -1, -2, -3, -4, -5
+PRECISION = {"fp64": 0, "fp32_refined": 1}
+K0 = {"include": 0, "exclude": 1}
+
+
+class FvimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("fvim error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class _Material(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("nu", ctypes.c_double),
+                ("sigma_y0", ctypes.c_double), ("E_h", ctypes.c_double)]
+
+
+class _ContactInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_change", ctypes.c_double),
+                ("kkt_residual", ctypes.c_double), ("contact_fraction", ctypes.c_double),
+                ("mean_gap", ctypes.c_double)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("eps_p", ctypes.c_void_p), ("ep", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("traction", ctypes.c_void_p), ("u3p", ctypes.c_void_p)]
+
+
+class EPOptions(ctypes.Structure):
+    _fields_ = [("tol_outer", ctypes.c_double), ("relax", ctypes.c_double),
+                ("tol_plastic", ctypes.c_double), ("tol_contact", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("max_plastic", ctypes.c_int),
+                ("max_contact", ctypes.c_int), ("solver", ctypes.c_int),
+                ("literal_alg1", ctypes.c_int)]
+
+    def __init__(self, tol_outer=1e-9, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14,
+                 max_outer=200, max_plastic=2000, max_contact=2000, solver=0, literal_alg1=1):
+        super().__init__(tol_outer, relax, tol_plastic, tol_contact, max_outer, max_plastic,
+                         max_contact, solver, literal_alg1)
+
+
+class _EPInfo(ctypes.Structure):
+    _fields_ = [("outer_iters", ctypes.c_int), ("plastic_iters", ctypes.c_int),
+                ("contact_iters", ctypes.c_int), ("r_evals", ctypes.c_int),
+                ("outer_err", ctypes.c_double), ("plastic_res", ctypes.c_double),
+                ("kkt", ctypes.c_double)]
+
+
+_LIB = None
+_P = ctypes.c_void_p
+
+
+def load_library(path=None):
+    """Load libfvim.so once and declare the signatures."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise FvimError(FVIM_ENODEV, "%s is not built; run python -m paper_1811_11558_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    lib.fvim_create.argtypes = [ctypes.POINTER(_Grid), ctypes.POINTER(_Material), ctypes.c_int,
+                                ctypes.c_int, _P, ctypes.POINTER(_P)]
+    lib.fvim_destroy.argtypes = [_P]
+    lib.fvim_destroy.restype = None
+    lib.fvim_set_stream.argtypes = [_P, _P]
+    lib.fvim_footprint_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.c_int]
+    lib.fvim_footprint_bytes.restype = ctypes.c_size_t
+    lib.fvim_last_error.restype = ctypes.c_char_p
+    lib.fvim_version.restype = ctypes.c_char_p
+    lib.fvim_set_timing.argtypes = [_P, ctypes.c_int]
+    lib.fvim_stage_times.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.mindlin_apply.argtypes = [_P, _P, _P, _P, _P, _P]
+    lib.boussinesq_apply.argtypes = [_P, _P, _P, _P, _P, _P]
+    lib.fvim_operator_apply.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    lib.return_map.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    lib.contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P,
+                                  ctypes.POINTER(_ContactInfo)]
+    lib.elastoplastic_solve.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                        ctypes.POINTER(EPOptions), ctypes.POINTER(_State),
+                                        ctypes.POINTER(_EPInfo)]
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc != FVIM_OK:
+        msg = _LIB.fvim_last_error().decode()
+        raise FvimError(rc, msg)
+
+
+def _ptr(t, shape, name):
+    """Device pointer of a contiguous float64 tensor of the given shape."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise FvimError(FVIM_EINVAL, "%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise FvimError(FVIM_EINVAL, "%s must live on the GPU" % name)
+    if t.dtype != torch.float64:
+        raise FvimError(FVIM_EINVAL, "%s must be float64" % name)
+    if not t.is_contiguous():
+        raise FvimError(FVIM_EINVAL, "%s must be contiguous" % name)
+    if tuple(t.shape) != tuple(shape):
+        raise FvimError(FVIM_EINVAL, "%s has shape %s, expected %s" % (name, tuple(t.shape), tuple(shape)))
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    """One grid + material + precision; owns the device workspace.
+
+    grid: dict(nx, ny, nz, lx, ly, lz).  Tensors passed to the methods must be
+    float64, contiguous and on the context's device.
+    """
+
+    def __init__(self, grid, E, nu, sigma_y0=0.0, E_h=0.0, precision="fp64", k0="include",
+                 stream=None):
+        lib = load_library()
+        self.grid = dict(grid)
+        self.nx, self.ny, self.nz = int(grid["nx"]), int(grid["ny"]), int(grid["nz"])
+        self.E, self.nu, self.sigma_y0, self.E_h = float(E), float(nu), float(sigma_y0), float(E_h)
+        self._g = _Grid(self.nx, self.ny, self.nz, float(grid["lx"]), float(grid["ly"]), float(grid["lz"]))
+        self._m = _Material(self.E, self.nu, self.sigma_y0, self.E_h)
+        self._h = _P()
+        _check(lib.fvim_create(ctypes.byref(self._g), ctypes.byref(self._m), PRECISION[precision],
+                               K0[k0], _stream_handle(stream), ctypes.byref(self._h)))
+        self.precision = precision
+
+    def close(self):
+        if self._h:
+            _LIB.fvim_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv")
+
+    def set_timing(self, on=True):
+        _check(_LIB.fvim_set_timing(self._h, 1 if on else 0))
+
+    def stage_times(self):
+        """{stage: (total ms, launches)} since the last call (synchronises)."""
+        n = len(self.STAGES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(_LIB.fvim_stage_times(self._h, ms, cnt))
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(self.STAGES)}
+
+    def set_stream(self, stream):
+        _check(_LIB.fvim_set_stream(self._h, _stream_handle(stream)))
+
+    # shapes
+    @property
+    def tensor_shape(self):
+        return (6, self.nz, self.ny, self.nx)
+
+    @property
+    def vector_shape(self):
+        return (3, self.nz, self.ny, self.nx)
+
+    @property
+    def scalar_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def surface_shape(self):
+        return (self.ny, self.nx)
+
+    def _outputs(self, want, out, device):
+        shapes = {"strain": self.tensor_shape, "stress": self.tensor_shape,
+                  "disp": self.vector_shape, "surf_u3": self.surface_shape}
+        res = dict(out or {})
+        for k in want:
+            if k not in shapes:
+                raise FvimError(FVIM_EINVAL, "unknown output %r" % k)
+            if k not in res:
+                res[k] = torch.empty(shapes[k], dtype=torch.float64, device=device)
+        ptrs = [_ptr(res.get(k), shapes[k], k) for k in ("strain", "stress", "disp", "surf_u3")]
+        return res, ptrs
+
+    def operator_apply(self, eps_p=None, traction=None, want=("strain",), out=None):
+        """strain/stress/disp/surf_u3 of u = M[traction] + N[C:eps_p]."""
+        dev = (eps_p if eps_p is not None else traction).device
+        pe = _ptr(eps_p, self.tensor_shape, "eps_p")
+        pt = _ptr(traction, (3, self.ny, self.nx), "traction")
+        res, ptrs = self._outputs(want, out, dev)
+        _check(_LIB.fvim_operator_apply(self._h, pe, pt, *ptrs))
+        return res
+
+    def mindlin_apply(self, eps_p, want=("strain",), out=None):
+        pe = _ptr(eps_p, self.tensor_shape, "eps_p")
+        res, ptrs = self._outputs(want, out, eps_p.device)
+        _check(_LIB.mindlin_apply(self._h, pe, *ptrs))
+        return res
+
+    def boussinesq_apply(self, traction, want=("strain",), out=None):
+        pt = _ptr(traction, (3, self.ny, self.nx), "traction")
+        res, ptrs = self._outputs(want, out, traction.device)
+        _check(_LIB.boussinesq_apply(self._h, pt, *ptrs))
+        return res
+
+    def return_map(self, d_eps, sigma_n, ep_n, d_eps_p=None, d_ep=None, sigma_np1=None):
+        ts, ss = self.tensor_shape, self.scalar_shape
+        dev = d_eps.device
+        if d_eps_p is None:
+            d_eps_p = torch.empty(ts, dtype=torch.float64, device=dev)
+        if d_ep is None:
+            d_ep = torch.empty(ss, dtype=torch.float64, device=dev)
+        if sigma_np1 is None:
+            sigma_np1 = torch.empty(ts, dtype=torch.float64, device=dev)
+        _check(_LIB.return_map(self._h, _ptr(d_eps, ts, "d_eps"), _ptr(sigma_n, ts, "sigma_n"),
+                               _ptr(ep_n, ss, "ep_n"), _ptr(d_eps_p, ts, "d_eps_p"),
+                               _ptr(d_ep, ss, "d_ep"), _ptr(sigma_np1, ts, "sigma_np1")))
+        return d_eps_p, d_ep, sigma_np1
+
+    def contact_solve(self, h, W, tol=1e-14, max_iter=2000, p=None, want_gap=False):
+        sh = self.surface_shape
+        if p is None:
+            p = torch.zeros(sh, dtype=torch.float64, device=h.device)
+        gap = torch.empty(sh, dtype=torch.float64, device=h.device) if want_gap else None
+        info = _ContactInfo()
+        _check(_LIB.contact_solve(self._h, _ptr(h, sh, "h"), float(W), float(tol), int(max_iter),
+                                  _ptr(p, sh, "p"), _ptr(gap, sh, "gap"), ctypes.byref(info)))
+        return p, gap, contact_info_dict(info)
+
+    def new_state(self, device="cuda"):
+        z = lambda s: torch.zeros(s, dtype=torch.float64, device=device)
+        return {"eps_p": z(self.tensor_shape), "ep": z(self.scalar_shape), "sigma": z(self.tensor_shape),
+                "traction": z((3, self.ny, self.nx)), "u3p": z(self.surface_shape)}
+
+    def elastoplastic_solve(self, h, W_steps, state, opts=None):
+        """Algorithm 1 over the cumulative loads W_steps; state updated in place."""
+        opts = opts or EPOptions()
+        ts, ss, sf = self.tensor_shape, self.scalar_shape, self.surface_shape
+        st = _State(_ptr(state["eps_p"], ts, "eps_p"), _ptr(state["ep"], ss, "ep"),
+                    _ptr(state["sigma"], ts, "sigma"), _ptr(state["traction"], (3,) + sf, "traction"),
+                    _ptr(state["u3p"], sf, "u3p"))
+        n = len(W_steps)
+        ws = (ctypes.c_double * n)(*[float(w) for w in W_steps])
+        infos = (_EPInfo * n)()
+        _check(_LIB.elastoplastic_solve(self._h, _ptr(h, sf, "h"), ws, n, ctypes.byref(opts),
+                                        ctypes.byref(st), infos))
+        return [{f: getattr(i, f) for f, _ in _EPInfo._fields_} for i in infos]
+
+
+def contact_info_dict(info):
+    return {f: getattr(info, f) for f, _ in _ContactInfo._fields_}
+
+
+# module-level functions with the C names
+def mindlin_apply(ctx, eps_p, **kw):
+    return ctx.mindlin_apply(eps_p, **kw)
+
+
+def boussinesq_apply(ctx, traction, **kw):
+    return ctx.boussinesq_apply(traction, **kw)
+
+
+def operator_apply(ctx, eps_p=None, traction=None, **kw):
+    return ctx.operator_apply(eps_p, traction, **kw)
+
+
+def return_map(ctx, d_eps, sigma_n, ep_n, **kw):
+    return ctx.return_map(d_eps, sigma_n, ep_n, **kw)
+
+
+def contact_solve(ctx, h, W, **kw):
+    return ctx.contact_solve(h, W, **kw)
+
+
+def elastoplastic_solve(ctx, h, W_steps, state, opts=None):
+    return ctx.elastoplastic_solve(h, W_steps, state, opts)

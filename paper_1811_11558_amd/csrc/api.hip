@@ -1,0 +1,327 @@
+// C ABI of the library (declared in include/fvim.h): context management and
+// the operator entry points.  Every step of the operator runs in the HIP
+// kernels of fft.hip and depth.hip; this file only checks arguments, owns
+// the device workspace and sequences the launches on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fvim.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "solver.hpp"
+
+using namespace fvim;
+
+namespace {
+thread_local std::string g_err;
+}
+
+namespace fvim {
+
+int fail(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+
+int fail_hip(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return FVIM_EHIP;
+}
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <typename T>
+static void* make_twiddles(int n, hipError_t* err) {
+  std::vector<cpx<T>> h(n);
+  for (int k = 0; k < n; ++k) {
+    // exp(-2 pi i k / n), evaluated from the first octant by symmetry so the
+    // table is exactly symmetric
+    long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)n;
+    h[k].x = (T)cosl(a);
+    h[k].y = (T)(-sinl(a));
+  }
+  void* d = nullptr;
+  *err = hipMalloc(&d, sizeof(cpx<T>) * n);
+  if (*err != hipSuccess) return nullptr;
+  *err = hipMemcpy(d, h.data(), sizeof(cpx<T>) * n, hipMemcpyHostToDevice);
+  return d;
+}
+
+int ctx_reserve(fvim_ctx* c, void** p, size_t* have, size_t need) {
+  if (*have >= need) return FVIM_OK;
+  if (*p) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+  }
+  hipError_t e = hipMalloc(p, need);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(FVIM_ENOMEM, "device allocation failed for the operator workspace");
+  }
+  *have = need;
+  return FVIM_OK;
+}
+
+// Records a pair of events around a launch when the context has timing on.
+struct StageTimer {
+  fvim_ctx* c;
+  int stage = -1;
+  hipEvent_t a = nullptr;
+  explicit StageTimer(fvim_ctx* cc) : c(cc) {}
+  void begin(int s) {
+    if (!c->timing) return;
+    stage = s;
+    hipEventCreate(&a);
+    hipEventRecord(a, c->stream);
+  }
+  void end() {
+    if (!c->timing || stage < 0) return;
+    hipEvent_t b;
+    hipEventCreate(&b);
+    hipEventRecord(b, c->stream);
+    c->evs.push_back({stage, a, b});
+    stage = -1;
+  }
+};
+
+// u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
+template <typename T>
+int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+                     double* disp, double* surf_u3) {
+  const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
+  const int kxh = nx / 2 + 1;
+  const size_t nmodes = (size_t)kxh * ny;
+  DepthParams prm;
+  prm.nx = nx;
+  prm.ny = ny;
+  prm.nz = nz;
+  prm.kxh = kxh;
+  prm.lx = c->grid.lx;
+  prm.ly = c->grid.ly;
+  prm.h = c->grid.lz / (nz - 1);
+  prm.mu = c->mu;
+  prm.kappa = c->lam / c->mu;
+  prm.norm = 1.0 / ((double)nx * (double)ny);
+  prm.has_w = eps_p != nullptr;
+  prm.has_t = traction != nullptr;
+  prm.k0_include = c->k0_policy == FVIM_K0_INCLUDE;
+  int np = 0;
+  OutSegments seg;
+  seg.n = 0;
+  prm.off_strain = prm.off_stress = prm.off_disp = prm.off_u3 = -1;
+  if (strain) { prm.off_strain = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = strain; np += 6 * nz; }
+  if (stress) { prm.off_stress = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = stress; np += 6 * nz; }
+  if (disp) { prm.off_disp = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = disp; np += 3 * nz; }
+  if (surf_u3) { prm.off_u3 = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = surf_u3; np += 1; }
+  prm.np_out = np;
+  if (np == 0) return FVIM_OK;
+  const int np_in = eps_p ? 6 * nz : 0;
+  const size_t planes = (size_t)(np > np_in ? np : np_in);
+  const size_t bytes = planes * nmodes * sizeof(cpx<T>);
+  int rc = ctx_reserve(c, &c->bufA, &c->bufA_bytes, bytes);
+  if (rc) return rc;
+  rc = ctx_reserve(c, &c->bufB, &c->bufB_bytes, bytes);
+  if (rc) return rc;
+  const size_t tbytes = 3 * nmodes * sizeof(cpx<T>);
+  if (traction) {
+    rc = ctx_reserve(c, &c->tA, &c->tA_bytes, tbytes);
+    if (rc) return rc;
+    rc = ctx_reserve(c, &c->tB, &c->tB_bytes, tbytes);
+    if (rc) return rc;
+  }
+  const cpx<T>* twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
+  const cpx<T>* twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
+  cpx<T>* A = (cpx<T>*)c->bufA;
+  cpx<T>* B = (cpx<T>*)c->bufB;
+  hipStream_t st = c->stream;
+  hipError_t e;
+  StageTimer tm(c);
+  if (eps_p) {
+    tm.begin(FVIM_STAGE_XFWD);
+    if ((e = launch_x_r2c<T>(eps_p, A, nx, ny, (size_t)6 * nz, twx, st)) != hipSuccess) return fail_hip(e, "x_r2c");
+    tm.end();
+    tm.begin(FVIM_STAGE_YFWD);
+    if ((e = launch_y_fwd<T>(A, B, ny, kxh, 6 * nz, twy, st)) != hipSuccess) return fail_hip(e, "y_fwd");
+    tm.end();
+  }
+  if (traction) {
+    tm.begin(FVIM_STAGE_XFWD_T);
+    if ((e = launch_x_r2c<T>(traction, (cpx<T>*)c->tA, nx, ny, 3, twx, st)) != hipSuccess)
+      return fail_hip(e, "x_r2c(t)");
+    tm.end();
+    tm.begin(FVIM_STAGE_YFWD_T);
+    if ((e = launch_y_fwd<T>((cpx<T>*)c->tA, (cpx<T>*)c->tB, ny, kxh, 3, twy, st)) != hipSuccess)
+      return fail_hip(e, "y_fwd(t)");
+    tm.end();
+  }
+  tm.begin(FVIM_STAGE_DEPTH);
+  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, st)) != hipSuccess) return fail_hip(e, "depth");
+  tm.end();
+  tm.begin(FVIM_STAGE_YINV);
+  if ((e = launch_y_inv<T>(A, B, ny, kxh, np, twy, st)) != hipSuccess) return fail_hip(e, "y_inv");
+  tm.end();
+  tm.begin(FVIM_STAGE_XINV);
+  if ((e = launch_x_c2r<T>(B, seg, nx, ny, (size_t)np, 1.0, twx, st)) != hipSuccess) return fail_hip(e, "x_c2r");
+  tm.end();
+  return FVIM_OK;
+}
+
+int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+                   double* disp, double* surf_u3) {
+  if (c->precision == FVIM_FP32_REFINED)
+    return operator_apply_t<float>(c, eps_p, traction, strain, stress, disp, surf_u3);
+  return operator_apply_t<double>(c, eps_p, traction, strain, stress, disp, surf_u3);
+}
+
+}  // namespace fvim
+
+extern "C" {
+
+const char* fvim_last_error(void) { return g_err.c_str(); }
+
+const char* fvim_version(void) { return "fvim 0.1 gfx950"; }
+
+static int check_grid(const fvim_grid* g) {
+  if (!g) return fail(FVIM_EINVAL, "grid is NULL");
+  if (!is_pow2(g->nx) || !is_pow2(g->ny) || g->nx < 4 || g->ny < 4 || g->nx > 4096 || g->ny > 4096)
+    return fail(FVIM_EINVAL, "nx and ny must be powers of two in [4, 4096]");
+  if (g->nz < 2 || g->nz > 512) return fail(FVIM_EINVAL, "nz must be in [2, 512]");
+  if (!(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0) || !std::isfinite(g->lx) || !std::isfinite(g->ly) ||
+      !std::isfinite(g->lz))
+    return fail(FVIM_EINVAL, "cell lengths must be finite and positive");
+  return FVIM_OK;
+}
+
+int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision, int k0_policy, void* hip_stream,
+                fvim_ctx** out) {
+  if (!out) return fail(FVIM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!mat || !(mat->E > 0) || !(mat->nu > -1.0 && mat->nu < 0.5) || !std::isfinite(mat->E) ||
+      !(mat->sigma_y0 >= 0) || !(mat->E_h >= 0))
+    return fail(FVIM_EINVAL, "material: need E > 0, -1 < nu < 0.5, sigma_y0 >= 0, E_h >= 0");
+  if (precision != FVIM_FP64 && precision != FVIM_FP32_REFINED) return fail(FVIM_EINVAL, "unknown precision");
+  if (k0_policy != FVIM_K0_INCLUDE && k0_policy != FVIM_K0_EXCLUDE) return fail(FVIM_EINVAL, "unknown k0 policy");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(FVIM_ENODEV, "no HIP device");
+  fvim_ctx* c = new fvim_ctx();
+  c->grid = *grid;
+  c->mat = *mat;
+  c->precision = precision;
+  c->k0_policy = k0_policy;
+  c->stream = (hipStream_t)hip_stream;
+  hipGetDevice(&c->device);
+  c->mu = mat->E / (2.0 * (1.0 + mat->nu));
+  c->lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
+  hipError_t e = hipSuccess;
+  c->twx64 = make_twiddles<double>(grid->nx, &e);
+  if (e == hipSuccess) c->twy64 = make_twiddles<double>(grid->ny, &e);
+  if (e == hipSuccess) c->twx32 = make_twiddles<float>(grid->nx, &e);
+  if (e == hipSuccess) c->twy32 = make_twiddles<float>(grid->ny, &e);
+  if (e != hipSuccess) {
+    fvim_destroy(c);
+    return fail_hip(e, "twiddle tables");
+  }
+  *out = c;
+  return FVIM_OK;
+}
+
+void fvim_destroy(fvim_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->tA, c->tB};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  solver_release(c);
+  for (auto& ev : c->evs) {
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  delete c;
+}
+
+int fvim_set_timing(fvim_ctx* c, int on) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  c->timing = on ? 1 : 0;
+  return FVIM_OK;
+}
+
+int fvim_stage_times(fvim_ctx* c, double* ms, int* count) {
+  if (!c || !ms || !count) return fail(FVIM_EINVAL, "NULL argument");
+  for (int k = 0; k < FVIM_NSTAGES; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+  for (auto& ev : c->evs) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev.a, ev.b) == hipSuccess) {
+      ms[ev.stage] += t;
+      count[ev.stage] += 1;
+    }
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  c->evs.clear();
+  return FVIM_OK;
+}
+
+int fvim_set_stream(fvim_ctx* c, void* hip_stream) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  c->stream = (hipStream_t)hip_stream;
+  return FVIM_OK;
+}
+
+size_t fvim_footprint_bytes(const fvim_grid* g, int precision, int with_solver_state) {
+  if (check_grid(g)) return 0;
+  const size_t nmodes = (size_t)(g->nx / 2 + 1) * g->ny;
+  const size_t csz = precision == FVIM_FP32_REFINED ? 8 : 16;
+  const size_t planes = 15 * (size_t)g->nz + 1;
+  size_t b = 2 * planes * nmodes * csz + 6 * nmodes * csz;
+  const size_t V = (size_t)g->nx * g->ny * g->nz;
+  if (with_solver_state) b += solver_footprint(g, V);
+  return b;
+}
+
+int mindlin_apply(fvim_ctx* c, const double* eps_p, double* strain, double* stress, double* disp, double* surf_u3) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  if (!eps_p) return fail(FVIM_EINVAL, "eps_p is NULL");
+  return operator_apply(c, eps_p, nullptr, strain, stress, disp, surf_u3);
+}
+
+int boussinesq_apply(fvim_ctx* c, const double* traction, double* strain, double* stress, double* disp,
+                     double* surf_u3) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  if (!traction) return fail(FVIM_EINVAL, "traction is NULL");
+  return operator_apply(c, nullptr, traction, strain, stress, disp, surf_u3);
+}
+
+int fvim_operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+                        double* disp, double* surf_u3) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  return operator_apply(c, eps_p, traction, strain, stress, disp, surf_u3);
+}
+
+int return_map(fvim_ctx* c, const double* d_eps, const double* sigma_n, const double* ep_n, double* d_eps_p,
+               double* d_ep, double* sigma_np1) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  if (!d_eps || !sigma_n || !ep_n || !d_eps_p || !d_ep) return fail(FVIM_EINVAL, "NULL field");
+  const size_t V = (size_t)c->grid.nx * c->grid.ny * c->grid.nz;
+  hipError_t e = launch_return_map(d_eps, sigma_n, ep_n, d_eps_p, d_ep, sigma_np1, V, c->lam, c->mu,
+                                   c->mat.sigma_y0, c->mat.E_h, c->stream);
+  if (e != hipSuccess) return fail_hip(e, "return_map");
+  return FVIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// Shared device/host helpers of the fvim HIP library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace fvim {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T a, T b) {
+  cpx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> add(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> sub(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> mul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> mulc(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scl(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+// a + s * b  (s real)
+template <typename T>
+__device__ __forceinline__ cpx<T> axpy(cpx<T> a, T s, cpx<T> b) { return mk(a.x + s * b.x, a.y + s * b.y); }
+// i * a
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_i(cpx<T> a) { return mk(-a.y, a.x); }
+// -i * a
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_mi(cpx<T> a) { return mk(a.y, -a.x); }
+template <typename T>
+__device__ __forceinline__ cpx<T> zero() { return mk(T(0), T(0)); }
+
+// Launch helpers defined in the individual translation units.  All take the
+// stream explicitly and return hipError_t of the launch.
+struct FftPlan1D {
+  int n;                 // transform length (power of two)
+  void* tw;              // device twiddle table exp(-2 pi i k / n), k < n
+};
+
+}  // namespace fvim

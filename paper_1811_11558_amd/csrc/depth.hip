@@ -1,0 +1,463 @@
+// Per-mode depth pass of the Mindlin + Boussinesq operators (gfx950).
+//
+// For one in-plane mode exp(i q.x) the response of the half-space to the
+// P1-interpolated eigenstress w = C : eps_p (Sec. 3.2) and to a surface
+// traction t is the decaying solution of a 1D linear system in the depth
+// variable Z = |q| z.  In the frame (n = q/|q|, t = e3 x n, e3) it splits
+// into an in-plane part (u_n, u_z, tractions sigma_nz, sigma_zz) and an
+// antiplane part (u_t, sigma_tz); quantities with an odd number of n indices
+// carry a factor i, so all coefficients are real.  Scaled by 1/mu and with
+// a = |q| u_n / i, c = |q| u_z, t1 = sigma_nz / (i mu), t2 = sigma_zz / mu,
+// kappa = lambda / mu, omega = w / mu:
+//   a'  = -c + t1 + omega_nz/i
+//   c'  = (kappa a + t2 + omega_zz) / (kappa + 2)
+//   t1' = 4 (kappa+1)/(kappa+2) a - kappa/(kappa+2) (t2 + omega_zz) + omega_nn
+//   t2' = t1
+// and v = |q| u_t, t3 = sigma_tz / mu:  v' = t3 + omega_tz,  t3' = v - omega_nt/i.
+// The in-plane matrix has the Jordan form diag(J(-1), J(+1)) with 2x2 blocks
+// J(l) = [[l, 1], [0, l]]; the antiplane one has eigenvalues -1, +1.  So the
+// solution is carried by two decaying and two growing modal coordinates
+// (plus one of each antiplane):
+//   * growing ones vanish below the last node and are integrated upward
+//     (a backward scan over depth),
+//   * the decaying ones start from the surface condition
+//     sigma . e3 = -t at z = 0 (total stress; traction-free surface for the
+//     eigenstress part, Sec. 2.1) and are integrated downward (a forward scan).
+// Over an element of scaled length s = |q| h the exact propagators are
+// exp(-s) [[1, +/-s], [0, 1]] and the P1 load enters through four functions
+// of s (G0, G0', H0, H0' below), so the per-mode kernel is built on the fly
+// and the depth work is O(nz) with no cutoff.  This is mathematically the
+// paper's Green's-function sum (Kelvin part, jump term, Boussinesq image),
+// organised as recurrences instead of element-pair integrals.
+//
+// Threads: LPM lanes per mode, P consecutive depth nodes per lane; the
+// recurrences run sequentially inside a lane and as Kogge-Stone scans across
+// the LPM lanes (log2(LPM) shuffle steps).  Input and output are mode-major,
+// so the nz values of one component of one mode are contiguous.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fvim {
+namespace {
+
+constexpr int NT = 256;
+
+// Taylor coefficients of the element functions, divided by the power of s
+// that multiplies them:
+//   G0  = s   int_0^1 (1-t) e^{-st} dt,   G0' = s   int_0^1 t e^{-st} dt,
+//   H0  = s^2 int_0^1 t(1-t) e^{-st} dt,  H0' = s^2 int_0^1 t^2 e^{-st} dt.
+constexpr double inv_fact(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return 1.0 / f;
+}
+constexpr double sgn(int k) { return (k & 1) ? -1.0 : 1.0; }
+constexpr double ca(int k) { return sgn(k) * inv_fact(k) / ((k + 1.0) * (k + 2.0)); }
+constexpr double cb(int k) { return sgn(k) * inv_fact(k) / (k + 2.0); }
+constexpr double cc(int k) { return sgn(k) * inv_fact(k) / ((k + 2.0) * (k + 3.0)); }
+constexpr double cd(int k) { return sgn(k) * inv_fact(k) / (k + 3.0); }
+
+template <typename T>
+struct Terms {
+  static constexpr int n = 26;
+};
+template <>
+struct Terms<float> {
+  static constexpr int n = 16;
+};
+
+template <typename T>
+__device__ __forceinline__ void elem_coeffs(T s, T& G0, T& G0p, T& H0, T& H0p) {
+  if (s < T(2)) {
+    constexpr int N = Terms<T>::n;
+    T a = (T)ca(N - 1), b = (T)cb(N - 1), c = (T)cc(N - 1), d = (T)cd(N - 1);
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) {
+      a = a * s + (T)ca(k);
+      b = b * s + (T)cb(k);
+      c = c * s + (T)cc(k);
+      d = d * s + (T)cd(k);
+    }
+    G0 = s * a;
+    G0p = s * b;
+    H0 = s * s * c;
+    H0p = s * s * d;
+  } else {
+    T e = exp(-s);
+    T I0 = T(1) - e;
+    T I1 = T(1) - e * (T(1) + s);
+    T I2 = T(2) - e * (T(2) + s * (T(2) + s));
+    T is = T(1) / s;
+    G0 = I0 - I1 * is;
+    G0p = I1 * is;
+    H0 = I1 - I2 * is;
+    H0p = I2 * is;
+  }
+}
+
+template <typename T, int LPM>
+__device__ __forceinline__ cpx<T> sh_down(cpx<T> v, int d) {
+  return mk(__shfl_down(v.x, d, LPM), __shfl_down(v.y, d, LPM));
+}
+template <typename T, int LPM>
+__device__ __forceinline__ cpx<T> sh_up(cpx<T> v, int d) {
+  return mk(__shfl_up(v.x, d, LPM), __shfl_up(v.y, d, LPM));
+}
+template <typename T, int LPM>
+__device__ __forceinline__ cpx<T> sh_idx(cpx<T> v, int src) {
+  return mk(__shfl(v.x, src, LPM), __shfl(v.y, src, LPM));
+}
+
+// Modal loads of one node from the rotated eigenstress/mu (in-plane part
+// (f0, f1) decaying, (f2, f3) growing; antiplane fm decaying, fp growing).
+template <typename T>
+struct Loads {
+  cpx<T> f0, f1, f2, f3, fm, fp;
+};
+
+template <typename T>
+__device__ __forceinline__ Loads<T> modal_loads(const cpx<T> o[5], T kap) {
+  // o = (omega_nn, omega_zz, omega_nz / i, omega_nt / i, omega_tz)
+  const T kp2 = kap + T(2);
+  const T kk = (kap + T(1)) / kp2;
+  const T i2k4 = T(1) / (T(2) * kp2);
+  cpx<T> ec = scl(o[1], T(1) / kp2);
+  cpx<T> et1 = sub(o[0], scl(o[1], kap / kp2));
+  Loads<T> L;
+  L.f0 = sub(scl(ec, -kk), scl(et1, i2k4));
+  L.f1 = axpy(sub(scl(o[2], -kk), scl(ec, kk)), T(0.5) * kk, et1);
+  L.f2 = axpy(scl(ec, kk), i2k4, et1);
+  L.f3 = axpy(sub(scl(o[2], kk), scl(ec, kk)), T(0.5) * kk, et1);
+  L.fm = scl(add(o[4], o[3]), T(0.5));
+  L.fp = scl(sub(o[4], o[3]), T(0.5));
+  return L;
+}
+
+template <typename T>
+__device__ __forceinline__ void put(cpx<T>* __restrict__ dst, cpx<T> v, bool first) {
+  if (!first) v = add(v, *dst);
+  *dst = v;
+}
+
+template <typename T, int LPM, int P, bool DISP>
+__global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, const cpx<T>* __restrict__ tin,
+                                             cpx<T>* __restrict__ out, DepthParams prm) {
+  constexpr int GPB = NT / LPM;
+  const int g = threadIdx.x / LPM;
+  const int l = threadIdx.x - g * LPM;
+  const int nmodes = prm.kxh * prm.ny;
+  const int mode = blockIdx.x * GPB + g;
+  if (mode >= nmodes) return;                 // the whole lane group leaves together
+  const int nz = prm.nz;
+  const int kx = mode / prm.ny;
+  const int ky = mode - kx * prm.ny;
+  const cpx<T>* __restrict__ src = in + (size_t)mode * 6 * nz;
+  cpx<T>* __restrict__ dst = out + (size_t)mode * prm.np_out;
+  const T nrm = (T)prm.norm;
+  const T kap = (T)prm.kappa;
+  const T mu = (T)prm.mu;
+  const T kp2 = kap + T(2);
+  const int i0 = l * P;
+  const bool wantS = prm.off_strain >= 0, wantX = prm.off_stress >= 0;
+
+  cpx<T> tr[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) tr[c] = prm.has_t ? scl(tin[(size_t)mode * 3 + c], nrm / mu) : zero<T>();
+
+  // strain e (original frame, 6 comps) of node i -> outputs (stress needs eps_p again)
+  auto emit = [&](int i, const cpx<T> e[6], bool first, T wgt) {
+    if (wantS) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) put(dst + prm.off_strain + (size_t)c * nz + i, scl(e[c], wgt), first);
+    }
+    if (wantX) {
+      cpx<T> ep[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? scl(src[(size_t)c * nz + i], nrm) : zero<T>();
+      cpx<T> tre = add(add(e[0], e[1]), e[2]);
+      cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        cpx<T> sc = scl(sub(e[c], ep[c]), T(2) * mu);
+        if (c < 3) sc = axpy(sc, kap * mu, sub(tre, trp));
+        put(dst + prm.off_stress + (size_t)c * nz + i, scl(sc, wgt), first);
+      }
+    }
+  };
+
+  if (kx == 0 && ky == 0) {
+    // laterally uniform mode: sigma . e3 = -t everywhere, no in-plane strain
+    const T tk = prm.k0_include ? T(1) : T(0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = i0 + p;
+      if (i >= nz) continue;
+      cpx<T> ep[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? src[(size_t)c * nz + i] : zero<T>();
+      cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
+      cpx<T> w33 = scl(axpy(scl(trp, kap), T(2), ep[2]), nrm);     // w33 / mu
+      cpx<T> e[6] = {zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>()};
+      e[4] = sub(scl(ep[4], nrm), scl(tr[0], T(0.5) * tk));        // e13
+      e[3] = sub(scl(ep[3], nrm), scl(tr[1], T(0.5) * tk));        // e23
+      e[2] = scl(sub(w33, scl(tr[2], tk)), T(1) / kp2);             // e33
+      emit(i, e, true, T(1));
+      if (DISP) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          if (prm.off_disp >= 0) dst[prm.off_disp + (size_t)c * nz + i] = zero<T>();
+        if (prm.off_u3 >= 0 && i == 0) dst[prm.off_u3] = zero<T>();
+      }
+    }
+    return;
+  }
+
+  const int nyqx = (kx * 2 == prm.nx);
+  const int nyqy = (ky * 2 == prm.ny);
+  const int nrep = (nyqx ? 2 : 1) * (nyqy ? 2 : 1);
+  const int k1 = kx;
+  const int k2 = (ky * 2 <= prm.ny) ? ky : ky - prm.ny;
+  const T wrep = T(1) / (T)nrep;
+  const T cfac = kp2 / (T(2) * (kap + T(1)));
+  const T ik2 = T(1) / (T(2) * kap + T(2));
+  // |q| and everything built from it are the same for every sign replica
+  const double twopi = 6.283185307179586476925286766559;
+  const T q1a = (T)(twopi * k1 / prm.lx);
+  const T q2a = (T)(twopi * k2 / prm.ly);
+  const T q = sqrt(q1a * q1a + q2a * q2a);
+  const T iq = T(1) / q;
+  const T s = q * (T)prm.h;
+  const T r = exp(-s);
+  const T rP = exp(-(T)P * s);
+  T G0, G0p, H0, H0p;
+  elem_coeffs<T>(s, G0, G0p, H0, H0p);
+
+  for (int rep = 0; rep < nrep; ++rep) {
+    int bits = rep;
+    T s1 = T(1), s2 = T(1);
+    if (nyqx) { s1 = (bits & 1) ? T(-1) : T(1); bits >>= 1; }
+    if (nyqy) { s2 = (bits & 1) ? T(-1) : T(1); }
+    const T n1 = s1 * q1a * iq, n2 = s2 * q2a * iq;
+
+    // ---- load, rotate, scale: o = (w_nn, w_zz, w_nz/i, w_nt/i, w_tz) / mu ----
+    cpx<T> o[P][5];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int i = i0 + p;
+      cpx<T> ep[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ep[c] = (prm.has_w && i < nz) ? src[(size_t)c * nz + i] : zero<T>();
+      cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
+      cpx<T> exx = add(add(scl(ep[0], n1 * n1), scl(ep[5], T(2) * n1 * n2)), scl(ep[1], n2 * n2));
+      cpx<T> exe = add(add(scl(ep[0], -n1 * n2), scl(ep[5], n1 * n1 - n2 * n2)), scl(ep[1], n1 * n2));
+      cpx<T> exz = add(scl(ep[4], n1), scl(ep[3], n2));
+      cpx<T> eez = sub(scl(ep[3], n1), scl(ep[4], n2));
+      o[p][0] = scl(axpy(scl(trp, kap), T(2), exx), nrm);
+      o[p][1] = scl(axpy(scl(trp, kap), T(2), ep[2]), nrm);
+      o[p][2] = scl(mul_mi(exz), T(2) * nrm);
+      o[p][3] = scl(mul_mi(exe), T(2) * nrm);
+      o[p][4] = scl(eez, T(2) * nrm);
+    }
+    // rotated loads of the next lane's first node (zero past the last node)
+    cpx<T> on[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) on[c] = sh_down<T, LPM>(o[0][c], 1);
+
+    // ---- backward (growing) recurrence inside the lane, zero carry ----
+    cpx<T> M2[P], M3[P], MP[P];
+    {
+      cpx<T> x2 = zero<T>(), x3 = zero<T>(), xp = zero<T>();
+      Loads<T> Ln = modal_loads<T>(on, kap);
+#pragma unroll
+      for (int p = P - 1; p >= 0; --p) {
+        const int e = i0 + p;                    // element e joins nodes e, e+1
+        Loads<T> L = modal_loads<T>(o[p], kap);
+        cpx<T> b2 = zero<T>(), b3 = zero<T>(), bp = zero<T>();
+        if (e + 1 < nz) {
+          b3 = add(scl(L.f3, G0), scl(Ln.f3, G0p));
+          b2 = sub(add(scl(L.f2, G0), scl(Ln.f2, G0p)), add(scl(L.f3, H0), scl(Ln.f3, H0p)));
+          bp = add(scl(L.fp, G0), scl(Ln.fp, G0p));
+        }
+        x2 = sub(scl(axpy(x2, -s, x3), r), b2);
+        x3 = sub(scl(x3, r), b3);
+        xp = sub(scl(xp, r), bp);
+        M2[p] = x2;
+        M3[p] = x3;
+        MP[p] = xp;
+        Ln = L;
+      }
+    }
+    // ---- reverse scan across lanes: Y_l = A_l + Rb^P Y_(l+1) ----
+    cpx<T> Y2 = M2[0], Y3 = M3[0], YP = MP[0];
+    {
+      T rk = rP, ks = (T)P * s;
+#pragma unroll
+      for (int d = 1; d < LPM; d <<= 1) {
+        cpx<T> o2 = sh_down<T, LPM>(Y2, d), o3 = sh_down<T, LPM>(Y3, d), op = sh_down<T, LPM>(YP, d);
+        if (l + d < LPM) {
+          Y2 = add(Y2, scl(axpy(o2, -ks, o3), rk));
+          Y3 = add(Y3, scl(o3, rk));
+          YP = add(YP, scl(op, rk));
+        }
+        rk = rk * rk;
+        ks = ks + ks;
+      }
+    }
+    {
+      cpx<T> C2 = sh_down<T, LPM>(Y2, 1), C3 = sh_down<T, LPM>(Y3, 1), CP = sh_down<T, LPM>(YP, 1);
+      if (l == LPM - 1) { C2 = zero<T>(); C3 = zero<T>(); CP = zero<T>(); }
+      T rk = r, ks = s;            // Rb^(P-p) applied to the carry, p from P-1 down
+#pragma unroll
+      for (int p = P - 1; p >= 0; --p) {
+        M2[p] = add(M2[p], scl(axpy(C2, -ks, C3), rk));
+        M3[p] = add(M3[p], scl(C3, rk));
+        MP[p] = add(MP[p], scl(CP, rk));
+        rk = rk * r;
+        ks = ks + s;
+      }
+    }
+    // ---- surface condition: sigma . e3 = -t at z = 0 ----
+    cpx<T> bc0, bc1, bcm;
+    {
+      cpx<T> g20 = sh_idx<T, LPM>(M2[0], 0), g30 = sh_idx<T, LPM>(M3[0], 0), gp0 = sh_idx<T, LPM>(MP[0], 0);
+      cpx<T> Txi = add(scl(tr[0], n1), scl(tr[1], n2));
+      cpx<T> t1bc = mul_i(Txi);                          // -(T_n / i) = i T_n
+      cpx<T> t2bc = scl(tr[2], T(-1));
+      cpx<T> t3bc = sub(scl(tr[0], n2), scl(tr[1], n1)); // -T_t
+      bc0 = sub(t2bc, g20);
+      bc1 = sub(sub(add(t1bc, bc0), g20), g30);
+      bcm = sub(gp0, t3bc);
+    }
+    // ---- forward (decaying) recurrence inside the lane, zero carry ----
+    cpx<T> Z0[P], Z1[P], ZM[P];
+    cpx<T> F0, F1, FM;
+    {
+      cpx<T> z0 = zero<T>(), z1 = zero<T>(), zm = zero<T>();
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        Z0[p] = z0;
+        Z1[p] = z1;
+        ZM[p] = zm;
+        const int e = i0 + p;
+        cpx<T> a0 = zero<T>(), a1 = zero<T>(), am = zero<T>();
+        if (e + 1 < nz) {
+          Loads<T> L = modal_loads<T>(o[p], kap);
+          Loads<T> Ln = modal_loads<T>(p + 1 < P ? o[(p + 1) % P] : on, kap);
+          a1 = add(scl(L.f1, G0p), scl(Ln.f1, G0));
+          a0 = add(add(scl(L.f0, G0p), scl(Ln.f0, G0)), add(scl(L.f1, H0p), scl(Ln.f1, H0)));
+          am = add(scl(L.fm, G0p), scl(Ln.fm, G0));
+        }
+        z0 = add(scl(axpy(z0, s, z1), r), a0);
+        z1 = add(scl(z1, r), a1);
+        zm = add(scl(zm, r), am);
+      }
+      F0 = z0;
+      F1 = z1;
+      FM = zm;
+    }
+    // ---- forward scan across lanes with the surface value on lane 0 ----
+    if (l == 0) {
+      T ps = (T)P * s;
+      F0 = add(F0, scl(axpy(bc0, ps, bc1), rP));
+      F1 = add(F1, scl(bc1, rP));
+      FM = add(FM, scl(bcm, rP));
+    }
+    {
+      T rk = rP, ks = (T)P * s;
+#pragma unroll
+      for (int d = 1; d < LPM; d <<= 1) {
+        cpx<T> o0 = sh_up<T, LPM>(F0, d), o1 = sh_up<T, LPM>(F1, d), om = sh_up<T, LPM>(FM, d);
+        if (l >= d) {
+          F0 = add(F0, scl(axpy(o0, ks, o1), rk));
+          F1 = add(F1, scl(o1, rk));
+          FM = add(FM, scl(om, rk));
+        }
+        rk = rk * rk;
+        ks = ks + ks;
+      }
+    }
+    cpx<T> D0 = sh_up<T, LPM>(F0, 1), D1 = sh_up<T, LPM>(F1, 1), DM = sh_up<T, LPM>(FM, 1);
+    if (l == 0) { D0 = bc0; D1 = bc1; DM = bcm; }
+
+    // ---- nodal fields, strains, outputs ----
+    {
+      T rk = T(1), ks = T(0);
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int i = i0 + p;
+        cpx<T> m0 = add(Z0[p], scl(axpy(D0, ks, D1), rk));
+        cpx<T> m1 = add(Z1[p], scl(D1, rk));
+        cpx<T> mm = add(ZM[p], scl(DM, rk));
+        rk = rk * r;
+        ks = ks + s;
+        if (i >= nz) continue;
+        cpx<T> m2 = M2[p], m3 = M3[p], mpp = MP[p];
+        cpx<T> a = add(sub(scl(add(m0, m2), T(0.5)), scl(m1, cfac)), scl(m3, cfac));
+        cpx<T> t1 = add(add(sub(m1, m0), m2), m3);
+        cpx<T> t2 = add(m0, m2);
+        cpx<T> v = add(mpp, mm);
+        cpx<T> t3 = sub(mpp, mm);
+        cpx<T> exx = scl(a, T(-1));
+        cpx<T> ezz = scl(add(add(scl(a, kap), t2), o[p][1]), T(1) / kp2);
+        cpx<T> exz = mul_i(scl(add(t1, o[p][2]), T(0.5)));
+        cpx<T> eez = scl(add(t3, o[p][4]), T(0.5));
+        cpx<T> exe = mul_i(scl(v, T(0.5)));
+        cpx<T> e[6];
+        e[0] = sub(scl(exx, n1 * n1), scl(exe, T(2) * n1 * n2));
+        e[1] = add(scl(exx, n2 * n2), scl(exe, T(2) * n1 * n2));
+        e[2] = ezz;
+        e[3] = add(scl(exz, n2), scl(eez, n1));
+        e[4] = sub(scl(exz, n1), scl(eez, n2));
+        e[5] = add(scl(exx, n1 * n2), scl(exe, n1 * n1 - n2 * n2));
+        emit(i, e, rep == 0, wrep);
+        if (DISP) {
+          cpx<T> c = sub(sub(scl(sub(m2, m0), T(0.5)), scl(m1, ik2)), scl(m3, ik2));
+          cpx<T> U = mul_i(scl(a, iq));
+          cpx<T> V = scl(v, iq);
+          cpx<T> W = scl(c, iq);
+          if (prm.off_disp >= 0) {
+            put(dst + prm.off_disp + i, scl(sub(scl(U, n1), scl(V, n2)), wrep), rep == 0);
+            put(dst + prm.off_disp + (size_t)nz + i, scl(add(scl(U, n2), scl(V, n1)), wrep), rep == 0);
+            put(dst + prm.off_disp + (size_t)2 * nz + i, scl(W, wrep), rep == 0);
+          }
+          if (prm.off_u3 >= 0 && i == 0) put(dst + prm.off_u3, scl(W, wrep), rep == 0);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int LPM, int P>
+hipError_t launch_cfg(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st) {
+  constexpr int GPB = NT / LPM;
+  const int nmodes = p.kxh * p.ny;
+  const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
+  if (p.off_disp >= 0 || p.off_u3 >= 0)
+    hipLaunchKernelGGL((k_depth<T, LPM, P, true>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
+  else
+    hipLaunchKernelGGL((k_depth<T, LPM, P, false>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// nz <= 512.  Lanes per mode and nodes per lane: keep P <= 2 up to nz = 128.
+template <typename T>
+hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p,
+                        hipStream_t st) {
+  const int nz = p.nz;
+  if (nz <= 16) return launch_cfg<T, 16, 1>(in, tin, out, p, st);
+  if (nz <= 32) return launch_cfg<T, 16, 2>(in, tin, out, p, st);
+  if (nz <= 64) return launch_cfg<T, 32, 2>(in, tin, out, p, st);
+  if (nz <= 128) return launch_cfg<T, 64, 2>(in, tin, out, p, st);
+  if (nz <= 256) return launch_cfg<T, 64, 4>(in, tin, out, p, st);
+  if (nz <= 512) return launch_cfg<T, 64, 8>(in, tin, out, p, st);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_depth<double>(const cpx<double>*, const cpx<double>*, cpx<double>*,
+                                         const DepthParams&, hipStream_t);
+template hipError_t launch_depth<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const DepthParams&,
+                                        hipStream_t);
+
+}  // namespace fvim

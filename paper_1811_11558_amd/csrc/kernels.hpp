@@ -1,0 +1,52 @@
+// Launch wrappers shared between the translation units of the library.
+#pragma once
+#include "common.hpp"
+
+namespace fvim {
+
+// Destination of the planes leaving the inverse x transform: plane p goes to
+// ptr[s] at local plane p - first[s] for the last s with first[s] <= p.
+struct OutSegments {
+  int n;
+  int first[4];
+  double* ptr[4];
+};
+
+template <typename T>
+hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
+                        double scale, const cpx<T>* tw, hipStream_t st);
+
+// Per-mode depth pass.  Input spectrum (unnormalised DFT of the plastic
+// strain) in mode-major layout in[mode][6][nz]; traction spectrum
+// tin[mode][3]; output out[mode][np_out] holding the requested fields at
+// plane offsets off_* (negative = not requested): strain and stress as
+// [6][nz], displacement as [3][nz], surface u3 as one plane.
+struct DepthParams {
+  int nx, ny, nz, kxh;
+  double lx, ly, h;       // cell size and depth-node spacing
+  double mu, kappa;       // shear modulus, lambda / mu
+  double norm;            // 1 / (nx ny)
+  int has_w, has_t, k0_include;
+  int np_out;
+  int off_strain, off_stress, off_disp, off_u3;
+};
+
+template <typename T>
+hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p,
+                        hipStream_t st);
+
+// Pointwise kernels (float64).
+hipError_t launch_return_map(const double* d_eps, const double* sig_n, const double* ep_n, double* d_eps_p,
+                             double* d_ep, double* sig_np1, size_t nvox, double lam, double mu,
+                             double sy0, double eh, hipStream_t st);
+
+}  // namespace fvim

@@ -1,0 +1,63 @@
+// Pointwise float64 kernels: the J2 radial return (Sec. 4.1) and the vector
+// algebra of the iterative solvers.  All are HBM-streaming; each thread
+// handles consecutive voxels of one component plane so every access is a
+// contiguous run.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace fvim {
+namespace {
+
+constexpr int NT = 256;
+
+// Backward-Euler radial return for linear isotropic hardening.  The plastic
+// multiplier increment is exact for this law: with f = sigma_eq_trial -
+// (sy0 + eh ep_n) > 0, the consistency condition
+// sigma_eq_trial - 3 mu d_ep = sy0 + eh (ep_n + d_ep) gives
+// d_ep = f / (3 mu + eh), and the flow direction is that of dev sigma_trial.
+__global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de, const double* sn,
+                                                  const double* __restrict__ epn, double* __restrict__ dep,
+                                                  double* __restrict__ dp, double* sn1, size_t V, double lam,
+                                                  double mu, double sy0, double eh) {
+  size_t v = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (v >= V) return;
+  double e[6], s[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    e[c] = de[c * V + v];
+    s[c] = sn[c * V + v];
+  }
+  const double tre = e[0] + e[1] + e[2];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s[c] += 2.0 * mu * e[c] + (c < 3 ? lam * tre : 0.0);
+  const double m = (s[0] + s[1] + s[2]) * (1.0 / 3.0);
+  double d[6] = {s[0] - m, s[1] - m, s[2] - m, s[3], s[4], s[5]};
+  const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0 * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+  const double seq = sqrt(1.5 * nn);
+  const double f = seq - (sy0 + eh * epn[v]);
+  double dpv = 0.0, fac = 0.0;
+  if (f > 0.0) {
+    dpv = f / (3.0 * mu + eh);
+    fac = 1.5 * dpv / seq;
+  }
+  dp[v] = dpv;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double x = fac * d[c];
+    dep[c * V + v] = x;
+    if (sn1) sn1[c * V + v] = s[c] - 2.0 * mu * x;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_return_map(const double* d_eps, const double* sig_n, const double* ep_n, double* d_eps_p,
+                             double* d_ep, double* sig_np1, size_t nvox, double lam, double mu, double sy0,
+                             double eh, hipStream_t st) {
+  unsigned nb = (unsigned)((nvox + NT - 1) / NT);
+  hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, d_eps, sig_n, ep_n, d_eps_p, d_ep, sig_np1, nvox,
+                     lam, mu, sy0, eh);
+  return hipGetLastError();
+}
+
+}  // namespace fvim

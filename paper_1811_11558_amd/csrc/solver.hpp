@@ -1,0 +1,50 @@
+// Context object and the internal interface between the operator entry points
+// and the iterative solvers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/fvim.h"
+
+namespace fvim {
+struct SolverWork;
+}
+
+struct fvim_ctx {
+  fvim_grid grid;
+  fvim_material mat;
+  int precision = 0;
+  int k0_policy = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double mu = 0, lam = 0;
+  void* twx64 = nullptr;
+  void* twy64 = nullptr;
+  void* twx32 = nullptr;
+  void* twy32 = nullptr;
+  void* bufA = nullptr;
+  void* bufB = nullptr;
+  void* tA = nullptr;
+  void* tB = nullptr;
+  size_t bufA_bytes = 0, bufB_bytes = 0, tA_bytes = 0, tB_bytes = 0;
+  fvim::SolverWork* sw = nullptr;
+  // stage timing: pairs of events per launch, tagged by stage
+  int timing = 0;
+  struct StageEv {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<StageEv> evs;
+};
+
+namespace fvim {
+int fail(int code, const char* msg);
+int fail_hip(hipError_t e, const char* where);
+int ctx_reserve(fvim_ctx* c, void** p, size_t* have, size_t need);
+int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+                   double* disp, double* surf_u3);
+void solver_release(fvim_ctx* c);
+size_t solver_footprint(const fvim_grid* g, size_t V);
+}  // namespace fvim
