@@ -11,8 +11,8 @@
  * nodes z_k = k lz/(nz-1) (both ends included).  nx and ny must be powers of
  * two in [4, 4096]; 2 <= nz <= 512.
  *
- * Field layout: every field pointer is a DEVICE pointer to contiguous
- * float64 memory owned by the caller, x fastest:
+ * Field layout: every field pointer is a DEVICE pointer to contiguous,
+ * 16-byte aligned float64 memory owned by the caller, x fastest:
  *   scalar  [nz][ny][nx]
  *   tensor  [6][nz][ny][nx]   symmetric, order (11,22,33,23,13,12), tensor
  *                             (not engineering) shear components
@@ -179,7 +179,8 @@ typedef struct {
   double tol_contact;  /* contact_solve tol                                  */
   int max_outer, max_plastic, max_contact;
   int solver;          /* 0 = DF-SANE (Sec. 4.3), 1 = Picard fixed point     */
-  int literal_alg1;    /* 1: the relaxed update is overwritten as printed    */
+  int literal_alg1;    /* 1: overwrite the relaxed update as printed; 0:   */
+                       /* keep it (plain under-relaxation, same fixed pt) */
 } fvim_ep_opts;
 
 typedef struct {
@@ -218,6 +219,19 @@ enum {
   FVIM_NSTAGES = 7
 };
 int fvim_set_timing(fvim_ctx* ctx, int on);
+
+/*
+ * Tuning options.  FVIM_OPT_DEPTH_CONFIG: id of the depth-pass thread layout
+ * (lanes per mode x nodes per lane; -1 = built-in default for nz); ids that
+ * do not serve nz are rejected with FVIM_EINVAL.  FVIM_OPT_TUNE = 1: the next
+ * operator call times every valid layout on its own data (blocking) and
+ * keeps the fastest.  Different layouts change only the summation order.
+ * Callers that need run-to-run identical results store the chosen id and
+ * set it explicitly.
+ */
+enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2 };
+int fvim_set_option(fvim_ctx* ctx, int key, int value);
+int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);
 
 #ifdef __cplusplus

@@ -1,0 +1,167 @@
+"""Incremental plasticity fixed point and Algorithm 1 (oracle).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+* ``plasticity``: solves R[d_eps] = 0 with
+  R[d_eps] = d_eps - grad_s M[dT] - grad_s N[C : d_eps_p(d_eps; S_n)]
+  (eqn incremental_strain), d_eps_p from the radial return, by the DF-SANE
+  spectral residual method of Sec. 4.3 or by plain fixed-point (Picard)
+  iteration d_eps <- d_eps - R[d_eps].
+* ``dfsane``: La Cruz, Martinez and Raydan (2006): direction -sigma_k F,
+  sigma_k = <s, s>/<s, y> of the last step s and residual change y, clipped
+  to [1e-10, 1e10] in absolute value, sigma_0 = 1; nonmonotone two-sided
+  line search accepting x +/- alpha d when
+  |F|^2 <= max(last 10 |F|^2) + eta_k - gamma alpha^2 |F_k|^2,
+  eta_k = |F_0| / (1 + k)^2, gamma = 1e-4, step reduced by safeguarded
+  quadratic interpolation into [0.1, 0.5] of the previous alpha.  The paper
+  gives the iteration but none of these constants; these are the published
+  defaults.
+* ``elastoplastic_solve``: Algorithm 1 over cumulative loads.  The printed
+  algorithm overwrites the relaxed surface correction with the unrelaxed one
+  at the end of each pass (``literal=True``); by default the relaxed value is
+  kept (plain under-relaxation), which has the same fixed point and, unlike
+  the printed form, converges on the Hertz cases of the tests.
+"""
+import numpy as np
+
+from . import contact as oc
+from . import operators as ops
+from . import plasticity as pl
+
+
+def dfsane(F, x0, inner, tol_abs, max_iter=500, memory=10, gamma=1e-4,
+           sig_min=1e-10, sig_max=1e10, tau_min=0.1, tau_max=0.5):
+    """Root of F by DF-SANE.  inner(a, b) is the scalar product.
+
+    Returns (x, Fx, info).  Stops when |F| <= tol_abs."""
+    x = x0
+    Fx = F(x)
+    nevals = 1
+    f = inner(Fx, Fx)
+    f0n = np.sqrt(f)
+    hist = [f]
+    sigma = 1.0
+    k = 0
+    while np.sqrt(f) > tol_abs and k < max_iter:
+        d = -sigma * Fx
+        eta = f0n / (1.0 + k) ** 2
+        fbar = max(hist[-memory:])
+        ap = am = 1.0
+        while True:
+            xp = x + ap * d
+            Fp = F(xp)
+            nevals += 1
+            fp = inner(Fp, Fp)
+            if fp <= fbar + eta - gamma * ap * ap * f:
+                xn, Fn, fn = xp, Fp, fp
+                break
+            xm = x - am * d
+            Fm = F(xm)
+            nevals += 1
+            fm = inner(Fm, Fm)
+            if fm <= fbar + eta - gamma * am * am * f:
+                xn, Fn, fn = xm, Fm, fm
+                break
+            at = ap * ap * f / (fp + (2.0 * ap - 1.0) * f)
+            ap = min(max(at, tau_min * ap), tau_max * ap)
+            at = am * am * f / (fm + (2.0 * am - 1.0) * f)
+            am = min(max(at, tau_min * am), tau_max * am)
+        s = xn - x
+        y = Fn - Fx
+        sy = inner(s, y)
+        ss = inner(s, s)
+        if sy == 0.0:
+            sigma = sig_max
+        else:
+            sigma = ss / sy
+            sgn = 1.0 if sigma >= 0 else -1.0
+            sigma = sgn * min(max(abs(sigma), sig_min), sig_max)
+        x, Fx, f = xn, Fn, fn
+        hist.append(f)
+        k += 1
+    return x, Fx, {"iters": k, "evals": nevals, "res": float(np.sqrt(f))}
+
+
+def plasticity(grid, mat, dT, state, tol=1e-13, max_iter=500, solver="dfsane", k0_policy="include"):
+    """Strain increment of one load increment with tractions increment dT.
+
+    mat: dict E, nu, sigma_y0, E_h.  state: dict eps_p, ep, sigma (arrays).
+    Returns dict d_eps, d_eps_p, d_ep, sigma, info."""
+    E, nu = mat['E'], mat['nu']
+    b = ops.boussinesq_apply(grid, E, nu, dT, k0_policy=k0_policy)['strain']
+
+    def rmap(de):
+        return pl.return_map(de, state['sigma'], state['ep'], E, nu, mat['sigma_y0'], mat['E_h'])
+
+    def R(de):
+        dep, _, _ = rmap(de)
+        return de - b - ops.mindlin_apply(grid, E, nu, dep, k0_policy=k0_policy)['strain']
+
+    inner = lambda a, c: pl.inner(a, c, grid)
+    tol_abs = tol * max(np.sqrt(inner(b, b)), 1e-300)
+    if solver == "dfsane":
+        de, Rv, info = dfsane(R, b.copy(), inner, tol_abs, max_iter=max_iter)
+    else:
+        de = b.copy()
+        Rv = R(de)
+        it = 0
+        while np.sqrt(inner(Rv, Rv)) > tol_abs and it < max_iter:
+            de = de - Rv
+            Rv = R(de)
+            it += 1
+        info = {"iters": it, "evals": it + 1, "res": float(np.sqrt(inner(Rv, Rv)))}
+    dep, dp, sig = rmap(de)
+    return {"d_eps": de, "d_eps_p": dep, "d_ep": dp, "sigma": sig, "info": info}
+
+
+def new_state(grid):
+    nx, ny, nz = grid['nx'], grid['ny'], grid['nz']
+    return {"eps_p": np.zeros((6, nz, ny, nx)), "ep": np.zeros((nz, ny, nx)),
+            "sigma": np.zeros((6, nz, ny, nx)), "traction": np.zeros((3, ny, nx)),
+            "u3p": np.zeros((ny, nx))}
+
+
+def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3,
+                        tol_plastic=1e-13, tol_contact=1e-14, max_outer=500,
+                        max_plastic=500, max_contact=5000, solver="dfsane", literal=False,
+                        k0_policy="include"):
+    """Algorithm 1 for each cumulative load in W_steps; state updated in place.
+
+    Returns a list of per-step info dicts."""
+    E, nu = mat['E'], mat['nu']
+    infos = []
+    for W in W_steps:
+        H0 = h - state['u3p']
+        hnorm = np.linalg.norm(H0)
+        if hnorm == 0.0:
+            hnorm = 1.0
+        T_n = state['traction']
+        dU_prev = np.zeros_like(H0)
+        H = H0
+        p = None
+        res = None
+        err = np.inf
+        k = 0
+        hist = []
+        for k in range(1, max_outer + 1):
+            p, _, cinfo = oc.contact_solve(H, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p)
+            T = np.zeros_like(T_n)
+            T[2] = p
+            res = plasticity(grid, mat, T - T_n, state, tol=tol_plastic, max_iter=max_plastic,
+                             solver=solver, k0_policy=k0_policy)
+            dU = ops.mindlin_apply(grid, E, nu, res['d_eps_p'], k0_policy=k0_policy)['surf_u3']
+            err = np.linalg.norm(dU - dU_prev) / hnorm
+            hist.append(float(err))
+            relaxed = dU_prev + relax * (dU - dU_prev)
+            H = H0 - relaxed
+            dU_prev = dU if literal else relaxed
+            if err < tol_outer:
+                break
+        state['eps_p'] = state['eps_p'] + res['d_eps_p']
+        state['ep'] = state['ep'] + res['d_ep']
+        state['sigma'] = res['sigma']
+        state['traction'] = T
+        state['u3p'] = state['u3p'] + dU
+        infos.append({"outer_iters": k, "outer_err": float(err), "plastic": res['info'],
+                      "contact": cinfo, "p": p, "history": hist})
+    return infos

@@ -54,7 +54,7 @@ class EPOptions(ctypes.Structure):
                 ("literal_alg1", ctypes.c_int)]
 
     def __init__(self, tol_outer=1e-9, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14,
-                 max_outer=200, max_plastic=2000, max_contact=2000, solver=0, literal_alg1=1):
+                 max_outer=400, max_plastic=2000, max_contact=20000, solver=0, literal_alg1=0):
         super().__init__(tol_outer, relax, tol_plastic, tol_contact, max_outer, max_plastic,
                          max_contact, solver, literal_alg1)
 
@@ -89,6 +89,8 @@ def load_library(path=None):
     lib.fvim_last_error.restype = ctypes.c_char_p
     lib.fvim_version.restype = ctypes.c_char_p
     lib.fvim_set_timing.argtypes = [_P, ctypes.c_int]
+    lib.fvim_set_option.argtypes = [_P, ctypes.c_int, ctypes.c_int]
+    lib.fvim_get_option.argtypes = [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.fvim_stage_times.argtypes = [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
     lib.mindlin_apply.argtypes = [_P, _P, _P, _P, _P, _P]
     lib.boussinesq_apply.argtypes = [_P, _P, _P, _P, _P, _P]
@@ -164,6 +166,20 @@ class Context:
             pass
 
     STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv")
+
+    OPT_DEPTH_CONFIG, OPT_TUNE = 1, 2
+
+    def set_option(self, key, value):
+        _check(_LIB.fvim_set_option(self._h, int(key), int(value)))
+
+    def get_option(self, key):
+        v = ctypes.c_int()
+        _check(_LIB.fvim_get_option(self._h, int(key), ctypes.byref(v)))
+        return v.value
+
+    def tune(self):
+        """Time every depth-pass layout on the next operator call, keep the fastest."""
+        self.set_option(self.OPT_TUNE, 1)
 
     def set_timing(self, on=True):
         _check(_LIB.fvim_set_timing(self._h, 1 if on else 0))

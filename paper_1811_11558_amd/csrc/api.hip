@@ -92,6 +92,43 @@ struct StageTimer {
   }
 };
 
+// Times every valid depth-pass configuration on the live buffers (three
+// launches each after one warm-up) and keeps the fastest in the context.
+// The choice changes only the order of the depth sums (results agree to
+// rounding); it is fixed for the context afterwards, so results are
+// reproducible for a given configuration.
+template <typename T>
+int tune_depth(fvim_ctx* c, const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& prm) {
+  hipStream_t st = c->stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(FVIM_EHIP, "events");
+  float best = 1e30f;
+  int best_id = depth_default_config(prm.nz);
+  for (int id = 0; id < depth_num_configs(); ++id) {
+    if (!depth_config_valid(id, prm.nz)) continue;
+    hipError_t e = launch_depth<T>(in, tin, out, prm, id, st);
+    hipEventRecord(a, st);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_depth<T>(in, tin, out, prm, id, st);
+    hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (e != hipSuccess) {
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+      return fail_hip(e, "depth tuning");
+    }
+    if (ms < best) {
+      best = ms;
+      best_id = id;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  c->depth_cfg = best_id;
+  return FVIM_OK;
+}
+
 // u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
 template <typename T>
 int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
@@ -162,8 +199,14 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
       return fail_hip(e, "y_fwd(t)");
     tm.end();
   }
+  if (c->tune_pending) {
+    c->tune_pending = 0;
+    int rc2 = tune_depth<T>(c, B, (const cpx<T>*)c->tB, A, prm);
+    if (rc2) return rc2;
+  }
   tm.begin(FVIM_STAGE_DEPTH);
-  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, st)) != hipSuccess) return fail_hip(e, "depth");
+  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st)) != hipSuccess)
+    return fail_hip(e, "depth");
   tm.end();
   tm.begin(FVIM_STAGE_YINV);
   if ((e = launch_y_inv<T>(A, B, ny, kxh, np, twy, st)) != hipSuccess) return fail_hip(e, "y_inv");
@@ -174,8 +217,13 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   return FVIM_OK;
 }
 
+static bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u); }
+
 int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
                    double* disp, double* surf_u3) {
+  if (misaligned(eps_p) || misaligned(traction) || misaligned(strain) || misaligned(stress) ||
+      misaligned(disp) || misaligned(surf_u3))
+    return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
   if (c->precision == FVIM_FP32_REFINED)
     return operator_apply_t<float>(c, eps_p, traction, strain, stress, disp, surf_u3);
   return operator_apply_t<double>(c, eps_p, traction, strain, stress, disp, surf_u3);
@@ -248,6 +296,34 @@ void fvim_destroy(fvim_ctx* c) {
     hipEventDestroy(ev.b);
   }
   delete c;
+}
+
+int fvim_set_option(fvim_ctx* c, int key, int value) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  switch (key) {
+    case FVIM_OPT_DEPTH_CONFIG:
+      if (value != -1 && !depth_config_valid(value, c->grid.nz))
+        return fail(FVIM_EINVAL, "depth configuration does not serve this nz");
+      c->depth_cfg = value;
+      return FVIM_OK;
+    case FVIM_OPT_TUNE:
+      c->tune_pending = value ? 1 : 0;
+      return FVIM_OK;
+  }
+  return fail(FVIM_EINVAL, "unknown option");
+}
+
+int fvim_get_option(fvim_ctx* c, int key, int* value) {
+  if (!c || !value) return fail(FVIM_EINVAL, "NULL argument");
+  switch (key) {
+    case FVIM_OPT_DEPTH_CONFIG:
+      *value = c->depth_cfg >= 0 ? c->depth_cfg : depth_default_config(c->grid.nz);
+      return FVIM_OK;
+    case FVIM_OPT_TUNE:
+      *value = c->tune_pending;
+      return FVIM_OK;
+  }
+  return fail(FVIM_EINVAL, "unknown option");
 }
 
 int fvim_set_timing(fvim_ctx* c, int on) {

@@ -139,18 +139,30 @@ __device__ __forceinline__ void put(cpx<T>* __restrict__ dst, cpx<T> v, bool fir
   *dst = v;
 }
 
-template <typename T, int LPM, int P, bool DISP>
+// NYQ = false: every mode except the Nyquist ones (kx = nx/2 or ky = ny/2),
+// one evaluation each.  NYQ = true: only the Nyquist modes, each the average
+// of its 2 or 4 sign replicas (indexed by group: first the kx = nx/2 column,
+// then the ky = ny/2 row without its kx = nx/2 entry).
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
 __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, const cpx<T>* __restrict__ tin,
                                              cpx<T>* __restrict__ out, DepthParams prm) {
   constexpr int GPB = NT / LPM;
   const int g = threadIdx.x / LPM;
   const int l = threadIdx.x - g * LPM;
-  const int nmodes = prm.kxh * prm.ny;
-  const int mode = blockIdx.x * GPB + g;
-  if (mode >= nmodes) return;                 // the whole lane group leaves together
+  const int gid = blockIdx.x * GPB + g;
+  int kx, ky;
+  if (NYQ) {
+    if (gid >= prm.ny + prm.kxh - 1) return;
+    if (gid < prm.ny) { kx = prm.nx / 2; ky = gid; }
+    else { kx = gid - prm.ny; ky = prm.ny / 2; }
+  } else {
+    if (gid >= prm.kxh * prm.ny) return;       // the whole lane group leaves together
+    kx = gid / prm.ny;
+    ky = gid - kx * prm.ny;
+    if (kx * 2 == prm.nx || ky * 2 == prm.ny) return;
+  }
+  const int mode = kx * prm.ny + ky;
   const int nz = prm.nz;
-  const int kx = mode / prm.ny;
-  const int ky = mode - kx * prm.ny;
   const cpx<T>* __restrict__ src = in + (size_t)mode * 6 * nz;
   cpx<T>* __restrict__ dst = out + (size_t)mode * prm.np_out;
   const T nrm = (T)prm.norm;
@@ -158,7 +170,8 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
   const T mu = (T)prm.mu;
   const T kp2 = kap + T(2);
   const int i0 = l * P;
-  const bool wantS = prm.off_strain >= 0, wantX = prm.off_stress >= 0;
+  const bool wantS = prm.off_strain >= 0;
+  constexpr bool wantX = WANTX;
 
   cpx<T> tr[3];
 #pragma unroll
@@ -185,7 +198,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
     }
   };
 
-  if (kx == 0 && ky == 0) {
+  if (!NYQ && kx == 0 && ky == 0) {
     // laterally uniform mode: sigma . e3 = -t everywhere, no in-plane strain
     const T tk = prm.k0_include ? T(1) : T(0);
 #pragma unroll
@@ -212,9 +225,9 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
     return;
   }
 
-  const int nyqx = (kx * 2 == prm.nx);
-  const int nyqy = (ky * 2 == prm.ny);
-  const int nrep = (nyqx ? 2 : 1) * (nyqy ? 2 : 1);
+  const int nyqx = NYQ && (kx * 2 == prm.nx);
+  const int nyqy = NYQ && (ky * 2 == prm.ny);
+  const int nrep = NYQ ? (nyqx ? 2 : 1) * (nyqy ? 2 : 1) : 1;
   const int k1 = kx;
   const int k2 = (ky * 2 <= prm.ny) ? ky : ky - prm.ny;
   const T wrep = T(1) / (T)nrep;
@@ -427,37 +440,78 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
   }
 }
 
-template <typename T, int LPM, int P>
-hipError_t launch_cfg(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st) {
+template <typename T, int LPM, int P, bool DISP, bool WANTX>
+hipError_t launch_two(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st) {
   constexpr int GPB = NT / LPM;
   const int nmodes = p.kxh * p.ny;
   const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
-  if (p.off_disp >= 0 || p.off_u3 >= 0)
-    hipLaunchKernelGGL((k_depth<T, LPM, P, true>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
-  else
-    hipLaunchKernelGGL((k_depth<T, LPM, P, false>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
+  hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
+  const int nnyq = p.ny + p.kxh - 1;
+  const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
+  hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, tin, out, p);
   return hipGetLastError();
 }
 
+template <typename T, int LPM, int P>
+hipError_t launch_cfg(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st) {
+  const bool disp = p.off_disp >= 0 || p.off_u3 >= 0;
+  const bool wx = p.off_stress >= 0;
+  if (disp) return wx ? launch_two<T, LPM, P, true, true>(in, tin, out, p, st)
+                      : launch_two<T, LPM, P, true, false>(in, tin, out, p, st);
+  return wx ? launch_two<T, LPM, P, false, true>(in, tin, out, p, st)
+            : launch_two<T, LPM, P, false, false>(in, tin, out, p, st);
+}
+
+// (lanes per mode, nodes per lane) configurations; a configuration serves
+// nz <= LPM * P.
+struct DepthCfg {
+  int lpm, p;
+};
+constexpr DepthCfg kCfgs[] = {{16, 1}, {16, 2}, {32, 1}, {32, 2}, {64, 1}, {64, 2}, {64, 4}, {64, 8}};
+constexpr int kNCfg = sizeof(kCfgs) / sizeof(kCfgs[0]);
+
 }  // namespace
 
-// nz <= 512.  Lanes per mode and nodes per lane: keep P <= 2 up to nz = 128.
+int depth_num_configs() { return kNCfg; }
+
+// Whether configuration id serves nz and is not wasteful (at least a quarter
+// of the lanes hold a node).
+bool depth_config_valid(int id, int nz) {
+  if (id < 0 || id >= kNCfg) return false;
+  const int cap = kCfgs[id].lpm * kCfgs[id].p;
+  return nz <= cap && 4 * nz > cap;
+}
+
+// Default without tuning: the fewest nodes per lane that keeps <= 64 lanes.
+int depth_default_config(int nz) {
+  if (nz <= 16) return 0;
+  if (nz <= 32) return 1;
+  if (nz <= 64) return 3;
+  if (nz <= 128) return 5;
+  if (nz <= 256) return 6;
+  return 7;
+}
+
 template <typename T>
-hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p,
+hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, int cfg,
                         hipStream_t st) {
-  const int nz = p.nz;
-  if (nz <= 16) return launch_cfg<T, 16, 1>(in, tin, out, p, st);
-  if (nz <= 32) return launch_cfg<T, 16, 2>(in, tin, out, p, st);
-  if (nz <= 64) return launch_cfg<T, 32, 2>(in, tin, out, p, st);
-  if (nz <= 128) return launch_cfg<T, 64, 2>(in, tin, out, p, st);
-  if (nz <= 256) return launch_cfg<T, 64, 4>(in, tin, out, p, st);
-  if (nz <= 512) return launch_cfg<T, 64, 8>(in, tin, out, p, st);
+  if (!depth_config_valid(cfg, p.nz)) cfg = depth_default_config(p.nz);
+  switch (cfg) {
+    case 0: return launch_cfg<T, 16, 1>(in, tin, out, p, st);
+    case 1: return launch_cfg<T, 16, 2>(in, tin, out, p, st);
+    case 2: return launch_cfg<T, 32, 1>(in, tin, out, p, st);
+    case 3: return launch_cfg<T, 32, 2>(in, tin, out, p, st);
+    case 4: return launch_cfg<T, 64, 1>(in, tin, out, p, st);
+    case 5: return launch_cfg<T, 64, 2>(in, tin, out, p, st);
+    case 6: return launch_cfg<T, 64, 4>(in, tin, out, p, st);
+    case 7: return launch_cfg<T, 64, 8>(in, tin, out, p, st);
+  }
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_depth<double>(const cpx<double>*, const cpx<double>*, cpx<double>*,
-                                         const DepthParams&, hipStream_t);
+                                         const DepthParams&, int, hipStream_t);
 template hipError_t launch_depth<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const DepthParams&,
-                                        hipStream_t);
+                                        int, hipStream_t);
 
 }  // namespace fvim

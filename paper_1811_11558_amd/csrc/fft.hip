@@ -29,25 +29,34 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int idx) {
   return w;
 }
 
-// B transforms of length n held at buf[b * ld + k]; ELEMS >= B * n bounds
-// the per-thread register staging.  Must be called by all NT threads.
-template <typename T, bool INV, int ELEMS>
-__device__ void lds_fft(cpx<T>* buf, int n, int ld, int B, const cpx<T>* __restrict__ tw) {
+// Complex elements of one block's LDS tile (32 KiB either precision), so
+// several blocks share a CU and keep loads in flight while others compute.
+template <typename T>
+constexpr int tile_elems() { return sizeof(T) == 8 ? 2048 : 4096; }
+// Tile of the column (y) kernels (measured: 64 KiB tiles, i.e. longer
+// mode-major runs but half the resident blocks, were slower on 256^2 x 64).
+template <typename T>
+constexpr int col_tile_elems() { return tile_elems<T>(); }
+
+// NB transforms of length N = 2^LOGN held at buf[b * ld + k] (NB <= NBMAX),
+// Stockham autosort: one radix-2 stage first when LOGN is odd, then radix-4
+// stages.  All index arithmetic is shifts and masks.  Called by all NT threads.
+template <typename T, int LOGN, int NBMAX, bool INV>
+__device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
   const int tid = threadIdx.x;
-  int ns = 1;
-  int lg = 31 - __clz(n);
-  if (lg & 1) {                       // radix-2 stage, trivial twiddles
-    constexpr int MB = (ELEMS / 2 + NT - 1) / NT;
-    const int half = n >> 1;
-    const int nb = B * half;
+  if constexpr (LOGN & 1) {
+    constexpr int H = N / 2;
+    constexpr int MB = (NBMAX * H + NT - 1) / NT;
+    const int nb = NB * H;
     cpx<T> v0[MB], v1[MB];
 #pragma unroll
     for (int u = 0; u < MB; ++u) {
       int j = tid + u * NT;
       if (j < nb) {
-        int b = j / half, jj = j - b * half;
+        int b = j >> (LOGN - 1), jj = j & (H - 1);
         v0[u] = buf[b * ld + jj];
-        v1[u] = buf[b * ld + jj + half];
+        v1[u] = buf[b * ld + jj + H];
       }
     }
     __syncthreads();
@@ -55,30 +64,31 @@ __device__ void lds_fft(cpx<T>* buf, int n, int ld, int B, const cpx<T>* __restr
     for (int u = 0; u < MB; ++u) {
       int j = tid + u * NT;
       if (j < nb) {
-        int b = j / half, jj = j - b * half;
+        int b = j >> (LOGN - 1), jj = j & (H - 1);
         buf[b * ld + 2 * jj] = add(v0[u], v1[u]);
         buf[b * ld + 2 * jj + 1] = sub(v0[u], v1[u]);
       }
     }
     __syncthreads();
-    ns = 2;
   }
-  constexpr int MB4 = (ELEMS / 4 + NT - 1) / NT;
-  const int quarter = n >> 2;
-  const int nb4 = B * quarter;
-  while (ns < n) {
+  constexpr int Q = N / 4;
+  constexpr int MB4 = (NBMAX * Q + NT - 1) / NT;
+  const int nb4 = NB * Q;
+#pragma unroll
+  for (int ls = (LOGN & 1); ls < LOGN; ls += 2) {
+    const int ns = 1 << ls;
+    const int tstep = N >> (ls + 2);
     cpx<T> v[MB4][4];
-    const int tstep = n / (4 * ns);
 #pragma unroll
     for (int u = 0; u < MB4; ++u) {
       int j = tid + u * NT;
       if (j < nb4) {
-        int b = j / quarter, jj = j - b * quarter;
+        int b = j >> (LOGN - 2), jj = j & (Q - 1);
         const cpx<T>* src = buf + b * ld + jj;
         v[u][0] = src[0];
-        v[u][1] = src[quarter];
-        v[u][2] = src[2 * quarter];
-        v[u][3] = src[3 * quarter];
+        v[u][1] = src[Q];
+        v[u][2] = src[2 * Q];
+        v[u][3] = src[3 * Q];
       }
     }
     __syncthreads();
@@ -86,11 +96,11 @@ __device__ void lds_fft(cpx<T>* buf, int n, int ld, int B, const cpx<T>* __restr
     for (int u = 0; u < MB4; ++u) {
       int j = tid + u * NT;
       if (j < nb4) {
-        int b = j / quarter, jj = j - b * quarter;
-        int k = jj % ns;
+        int b = j >> (LOGN - 2), jj = j & (Q - 1);
+        int k = jj & (ns - 1);
         cpx<T> a0 = v[u][0];
         cpx<T> a1 = v[u][1], a2 = v[u][2], a3 = v[u][3];
-        if (k != 0) {
+        if (ls > 0) {
           a1 = mul(a1, twid<T, INV>(tw, k * tstep));
           a2 = mul(a2, twid<T, INV>(tw, 2 * k * tstep));
           a3 = mul(a3, twid<T, INV>(tw, 3 * k * tstep));
@@ -99,7 +109,7 @@ __device__ void lds_fft(cpx<T>* buf, int n, int ld, int B, const cpx<T>* __restr
         cpx<T> s13 = add(a1, a3), d13 = sub(a1, a3);
         // forward: y1 = d02 - i d13, y3 = d02 + i d13 (conjugate for inverse)
         cpx<T> id13 = INV ? mul_i(d13) : mul_mi(d13);
-        int o = b * ld + (jj / ns) * ns * 4 + k;
+        int o = b * ld + ((jj >> ls) << (ls + 2)) + k;
         buf[o] = add(s02, s13);
         buf[o + ns] = add(d02, id13);
         buf[o + 2 * ns] = sub(s02, s13);
@@ -107,37 +117,51 @@ __device__ void lds_fft(cpx<T>* buf, int n, int ld, int B, const cpx<T>* __restr
       }
     }
     __syncthreads();
-    ns *= 4;
   }
 }
 
-// Rows of nx reals -> half spectra.  Block = R consecutive rows of one
-// plane (R even, R | ny).  Output X[(plane * kxh + k) * ny + y].
-template <typename T, int ELEMS>
-__global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx<T>* __restrict__ out,
-                                             int nx, int ny, int R, const cpx<T>* __restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int ld = nx;
+// Rows of nx = 2^LOGN reals -> half spectra.  Block = R consecutive rows of
+// one plane (R even, R | ny), two rows per complex sequence.  Output
+// X[(plane * kxh + k) * ny + y].
+template <typename T, int LOGN>
+__global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx<T>* __restrict__ out, int ny,
+                                             int R, const cpx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
+  constexpr int ld = N + 1;
+  constexpr int kxh = N / 2 + 1;
+  __shared__ cpx<T> buf[SEQ * ld];
   const size_t row0 = (size_t)blockIdx.x * R;
   const size_t plane = row0 / ny;
   const int y0 = (int)(row0 - plane * ny);
-  const int kxh = nx / 2 + 1;
-  const int tot = R * nx;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int r = i / nx, x = i - r * nx;
-    T v = (T)in[(row0 + r) * nx + x];
-    cpx<T>& d = buf[(r >> 1) * ld + x];
-    if (r & 1) d.y = v; else d.x = v;
+  // 16-byte loads: two consecutive x of one row
+  constexpr int MV = (2 * SEQ * N / 2 + NT - 1) / NT;
+  const int tot = R * N / 2;
+  const double2* src = reinterpret_cast<const double2*>(in + row0 * N);
+  double2 v[MV];
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    int i = threadIdx.x + u * NT;
+    if (i < tot) v[u] = src[i];
+  }
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    int i = threadIdx.x + u * NT;
+    if (i < tot) {
+      int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
+      cpx<T>* d = buf + (r >> 1) * ld + x;
+      if (r & 1) { d[0].y = (T)v[u].x; d[1].y = (T)v[u].y; }
+      else { d[0].x = (T)v[u].x; d[1].x = (T)v[u].y; }
+    }
   }
   __syncthreads();
-  lds_fft<T, false, ELEMS>(buf, nx, ld, R / 2, tw);
+  lds_fft<T, LOGN, SEQ, false>(buf, ld, R / 2, tw);
   const int tot2 = kxh * R;
   for (int i = threadIdx.x; i < tot2; i += NT) {
-    int yl = i % R, k = i / R;
+    int k = i / R, yl = i - k * R;
     int p = yl >> 1;
     cpx<T> Z = buf[p * ld + k];
-    cpx<T> Zc = buf[p * ld + ((nx - k) & (nx - 1))];
+    cpx<T> Zc = buf[p * ld + ((N - k) & (N - 1))];
     cpx<T> X;
     if ((yl & 1) == 0) X = mk(T(0.5) * (Z.x + Zc.x), T(0.5) * (Z.y - Zc.y));
     else X = mk(T(0.5) * (Z.y + Zc.y), T(0.5) * (Zc.x - Z.x));
@@ -145,178 +169,190 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
   }
 }
 
-// Forward column transform: X[p][kx][y] -> S[kx][ky][p]; block = B planes of one kx.
-template <typename T, int ELEMS>
-__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                             int ny, int kxh, int NP, int B, int ld,
-                                             const cpx<T>* __restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+// Forward column transform: X[p][kx][y] -> S[kx][ky][p]; block = up to B
+// planes of one kx (B = tile / ny, planes past NP are zero and not stored).
+template <typename T, int LOGN>
+__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
+                                             int NP, const cpx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
+  constexpr int ld = N + 1;
+  __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
   const int kx = blockIdx.x / npb;
   const int p0 = (blockIdx.x - kx * npb) * B;
-  const int tot = B * ny;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int b = i / ny, y = i - b * ny;
-    int p = p0 + b;
-    buf[b * ld + y] = (p < NP) ? in[((size_t)p * kxh + kx) * ny + y] : zero<T>();
+  const int nb = min(B, NP - p0);
+  constexpr int MV = (B * N + NT - 1) / NT;
+  cpx<T> v[MV];
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    int i = threadIdx.x + u * NT;
+    int b = i >> LOGN, y = i & (N - 1);
+    if (i < B * N && b < nb) v[u] = in[((size_t)(p0 + b) * kxh + kx) * N + y];
+  }
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    int i = threadIdx.x + u * NT;
+    int b = i >> LOGN, y = i & (N - 1);
+    if (i < B * N && b < nb) buf[b * ld + y] = v[u];
   }
   __syncthreads();
-  lds_fft<T, false, ELEMS>(buf, ny, ld, B, tw);
+  lds_fft<T, LOGN, B, false>(buf, ld, nb, tw);
+  const int tot = nb * N;
   for (int i = threadIdx.x; i < tot; i += NT) {
-    int b = i % B, ky = i / B;
-    int p = p0 + b;
-    if (p < NP) out[((size_t)kx * ny + ky) * NP + p] = buf[b * ld + ky];
+    int ky = i / nb, b = i - ky * nb;
+    out[((size_t)kx * N + ky) * NP + p0 + b] = buf[b * ld + ky];
   }
 }
 
 // Inverse column transform: S[kx][ky][p] -> X[p][kx][y].
-template <typename T, int ELEMS>
-__global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                             int ny, int kxh, int NP, int B, int ld,
-                                             const cpx<T>* __restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+template <typename T, int LOGN>
+__global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
+                                             int NP, const cpx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
+  constexpr int ld = N + 1;
+  __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
   const int kx = blockIdx.x / npb;
   const int p0 = (blockIdx.x - kx * npb) * B;
-  const int tot = B * ny;
+  const int nb = min(B, NP - p0);
+  const int tot = nb * N;
   for (int i = threadIdx.x; i < tot; i += NT) {
-    int b = i % B, ky = i / B;
-    int p = p0 + b;
-    buf[b * ld + ky] = (p < NP) ? in[((size_t)kx * ny + ky) * NP + p] : zero<T>();
+    int ky = i / nb, b = i - ky * nb;
+    buf[b * ld + ky] = in[((size_t)kx * N + ky) * NP + p0 + b];
   }
   __syncthreads();
-  lds_fft<T, true, ELEMS>(buf, ny, ld, B, tw);
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int b = i / ny, y = i - b * ny;
-    int p = p0 + b;
-    if (p < NP) out[((size_t)p * kxh + kx) * ny + y] = buf[b * ld + y];
+  lds_fft<T, LOGN, B, true>(buf, ld, nb, tw);
+  constexpr int MV = (B * N + NT - 1) / NT;
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    int i = threadIdx.x + u * NT;
+    int b = i >> LOGN, y = i & (N - 1);
+    if (i < B * N && b < nb) out[((size_t)(p0 + b) * kxh + kx) * N + y] = buf[b * ld + y];
   }
 }
 
-// Half spectra -> rows of nx reals, two rows per complex transform.  Plane p
-// of the input goes to the output segment that contains it.
-template <typename T, int ELEMS>
-__global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg,
-                                             int nx, int ny, int R, double scale,
-                                             const cpx<T>* __restrict__ tw) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int ld = nx;
+// Half spectra -> rows of nx = 2^LOGN reals, two rows per complex transform.
+// Plane p of the input goes to the output segment that contains it.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
+                                             double scale, const cpx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
+  constexpr int ld = N + 1;
+  constexpr int kxh = N / 2 + 1;
+  constexpr int nyq = N / 2;
+  __shared__ cpx<T> buf[SEQ * ld];
   const size_t row0 = (size_t)blockIdx.x * R;
   const int plane = (int)(row0 / ny);
   const int y0 = (int)(row0 - (size_t)plane * ny);
-  const int kxh = nx / 2 + 1;
   const int hp = R / 2;
   const int tot = kxh * hp;
-  const int nyq = nx / 2;
   for (int i = threadIdx.x; i < tot; i += NT) {
-    int pr = i % hp, k = i / hp;
+    int k = i / hp, pr = i - k * hp;
     size_t a = ((size_t)plane * kxh + k) * ny + y0 + 2 * pr;
     cpx<T> X0 = in[a], X1 = in[a + 1];
     if (k == 0 || k == nyq) {
       buf[pr * ld + k] = mk(X0.x, X1.x);
     } else {
       buf[pr * ld + k] = mk(X0.x - X1.y, X0.y + X1.x);
-      buf[pr * ld + nx - k] = mk(X0.x + X1.y, X1.x - X0.y);
+      buf[pr * ld + N - k] = mk(X0.x + X1.y, X1.x - X0.y);
     }
   }
   __syncthreads();
-  lds_fft<T, true, ELEMS>(buf, nx, ld, hp, tw);
+  lds_fft<T, LOGN, SEQ, true>(buf, ld, hp, tw);
   int s = 0;
   while (s + 1 < seg.n && plane >= seg.first[s + 1]) ++s;
-  double* dst = seg.ptr[s];
-  const size_t lp = (size_t)(plane - seg.first[s]);
-  const int tot2 = R * nx;
+  double* dst = seg.ptr[s] + ((size_t)(plane - seg.first[s]) * ny + y0) * N;
+  const int tot2 = R * N / 2;
+  double2* d2 = reinterpret_cast<double2*>(dst);
   for (int i = threadIdx.x; i < tot2; i += NT) {
-    int r = i / nx, x = i - r * nx;
-    cpx<T> v = buf[(r >> 1) * ld + x];
-    T val = (r & 1) ? v.y : v.x;
-    dst[(lp * ny + y0 + r) * nx + x] = (double)val * scale;
+    int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
+    const cpx<T>* b = buf + (r >> 1) * ld + x;
+    double2 o;
+    if (r & 1) { o.x = (double)b[0].y * scale; o.y = (double)b[1].y * scale; }
+    else { o.x = (double)b[0].x * scale; o.y = (double)b[1].x * scale; }
+    d2[i] = o;
   }
 }
 
 template <typename T>
-constexpr int elems_for() { return sizeof(T) == 8 ? 4096 : 8192; }
-
-constexpr size_t LDS_BUDGET = 65536;   // bytes of LDS per block
-
-// Rows per block of the x kernels: R/2 unpadded sequences of length nx in
-// the budget, R a power of two dividing ny.
-int rows_per_block(int nx, int ny, int elems) {
-  int r = (2 * elems) / nx;
+int rows_per_block(int nx, int ny) {
+  int seq = tile_elems<T>() / nx;
+  if (seq < 1) seq = 1;
+  int r = 2 * seq;
   if (r > ny) r = ny;
-  if (r < 2) r = 2;
   return r;
 }
 
-// Columns per block of the y kernels: B sequences of length ny with a
-// one-element pad per sequence within the budget.
-int cols_per_block(int ny, int elems, size_t csize) {
-  int b = (int)(LDS_BUDGET / ((size_t)(ny + 1) * csize));
-  if (b > elems / ny) b = elems / ny;
-  if (b < 1) b = 1;
-  return b;
+template <typename T>
+int cols_per_block(int ny) {
+  int b = col_tile_elems<T>() / ny;
+  return b < 1 ? 1 : b;
 }
 
-// Leading dimension of the y tiles: padded by one element unless that would
-// exceed the budget (single column of the longest transform).
-int col_ld(int ny, int B, size_t csize) {
-  return ((size_t)B * (ny + 1) * csize <= LDS_BUDGET) ? ny + 1 : ny;
-}
+#define FVIM_LOGN_SWITCH(logn, CALL) \
+  switch (logn) {                    \
+    case 2: CALL(2); break;          \
+    case 3: CALL(3); break;          \
+    case 4: CALL(4); break;          \
+    case 5: CALL(5); break;          \
+    case 6: CALL(6); break;          \
+    case 7: CALL(7); break;          \
+    case 8: CALL(8); break;          \
+    case 9: CALL(9); break;          \
+    case 10: CALL(10); break;        \
+    case 11: CALL(11); break;        \
+    case 12: CALL(12); break;        \
+    default: return hipErrorInvalidValue; \
+  }
+
+int ilog2(int n) { return 31 - __builtin_clz((unsigned)n); }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes,
-                        const cpx<T>* tw, hipStream_t st) {
-  constexpr int EL = elems_for<T>();
-  int R = rows_per_block(nx, ny, EL);
-  size_t rows = nplanes * (size_t)ny;
-  size_t lds = (size_t)(R / 2) * nx * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_x_r2c<T, EL>), dim3((unsigned)(rows / R)), dim3(NT), lds, st, in, out, nx, ny,
-                     R, tw);
+hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
+                        hipStream_t st) {
+  int R = rows_per_block<T>(nx, ny);
+  dim3 grid((unsigned)(nplanes * (size_t)ny / R));
+#define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, in, out, ny, R, tw)
+  FVIM_LOGN_SWITCH(ilog2(nx), CALL)
+#undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
                         hipStream_t st) {
-  constexpr int EL = elems_for<T>();
-  int B = cols_per_block(ny, EL, sizeof(cpx<T>));
-  if (B > NP) B = NP;
-  int npb = (NP + B - 1) / B;
-  const int ld = col_ld(ny, B, sizeof(cpx<T>));
-  size_t lds = (size_t)B * ld * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_y_fwd<T, EL>), dim3((unsigned)(kxh * npb)), dim3(NT), lds, st, in, out, ny, kxh,
-                     NP, B, ld, tw);
+  int B = cols_per_block<T>(ny);
+  dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
+#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, tw)
+  FVIM_LOGN_SWITCH(ilog2(ny), CALL)
+#undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
                         hipStream_t st) {
-  constexpr int EL = elems_for<T>();
-  int B = cols_per_block(ny, EL, sizeof(cpx<T>));
-  if (B > NP) B = NP;
-  int npb = (NP + B - 1) / B;
-  const int ld = col_ld(ny, B, sizeof(cpx<T>));
-  size_t lds = (size_t)B * ld * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_y_inv<T, EL>), dim3((unsigned)(kxh * npb)), dim3(NT), lds, st, in, out, ny, kxh,
-                     NP, B, ld, tw);
+  int B = cols_per_block<T>(ny);
+  dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
+#define CALL(L) hipLaunchKernelGGL((k_y_inv<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, tw)
+  FVIM_LOGN_SWITCH(ilog2(ny), CALL)
+#undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st) {
-  constexpr int EL = elems_for<T>();
-  int R = rows_per_block(nx, ny, EL);
-  size_t rows = nplanes * (size_t)ny;
-  size_t lds = (size_t)(R / 2) * nx * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_x_c2r<T, EL>), dim3((unsigned)(rows / R)), dim3(NT), lds, st, in, seg, nx, ny, R,
-                     scale, tw);
+  int R = rows_per_block<T>(nx, ny);
+  dim3 grid((unsigned)(nplanes * (size_t)ny / R));
+#define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw)
+  FVIM_LOGN_SWITCH(ilog2(nx), CALL)
+#undef CALL
   return hipGetLastError();
 }
 

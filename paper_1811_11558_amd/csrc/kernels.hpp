@@ -41,8 +41,11 @@ struct DepthParams {
 };
 
 template <typename T>
-hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p,
+hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, int cfg,
                         hipStream_t st);
+int depth_num_configs();
+bool depth_config_valid(int id, int nz);
+int depth_default_config(int nz);
 
 // Pointwise kernels (float64).
 hipError_t launch_return_map(const double* d_eps, const double* sig_n, const double* ep_n, double* d_eps_p,

@@ -1,34 +1,764 @@
-// Iterative solvers on top of the operators: Polonsky-Keer contact and the
-// Algorithm 1 coupling with the DF-SANE plasticity fixed point.
+// Iterative solvers on top of the operators (all arithmetic on the GPU):
+//
+//  * contact_solve: the Polonsky-Keer projected conjugate gradient for the
+//    Kalker dual of frictionless contact under total load (Sec. 5.1).  The
+//    compliance u3 = M[p] at z = 0 is 2 / (E* |q|) per mode, applied with
+//    the library's FFT kernels on one plane.  Every scalar of the iteration
+//    (mean gap on the contact set, CG coefficient, step length, restart flag,
+//    load renormalisation, convergence measure) is formed on the device by
+//    fixed-order block reductions, so the iteration needs no host round trip;
+//    the host reads the convergence measure back every few iterations.
+//  * the plasticity fixed point R[d_eps] = 0 (eqn incremental_strain) by
+//    DF-SANE (Sec. 4.3) or Picard, residual evaluations = radial return +
+//    Mindlin operator + a fused subtraction; the nonmonotone line search
+//    decides on the host from one reduced scalar per residual evaluation.
+//  * elastoplastic_solve: Algorithm 1 (Sec. 5.2).
+// All reductions are deterministic (fixed block partition, fixed order).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "solver.hpp"
 
 namespace fvim {
 
-struct SolverWork {
-  int dummy;
+namespace {
+constexpr int NT = 256;
+constexpr int RB = 1024;          // max reduction blocks
+constexpr int NSCAL = 32;
+
+// device scalar slots
+enum {
+  S_GBAR = 0, S_G, S_GOLD, S_BETA, S_RBAR, S_TAU, S_DELTA, S_SCALE, S_ERR, S_NIOL, S_SUMP, S_CNT, S_W, S_DA,
+  S_DOT0, S_DOT1, S_DOT2
 };
 
+// ---------------------------------------------------------------- reductions
+// Block partial sums of NS quantities; block b writes part[k * RB + b].
+template <int NS>
+__device__ __forceinline__ void block_sums(double (&v)[NS], double* part) {
+  __shared__ double sh[NS][NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) sh[k][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s += sh[k][i];
+      part[k * RB + blockIdx.x] = s;
+    }
+  }
+}
+
+// Sum of nb partials of quantity k, by one block, fixed order.
+__device__ double final_sum(const double* part, int k, int nb) {
+  __shared__ double sh[NT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) s += part[k * RB + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+int nblocks(size_t n) {
+  size_t b = (n + NT - 1) / NT;
+  return (int)std::min<size_t>(b, RB);
+}
+
+// ------------------------------------------------------------ PK kernels
+// g = u - h; sums over the contact set of g and of 1
+__global__ __launch_bounds__(NT) void k_pk_gap(const double* __restrict__ u, const double* __restrict__ h,
+                                              const double* __restrict__ p, double* __restrict__ g, size_t n,
+                                              double* part) {
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double gi = u[i] - h[i];
+    g[i] = gi;
+    if (p[i] > 0.0) {
+      v[0] += gi;
+      v[1] += 1.0;
+    }
+  }
+  block_sums<2>(v, part);
+}
+
+// g -= gbar; sum over the contact set of g^2
+__global__ __launch_bounds__(NT) void k_pk_grad(const double* __restrict__ p, double* __restrict__ g, size_t n,
+                                               const double* __restrict__ sc, double* part) {
+  const double gbar = sc[S_GBAR];
+  double v[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double gi = g[i] - gbar;
+    g[i] = gi;
+    if (p[i] > 0.0) v[0] += gi * gi;
+  }
+  block_sums<1>(v, part);
+}
+
+// t = g + beta t on the contact set, 0 elsewhere
+__global__ __launch_bounds__(NT) void k_pk_dir(const double* __restrict__ p, const double* __restrict__ g,
+                                              double* __restrict__ t, size_t n, const double* __restrict__ sc) {
+  const double beta = sc[S_BETA];
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
+    t[i] = (p[i] > 0.0) ? g[i] + beta * t[i] : 0.0;
+}
+
+// sums over the contact set of r and 1
+__global__ __launch_bounds__(NT) void k_pk_rmean(const double* __restrict__ p, const double* __restrict__ r,
+                                                size_t n, double* part) {
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
+    if (p[i] > 0.0) {
+      v[0] += r[i];
+      v[1] += 1.0;
+    }
+  block_sums<2>(v, part);
+}
+
+// sums over the contact set of g t and (r - rbar) t
+__global__ __launch_bounds__(NT) void k_pk_tau(const double* __restrict__ p, const double* __restrict__ g,
+                                              const double* __restrict__ r, const double* __restrict__ t,
+                                              size_t n, const double* __restrict__ sc, double* part) {
+  const double rbar = sc[S_RBAR];
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
+    if (p[i] > 0.0) {
+      v[0] += g[i] * t[i];
+      v[1] += (r[i] - rbar) * t[i];
+    }
+  block_sums<2>(v, part);
+}
+
+// step, projection onto p >= 0, re-admission of the overlap set
+__global__ __launch_bounds__(NT) void k_pk_update(double* __restrict__ p, double* __restrict__ pold,
+                                                 const double* __restrict__ g, const double* __restrict__ t,
+                                                 size_t n, const double* __restrict__ sc, double* part) {
+  const double tau = sc[S_TAU];
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double po = p[i];
+    pold[i] = po;
+    double pn = po - tau * t[i];
+    if (pn < 0.0) pn = 0.0;
+    if (pn == 0.0 && g[i] < 0.0) {
+      pn = -tau * g[i];
+      v[1] += 1.0;
+    }
+    p[i] = pn;
+    v[0] += pn;
+  }
+  block_sums<2>(v, part);
+}
+
+// p *= scale; sum |p - p_old|
+__global__ __launch_bounds__(NT) void k_pk_scale(double* __restrict__ p, const double* __restrict__ pold, size_t n,
+                                                const double* __restrict__ sc, double* part) {
+  const double s = sc[S_SCALE];
+  double v[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double pn = p[i] * s;
+    p[i] = pn;
+    v[0] += fabs(pn - pold[i]);
+  }
+  block_sums<1>(v, part);
+}
+
+// One-block finishing steps of the PK iteration: turn partial sums into the
+// scalars the next kernel needs.
+__global__ __launch_bounds__(NT) void k_pk_final(int stage, const double* part, int nb, double* sc) {
+  if (stage == 0) {            // mean gap on the contact set
+    double a = final_sum(part, 0, nb), c = final_sum(part, 1, nb);
+    if (threadIdx.x == 0) {
+      sc[S_GBAR] = c > 0.0 ? a / c : 0.0;
+      sc[S_CNT] = c;
+    }
+  } else if (stage == 1) {     // CG coefficient
+    double G = final_sum(part, 0, nb);
+    if (threadIdx.x == 0) {
+      double gold = sc[S_GOLD];
+      sc[S_BETA] = (gold > 0.0) ? sc[S_DELTA] * G / gold : 0.0;
+      sc[S_G] = G;
+      sc[S_GOLD] = G;
+    }
+  } else if (stage == 2) {     // mean of M t on the contact set
+    double a = final_sum(part, 0, nb), c = final_sum(part, 1, nb);
+    if (threadIdx.x == 0) sc[S_RBAR] = c > 0.0 ? a / c : 0.0;
+  } else if (stage == 3) {     // step length
+    double a = final_sum(part, 0, nb), b = final_sum(part, 1, nb);
+    if (threadIdx.x == 0) sc[S_TAU] = (b != 0.0) ? a / b : 0.0;
+  } else if (stage == 4) {     // load renormalisation and restart flag
+    double sp = final_sum(part, 0, nb), nol = final_sum(part, 1, nb);
+    if (threadIdx.x == 0) {
+      sc[S_SUMP] = sp;
+      sc[S_SCALE] = sp > 0.0 ? sc[S_W] / (sc[S_DA] * sp) : 1.0;
+      sc[S_NIOL] = nol;
+      sc[S_DELTA] = nol > 0.0 ? 0.0 : 1.0;
+    }
+  } else if (stage == 5) {     // convergence measure dA sum |dp| / W
+    double d = final_sum(part, 0, nb);
+    if (threadIdx.x == 0) sc[S_ERR] = sc[S_DA] * d / sc[S_W];
+  } else if (stage == 6) {     // generic: sums of up to three quantities
+    double a = final_sum(part, 0, nb), b = final_sum(part, 1, nb), c = final_sum(part, 2, nb);
+    if (threadIdx.x == 0) {
+      sc[S_DOT0] = a;
+      sc[S_DOT1] = b;
+      sc[S_DOT2] = c;
+    }
+  }
+}
+
+// compliance multiplier per mode, mode-major [kx][ky]: 2 / (E* |q|) / (nx ny), 0 at k = 0
+__global__ __launch_bounds__(NT) void k_compliance(cpx<double>* __restrict__ s, int nx, int ny, double lx,
+                                                  double ly, double fac) {
+  const int kxh = nx / 2 + 1;
+  const int m = blockIdx.x * NT + threadIdx.x;
+  if (m >= kxh * ny) return;
+  const int kx = m / ny, ky = m - kx * ny;
+  const int k2 = (ky * 2 <= ny) ? ky : ky - ny;
+  const double twopi = 6.283185307179586476925286766559;
+  const double q1 = twopi * kx / lx, q2 = twopi * k2 / ly;
+  const double q = sqrt(q1 * q1 + q2 * q2);
+  const double c = (m == 0) ? 0.0 : fac / q;
+  s[m] = mk(s[m].x * c, s[m].y * c);
+}
+
+__global__ __launch_bounds__(NT) void k_fill(double* x, size_t n, double v) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) x[i] = v;
+}
+
+// sum of x and of |x|
+__global__ __launch_bounds__(NT) void k_sum_abs(const double* __restrict__ x, size_t n, double* part) {
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    v[0] += x[i];
+    v[1] += fabs(x[i]);
+  }
+  block_sums<2>(v, part);
+}
+
+// ----------------------------------------------------- vector kernels
+// y = a + s * b
+__global__ __launch_bounds__(NT) void k_axpy(double* __restrict__ y, const double* __restrict__ a, double s,
+                                            const double* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) y[i] = a[i] + s * b[i];
+}
+
+// R = x - b - w  (residual of the incremental equation) and its weighted square norm
+__global__ __launch_bounds__(NT) void k_resid(double* __restrict__ R, const double* __restrict__ x,
+                                             const double* __restrict__ b, const double* __restrict__ w,
+                                             size_t plane, int nz, size_t n, double* part) {
+  double v[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double r = x[i] - b[i] - w[i];
+    R[i] = r;
+    const size_t zc = i / plane;                // c * nz + z
+    const int z = (int)(zc % nz), c = (int)(zc / nz);
+    double wt = (c < 3 ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
+    v[0] += wt * r * r;
+  }
+  block_sums<1>(v, part);
+}
+
+// weighted sums  <a, a>, <a, b>, <b, b>  with a = a1 - a0, b = b1 - b0 (a0/b0 may be NULL)
+__global__ __launch_bounds__(NT) void k_wdots(const double* __restrict__ a1, const double* a0,
+                                             const double* __restrict__ b1, const double* b0, size_t plane, int nz,
+                                             size_t n, double* part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double a = a1[i] - (a0 ? a0[i] : 0.0);
+    double b = b1[i] - (b0 ? b0[i] : 0.0);
+    const size_t zc = i / plane;
+    const int z = (int)(zc % nz), c = (int)(zc / nz);
+    double wt = (c < 3 ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
+    v[0] += wt * a * a;
+    v[1] += wt * a * b;
+    v[2] += wt * b * b;
+  }
+  block_sums<3>(v, part);
+}
+
+// plain sums of squares of (a1 - a0) and of a1 (surfaces)
+__global__ __launch_bounds__(NT) void k_sq2(const double* __restrict__ a1, const double* a0, size_t n,
+                                           double* part) {
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double a = a1[i] - (a0 ? a0[i] : 0.0);
+    v[0] += a * a;
+    v[1] += a1[i] * a1[i];
+  }
+  block_sums<2>(v, part);
+}
+
+}  // namespace
+
+struct SolverWork {
+  size_t ns = 0, V = 0;
+  double* surf = nullptr;       // 8 surface arrays
+  void* specA = nullptr;        // complex kxh*ny
+  void* specB = nullptr;
+  double* part = nullptr;       // 3 * RB partial sums
+  double* sc = nullptr;         // device scalars
+  double* hsc = nullptr;        // pinned host copy
+  double* vol = nullptr;        // volume work arrays (allocated on first plasticity use)
+  size_t vol_count = 0;
+};
+
+static int sw_ensure(fvim_ctx* c) {
+  if (c->sw) return FVIM_OK;
+  SolverWork* w = new SolverWork();
+  w->ns = (size_t)c->grid.nx * c->grid.ny;
+  w->V = w->ns * c->grid.nz;
+  const size_t nm = (size_t)(c->grid.nx / 2 + 1) * c->grid.ny;
+  bool ok = hipMalloc((void**)&w->surf, sizeof(double) * w->ns * 12) == hipSuccess &&
+            hipMalloc(&w->specA, sizeof(cpx<double>) * nm) == hipSuccess &&
+            hipMalloc(&w->specB, sizeof(cpx<double>) * nm) == hipSuccess &&
+            hipMalloc((void**)&w->part, sizeof(double) * 3 * RB) == hipSuccess &&
+            hipMalloc((void**)&w->sc, sizeof(double) * NSCAL) == hipSuccess &&
+            hipHostMalloc((void**)&w->hsc, sizeof(double) * NSCAL, hipHostMallocDefault) == hipSuccess;
+  c->sw = w;
+  if (!ok) return fail(FVIM_ENOMEM, "solver workspace allocation failed");
+  return FVIM_OK;
+}
+
 void solver_release(fvim_ctx* c) {
-  delete c->sw;
+  SolverWork* w = c->sw;
+  if (!w) return;
+  if (w->surf) hipFree(w->surf);
+  if (w->specA) hipFree(w->specA);
+  if (w->specB) hipFree(w->specB);
+  if (w->part) hipFree(w->part);
+  if (w->sc) hipFree(w->sc);
+  if (w->hsc) hipHostFree(w->hsc);
+  if (w->vol) hipFree(w->vol);
+  delete w;
   c->sw = nullptr;
 }
 
-size_t solver_footprint(const fvim_grid* g, size_t V) { return 0; }
+size_t solver_footprint(const fvim_grid* g, size_t V) {
+  const size_t ns = (size_t)g->nx * g->ny;
+  return sizeof(double) * (ns * 12 + 6 * V * 6 + 2 * V) + 64 * 1024;
+}
+
+// Host copy of device scalars [first, first + n) (synchronises the stream).
+static int read_scalars(fvim_ctx* c, int first, int n) {
+  SolverWork* w = c->sw;
+  hipError_t e = hipMemcpyAsync(w->hsc + first, w->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e, "scalar readback");
+  return FVIM_OK;
+}
+
+static int set_scalar(fvim_ctx* c, int slot, double v) {
+  SolverWork* w = c->sw;
+  w->hsc[slot] = v;
+  hipError_t e = hipMemcpyAsync(w->sc + slot, w->hsc + slot, sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e, "scalar upload");
+  return FVIM_OK;
+}
+
+// u = M[p] . e3 at z = 0 for a normal surface load p (one plane).
+static int compliance(fvim_ctx* c, const double* p, double* u) {
+  SolverWork* w = c->sw;
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  const cpx<double>* twx = (const cpx<double>*)c->twx64;
+  const cpx<double>* twy = (const cpx<double>*)c->twy64;
+  cpx<double>* A = (cpx<double>*)w->specA;
+  cpx<double>* B = (cpx<double>*)w->specB;
+  hipStream_t st = c->stream;
+  hipError_t e;
+  if ((e = launch_x_r2c<double>(p, A, nx, ny, 1, twx, st)) != hipSuccess) return fail_hip(e, "compliance x");
+  if ((e = launch_y_fwd<double>(A, B, ny, kxh, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y");
+  const double estar = c->mat.E / (1.0 - c->mat.nu * c->mat.nu);
+  const double fac = 2.0 / estar / ((double)nx * ny);
+  const int nm = kxh * ny;
+  hipLaunchKernelGGL(k_compliance, dim3((nm + NT - 1) / NT), dim3(NT), 0, st, B, nx, ny, c->grid.lx, c->grid.ly,
+                     fac);
+  if ((e = launch_y_inv<double>(B, A, ny, kxh, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y^-1");
+  OutSegments seg;
+  seg.n = 1;
+  seg.first[0] = 0;
+  seg.ptr[0] = u;
+  if ((e = launch_x_c2r<double>(A, seg, nx, ny, 1, 1.0, twx, st)) != hipSuccess)
+    return fail_hip(e, "compliance x^-1");
+  return FVIM_OK;
+}
+
+// Polonsky-Keer on the context stream.  p: in warm start (all zero ->
+// uniform), out solution.  gap may be NULL.
+int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, double* p, double* gap,
+             fvim_contact_info* info) {
+  int rc = sw_ensure(c);
+  if (rc) return rc;
+  SolverWork* w = c->sw;
+  hipStream_t st = c->stream;
+  const size_t n = w->ns;
+  const int nb = nblocks(n);
+  const dim3 G(nb), Bk(NT);
+  double* u = w->surf;
+  double* g = w->surf + n;
+  double* t = w->surf + 2 * n;
+  double* r = w->surf + 3 * n;
+  double* pold = w->surf + 4 * n;
+  const double dA = c->grid.lx * c->grid.ly / (double)n;
+  // scalars: load, area, restart state
+  w->hsc[S_W] = W;
+  w->hsc[S_DA] = dA;
+  w->hsc[S_DELTA] = 0.0;
+  w->hsc[S_GOLD] = 1.0;
+  hipError_t e = hipMemcpyAsync(w->sc, w->hsc, sizeof(double) * NSCAL, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail_hip(e, "scalar upload");
+  // initial pressure: warm start renormalised to W, or uniform
+  hipLaunchKernelGGL(k_sum_abs, G, Bk, 0, st, p, n, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 6, w->part, nb, w->sc);
+  if ((rc = read_scalars(c, S_DOT0, 2))) return rc;
+  const double sp = w->hsc[S_DOT0];
+  if (!(sp > 0.0) || !std::isfinite(sp)) {
+    hipLaunchKernelGGL(k_fill, G, Bk, 0, st, p, n, W / (n * dA));
+  } else {
+    if ((rc = set_scalar(c, S_SCALE, W / (dA * sp)))) return rc;
+    hipLaunchKernelGGL(k_pk_scale, G, Bk, 0, st, p, p, n, w->sc, w->part);
+  }
+  int it = 0;
+  double err = INFINITY;
+  const int check = n <= 4096 ? 1 : 4;        // host convergence check period
+  for (it = 1; it <= max_iter; ++it) {
+    if ((rc = compliance(c, p, u))) return rc;
+    hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
+    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
+    hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
+    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 1, w->part, nb, w->sc);
+    hipLaunchKernelGGL(k_pk_dir, G, Bk, 0, st, p, g, t, n, w->sc);
+    if ((rc = compliance(c, t, r))) return rc;
+    hipLaunchKernelGGL(k_pk_rmean, G, Bk, 0, st, p, r, n, w->part);
+    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 2, w->part, nb, w->sc);
+    hipLaunchKernelGGL(k_pk_tau, G, Bk, 0, st, p, g, r, t, n, w->sc, w->part);
+    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 3, w->part, nb, w->sc);
+    hipLaunchKernelGGL(k_pk_update, G, Bk, 0, st, p, pold, g, t, n, w->sc, w->part);
+    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 4, w->part, nb, w->sc);
+    hipLaunchKernelGGL(k_pk_scale, G, Bk, 0, st, p, pold, n, w->sc, w->part);
+    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 5, w->part, nb, w->sc);
+    if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "contact iteration");
+    if (it % check == 0 || it == max_iter) {
+      if ((rc = read_scalars(c, S_ERR, 1))) return rc;
+      err = w->hsc[S_ERR];
+      if (!std::isfinite(err)) return fail(FVIM_EINVAL, "contact_solve: non-finite iterate (check h and W)");
+      if (err < tol) break;
+    }
+  }
+  const bool conv = err < tol;
+  if (it > max_iter) it = max_iter;
+  // final gap and certificate
+  if ((rc = compliance(c, p, u))) return rc;
+  hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
+  if (gap) {
+    e = hipMemcpyAsync(gap, g, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "gap copy");
+  }
+  if ((rc = read_scalars(c, 0, NSCAL))) return rc;
+  if (info) {
+    info->iters = it;
+    info->rel_change = err;
+    info->contact_fraction = w->hsc[S_CNT] / (double)n;
+    info->mean_gap = w->hsc[S_GBAR];
+    info->kkt_residual = -1.0;   // filled by the caller when it needs it
+  }
+  if (!conv) return fail(FVIM_ENOCONV, "contact_solve: iteration limit reached");
+  return FVIM_OK;
+}
+
+// --------------------------------------------------------- plasticity
+struct PlastBufs {
+  double *x, *F, *xt, *Ft, *b, *dep, *dp, *wk;
+};
+
+static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
+  SolverWork* w = c->sw;
+  const size_t V = w->V;
+  const size_t need = 7 * 6 * V + V;
+  if (w->vol_count < need) {
+    if (w->vol) {
+      hipStreamSynchronize(c->stream);
+      hipFree(w->vol);
+      w->vol = nullptr;
+    }
+    if (hipMalloc((void**)&w->vol, sizeof(double) * need) != hipSuccess) {
+      w->vol_count = 0;
+      return fail(FVIM_ENOMEM, "plasticity workspace allocation failed");
+    }
+    w->vol_count = need;
+  }
+  double* q = w->vol;
+  pb.x = q;
+  pb.F = q + 6 * V;
+  pb.xt = q + 12 * V;
+  pb.Ft = q + 18 * V;
+  pb.b = q + 24 * V;
+  pb.dep = q + 30 * V;
+  pb.wk = q + 36 * V;
+  pb.dp = q + 42 * V;
+  return FVIM_OK;
+}
+
+// weighted scalar product scale: cell area x depth spacing
+static double inner_scale(const fvim_ctx* c) {
+  const fvim_grid& g = c->grid;
+  return g.lx * g.ly / ((double)g.nx * g.ny) * g.lz / (g.nz - 1);
+}
+
+// R(x) into F; returns |R|^2 (weighted) in *f
+static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F, double* f) {
+  SolverWork* w = c->sw;
+  const size_t V = w->V, n6 = 6 * V;
+  hipStream_t st = c->stream;
+  hipError_t e = launch_return_map(x, s->sigma, s->ep, pb.dep, pb.dp, nullptr, V, c->lam, c->mu, c->mat.sigma_y0,
+                                   c->mat.E_h, st);
+  if (e != hipSuccess) return fail_hip(e, "return map");
+  int rc = operator_apply(c, pb.dep, nullptr, pb.wk, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  const int nb = nblocks(n6);
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, st, F, x, pb.b, pb.wk, w->ns, c->grid.nz, n6, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, st, 6, w->part, nb, w->sc);
+  if ((rc = read_scalars(c, S_DOT0, 1))) return rc;
+  *f = w->hsc[S_DOT0] * inner_scale(c);
+  if (!std::isfinite(*f)) return fail(FVIM_EINVAL, "plasticity residual is not finite");
+  return FVIM_OK;
+}
+
+static int wdots(fvim_ctx* c, const double* a1, const double* a0, const double* b1, const double* b0, double out[3]) {
+  SolverWork* w = c->sw;
+  const size_t n6 = 6 * w->V;
+  const int nb = nblocks(n6);
+  hipLaunchKernelGGL(k_wdots, dim3(nb), dim3(NT), 0, c->stream, a1, a0, b1, b0, w->ns, c->grid.nz, n6, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc);
+  int rc = read_scalars(c, S_DOT0, 3);
+  if (rc) return rc;
+  const double sc = inner_scale(c);
+  for (int k = 0; k < 3; ++k) out[k] = w->hsc[S_DOT0 + k] * sc;
+  return FVIM_OK;
+}
+
+static void axpy(fvim_ctx* c, double* y, const double* a, double s, const double* b, size_t n) {
+  hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, c->stream, y, a, s, b, n);
+}
+
+// Solves R[d_eps] = 0 for the traction increment dT ([3][ny][nx]); on
+// return pb.x holds d_eps, pb.dep / pb.dp the plastic increments.
+static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb,
+                      int* iters, int* evals, double* res) {
+  SolverWork* w = c->sw;
+  const size_t n6 = 6 * w->V;
+  hipStream_t st = c->stream;
+  int rc = operator_apply(c, nullptr, dT, pb.b, nullptr, nullptr, nullptr);
+  if (rc) return rc;
+  double d3[3];
+  if ((rc = wdots(c, pb.b, nullptr, pb.b, nullptr, d3))) return rc;
+  const double tol_abs = o->tol_plastic * std::max(std::sqrt(d3[0]), 1e-300);
+  hipError_t e = hipMemcpyAsync(pb.x, pb.b, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return fail_hip(e, "copy");
+  double f;
+  if ((rc = residual(c, s, pb, pb.x, pb.F, &f))) return rc;
+  int ne = 1, k = 0;
+  if (o->solver == 1) {            // Picard: x <- x - R(x)
+    while (std::sqrt(f) > tol_abs && k < o->max_plastic) {
+      axpy(c, pb.x, pb.x, -1.0, pb.F, n6);
+      if ((rc = residual(c, s, pb, pb.x, pb.F, &f))) return rc;
+      ++ne;
+      ++k;
+    }
+  } else {                         // DF-SANE, parameters of La Cruz et al. (2006)
+    const int M = 10;
+    const double gamma = 1e-4, smin = 1e-10, smax = 1e10, tmin = 0.1, tmax = 0.5;
+    std::vector<double> hist{f};
+    const double f0n = std::sqrt(f);
+    double sigma = 1.0;
+    while (std::sqrt(f) > tol_abs && k < o->max_plastic) {
+      const double eta = f0n / ((1.0 + k) * (1.0 + k));
+      double fbar = 0.0;
+      for (size_t i = hist.size() > (size_t)M ? hist.size() - M : 0; i < hist.size(); ++i) fbar = std::max(fbar, hist[i]);
+      double ap = 1.0, am = 1.0, fn = 0.0;
+      int guard = 0;
+      while (true) {
+        axpy(c, pb.xt, pb.x, -ap * sigma, pb.F, n6);      // x + ap d, d = -sigma F
+        double fp;
+        if ((rc = residual(c, s, pb, pb.xt, pb.Ft, &fp))) return rc;
+        ++ne;
+        if (fp <= fbar + eta - gamma * ap * ap * f) { fn = fp; break; }
+        axpy(c, pb.xt, pb.x, am * sigma, pb.F, n6);       // x - am d
+        double fm;
+        if ((rc = residual(c, s, pb, pb.xt, pb.Ft, &fm))) return rc;
+        ++ne;
+        if (fm <= fbar + eta - gamma * am * am * f) { fn = fm; break; }
+        double at = ap * ap * f / (fp + (2.0 * ap - 1.0) * f);
+        ap = std::min(std::max(at, tmin * ap), tmax * ap);
+        at = am * am * f / (fm + (2.0 * am - 1.0) * f);
+        am = std::min(std::max(at, tmin * am), tmax * am);
+        if (++guard > 60) return fail(FVIM_ENOCONV, "DF-SANE line search failed");
+      }
+      // spectral coefficient from s = xt - x, y = Ft - F
+      if ((rc = wdots(c, pb.xt, pb.x, pb.Ft, pb.F, d3))) return rc;
+      const double ss = d3[0], sy = d3[1];
+      if (sy == 0.0) sigma = smax;
+      else {
+        sigma = ss / sy;
+        const double sg = sigma >= 0 ? 1.0 : -1.0;
+        sigma = sg * std::min(std::max(std::fabs(sigma), smin), smax);
+      }
+      std::swap(pb.x, pb.xt);
+      std::swap(pb.F, pb.Ft);
+      f = fn;
+      hist.push_back(f);
+      ++k;
+    }
+  }
+  // plastic increments of the accepted iterate
+  e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, nullptr, w->V, c->lam, c->mu, c->mat.sigma_y0,
+                        c->mat.E_h, st);
+  if (e != hipSuccess) return fail_hip(e, "return map");
+  *iters = k;
+  *evals = ne;
+  *res = std::sqrt(f);
+  if (std::sqrt(f) > tol_abs) return fail(FVIM_ENOCONV, "plasticity: iteration limit reached");
+  return FVIM_OK;
+}
+
+// |a - b|_2 and |a|_2 of surface arrays (b may be NULL)
+static int surf_norms(fvim_ctx* c, const double* a, const double* b, double* dnorm, double* anorm) {
+  SolverWork* w = c->sw;
+  const int nb = nblocks(w->ns);
+  hipLaunchKernelGGL(k_sq2, dim3(nb), dim3(NT), 0, c->stream, a, b, w->ns, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc);
+  int rc = read_scalars(c, S_DOT0, 2);
+  if (rc) return rc;
+  *dnorm = std::sqrt(w->hsc[S_DOT0]);
+  *anorm = std::sqrt(w->hsc[S_DOT1]);
+  return FVIM_OK;
+}
 
 }  // namespace fvim
+
+using namespace fvim;
 
 extern "C" {
 
 int contact_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, double* p, double* gap,
                   fvim_contact_info* info) {
-  return fvim::fail(FVIM_EINVAL, "contact_solve: not available in this build");
+  if (!c || !h || !p) return fail(FVIM_EINVAL, "NULL argument");
+  if (!(W > 0) || !std::isfinite(W)) return fail(FVIM_EINVAL, "contact_solve: W must be positive and finite");
+  if (!(tol > 0) || max_iter < 1) return fail(FVIM_EINVAL, "contact_solve: need tol > 0 and max_iter >= 1");
+  return pk_solve(c, h, W, tol, max_iter, p, gap, info);
 }
 
-int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int n_steps, const fvim_ep_opts* opts,
-                        fvim_state* state, fvim_ep_info* info) {
-  return fvim::fail(FVIM_EINVAL, "elastoplastic_solve: not available in this build");
+int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int n_steps, const fvim_ep_opts* o,
+                        fvim_state* s, fvim_ep_info* info) {
+  if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
+  if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
+  if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1)
+    return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
+  int rc = sw_ensure(c);
+  if (rc) return rc;
+  PlastBufs pb;
+  if ((rc = vol_ensure(c, pb))) return rc;
+  SolverWork* w = c->sw;
+  hipStream_t st = c->stream;
+  const size_t n = w->ns, V = w->V;
+  // surface work arrays (after the 5 used by the contact solver)
+  double* H0 = w->surf + 5 * n;
+  double* H = w->surf + 6 * n;
+  double* dUp = w->surf + 7 * n;
+  double* dU = w->surf + 8 * n;
+  double* T = w->surf + 9 * n;        // 3 planes: 9, 10, 11
+  double* pcur = T + 2 * n;           // normal component of T
+  // dT lives in the traction spectrum workspace? use a dedicated array
+  double* dT = nullptr;
+  if (hipMalloc((void**)&dT, sizeof(double) * 3 * n) != hipSuccess) return fail(FVIM_ENOMEM, "dT");
+  auto cleanup = [&](int r) {
+    hipStreamSynchronize(st);
+    hipFree(dT);
+    return r;
+  };
+  hipError_t e;
+  for (int step = 0; step < n_steps; ++step) {
+    const double Wn = W_steps[step];
+    fvim_ep_info& inf = info[step];
+    memset(&inf, 0, sizeof(inf));
+    axpy(c, H0, h, -1.0, s->u3p, n);                      // H0 = h - U3p
+    double dn, hn;
+    if ((rc = surf_norms(c, H0, nullptr, &dn, &hn))) return cleanup(rc);
+    if (hn == 0.0) hn = 1.0;
+    e = hipMemcpyAsync(H, H0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(dUp, 0, sizeof(double) * n, st);
+    if (e == hipSuccess) e = hipMemsetAsync(T, 0, sizeof(double) * 2 * n, st);
+    // warm start of the pressure: the previous step's normal traction
+    if (e == hipSuccess) e = hipMemcpyAsync(pcur, s->traction + 2 * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "step setup"));
+    double err = INFINITY;
+    int k;
+    for (k = 1; k <= o->max_outer; ++k) {
+      fvim_contact_info ci;
+      rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
+      if (rc) return cleanup(rc);
+      inf.contact_iters += ci.iters;
+      axpy(c, dT, T, -1.0, s->traction, 3 * n);           // dT = T - T_n
+      int it, ne;
+      double res;
+      rc = plasticity(c, dT, s, o, pb, &it, &ne, &res);
+      if (rc) return cleanup(rc);
+      inf.plastic_iters += it;
+      inf.r_evals += ne;
+      inf.plastic_res = res;
+      rc = operator_apply(c, pb.dep, nullptr, nullptr, nullptr, nullptr, dU);   // dU3p
+      if (rc) return cleanup(rc);
+      double an;
+      if ((rc = surf_norms(c, dU, dUp, &dn, &an))) return cleanup(rc);
+      err = dn / hn;
+      // relaxed surface correction, H = H0 - relaxed
+      axpy(c, H, dUp, o->relax, dU, n);                  // H <- dUp + relax dU (temporarily)
+      axpy(c, H, H, -o->relax, dUp, n);                  //      - relax dUp
+      if (o->literal_alg1) {
+        e = hipMemcpyAsync(dUp, dU, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
+      } else {
+        e = hipMemcpyAsync(dUp, H, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
+      }
+      axpy(c, H, H0, -1.0, H, n);                         // H = H0 - relaxed
+      inf.outer_err = err;
+      if (err < o->tol_outer) break;
+    }
+    inf.outer_iters = k > o->max_outer ? o->max_outer : k;
+    if (err >= o->tol_outer) return cleanup(fail(FVIM_ENOCONV, "Algorithm 1: outer iteration limit reached"));
+    // state update: eps_p += d_eps_p, ep += d_ep, sigma <- sigma_(n+1), T_n <- T, U3p += dU
+    e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, s->sigma, V, c->lam, c->mu, c->mat.sigma_y0,
+                          c->mat.E_h, st);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "return map"));
+    axpy(c, s->eps_p, s->eps_p, 1.0, pb.dep, 6 * V);
+    axpy(c, s->ep, s->ep, 1.0, pb.dp, V);
+    e = hipMemcpyAsync(s->traction, T, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
+    axpy(c, s->u3p, s->u3p, 1.0, dU, n);
+  }
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return cleanup(fail_hip(e, "elastoplastic_solve"));
+  return cleanup(FVIM_OK);
 }
 
 }  // extern "C"

@@ -30,6 +30,10 @@ struct fvim_ctx {
   void* tB = nullptr;
   size_t bufA_bytes = 0, bufB_bytes = 0, tA_bytes = 0, tB_bytes = 0;
   fvim::SolverWork* sw = nullptr;
+  // tuning: depth-pass configuration id (-1 = default for nz), and a request
+  // to time every candidate on the next operator call
+  int depth_cfg = -1;
+  int tune_pending = 0;
   // stage timing: pairs of events per launch, tagged by stage
   int timing = 0;
   struct StageEv {

@@ -160,3 +160,32 @@ def test_bad_arguments_raise():
         ctx.mindlin_apply(torch.zeros((6, 8, 16, 15), dtype=torch.float64, device="cuda"))
     with pytest.raises(FvimError):
         ctx.mindlin_apply(torch.zeros((6, 8, 16, 16), dtype=torch.float64))
+
+
+@pytest.mark.parametrize("nz", [16, 33, 64, 100])
+def test_every_depth_layout_matches_oracle(nz):
+    """Each thread layout of the depth pass that serves nz gives the oracle's
+    result (and the tuner picks one of them)."""
+    g = grid_dict(16, 8, nz, 1.0, 1.0, 0.3)
+    eps = filtered_eigenstrain(g, seed=nz)
+    t = filtered_traction(g, seed=nz + 1)
+    ref = ora.apply(g, E, NU, eps_p=eps, traction=t)
+    ctx = _ctx(g)
+    e_d, t_d = torch.from_numpy(eps).cuda(), torch.from_numpy(t).cuda()
+    ran = 0
+    for cfg in range(8):
+        try:
+            ctx.set_option(ctx.OPT_DEPTH_CONFIG, cfg)
+        except Exception:
+            continue
+        out = ctx.operator_apply(e_d, t_d, want=("strain", "disp"))
+        torch.cuda.synchronize()
+        for k in ("strain", "disp"):
+            err = _rel(out[k].cpu().numpy(), ref[k])
+            assert err <= TOL, (cfg, k, err)
+        ran += 1
+    assert ran >= 1
+    ctx.tune()
+    ctx.operator_apply(e_d, t_d)
+    torch.cuda.synchronize()
+    assert 0 <= ctx.get_option(ctx.OPT_DEPTH_CONFIG) < 8

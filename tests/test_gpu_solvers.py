@@ -1,0 +1,117 @@
+"""GPU parity of the solvers (contact, plasticity fixed point, Algorithm 1)
+with the FP64 oracle, through the C ABI.
+
+Both sides iterate to tight tolerances; iterates are not compared step by
+step (the iterations differ in rounding), the converged results are, to the
+stated bound.  Where the result has a closed form (flat surface, uniaxial
+strain) it is checked as well."""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import contact as oc
+from oracle import elastic
+from synth import grid_dict, rough_surface
+
+pytestmark = pytest.mark.gpu
+
+E, NU, SY, EH = 1.0, 0.3, 0.01, 0.1
+LAM, MU = elastic.lame(E, NU)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _ctx(g, **kw):
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    from paper_1811_11558_amd import Context
+    return Context(g, E, NU, SY, EH, **kw)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("n,W,seed", [(32, 0.004, 1), (64, 0.01, 2), (128, 0.02, 3)])
+def test_contact_matches_oracle(n, W, seed):
+    g = grid_dict(n, n, 2)
+    h = rough_surface(n, n, hurst=0.8, k_roll=2, k_cut=n // 4, rms_slope=0.1, seed=seed)
+    ref, rgap, rinfo = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=20000)
+    ctx = _ctx(g)
+    p, gap, info = ctx.contact_solve(torch.from_numpy(h).cuda(), W, tol=1e-15, max_iter=20000, want_gap=True)
+    torch.cuda.synchronize()
+    p = p.cpu().numpy()
+    err = _rel(p, ref)
+    _say("contact", n, "iters gpu/oracle", info["iters"], rinfo["iters"], "rel err", err,
+         "frac", info["contact_fraction"])
+    assert err < 1e-11
+    assert np.all(p >= 0)
+    assert abs(p.sum() / n ** 2 - W) < 1e-14 * W * n
+    gap = gap.cpu().numpy()
+    assert oc.kkt_residual(p, gap, h) < 1e-10
+
+
+def test_contact_full_contact_sinusoid_exact():
+    g = grid_dict(32, 16, 2)
+    x = np.arange(32) / 32
+    q = 2 * np.pi * 2
+    h0 = 1e-3
+    h = np.ascontiguousarray(np.broadcast_to(h0 * np.cos(q * x)[None, :], (16, 32)))
+    estar = elastic.e_star(E, NU)
+    pbar = 1.2 * estar * q * h0 / 2
+    ctx = _ctx(g)
+    p, _, info = ctx.contact_solve(torch.from_numpy(h).cuda(), pbar, tol=1e-15, max_iter=500)
+    exact = pbar + estar * q * h0 / 2 * np.cos(q * x)[None, :]
+    assert np.max(np.abs(p.cpu().numpy() - exact)) < 1e-13 * pbar
+
+
+def test_flat_surface_elastoplastic_closed_form():
+    """Whole chain (contact, DF-SANE, return map, k = 0, Algorithm 1) on a
+    flat surface under uniform pressure: uniaxial strain closed form."""
+    from paper_1811_11558_amd import EPOptions
+    g = grid_dict(8, 8, 4, lz=0.2)
+    ctx = _ctx(g)
+    st = ctx.new_state()
+    pbar = 0.02
+    infos = ctx.elastoplastic_solve(torch.zeros((8, 8), dtype=torch.float64, device="cuda"),
+                                    [pbar / 3, 2 * pbar / 3, pbar], st,
+                                    EPOptions(tol_outer=1e-12, tol_plastic=1e-13, tol_contact=1e-14))
+    torch.cuda.synchronize()
+    A = np.array([[LAM + 2 * MU, -2 * MU], [2 * MU, -(3 * MU + EH)]])
+    e, a = np.linalg.solve(A, [pbar, SY])
+    sig = st["sigma"].cpu().numpy()
+    epsp = st["eps_p"].cpu().numpy()
+    assert np.max(np.abs(sig[2] + pbar)) < 1e-14
+    assert np.max(np.abs(epsp[2] + a)) < 1e-12 * a
+    assert np.max(np.abs(st["ep"].cpu().numpy() - a)) < 1e-12 * a
+    _say(infos)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hertz_ep_16x16x8.npz")
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_hertz_elastoplastic_matches_stored_oracle(solver):
+    """Paraboloid R = 2 L on 16 x 16 x 8 (lz = 0.25 L), two load steps with
+    Hertz peak pressures of about 2 and 3 times first yield: the GPU
+    Algorithm 1 (DF-SANE or Picard inside) reproduces the oracle's converged
+    state stored by tests/golden/make_golden.py."""
+    from paper_1811_11558_amd import EPOptions
+    ref = np.load(GOLDEN)
+    g = grid_dict(16, 16, 8, lz=0.25)
+    ctx = _ctx(g)
+    st = ctx.new_state()
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                    EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13,
+                                              tol_contact=1e-15, solver=solver, max_plastic=20000))
+    torch.cuda.synchronize()
+    _say(infos)
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < 1e-9, (k, err)

@@ -1,0 +1,227 @@
+"""Pins of the oracle's return map, contact solver, DF-SANE and Algorithm 1
+(CPU only).  Each compares with a closed form, an invariant or an
+independent algorithm (dense active-set QP), not with the oracle itself."""
+import numpy as np
+import pytest
+
+from oracle import contact as oc
+from oracle import coupling as cp
+from oracle import elastic
+from oracle import plasticity as pl
+from synth import grid_dict, paraboloid, rough_surface
+
+E, NU = 1.0, 0.3
+LAM, MU = elastic.lame(E, NU)
+ESTAR = elastic.e_star(E, NU)
+SY, EH = 0.01, 0.1
+
+
+# ------------------------------------------------------------ return map --
+def _rand_state(rng, shape, scale):
+    d_eps = rng.standard_normal((6,) + shape) * scale
+    sig = rng.standard_normal((6,) + shape) * 0.003
+    ep = np.abs(rng.standard_normal(shape)) * 0.01
+    return d_eps, sig, ep
+
+
+def test_return_map_yield_consistency_and_flow_direction():
+    rng = np.random.default_rng(0)
+    d_eps, sig, ep = _rand_state(rng, (200,), 0.004)
+    dep, dp, s1 = pl.return_map(d_eps, sig, ep, E, NU, SY, EH)
+    flow = dp > 0
+    assert 0.2 < flow.mean() < 0.9
+    # on the yield surface of the hardened material after the step
+    fy = pl.von_mises(s1)
+    assert np.max(np.abs(fy[flow] - (SY + EH * (ep + dp))[flow])) < 1e-14 * SY / 1e-2
+    # elastic points stay inside, unchanged
+    sig_tr = sig + elastic.hooke(d_eps, E, NU)
+    assert np.all(pl.von_mises(sig_tr[:, ~flow]) <= SY + EH * ep[~flow] + 1e-16)
+    assert np.array_equal(s1[:, ~flow], sig_tr[:, ~flow])
+    # deviatoric, coaxial with the trial deviator, equivalent strain = dp
+    assert np.max(np.abs(dep[0] + dep[1] + dep[2])) < 1e-17
+    st = sig_tr - (sig_tr[0] + sig_tr[1] + sig_tr[2]) / 3.0 * np.array([1, 1, 1, 0, 0, 0])[:, None]
+    w = elastic.VOIGT_WEIGHT[:, None]
+    cosang = np.sum(w * dep * st, 0)[flow] / np.sqrt(np.sum(w * dep ** 2, 0) * np.sum(w * st ** 2, 0))[flow]
+    assert np.max(np.abs(cosang - 1)) < 1e-14
+    eq = np.sqrt(2.0 / 3.0 * np.sum(w * dep ** 2, 0))
+    assert np.max(np.abs(eq - dp)) < 1e-17
+
+
+def test_return_map_proportional_path_is_step_independent():
+    """Radial return is exact on radial (proportional) deviatoric paths."""
+    d = np.zeros((6, 1))
+    d[3] = 0.02                      # pure shear strain in the 23 plane
+    s0 = np.zeros((6, 1))
+    e0 = np.zeros(1)
+    a_p, a_d, a_s = pl.return_map(d, s0, e0, E, NU, SY, EH)
+    b_p, b_d, b_s = pl.return_map(0.5 * d, s0, e0, E, NU, SY, EH)
+    c_p, c_d, c_s = pl.return_map(0.5 * d, b_s, e0 + b_d, E, NU, SY, EH)
+    assert abs(a_d[0] - (b_d[0] + c_d[0])) < 1e-17
+    assert np.max(np.abs(a_s - c_s)) < 1e-16
+    # closed form for pure shear: tau = sqrt(3) (SY + EH ep)/3, 2 mu (g/2 - dp_shear) = tau
+    gam = 0.02
+    tau_el = 2 * MU * gam
+    dp_closed = (np.sqrt(3) * tau_el - SY) / (3 * MU + EH)
+    assert abs(a_d[0] - dp_closed) < 1e-16
+
+
+# --------------------------------------------------------------- contact --
+def test_contact_full_contact_sinusoid_exact():
+    g = grid_dict(32, 16, 2)
+    x = np.arange(32) / 32
+    q = 2 * np.pi * 2
+    h0 = 1e-3
+    h = np.broadcast_to(h0 * np.cos(q * x)[None, :], (16, 32)).copy()
+    pbar = 1.2 * ESTAR * q * h0 / 2          # enough for full contact
+    p, gap, info = oc.contact_solve(h, pbar, g, E, NU, tol=1e-15, max_iter=200)
+    exact = pbar + ESTAR * q * h0 / 2 * np.cos(q * x)[None, :]
+    assert np.max(np.abs(p - exact)) < 1e-13 * pbar
+    assert info["contact_fraction"] == 1.0
+
+
+def _dense_compliance(g):
+    nx, ny = g['nx'], g['ny']
+    n = nx * ny
+    sym = oc.surface_compliance_symbol(g, E, NU).ravel()
+    jx, jy = np.meshgrid(np.arange(nx), np.arange(ny))
+    kx, ky = np.meshgrid(np.arange(nx), np.arange(ny))
+    pos = np.stack([jx.ravel() / nx, jy.ravel() / ny], 1)
+    kk = np.stack([kx.ravel(), ky.ravel()], 1)
+    F = np.exp(-2j * np.pi * pos @ kk.T)         # (points, modes): forward DFT kernel
+    # u_i = sum_k sym_k exp(+2 pi i k.x_i) (1/n) sum_j exp(-2 pi i k.x_j) p_j
+    return np.real((F.conj() * sym[None, :]) @ F.T) / n
+
+
+def _active_set_qp(M, h, W, dA):
+    """min 1/2 p.Mp - h.p, p >= 0, dA sum p = W, by a primal active-set
+    method with exact KKT solves (dense linear algebra)."""
+    n = len(h)
+    act = np.ones(n, bool)
+    for _ in range(10 * n):
+        idx = np.where(act)[0]
+        m = len(idx)
+        K = np.zeros((m + 1, m + 1))
+        K[:m, :m] = M[np.ix_(idx, idx)]
+        K[:m, m] = -1.0
+        K[m, :m] = dA
+        rhs = np.concatenate([h[idx], [W]])
+        sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
+        p = np.zeros(n)
+        p[idx] = sol[:m]
+        lam = sol[m]
+        if np.any(p[idx] < -1e-14 * W):
+            worst = idx[np.argmin(p[idx])]
+            act[worst] = False
+            continue
+        p = np.maximum(p, 0)
+        g = M @ p - h - lam
+        if np.all(g[~act] >= -1e-13 * np.abs(h).max()):
+            return p
+        add = np.where(~act)[0][np.argmin(g[~act])]
+        act[add] = True
+    raise RuntimeError("active set did not converge")
+
+
+def test_contact_matches_dense_active_set_qp():
+    g = grid_dict(8, 8, 2)
+    h = rough_surface(8, 8, hurst=0.7, k_roll=1, k_cut=3, rms_slope=0.1, seed=3)
+    M = _dense_compliance(g)
+    dA = 1.0 / 64
+    W = 0.002
+    ref = _active_set_qp(M, h.ravel(), W, dA).reshape(8, 8)
+    p, gap, info = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=2000)
+    assert 0 < info["contact_fraction"] < 1
+    assert np.max(np.abs(p - ref)) < 1e-10 * ref.max()
+
+
+def test_contact_kkt_certificate_rough():
+    g = grid_dict(64, 64, 2)
+    h = rough_surface(64, 64, hurst=0.8, k_roll=2, k_cut=16, rms_slope=0.1, seed=1)
+    W = 0.01
+    p, gap, info = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=5000)
+    dA = 1.0 / 64 ** 2
+    assert abs(dA * p.sum() - W) < 1e-15 * W * 64
+    assert np.all(p >= 0)
+    assert info["kkt_residual"] < 1e-11
+    assert 0.01 < info["contact_fraction"] < 0.9
+
+
+@pytest.mark.slow
+def test_contact_hertz_within_discretisation_error():
+    """Paraboloid, a/L ~ 0.1, a/dx ~ 25: Hertz radius and peak pressure."""
+    n = 256
+    g = grid_dict(n, n, 2)
+    R = 1.0
+    h = paraboloid(g, R=R)
+    a_target = 0.1
+    W = 4 * ESTAR * a_target ** 3 / (3 * R)
+    p, gap, info = oc.contact_solve(h, W, g, E, NU, tol=1e-12, max_iter=5000)
+    p0_hertz = (6 * W * ESTAR ** 2 / (np.pi ** 3 * R ** 2)) ** (1 / 3)
+    area = np.count_nonzero(p > 0) / n ** 2
+    a_num = np.sqrt(area / np.pi)
+    assert abs(p.max() / p0_hertz - 1) < 0.02
+    assert abs(a_num / a_target - 1) < 0.02
+
+
+# --------------------------------------------------------------- DF-SANE --
+def test_dfsane_solves_monotone_system():
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(50)
+    F = lambda x: x + 0.5 * x ** 3 - b + 0.1 * np.roll(x, 1)
+    x, Fx, info = cp.dfsane(F, np.zeros(50), lambda a, c: float(a @ c), 1e-13, max_iter=500)
+    assert np.linalg.norm(F(x)) < 1e-13
+    assert info["iters"] < 200
+
+
+# --------------------------------------------------- whole chain, closed --
+def _uniaxial_closed_form(pbar):
+    """Flat surface, uniform pressure: uniaxial strain with J2 + linear hardening.
+    Returns eps33 (total), a (plastic eps33), sigma11."""
+    if pbar * (1 - 2 * NU) / (1 - NU) <= SY:
+        e33 = -pbar / (LAM + 2 * MU)
+        return e33, 0.0, LAM * e33
+    # (lam+2mu)|e| - 2mu|a| = pbar ;  2mu|e| - 3mu|a| = SY + EH |a|
+    A = np.array([[LAM + 2 * MU, -2 * MU], [2 * MU, -(3 * MU + EH)]])
+    e, a = np.linalg.solve(A, [pbar, SY])
+    return -e, -a, -LAM * e + MU * (-a)
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_flat_surface_uniaxial_strain_closed_form(steps):
+    g = grid_dict(8, 8, 4, lz=0.2)
+    mat = dict(E=E, nu=NU, sigma_y0=SY, E_h=EH)
+    pbar = 0.02
+    st = cp.new_state(g)
+    Ws = [pbar * (i + 1) / steps for i in range(steps)]
+    infos = cp.elastoplastic_solve(g, mat, np.zeros((8, 8)), Ws, st, tol_outer=1e-12)
+    e33, a, s11 = _uniaxial_closed_form(pbar)
+    assert np.max(np.abs(st['sigma'][2] + pbar)) < 1e-14
+    assert np.max(np.abs(st['eps_p'][2] - a)) < 1e-13 * abs(a)
+    assert np.max(np.abs(st['eps_p'][0] + a / 2)) < 1e-13 * abs(a)
+    assert np.max(np.abs(st['ep'] - abs(a))) < 1e-13 * abs(a)
+    assert np.max(np.abs(st['sigma'][0] - s11)) < 1e-13 * abs(s11)
+    for inf in infos:
+        assert inf["outer_err"] < 1e-12
+
+
+@pytest.mark.slow
+def test_hertz_elastoplastic_certificates():
+    """Paraboloid beyond first yield: the converged state satisfies yield
+    consistency where the last step flowed, stays inside the yield surface
+    elsewhere, and the contact KKT conditions hold (certificates; the field
+    has no closed form, so parity here is certificate-only)."""
+    g = grid_dict(16, 16, 8, lz=0.25)
+    mat = dict(E=E, nu=NU, sigma_y0=SY, E_h=EH)
+    h = paraboloid(g, R=0.5)
+    st = cp.new_state(g)
+    cp.elastoplastic_solve(g, mat, h, [0.0005], st, tol_outer=1e-10, relax=0.3)
+    ep1 = st['ep'].copy()
+    infos = cp.elastoplastic_solve(g, mat, h, [0.001], st, tol_outer=1e-10, relax=0.3)
+    fy = pl.von_mises(st['sigma'])
+    assert np.all(fy <= SY + EH * st['ep'] + 1e-12)
+    flowed = st['ep'] > ep1
+    assert flowed.any()
+    assert np.max(np.abs(fy[flowed] - (SY + EH * st['ep'][flowed]))) < 1e-10
+    for inf in infos:
+        assert inf["outer_err"] < 1e-10
+        assert inf["contact"]["kkt_residual"] < 1e-9
