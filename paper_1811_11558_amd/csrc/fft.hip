@@ -6,11 +6,14 @@
 //
 //   real field        [P][ny][nx]          (P planes = components x layers)
 //   x-spectrum   X    [P][nx/2+1][ny]      written by x_r2c, read by y_fwd
-//   mode-major   S    [nx/2+1][ny][P]      written by y_fwd, read by the
-//                                          depth pass (all planes of one
-//                                          mode are contiguous)
+//   plane-major  S    [P][nx/2+1][ny]      written by y_fwd (contiguous),
+//                                          read by the depth pass, which
+//                                          gathers the P planes of a mode
+//   mode-major   E    [nx/2+1][ny][P']     written by the depth pass (all
+//                                          planes of a mode contiguous),
+//                                          read by y_inv
 //
-// and the mirror images for the inverse.  Real transforms of length nx are
+// and X again on the way back.  Real transforms of length nx are
 // done two rows at a time as one complex transform (z = a + i b).
 // Forward transforms are unnormalised; the depth pass applies 1/(nx ny).
 #include "common.hpp"
@@ -169,39 +172,39 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
   }
 }
 
-// Forward column transform: X[p][kx][y] -> S[kx][ky][p]; block = up to B
-// planes of one kx (B = tile / ny, planes past NP are zero and not stored).
+// Forward column transform in place order: column c = p * kxh + kx of
+// X[p][kx][y] (contiguous, length ny) -> the same column of S[p][kx][ky].
+// A block transforms B consecutive columns, so it reads and writes one
+// contiguous run; the per-mode gather is left to the depth pass's reads.
 template <typename T, int LOGN>
-__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
-                                             int NP, const cpx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int ncols,
+                                             const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
-  const int npb = (NP + B - 1) / B;
-  const int kx = blockIdx.x / npb;
-  const int p0 = (blockIdx.x - kx * npb) * B;
-  const int nb = min(B, NP - p0);
+  const size_t c0 = (size_t)blockIdx.x * B;
+  const int nb = (int)min((size_t)B, (size_t)ncols - c0);
+  const cpx<T>* src = in + c0 * N;
+  cpx<T>* dst = out + c0 * N;
   constexpr int MV = (B * N + NT - 1) / NT;
   cpx<T> v[MV];
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
-    int b = i >> LOGN, y = i & (N - 1);
-    if (i < B * N && b < nb) v[u] = in[((size_t)(p0 + b) * kxh + kx) * N + y];
+    if (i < nb * N) v[u] = src[i];
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
-    int b = i >> LOGN, y = i & (N - 1);
-    if (i < B * N && b < nb) buf[b * ld + y] = v[u];
+    if (i < nb * N) buf[(i >> LOGN) * ld + (i & (N - 1))] = v[u];
   }
   __syncthreads();
   lds_fft<T, LOGN, B, false>(buf, ld, nb, tw);
-  const int tot = nb * N;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int ky = i / nb, b = i - ky * nb;
-    out[((size_t)kx * N + ky) * NP + p0 + b] = buf[b * ld + ky];
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    int i = threadIdx.x + u * NT;
+    if (i < nb * N) dst[i] = buf[(i >> LOGN) * ld + (i & (N - 1))];
   }
 }
 
@@ -327,8 +330,9 @@ template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
                         hipStream_t st) {
   int B = cols_per_block<T>(ny);
-  dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, tw)
+  const int ncols = NP * kxh;
+  dim3 grid((unsigned)((ncols + B - 1) / B));
+#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, ncols, tw)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();

@@ -26,8 +26,8 @@ hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny
                         double scale, const cpx<T>* tw, hipStream_t st);
 
 // Per-mode depth pass.  Input spectrum (unnormalised DFT of the plastic
-// strain) in mode-major layout in[mode][6][nz]; traction spectrum
-// tin[mode][3]; output out[mode][np_out] holding the requested fields at
+// strain) in plane-major layout in[c][z][mode] (mode = kx * ny + ky);
+// traction spectrum tin[c][mode]; output out[mode][np_out] holding the requested fields at
 // plane offsets off_* (negative = not requested): strain and stress as
 // [6][nz], displacement as [3][nz], surface u3 as one plane.
 struct DepthParams {
