@@ -44,6 +44,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-modes", type=int, default=4096,
                     help="modes of the oracle sample for the CPU baseline")
+    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy"],
+                    help="operator: the fused operator (the headline line); serve: Poisson-arrival "
+                         "elastoplastic solves of mixed grids through the batching server; solve: the "
+                         "32x32x16 paraboloid elastoplastic solve; copy: a plain device copy of known size "
+                         "(reference for hardware counters)")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
+    ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals per second (0 = all at once)")
     return ap.parse_args()
 
 
@@ -127,12 +135,108 @@ def cpu_baseline(g, eps, t, nmodes_sample):
                                                times[1], t_full)}
 
 
+def bench_copy(a):
+    """A plain device-to-device copy of 400 MB, for scaling hardware byte
+    counters (FETCH_SIZE / WRITE_SIZE) to bytes."""
+    import torch
+    n = 50_000_000
+    x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(a.warmup):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / a.steps
+    print(json.dumps({"metric": "copy GB/s", "value": 2 * 8 * n / (ms * 1e-3) / 1e9, "unit": "GB/s",
+                      "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n,
+                      "ms_per_step": ms, "steps": a.steps, "n_gpus": 1}))
+
+
+def bench_solve(a):
+    """Elastoplastic paraboloid solve, 32 x 32 x 16 (R = 0.5 L, lz = 0.25 L,
+    E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1), cumulative loads up to
+    W = 0.02 in 10 equal steps."""
+    import torch
+    from paper_1811_11558_amd import Context, EPOptions
+    from synth import grid_dict, paraboloid
+    g = grid_dict(32, 32, 16, 1.0, 1.0, 0.25)
+    h = torch.from_numpy(paraboloid(g, R=0.5)).cuda()
+    Ws = [0.002 * (i + 1) for i in range(10)]
+    opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, max_outer=2000,
+                     max_plastic=20000)
+    times, infos = [], None
+    for _ in range(max(1, a.steps)):
+        ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=a.precision)
+        st = ctx.new_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = ctx.elastoplastic_solve(h, Ws, st, opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ctx.close()
+    ev = sum(i["r_evals"] for i in infos)
+    print(json.dumps({"metric": "elastoplastic solve time", "value": float(np.median(times)), "unit": "s",
+                      "higher_is_better": False, "n_gpus": 1, "steps": len(times),
+                      "config": {"workload": "paraboloid 32x32x16, W=0.02 in 10 steps", "precision": a.precision},
+                      "outer_iters": [i["outer_iters"] for i in infos], "residual_evals": ev,
+                      "voxel_updates_per_s": ev * 32 * 32 * 16 / float(np.median(times))}))
+
+
+def bench_serve(a):
+    """Seeded Poisson-arrival elastoplastic contact solves of mixed grids
+    (64^2 x 32, 128^2 x 64, 256^2 x 64, 512^2 x 96; rough surfaces with Hurst
+    exponent in [0.5, 0.9]) through the batching server; one load step each,
+    FP32 kernels with float64 refinement, outer tolerance 1e-7."""
+    from paper_1811_11558_amd import Server, EPOptions
+    from synth import grid_dict, poisson_requests, rough_surface
+    reqs = poisson_requests(n=a.requests, rate=a.rate if a.rate > 0 else 1e9, seed=2024)
+    prepared = []
+    for r in reqs:
+        g = grid_dict(r["nx"], r["ny"], r["nz"], 1.0, 1.0, 0.25)
+        h = rough_surface(r["nx"], r["ny"], hurst=r["hurst"], k_roll=4, k_cut=r["nx"] // 4, rms_slope=0.1,
+                          seed=r["seed"])
+        prepared.append((r, g, h))
+    opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
+                     max_plastic=20000)
+    srv = Server(hbm_budget_bytes=200 << 30, max_slots=a.slots)
+    t0 = time.perf_counter()
+    ids = []
+    for r, g, h in prepared:
+        if a.rate > 0:
+            dt = r["arrival"] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+        ids.append(srv.submit(g, h, [r["pbar"]], precision="fp32_refined", opts=opts))
+    res = [srv.wait(i, (g["ny"], g["nx"])) for i, (_, g, _) in zip(ids, prepared)]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([x["t_done"] - x["t_submit"] for x in res])
+    ok = [x["status"] == 0 for x in res]
+    vox = sum(r["nx"] * r["ny"] * r["nz"] * x["info"]["r_evals"] for (r, _, _), x in zip(prepared, res))
+    print(json.dumps({"metric": "served solves/s", "value": len(res) / wall, "unit": "solves/s",
+                      "higher_is_better": True, "n_gpus": 1, "requests": len(res), "ok": int(sum(ok)),
+                      "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                      "voxel_updates_per_s": vox / wall, "wall_s": wall, "peak_bytes": st["peak_bytes"],
+                      "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": a.slots,
+                                 "rate_per_s": a.rate, "precision": "fp32_refined"}}))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.workload == "copy":
+        return bench_copy(a)
+    if a.workload == "solve":
+        return bench_solve(a)
+    if a.workload == "serve":
+        return bench_serve(a)
     import torch
     from paper_1811_11558_amd import Context
     from synth import filtered_eigenstrain, filtered_traction, grid_dict

@@ -234,6 +234,66 @@ int fvim_set_option(fvim_ctx* ctx, int key, int value);
 int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);
 
+/*
+ * Continuous-batching solve server.
+ *
+ * A request is one elastoplastic contact solve (Algorithm 1 over n_steps
+ * cumulative loads) on its own grid; its inputs are copied at submission.
+ * Admission: a request starts when one of max_slots worker slots is free and
+ * its device footprint (fvim_request_bytes) fits in what remains of
+ * hbm_budget_bytes; the first pending request in submission order that fits
+ * is taken.  Each slot runs on its own HIP stream (default priority), so
+ * admitted requests overlap on the device while others keep arriving.  State
+ * stays in device memory from admission to completion.  A request's result
+ * does not depend on the other requests in flight (same kernels, own context,
+ * default depth-pass layout, deterministic reductions).
+ * Times are seconds since the server was created.  Results stay owned by the
+ * server until fvim_server_release.  Thread-safe.
+ */
+#define FVIM_MAX_STEPS 16
+typedef struct {
+  fvim_grid grid;
+  fvim_material mat;
+  int precision;
+  int n_steps;
+  double W_steps[FVIM_MAX_STEPS];
+  fvim_ep_opts opts;
+  const double* h;           /* HOST pointer [ny][nx], copied at submission */
+} fvim_request;
+
+typedef struct {
+  int status;                /* FVIM_OK or the solve's error code           */
+  double t_submit, t_admit, t_done;
+  fvim_ep_info info;         /* of the last load step                       */
+  double contact_fraction;   /* of the final pressure                       */
+  const double* p;           /* HOST [ny][nx] final contact pressure        */
+  const double* u3p;         /* HOST [ny][nx] final surface residual disp.  */
+} fvim_result;
+
+typedef struct {
+  int pending, running;
+  uint64_t completed;
+  size_t bytes_in_use, peak_bytes, budget;
+} fvim_server_stats;
+
+typedef struct fvim_server fvim_server;
+
+/* Index of the request the admission rule takes from pending footprints
+ * (first that fits in budget - in_use), or -1.  Pure function. */
+int fvim_admit_index(const size_t* pending_bytes, int n, size_t budget, size_t in_use);
+/* Device bytes a request holds while it runs (0 for an invalid grid). */
+size_t fvim_request_bytes(const fvim_request* r);
+int fvim_server_create(size_t hbm_budget_bytes, int max_slots, int device, fvim_server** out);
+/* FVIM_ENOMEM if the request can never fit the budget. */
+int fvim_server_submit(fvim_server* s, const fvim_request* r, uint64_t* id);
+/* Returns 1 and fills out when done, 0 while pending or running (wait = 1
+ * blocks until done), or a negative error code for an unknown id. */
+int fvim_server_poll(fvim_server* s, uint64_t id, int wait, fvim_result* out);
+int fvim_server_release(fvim_server* s, uint64_t id);
+int fvim_server_get_stats(fvim_server* s, fvim_server_stats* out);
+/* Finishes every submitted request, then frees the server. */
+void fvim_server_destroy(fvim_server* s);
+
 #ifdef __cplusplus
 }
 #endif

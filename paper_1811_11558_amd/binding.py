@@ -66,6 +66,26 @@ class _EPInfo(ctypes.Structure):
                 ("kkt", ctypes.c_double)]
 
 
+MAX_STEPS = 16
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("mat", _Material), ("precision", ctypes.c_int),
+                ("n_steps", ctypes.c_int), ("W_steps", ctypes.c_double * MAX_STEPS),
+                ("opts", EPOptions), ("h", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("info", _EPInfo), ("contact_fraction", ctypes.c_double),
+                ("p", ctypes.c_void_p), ("u3p", ctypes.c_void_p)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int), ("running", ctypes.c_int), ("completed", ctypes.c_uint64),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget", ctypes.c_size_t)]
+
+
 _LIB = None
 _P = ctypes.c_void_p
 
@@ -101,6 +121,17 @@ def load_library(path=None):
     lib.elastoplastic_solve.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(EPOptions), ctypes.POINTER(_State),
                                         ctypes.POINTER(_EPInfo)]
+    lib.fvim_admit_index.argtypes = [ctypes.POINTER(ctypes.c_size_t), ctypes.c_int, ctypes.c_size_t,
+                                     ctypes.c_size_t]
+    lib.fvim_request_bytes.argtypes = [ctypes.POINTER(_Request)]
+    lib.fvim_request_bytes.restype = ctypes.c_size_t
+    lib.fvim_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)]
+    lib.fvim_server_submit.argtypes = [_P, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.fvim_server_poll.argtypes = [_P, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(_Result)]
+    lib.fvim_server_release.argtypes = [_P, ctypes.c_uint64]
+    lib.fvim_server_get_stats.argtypes = [_P, ctypes.POINTER(_ServerStats)]
+    lib.fvim_server_destroy.argtypes = [_P]
+    lib.fvim_server_destroy.restype = None
     _LIB = lib
     return lib
 
@@ -316,3 +347,99 @@ def contact_solve(ctx, h, W, **kw):
 
 def elastoplastic_solve(ctx, h, W_steps, state, opts=None):
     return ctx.elastoplastic_solve(h, W_steps, state, opts)
+
+
+def admit_index(pending_bytes, budget, in_use):
+    """The server's admission rule (pure): index of the first pending request
+    whose footprint fits in budget - in_use, or -1."""
+    lib = load_library()
+    arr = (ctypes.c_size_t * max(1, len(pending_bytes)))(*pending_bytes)
+    return lib.fvim_admit_index(arr, len(pending_bytes), int(budget), int(in_use))
+
+
+def make_request(grid, h, W_steps, E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1, precision="fp64", opts=None):
+    import numpy as np
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    if h.shape != (grid["ny"], grid["nx"]):
+        raise FvimError(FVIM_EINVAL, "h must have shape (ny, nx)")
+    if not 1 <= len(W_steps) <= MAX_STEPS:
+        raise FvimError(FVIM_EINVAL, "between 1 and %d load steps" % MAX_STEPS)
+    r = _Request()
+    r.grid = _Grid(int(grid["nx"]), int(grid["ny"]), int(grid["nz"]), float(grid["lx"]), float(grid["ly"]),
+                   float(grid["lz"]))
+    r.mat = _Material(float(E), float(nu), float(sigma_y0), float(E_h))
+    r.precision = PRECISION[precision]
+    r.n_steps = len(W_steps)
+    for i, w in enumerate(W_steps):
+        r.W_steps[i] = float(w)
+    r.opts = opts or EPOptions()
+    r.h = h.ctypes.data
+    return r, h
+
+
+def request_bytes(grid, precision="fp64"):
+    import numpy as np
+    lib = load_library()
+    r, _ = make_request(grid, np.zeros((grid["ny"], grid["nx"])), [1.0], precision=precision)
+    return lib.fvim_request_bytes(ctypes.byref(r))
+
+
+class Server:
+    """Continuous-batching solve server (see fvim.h): requests are admitted by
+    free slot and HBM footprint and run concurrently on their own streams."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=4, device=0):
+        lib = load_library()
+        self._s = _P()
+        _check(lib.fvim_server_create(int(hbm_budget_bytes), int(max_slots), int(device), ctypes.byref(self._s)))
+
+    def submit(self, grid, h, W_steps, **kw):
+        r, keep = make_request(grid, h, W_steps, **kw)
+        rid = ctypes.c_uint64()
+        _check(_LIB.fvim_server_submit(self._s, ctypes.byref(r), ctypes.byref(rid)))
+        del keep
+        return rid.value
+
+    def poll(self, rid, wait=False):
+        """None while pending or running; else a dict with the result (arrays copied)."""
+        import numpy as np
+        res = _Result()
+        rc = _LIB.fvim_server_poll(self._s, ctypes.c_uint64(rid), 1 if wait else 0, ctypes.byref(res))
+        if rc < 0:
+            _check(rc)
+        if rc == 0:
+            return None
+        out = {f: getattr(res, f) for f in ("status", "t_submit", "t_admit", "t_done", "contact_fraction")}
+        out["info"] = {f: getattr(res.info, f) for f, _ in _EPInfo._fields_}
+        out["p"] = out["u3p"] = None
+        return out, res
+
+    def result_arrays(self, res, shape):
+        import numpy as np
+        n = shape[0] * shape[1]
+        p = np.ctypeslib.as_array((ctypes.c_double * n).from_address(res.p)).reshape(shape).copy()
+        u = np.ctypeslib.as_array((ctypes.c_double * n).from_address(res.u3p)).reshape(shape).copy()
+        return p, u
+
+    def wait(self, rid, shape):
+        out, res = self.poll(rid, wait=True)
+        if out["status"] == 0:
+            out["p"], out["u3p"] = self.result_arrays(res, shape)
+        _check(_LIB.fvim_server_release(self._s, ctypes.c_uint64(rid)))
+        return out
+
+    def stats(self):
+        st = _ServerStats()
+        _check(_LIB.fvim_server_get_stats(self._s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
+
+    def close(self):
+        if self._s:
+            _LIB.fvim_server_destroy(self._s)
+            self._s = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -150,6 +150,9 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   prm.has_w = eps_p != nullptr;
   prm.has_t = traction != nullptr;
   prm.k0_include = c->k0_policy == FVIM_K0_INCLUDE;
+  // in float32 the mean mode is formed in float64 from float64 plane sums
+  const bool k0x = sizeof(T) == 4;
+  prm.k0_external = k0x ? 1 : 0;
   int np = 0;
   OutSegments seg;
   seg.n = 0;
@@ -174,6 +177,18 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
     rc = ctx_reserve(c, &c->tB, &c->tB_bytes, tbytes);
     if (rc) return rc;
   }
+  const int wbpp = x_r2c_blocks_per_plane<T>(nx, ny);
+  double* wsum = nullptr;
+  double* tsum = nullptr;
+  double* padd = nullptr;
+  if (k0x) {
+    const size_t kb = sizeof(double) * ((size_t)(6 * nz + 3) * wbpp + (size_t)np);
+    rc = ctx_reserve(c, &c->k0buf, &c->k0buf_bytes, kb);
+    if (rc) return rc;
+    wsum = (double*)c->k0buf;
+    tsum = wsum + (size_t)6 * nz * wbpp;
+    padd = tsum + (size_t)3 * wbpp;
+  }
   const cpx<T>* twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
   const cpx<T>* twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
   cpx<T>* A = (cpx<T>*)c->bufA;
@@ -183,7 +198,8 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   StageTimer tm(c);
   if (eps_p) {
     tm.begin(FVIM_STAGE_XFWD);
-    if ((e = launch_x_r2c<T>(eps_p, A, nx, ny, (size_t)6 * nz, twx, st)) != hipSuccess) return fail_hip(e, "x_r2c");
+    if ((e = launch_x_r2c<T>(eps_p, A, nx, ny, (size_t)6 * nz, twx, st, wsum)) != hipSuccess)
+      return fail_hip(e, "x_r2c");
     tm.end();
     tm.begin(FVIM_STAGE_YFWD);
     if ((e = launch_y_fwd<T>(A, B, ny, kxh, 6 * nz, twy, st)) != hipSuccess) return fail_hip(e, "y_fwd");
@@ -191,7 +207,7 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   }
   if (traction) {
     tm.begin(FVIM_STAGE_XFWD_T);
-    if ((e = launch_x_r2c<T>(traction, (cpx<T>*)c->tA, nx, ny, 3, twx, st)) != hipSuccess)
+    if ((e = launch_x_r2c<T>(traction, (cpx<T>*)c->tA, nx, ny, 3, twx, st, tsum)) != hipSuccess)
       return fail_hip(e, "x_r2c(t)");
     tm.end();
     tm.begin(FVIM_STAGE_YFWD_T);
@@ -208,11 +224,15 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st)) != hipSuccess)
     return fail_hip(e, "depth");
   tm.end();
+  if (k0x) {
+    if ((e = launch_k0_fields(wsum, wbpp, tsum, wbpp, padd, prm, st)) != hipSuccess) return fail_hip(e, "k0");
+  }
   tm.begin(FVIM_STAGE_YINV);
   if ((e = launch_y_inv<T>(A, B, ny, kxh, np, twy, st)) != hipSuccess) return fail_hip(e, "y_inv");
   tm.end();
   tm.begin(FVIM_STAGE_XINV);
-  if ((e = launch_x_c2r<T>(B, seg, nx, ny, (size_t)np, 1.0, twx, st)) != hipSuccess) return fail_hip(e, "x_c2r");
+  if ((e = launch_x_c2r<T>(B, seg, nx, ny, (size_t)np, 1.0, twx, st, padd)) != hipSuccess)
+    return fail_hip(e, "x_c2r");
   tm.end();
   return FVIM_OK;
 }
@@ -224,7 +244,7 @@ int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, dou
   if (misaligned(eps_p) || misaligned(traction) || misaligned(strain) || misaligned(stress) ||
       misaligned(disp) || misaligned(surf_u3))
     return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
-  if (c->precision == FVIM_FP32_REFINED)
+  if (c->precision == FVIM_FP32_REFINED && !c->force_fp64)
     return operator_apply_t<float>(c, eps_p, traction, strain, stress, disp, surf_u3);
   return operator_apply_t<double>(c, eps_p, traction, strain, stress, disp, surf_u3);
 }
@@ -287,7 +307,7 @@ void fvim_destroy(fvim_ctx* c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->tA, c->tB};
+  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->tA, c->tB, c->k0buf};
   for (void* p : ptrs)
     if (p) hipFree(p);
   solver_release(c);
@@ -362,7 +382,8 @@ int fvim_set_stream(fvim_ctx* c, void* hip_stream) {
 size_t fvim_footprint_bytes(const fvim_grid* g, int precision, int with_solver_state) {
   if (check_grid(g)) return 0;
   const size_t nmodes = (size_t)(g->nx / 2 + 1) * g->ny;
-  const size_t csz = precision == FVIM_FP32_REFINED ? 8 : 16;
+  // the solvers of the FP32_REFINED mode also apply the float64 operator
+  const size_t csz = (precision == FVIM_FP32_REFINED && !with_solver_state) ? 8 : 16;
   const size_t planes = 15 * (size_t)g->nz + 1;
   size_t b = 2 * planes * nmodes * csz + 6 * nmodes * csz;
   const size_t V = (size_t)g->nx * g->ny * g->nz;

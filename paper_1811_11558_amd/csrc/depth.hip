@@ -32,10 +32,8 @@
 //
 // Threads: LPM lanes per mode, P consecutive depth nodes per lane; the
 // recurrences run sequentially inside a lane and as Kogge-Stone scans across
-// the LPM lanes (log2(LPM) shuffle steps).  The input is plane-major (the
-// lane groups of a block read consecutive modes of each plane, so a block's
-// reads of one plane form one contiguous run); the output is mode-major (the
-// nz values of one component of one mode are contiguous).
+// the LPM lanes (log2(LPM) shuffle steps).  Input and output are mode-major,
+// so the nz values of one component of one mode are contiguous.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -165,8 +163,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
   }
   const int mode = kx * prm.ny + ky;
   const int nz = prm.nz;
-  const size_t nmodes = (size_t)prm.kxh * prm.ny;   // plane stride of the input
-  const cpx<T>* __restrict__ src = in + mode;       // element (c, z) at src[(c * nz + z) * nmodes]
+  const cpx<T>* __restrict__ src = in + (size_t)mode * 6 * nz;
   cpx<T>* __restrict__ dst = out + (size_t)mode * prm.np_out;
   const T nrm = (T)prm.norm;
   const T kap = (T)prm.kappa;
@@ -178,7 +175,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
 
   cpx<T> tr[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) tr[c] = prm.has_t ? scl(tin[(size_t)c * nmodes + mode], nrm / mu) : zero<T>();
+  for (int c = 0; c < 3; ++c) tr[c] = prm.has_t ? scl(tin[(size_t)mode * 3 + c], nrm / mu) : zero<T>();
 
   // strain e (original frame, 6 comps) of node i -> outputs (stress needs eps_p again)
   auto emit = [&](int i, const cpx<T> e[6], bool first, T wgt) {
@@ -189,7 +186,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
     if (wantX) {
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? scl(src[((size_t)c * nz + i) * nmodes], nrm) : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? scl(src[(size_t)c * nz + i], nrm) : zero<T>();
       cpx<T> tre = add(add(e[0], e[1]), e[2]);
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
 #pragma unroll
@@ -210,14 +207,25 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
       if (i >= nz) continue;
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? src[((size_t)c * nz + i) * nmodes] : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? src[(size_t)c * nz + i] : zero<T>();
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
       cpx<T> w33 = scl(axpy(scl(trp, kap), T(2), ep[2]), nrm);     // w33 / mu
       cpx<T> e[6] = {zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>()};
       e[4] = sub(scl(ep[4], nrm), scl(tr[0], T(0.5) * tk));        // e13
       e[3] = sub(scl(ep[3], nrm), scl(tr[1], T(0.5) * tk));        // e23
       e[2] = scl(sub(w33, scl(tr[2], tk)), T(1) / kp2);             // e33
-      emit(i, e, true, T(1));
+      if (prm.k0_external) {          // the caller adds this mode in float64
+        if (wantS) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) dst[prm.off_strain + (size_t)c * nz + i] = zero<T>();
+        }
+        if (wantX) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) dst[prm.off_stress + (size_t)c * nz + i] = zero<T>();
+        }
+      } else {
+        emit(i, e, true, T(1));
+      }
       if (DISP) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -262,7 +270,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
       const int i = i0 + p;
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = (prm.has_w && i < nz) ? src[((size_t)c * nz + i) * nmodes] : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = (prm.has_w && i < nz) ? src[(size_t)c * nz + i] : zero<T>();
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
       cpx<T> exx = add(add(scl(ep[0], n1 * n1), scl(ep[5], T(2) * n1 * n2)), scl(ep[1], n2 * n2));
       cpx<T> exe = add(add(scl(ep[0], -n1 * n2), scl(ep[5], n1 * n1 - n2 * n2)), scl(ep[1], n1 * n2));

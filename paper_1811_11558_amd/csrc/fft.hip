@@ -6,14 +6,11 @@
 //
 //   real field        [P][ny][nx]          (P planes = components x layers)
 //   x-spectrum   X    [P][nx/2+1][ny]      written by x_r2c, read by y_fwd
-//   plane-major  S    [P][nx/2+1][ny]      written by y_fwd (contiguous),
-//                                          read by the depth pass, which
-//                                          gathers the P planes of a mode
-//   mode-major   E    [nx/2+1][ny][P']     written by the depth pass (all
-//                                          planes of a mode contiguous),
-//                                          read by y_inv
+//   mode-major   S    [nx/2+1][ny][P]      written by y_fwd, read by the
+//                                          depth pass (all planes of one
+//                                          mode are contiguous)
 //
-// and X again on the way back.  Real transforms of length nx are
+// and the mirror images for the inverse.  Real transforms of length nx are
 // done two rows at a time as one complex transform (z = a + i b).
 // Forward transforms are unnormalised; the depth pass applies 1/(nx ny).
 #include "common.hpp"
@@ -126,9 +123,11 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T
 // Rows of nx = 2^LOGN reals -> half spectra.  Block = R consecutive rows of
 // one plane (R even, R | ny), two rows per complex sequence.  Output
 // X[(plane * kxh + k) * ny + y].
+// If bsum is not NULL, block b also writes the float64 sum of its R rows to
+// bsum[b] (the plane means of the mean mode are then formed in float64).
 template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx<T>* __restrict__ out, int ny,
-                                             int R, const cpx<T>* __restrict__ tw) {
+                                             int R, const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
   constexpr int N = 1 << LOGN;
   constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
@@ -157,6 +156,22 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
       else { d[0].x = (T)v[u].x; d[1].x = (T)v[u].y; }
     }
   }
+  if (bsum) {
+    __shared__ double red[NT];
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < MV; ++u) {
+      int i = threadIdx.x + u * NT;
+      if (i < tot) acc += v[u].x + v[u].y;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+  }
   __syncthreads();
   lds_fft<T, LOGN, SEQ, false>(buf, ld, R / 2, tw);
   const int tot2 = kxh * R;
@@ -172,39 +187,39 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
   }
 }
 
-// Forward column transform in place order: column c = p * kxh + kx of
-// X[p][kx][y] (contiguous, length ny) -> the same column of S[p][kx][ky].
-// A block transforms B consecutive columns, so it reads and writes one
-// contiguous run; the per-mode gather is left to the depth pass's reads.
+// Forward column transform: X[p][kx][y] -> S[kx][ky][p]; block = up to B
+// planes of one kx (B = tile / ny, planes past NP are zero and not stored).
 template <typename T, int LOGN>
-__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int ncols,
-                                             const cpx<T>* __restrict__ tw) {
+__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
+                                             int NP, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
-  const size_t c0 = (size_t)blockIdx.x * B;
-  const int nb = (int)min((size_t)B, (size_t)ncols - c0);
-  const cpx<T>* src = in + c0 * N;
-  cpx<T>* dst = out + c0 * N;
+  const int npb = (NP + B - 1) / B;
+  const int kx = blockIdx.x / npb;
+  const int p0 = (blockIdx.x - kx * npb) * B;
+  const int nb = min(B, NP - p0);
   constexpr int MV = (B * N + NT - 1) / NT;
   cpx<T> v[MV];
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
-    if (i < nb * N) v[u] = src[i];
+    int b = i >> LOGN, y = i & (N - 1);
+    if (i < B * N && b < nb) v[u] = in[((size_t)(p0 + b) * kxh + kx) * N + y];
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
-    if (i < nb * N) buf[(i >> LOGN) * ld + (i & (N - 1))] = v[u];
+    int b = i >> LOGN, y = i & (N - 1);
+    if (i < B * N && b < nb) buf[b * ld + y] = v[u];
   }
   __syncthreads();
   lds_fft<T, LOGN, B, false>(buf, ld, nb, tw);
-#pragma unroll
-  for (int u = 0; u < MV; ++u) {
-    int i = threadIdx.x + u * NT;
-    if (i < nb * N) dst[i] = buf[(i >> LOGN) * ld + (i & (N - 1))];
+  const int tot = nb * N;
+  for (int i = threadIdx.x; i < tot; i += NT) {
+    int ky = i / nb, b = i - ky * nb;
+    out[((size_t)kx * N + ky) * NP + p0 + b] = buf[b * ld + ky];
   }
 }
 
@@ -238,9 +253,12 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
 
 // Half spectra -> rows of nx = 2^LOGN reals, two rows per complex transform.
 // Plane p of the input goes to the output segment that contains it.
+// If padd is not NULL, padd[plane] (float64) is added to every output value
+// of that plane (the mean mode computed in float64).
 template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
-                                             double scale, const cpx<T>* __restrict__ tw) {
+                                             double scale, const cpx<T>* __restrict__ tw,
+                                             const double* __restrict__ padd) {
   constexpr int N = 1 << LOGN;
   constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
@@ -268,14 +286,15 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
   int s = 0;
   while (s + 1 < seg.n && plane >= seg.first[s + 1]) ++s;
   double* dst = seg.ptr[s] + ((size_t)(plane - seg.first[s]) * ny + y0) * N;
+  const double add = padd ? padd[plane] : 0.0;
   const int tot2 = R * N / 2;
   double2* d2 = reinterpret_cast<double2*>(dst);
   for (int i = threadIdx.x; i < tot2; i += NT) {
     int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
     const cpx<T>* b = buf + (r >> 1) * ld + x;
     double2 o;
-    if (r & 1) { o.x = (double)b[0].y * scale; o.y = (double)b[1].y * scale; }
-    else { o.x = (double)b[0].x * scale; o.y = (double)b[1].x * scale; }
+    if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
+    else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
     d2[i] = o;
   }
 }
@@ -316,11 +335,16 @@ int ilog2(int n) { return 31 - __builtin_clz((unsigned)n); }
 }  // namespace
 
 template <typename T>
+int x_r2c_blocks_per_plane(int nx, int ny) {
+  return ny / rows_per_block<T>(nx, ny);
+}
+
+template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st) {
+                        hipStream_t st, double* bsum) {
   int R = rows_per_block<T>(nx, ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, in, out, ny, R, tw)
+#define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, in, out, ny, R, tw, bsum)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
@@ -330,9 +354,8 @@ template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
                         hipStream_t st) {
   int B = cols_per_block<T>(ny);
-  const int ncols = NP * kxh;
-  dim3 grid((unsigned)((ncols + B - 1) / B));
-#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, ncols, tw)
+  dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
+#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, tw)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();
@@ -351,19 +374,21 @@ hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
-                        double scale, const cpx<T>* tw, hipStream_t st) {
+                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd) {
   int R = rows_per_block<T>(nx, ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw)
+#define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 template hipError_t launch_x_r2c<double>(const double*, cpx<double>*, int, int, size_t, const cpx<double>*,
-                                         hipStream_t);
+                                         hipStream_t, double*);
 template hipError_t launch_x_r2c<float>(const double*, cpx<float>*, int, int, size_t, const cpx<float>*,
-                                        hipStream_t);
+                                        hipStream_t, double*);
+template int x_r2c_blocks_per_plane<double>(int, int);
+template int x_r2c_blocks_per_plane<float>(int, int);
 template hipError_t launch_y_fwd<double>(const cpx<double>*, cpx<double>*, int, int, int, const cpx<double>*,
                                          hipStream_t);
 template hipError_t launch_y_fwd<float>(const cpx<float>*, cpx<float>*, int, int, int, const cpx<float>*,
@@ -373,8 +398,8 @@ template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, 
 template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, const cpx<float>*,
                                         hipStream_t);
 template hipError_t launch_x_c2r<double>(const cpx<double>*, const OutSegments&, int, int, size_t, double,
-                                         const cpx<double>*, hipStream_t);
+                                         const cpx<double>*, hipStream_t, const double*);
 template hipError_t launch_x_c2r<float>(const cpx<float>*, const OutSegments&, int, int, size_t, double,
-                                        const cpx<float>*, hipStream_t);
+                                        const cpx<float>*, hipStream_t, const double*);
 
 }  // namespace fvim

@@ -12,22 +12,27 @@ struct OutSegments {
   double* ptr[4];
 };
 
+// bsum (optional): float64 sum of the rows of each block, blocks of a plane
+// consecutive (x_r2c_blocks_per_plane of them).
 template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st);
+                        hipStream_t st, double* bsum = nullptr);
+template <typename T>
+int x_r2c_blocks_per_plane(int nx, int ny);
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
                         hipStream_t st);
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
                         hipStream_t st);
+// padd (optional): float64 constant added to each plane of the output.
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
-                        double scale, const cpx<T>* tw, hipStream_t st);
+                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr);
 
 // Per-mode depth pass.  Input spectrum (unnormalised DFT of the plastic
-// strain) in plane-major layout in[c][z][mode] (mode = kx * ny + ky);
-// traction spectrum tin[c][mode]; output out[mode][np_out] holding the requested fields at
+// strain) in mode-major layout in[mode][6][nz]; traction spectrum
+// tin[mode][3]; output out[mode][np_out] holding the requested fields at
 // plane offsets off_* (negative = not requested): strain and stress as
 // [6][nz], displacement as [3][nz], surface u3 as one plane.
 struct DepthParams {
@@ -36,6 +41,7 @@ struct DepthParams {
   double mu, kappa;       // shear modulus, lambda / mu
   double norm;            // 1 / (nx ny)
   int has_w, has_t, k0_include;
+  int k0_external;        // 1: the mean mode is added by the caller in float64; write 0 here
   int np_out;
   int off_strain, off_stress, off_disp, off_u3;
 };
@@ -46,6 +52,12 @@ hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const 
 int depth_num_configs();
 bool depth_config_valid(int id, int nz);
 int depth_default_config(int nz);
+
+// Mean-mode (k = 0) fields in float64 from the block sums of the input
+// planes: out[plane] for every output plane (strain, stress, displacement,
+// surface u3 segments as in DepthParams).
+hipError_t launch_k0_fields(const double* wsum, int wblocks, const double* tsum, int tblocks, double* out,
+                            const DepthParams& p, hipStream_t st);
 
 // Pointwise kernels (float64).
 hipError_t launch_return_map(const double* d_eps, const double* sig_n, const double* ep_n, double* d_eps_p,

@@ -49,7 +49,64 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
   }
 }
 
+// Mean-mode fields in float64 (precision FP32_REFINED).  One thread per
+// depth node: sums the block partials of the 6 eigenstrain planes of that
+// node (and of the 3 traction planes) in a fixed order, forms the laterally
+// uniform response (sigma . e3 = -t_mean, eps13 = (w13 - t1)/(2 mu),
+// eps23 = (w23 - t2)/(2 mu), eps33 = (w33 - t3)/(lambda + 2 mu), other
+// strains 0, displacement 0) and writes one constant per output plane.
+__global__ __launch_bounds__(NT) void k_k0_fields(const double* __restrict__ wsum, int wblocks,
+                                                 const double* __restrict__ tsum, int tblocks,
+                                                 double* __restrict__ out, DepthParams p) {
+  const int z = blockIdx.x * NT + threadIdx.x;
+  const int nz = p.nz;
+  if (z >= nz) return;
+  const double inv = p.norm;                      // 1 / (nx ny)
+  const double mu = p.mu, lam = p.kappa * p.mu;
+  double e[6] = {0, 0, 0, 0, 0, 0};
+  double w[6] = {0, 0, 0, 0, 0, 0};
+  if (p.has_w) {
+    double ep[6];
+    for (int c = 0; c < 6; ++c) {
+      double s = 0.0;
+      const double* b = wsum + ((size_t)c * nz + z) * wblocks;
+      for (int k = 0; k < wblocks; ++k) s += b[k];
+      ep[c] = s * inv;
+    }
+    const double tr = ep[0] + ep[1] + ep[2];
+    for (int c = 0; c < 6; ++c) w[c] = 2.0 * mu * ep[c] + (c < 3 ? lam * tr : 0.0);
+  }
+  double t[3] = {0, 0, 0};
+  if (p.has_t && p.k0_include) {
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      const double* b = tsum + (size_t)c * tblocks;
+      for (int k = 0; k < tblocks; ++k) s += b[k];
+      t[c] = s * inv;
+    }
+  }
+  e[4] = (w[4] - t[0]) / (2.0 * mu);
+  e[3] = (w[3] - t[1]) / (2.0 * mu);
+  e[2] = (w[2] - t[2]) / (lam + 2.0 * mu);
+  if (p.off_strain >= 0)
+    for (int c = 0; c < 6; ++c) out[p.off_strain + c * nz + z] = e[c];
+  if (p.off_stress >= 0) {
+    const double tre = e[0] + e[1] + e[2];
+    for (int c = 0; c < 6; ++c) out[p.off_stress + c * nz + z] = 2.0 * mu * e[c] + (c < 3 ? lam * tre : 0.0) - w[c];
+  }
+  if (p.off_disp >= 0)
+    for (int c = 0; c < 3; ++c) out[p.off_disp + c * nz + z] = 0.0;
+  if (p.off_u3 >= 0 && z == 0) out[p.off_u3] = 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_k0_fields(const double* wsum, int wblocks, const double* tsum, int tblocks, double* out,
+                            const DepthParams& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_k0_fields, dim3((p.nz + NT - 1) / NT), dim3(NT), 0, st, wsum, wblocks, tsum, tblocks, out,
+                     p);
+  return hipGetLastError();
+}
 
 hipError_t launch_return_map(const double* d_eps, const double* sig_n, const double* ep_n, double* d_eps_p,
                              double* d_ep, double* sig_np1, size_t nvox, double lam, double mu, double sy0,

@@ -352,7 +352,10 @@ void solver_release(fvim_ctx* c) {
 
 size_t solver_footprint(const fvim_grid* g, size_t V) {
   const size_t ns = (size_t)g->nx * g->ny;
-  return sizeof(double) * (ns * 12 + 6 * V * 6 + 2 * V) + 64 * 1024;
+  const size_t nm = (size_t)(g->nx / 2 + 1) * g->ny;
+  // surface arrays (12 + dT 3), volume work arrays (7 tensors + 1 scalar),
+  // compliance spectra, reduction buffers
+  return sizeof(double) * (ns * 15 + 43 * V) + 2 * sizeof(cpx<double>) * nm + 64 * 1024;
 }
 
 // Host copy of device scalars [first, first + n) (synchronises the stream).
@@ -560,25 +563,25 @@ static void axpy(fvim_ctx* c, double* y, const double* a, double s, const double
   hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, c->stream, y, a, s, b, n);
 }
 
-// Solves R[d_eps] = 0 for the traction increment dT ([3][ny][nx]); on
-// return pb.x holds d_eps, pb.dep / pb.dp the plastic increments.
-static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb,
-                      int* iters, int* evals, double* res) {
-  SolverWork* w = c->sw;
-  const size_t n6 = 6 * w->V;
-  hipStream_t st = c->stream;
-  int rc = operator_apply(c, nullptr, dT, pb.b, nullptr, nullptr, nullptr);
-  if (rc) return rc;
-  double d3[3];
-  if ((rc = wdots(c, pb.b, nullptr, pb.b, nullptr, d3))) return rc;
-  const double tol_abs = o->tol_plastic * std::max(std::sqrt(d3[0]), 1e-300);
-  hipError_t e = hipMemcpyAsync(pb.x, pb.b, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
-  if (e != hipSuccess) return fail_hip(e, "copy");
+// Restores force_fp64 on scope exit.
+struct Fp64Scope {
+  fvim_ctx* c;
+  int saved;
+  Fp64Scope(fvim_ctx* cc, int on) : c(cc), saved(cc->force_fp64) { c->force_fp64 = on; }
+  ~Fp64Scope() { c->force_fp64 = saved; }
+};
+
+// One DF-SANE / Picard run from the current pb.x to |R| <= tol_abs.
+static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, double tol_abs,
+                       int max_it, int* iters, int* evals, double* fout) {
+  const size_t n6 = 6 * c->sw->V;
   double f;
-  if ((rc = residual(c, s, pb, pb.x, pb.F, &f))) return rc;
+  int rc = residual(c, s, pb, pb.x, pb.F, &f);
+  if (rc) return rc;
   int ne = 1, k = 0;
+  double d3[3];
   if (o->solver == 1) {            // Picard: x <- x - R(x)
-    while (std::sqrt(f) > tol_abs && k < o->max_plastic) {
+    while (std::sqrt(f) > tol_abs && k < max_it) {
       axpy(c, pb.x, pb.x, -1.0, pb.F, n6);
       if ((rc = residual(c, s, pb, pb.x, pb.F, &f))) return rc;
       ++ne;
@@ -590,7 +593,7 @@ static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const 
     std::vector<double> hist{f};
     const double f0n = std::sqrt(f);
     double sigma = 1.0;
-    while (std::sqrt(f) > tol_abs && k < o->max_plastic) {
+    while (std::sqrt(f) > tol_abs && k < max_it) {
       const double eta = f0n / ((1.0 + k) * (1.0 + k));
       double fbar = 0.0;
       for (size_t i = hist.size() > (size_t)M ? hist.size() - M : 0; i < hist.size(); ++i) fbar = std::max(fbar, hist[i]);
@@ -629,12 +632,51 @@ static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const 
       ++k;
     }
   }
+  *iters += k;
+  *evals += ne;
+  *fout = f;
+  return FVIM_OK;
+}
+
+// Solves R[d_eps] = 0 for the traction increment dT ([3][ny][nx]); on
+// return pb.x holds d_eps, pb.dep / pb.dp the plastic increments.  In the
+// FP32_REFINED mode the iteration first runs on the float32 operator down to
+// a relative residual of 3e-6 (about its rounding floor) and is then
+// continued on the float64 operator to the requested tolerance; the
+// right-hand side grad_s M[dT] is always formed in float64.
+static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb,
+                      int* iters, int* evals, double* res) {
+  SolverWork* w = c->sw;
+  const size_t n6 = 6 * w->V;
+  hipStream_t st = c->stream;
+  int rc;
+  {
+    Fp64Scope f64(c, 1);
+    rc = operator_apply(c, nullptr, dT, pb.b, nullptr, nullptr, nullptr);
+  }
+  if (rc) return rc;
+  double d3[3];
+  if ((rc = wdots(c, pb.b, nullptr, pb.b, nullptr, d3))) return rc;
+  const double bn = std::max(std::sqrt(d3[0]), 1e-300);
+  const double tol_abs = o->tol_plastic * bn;
+  hipError_t e = hipMemcpyAsync(pb.x, pb.b, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return fail_hip(e, "copy");
+  *iters = 0;
+  *evals = 0;
+  double f = 0.0;
+  const bool mixed = c->precision == FVIM_FP32_REFINED;
+  const double tol32 = 3e-6 * bn;
+  if (mixed && tol32 > tol_abs) {
+    if ((rc = fixed_point(c, s, o, pb, tol32, o->max_plastic, iters, evals, &f))) return rc;
+  }
+  {
+    Fp64Scope f64(c, mixed ? 1 : c->force_fp64);
+    if ((rc = fixed_point(c, s, o, pb, tol_abs, o->max_plastic, iters, evals, &f))) return rc;
+  }
   // plastic increments of the accepted iterate
   e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, nullptr, w->V, c->lam, c->mu, c->mat.sigma_y0,
                         c->mat.E_h, st);
   if (e != hipSuccess) return fail_hip(e, "return map");
-  *iters = k;
-  *evals = ne;
   *res = std::sqrt(f);
   if (std::sqrt(f) > tol_abs) return fail(FVIM_ENOCONV, "plasticity: iteration limit reached");
   return FVIM_OK;
@@ -725,7 +767,10 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       inf.plastic_iters += it;
       inf.r_evals += ne;
       inf.plastic_res = res;
-      rc = operator_apply(c, pb.dep, nullptr, nullptr, nullptr, nullptr, dU);   // dU3p
+      {
+        Fp64Scope f64(c, 1);                              // surface correction in float64
+        rc = operator_apply(c, pb.dep, nullptr, nullptr, nullptr, nullptr, dU);   // dU3p
+      }
       if (rc) return cleanup(rc);
       double an;
       if ((rc = surf_norms(c, dU, dUp, &dn, &an))) return cleanup(rc);

@@ -28,11 +28,15 @@ struct fvim_ctx {
   void* bufB = nullptr;
   void* tA = nullptr;
   void* tB = nullptr;
-  size_t bufA_bytes = 0, bufB_bytes = 0, tA_bytes = 0, tB_bytes = 0;
+  void* k0buf = nullptr;       // float64 plane sums and mean-mode constants (FP32 path)
+  size_t bufA_bytes = 0, bufB_bytes = 0, tA_bytes = 0, tB_bytes = 0, k0buf_bytes = 0;
   fvim::SolverWork* sw = nullptr;
   // tuning: depth-pass configuration id (-1 = default for nz), and a request
   // to time every candidate on the next operator call
   int depth_cfg = -1;
+  // set by the solvers of the FP32_REFINED mode for the applications that
+  // must be float64 (refinement phase, right-hand sides, surface corrections)
+  int force_fp64 = 0;
   int tune_pending = 0;
   // stage timing: pairs of events per launch, tagged by stage
   int timing = 0;

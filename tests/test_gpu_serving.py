@@ -1,0 +1,83 @@
+"""Continuous-batching server on the GPU: results are the same alone and in a
+mix of concurrent requests (bitwise, since every request runs the same
+deterministic kernels in its own context), requests overlap on the device,
+and admission keeps the device footprint within the budget."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from synth import grid_dict, paraboloid, rough_surface
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _requests():
+    out = []
+    for i, (n, nz, prec) in enumerate([(32, 16, "fp64"), (64, 32, "fp64"), (32, 8, "fp32_refined"),
+                                        (64, 16, "fp32_refined"), (32, 16, "fp64"), (128, 32, "fp64")]):
+        g = grid_dict(n, n, nz, lz=0.25)
+        if i % 2 == 0:
+            h = paraboloid(g, R=2.0)
+            W = [0.0005 * (1 + i % 3), 0.001 * (1 + i % 3)]
+        else:
+            h = rough_surface(n, n, hurst=0.7, k_roll=2, k_cut=n // 4, rms_slope=0.05, seed=i)
+            W = [0.002]
+        out.append((g, h, W, prec))
+    return out
+
+
+def _run(server, reqs):
+    from paper_1811_11558_amd import EPOptions
+    opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14)
+    ids = [server.submit(g, h, W, precision=prec, opts=opts) for (g, h, W, prec) in reqs]
+    return [server.wait(i, (g["ny"], g["nx"])) for i, (g, _, _, _) in zip(ids, reqs)]
+
+
+def test_results_identical_alone_and_in_mix():
+    assert torch.cuda.is_available()
+    from paper_1811_11558_amd import Server
+    reqs = _requests()
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
+    mixed = _run(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    for r in mixed:
+        assert r["status"] == 0, r
+    # overlap: some request was admitted before an earlier-admitted one finished
+    spans = sorted((r["t_admit"], r["t_done"]) for r in mixed)
+    overlap = any(spans[k + 1][0] < spans[k][1] for k in range(len(spans) - 1))
+    _say("spans", spans, "stats", st)
+    assert overlap
+    for k, req in enumerate(reqs):
+        alone = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+        a = _run(alone, [req])[0]
+        alone.close()
+        assert np.array_equal(a["p"], mixed[k]["p"]), k
+        assert np.array_equal(a["u3p"], mixed[k]["u3p"]), k
+        _say("request", k, "identical alone / in mix; contact fraction", a["contact_fraction"])
+
+
+def test_admission_respects_budget():
+    from paper_1811_11558_amd import Server, request_bytes, FvimError
+    g = grid_dict(64, 64, 32, lz=0.25)
+    one = request_bytes(g)
+    srv = Server(hbm_budget_bytes=int(1.5 * one), max_slots=4)       # room for one at a time
+    h = paraboloid(g, R=2.0)
+    reqs = [(g, h, [0.0005], "fp64")] * 3
+    res = _run(srv, reqs)
+    st = srv.stats()
+    assert all(r["status"] == 0 for r in res)
+    assert st["peak_bytes"] <= st["budget"]
+    spans = sorted((r["t_admit"], r["t_done"]) for r in res)
+    assert all(spans[k + 1][0] >= spans[k][1] for k in range(len(spans) - 1))   # serialised by memory
+    big = grid_dict(512, 512, 96, lz=0.25)
+    with pytest.raises(FvimError):
+        srv.submit(big, np.zeros((512, 512)), [0.001])
+    srv.close()
