@@ -227,9 +227,11 @@ int fvim_set_timing(fvim_ctx* ctx, int on);
  * operator call times every valid layout on its own data (blocking) and
  * keeps the fastest.  Different layouts change only the summation order.
  * Callers that need run-to-run identical results store the chosen id and
- * set it explicitly.
+ * set it explicitly.  FVIM_OPT_GRAPHS (default 1): the contact iteration is
+ * captured once as a HIP graph and replayed (same kernels, same results; 0
+ * launches the kernels one by one).
  */
-enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2 };
+enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3 };
 int fvim_set_option(fvim_ctx* ctx, int key, int value);
 int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);

@@ -329,6 +329,9 @@ int fvim_set_option(fvim_ctx* c, int key, int value) {
     case FVIM_OPT_TUNE:
       c->tune_pending = value ? 1 : 0;
       return FVIM_OK;
+    case FVIM_OPT_GRAPHS:
+      c->use_graphs = value ? 1 : 0;
+      return FVIM_OK;
   }
   return fail(FVIM_EINVAL, "unknown option");
 }
@@ -341,6 +344,9 @@ int fvim_get_option(fvim_ctx* c, int key, int* value) {
       return FVIM_OK;
     case FVIM_OPT_TUNE:
       *value = c->tune_pending;
+      return FVIM_OK;
+    case FVIM_OPT_GRAPHS:
+      *value = c->use_graphs;
       return FVIM_OK;
   }
   return fail(FVIM_EINVAL, "unknown option");

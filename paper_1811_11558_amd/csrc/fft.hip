@@ -188,38 +188,44 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
 }
 
 // Forward column transform: X[p][kx][y] -> S[kx][ky][p]; block = up to B
-// planes of one kx (B = tile / ny, planes past NP are zero and not stored).
+// planes of one kx (B = tile / ny).  Tile rows past the last plane are filled
+// with copies of it (never stored), so every load is unconditional: with
+// conditional loads the staging array was not kept in registers and went
+// through scratch memory, doubling the kernel's memory traffic.
 template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
                                              int NP, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
+  static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
   const int kx = blockIdx.x / npb;
   const int p0 = (blockIdx.x - kx * npb) * B;
   const int nb = min(B, NP - p0);
-  constexpr int MV = (B * N + NT - 1) / NT;
+  constexpr int MV = B * N / NT;
   cpx<T> v[MV];
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
-    int i = threadIdx.x + u * NT;
-    int b = i >> LOGN, y = i & (N - 1);
-    if (i < B * N && b < nb) v[u] = in[((size_t)(p0 + b) * kxh + kx) * N + y];
+    const int i = threadIdx.x + u * NT;
+    const int b = i >> LOGN, y = i & (N - 1);
+    const int bc = b < nb ? b : nb - 1;
+    v[u] = in[((size_t)(p0 + bc) * kxh + kx) * N + y];
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
-    int i = threadIdx.x + u * NT;
-    int b = i >> LOGN, y = i & (N - 1);
-    if (i < B * N && b < nb) buf[b * ld + y] = v[u];
+    const int i = threadIdx.x + u * NT;
+    buf[(i >> LOGN) * ld + (i & (N - 1))] = v[u];
   }
   __syncthreads();
   lds_fft<T, LOGN, B, false>(buf, ld, nb, tw);
-  const int tot = nb * N;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int ky = i / nb, b = i - ky * nb;
-    out[((size_t)kx * N + ky) * NP + p0 + b] = buf[b * ld + ky];
+  // consecutive lanes take consecutive planes of one ky: runs of nb elements
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int i = threadIdx.x + u * NT;
+    const int ky = i / B, b = i - ky * B;
+    if (b < nb) out[((size_t)kx * N + ky) * NP + p0 + b] = buf[b * ld + ky];
   }
 }
 

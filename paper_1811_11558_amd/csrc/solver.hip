@@ -317,6 +317,14 @@ struct SolverWork {
   double* hsc = nullptr;        // pinned host copy
   double* vol = nullptr;        // volume work arrays (allocated on first plasticity use)
   size_t vol_count = 0;
+  // one contact iteration captured as a HIP graph, replayed on a private
+  // stream fenced by events against the context stream
+  hipStream_t cap = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t pk_graph = nullptr;
+  hipGraphExec_t pk_exec = nullptr;
+  const double* g_h = nullptr;
+  const double* g_p = nullptr;
 };
 
 static int sw_ensure(fvim_ctx* c) {
@@ -346,6 +354,11 @@ void solver_release(fvim_ctx* c) {
   if (w->sc) hipFree(w->sc);
   if (w->hsc) hipHostFree(w->hsc);
   if (w->vol) hipFree(w->vol);
+  if (w->pk_exec) hipGraphExecDestroy(w->pk_exec);
+  if (w->pk_graph) hipGraphDestroy(w->pk_graph);
+  if (w->ev_in) hipEventDestroy(w->ev_in);
+  if (w->ev_out) hipEventDestroy(w->ev_out);
+  if (w->cap) hipStreamDestroy(w->cap);
   delete w;
   c->sw = nullptr;
 }
@@ -359,6 +372,14 @@ size_t solver_footprint(const fvim_grid* g, size_t V) {
 }
 
 // Host copy of device scalars [first, first + n) (synchronises the stream).
+static int read_scalars_on(fvim_ctx* c, hipStream_t st, int first, int n) {
+  SolverWork* w = c->sw;
+  hipError_t e = hipMemcpyAsync(w->hsc + first, w->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail_hip(e, "scalar readback");
+  return FVIM_OK;
+}
+
 static int read_scalars(fvim_ctx* c, int first, int n) {
   SolverWork* w = c->sw;
   hipError_t e = hipMemcpyAsync(w->hsc + first, w->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
@@ -377,14 +398,13 @@ static int set_scalar(fvim_ctx* c, int slot, double v) {
 }
 
 // u = M[p] . e3 at z = 0 for a normal surface load p (one plane).
-static int compliance(fvim_ctx* c, const double* p, double* u) {
+static int compliance(fvim_ctx* c, const double* p, double* u, hipStream_t st) {
   SolverWork* w = c->sw;
   const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
   const cpx<double>* twx = (const cpx<double>*)c->twx64;
   const cpx<double>* twy = (const cpx<double>*)c->twy64;
   cpx<double>* A = (cpx<double>*)w->specA;
   cpx<double>* B = (cpx<double>*)w->specB;
-  hipStream_t st = c->stream;
   hipError_t e;
   if ((e = launch_x_r2c<double>(p, A, nx, ny, 1, twx, st)) != hipSuccess) return fail_hip(e, "compliance x");
   if ((e = launch_y_fwd<double>(A, B, ny, kxh, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y");
@@ -403,6 +423,39 @@ static int compliance(fvim_ctx* c, const double* p, double* u) {
   return FVIM_OK;
 }
 
+// One Polonsky-Keer iteration as a fixed sequence of launches on st (no host
+// dependency: every scalar lives in device memory), so it can be captured.
+static int pk_iteration(fvim_ctx* c, hipStream_t st, const double* h, double* p) {
+  SolverWork* w = c->sw;
+  const size_t n = w->ns;
+  const int nb = nblocks(n);
+  const dim3 G(nb), Bk(NT);
+  double* u = w->surf;
+  double* g = w->surf + n;
+  double* t = w->surf + 2 * n;
+  double* r = w->surf + 3 * n;
+  double* pold = w->surf + 4 * n;
+  int rc;
+  if ((rc = compliance(c, p, u, st))) return rc;
+  hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 1, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_dir, G, Bk, 0, st, p, g, t, n, w->sc);
+  if ((rc = compliance(c, t, r, st))) return rc;
+  hipLaunchKernelGGL(k_pk_rmean, G, Bk, 0, st, p, r, n, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 2, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_tau, G, Bk, 0, st, p, g, r, t, n, w->sc, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 3, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_update, G, Bk, 0, st, p, pold, g, t, n, w->sc, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 4, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_scale, G, Bk, 0, st, p, pold, n, w->sc, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 5, w->part, nb, w->sc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip(e, "contact iteration");
+  return FVIM_OK;
+}
+
 // Polonsky-Keer on the context stream.  p: in warm start (all zero ->
 // uniform), out solution.  gap may be NULL.
 int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, double* p, double* gap,
@@ -416,9 +469,6 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   const dim3 G(nb), Bk(NT);
   double* u = w->surf;
   double* g = w->surf + n;
-  double* t = w->surf + 2 * n;
-  double* r = w->surf + 3 * n;
-  double* pold = w->surf + 4 * n;
   const double dA = c->grid.lx * c->grid.ly / (double)n;
   // scalars: load, area, restart state
   w->hsc[S_W] = W;
@@ -441,34 +491,53 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   int it = 0;
   double err = INFINITY;
   const int check = n <= 4096 ? 1 : 4;        // host convergence check period
+  hipStream_t run = st;
+  if (c->use_graphs) {
+    if (!w->cap) {
+      if (hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess)
+        return fail(FVIM_EHIP, "graph stream");
+    }
+    if ((e = hipEventRecord(w->ev_in, st)) != hipSuccess) return fail_hip(e, "event");
+    if ((e = hipStreamWaitEvent(w->cap, w->ev_in, 0)) != hipSuccess) return fail_hip(e, "event wait");
+    run = w->cap;
+    if (!w->pk_exec || w->g_h != h || w->g_p != p) {
+      if (w->pk_exec) { hipGraphExecDestroy(w->pk_exec); w->pk_exec = nullptr; }
+      if (w->pk_graph) { hipGraphDestroy(w->pk_graph); w->pk_graph = nullptr; }
+      if ((e = hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return fail_hip(e, "graph capture");
+      int rc2 = pk_iteration(c, run, h, p);
+      e = hipStreamEndCapture(run, &w->pk_graph);
+      if (rc2) return rc2;
+      if (e != hipSuccess) return fail_hip(e, "graph capture end");
+      if ((e = hipGraphInstantiate(&w->pk_exec, w->pk_graph, nullptr, nullptr, 0)) != hipSuccess)
+        return fail_hip(e, "graph instantiate");
+      w->g_h = h;
+      w->g_p = p;
+    }
+  }
   for (it = 1; it <= max_iter; ++it) {
-    if ((rc = compliance(c, p, u))) return rc;
-    hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
-    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
-    hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
-    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 1, w->part, nb, w->sc);
-    hipLaunchKernelGGL(k_pk_dir, G, Bk, 0, st, p, g, t, n, w->sc);
-    if ((rc = compliance(c, t, r))) return rc;
-    hipLaunchKernelGGL(k_pk_rmean, G, Bk, 0, st, p, r, n, w->part);
-    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 2, w->part, nb, w->sc);
-    hipLaunchKernelGGL(k_pk_tau, G, Bk, 0, st, p, g, r, t, n, w->sc, w->part);
-    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 3, w->part, nb, w->sc);
-    hipLaunchKernelGGL(k_pk_update, G, Bk, 0, st, p, pold, g, t, n, w->sc, w->part);
-    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 4, w->part, nb, w->sc);
-    hipLaunchKernelGGL(k_pk_scale, G, Bk, 0, st, p, pold, n, w->sc, w->part);
-    hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 5, w->part, nb, w->sc);
-    if ((e = hipGetLastError()) != hipSuccess) return fail_hip(e, "contact iteration");
+    if (c->use_graphs) {
+      if ((e = hipGraphLaunch(w->pk_exec, run)) != hipSuccess) return fail_hip(e, "graph launch");
+    } else {
+      if ((rc = pk_iteration(c, run, h, p))) return rc;
+    }
     if (it % check == 0 || it == max_iter) {
-      if ((rc = read_scalars(c, S_ERR, 1))) return rc;
+      if ((rc = read_scalars_on(c, run, S_ERR, 1))) return rc;
       err = w->hsc[S_ERR];
       if (!std::isfinite(err)) return fail(FVIM_EINVAL, "contact_solve: non-finite iterate (check h and W)");
       if (err < tol) break;
     }
   }
+  if (run != st) {
+    if ((e = hipEventRecord(w->ev_out, run)) != hipSuccess) return fail_hip(e, "event");
+    if ((e = hipStreamWaitEvent(st, w->ev_out, 0)) != hipSuccess) return fail_hip(e, "event wait");
+  }
   const bool conv = err < tol;
   if (it > max_iter) it = max_iter;
   // final gap and certificate
-  if ((rc = compliance(c, p, u))) return rc;
+  if ((rc = compliance(c, p, u, st))) return rc;
   hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
   hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
   hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);

@@ -37,6 +37,8 @@ struct fvim_ctx {
   // set by the solvers of the FP32_REFINED mode for the applications that
   // must be float64 (refinement phase, right-hand sides, surface corrections)
   int force_fp64 = 0;
+  // replay the contact iteration as a captured HIP graph
+  int use_graphs = 1;
   int tune_pending = 0;
   // stage timing: pairs of events per launch, tagged by stage
   int timing = 0;

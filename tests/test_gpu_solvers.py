@@ -115,3 +115,24 @@ def test_hertz_elastoplastic_matches_stored_oracle(solver):
         err = _rel(st[k].cpu().numpy(), ref[k])
         _say(k, err)
         assert err < 1e-11, (k, err)
+
+
+def test_contact_graph_replay_equals_eager():
+    """The contact iteration replayed as a captured HIP graph gives bitwise the
+    same pressure as launching its kernels one by one (many replays, with
+    host reads of the convergence scalar between them)."""
+    g = grid_dict(64, 64, 2)
+    h = torch.from_numpy(rough_surface(64, 64, hurst=0.8, k_roll=2, k_cut=16, rms_slope=0.1, seed=7)).cuda()
+    out = {}
+    for graphs in (1, 0, 1):
+        ctx = _ctx(g)
+        ctx.set_option(3, graphs)
+        p, _, info = ctx.contact_solve(h, 0.01, tol=1e-15, max_iter=5000)
+        torch.cuda.synchronize()
+        out.setdefault(graphs, []).append((p.cpu().numpy(), info["iters"]))
+        ctx.close()
+    (pg, ig), (pg2, ig2) = out[1]
+    (pe, ie), = out[0]
+    _say("iterations graph / eager", ig, ie)
+    assert ig == ie == ig2
+    assert np.array_equal(pg, pe) and np.array_equal(pg, pg2)
