@@ -136,7 +136,7 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
   const int kxh = nx / 2 + 1;
   const size_t nmodes = (size_t)kxh * ny;
-  DepthParams prm;
+  DepthParams prm{};
   prm.nx = nx;
   prm.ny = ny;
   prm.nz = nz;
@@ -189,6 +189,16 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
     tsum = wsum + (size_t)6 * nz * wbpp;
     padd = tsum + (size_t)3 * wbpp;
   }
+  void*& mt = sizeof(T) == 8 ? c->mt64 : c->mt32;
+  if (!mt) {
+    if (hipMalloc(&mt, sizeof(ModeConst<T>) * nmodes) != hipSuccess) {
+      mt = nullptr;
+      return fail(FVIM_ENOMEM, "device allocation failed for the mode table");
+    }
+    hipError_t e0 = launch_mode_table<T>((ModeConst<T>*)mt, nx, ny, c->grid.lx, c->grid.ly, prm.h, c->stream);
+    if (e0 != hipSuccess) return fail_hip(e0, "mode table");
+  }
+  prm.mtab = mt;
   const cpx<T>* twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
   const cpx<T>* twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
   cpx<T>* A = (cpx<T>*)c->bufA;
@@ -307,7 +317,7 @@ void fvim_destroy(fvim_ctx* c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->tA, c->tB, c->k0buf};
+  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->tA, c->tB, c->k0buf, c->mt64, c->mt32};
   for (void* p : ptrs)
     if (p) hipFree(p);
   solver_release(c);
@@ -392,6 +402,7 @@ size_t fvim_footprint_bytes(const fvim_grid* g, int precision, int with_solver_s
   const size_t csz = (precision == FVIM_FP32_REFINED && !with_solver_state) ? 8 : 16;
   const size_t planes = 15 * (size_t)g->nz + 1;
   size_t b = 2 * planes * nmodes * csz + 6 * nmodes * csz;
+  b += nmodes * (sizeof(ModeConst<double>) + (precision == FVIM_FP32_REFINED ? sizeof(ModeConst<float>) : 0));
   const size_t V = (size_t)g->nx * g->ny * g->nz;
   if (with_solver_state) b += solver_footprint(g, V);
   return b;

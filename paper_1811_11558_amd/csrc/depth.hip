@@ -57,26 +57,19 @@ constexpr double cb(int k) { return sgn(k) * inv_fact(k) / (k + 2.0); }
 constexpr double cc(int k) { return sgn(k) * inv_fact(k) / ((k + 2.0) * (k + 3.0)); }
 constexpr double cd(int k) { return sgn(k) * inv_fact(k) / (k + 3.0); }
 
-template <typename T>
-struct Terms {
-  static constexpr int n = 26;
-};
-template <>
-struct Terms<float> {
-  static constexpr int n = 16;
-};
-
-template <typename T>
-__device__ __forceinline__ void elem_coeffs(T s, T& G0, T& G0p, T& H0, T& H0p) {
+// Element functions in float64: 26 Taylor terms below s = 2 (the truncation
+// is below 2^-53 relative there), closed forms above.
+__device__ __forceinline__ void elem_coeffs(double s, double& G0, double& G0p, double& H0, double& H0p) {
+  using T = double;
   if (s < T(2)) {
-    constexpr int N = Terms<T>::n;
-    T a = (T)ca(N - 1), b = (T)cb(N - 1), c = (T)cc(N - 1), d = (T)cd(N - 1);
+    constexpr int N = 26;
+    T a = ca(N - 1), b = cb(N - 1), c = cc(N - 1), d = cd(N - 1);
 #pragma unroll
     for (int k = N - 2; k >= 0; --k) {
-      a = a * s + (T)ca(k);
-      b = b * s + (T)cb(k);
-      c = c * s + (T)cc(k);
-      d = d * s + (T)cd(k);
+      a = a * s + ca(k);
+      b = b * s + cb(k);
+      c = c * s + cc(k);
+      d = d * s + cd(k);
     }
     G0 = s * a;
     G0p = s * b;
@@ -115,14 +108,18 @@ struct Loads {
   cpx<T> f0, f1, f2, f3, fm, fp;
 };
 
+// Ratios of kappa = lambda / mu used per node (computed once on the host).
 template <typename T>
-__device__ __forceinline__ Loads<T> modal_loads(const cpx<T> o[5], T kap) {
+struct MatC {
+  T kap, ikp2, kk, i2k4, kapkp2;
+};
+
+template <typename T>
+__device__ __forceinline__ Loads<T> modal_loads(const cpx<T> o[5], const MatC<T>& m) {
   // o = (omega_nn, omega_zz, omega_nz / i, omega_nt / i, omega_tz)
-  const T kp2 = kap + T(2);
-  const T kk = (kap + T(1)) / kp2;
-  const T i2k4 = T(1) / (T(2) * kp2);
-  cpx<T> ec = scl(o[1], T(1) / kp2);
-  cpx<T> et1 = sub(o[0], scl(o[1], kap / kp2));
+  const T kk = m.kk, i2k4 = m.i2k4;
+  cpx<T> ec = scl(o[1], m.ikp2);
+  cpx<T> et1 = sub(o[0], scl(o[1], m.kapkp2));
   Loads<T> L;
   L.f0 = sub(scl(ec, -kk), scl(et1, i2k4));
   L.f1 = axpy(sub(scl(o[2], -kk), scl(ec, kk)), T(0.5) * kk, et1);
@@ -168,7 +165,6 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
   const T nrm = (T)prm.norm;
   const T kap = (T)prm.kappa;
   const T mu = (T)prm.mu;
-  const T kp2 = kap + T(2);
   const int i0 = l * P;
   const bool wantS = prm.off_strain >= 0;
   constexpr bool wantX = WANTX;
@@ -213,7 +209,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
       cpx<T> e[6] = {zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>()};
       e[4] = sub(scl(ep[4], nrm), scl(tr[0], T(0.5) * tk));        // e13
       e[3] = sub(scl(ep[3], nrm), scl(tr[1], T(0.5) * tk));        // e23
-      e[2] = scl(sub(w33, scl(tr[2], tk)), T(1) / kp2);             // e33
+      e[2] = scl(sub(w33, scl(tr[2], tk)), (T)prm.ikp2);             // e33
       if (prm.k0_external) {          // the caller adds this mode in float64
         if (wantS) {
 #pragma unroll
@@ -241,20 +237,21 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
   const int nrep = NYQ ? (nyqx ? 2 : 1) * (nyqy ? 2 : 1) : 1;
   const int k1 = kx;
   const int k2 = (ky * 2 <= prm.ny) ? ky : ky - prm.ny;
-  const T wrep = T(1) / (T)nrep;
-  const T cfac = kp2 / (T(2) * (kap + T(1)));
-  const T ik2 = T(1) / (T(2) * kap + T(2));
+  const T wrep = nrep == 1 ? T(1) : (nrep == 2 ? T(0.5) : T(0.25));
+  const T cfac = (T)prm.cfac;
+  const T ik2 = (T)prm.ik2;
+  const MatC<T> mc = {kap, (T)prm.ikp2, (T)prm.kk, (T)prm.i2k4, (T)prm.kapkp2};
   // |q| and everything built from it are the same for every sign replica
+  const ModeConst<T> K = static_cast<const ModeConst<T>*>(prm.mtab)[mode];
   const double twopi = 6.283185307179586476925286766559;
+  const T iq = K.iq;
   const T q1a = (T)(twopi * k1 / prm.lx);
   const T q2a = (T)(twopi * k2 / prm.ly);
-  const T q = sqrt(q1a * q1a + q2a * q2a);
-  const T iq = T(1) / q;
-  const T s = q * (T)prm.h;
-  const T r = exp(-s);
-  const T rP = exp(-(T)P * s);
-  T G0, G0p, H0, H0p;
-  elem_coeffs<T>(s, G0, G0p, H0, H0p);
+  const T s = K.s, r = K.r;
+  T rP = r;
+#pragma unroll
+  for (int k = 1; k < P; ++k) rP *= r;
+  const T G0 = K.G0, G0p = K.G0p, H0 = K.H0, H0p = K.H0p;
 
   for (int rep = 0; rep < nrep; ++rep) {
     int bits = rep;
@@ -291,11 +288,11 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
     cpx<T> M2[P], M3[P], MP[P];
     {
       cpx<T> x2 = zero<T>(), x3 = zero<T>(), xp = zero<T>();
-      Loads<T> Ln = modal_loads<T>(on, kap);
+      Loads<T> Ln = modal_loads<T>(on, mc);
 #pragma unroll
       for (int p = P - 1; p >= 0; --p) {
         const int e = i0 + p;                    // element e joins nodes e, e+1
-        Loads<T> L = modal_loads<T>(o[p], kap);
+        Loads<T> L = modal_loads<T>(o[p], mc);
         cpx<T> b2 = zero<T>(), b3 = zero<T>(), bp = zero<T>();
         if (e + 1 < nz) {
           b3 = add(scl(L.f3, G0), scl(Ln.f3, G0p));
@@ -318,11 +315,10 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
 #pragma unroll
       for (int d = 1; d < LPM; d <<= 1) {
         cpx<T> o2 = sh_down<T, LPM>(Y2, d), o3 = sh_down<T, LPM>(Y3, d), op = sh_down<T, LPM>(YP, d);
-        if (l + d < LPM) {
-          Y2 = add(Y2, scl(axpy(o2, -ks, o3), rk));
-          Y3 = add(Y3, scl(o3, rk));
-          YP = add(YP, scl(op, rk));
-        }
+        const T wk = (l + d < LPM) ? rk : T(0);    // no partner below the last lane
+        Y2 = add(Y2, scl(axpy(o2, -ks, o3), wk));
+        Y3 = add(Y3, scl(o3, wk));
+        YP = add(YP, scl(op, wk));
         rk = rk * rk;
         ks = ks + ks;
       }
@@ -365,8 +361,8 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
         const int e = i0 + p;
         cpx<T> a0 = zero<T>(), a1 = zero<T>(), am = zero<T>();
         if (e + 1 < nz) {
-          Loads<T> L = modal_loads<T>(o[p], kap);
-          Loads<T> Ln = modal_loads<T>(p + 1 < P ? o[(p + 1) % P] : on, kap);
+          Loads<T> L = modal_loads<T>(o[p], mc);
+          Loads<T> Ln = modal_loads<T>(p + 1 < P ? o[(p + 1) % P] : on, mc);
           a1 = add(scl(L.f1, G0p), scl(Ln.f1, G0));
           a0 = add(add(scl(L.f0, G0p), scl(Ln.f0, G0)), add(scl(L.f1, H0p), scl(Ln.f1, H0)));
           am = add(scl(L.fm, G0p), scl(Ln.fm, G0));
@@ -391,11 +387,10 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
 #pragma unroll
       for (int d = 1; d < LPM; d <<= 1) {
         cpx<T> o0 = sh_up<T, LPM>(F0, d), o1 = sh_up<T, LPM>(F1, d), om = sh_up<T, LPM>(FM, d);
-        if (l >= d) {
-          F0 = add(F0, scl(axpy(o0, ks, o1), rk));
-          F1 = add(F1, scl(o1, rk));
-          FM = add(FM, scl(om, rk));
-        }
+        const T wk = (l >= d) ? rk : T(0);         // no partner above the first lane
+        F0 = add(F0, scl(axpy(o0, ks, o1), wk));
+        F1 = add(F1, scl(o1, wk));
+        FM = add(FM, scl(om, wk));
         rk = rk * rk;
         ks = ks + ks;
       }
@@ -422,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
         cpx<T> v = add(mpp, mm);
         cpx<T> t3 = sub(mpp, mm);
         cpx<T> exx = scl(a, T(-1));
-        cpx<T> ezz = scl(add(add(scl(a, kap), t2), o[p][1]), T(1) / kp2);
+        cpx<T> ezz = scl(add(add(scl(a, kap), t2), o[p][1]), (T)prm.ikp2);
         cpx<T> exz = mul_i(scl(add(t1, o[p][2]), T(0.5)));
         cpx<T> eez = scl(add(t3, o[p][4]), T(0.5));
         cpx<T> exe = mul_i(scl(v, T(0.5)));
@@ -449,6 +444,33 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
       }
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_mode_table(ModeConst<T>* __restrict__ tab, int nx, int ny, double lx,
+                                                  double ly, double h) {
+  const int kxh = nx / 2 + 1;
+  const int m = blockIdx.x * NT + threadIdx.x;
+  if (m >= kxh * ny) return;
+  const int kx = m / ny, ky = m - kx * ny;
+  const int k2 = (ky * 2 <= ny) ? ky : ky - ny;
+  ModeConst<T> c = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
+  if (kx != 0 || ky != 0) {
+    const double twopi = 6.283185307179586476925286766559;
+    const double q1 = twopi * kx / lx, q2 = twopi * k2 / ly;
+    const double q = sqrt(q1 * q1 + q2 * q2);
+    const double s = q * h;
+    double G0, G0p, H0, H0p;
+    elem_coeffs(s, G0, G0p, H0, H0p);
+    c.s = (T)s;
+    c.r = (T)exp(-s);
+    c.G0 = (T)G0;
+    c.G0p = (T)G0p;
+    c.H0 = (T)H0;
+    c.H0p = (T)H0p;
+    c.iq = (T)(1.0 / q);
+  }
+  tab[m] = c;
 }
 
 template <typename T, int LPM, int P, bool DISP, bool WANTX>
@@ -504,8 +526,25 @@ int depth_default_config(int nz) {
 }
 
 template <typename T>
-hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, int cfg,
+hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, double ly, double h, hipStream_t st) {
+  const int nm = (nx / 2 + 1) * ny;
+  hipLaunchKernelGGL(k_mode_table<T>, dim3((unsigned)((nm + NT - 1) / NT)), dim3(NT), 0, st, tab, nx, ny, lx, ly,
+                     h);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& prm, int cfg,
                         hipStream_t st) {
+  if (!prm.mtab) return hipErrorInvalidValue;
+  DepthParams p = prm;
+  const double kap = p.kappa, kp2 = kap + 2.0;
+  p.ikp2 = 1.0 / kp2;
+  p.kk = (kap + 1.0) / kp2;
+  p.i2k4 = 1.0 / (2.0 * kp2);
+  p.kapkp2 = kap / kp2;
+  p.cfac = kp2 / (2.0 * (kap + 1.0));
+  p.ik2 = 1.0 / (2.0 * kap + 2.0);
   if (!depth_config_valid(cfg, p.nz)) cfg = depth_default_config(p.nz);
   switch (cfg) {
     case 0: return launch_cfg<T, 16, 1>(in, tin, out, p, st);
@@ -524,5 +563,7 @@ template hipError_t launch_depth<double>(const cpx<double>*, const cpx<double>*,
                                          const DepthParams&, int, hipStream_t);
 template hipError_t launch_depth<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const DepthParams&,
                                         int, hipStream_t);
+template hipError_t launch_mode_table<double>(ModeConst<double>*, int, int, double, double, double, hipStream_t);
+template hipError_t launch_mode_table<float>(ModeConst<float>*, int, int, double, double, double, hipStream_t);
 
 }  // namespace fvim

@@ -37,14 +37,30 @@ hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny
 // [6][nz], displacement as [3][nz], surface u3 as one plane.
 struct DepthParams {
   int nx, ny, nz, kxh;
-  double lx, ly, h;       // cell size and depth-node spacing
+  double lx, ly, h;       // in-plane domain lengths, depth-node spacing
   double mu, kappa;       // shear modulus, lambda / mu
   double norm;            // 1 / (nx ny)
   int has_w, has_t, k0_include;
   int k0_external;        // 1: the mean mode is added by the caller in float64; write 0 here
   int np_out;
   int off_strain, off_stress, off_disp, off_u3;
+  const void* mtab;       // ModeConst<T>[kxh * ny] of this grid (launch_mode_table)
+  // ratios of kappa, filled by launch_depth: 1/(kappa+2), (kappa+1)/(kappa+2),
+  // 1/(2(kappa+2)), kappa/(kappa+2), (kappa+2)/(2(kappa+1)), 1/(2 kappa+2)
+  double ikp2, kk, i2k4, kapkp2, cfac, ik2;
 };
+
+// Constants of one in-plane mode for the depth pass, computed once per grid
+// in float64 and stored in the working precision: s = |q| h, r = exp(-s),
+// the element functions G0, G0', H0, H0' of s, and 1/|q| (all 0 for the
+// mean mode).
+template <typename T>
+struct alignas(16) ModeConst {
+  T s, r, G0, G0p, H0, H0p, iq, pad;
+};
+
+template <typename T>
+hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, double ly, double h, hipStream_t st);
 
 template <typename T>
 hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, int cfg,

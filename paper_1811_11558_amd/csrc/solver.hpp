@@ -29,6 +29,8 @@ struct fvim_ctx {
   void* tA = nullptr;
   void* tB = nullptr;
   void* k0buf = nullptr;       // float64 plane sums and mean-mode constants (FP32 path)
+  void* mt64 = nullptr;        // per-mode depth-pass constants (built on first use)
+  void* mt32 = nullptr;
   size_t bufA_bytes = 0, bufB_bytes = 0, tA_bytes = 0, tB_bytes = 0, k0buf_bytes = 0;
   fvim::SolverWork* sw = nullptr;
   // tuning: depth-pass configuration id (-1 = default for nz), and a request
