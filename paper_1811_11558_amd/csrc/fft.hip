@@ -241,19 +241,31 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
   const int kx = blockIdx.x / npb;
   const int p0 = (blockIdx.x - kx * npb) * B;
   const int nb = min(B, NP - p0);
-  const int tot = nb * N;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int ky = i / nb, b = i - ky * nb;
-    buf[b * ld + ky] = in[((size_t)kx * N + ky) * NP + p0 + b];
+  static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
+  constexpr int MV = B * N / NT;
+  // consecutive lanes read consecutive planes of one ky (runs of nb
+  // elements); lanes past the last plane repeat it into unused tile rows
+  cpx<T> v[MV];
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int i = threadIdx.x + u * NT;
+    const int ky = i / B, b = i - ky * B;
+    const int bc = b < nb ? b : nb - 1;
+    v[u] = in[((size_t)kx * N + ky) * NP + p0 + bc];
+  }
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int i = threadIdx.x + u * NT;
+    const int ky = i / B, b = i - ky * B;
+    buf[b * ld + ky] = v[u];
   }
   __syncthreads();
   lds_fft<T, LOGN, B, true>(buf, ld, nb, tw);
-  constexpr int MV = (B * N + NT - 1) / NT;
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
     int b = i >> LOGN, y = i & (N - 1);
-    if (i < B * N && b < nb) out[((size_t)(p0 + b) * kxh + kx) * N + y] = buf[b * ld + y];
+    if (b < nb) out[((size_t)(p0 + b) * kxh + kx) * N + y] = buf[b * ld + y];
   }
 }
 
@@ -274,12 +286,26 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
   const size_t row0 = (size_t)blockIdx.x * R;
   const int plane = (int)(row0 / ny);
   const int y0 = (int)(row0 - (size_t)plane * ny);
-  const int hp = R / 2;
+  const int hp = R / 2;                  // a power of two (R = ny or 2 SEQ)
+  const int lhp = __builtin_ctz(hp);
   const int tot = kxh * hp;
-  for (int i = threadIdx.x; i < tot; i += NT) {
-    int k = i / hp, pr = i - k * hp;
-    size_t a = ((size_t)plane * kxh + k) * ny + y0 + 2 * pr;
-    cpx<T> X0 = in[a], X1 = in[a + 1];
+  // all loads first (slots past the end repeat the last pair, which writes
+  // the same values again), then the LDS writes
+  constexpr int MV = (kxh * SEQ + NT - 1) / NT;
+  cpx<T> v0[MV], v1[MV];
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int i = min((int)threadIdx.x + u * NT, tot - 1);
+    const int k = i >> lhp, pr = i - (k << lhp);
+    const size_t a = ((size_t)plane * kxh + k) * ny + y0 + 2 * pr;
+    v0[u] = in[a];
+    v1[u] = in[a + 1];
+  }
+#pragma unroll
+  for (int u = 0; u < MV; ++u) {
+    const int i = min((int)threadIdx.x + u * NT, tot - 1);
+    const int k = i >> lhp, pr = i - (k << lhp);
+    const cpx<T> X0 = v0[u], X1 = v1[u];
     if (k == 0 || k == nyq) {
       buf[pr * ld + k] = mk(X0.x, X1.x);
     } else {
