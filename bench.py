@@ -10,14 +10,15 @@ depth, traction filtered the same way).  Inputs are resident in HBM before
 the timed region.
 
 Prints one JSON line (see the design notes for the field definitions):
-value = voxel-updates/s = nx ny nz / time per application; ``roofline`` for
-the slowest stage with its algorithmic bytes per launch and the launch time
-measured by HIP events on the library stream during the timed steps;
+value = voxel-updates/s = nx ny nz / time per application, from K timed
+steps with no instrumentation in the stream; ``roofline`` for the slowest
+kernel with its algorithmic bytes per launch and its launch time measured by
+HIP event pairs around every launch on the library stream over K further
+steps;
 ``cpu_baseline`` = the FP64 oracle timed on the host cores on a sample of
 modes of the same workload.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -59,34 +60,29 @@ def stage_bytes(nx, ny, nz, csize=16, rsize=8):
     """Algorithmic (compulsory) bytes per launch of each stage."""
     kxh = nx // 2 + 1
     nm = kxh * ny
+    nnyq = ny + kxh - 1                    # modes with kx = nx/2 or ky = ny/2
     V = nx * ny * nz
     p6 = 6 * nz
+    per_mode = (p6 + 3 + p6) * csize       # eigenstress and traction spectra in, strain out
     return {
         "x_fwd": 6 * V * rsize + p6 * nm * csize,
         "y_fwd": 2 * p6 * nm * csize,
         "x_fwd_t": 3 * nx * ny * rsize + 3 * nm * csize,
         "y_fwd_t": 2 * 3 * nm * csize,
-        "depth": p6 * nm * csize + 3 * nm * csize + p6 * nm * csize,
+        "depth": (nm - nnyq) * per_mode,
+        "depth_nyq": nnyq * per_mode,
         "y_inv": 2 * p6 * nm * csize,
         "x_inv": p6 * nm * csize + 6 * V * rsize,
     }
 
 
 KERNEL_OF_STAGE = {"x_fwd": "k_x_r2c", "y_fwd": "k_y_fwd", "x_fwd_t": "k_x_r2c", "y_fwd_t": "k_y_fwd",
-                   "depth": "k_depth", "y_inv": "k_y_inv", "x_inv": "k_x_c2r"}
-SOURCE_OF_STAGE = {"x_fwd": "fft.hip", "y_fwd": "fft.hip", "x_fwd_t": "fft.hip", "y_fwd_t": "fft.hip",
-                   "depth": "depth.hip", "y_inv": "fft.hip", "x_inv": "fft.hip"}
-
-
-def source_sha(name):
-    p = os.path.join(ROOT, "paper_1811_11558_amd", "csrc", name)
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
+                   "depth": "k_depth", "depth_nyq": "k_depth (Nyquist modes)", "y_inv": "k_y_inv",
+                   "x_inv": "k_x_c2r"}
 def measured_traffic(stage, nx, ny, nz, precision):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if
     they were taken on the current kernel source; else None."""
+    from paper_1811_11558_amd.profile_summary import SOURCE_OF_STAGE, source_sha
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -255,8 +251,7 @@ def main():
     for _ in range(a.warmup):
         ctx.operator_apply(eps, trac, out=out)
     torch.cuda.synchronize()
-    ctx.set_timing(True)
-    ctx.stage_times()
+    # headline: the steps alone, no per-kernel instrumentation in the stream
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -266,9 +261,16 @@ def main():
         evs[i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    per = np.array([s.elapsed_time(e) for s, e in evs])
+    # per-kernel launch times: the same steps again with a HIP event pair
+    # around every launch on the library stream
+    ctx.set_timing(True)
+    ctx.stage_times()
+    for i in range(a.steps):
+        ctx.operator_apply(eps, trac, out=out)
+    torch.cuda.synchronize()
     st = ctx.stage_times()
     ctx.set_timing(False)
-    per = np.array([s.elapsed_time(e) for s, e in evs])
     ms_per_step = 1e3 * wall / a.steps
     V = a.nx * a.ny * a.nz
     value = V / (ms_per_step * 1e-3)

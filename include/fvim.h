@@ -213,10 +213,11 @@ enum {
   FVIM_STAGE_YFWD = 1,   /* y transform of the eigenstrain planes        */
   FVIM_STAGE_XFWD_T = 2, /* x transform of the traction planes           */
   FVIM_STAGE_YFWD_T = 3, /* y transform of the traction planes           */
-  FVIM_STAGE_DEPTH = 4,  /* per-mode depth pass                          */
+  FVIM_STAGE_DEPTH = 4,  /* per-mode depth pass, all but Nyquist modes   */
   FVIM_STAGE_YINV = 5,   /* inverse y transform of the output planes     */
   FVIM_STAGE_XINV = 6,   /* inverse x transform of the output planes     */
-  FVIM_NSTAGES = 7
+  FVIM_STAGE_DEPTH_NYQ = 7, /* depth pass of the Nyquist modes           */
+  FVIM_NSTAGES = 8
 };
 int fvim_set_timing(fvim_ctx* ctx, int on);
 

@@ -196,7 +196,7 @@ class Context:
         except Exception:
             pass
 
-    STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv")
+    STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv", "depth_nyq")
 
     OPT_DEPTH_CONFIG, OPT_TUNE = 1, 2
 

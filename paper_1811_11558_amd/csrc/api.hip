@@ -231,8 +231,12 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
     if (rc2) return rc2;
   }
   tm.begin(FVIM_STAGE_DEPTH);
-  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st)) != hipSuccess)
+  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st, 1)) != hipSuccess)
     return fail_hip(e, "depth");
+  tm.end();
+  tm.begin(FVIM_STAGE_DEPTH_NYQ);
+  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st, 2)) != hipSuccess)
+    return fail_hip(e, "depth (Nyquist modes)");
   tm.end();
   if (k0x) {
     if ((e = launch_k0_fields(wsum, wbpp, tsum, wbpp, padd, prm, st)) != hipSuccess) return fail_hip(e, "k0");

@@ -474,25 +474,31 @@ __global__ __launch_bounds__(NT) void k_mode_table(ModeConst<T>* __restrict__ ta
 }
 
 template <typename T, int LPM, int P, bool DISP, bool WANTX>
-hipError_t launch_two(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st) {
+hipError_t launch_two(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st,
+                      int part) {
   constexpr int GPB = NT / LPM;
-  const int nmodes = p.kxh * p.ny;
-  const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
-  hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
-  const int nnyq = p.ny + p.kxh - 1;
-  const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
-  hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, tin, out, p);
+  if (part != 2) {
+    const int nmodes = p.kxh * p.ny;
+    const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
+    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
+  }
+  if (part != 1) {
+    const int nnyq = p.ny + p.kxh - 1;
+    const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
+    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, tin, out, p);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int LPM, int P>
-hipError_t launch_cfg(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st) {
+hipError_t launch_cfg(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st,
+                      int part) {
   const bool disp = p.off_disp >= 0 || p.off_u3 >= 0;
   const bool wx = p.off_stress >= 0;
-  if (disp) return wx ? launch_two<T, LPM, P, true, true>(in, tin, out, p, st)
-                      : launch_two<T, LPM, P, true, false>(in, tin, out, p, st);
-  return wx ? launch_two<T, LPM, P, false, true>(in, tin, out, p, st)
-            : launch_two<T, LPM, P, false, false>(in, tin, out, p, st);
+  if (disp) return wx ? launch_two<T, LPM, P, true, true>(in, tin, out, p, st, part)
+                      : launch_two<T, LPM, P, true, false>(in, tin, out, p, st, part);
+  return wx ? launch_two<T, LPM, P, false, true>(in, tin, out, p, st, part)
+            : launch_two<T, LPM, P, false, false>(in, tin, out, p, st, part);
 }
 
 // (lanes per mode, nodes per lane) configurations; a configuration serves
@@ -535,7 +541,7 @@ hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, doubl
 
 template <typename T>
 hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& prm, int cfg,
-                        hipStream_t st) {
+                        hipStream_t st, int part) {
   if (!prm.mtab) return hipErrorInvalidValue;
   DepthParams p = prm;
   const double kap = p.kappa, kp2 = kap + 2.0;
@@ -547,22 +553,22 @@ hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const 
   p.ik2 = 1.0 / (2.0 * kap + 2.0);
   if (!depth_config_valid(cfg, p.nz)) cfg = depth_default_config(p.nz);
   switch (cfg) {
-    case 0: return launch_cfg<T, 16, 1>(in, tin, out, p, st);
-    case 1: return launch_cfg<T, 16, 2>(in, tin, out, p, st);
-    case 2: return launch_cfg<T, 32, 1>(in, tin, out, p, st);
-    case 3: return launch_cfg<T, 32, 2>(in, tin, out, p, st);
-    case 4: return launch_cfg<T, 64, 1>(in, tin, out, p, st);
-    case 5: return launch_cfg<T, 64, 2>(in, tin, out, p, st);
-    case 6: return launch_cfg<T, 64, 4>(in, tin, out, p, st);
-    case 7: return launch_cfg<T, 64, 8>(in, tin, out, p, st);
+    case 0: return launch_cfg<T, 16, 1>(in, tin, out, p, st, part);
+    case 1: return launch_cfg<T, 16, 2>(in, tin, out, p, st, part);
+    case 2: return launch_cfg<T, 32, 1>(in, tin, out, p, st, part);
+    case 3: return launch_cfg<T, 32, 2>(in, tin, out, p, st, part);
+    case 4: return launch_cfg<T, 64, 1>(in, tin, out, p, st, part);
+    case 5: return launch_cfg<T, 64, 2>(in, tin, out, p, st, part);
+    case 6: return launch_cfg<T, 64, 4>(in, tin, out, p, st, part);
+    case 7: return launch_cfg<T, 64, 8>(in, tin, out, p, st, part);
   }
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_depth<double>(const cpx<double>*, const cpx<double>*, cpx<double>*,
-                                         const DepthParams&, int, hipStream_t);
+                                         const DepthParams&, int, hipStream_t, int);
 template hipError_t launch_depth<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const DepthParams&,
-                                        int, hipStream_t);
+                                        int, hipStream_t, int);
 template hipError_t launch_mode_table<double>(ModeConst<double>*, int, int, double, double, double, hipStream_t);
 template hipError_t launch_mode_table<float>(ModeConst<float>*, int, int, double, double, double, hipStream_t);
 

@@ -62,9 +62,11 @@ struct alignas(16) ModeConst {
 template <typename T>
 hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, double ly, double h, hipStream_t st);
 
+// part: 0 = every mode (two launches), 1 = all but the Nyquist modes,
+// 2 = the Nyquist modes only.
 template <typename T>
 hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, int cfg,
-                        hipStream_t st);
+                        hipStream_t st, int part = 0);
 int depth_num_configs();
 bool depth_config_valid(int id, int nz);
 int depth_default_config(int nz);

@@ -1,63 +1,223 @@
-"""Summarise rocprofv3 CSV output of bench.py runs (kernel stats and
-FETCH_SIZE / WRITE_SIZE counters) into the text tables kept under profiles/.
+"""Summarise rocprofv3 CSV output of bench.py runs into the text tables kept
+under profiles/ and into profiles/traffic.json (read by bench.py).
 
-Usage (from the repository root, on the CSV directories written by the
-commands quoted in the generated file):
+Usage (from the repository root):
     python -m paper_1811_11558_amd.profile_summary stats <kernel_stats.csv>
-    python -m paper_1811_11558_amd.profile_summary traffic <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv> <copy_bytes>
-The traffic mode scales each counter by the bytes a plain device copy of
-known size moves per counted KiB, and reports bytes per launch per kernel.
+    python -m paper_1811_11558_amd.profile_summary report --workload 256x256x64/fp64 \\
+        --stats S.csv --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
+        --copy-bytes 400000000 [--raw-read R1.csv --raw-write R2.csv] \\
+        --commands commands.txt --out profiles/NAME.md --traffic profiles/traffic.json
+
+Byte accounting.  FETCH_SIZE and WRITE_SIZE are scaled by what they read for
+a plain device copy of known size (bytes per counted unit).  On gfx950 the
+FETCH_SIZE expression counts a 128-byte read request as 64 bytes (its
+128-byte term reads TCC_BUBBLE, which stays 0 there), so the copy factor is
+2 for reads; that factor is right for a kernel whose reads are 128-byte
+requests like the copy's.  When the raw request counters are given, bytes
+are also formed directly, 128 TCC_EA0_RDREQ_128B + 64 (the other requests)
++ 32 TCC_EA0_RDREQ_32B for reads and 64 TCC_EA0_WRREQ_64B + 32 (the rest)
+for writes, and both figures are listed.
 """
+import argparse
 import csv
+import hashlib
+import json
+import os
 import re
 import sys
 from collections import defaultdict
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1811_11558_amd", "csrc")
+
+# kernel source of each stage; the hash also covers the shared headers
+SOURCE_OF_STAGE = {"x_fwd": "fft.hip", "y_fwd": "fft.hip", "x_fwd_t": "fft.hip", "y_fwd_t": "fft.hip",
+                   "depth": "depth.hip", "depth_nyq": "depth.hip", "y_inv": "fft.hip", "x_inv": "fft.hip"}
+HEADERS = ("common.hpp", "kernels.hpp")
+
+
+def source_sha(name):
+    h = hashlib.sha256()
+    for f in (name,) + HEADERS:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def short(name):
     name = name.replace("void fvim::(anonymous namespace)::", "")
-    return re.sub(r"\(.*\)$", "", name)
+    return re.sub(r"\(.*\)$", "", name).strip()
+
+
+def stats_rows(path):
+    return [(short(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["Percentage"]))
+            for r in csv.DictReader(open(path))]
 
 
 def stats(path):
-    rows = list(csv.DictReader(open(path)))
     out = ["| kernel | calls | average (us) | share |", "|---|---|---|---|"]
-    for r in rows:
-        out.append("| `%s` | %s | %.2f | %.1f %% |" % (short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3,
-                                                     float(r["Percentage"])))
+    for n, c, us, pct in stats_rows(path):
+        out.append("| `%s` | %d | %.2f | %.1f %% |" % (n, c, us, pct))
     return "\n".join(out)
 
 
-def per_kernel(path):
+def trace_table(path):
+    """Average duration per (kernel, grid) from a --kernel-trace CSV, with the
+    VGPR count and scratch size of the launch."""
     acc = defaultdict(list)
+    meta = {}
     for r in csv.DictReader(open(path)):
-        acc[short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+        k = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]))
+        acc[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        meta[k] = (r["VGPR_Count"], r["Scratch_Size"], r["LDS_Block_Size"])
+    out = ["| kernel | grid (threads) | launches | average (us) | VGPRs | scratch (B) | LDS (B) |",
+           "|---|---|---|---|---|---|---|"]
+    for k in sorted(acc, key=lambda k: -sum(acc[k])):
+        v = acc[k]
+        out.append("| `%s` | %d | %d | %.2f | %s | %s | %s |" % (k[0], k[1], len(v), sum(v) / len(v), *meta[k]))
+    return "\n".join(out)
+
+
+def dispatches(path):
+    """{(kernel, grid): {counter: [values per dispatch]}}"""
+    acc = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        acc[(short(r["Kernel_Name"]), int(r["Grid_Size"]))][r["Counter_Name"]].append(float(r["Counter_Value"]))
     return acc
 
 
-def traffic(fetch, write, cfetch, cwrite, copy_bytes):
-    f, w = per_kernel(fetch), per_kernel(write)
-    cf, cw = per_kernel(cfetch), per_kernel(cwrite)
-    copy_name = max(cf, key=lambda k: max(cf[k]))          # the large copy kernel
-    fs = copy_bytes / max(cf[copy_name])                   # bytes per counted unit (reads)
-    ws = copy_bytes / max(cw[copy_name])                   # bytes per counted unit (writes)
-    out = ["copy reference `%s`: %d bytes read and written; FETCH_SIZE %.1f, WRITE_SIZE %.1f "
-           "-> %.1f / %.1f bytes per unit" % (copy_name, copy_bytes, max(cf[copy_name]), max(cw[copy_name]), fs, ws),
-           "", "| kernel | launches | fetched MB / launch | written MB / launch |", "|---|---|---|---|"]
-    res = {}
-    for k in sorted(f, key=lambda k: -max(f[k])):
-        if k not in w:
+def median(v):
+    v = sorted(v)
+    return v[len(v) // 2]
+
+
+def stage_keys(keys):
+    """Map (kernel, grid) keys of one operator run to bench stages."""
+    by = defaultdict(list)
+    for k in keys:
+        by[k[0].split("<")[0]].append(k)
+    st = {}
+    for base, fwd, trac in (("k_x_r2c", "x_fwd", "x_fwd_t"), ("k_y_fwd", "y_fwd", "y_fwd_t")):
+        ks = sorted(by.get(base, []), key=lambda k: -k[1])
+        if ks:
+            st[fwd] = ks[0]
+        if len(ks) > 1:
+            st[trac] = ks[-1]
+    for base, name in (("k_y_inv", "y_inv"), ("k_x_c2r", "x_inv")):
+        ks = sorted(by.get(base, []), key=lambda k: -k[1])
+        if ks:
+            st[name] = ks[0]
+    return st, by.get("k_depth", [])
+
+
+def copy_factor(path, counter, copy_bytes):
+    d = dispatches(path)
+    name = max(d, key=lambda k: max(d[k].get(counter, [0])))
+    return copy_bytes / max(d[name][counter]), name[0], max(d[name][counter])
+
+
+def report(a):
+    fetch, write = dispatches(a.fetch), dispatches(a.write)
+    fs, copy_name, cf = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
+    ws, _, cw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes)
+    raw_r = dispatches(a.raw_read) if a.raw_read else None
+    raw_w = dispatches(a.raw_write) if a.raw_write else None
+
+    st, depth_keys = stage_keys(fetch.keys())
+    # depth: the layout with the most launches in the timing run (the trace)
+    # is the tuned one (every layout also runs during tuning in the counter
+    # runs); Nyquist launches are the instances whose last flag is true
+    launches = defaultdict(int)
+    if a.trace:
+        for r in csv.DictReader(open(a.trace)):
+            launches[short(r["Kernel_Name"])] += 1
+    else:
+        for k in depth_keys:
+            launches[k[0]] += len(fetch[k]["FETCH_SIZE"])
+    for stage, flag in (("depth", "false>"), ("depth_nyq", "true>")):
+        names = [n for n in launches if n.startswith("k_depth") and n.endswith(flag)]
+        if names:
+            best = max(names, key=lambda n: launches[n])
+            ks = [k for k in depth_keys if k[0] == best]
+            if ks:
+                st[stage] = ks[0]
+
+    lines = ["Copy reference `%s`: %d bytes read and %d written per launch; FETCH_SIZE reads %.1f and "
+             "WRITE_SIZE %.1f, so %.1f bytes per FETCH_SIZE unit and %.1f per WRITE_SIZE unit."
+             % (copy_name, a.copy_bytes, a.copy_bytes, cf, cw, fs, ws), "",
+             "| stage | kernel | grid | fetched MB (copy-scaled) | written MB (copy-scaled) |"
+             + (" fetched MB (requests) | written MB (requests) |" if raw_r else ""),
+             "|---|---|---|---|---|" + ("---|---|" if raw_r else "")]
+    traffic = {}
+    for stage in ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "depth_nyq", "y_inv", "x_inv"):
+        k = st.get(stage)
+        if not k or k not in write:
             continue
-        fm = sorted(f[k])[len(f[k]) // 2] * fs
-        wm = sorted(w[k])[len(w[k]) // 2] * ws
-        res[k] = (fm, wm)
-        out.append("| `%s` | %d | %.1f | %.1f |" % (k, len(f[k]), fm / 1e6, wm / 1e6))
-    return "\n".join(out), res
+        fb = median(fetch[k]["FETCH_SIZE"]) * fs
+        wb = median(write[k]["WRITE_SIZE"]) * ws
+        row = "| %s | `%s` | %d | %.1f | %.1f |" % (stage, k[0], k[1], fb / 1e6, wb / 1e6)
+        rec = {"kernel": k[0], "grid": k[1], "fetch": round(fb), "write": round(wb),
+               "bytes_per_launch": round(fb + wb), "source_sha": source_sha(SOURCE_OF_STAGE[stage])}
+        if raw_r and k in raw_r and raw_w and k in raw_w:
+            r = {c: median(v) for c, v in raw_r[k].items()}
+            w = {c: median(v) for c, v in raw_w[k].items()}
+            rr = (128 * r["TCC_EA0_RDREQ_128B_sum"] + 32 * r["TCC_EA0_RDREQ_32B_sum"]
+                  + 64 * (r["TCC_EA0_RDREQ_sum"] - r["TCC_EA0_RDREQ_128B_sum"] - r["TCC_EA0_RDREQ_32B_sum"]))
+            rw = 64 * w["TCC_EA0_WRREQ_64B_sum"] + 32 * (w["TCC_EA0_WRREQ_sum"] - w["TCC_EA0_WRREQ_64B_sum"])
+            row += " %.1f | %.1f |" % (rr / 1e6, rw / 1e6)
+            rec["fetch_requests"] = round(rr)
+            rec["write_requests"] = round(rw)
+        lines.append(row)
+        traffic["%s/%s" % (stage, a.workload)] = rec
+
+    doc = ["# %s" % a.title, ""]
+    if a.commands:
+        doc += ["Commands (from the repository root on the GPU host; CSV paths as written by them):", "", "```"]
+        doc += [l.rstrip("\n") for l in open(a.commands)] + ["```", ""]
+    if a.stats:
+        doc += ["## Kernel durations (`rocprofv3 --kernel-trace --stats`)", "", stats(a.stats), ""]
+    if a.trace:
+        doc += ["Per launch shape (same run, from the kernel trace; the tuning launches of the first "
+                "call are the layouts with 4 launches):", "", trace_table(a.trace), ""]
+    doc += ["## HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`)", ""] + lines + [""]
+    if a.note:
+        doc += [a.note, ""]
+    with open(a.out, "w") as f:
+        f.write("\n".join(doc))
+    if a.traffic:
+        old = {}
+        if os.path.exists(a.traffic):
+            old = json.load(open(a.traffic))
+        old.update(traffic)
+        with open(a.traffic, "w") as f:
+            json.dump(old, f, indent=1, sort_keys=True)
+            f.write("\n")
+    print("\n".join(doc))
+
+
+def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "stats":
+        print(stats(sys.argv[2]))
+        return
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["report"])
+    ap.add_argument("--workload", required=True, help="e.g. 256x256x64/fp64 (key of traffic.json)")
+    ap.add_argument("--title", default="Operator kernels")
+    ap.add_argument("--stats")
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-bytes", type=int, required=True)
+    ap.add_argument("--raw-read")
+    ap.add_argument("--raw-write")
+    ap.add_argument("--commands")
+    ap.add_argument("--note")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic")
+    report(ap.parse_args())
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
-        print(stats(sys.argv[2]))
-    else:
-        text, _ = traffic(*sys.argv[2:6], int(sys.argv[6]))
-        print(text)
+    main()
