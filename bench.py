@@ -212,11 +212,23 @@ def bench_serve(a):
     srv.close()
     lat = np.array([x["t_done"] - x["t_submit"] for x in res])
     ok = [x["status"] == 0 for x in res]
+    detail = [{"grid": "%dx%dx%d" % (r["nx"], r["ny"], r["nz"]), "pbar": round(r["pbar"], 5),
+               "hurst": round(r["hurst"], 3), "status": x["status"], "error": x["error"],
+               "outer": x["info"]["outer_iters"], "r_evals": x["info"]["r_evals"],
+               "latency_s": round(x["t_done"] - x["t_submit"], 3), "run_s": round(x["t_done"] - x["t_admit"], 3)}
+              for (r, _, _), x in zip(prepared, res)]
+    for d in detail:
+        print(json.dumps(d), file=sys.stderr)
+    by_grid = {}
+    for d in detail:
+        by_grid.setdefault(d["grid"], []).append(d["run_s"])
     vox = sum(r["nx"] * r["ny"] * r["nz"] * x["info"]["r_evals"] for (r, _, _), x in zip(prepared, res))
     print(json.dumps({"metric": "served solves/s", "value": len(res) / wall, "unit": "solves/s",
                       "higher_is_better": True, "n_gpus": 1, "requests": len(res), "ok": int(sum(ok)),
                       "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                       "voxel_updates_per_s": vox / wall, "wall_s": wall, "peak_bytes": st["peak_bytes"],
+                      "run_s_median_by_grid": {k: float(np.median(v)) for k, v in sorted(by_grid.items())},
+                      "failures": [d for d in detail if d["status"] != 0],
                       "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": a.slots,
                                  "rate_per_s": a.rate, "precision": "fp32_refined"}}))
 

@@ -271,6 +271,7 @@ typedef struct {
   double contact_fraction;   /* of the final pressure                       */
   const double* p;           /* HOST [ny][nx] final contact pressure        */
   const double* u3p;         /* HOST [ny][nx] final surface residual disp.  */
+  char error[160];           /* message of a failed solve ("" when status 0) */
 } fvim_result;
 
 typedef struct {

@@ -78,7 +78,7 @@ class _Request(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_done", ctypes.c_double), ("info", _EPInfo), ("contact_fraction", ctypes.c_double),
-                ("p", ctypes.c_void_p), ("u3p", ctypes.c_void_p)]
+                ("p", ctypes.c_void_p), ("u3p", ctypes.c_void_p), ("error", ctypes.c_char * 160)]
 
 
 class _ServerStats(ctypes.Structure):
@@ -411,6 +411,7 @@ class Server:
             return None
         out = {f: getattr(res, f) for f in ("status", "t_submit", "t_admit", "t_done", "contact_fraction")}
         out["info"] = {f: getattr(res.info, f) for f, _ in _EPInfo._fields_}
+        out["error"] = res.error.decode(errors="replace")
         out["p"] = out["u3p"] = None
         return out, res
 

@@ -33,10 +33,24 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int idx) {
 // several blocks share a CU and keep loads in flight while others compute.
 template <typename T>
 constexpr int tile_elems() { return sizeof(T) == 8 ? 2048 : 4096; }
-// Tile of the column (y) kernels (measured: 64 KiB tiles, i.e. longer
-// mode-major runs but half the resident blocks, were slower on 256^2 x 64).
+// Columns (planes) per block of the column (y) kernels.  The mode-major side
+// S[kx][ky][p] is touched in runs of B consecutive planes, so B is the 32 KiB
+// tile's share unless that makes runs shorter than 64 bytes (ny >= 1024 in
+// float64, >= 1024 in float32), in which case the tile grows up to the
+// 160 KiB of LDS a block may use (powers of two).  Measured: 32-byte runs ran
+// at 1.5 TB/s, 64-byte runs at 4.4 TB/s, and 64 KiB tiles with 256-byte runs
+// were slower than 32 KiB ones at ny = 256.
+__host__ __device__ constexpr int col_batch_bytes(int n, int csize) {
+  int b = (32768 / csize) / n;
+  if (b < 1) b = 1;
+  const int minb = 64 / csize;
+  int maxb = 1;
+  while (2 * maxb * (n + 1) * csize <= 160 * 1024) maxb *= 2;
+  if (b < minb) b = minb < maxb ? minb : maxb;
+  return b;
+}
 template <typename T>
-constexpr int col_tile_elems() { return tile_elems<T>(); }
+__host__ __device__ constexpr int col_batch(int n) { return col_batch_bytes(n, (int)sizeof(cpx<T>)); }
 
 // NB transforms of length N = 2^LOGN held at buf[b * ld + k] (NB <= NBMAX),
 // Stockham autosort: one radix-2 stage first when LOGN is odd, then radix-4
@@ -196,7 +210,7 @@ template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
                                              int NP, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
-  constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
+  constexpr int B = col_batch<T>(N);
   static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
@@ -234,7 +248,7 @@ template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
                                              int NP, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
-  constexpr int B = (col_tile_elems<T>() / N) > 1 ? col_tile_elems<T>() / N : 1;
+  constexpr int B = col_batch<T>(N);
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
@@ -342,8 +356,7 @@ int rows_per_block(int nx, int ny) {
 
 template <typename T>
 int cols_per_block(int ny) {
-  int b = col_tile_elems<T>() / ny;
-  return b < 1 ? 1 : b;
+  return col_batch<T>(ny);
 }
 
 #define FVIM_LOGN_SWITCH(logn, CALL) \

@@ -18,6 +18,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -148,6 +149,7 @@ void worker(fvim_server* s) {
     {
       std::lock_guard<std::mutex> lk(s->mu);
       j->res.status = rc;
+      if (rc) snprintf(j->res.error, sizeof(j->res.error), "%s", fvim_last_error());
       j->res.t_done = now_s() - s->t0;
       j->res.p = j->p_host.empty() ? nullptr : j->p_host.data();
       j->res.u3p = j->u3_host.empty() ? nullptr : j->u3_host.data();

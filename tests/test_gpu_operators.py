@@ -46,6 +46,11 @@ CASES = [
     (8, 8, 2, 1.0, 1.0, 0.1),        # minimum depth count
     (4, 64, 200, 1.0, 2.0, 1.0),     # 64 lanes x 4 nodes, nx = 4
     (8, 4, 300, 0.5, 1.0, 2.0),      # 64 lanes x 8 nodes
+    (4, 1024, 5, 1.0, 4.0, 0.25),    # column kernels with 64 KiB tiles (4 planes per block)
+    (4, 2048, 3, 1.0, 8.0, 0.25),    # 128 KiB column tiles
+    (8, 4096, 2, 1.0, 8.0, 0.25),    # longest columns (2 planes per block)
+    (1024, 4, 3, 4.0, 1.0, 0.25),    # rows of 1024
+    (4096, 4, 2, 8.0, 1.0, 0.25),    # longest rows
 ]
 
 

@@ -37,7 +37,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("nx,ny,nz", [(32, 32, 16), (64, 32, 33), (128, 128, 64)])
+@pytest.mark.parametrize("nx,ny,nz", [(32, 32, 16), (64, 32, 33), (4, 1024, 5), (128, 128, 64)])
 def test_fp32_operator_error_vs_oracle(nx, ny, nz):
     g = grid_dict(nx, ny, nz, lz=0.25)
     eps = filtered_eigenstrain(g, seed=nz)
