@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals per second (0 = all at once)")
+    ap.add_argument("--anderson", type=int, default=0,
+                    help="solve/serve: Anderson depth of the outer fixed point (0 = Algorithm 1 relaxation)")
     return ap.parse_args()
 
 
@@ -162,7 +164,7 @@ def bench_solve(a):
     h = torch.from_numpy(paraboloid(g, R=0.5)).cuda()
     Ws = [0.002 * (i + 1) for i in range(10)]
     opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, max_outer=2000,
-                     max_plastic=20000)
+                     max_plastic=20000, anderson_m=a.anderson)
     times, infos = [], None
     for _ in range(max(1, a.steps)):
         ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=a.precision)
@@ -176,7 +178,8 @@ def bench_solve(a):
     ev = sum(i["r_evals"] for i in infos)
     print(json.dumps({"metric": "elastoplastic solve time", "value": float(np.median(times)), "unit": "s",
                       "higher_is_better": False, "n_gpus": 1, "steps": len(times),
-                      "config": {"workload": "paraboloid 32x32x16, W=0.02 in 10 steps", "precision": a.precision},
+                      "config": {"workload": "paraboloid 32x32x16, W=0.02 in 10 steps", "precision": a.precision,
+                                 "anderson": a.anderson},
                       "outer_iters": [i["outer_iters"] for i in infos], "residual_evals": ev,
                       "voxel_updates_per_s": ev * 32 * 32 * 16 / float(np.median(times))}))
 
@@ -196,7 +199,7 @@ def bench_serve(a):
                           seed=r["seed"])
         prepared.append((r, g, h))
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
-                     max_plastic=20000)
+                     max_plastic=20000, anderson_m=a.anderson)
     srv = Server(hbm_budget_bytes=200 << 30, max_slots=a.slots)
     t0 = time.perf_counter()
     ids = []
@@ -230,7 +233,7 @@ def bench_serve(a):
                       "run_s_median_by_grid": {k: float(np.median(v)) for k, v in sorted(by_grid.items())},
                       "failures": [d for d in detail if d["status"] != 0],
                       "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": a.slots,
-                                 "rate_per_s": a.rate, "precision": "fp32_refined"}}))
+                                 "rate_per_s": a.rate, "precision": "fp32_refined", "anderson": a.anderson}}))
 
 
 def main():

@@ -181,6 +181,10 @@ typedef struct {
   int solver;          /* 0 = DF-SANE (Sec. 4.3), 1 = Picard fixed point     */
   int literal_alg1;    /* 1: overwrite the relaxed update as printed; 0:   */
                        /* keep it (plain under-relaxation, same fixed pt) */
+  int anderson_m;      /* 0: Alg. 1 relaxation; 1..6: Anderson acceleration */
+                       /* of the same outer fixed point with that history  */
+                       /* depth and damping relax (Walker & Ni 2011); the  */
+                       /* stopping test is unchanged; ignored if literal   */
 } fvim_ep_opts;
 
 typedef struct {

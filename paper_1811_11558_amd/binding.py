@@ -51,12 +51,13 @@ class EPOptions(ctypes.Structure):
                 ("tol_plastic", ctypes.c_double), ("tol_contact", ctypes.c_double),
                 ("max_outer", ctypes.c_int), ("max_plastic", ctypes.c_int),
                 ("max_contact", ctypes.c_int), ("solver", ctypes.c_int),
-                ("literal_alg1", ctypes.c_int)]
+                ("literal_alg1", ctypes.c_int), ("anderson_m", ctypes.c_int)]
 
     def __init__(self, tol_outer=1e-9, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14,
-                 max_outer=400, max_plastic=2000, max_contact=20000, solver=0, literal_alg1=0):
+                 max_outer=400, max_plastic=2000, max_contact=20000, solver=0, literal_alg1=0,
+                 anderson_m=0):
         super().__init__(tol_outer, relax, tol_plastic, tol_contact, max_outer, max_plastic,
-                         max_contact, solver, literal_alg1)
+                         max_contact, solver, literal_alg1, anderson_m)
 
 
 class _EPInfo(ctypes.Structure):

@@ -305,6 +305,59 @@ __global__ __launch_bounds__(NT) void k_sq2(const double* __restrict__ a1, const
   block_sums<2>(v, part);
 }
 
+// ------------------------------------------- Anderson acceleration (outer)
+constexpr int AA_MMAX = 6;
+constexpr int aa_nsums(int m) { return m * (m + 1) / 2 + m; }
+
+// Gram matrix of the M residual differences dF[j] (stride n) and their
+// products with f: sums in the order (0,0) (0,1) .. (M-1,M-1), then <dF_j, f>.
+template <int M>
+__global__ __launch_bounds__(NT) void k_aa_gram(const double* __restrict__ dF, const double* __restrict__ f,
+                                               size_t n, double* part) {
+  constexpr int K = aa_nsums(M);
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double a[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) a[j] = dF[(size_t)j * n + i];
+    const double fi = f[i];
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+#pragma unroll
+      for (int l = j; l < M; ++l) v[k++] += a[j] * a[l];
+#pragma unroll
+    for (int j = 0; j < M; ++j) v[k++] += a[j] * fi;
+  }
+  block_sums<K>(v, part);
+}
+
+// out[k] = sum over the nb block partials of quantity k, fixed order
+__global__ __launch_bounds__(64) void k_aa_final(const double* __restrict__ part, int K, int nb, double* out) {
+  const int k = threadIdx.x;
+  if (k >= K) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[(size_t)k * RB + b];
+  out[k] = s;
+}
+
+struct AACoef {
+  double g[AA_MMAX];
+};
+
+// x <- x + beta f - sum_j g_j (dX_j + beta dF_j)
+__global__ __launch_bounds__(NT) void k_aa_step(double* __restrict__ x, const double* __restrict__ f,
+                                               const double* __restrict__ dX, const double* __restrict__ dF,
+                                               AACoef c, int m, double beta, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    double v = x[i] + beta * f[i];
+    for (int j = 0; j < m; ++j) v -= c.g[j] * (dX[(size_t)j * n + i] + beta * dF[(size_t)j * n + i]);
+    x[i] = v;
+  }
+}
+
 }  // namespace
 
 struct SolverWork {
@@ -325,6 +378,12 @@ struct SolverWork {
   hipGraphExec_t pk_exec = nullptr;
   const double* g_h = nullptr;
   const double* g_p = nullptr;
+  // Anderson history of the outer fixed point: dX, dF [AA_MMAX][ns];
+  // xprev, fprev, f [ns]; Gram partials and results (device, pinned host)
+  double* aa = nullptr;
+  double* aa_part = nullptr;
+  double* aa_out = nullptr;
+  double* aa_hout = nullptr;
 };
 
 static int sw_ensure(fvim_ctx* c) {
@@ -354,6 +413,10 @@ void solver_release(fvim_ctx* c) {
   if (w->sc) hipFree(w->sc);
   if (w->hsc) hipHostFree(w->hsc);
   if (w->vol) hipFree(w->vol);
+  if (w->aa) hipFree(w->aa);
+  if (w->aa_part) hipFree(w->aa_part);
+  if (w->aa_out) hipFree(w->aa_out);
+  if (w->aa_hout) hipHostFree(w->aa_hout);
   if (w->pk_exec) hipGraphExecDestroy(w->pk_exec);
   if (w->pk_graph) hipGraphDestroy(w->pk_graph);
   if (w->ev_in) hipEventDestroy(w->ev_in);
@@ -366,9 +429,10 @@ void solver_release(fvim_ctx* c) {
 size_t solver_footprint(const fvim_grid* g, size_t V) {
   const size_t ns = (size_t)g->nx * g->ny;
   const size_t nm = (size_t)(g->nx / 2 + 1) * g->ny;
-  // surface arrays (12 + dT 3), volume work arrays (7 tensors + 1 scalar),
-  // compliance spectra, reduction buffers
-  return sizeof(double) * (ns * 15 + 43 * V) + 2 * sizeof(cpx<double>) * nm + 64 * 1024;
+  // surface arrays (12 + dT 3 + Anderson history 2 AA_MMAX + 3), volume work
+  // arrays (7 tensors + 1 scalar), compliance spectra, reduction buffers
+  return sizeof(double) * (ns * (18 + 2 * AA_MMAX) + 43 * V) + 2 * sizeof(cpx<double>) * nm +
+         sizeof(double) * aa_nsums(AA_MMAX) * (RB + 2) + 64 * 1024;
 }
 
 // Host copy of device scalars [first, first + n) (synchronises the stream).
@@ -764,6 +828,80 @@ static int surf_norms(fvim_ctx* c, const double* a, const double* b, double* dno
   return FVIM_OK;
 }
 
+static int aa_ensure(fvim_ctx* c) {
+  SolverWork* w = c->sw;
+  if (w->aa) return FVIM_OK;
+  const int K = aa_nsums(AA_MMAX);
+  if (hipMalloc((void**)&w->aa, sizeof(double) * w->ns * (2 * AA_MMAX + 3)) != hipSuccess ||
+      hipMalloc((void**)&w->aa_part, sizeof(double) * K * RB) != hipSuccess ||
+      hipMalloc((void**)&w->aa_out, sizeof(double) * K) != hipSuccess ||
+      hipHostMalloc((void**)&w->aa_hout, sizeof(double) * K, hipHostMallocDefault) != hipSuccess)
+    return fail(FVIM_ENOMEM, "Anderson history allocation failed");
+  return FVIM_OK;
+}
+
+// Gram sums of the first m residual differences and f, copied to the host.
+static int aa_gram(fvim_ctx* c, int m, const double* f) {
+  SolverWork* w = c->sw;
+  hipStream_t st = c->stream;
+  const int nb = nblocks(w->ns);
+  const double* dF = w->aa + (size_t)AA_MMAX * w->ns;
+#define FVIM_AA_GRAM(M) hipLaunchKernelGGL(k_aa_gram<M>, dim3(nb), dim3(NT), 0, st, dF, f, w->ns, w->aa_part)
+  switch (m) {
+    case 1: FVIM_AA_GRAM(1); break;
+    case 2: FVIM_AA_GRAM(2); break;
+    case 3: FVIM_AA_GRAM(3); break;
+    case 4: FVIM_AA_GRAM(4); break;
+    case 5: FVIM_AA_GRAM(5); break;
+    case 6: FVIM_AA_GRAM(6); break;
+    default: return fail(FVIM_EINVAL, "Anderson depth out of range");
+  }
+#undef FVIM_AA_GRAM
+  const int K = aa_nsums(m);
+  hipLaunchKernelGGL(k_aa_final, dim3(1), dim3(64), 0, st, w->aa_part, K, nb, w->aa_out);
+  hipError_t e = hipMemcpyAsync(w->aa_hout, w->aa_out, sizeof(double) * K, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e == hipSuccess ? FVIM_OK : fail_hip(e, "Anderson Gram matrix");
+}
+
+// Least-squares weights: (G + 1e-12 max G_jj I) g = r by Cholesky, G_jl =
+// <dF_j, dF_l>, r_j = <dF_j, f>.  False when the differences are close to
+// linearly dependent (a pivot below 1e-10 of the largest diagonal), in
+// which case the caller drops the history.
+static bool aa_solve(int m, const double* sums, double* g) {
+  double G[AA_MMAX][AA_MMAX], L[AA_MMAX][AA_MMAX] = {}, r[AA_MMAX], y[AA_MMAX];
+  int k = 0;
+  for (int j = 0; j < m; ++j)
+    for (int l = j; l < m; ++l) G[j][l] = G[l][j] = sums[k++];
+  for (int j = 0; j < m; ++j) r[j] = sums[k++];
+  double dmax = 0.0;
+  for (int j = 0; j < m; ++j) dmax = std::max(dmax, G[j][j]);
+  if (!(dmax > 0.0) || !std::isfinite(dmax)) return false;
+  for (int j = 0; j < m; ++j) G[j][j] += 1e-12 * dmax;
+  for (int j = 0; j < m; ++j) {
+    double d = G[j][j];
+    for (int p = 0; p < j; ++p) d -= L[j][p] * L[j][p];
+    if (!(d > 1e-10 * dmax)) return false;
+    L[j][j] = std::sqrt(d);
+    for (int i = j + 1; i < m; ++i) {
+      double t = G[i][j];
+      for (int p = 0; p < j; ++p) t -= L[i][p] * L[j][p];
+      L[i][j] = t / L[j][j];
+    }
+  }
+  for (int j = 0; j < m; ++j) {
+    double t = r[j];
+    for (int p = 0; p < j; ++p) t -= L[j][p] * y[p];
+    y[j] = t / L[j][j];
+  }
+  for (int j = m - 1; j >= 0; --j) {
+    double t = y[j];
+    for (int p = j + 1; p < m; ++p) t -= L[p][j] * g[p];
+    g[j] = t / L[j][j];
+  }
+  return true;
+}
+
 }  // namespace fvim
 
 using namespace fvim;
@@ -782,7 +920,8 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
                         fvim_state* s, fvim_ep_info* info) {
   if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
   if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
-  if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1)
+  if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1 || o->anderson_m < 0 ||
+      o->anderson_m > AA_MMAX)
     return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
   int rc = sw_ensure(c);
   if (rc) return rc;
@@ -801,6 +940,17 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   // dT lives in the traction spectrum workspace? use a dedicated array
   double* dT = nullptr;
   if (hipMalloc((void**)&dT, sizeof(double) * 3 * n) != hipSuccess) return fail(FVIM_ENOMEM, "dT");
+  const int aam = o->literal_alg1 ? 0 : o->anderson_m;
+  if (aam > 0 && (rc = aa_ensure(c))) {
+    hipFree(dT);
+    return rc;
+  }
+  // Anderson history: differences of the iterates and of the residuals
+  double* aX = aam ? w->aa : nullptr;
+  double* aF = aam ? w->aa + (size_t)AA_MMAX * n : nullptr;
+  double* xprev = aam ? aF + (size_t)AA_MMAX * n : nullptr;
+  double* fprev = aam ? xprev + n : nullptr;
+  double* fres = aam ? fprev + n : nullptr;
   auto cleanup = [&](int r) {
     hipStreamSynchronize(st);
     hipFree(dT);
@@ -823,6 +973,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     if (e != hipSuccess) return cleanup(fail_hip(e, "step setup"));
     double err = INFINITY;
     int k;
+    int aa_count = 0, aa_head = 0;
     for (k = 1; k <= o->max_outer; ++k) {
       fvim_contact_info ci;
       rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
@@ -844,6 +995,31 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       double an;
       if ((rc = surf_norms(c, dU, dUp, &dn, &an))) return cleanup(rc);
       err = dn / hn;
+      inf.outer_err = err;
+      inf.outer_iters = k;
+      if (aam > 0) {
+        // x = dUp, f = G(x) - x; history update, least squares, step
+        axpy(c, fres, dU, -1.0, dUp, n);
+        if (k > 1) {
+          axpy(c, aX + (size_t)aa_head * n, dUp, -1.0, xprev, n);
+          axpy(c, aF + (size_t)aa_head * n, fres, -1.0, fprev, n);
+          aa_head = (aa_head + 1) % aam;
+          aa_count = std::min(aa_count + 1, aam);
+        }
+        e = hipMemcpyAsync(xprev, dUp, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(fprev, fres, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
+        if (err < o->tol_outer) break;
+        AACoef co = {};
+        int me = aa_count;
+        if (me > 0) {
+          if ((rc = aa_gram(c, me, fres))) return cleanup(rc);
+          if (!aa_solve(me, w->aa_hout, co.g)) me = aa_count = aa_head = 0;
+        }
+        hipLaunchKernelGGL(k_aa_step, dim3(nblocks(n)), dim3(NT), 0, st, dUp, fres, aX, aF, co, me, o->relax, n);
+        axpy(c, H, H0, -1.0, dUp, n);                     // H = H0 - x_(k+1)
+        continue;
+      }
       // relaxed surface correction, H = H0 - relaxed
       axpy(c, H, dUp, o->relax, dU, n);                  // H <- dUp + relax dU (temporarily)
       axpy(c, H, H, -o->relax, dUp, n);                  //      - relax dUp
@@ -855,7 +1031,6 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
         if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
       }
       axpy(c, H, H0, -1.0, H, n);                         // H = H0 - relaxed
-      inf.outer_err = err;
       if (err < o->tol_outer) break;
     }
     inf.outer_iters = k > o->max_outer ? o->max_outer : k;

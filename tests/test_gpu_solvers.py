@@ -117,6 +117,32 @@ def test_hertz_elastoplastic_matches_stored_oracle(solver):
         assert err < 1e-11, (k, err)
 
 
+def test_anderson_outer_reaches_the_stored_fixed_point():
+    """Anderson acceleration (depth 5, damping 0.3) of Algorithm 1's outer
+    fixed point reaches the state of the oracle's relaxed iteration (stored
+    by tests/golden/make_golden.py, outer error below 1e-11), within what the
+    two outer tolerances allow, in fewer outer passes (the oracle took 51 and
+    57)."""
+    import ast
+    from paper_1811_11558_amd import EPOptions
+    ref = np.load(GOLDEN)
+    meta = ast.literal_eval(str(ref["meta"][0]))
+    g = grid_dict(16, 16, 8, lz=0.25)
+    ctx = _ctx(g)
+    st = ctx.new_state()
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                    EPOptions(tol_outer=1e-12, relax=0.3, tol_plastic=1e-13,
+                                              tol_contact=1e-15, max_plastic=20000, anderson_m=5))
+    torch.cuda.synchronize()
+    passes = [i["outer_iters"] for i in infos]
+    _say("outer passes anderson / oracle relaxed", passes, meta["outer"])
+    assert all(a < b for a, b in zip(passes, meta["outer"]))
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < 1e-8, (k, err)
+
+
 def test_contact_graph_replay_equals_eager():
     """The contact iteration replayed as a captured HIP graph gives bitwise the
     same pressure as launching its kernels one by one (many replays, with
