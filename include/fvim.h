@@ -213,10 +213,10 @@ int elastoplastic_solve(fvim_ctx* ctx, const double* h, const double* W_steps, i
  * memory, caller-owned), then clears the record.  Stages:
  */
 enum {
-  FVIM_STAGE_XFWD = 0,   /* x transform of the eigenstrain planes        */
-  FVIM_STAGE_YFWD = 1,   /* y transform of the eigenstrain planes        */
-  FVIM_STAGE_XFWD_T = 2, /* x transform of the traction planes           */
-  FVIM_STAGE_YFWD_T = 3, /* y transform of the traction planes           */
+  FVIM_STAGE_XFWD = 0,   /* x transform of the eigenstrain and traction planes */
+  FVIM_STAGE_YFWD = 1,   /* y transform of the same planes               */
+  FVIM_STAGE_XFWD_T = 2, /* unused (the traction planes are part of XFWD) */
+  FVIM_STAGE_YFWD_T = 3, /* unused (part of YFWD)                        */
   FVIM_STAGE_DEPTH = 4,  /* per-mode depth pass, all but Nyquist modes   */
   FVIM_STAGE_YINV = 5,   /* inverse y transform of the output planes     */
   FVIM_STAGE_XINV = 6,   /* inverse x transform of the output planes     */
@@ -234,9 +234,11 @@ int fvim_set_timing(fvim_ctx* ctx, int on);
  * Callers that need run-to-run identical results store the chosen id and
  * set it explicitly.  FVIM_OPT_GRAPHS (default 1): the contact iteration is
  * captured once as a HIP graph and replayed (same kernels, same results; 0
- * launches the kernels one by one).
+ * launches the kernels one by one).  FVIM_OPT_SIDE_STREAM (default 0): 1 runs
+ * the Nyquist-mode depth launch on a second library stream beside the main
+ * depth launch (same results).
  */
-enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3 };
+enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3, FVIM_OPT_SIDE_STREAM = 4 };
 int fvim_set_option(fvim_ctx* ctx, int key, int value);
 int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);

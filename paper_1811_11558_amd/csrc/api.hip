@@ -4,6 +4,7 @@
 // the device workspace and sequences the launches on the context stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -75,22 +76,39 @@ struct StageTimer {
   fvim_ctx* c;
   int stage = -1;
   hipEvent_t a = nullptr;
+  hipStream_t s = nullptr;
   explicit StageTimer(fvim_ctx* cc) : c(cc) {}
-  void begin(int s) {
+  void begin(int stg, hipStream_t on) {
     if (!c->timing) return;
-    stage = s;
+    stage = stg;
+    s = on;
     hipEventCreate(&a);
-    hipEventRecord(a, c->stream);
+    hipEventRecord(a, s);
   }
   void end() {
     if (!c->timing || stage < 0) return;
     hipEvent_t b;
     hipEventCreate(&b);
-    hipEventRecord(b, c->stream);
+    hipEventRecord(b, s);
     c->evs.push_back({stage, a, b});
     stage = -1;
   }
 };
+
+static int side_ensure(fvim_ctx* c) {
+  if (c->side) return FVIM_OK;
+  hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  hipEvent_t* evs[] = {&c->ev_spec, &c->ev_nyq};
+  for (hipEvent_t* ev : evs)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  return e == hipSuccess ? FVIM_OK : fail_hip(e, "side stream");
+}
+
+// b waits for everything issued on a so far
+static hipError_t join(hipEvent_t ev, hipStream_t a, hipStream_t b) {
+  hipError_t e = hipEventRecord(ev, a);
+  return e == hipSuccess ? hipStreamWaitEvent(b, ev, 0) : e;
+}
 
 // Times every valid depth-pass configuration on the live buffers (three
 // launches each after one warm-up) and keeps the fastest in the context.
@@ -98,7 +116,7 @@ struct StageTimer {
 // rounding); it is fixed for the context afterwards, so results are
 // reproducible for a given configuration.
 template <typename T>
-int tune_depth(fvim_ctx* c, const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& prm) {
+int tune_depth(fvim_ctx* c, const cpx<T>* in, cpx<T>* out, const DepthParams& prm) {
   hipStream_t st = c->stream;
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(FVIM_EHIP, "events");
@@ -106,9 +124,9 @@ int tune_depth(fvim_ctx* c, const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, co
   int best_id = depth_default_config(prm.nz);
   for (int id = 0; id < depth_num_configs(); ++id) {
     if (!depth_config_valid(id, prm.nz)) continue;
-    hipError_t e = launch_depth<T>(in, tin, out, prm, id, st);
+    hipError_t e = launch_depth<T>(in, out, prm, id, st);
     hipEventRecord(a, st);
-    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_depth<T>(in, tin, out, prm, id, st);
+    for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch_depth<T>(in, out, prm, id, st);
     hipEventRecord(b, st);
     if (e == hipSuccess) e = hipEventSynchronize(b);
     float ms = 0.f;
@@ -162,21 +180,26 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   if (disp) { prm.off_disp = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = disp; np += 3 * nz; }
   if (surf_u3) { prm.off_u3 = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = surf_u3; np += 1; }
   prm.np_out = np;
+  prm.ld_out = mode_stride<T>(np);
   if (np == 0) return FVIM_OK;
-  const int np_in = eps_p ? 6 * nz : 0;
-  const size_t planes = (size_t)(np > np_in ? np : np_in);
+  // input planes: the 6 nz eigenstrain planes, then the 3 traction planes,
+  // transformed together (one launch per direction)
+  const int np_in = (eps_p ? 6 * nz : 0) + (traction ? 3 : 0);
+  prm.np_in = np_in;
+  prm.ld_in = mode_stride<T>(np_in);
+  prm.off_t = eps_p ? 6 * nz : 0;
+  InSegments iseg;
+  iseg.n = 0;
+  iseg.first[0] = iseg.first[1] = 0;
+  iseg.ptr[0] = iseg.ptr[1] = nullptr;
+  if (eps_p) { iseg.first[iseg.n] = 0; iseg.ptr[iseg.n++] = eps_p; }
+  if (traction) { iseg.first[iseg.n] = prm.off_t; iseg.ptr[iseg.n++] = traction; }
+  const size_t planes = (size_t)std::max(prm.ld_out, prm.ld_in);
   const size_t bytes = planes * nmodes * sizeof(cpx<T>);
   int rc = ctx_reserve(c, &c->bufA, &c->bufA_bytes, bytes);
   if (rc) return rc;
   rc = ctx_reserve(c, &c->bufB, &c->bufB_bytes, bytes);
   if (rc) return rc;
-  const size_t tbytes = 3 * nmodes * sizeof(cpx<T>);
-  if (traction) {
-    rc = ctx_reserve(c, &c->tA, &c->tA_bytes, tbytes);
-    if (rc) return rc;
-    rc = ctx_reserve(c, &c->tB, &c->tB_bytes, tbytes);
-    if (rc) return rc;
-  }
   const int wbpp = x_r2c_blocks_per_plane<T>(nx, ny);
   double* wsum = nullptr;
   double* tsum = nullptr;
@@ -185,9 +208,9 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
     const size_t kb = sizeof(double) * ((size_t)(6 * nz + 3) * wbpp + (size_t)np);
     rc = ctx_reserve(c, &c->k0buf, &c->k0buf_bytes, kb);
     if (rc) return rc;
-    wsum = (double*)c->k0buf;
-    tsum = wsum + (size_t)6 * nz * wbpp;
-    padd = tsum + (size_t)3 * wbpp;
+    wsum = (double*)c->k0buf;                      // block sums of every input plane
+    tsum = wsum + (size_t)prm.off_t * wbpp;
+    padd = wsum + (size_t)(6 * nz + 3) * wbpp;
   }
   void*& mt = sizeof(T) == 8 ? c->mt64 : c->mt32;
   if (!mt) {
@@ -204,47 +227,41 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   cpx<T>* A = (cpx<T>*)c->bufA;
   cpx<T>* B = (cpx<T>*)c->bufB;
   hipStream_t st = c->stream;
+  const bool side = c->use_side != 0;
+  if (side && (rc = side_ensure(c))) return rc;
+  // the Nyquist-mode depth launch may run on the side stream beside the main
+  // one (disjoint modes); measured slower in float64, so off by default
+  hipStream_t ss = side ? c->side : st;
   hipError_t e;
   StageTimer tm(c);
-  if (eps_p) {
-    tm.begin(FVIM_STAGE_XFWD);
-    if ((e = launch_x_r2c<T>(eps_p, A, nx, ny, (size_t)6 * nz, twx, st, wsum)) != hipSuccess)
-      return fail_hip(e, "x_r2c");
-    tm.end();
-    tm.begin(FVIM_STAGE_YFWD);
-    if ((e = launch_y_fwd<T>(A, B, ny, kxh, 6 * nz, twy, st)) != hipSuccess) return fail_hip(e, "y_fwd");
-    tm.end();
-  }
-  if (traction) {
-    tm.begin(FVIM_STAGE_XFWD_T);
-    if ((e = launch_x_r2c<T>(traction, (cpx<T>*)c->tA, nx, ny, 3, twx, st, tsum)) != hipSuccess)
-      return fail_hip(e, "x_r2c(t)");
-    tm.end();
-    tm.begin(FVIM_STAGE_YFWD_T);
-    if ((e = launch_y_fwd<T>((cpx<T>*)c->tA, (cpx<T>*)c->tB, ny, kxh, 3, twy, st)) != hipSuccess)
-      return fail_hip(e, "y_fwd(t)");
-    tm.end();
-  }
+  tm.begin(FVIM_STAGE_XFWD, st);
+  if ((e = launch_x_r2c<T>(iseg, A, nx, ny, (size_t)np_in, twx, st, wsum)) != hipSuccess)
+    return fail_hip(e, "x_r2c");
+  tm.end();
+  tm.begin(FVIM_STAGE_YFWD, st);
+  if ((e = launch_y_fwd<T>(A, B, ny, kxh, np_in, prm.ld_in, twy, st)) != hipSuccess) return fail_hip(e, "y_fwd");
+  tm.end();
   if (c->tune_pending) {
     c->tune_pending = 0;
-    int rc2 = tune_depth<T>(c, B, (const cpx<T>*)c->tB, A, prm);
+    int rc2 = tune_depth<T>(c, B, A, prm);
     if (rc2) return rc2;
   }
-  tm.begin(FVIM_STAGE_DEPTH);
-  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st, 1)) != hipSuccess)
-    return fail_hip(e, "depth");
+  if (ss != st && (e = join(c->ev_spec, st, ss)) != hipSuccess) return fail_hip(e, "fork");
+  tm.begin(FVIM_STAGE_DEPTH, st);
+  if ((e = launch_depth<T>(B, A, prm, c->depth_cfg, st, 1)) != hipSuccess) return fail_hip(e, "depth");
   tm.end();
-  tm.begin(FVIM_STAGE_DEPTH_NYQ);
-  if ((e = launch_depth<T>(B, (const cpx<T>*)c->tB, A, prm, c->depth_cfg, st, 2)) != hipSuccess)
+  tm.begin(FVIM_STAGE_DEPTH_NYQ, ss);
+  if ((e = launch_depth<T>(B, A, prm, c->depth_cfg, ss, 2)) != hipSuccess)
     return fail_hip(e, "depth (Nyquist modes)");
   tm.end();
+  if (ss != st && (e = join(c->ev_nyq, ss, st)) != hipSuccess) return fail_hip(e, "join");
   if (k0x) {
     if ((e = launch_k0_fields(wsum, wbpp, tsum, wbpp, padd, prm, st)) != hipSuccess) return fail_hip(e, "k0");
   }
-  tm.begin(FVIM_STAGE_YINV);
-  if ((e = launch_y_inv<T>(A, B, ny, kxh, np, twy, st)) != hipSuccess) return fail_hip(e, "y_inv");
+  tm.begin(FVIM_STAGE_YINV, st);
+  if ((e = launch_y_inv<T>(A, B, ny, kxh, np, prm.ld_out, twy, st)) != hipSuccess) return fail_hip(e, "y_inv");
   tm.end();
-  tm.begin(FVIM_STAGE_XINV);
+  tm.begin(FVIM_STAGE_XINV, st);
   if ((e = launch_x_c2r<T>(B, seg, nx, ny, (size_t)np, 1.0, twx, st, padd)) != hipSuccess)
     return fail_hip(e, "x_c2r");
   tm.end();
@@ -321,9 +338,14 @@ void fvim_destroy(fvim_ctx* c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->tA, c->tB, c->k0buf, c->mt64, c->mt32};
+  if (c->side) hipStreamSynchronize(c->side);
+  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32};
   for (void* p : ptrs)
     if (p) hipFree(p);
+  hipEvent_t evs[] = {c->ev_spec, c->ev_nyq};
+  for (hipEvent_t ev : evs)
+    if (ev) hipEventDestroy(ev);
+  if (c->side) hipStreamDestroy(c->side);
   solver_release(c);
   for (auto& ev : c->evs) {
     hipEventDestroy(ev.a);
@@ -346,6 +368,9 @@ int fvim_set_option(fvim_ctx* c, int key, int value) {
     case FVIM_OPT_GRAPHS:
       c->use_graphs = value ? 1 : 0;
       return FVIM_OK;
+    case FVIM_OPT_SIDE_STREAM:
+      c->use_side = value ? 1 : 0;
+      return FVIM_OK;
   }
   return fail(FVIM_EINVAL, "unknown option");
 }
@@ -361,6 +386,9 @@ int fvim_get_option(fvim_ctx* c, int key, int* value) {
       return FVIM_OK;
     case FVIM_OPT_GRAPHS:
       *value = c->use_graphs;
+      return FVIM_OK;
+    case FVIM_OPT_SIDE_STREAM:
+      *value = c->use_side;
       return FVIM_OK;
   }
   return fail(FVIM_EINVAL, "unknown option");
@@ -404,8 +432,8 @@ size_t fvim_footprint_bytes(const fvim_grid* g, int precision, int with_solver_s
   const size_t nmodes = (size_t)(g->nx / 2 + 1) * g->ny;
   // the solvers of the FP32_REFINED mode also apply the float64 operator
   const size_t csz = (precision == FVIM_FP32_REFINED && !with_solver_state) ? 8 : 16;
-  const size_t planes = 15 * (size_t)g->nz + 1;
-  size_t b = 2 * planes * nmodes * csz + 6 * nmodes * csz;
+  const size_t planes = 15 * (size_t)g->nz + 16;   // largest record, padded to 128 B
+  size_t b = 2 * planes * nmodes * csz;
   b += nmodes * (sizeof(ModeConst<double>) + (precision == FVIM_FP32_REFINED ? sizeof(ModeConst<float>) : 0));
   const size_t V = (size_t)g->nx * g->ny * g->nz;
   if (with_solver_state) b += solver_footprint(g, V);

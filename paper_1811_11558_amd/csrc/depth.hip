@@ -141,8 +141,8 @@ __device__ __forceinline__ void put(cpx<T>* __restrict__ dst, cpx<T> v, bool fir
 // of its 2 or 4 sign replicas (indexed by group: first the kx = nx/2 column,
 // then the ky = ny/2 row without its kx = nx/2 entry).
 template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
-__global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, const cpx<T>* __restrict__ tin,
-                                             cpx<T>* __restrict__ out, DepthParams prm) {
+__global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                             DepthParams prm) {
   constexpr int GPB = NT / LPM;
   const int g = threadIdx.x / LPM;
   const int l = threadIdx.x - g * LPM;
@@ -160,8 +160,8 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
   }
   const int mode = kx * prm.ny + ky;
   const int nz = prm.nz;
-  const cpx<T>* __restrict__ src = in + (size_t)mode * 6 * nz;
-  cpx<T>* __restrict__ dst = out + (size_t)mode * prm.np_out;
+  const cpx<T>* __restrict__ src = in + (size_t)mode * prm.ld_in;
+  cpx<T>* __restrict__ dst = out + (size_t)mode * prm.ld_out;
   const T nrm = (T)prm.norm;
   const T kap = (T)prm.kappa;
   const T mu = (T)prm.mu;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, con
 
   cpx<T> tr[3];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) tr[c] = prm.has_t ? scl(tin[(size_t)mode * 3 + c], nrm / mu) : zero<T>();
+  for (int c = 0; c < 3; ++c) tr[c] = prm.has_t ? scl(src[prm.off_t + c], nrm / mu) : zero<T>();
 
   // strain e (original frame, 6 comps) of node i -> outputs (stress needs eps_p again)
   auto emit = [&](int i, const cpx<T> e[6], bool first, T wgt) {
@@ -474,31 +474,31 @@ __global__ __launch_bounds__(NT) void k_mode_table(ModeConst<T>* __restrict__ ta
 }
 
 template <typename T, int LPM, int P, bool DISP, bool WANTX>
-hipError_t launch_two(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st,
+hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipStream_t st,
                       int part) {
   constexpr int GPB = NT / LPM;
   if (part != 2) {
     const int nmodes = p.kxh * p.ny;
     const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
-    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, tin, out, p);
+    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, out, p);
   }
   if (part != 1) {
     const int nnyq = p.ny + p.kxh - 1;
     const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
-    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, tin, out, p);
+    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, out, p);
   }
   return hipGetLastError();
 }
 
 template <typename T, int LPM, int P>
-hipError_t launch_cfg(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, hipStream_t st,
+hipError_t launch_cfg(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipStream_t st,
                       int part) {
   const bool disp = p.off_disp >= 0 || p.off_u3 >= 0;
   const bool wx = p.off_stress >= 0;
-  if (disp) return wx ? launch_two<T, LPM, P, true, true>(in, tin, out, p, st, part)
-                      : launch_two<T, LPM, P, true, false>(in, tin, out, p, st, part);
-  return wx ? launch_two<T, LPM, P, false, true>(in, tin, out, p, st, part)
-            : launch_two<T, LPM, P, false, false>(in, tin, out, p, st, part);
+  if (disp) return wx ? launch_two<T, LPM, P, true, true>(in, out, p, st, part)
+                      : launch_two<T, LPM, P, true, false>(in, out, p, st, part);
+  return wx ? launch_two<T, LPM, P, false, true>(in, out, p, st, part)
+            : launch_two<T, LPM, P, false, false>(in, out, p, st, part);
 }
 
 // (lanes per mode, nodes per lane) configurations; a configuration serves
@@ -540,8 +540,8 @@ hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, doubl
 }
 
 template <typename T>
-hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& prm, int cfg,
-                        hipStream_t st, int part) {
+hipError_t launch_depth(const cpx<T>* in, cpx<T>* out, const DepthParams& prm, int cfg, hipStream_t st,
+                        int part) {
   if (!prm.mtab) return hipErrorInvalidValue;
   DepthParams p = prm;
   const double kap = p.kappa, kp2 = kap + 2.0;
@@ -553,22 +553,21 @@ hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const 
   p.ik2 = 1.0 / (2.0 * kap + 2.0);
   if (!depth_config_valid(cfg, p.nz)) cfg = depth_default_config(p.nz);
   switch (cfg) {
-    case 0: return launch_cfg<T, 16, 1>(in, tin, out, p, st, part);
-    case 1: return launch_cfg<T, 16, 2>(in, tin, out, p, st, part);
-    case 2: return launch_cfg<T, 32, 1>(in, tin, out, p, st, part);
-    case 3: return launch_cfg<T, 32, 2>(in, tin, out, p, st, part);
-    case 4: return launch_cfg<T, 64, 1>(in, tin, out, p, st, part);
-    case 5: return launch_cfg<T, 64, 2>(in, tin, out, p, st, part);
-    case 6: return launch_cfg<T, 64, 4>(in, tin, out, p, st, part);
-    case 7: return launch_cfg<T, 64, 8>(in, tin, out, p, st, part);
+    case 0: return launch_cfg<T, 16, 1>(in, out, p, st, part);
+    case 1: return launch_cfg<T, 16, 2>(in, out, p, st, part);
+    case 2: return launch_cfg<T, 32, 1>(in, out, p, st, part);
+    case 3: return launch_cfg<T, 32, 2>(in, out, p, st, part);
+    case 4: return launch_cfg<T, 64, 1>(in, out, p, st, part);
+    case 5: return launch_cfg<T, 64, 2>(in, out, p, st, part);
+    case 6: return launch_cfg<T, 64, 4>(in, out, p, st, part);
+    case 7: return launch_cfg<T, 64, 8>(in, out, p, st, part);
   }
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_depth<double>(const cpx<double>*, const cpx<double>*, cpx<double>*,
-                                         const DepthParams&, int, hipStream_t, int);
-template hipError_t launch_depth<float>(const cpx<float>*, const cpx<float>*, cpx<float>*, const DepthParams&,
-                                        int, hipStream_t, int);
+template hipError_t launch_depth<double>(const cpx<double>*, cpx<double>*, const DepthParams&, int, hipStream_t,
+                                         int);
+template hipError_t launch_depth<float>(const cpx<float>*, cpx<float>*, const DepthParams&, int, hipStream_t, int);
 template hipError_t launch_mode_table<double>(ModeConst<double>*, int, int, double, double, double, hipStream_t);
 template hipError_t launch_mode_table<float>(ModeConst<float>*, int, int, double, double, double, hipStream_t);
 

@@ -140,8 +140,8 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T
 // If bsum is not NULL, block b also writes the float64 sum of its R rows to
 // bsum[b] (the plane means of the mean mode are then formed in float64).
 template <typename T, int LOGN>
-__global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx<T>* __restrict__ out, int ny,
-                                             int R, const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
+__global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
+                                             const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
   constexpr int N = 1 << LOGN;
   constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
@@ -150,10 +150,12 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
   const size_t row0 = (size_t)blockIdx.x * R;
   const size_t plane = row0 / ny;
   const int y0 = (int)(row0 - plane * ny);
+  const int sg = (seg.n > 1 && (int)plane >= seg.first[1]) ? 1 : 0;
+  const double* in = seg.ptr[sg] + ((plane - seg.first[sg]) * ny + y0) * (size_t)N;
   // 16-byte loads: two consecutive x of one row
   constexpr int MV = (2 * SEQ * N / 2 + NT - 1) / NT;
   const int tot = R * N / 2;
-  const double2* src = reinterpret_cast<const double2*>(in + row0 * N);
+  const double2* src = reinterpret_cast<const double2*>(in);
   double2 v[MV];
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(NT) void k_x_r2c(const double* __restrict__ in, cpx
 // through scratch memory, doubling the kernel's memory traffic.
 template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
-                                             int NP, const cpx<T>* __restrict__ tw) {
+                                             int NP, int ldp, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   constexpr int B = col_batch<T>(N);
   static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
@@ -239,14 +241,14 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
   for (int u = 0; u < MV; ++u) {
     const int i = threadIdx.x + u * NT;
     const int ky = i / B, b = i - ky * B;
-    if (b < nb) out[((size_t)kx * N + ky) * NP + p0 + b] = buf[b * ld + ky];
+    if (b < nb) out[((size_t)kx * N + ky) * ldp + p0 + b] = buf[b * ld + ky];
   }
 }
 
 // Inverse column transform: S[kx][ky][p] -> X[p][kx][y].
 template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
-                                             int NP, const cpx<T>* __restrict__ tw) {
+                                             int NP, int ldp, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
   constexpr int B = col_batch<T>(N);
   constexpr int ld = N + 1;
@@ -265,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
     const int i = threadIdx.x + u * NT;
     const int ky = i / B, b = i - ky * B;
     const int bc = b < nb ? b : nb - 1;
-    v[u] = in[((size_t)kx * N + ky) * NP + p0 + bc];
+    v[u] = in[((size_t)kx * N + ky) * ldp + p0 + bc];
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -385,33 +387,46 @@ int x_r2c_blocks_per_plane(int nx, int ny) {
 }
 
 template <typename T>
-hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
+hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum) {
+  if (seg.n < 1 || seg.n > 2 || seg.first[0] != 0) return hipErrorInvalidValue;
   int R = rows_per_block<T>(nx, ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, in, out, ny, R, tw, bsum)
+#define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
+hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
+                        hipStream_t st, double* bsum) {
+  InSegments seg;
+  seg.n = 1;
+  seg.first[0] = seg.first[1] = 0;
+  seg.ptr[0] = seg.ptr[1] = in;
+  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum);
+}
+
+template <typename T>
+hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
                         hipStream_t st) {
+  if (ldp < NP) return hipErrorInvalidValue;
   int B = cols_per_block<T>(ny);
   dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, tw)
+#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
+hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
                         hipStream_t st) {
+  if (ldp < NP) return hipErrorInvalidValue;
   int B = cols_per_block<T>(ny);
   dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L) hipLaunchKernelGGL((k_y_inv<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, tw)
+#define CALL(L) hipLaunchKernelGGL((k_y_inv<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();
@@ -430,17 +445,21 @@ hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny
 
 template hipError_t launch_x_r2c<double>(const double*, cpx<double>*, int, int, size_t, const cpx<double>*,
                                          hipStream_t, double*);
+template hipError_t launch_x_r2c<double>(const InSegments&, cpx<double>*, int, int, size_t,
+                                         const cpx<double>*, hipStream_t, double*);
+template hipError_t launch_x_r2c<float>(const InSegments&, cpx<float>*, int, int, size_t, const cpx<float>*,
+                                        hipStream_t, double*);
 template hipError_t launch_x_r2c<float>(const double*, cpx<float>*, int, int, size_t, const cpx<float>*,
                                         hipStream_t, double*);
 template int x_r2c_blocks_per_plane<double>(int, int);
 template int x_r2c_blocks_per_plane<float>(int, int);
-template hipError_t launch_y_fwd<double>(const cpx<double>*, cpx<double>*, int, int, int, const cpx<double>*,
-                                         hipStream_t);
-template hipError_t launch_y_fwd<float>(const cpx<float>*, cpx<float>*, int, int, int, const cpx<float>*,
+template hipError_t launch_y_fwd<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
+                                         const cpx<double>*, hipStream_t);
+template hipError_t launch_y_fwd<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
                                         hipStream_t);
-template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, int, int, const cpx<double>*,
-                                         hipStream_t);
-template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, const cpx<float>*,
+template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
+                                         const cpx<double>*, hipStream_t);
+template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
                                         hipStream_t);
 template hipError_t launch_x_c2r<double>(const cpx<double>*, const OutSegments&, int, int, size_t, double,
                                          const cpx<double>*, hipStream_t, const double*);

@@ -12,27 +12,48 @@ struct OutSegments {
   double* ptr[4];
 };
 
+// Source of the planes entering the forward x transform: plane p comes from
+// ptr[s] at local plane p - first[s] for the last s with first[s] <= p.
+struct InSegments {
+  int n;
+  int first[2];
+  const double* ptr[2];
+};
+
 // bsum (optional): float64 sum of the rows of each block, blocks of a plane
 // consecutive (x_r2c_blocks_per_plane of them).
+template <typename T>
+hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
+                        hipStream_t st, double* bsum = nullptr);
 template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum = nullptr);
 template <typename T>
 int x_r2c_blocks_per_plane(int nx, int ny);
+// Column transforms between X[p][kx][y] (p < NP) and the mode-major
+// S[kx][ky][ldp] (record stride ldp >= NP; the padding is not touched).
 template <typename T>
-hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
+hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
                         hipStream_t st);
 template <typename T>
-hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, const cpx<T>* tw,
+hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
                         hipStream_t st);
+// Record stride of a mode-major spectrum of np planes: a whole number of
+// 128-byte lines, so every mode's record starts on a line.
+template <typename T>
+inline int mode_stride(int np) {
+  const int q = 128 / (int)sizeof(cpx<T>);
+  return (np + q - 1) / q * q;
+}
 // padd (optional): float64 constant added to each plane of the output.
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr);
 
-// Per-mode depth pass.  Input spectrum (unnormalised DFT of the plastic
-// strain) in mode-major layout in[mode][6][nz]; traction spectrum
-// tin[mode][3]; output out[mode][np_out] holding the requested fields at
+// Per-mode depth pass.  Input spectra (unnormalised DFTs) in mode-major
+// layout in[mode][ld_in]: the plastic strain as [6][nz] at offset 0 (if
+// has_w) and the traction as [3] at offset off_t (if has_t); output
+// out[mode][ld_out] holding the np_out requested planes at
 // plane offsets off_* (negative = not requested): strain and stress as
 // [6][nz], displacement as [3][nz], surface u3 as one plane.
 struct DepthParams {
@@ -42,7 +63,8 @@ struct DepthParams {
   double norm;            // 1 / (nx ny)
   int has_w, has_t, k0_include;
   int k0_external;        // 1: the mean mode is added by the caller in float64; write 0 here
-  int np_out;
+  int np_in, off_t, ld_in;
+  int np_out, ld_out;
   int off_strain, off_stress, off_disp, off_u3;
   const void* mtab;       // ModeConst<T>[kxh * ny] of this grid (launch_mode_table)
   // ratios of kappa, filled by launch_depth: 1/(kappa+2), (kappa+1)/(kappa+2),
@@ -65,8 +87,8 @@ hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, doubl
 // part: 0 = every mode (two launches), 1 = all but the Nyquist modes,
 // 2 = the Nyquist modes only.
 template <typename T>
-hipError_t launch_depth(const cpx<T>* in, const cpx<T>* tin, cpx<T>* out, const DepthParams& p, int cfg,
-                        hipStream_t st, int part = 0);
+hipError_t launch_depth(const cpx<T>* in, cpx<T>* out, const DepthParams& p, int cfg, hipStream_t st,
+                        int part = 0);
 int depth_num_configs();
 bool depth_config_valid(int id, int nz);
 int depth_default_config(int nz);

@@ -471,13 +471,13 @@ static int compliance(fvim_ctx* c, const double* p, double* u, hipStream_t st) {
   cpx<double>* B = (cpx<double>*)w->specB;
   hipError_t e;
   if ((e = launch_x_r2c<double>(p, A, nx, ny, 1, twx, st)) != hipSuccess) return fail_hip(e, "compliance x");
-  if ((e = launch_y_fwd<double>(A, B, ny, kxh, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y");
+  if ((e = launch_y_fwd<double>(A, B, ny, kxh, 1, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y");
   const double estar = c->mat.E / (1.0 - c->mat.nu * c->mat.nu);
   const double fac = 2.0 / estar / ((double)nx * ny);
   const int nm = kxh * ny;
   hipLaunchKernelGGL(k_compliance, dim3((nm + NT - 1) / NT), dim3(NT), 0, st, B, nx, ny, c->grid.lx, c->grid.ly,
                      fac);
-  if ((e = launch_y_inv<double>(B, A, ny, kxh, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y^-1");
+  if ((e = launch_y_inv<double>(B, A, ny, kxh, 1, 1, twy, st)) != hipSuccess) return fail_hip(e, "compliance y^-1");
   OutSegments seg;
   seg.n = 1;
   seg.first[0] = 0;

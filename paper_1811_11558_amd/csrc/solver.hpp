@@ -26,12 +26,15 @@ struct fvim_ctx {
   void* twy32 = nullptr;
   void* bufA = nullptr;
   void* bufB = nullptr;
-  void* tA = nullptr;
-  void* tB = nullptr;
   void* k0buf = nullptr;       // float64 plane sums and mean-mode constants (FP32 path)
   void* mt64 = nullptr;        // per-mode depth-pass constants (built on first use)
   void* mt32 = nullptr;
-  size_t bufA_bytes = 0, bufB_bytes = 0, tA_bytes = 0, tB_bytes = 0, k0buf_bytes = 0;
+  // optional second stream (default priority) for the Nyquist-mode depth
+  // launch beside the main one, with its fork/join events
+  int use_side = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_spec = nullptr, ev_nyq = nullptr;
+  size_t bufA_bytes = 0, bufB_bytes = 0, k0buf_bytes = 0;
   fvim::SolverWork* sw = nullptr;
   // tuning: depth-pass configuration id (-1 = default for nz), and a request
   // to time every candidate on the next operator call
