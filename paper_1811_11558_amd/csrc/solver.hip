@@ -384,6 +384,18 @@ struct SolverWork {
   double* aa_part = nullptr;
   double* aa_out = nullptr;
   double* aa_hout = nullptr;
+  // captured residual evaluations R(x) -> F (return map, operator, residual
+  // and its reduction), one per combination of the pointers and settings they
+  // bake in; replayed on the context stream
+  struct ResGraph {
+    const void* key[10] = {};
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+  };
+  ResGraph rg[4];
+  int rg_next = 0;
+  int rg_warm[2] = {0, 0};       // an eager evaluation has sized every buffer (per precision)
+  int rg_off = 0;                // capture failed once: evaluate eagerly from now on
 };
 
 static int sw_ensure(fvim_ctx* c) {
@@ -417,6 +429,10 @@ void solver_release(fvim_ctx* c) {
   if (w->aa_part) hipFree(w->aa_part);
   if (w->aa_out) hipFree(w->aa_out);
   if (w->aa_hout) hipHostFree(w->aa_hout);
+  for (auto& r : w->rg) {
+    if (r.ex) hipGraphExecDestroy(r.ex);
+    if (r.g) hipGraphDestroy(r.g);
+  }
   if (w->pk_exec) hipGraphExecDestroy(w->pk_exec);
   if (w->pk_graph) hipGraphDestroy(w->pk_graph);
   if (w->ev_in) hipEventDestroy(w->ev_in);
@@ -661,7 +677,8 @@ static double inner_scale(const fvim_ctx* c) {
 }
 
 // R(x) into F; returns |R|^2 (weighted) in *f
-static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F, double* f) {
+// Launches of one residual evaluation on the context stream.
+static int residual_launches(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F) {
   SolverWork* w = c->sw;
   const size_t V = w->V, n6 = 6 * V;
   hipStream_t st = c->stream;
@@ -673,6 +690,60 @@ static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const doubl
   const int nb = nblocks(n6);
   hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, st, F, x, pb.b, pb.wk, w->ns, c->grid.nz, n6, w->part);
   hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, st, 6, w->part, nb, w->sc);
+  return FVIM_OK;
+}
+
+// The residual evaluation as a replayed HIP graph when the context allows it
+// (graphs on, no tuning or stage timing pending, buffers already sized by an
+// eager evaluation in this precision); else launched directly.
+static int residual_enqueue(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F) {
+  SolverWork* w = c->sw;
+  const int p64 = (c->precision == FVIM_FP64 || c->force_fp64) ? 1 : 0;
+  if (!c->use_graphs || w->rg_off || c->tune_pending || c->timing || c->use_side)
+    return residual_launches(c, s, pb, x, F);
+  if (!w->rg_warm[p64]) {
+    w->rg_warm[p64] = 1;
+    return residual_launches(c, s, pb, x, F);
+  }
+  const void* key[10] = {x, F, s->sigma, s->ep, w->vol, c->bufA, c->bufB, c->k0buf,
+                         (const void*)(intptr_t)(p64 + 2), (const void*)(intptr_t)(c->depth_cfg + 16)};
+  for (auto& r : w->rg)
+    if (r.ex && std::equal(key, key + 10, r.key)) {
+      hipError_t e = hipGraphLaunch(r.ex, c->stream);
+      return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
+    }
+  // capture on the private stream (the context stream is pointed at it)
+  if (!w->cap && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess)
+    return fail(FVIM_EHIP, "graph stream");
+  SolverWork::ResGraph& r = w->rg[w->rg_next];
+  w->rg_next = (w->rg_next + 1) % 4;
+  if (r.ex) { hipGraphExecDestroy(r.ex); r.ex = nullptr; }
+  if (r.g) { hipGraphDestroy(r.g); r.g = nullptr; }
+  hipStream_t saved = c->stream;
+  hipError_t e = hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return fail_hip(e, "graph capture");
+  c->stream = w->cap;
+  int rc = residual_launches(c, s, pb, x, F);
+  c->stream = saved;
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(w->cap, &g);
+  if (rc || e != hipSuccess || !g ||
+      hipGraphInstantiate(&r.ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    r.ex = nullptr;
+    w->rg_off = 1;                     // do not try again; evaluate eagerly
+    return residual_launches(c, s, pb, x, F);
+  }
+  r.g = g;
+  std::copy(key, key + 10, r.key);
+  e = hipGraphLaunch(r.ex, c->stream);
+  return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
+}
+
+static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F, double* f) {
+  SolverWork* w = c->sw;
+  int rc = residual_enqueue(c, s, pb, x, F);
+  if (rc) return rc;
   if ((rc = read_scalars(c, S_DOT0, 1))) return rc;
   *f = w->hsc[S_DOT0] * inner_scale(c);
   if (!std::isfinite(*f)) return fail(FVIM_EINVAL, "plasticity residual is not finite");

@@ -143,6 +143,33 @@ def test_anderson_outer_reaches_the_stored_fixed_point():
         assert err < 1e-8, (k, err)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_residual_graphs_equal_eager(precision):
+    """Algorithm 1 on the stored Hertz case with the plasticity residual
+    evaluations replayed from captured HIP graphs gives bitwise the same state
+    and the same iteration and evaluation counts as launching every kernel
+    one by one."""
+    from paper_1811_11558_amd import Context, EPOptions
+    ref = np.load(GOLDEN)
+    g = grid_dict(16, 16, 8, lz=0.25)
+    out = {}
+    for graphs in (1, 0):
+        ctx = Context(g, E, NU, SY, EH, precision=precision)
+        ctx.set_option(ctx.OPT_GRAPHS, graphs)
+        st = ctx.new_state()
+        infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                        EPOptions(tol_outer=1e-10, relax=0.3, tol_plastic=1e-12,
+                                                  tol_contact=1e-14, max_plastic=20000, anderson_m=5))
+        torch.cuda.synchronize()
+        out[graphs] = ({k: st[k].cpu().numpy() for k in ("eps_p", "ep", "sigma", "traction", "u3p")},
+                       [(i["outer_iters"], i["r_evals"]) for i in infos])
+        ctx.close()
+    _say(precision, "counts graphs / eager", out[1][1], out[0][1])
+    assert out[1][1] == out[0][1]
+    for k in out[1][0]:
+        assert np.array_equal(out[1][0][k], out[0][0][k]), k
+
+
 def test_contact_graph_replay_equals_eager():
     """The contact iteration replayed as a captured HIP graph gives bitwise the
     same pressure as launching its kernels one by one (many replays, with
