@@ -181,7 +181,11 @@ __global__ __launch_bounds__(NT) void k_pk_scale(double* __restrict__ p, const d
 
 // One-block finishing steps of the PK iteration: turn partial sums into the
 // scalars the next kernel needs.
-__global__ __launch_bounds__(NT) void k_pk_final(int stage, const double* part, int nb, double* sc) {
+// Final reductions into the device scalars; the slots the host reads after
+// stages 5 and 6 are also written to mirror (mapped host memory), so reading
+// them needs no copy.
+__global__ __launch_bounds__(NT) void k_pk_final(int stage, const double* part, int nb, double* sc,
+                                                double* mirror) {
   if (stage == 0) {            // mean gap on the contact set
     double a = final_sum(part, 0, nb), c = final_sum(part, 1, nb);
     if (threadIdx.x == 0) {
@@ -212,13 +216,17 @@ __global__ __launch_bounds__(NT) void k_pk_final(int stage, const double* part, 
     }
   } else if (stage == 5) {     // convergence measure dA sum |dp| / W
     double d = final_sum(part, 0, nb);
-    if (threadIdx.x == 0) sc[S_ERR] = sc[S_DA] * d / sc[S_W];
+    if (threadIdx.x == 0) {
+      const double err = sc[S_DA] * d / sc[S_W];
+      sc[S_ERR] = err;
+      mirror[S_ERR] = err;
+    }
   } else if (stage == 6) {     // generic: sums of up to three quantities
     double a = final_sum(part, 0, nb), b = final_sum(part, 1, nb), c = final_sum(part, 2, nb);
     if (threadIdx.x == 0) {
-      sc[S_DOT0] = a;
-      sc[S_DOT1] = b;
-      sc[S_DOT2] = c;
+      sc[S_DOT0] = mirror[S_DOT0] = a;
+      sc[S_DOT1] = mirror[S_DOT1] = b;
+      sc[S_DOT2] = mirror[S_DOT2] = c;
     }
   }
 }
@@ -368,6 +376,8 @@ struct SolverWork {
   double* part = nullptr;       // 3 * RB partial sums
   double* sc = nullptr;         // device scalars
   double* hsc = nullptr;        // pinned host copy
+  double* hmap = nullptr;       // mapped host memory written by k_pk_final (host view)
+  double* dmap = nullptr;       //   (device view)
   double* vol = nullptr;        // volume work arrays (allocated on first plasticity use)
   size_t vol_count = 0;
   // one contact iteration captured as a HIP graph, replayed on a private
@@ -382,7 +392,7 @@ struct SolverWork {
   // xprev, fprev, f [ns]; Gram partials and results (device, pinned host)
   double* aa = nullptr;
   double* aa_part = nullptr;
-  double* aa_out = nullptr;
+  double* aa_out = nullptr;     // device view of aa_hout (mapped host memory)
   double* aa_hout = nullptr;
   // captured residual evaluations R(x) -> F (return map, operator, residual
   // and its reduction), one per combination of the pointers and settings they
@@ -409,7 +419,10 @@ static int sw_ensure(fvim_ctx* c) {
             hipMalloc(&w->specB, sizeof(cpx<double>) * nm) == hipSuccess &&
             hipMalloc((void**)&w->part, sizeof(double) * 3 * RB) == hipSuccess &&
             hipMalloc((void**)&w->sc, sizeof(double) * NSCAL) == hipSuccess &&
-            hipHostMalloc((void**)&w->hsc, sizeof(double) * NSCAL, hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc((void**)&w->hsc, sizeof(double) * NSCAL, hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&w->hmap, sizeof(double) * NSCAL,
+                          hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+            hipHostGetDevicePointer((void**)&w->dmap, w->hmap, 0) == hipSuccess;
   c->sw = w;
   if (!ok) return fail(FVIM_ENOMEM, "solver workspace allocation failed");
   return FVIM_OK;
@@ -424,10 +437,10 @@ void solver_release(fvim_ctx* c) {
   if (w->part) hipFree(w->part);
   if (w->sc) hipFree(w->sc);
   if (w->hsc) hipHostFree(w->hsc);
+  if (w->hmap) hipHostFree(w->hmap);
   if (w->vol) hipFree(w->vol);
   if (w->aa) hipFree(w->aa);
   if (w->aa_part) hipFree(w->aa_part);
-  if (w->aa_out) hipFree(w->aa_out);
   if (w->aa_hout) hipHostFree(w->aa_hout);
   for (auto& r : w->rg) {
     if (r.ex) hipGraphExecDestroy(r.ex);
@@ -452,21 +465,21 @@ size_t solver_footprint(const fvim_grid* g, size_t V) {
 }
 
 // Host copy of device scalars [first, first + n) (synchronises the stream).
+// The slots k_pk_final mirrors (S_ERR, S_DOT0..S_DOT2) are taken from the
+// mapped mirror once the stream is idle; others are copied.
 static int read_scalars_on(fvim_ctx* c, hipStream_t st, int first, int n) {
   SolverWork* w = c->sw;
-  hipError_t e = hipMemcpyAsync(w->hsc + first, w->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+  const bool mirrored = (first == S_ERR && n == 1) || (first >= S_DOT0 && first + n <= S_DOT2 + 1);
+  hipError_t e = hipSuccess;
+  if (!mirrored) e = hipMemcpyAsync(w->hsc + first, w->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail_hip(e, "scalar readback");
+  if (mirrored)
+    for (int k = first; k < first + n; ++k) w->hsc[k] = w->hmap[k];
   return FVIM_OK;
 }
 
-static int read_scalars(fvim_ctx* c, int first, int n) {
-  SolverWork* w = c->sw;
-  hipError_t e = hipMemcpyAsync(w->hsc + first, w->sc + first, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return fail_hip(e, "scalar readback");
-  return FVIM_OK;
-}
+static int read_scalars(fvim_ctx* c, int first, int n) { return read_scalars_on(c, c->stream, first, n); }
 
 static int set_scalar(fvim_ctx* c, int slot, double v) {
   SolverWork* w = c->sw;
@@ -518,19 +531,19 @@ static int pk_iteration(fvim_ctx* c, hipStream_t st, const double* h, double* p)
   int rc;
   if ((rc = compliance(c, p, u, st))) return rc;
   hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 1, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 1, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_dir, G, Bk, 0, st, p, g, t, n, w->sc);
   if ((rc = compliance(c, t, r, st))) return rc;
   hipLaunchKernelGGL(k_pk_rmean, G, Bk, 0, st, p, r, n, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 2, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 2, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_tau, G, Bk, 0, st, p, g, r, t, n, w->sc, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 3, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 3, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_update, G, Bk, 0, st, p, pold, g, t, n, w->sc, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 4, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 4, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_scale, G, Bk, 0, st, p, pold, n, w->sc, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 5, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 5, w->part, nb, w->sc, w->dmap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail_hip(e, "contact iteration");
   return FVIM_OK;
@@ -559,7 +572,7 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   if (e != hipSuccess) return fail_hip(e, "scalar upload");
   // initial pressure: warm start renormalised to W, or uniform
   hipLaunchKernelGGL(k_sum_abs, G, Bk, 0, st, p, n, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 6, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 6, w->part, nb, w->sc, w->dmap);
   if ((rc = read_scalars(c, S_DOT0, 2))) return rc;
   const double sp = w->hsc[S_DOT0];
   if (!(sp > 0.0) || !std::isfinite(sp)) {
@@ -619,7 +632,7 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   // final gap and certificate
   if ((rc = compliance(c, p, u, st))) return rc;
   hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
   if (gap) {
     e = hipMemcpyAsync(gap, g, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
@@ -689,7 +702,7 @@ static int residual_launches(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, co
   if (rc) return rc;
   const int nb = nblocks(n6);
   hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, st, F, x, pb.b, pb.wk, w->ns, c->grid.nz, n6, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, st, 6, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, st, 6, w->part, nb, w->sc, w->dmap);
   return FVIM_OK;
 }
 
@@ -755,7 +768,7 @@ static int wdots(fvim_ctx* c, const double* a1, const double* a0, const double* 
   const size_t n6 = 6 * w->V;
   const int nb = nblocks(n6);
   hipLaunchKernelGGL(k_wdots, dim3(nb), dim3(NT), 0, c->stream, a1, a0, b1, b0, w->ns, c->grid.nz, n6, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
   int rc = read_scalars(c, S_DOT0, 3);
   if (rc) return rc;
   const double sc = inner_scale(c);
@@ -891,7 +904,7 @@ static int surf_norms(fvim_ctx* c, const double* a, const double* b, double* dno
   SolverWork* w = c->sw;
   const int nb = nblocks(w->ns);
   hipLaunchKernelGGL(k_sq2, dim3(nb), dim3(NT), 0, c->stream, a, b, w->ns, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
   int rc = read_scalars(c, S_DOT0, 2);
   if (rc) return rc;
   *dnorm = std::sqrt(w->hsc[S_DOT0]);
@@ -905,8 +918,9 @@ static int aa_ensure(fvim_ctx* c) {
   const int K = aa_nsums(AA_MMAX);
   if (hipMalloc((void**)&w->aa, sizeof(double) * w->ns * (2 * AA_MMAX + 3)) != hipSuccess ||
       hipMalloc((void**)&w->aa_part, sizeof(double) * K * RB) != hipSuccess ||
-      hipMalloc((void**)&w->aa_out, sizeof(double) * K) != hipSuccess ||
-      hipHostMalloc((void**)&w->aa_hout, sizeof(double) * K, hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc((void**)&w->aa_hout, sizeof(double) * K, hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&w->aa_out, w->aa_hout, 0) != hipSuccess)
     return fail(FVIM_ENOMEM, "Anderson history allocation failed");
   return FVIM_OK;
 }
@@ -930,8 +944,7 @@ static int aa_gram(fvim_ctx* c, int m, const double* f) {
 #undef FVIM_AA_GRAM
   const int K = aa_nsums(m);
   hipLaunchKernelGGL(k_aa_final, dim3(1), dim3(64), 0, st, w->aa_part, K, nb, w->aa_out);
-  hipError_t e = hipMemcpyAsync(w->aa_hout, w->aa_out, sizeof(double) * K, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipError_t e = hipStreamSynchronize(st);
   return e == hipSuccess ? FVIM_OK : fail_hip(e, "Anderson Gram matrix");
 }
 
