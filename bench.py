@@ -45,11 +45,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-modes", type=int, default=4096,
                     help="modes of the oracle sample for the CPU baseline")
-    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy"],
+    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch"],
                     help="operator: the fused operator (the headline line); serve: Poisson-arrival "
                          "elastoplastic solves of mixed grids through the batching server; solve: the "
                          "32x32x16 paraboloid elastoplastic solve; copy: a plain device copy of known size "
-                         "(reference for hardware counters)")
+                         "(reference for hardware counters); batch: the fused operator on eight small grids of "
+                         "different sizes, one call each vs one batched call")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals per second (0 = all at once)")
@@ -155,6 +156,52 @@ def bench_copy(a):
                       "ms_per_step": ms, "steps": a.steps, "n_gpus": 1}))
 
 
+def bench_batch(a):
+    """The fused operator (float64) on eight grids of different sizes
+    (32^2 x 8 ... 128^2 x 64): one application per context in turn against
+    one batched application that shares the depth-pass launches."""
+    import torch
+    from paper_1811_11558_amd import Context, operator_apply_batch
+    from synth import filtered_eigenstrain, filtered_traction, grid_dict
+    shapes = [(64, 64, 32), (32, 32, 16), (128, 128, 64), (64, 32, 16), (32, 64, 32), (64, 64, 16),
+              (128, 64, 32), (32, 32, 8)]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    ctxs, eps, ts = [], [], []
+    for i, (nx, ny, nz) in enumerate(shapes):
+        g = grid_dict(nx, ny, nz, 1.0, 1.0, 0.25)
+        ctxs.append(Context(g, 1.0, 0.3, stream=stream))
+        eps.append(torch.from_numpy(filtered_eigenstrain(g, seed=i)).to(dev))
+        ts.append(torch.from_numpy(filtered_traction(g, seed=1000 + i)).to(dev))
+    vox = sum(nx * ny * nz for nx, ny, nz in shapes)
+
+    def sequential():
+        for c, e, t in zip(ctxs, eps, ts):
+            c.operator_apply(e, t)
+
+    def batched():
+        operator_apply_batch(ctxs, eps, ts)
+
+    res = {}
+    for name, fn in (("sequential", sequential), ("batched", batched)):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = 1e3 * (time.perf_counter() - t0) / a.steps
+    for c in ctxs:
+        c.close()
+    print(json.dumps({"metric": "batched operator voxel-updates/s", "value": vox / (res["batched"] * 1e-3),
+                      "unit": "voxel-updates/s", "higher_is_better": True, "n_gpus": 1, "steps": a.steps,
+                      "ms_per_batch": res["batched"], "ms_sequential": res["sequential"],
+                      "speedup": res["sequential"] / res["batched"], "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "fused operator on 8 grids: " +
+                                 ", ".join("%dx%dx%d" % s_ for s_ in shapes)}}))
+
+
 def bench_solve(a):
     """Elastoplastic paraboloid solve, 32 x 32 x 16 (R = 0.5 L, lz = 0.25 L,
     E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1), cumulative loads up to
@@ -246,6 +293,8 @@ def main():
         sys.exit(2)
     if a.workload == "copy":
         return bench_copy(a)
+    if a.workload == "batch":
+        return bench_batch(a)
     if a.workload == "solve":
         return bench_solve(a)
     if a.workload == "serve":

@@ -126,6 +126,24 @@ int fvim_operator_apply(fvim_ctx* ctx, const double* eps_p, const double* tracti
                         double* strain, double* stress, double* disp, double* surf_u3);
 
 /*
+ * Batched application (batching of grids of different sizes): the fused
+ * operator of fvim_operator_apply for n contexts at once, ordered on the
+ * stream of ctxs[0].  Each context's in-plane transforms run as before; the
+ * depth pass of up to 8 contexts runs as one launch for their regular modes
+ * and one for their Nyquist modes, a table mapping each block to its grid
+ * (the layout is the default one for the largest nz, so results agree with
+ * separate applications up to the summation order of that layout, bitwise
+ * when the contexts use the same layout).  The arrays hold one device
+ * pointer per context (eps_p[i] [6][nz][ny][nx], ...); an array that is NULL
+ * is not requested for any context, and every requested pointer must be
+ * non-NULL.  All contexts must share the device and the precision.
+ * Asynchronous.  Errors: FVIM_EINVAL for mismatched contexts or arguments.
+ */
+int fvim_operator_apply_batch(fvim_ctx* const* ctxs, int n, const double* const* eps_p,
+                              const double* const* traction, double* const* strain, double* const* stress,
+                              double* const* disp, double* const* surf_u3);
+
+/*
  * J2 return mapping with linear isotropic hardening (Sec. 4.1), backward
  * Euler radial return, pointwise over V = nx*ny*nz voxels:
  *   sigma_tr = sigma_n + C : d_eps;  s = dev sigma_tr;  f = sqrt(3/2)|s| -

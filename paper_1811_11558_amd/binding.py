@@ -116,6 +116,7 @@ def load_library(path=None):
     lib.mindlin_apply.argtypes = [_P, _P, _P, _P, _P, _P]
     lib.boussinesq_apply.argtypes = [_P, _P, _P, _P, _P, _P]
     lib.fvim_operator_apply.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    lib.fvim_operator_apply_batch.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P]
     lib.return_map.argtypes = [_P, _P, _P, _P, _P, _P, _P]
     lib.contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P,
                                   ctypes.POINTER(_ContactInfo)]
@@ -336,6 +337,36 @@ def boussinesq_apply(ctx, traction, **kw):
 
 def operator_apply(ctx, eps_p=None, traction=None, **kw):
     return ctx.operator_apply(eps_p, traction, **kw)
+
+
+def operator_apply_batch(ctxs, eps_p=None, traction=None, want=("strain",)):
+    """The fused operator for several contexts (grids may differ) with the
+    depth pass of up to 8 of them in one launch; ordered on ctxs[0]'s stream.
+    eps_p / traction: lists of tensors (one per context) or None.  Returns a
+    list of output dicts."""
+    n = len(ctxs)
+    if n == 0:
+        raise FvimError(FVIM_EINVAL, "batch: no context")
+    outs, cols = [], {k: [] for k in ("strain", "stress", "disp", "surf_u3")}
+    ins = {"eps": [], "t": []}
+    for i, c in enumerate(ctxs):
+        e = eps_p[i] if eps_p is not None else None
+        t = traction[i] if traction is not None else None
+        ins["eps"].append(_ptr(e, c.tensor_shape, "eps_p"))
+        ins["t"].append(_ptr(t, (3, c.ny, c.nx), "traction"))
+        res, ptrs = c._outputs(want, None, (e if e is not None else t).device)
+        outs.append(res)
+        for k, p in zip(("strain", "stress", "disp", "surf_u3"), ptrs):
+            cols[k].append(p)
+
+    def arr(v, used):
+        return (ctypes.c_void_p * n)(*v) if used else None
+
+    keep = [arr(ins["eps"], eps_p is not None), arr(ins["t"], traction is not None)]
+    keep += [arr(cols[k], k in want) for k in ("strain", "stress", "disp", "surf_u3")]
+    hs = (ctypes.c_void_p * n)(*[c._h.value for c in ctxs])
+    _check(_LIB.fvim_operator_apply_batch(hs, n, *keep))
+    return outs
 
 
 def return_map(ctx, d_eps, sigma_n, ep_n, **kw):

@@ -147,14 +147,34 @@ int tune_depth(fvim_ctx* c, const cpx<T>* in, cpx<T>* out, const DepthParams& pr
   return FVIM_OK;
 }
 
-// u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
+// One operator application on one grid: parameters, buffers, launches.
 template <typename T>
-int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
-                     double* disp, double* surf_u3) {
+struct OpPlan {
+  DepthParams prm{};
+  OutSegments seg{};
+  InSegments iseg{};
+  int np = 0, np_in = 0, wbpp = 0;
+  bool k0x = false;
+  double* wsum = nullptr;
+  double* tsum = nullptr;
+  double* padd = nullptr;
+  cpx<T>* A = nullptr;
+  cpx<T>* B = nullptr;
+  const cpx<T>* twx = nullptr;
+  const cpx<T>* twy = nullptr;
+};
+
+// Depth parameters, output/input plane layout, workspace and the mode table
+// of one application u = M[t] + N[C : eps_p] (any subset of outputs, see
+// fvim.h).  P.np == 0: nothing requested.
+template <typename T>
+int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+            double* disp, double* surf_u3, OpPlan<T>& P) {
   const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
   const int kxh = nx / 2 + 1;
   const size_t nmodes = (size_t)kxh * ny;
-  DepthParams prm{};
+  DepthParams& prm = P.prm;
+  prm = DepthParams{};
   prm.nx = nx;
   prm.ny = ny;
   prm.nz = nz;
@@ -169,26 +189,28 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   prm.has_t = traction != nullptr;
   prm.k0_include = c->k0_policy == FVIM_K0_INCLUDE;
   // in float32 the mean mode is formed in float64 from float64 plane sums
-  const bool k0x = sizeof(T) == 4;
-  prm.k0_external = k0x ? 1 : 0;
+  P.k0x = sizeof(T) == 4;
+  prm.k0_external = P.k0x ? 1 : 0;
   int np = 0;
-  OutSegments seg;
+  OutSegments& seg = P.seg;
   seg.n = 0;
   prm.off_strain = prm.off_stress = prm.off_disp = prm.off_u3 = -1;
   if (strain) { prm.off_strain = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = strain; np += 6 * nz; }
   if (stress) { prm.off_stress = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = stress; np += 6 * nz; }
   if (disp) { prm.off_disp = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = disp; np += 3 * nz; }
   if (surf_u3) { prm.off_u3 = np; seg.first[seg.n] = np; seg.ptr[seg.n++] = surf_u3; np += 1; }
+  P.np = np;
   prm.np_out = np;
   prm.ld_out = mode_stride<T>(np);
   if (np == 0) return FVIM_OK;
   // input planes: the 6 nz eigenstrain planes, then the 3 traction planes,
   // transformed together (one launch per direction)
   const int np_in = (eps_p ? 6 * nz : 0) + (traction ? 3 : 0);
+  P.np_in = np_in;
   prm.np_in = np_in;
   prm.ld_in = mode_stride<T>(np_in);
   prm.off_t = eps_p ? 6 * nz : 0;
-  InSegments iseg;
+  InSegments& iseg = P.iseg;
   iseg.n = 0;
   iseg.first[0] = iseg.first[1] = 0;
   iseg.ptr[0] = iseg.ptr[1] = nullptr;
@@ -200,17 +222,14 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   if (rc) return rc;
   rc = ctx_reserve(c, &c->bufB, &c->bufB_bytes, bytes);
   if (rc) return rc;
-  const int wbpp = x_r2c_blocks_per_plane<T>(nx, ny);
-  double* wsum = nullptr;
-  double* tsum = nullptr;
-  double* padd = nullptr;
-  if (k0x) {
-    const size_t kb = sizeof(double) * ((size_t)(6 * nz + 3) * wbpp + (size_t)np);
+  P.wbpp = x_r2c_blocks_per_plane<T>(nx, ny);
+  if (P.k0x) {
+    const size_t kb = sizeof(double) * ((size_t)(6 * nz + 3) * P.wbpp + (size_t)np);
     rc = ctx_reserve(c, &c->k0buf, &c->k0buf_bytes, kb);
     if (rc) return rc;
-    wsum = (double*)c->k0buf;                      // block sums of every input plane
-    tsum = wsum + (size_t)prm.off_t * wbpp;
-    padd = wsum + (size_t)(6 * nz + 3) * wbpp;
+    P.wsum = (double*)c->k0buf;                    // block sums of every input plane
+    P.tsum = P.wsum + (size_t)prm.off_t * P.wbpp;
+    P.padd = P.wsum + (size_t)(6 * nz + 3) * P.wbpp;
   }
   void*& mt = sizeof(T) == 8 ? c->mt64 : c->mt32;
   if (!mt) {
@@ -222,10 +241,54 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
     if (e0 != hipSuccess) return fail_hip(e0, "mode table");
   }
   prm.mtab = mt;
-  const cpx<T>* twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
-  const cpx<T>* twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
-  cpx<T>* A = (cpx<T>*)c->bufA;
-  cpx<T>* B = (cpx<T>*)c->bufB;
+  P.twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
+  P.twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
+  P.A = (cpx<T>*)c->bufA;
+  P.B = (cpx<T>*)c->bufB;
+  return FVIM_OK;
+}
+
+// Forward transforms of the input planes: real fields -> mode-major B.
+template <typename T>
+int op_forward(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  hipError_t e;
+  tm.begin(FVIM_STAGE_XFWD, st);
+  if ((e = launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum)) != hipSuccess)
+    return fail_hip(e, "x_r2c");
+  tm.end();
+  tm.begin(FVIM_STAGE_YFWD, st);
+  if ((e = launch_y_fwd<T>(P.A, P.B, ny, kxh, P.np_in, P.prm.ld_in, P.twy, st)) != hipSuccess)
+    return fail_hip(e, "y_fwd");
+  tm.end();
+  return FVIM_OK;
+}
+
+// Mean mode (float32 path) and inverse transforms: mode-major A -> outputs.
+template <typename T>
+int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  hipError_t e;
+  if (P.k0x && (e = launch_k0_fields(P.wsum, P.wbpp, P.tsum, P.wbpp, P.padd, P.prm, st)) != hipSuccess)
+    return fail_hip(e, "k0");
+  tm.begin(FVIM_STAGE_YINV, st);
+  if ((e = launch_y_inv<T>(P.A, P.B, ny, kxh, P.np, P.prm.ld_out, P.twy, st)) != hipSuccess)
+    return fail_hip(e, "y_inv");
+  tm.end();
+  tm.begin(FVIM_STAGE_XINV, st);
+  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd)) != hipSuccess)
+    return fail_hip(e, "x_c2r");
+  tm.end();
+  return FVIM_OK;
+}
+
+// u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
+template <typename T>
+int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+                     double* disp, double* surf_u3) {
+  OpPlan<T> P;
+  int rc = op_plan<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P);
+  if (rc || P.np == 0) return rc;
   hipStream_t st = c->stream;
   const bool side = c->use_side != 0;
   if (side && (rc = side_ensure(c))) return rc;
@@ -234,38 +297,74 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   hipStream_t ss = side ? c->side : st;
   hipError_t e;
   StageTimer tm(c);
-  tm.begin(FVIM_STAGE_XFWD, st);
-  if ((e = launch_x_r2c<T>(iseg, A, nx, ny, (size_t)np_in, twx, st, wsum)) != hipSuccess)
-    return fail_hip(e, "x_r2c");
-  tm.end();
-  tm.begin(FVIM_STAGE_YFWD, st);
-  if ((e = launch_y_fwd<T>(A, B, ny, kxh, np_in, prm.ld_in, twy, st)) != hipSuccess) return fail_hip(e, "y_fwd");
-  tm.end();
+  if ((rc = op_forward<T>(c, P, st, tm))) return rc;
   if (c->tune_pending) {
     c->tune_pending = 0;
-    int rc2 = tune_depth<T>(c, B, A, prm);
+    int rc2 = tune_depth<T>(c, P.B, P.A, P.prm);
     if (rc2) return rc2;
   }
   if (ss != st && (e = join(c->ev_spec, st, ss)) != hipSuccess) return fail_hip(e, "fork");
   tm.begin(FVIM_STAGE_DEPTH, st);
-  if ((e = launch_depth<T>(B, A, prm, c->depth_cfg, st, 1)) != hipSuccess) return fail_hip(e, "depth");
+  if ((e = launch_depth<T>(P.B, P.A, P.prm, c->depth_cfg, st, 1)) != hipSuccess) return fail_hip(e, "depth");
   tm.end();
   tm.begin(FVIM_STAGE_DEPTH_NYQ, ss);
-  if ((e = launch_depth<T>(B, A, prm, c->depth_cfg, ss, 2)) != hipSuccess)
+  if ((e = launch_depth<T>(P.B, P.A, P.prm, c->depth_cfg, ss, 2)) != hipSuccess)
     return fail_hip(e, "depth (Nyquist modes)");
   tm.end();
   if (ss != st && (e = join(c->ev_nyq, ss, st)) != hipSuccess) return fail_hip(e, "join");
-  if (k0x) {
-    if ((e = launch_k0_fields(wsum, wbpp, tsum, wbpp, padd, prm, st)) != hipSuccess) return fail_hip(e, "k0");
+  return op_inverse<T>(c, P, st, tm);
+}
+
+// Several contexts (grids may differ) on the stream of the first: every
+// context's forward transforms, one depth launch per part for up to
+// DEPTH_BATCH_MAX contexts at a time, every context's inverse transforms.
+template <typename T>
+int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps, const double* const* tr,
+                           double* const* strain, double* const* stress, double* const* disp,
+                           double* const* surf_u3) {
+  hipStream_t st = cs[0]->stream;
+  std::vector<OpPlan<T>> P(n);
+  std::vector<hipStream_t> saved(n);
+  for (int i = 0; i < n; ++i) saved[i] = cs[i]->stream;
+  auto restore = [&](int r) {
+    for (int i = 0; i < n; ++i) cs[i]->stream = saved[i];
+    return r;
+  };
+  for (int i = 0; i < n; ++i) cs[i]->stream = st;   // one stream orders the whole batch
+  int rc = 0, maxnz = 0;
+  for (int i = 0; i < n && !rc; ++i) {
+    rc = op_plan<T>(cs[i], eps ? eps[i] : nullptr, tr ? tr[i] : nullptr, strain ? strain[i] : nullptr,
+                    stress ? stress[i] : nullptr, disp ? disp[i] : nullptr, surf_u3 ? surf_u3[i] : nullptr, P[i]);
+    if (!rc && P[i].np == 0) rc = fail(FVIM_EINVAL, "batch: every context needs an output");
+    maxnz = std::max(maxnz, cs[i]->grid.nz);
   }
-  tm.begin(FVIM_STAGE_YINV, st);
-  if ((e = launch_y_inv<T>(A, B, ny, kxh, np, prm.ld_out, twy, st)) != hipSuccess) return fail_hip(e, "y_inv");
-  tm.end();
-  tm.begin(FVIM_STAGE_XINV, st);
-  if ((e = launch_x_c2r<T>(B, seg, nx, ny, (size_t)np, 1.0, twx, st, padd)) != hipSuccess)
-    return fail_hip(e, "x_c2r");
-  tm.end();
-  return FVIM_OK;
+  if (rc) return restore(rc);
+  fvim_ctx* c0 = cs[0];
+  if ((rc = ctx_reserve(c0, &c0->dbatch, &c0->dbatch_bytes, sizeof(DepthBatch)))) return restore(rc);
+  StageTimer tm(c0);
+  for (int i = 0; i < n && !rc; ++i) rc = op_forward<T>(cs[i], P[i], st, tm);
+  if (rc) return restore(rc);
+  const int cfg = depth_default_config(maxnz);
+  const int gpb = depth_groups_per_block(cfg);
+  for (int i0 = 0; i0 < n; i0 += DEPTH_BATCH_MAX) {
+    DepthBatch b{};
+    b.n = std::min(DEPTH_BATCH_MAX, n - i0);
+    for (int k = 0; k < b.n; ++k) {
+      const DepthParams& p = P[i0 + k].prm;
+      b.prm[k] = p;
+      depth_derive(b.prm[k]);
+      b.in[k] = P[i0 + k].B;
+      b.out[k] = P[i0 + k].A;
+      b.first_main[k + 1] = b.first_main[k] + (p.kxh * p.ny + gpb - 1) / gpb;
+      b.first_nyq[k + 1] = b.first_nyq[k] + (p.ny + p.kxh - 1 + gpb - 1) / gpb;
+    }
+    tm.begin(FVIM_STAGE_DEPTH, st);
+    hipError_t e = launch_depth_batch<T>(b, (DepthBatch*)c0->dbatch, cfg, st);
+    tm.end();
+    if (e != hipSuccess) return restore(fail_hip(e, "batched depth pass"));
+  }
+  for (int i = 0; i < n && !rc; ++i) rc = op_inverse<T>(cs[i], P[i], st, tm);
+  return restore(rc);
 }
 
 static bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u); }
@@ -339,7 +438,7 @@ void fvim_destroy(fvim_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   if (c->side) hipStreamSynchronize(c->side);
-  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32};
+  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32, c->dbatch};
   for (void* p : ptrs)
     if (p) hipFree(p);
   hipEvent_t evs[] = {c->ev_spec, c->ev_nyq};
@@ -457,6 +556,34 @@ int fvim_operator_apply(fvim_ctx* c, const double* eps_p, const double* traction
                         double* disp, double* surf_u3) {
   if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
   return operator_apply(c, eps_p, traction, strain, stress, disp, surf_u3);
+}
+
+int fvim_operator_apply_batch(fvim_ctx* const* ctxs, int n, const double* const* eps_p,
+                              const double* const* traction, double* const* strain, double* const* stress,
+                              double* const* disp, double* const* surf_u3) {
+  if (!ctxs || n < 1) return fail(FVIM_EINVAL, "batch: need at least one context");
+  if (!eps_p && !traction) return fail(FVIM_EINVAL, "batch: no input");
+  if (!strain && !stress && !disp && !surf_u3) return fail(FVIM_EINVAL, "batch: no output");
+  const fvim_ctx* c0 = ctxs[0];
+  for (int i = 0; i < n; ++i) {
+    const fvim_ctx* c = ctxs[i];
+    if (!c) return fail(FVIM_EINVAL, "batch: NULL context");
+    if (c->device != c0->device || c->precision != c0->precision || c->force_fp64 != c0->force_fp64)
+      return fail(FVIM_EINVAL, "batch: contexts must share the device and the precision");
+    const double* ptrs[] = {eps_p ? eps_p[i] : nullptr, traction ? traction[i] : nullptr};
+    double* outs[] = {strain ? strain[i] : nullptr, stress ? stress[i] : nullptr, disp ? disp[i] : nullptr,
+                      surf_u3 ? surf_u3[i] : nullptr};
+    for (const double* p : ptrs)
+      if (misaligned(p)) return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
+    for (double* p : outs)
+      if (misaligned(p)) return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
+    if ((eps_p && !eps_p[i]) || (traction && !traction[i]) || (strain && !strain[i]) || (stress && !stress[i]) ||
+        (disp && !disp[i]) || (surf_u3 && !surf_u3[i]))
+      return fail(FVIM_EINVAL, "batch: a requested field is NULL for one context");
+  }
+  if (c0->precision == FVIM_FP32_REFINED && !c0->force_fp64)
+    return operator_apply_batch_t<float>(ctxs, n, eps_p, traction, strain, stress, disp, surf_u3);
+  return operator_apply_batch_t<double>(ctxs, n, eps_p, traction, strain, stress, disp, surf_u3);
 }
 
 int return_map(fvim_ctx* c, const double* d_eps, const double* sigma_n, const double* ep_n, double* d_eps_p,

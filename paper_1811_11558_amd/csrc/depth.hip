@@ -140,13 +140,15 @@ __device__ __forceinline__ void put(cpx<T>* __restrict__ dst, cpx<T> v, bool fir
 // one evaluation each.  NYQ = true: only the Nyquist modes, each the average
 // of its 2 or 4 sign replicas (indexed by group: first the kx = nx/2 column,
 // then the ky = ny/2 row without its kx = nx/2 entry).
+// Block `block` of the pass over one grid (prm): GPB = NT / LPM lane groups,
+// one mode each.
 template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
-__global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
-                                             DepthParams prm) {
+__device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                            const DepthParams& prm, int block) {
   constexpr int GPB = NT / LPM;
   const int g = threadIdx.x / LPM;
   const int l = threadIdx.x - g * LPM;
-  const int gid = blockIdx.x * GPB + g;
+  const int gid = block * GPB + g;
   int kx, ky;
   if (NYQ) {
     if (gid >= prm.ny + prm.kxh - 1) return;
@@ -446,6 +448,24 @@ __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, cpx
   }
 }
 
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
+__global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
+                                             DepthParams prm) {
+  depth_modes<T, LPM, P, DISP, WANTX, NYQ>(in, out, prm, blockIdx.x);
+}
+
+// Several grids in one launch: block b belongs to the grid c with
+// first[c] <= b < first[c + 1] (main or Nyquist block counts); the table is
+// in device memory, so its fields are block-uniform loads.
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
+__global__ __launch_bounds__(NT) void k_depth_batch(const DepthBatch* __restrict__ b) {
+  const int* first = NYQ ? b->first_nyq : b->first_main;
+  int c = 0;
+  while (c + 1 < b->n && (int)blockIdx.x >= first[c + 1]) ++c;
+  depth_modes<T, LPM, P, DISP, WANTX, NYQ>(static_cast<const cpx<T>*>(b->in[c]), static_cast<cpx<T>*>(b->out[c]),
+                                           b->prm[c], (int)blockIdx.x - first[c]);
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_mode_table(ModeConst<T>* __restrict__ tab, int nx, int ny, double lx,
                                                   double ly, double h) {
@@ -539,11 +559,7 @@ hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, doubl
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_depth(const cpx<T>* in, cpx<T>* out, const DepthParams& prm, int cfg, hipStream_t st,
-                        int part) {
-  if (!prm.mtab) return hipErrorInvalidValue;
-  DepthParams p = prm;
+void depth_derive(DepthParams& p) {
   const double kap = p.kappa, kp2 = kap + 2.0;
   p.ikp2 = 1.0 / kp2;
   p.kk = (kap + 1.0) / kp2;
@@ -551,6 +567,62 @@ hipError_t launch_depth(const cpx<T>* in, cpx<T>* out, const DepthParams& prm, i
   p.kapkp2 = kap / kp2;
   p.cfac = kp2 / (2.0 * (kap + 1.0));
   p.ik2 = 1.0 / (2.0 * kap + 2.0);
+}
+
+int depth_groups_per_block(int cfg) { return NT / kCfgs[cfg].lpm; }
+
+template <typename T, int LPM, int P, bool DISP, bool WANTX>
+hipError_t launch_batch_two(const DepthBatch* dtab, int nb_main, int nb_nyq, hipStream_t st) {
+  if (nb_main > 0)
+    hipLaunchKernelGGL((k_depth_batch<T, LPM, P, DISP, WANTX, false>), dim3(nb_main), dim3(NT), 0, st, dtab);
+  if (nb_nyq > 0)
+    hipLaunchKernelGGL((k_depth_batch<T, LPM, P, DISP, WANTX, true>), dim3(nb_nyq), dim3(NT), 0, st, dtab);
+  return hipGetLastError();
+}
+
+template <typename T, int LPM, int P>
+hipError_t launch_batch_cfg(const DepthBatch* dtab, bool disp, bool wx, int nb_main, int nb_nyq, hipStream_t st) {
+  if (disp) return wx ? launch_batch_two<T, LPM, P, true, true>(dtab, nb_main, nb_nyq, st)
+                      : launch_batch_two<T, LPM, P, true, false>(dtab, nb_main, nb_nyq, st);
+  return wx ? launch_batch_two<T, LPM, P, false, true>(dtab, nb_main, nb_nyq, st)
+            : launch_batch_two<T, LPM, P, false, false>(dtab, nb_main, nb_nyq, st);
+}
+
+template <typename T>
+hipError_t launch_depth_batch(const DepthBatch& host, DepthBatch* dtab, int cfg, hipStream_t st) {
+  if (host.n < 1 || host.n > DEPTH_BATCH_MAX || cfg < 0 || cfg >= kNCfg) return hipErrorInvalidValue;
+  const DepthParams& p0 = host.prm[0];
+  const bool disp = p0.off_disp >= 0 || p0.off_u3 >= 0;
+  const bool wx = p0.off_stress >= 0;
+  for (int c = 0; c < host.n; ++c) {
+    const DepthParams& p = host.prm[c];
+    if (!p.mtab || p.nz > kCfgs[cfg].lpm * kCfgs[cfg].p || (p.off_disp >= 0 || p.off_u3 >= 0) != disp ||
+        (p.off_stress >= 0) != wx)
+      return hipErrorInvalidValue;
+  }
+  // pageable source: the copy is staged before the call returns
+  hipError_t e = hipMemcpyAsync(dtab, &host, sizeof(DepthBatch), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  const int nm = host.first_main[host.n], nq = host.first_nyq[host.n];
+  switch (cfg) {
+    case 0: return launch_batch_cfg<T, 16, 1>(dtab, disp, wx, nm, nq, st);
+    case 1: return launch_batch_cfg<T, 16, 2>(dtab, disp, wx, nm, nq, st);
+    case 2: return launch_batch_cfg<T, 32, 1>(dtab, disp, wx, nm, nq, st);
+    case 3: return launch_batch_cfg<T, 32, 2>(dtab, disp, wx, nm, nq, st);
+    case 4: return launch_batch_cfg<T, 64, 1>(dtab, disp, wx, nm, nq, st);
+    case 5: return launch_batch_cfg<T, 64, 2>(dtab, disp, wx, nm, nq, st);
+    case 6: return launch_batch_cfg<T, 64, 4>(dtab, disp, wx, nm, nq, st);
+    case 7: return launch_batch_cfg<T, 64, 8>(dtab, disp, wx, nm, nq, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_depth(const cpx<T>* in, cpx<T>* out, const DepthParams& prm, int cfg, hipStream_t st,
+                        int part) {
+  if (!prm.mtab) return hipErrorInvalidValue;
+  DepthParams p = prm;
+  depth_derive(p);
   if (!depth_config_valid(cfg, p.nz)) cfg = depth_default_config(p.nz);
   switch (cfg) {
     case 0: return launch_cfg<T, 16, 1>(in, out, p, st, part);
@@ -569,6 +641,8 @@ template hipError_t launch_depth<double>(const cpx<double>*, cpx<double>*, const
                                          int);
 template hipError_t launch_depth<float>(const cpx<float>*, cpx<float>*, const DepthParams&, int, hipStream_t, int);
 template hipError_t launch_mode_table<double>(ModeConst<double>*, int, int, double, double, double, hipStream_t);
+template hipError_t launch_depth_batch<double>(const DepthBatch&, DepthBatch*, int, hipStream_t);
+template hipError_t launch_depth_batch<float>(const DepthBatch&, DepthBatch*, int, hipStream_t);
 template hipError_t launch_mode_table<float>(ModeConst<float>*, int, int, double, double, double, hipStream_t);
 
 }  // namespace fvim

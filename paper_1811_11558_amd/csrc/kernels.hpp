@@ -81,6 +81,26 @@ struct alignas(16) ModeConst {
   T s, r, G0, G0p, H0, H0p, iq, pad;
 };
 
+// Depth pass over several grids in one launch per part (main, Nyquist): the
+// host table lists each grid's parameters (derived constants filled by
+// depth_derive), input and output spectra, and the prefix counts of blocks
+// of each part (groups per block: depth_groups_per_block(cfg)); dtab is a
+// device copy target.  Every grid must request the same kinds of output and
+// have nz <= the configuration's capacity.
+constexpr int DEPTH_BATCH_MAX = 8;
+struct DepthBatch {
+  int n;
+  int first_main[DEPTH_BATCH_MAX + 1];
+  int first_nyq[DEPTH_BATCH_MAX + 1];
+  DepthParams prm[DEPTH_BATCH_MAX];
+  const void* in[DEPTH_BATCH_MAX];
+  void* out[DEPTH_BATCH_MAX];
+};
+void depth_derive(DepthParams& p);
+int depth_groups_per_block(int cfg);
+template <typename T>
+hipError_t launch_depth_batch(const DepthBatch& host, DepthBatch* dtab, int cfg, hipStream_t st);
+
 template <typename T>
 hipError_t launch_mode_table(ModeConst<T>* tab, int nx, int ny, double lx, double ly, double h, hipStream_t st);
 

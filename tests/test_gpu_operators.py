@@ -194,3 +194,60 @@ def test_every_depth_layout_matches_oracle(nz):
     ctx.operator_apply(e_d, t_d)
     torch.cuda.synchronize()
     assert 0 <= ctx.get_option(ctx.OPT_DEPTH_CONFIG) < 8
+
+
+BATCH = [(16, 16, 9, 1.0, 1.0, 0.3), (32, 16, 16, 1.0, 0.5, 0.25), (64, 64, 33, 1.0, 1.0, 0.25),
+         (8, 32, 5, 0.5, 1.0, 0.2)]
+
+
+def test_batched_operator_uneven_grids():
+    """Four grids of different sizes in one batched application: each result
+    matches the oracle and the context's own application (the batch uses one
+    depth layout for all, so only the order of the depth sums can differ)."""
+    from paper_1811_11558_amd import operator_apply_batch
+    dev = torch.device("cuda")
+    ctxs, eps, ts, refs, own = [], [], [], [], []
+    for (nx, ny, nz, lx, ly, lz) in BATCH:
+        g = grid_dict(nx, ny, nz, lx, ly, lz)
+        e = filtered_eigenstrain(g, seed=nx + 3 * ny + nz, decay=0.3 * lz)
+        t = filtered_traction(g, seed=11 + nz)
+        refs.append(ora.apply(g, E, NU, eps_p=e, traction=t))
+        c = _ctx(g)
+        ctxs.append(c)
+        eps.append(torch.from_numpy(e).to(dev))
+        ts.append(torch.from_numpy(t).to(dev))
+        own.append(c.operator_apply(eps[-1], ts[-1], want=("strain", "surf_u3")))
+    got = operator_apply_batch(ctxs, eps, ts, want=("strain", "surf_u3"))
+    torch.cuda.synchronize()
+    for i, (r, o, gb) in enumerate(zip(refs, own, got)):
+        for k in ("strain", "surf_u3"):
+            e_or = _rel(gb[k].cpu().numpy(), r[k])
+            e_own = _rel(gb[k].cpu().numpy(), o[k].cpu().numpy())
+            _say("batch", BATCH[i][:3], k, e_or, e_own)
+            assert e_or <= TOL and e_own <= 1e-13, (i, k, e_or, e_own)
+    for c in ctxs:
+        c.close()
+
+
+def test_batched_operator_more_than_eight_contexts_and_fp32():
+    """Eleven contexts (two depth launches of at most eight grids each) in
+    float64, and the same grids in the FP32-refined precision against their
+    own float32 applications."""
+    from paper_1811_11558_amd import Context, operator_apply_batch
+    dev = torch.device("cuda")
+    for prec, bound in (("fp64", 1e-13), ("fp32_refined", 1e-6)):
+        ctxs, eps, own = [], [], []
+        for i in range(11):
+            g = grid_dict(8 << (i % 3), 8 << ((i // 3) % 2), 3 + i, 1.0, 1.0, 0.25)
+            e = torch.from_numpy(filtered_eigenstrain(g, seed=100 + i)).to(dev)
+            c = Context(g, E, NU, precision=prec)
+            ctxs.append(c)
+            eps.append(e)
+            own.append(c.operator_apply(e, None, want=("strain",))["strain"])
+        got = operator_apply_batch(ctxs, eps, None, want=("strain",))
+        torch.cuda.synchronize()
+        worst = max(_rel(gb["strain"].cpu().numpy(), o.cpu().numpy()) for gb, o in zip(got, own))
+        _say("batch of 11", prec, worst)
+        assert worst <= bound
+        for c in ctxs:
+            c.close()
