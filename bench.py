@@ -45,17 +45,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-modes", type=int, default=4096,
                     help="modes of the oracle sample for the CPU baseline")
-    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch"],
+    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch", "rough"],
                     help="operator: the fused operator (the headline line); serve: Poisson-arrival "
                          "elastoplastic solves of mixed grids through the batching server; solve: the "
                          "32x32x16 paraboloid elastoplastic solve; copy: a plain device copy of known size "
                          "(reference for hardware counters); batch: the fused operator on eight small grids of "
-                         "different sizes, one call each vs one batched call")
+                         "different sizes, one call each vs one batched call; rough: elastoplastic contact of a "
+                         "self-affine surface on nx x ny x nz (5 load steps)")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals per second (0 = all at once)")
     ap.add_argument("--side-stream", type=int, default=0,
                     help="operator: 1 runs the traction transforms and Nyquist depth launch on a second stream")
+    ap.add_argument("--hurst", type=float, default=0.8, help="rough: Hurst exponent")
+    ap.add_argument("--k-roll", type=int, default=4, help="rough: roll-off wavenumber")
+    ap.add_argument("--k-cut", type=int, default=0, help="rough: cut-off wavenumber (0 = nx / 4)")
+    ap.add_argument("--load", type=float, default=1e-4, help="rough: final total load W (E L^2 units)")
+    ap.add_argument("--compare", action="store_true",
+                    help="rough: solve in float64 and in FP32_REFINED and report the differences")
     ap.add_argument("--anderson", type=int, default=0,
                     help="solve/serve: Anderson depth of the outer fixed point (0 = Algorithm 1 relaxation)")
     return ap.parse_args()
@@ -122,7 +129,7 @@ def cpu_baseline(g, eps, t, nmodes_sample):
         pick = rng.choice(len(allm), size=min(n, len(allm)), replace=False)
         modes = [allm[i] for i in sorted(pick)]
         t0 = time.perf_counter()
-        ora.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes)
+        ora.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes, direct_dft=False)
         times.append(time.perf_counter() - t0)
     per_mode = max((times[1] - times[0]) / (sizes[1] - sizes[0]), 0.0)
     fixed = max(times[0] - per_mode * sizes[0], 0.0)
@@ -200,6 +207,66 @@ def bench_batch(a):
                       "speedup": res["sequential"] / res["batched"], "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "fused operator on 8 grids: " +
                                  ", ".join("%dx%dx%d" % s_ for s_ in shapes)}}))
+
+
+def bench_rough(a):
+    """Elastoplastic contact of a self-affine rough surface (flat PSD below
+    k_roll, power law with Hurst exponent H up to k_cut, rms slope 0.1, seed
+    0) on nx x ny x nz, lz = 0.25 L, E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1,
+    cumulative loads W/5, ..., W; outer tolerance 1e-7, lambda = 0.3.
+    Throughput = voxel-updates of the plasticity residual evaluations / solve
+    time.  With --compare: float64 and FP32_REFINED on the same problem and
+    the relative L2 differences of the final pressure, plastic strain,
+    cumulated plastic strain and contact area."""
+    import torch
+    from paper_1811_11558_amd import Context, EPOptions
+    from synth import grid_dict, rough_surface
+    g = grid_dict(a.nx, a.ny, a.nz, 1.0, 1.0, 0.25)
+    kcut = a.k_cut or a.nx // 4
+    h = torch.from_numpy(rough_surface(a.nx, a.ny, hurst=a.hurst, k_roll=a.k_roll, k_cut=kcut, rms_slope=0.1,
+                                       seed=0)).cuda()
+    Ws = [a.load * (i + 1) / 5 for i in range(5)]
+    opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
+                     max_plastic=20000, max_contact=50000, anderson_m=a.anderson)
+    V = a.nx * a.ny * a.nz
+    runs = {}
+    for prec in (["fp64", "fp32_refined"] if a.compare else [a.precision]):
+        ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=prec)
+        st = ctx.new_state()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = ctx.elastoplastic_solve(h, Ws, st, opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ev = sum(i["r_evals"] for i in infos)
+        runs[prec] = {"time_s": dt, "residual_evals": ev, "voxel_updates_per_s": ev * V / dt,
+                      "outer_iters": [i["outer_iters"] for i in infos], "state": st}
+        print("%s: %.1f s, %d residual evaluations" % (prec, dt, ev), file=sys.stderr, flush=True)
+        ctx.close()
+    out = {"metric": "rough-contact solve voxel-updates/s", "unit": "voxel-updates/s", "higher_is_better": True,
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "rough elastoplastic contact %dx%dx%d" % (a.nx, a.ny, a.nz), "hurst": a.hurst,
+                      "k_roll": a.k_roll, "k_cut": kcut, "rms_slope": 0.1, "W": a.load, "load_steps": 5,
+                      "tol_outer": 1e-7, "anderson": a.anderson}}
+    for prec, r in runs.items():
+        out[prec] = {k: v for k, v in r.items() if k != "state"}
+        p = r["state"]["traction"][2]
+        out[prec]["contact_fraction"] = float((p > 0).double().mean().item())
+    main = runs.get(a.precision, next(iter(runs.values())))
+    out["value"] = main["voxel_updates_per_s"]
+    if a.compare:
+        s64, s32 = runs["fp64"]["state"], runs["fp32_refined"]["state"]
+
+        def rel(x, y):
+            return float(torch.linalg.vector_norm(x - y) / torch.linalg.vector_norm(y))
+        a64 = (s64["traction"][2] > 0).double().sum().item()
+        a32 = (s32["traction"][2] > 0).double().sum().item()
+        out["fp32_vs_fp64"] = {"p": rel(s32["traction"][2], s64["traction"][2]),
+                               "eps_p": rel(s32["eps_p"], s64["eps_p"]), "ep": rel(s32["ep"], s64["ep"]),
+                               "u3p": rel(s32["u3p"], s64["u3p"]),
+                               "contact_area": abs(a32 - a64) / max(a64, 1.0),
+                               "speedup": runs["fp64"]["time_s"] / runs["fp32_refined"]["time_s"]}
+    print(json.dumps(out))
 
 
 def bench_solve(a):
@@ -295,6 +362,8 @@ def main():
         return bench_copy(a)
     if a.workload == "batch":
         return bench_batch(a)
+    if a.workload == "rough":
+        return bench_rough(a)
     if a.workload == "solve":
         return bench_solve(a)
     if a.workload == "serve":

@@ -96,29 +96,49 @@ def _signed(k, n):
     return k - n if k > n // 2 else k
 
 
-def mode_table(nx, ny, lx, ly):
-    """Evaluation list: (ky, kx, q1, q2, weight) for every bin but k = 0.
+def mode_rows(ky, kx, nx, ny, lx, ly):
+    """Evaluations of bin (ky, kx) != (0, 0): (ky, kx, q1, q2, weight), once
+    per sign of a Nyquist component of an even grid (weights 1/2 or 1/4)."""
+    k1, k2 = _signed(kx, nx), _signed(ky, ny)
+    s1 = (1, -1) if (nx % 2 == 0 and kx == nx // 2) else (1,)
+    s2 = (1, -1) if (ny % 2 == 0 and ky == ny // 2) else (1,)
+    wgt = 1.0 / (len(s1) * len(s2))
+    return [(ky, kx, 2 * np.pi * a * k1 / lx, 2 * np.pi * b * k2 / ly, wgt) for a in s1 for b in s2]
 
-    Nyquist bins of even grids appear once per sign of the Nyquist
-    component(s), with weights 1/2 or 1/4.
-    """
+
+def mode_table(nx, ny, lx, ly):
+    """Evaluation list: mode_rows of every bin but k = 0."""
     rows = []
     for ky in range(ny):
         for kx in range(nx):
             if kx == 0 and ky == 0:
                 continue
-            k1, k2 = _signed(kx, nx), _signed(ky, ny)
-            s1 = (1, -1) if (nx % 2 == 0 and kx == nx // 2) else (1,)
-            s2 = (1, -1) if (ny % 2 == 0 and ky == ny // 2) else (1,)
-            wgt = 1.0 / (len(s1) * len(s2))
-            for a in s1:
-                for b in s2:
-                    rows.append((ky, kx, 2 * np.pi * a * k1 / lx, 2 * np.pi * b * k2 / ly, wgt))
+            rows.extend(mode_rows(ky, kx, nx, ny, lx, ly))
     return rows
 
 
+def sampled_dft(f, modes):
+    """DFT coefficients (1/(nx ny)) sum_x f(x) exp(-2 pi i (kx x / nx +
+    ky y / ny)) over the last two axes of the real array f, at the (ky, kx)
+    bins of modes (eqn dft written out; the phases are reduced exactly, as
+    integers modulo n, before the trigonometric functions).  Returns shape
+    f.shape[:-2] + (len(modes),)."""
+    ny, nx = f.shape[-2:]
+    ky = np.array([m[0] for m in modes], dtype=np.int64)
+    kx = np.array([m[1] for m in modes], dtype=np.int64)
+    ax = 2 * np.pi * ((kx[:, None] * np.arange(nx)[None, :]) % nx) / nx     # (M, nx)
+    ay = 2 * np.pi * ((ky[:, None] * np.arange(ny)[None, :]) % ny) / ny     # (M, ny)
+    F = np.ascontiguousarray(f, dtype=float).reshape(-1, nx)                # (P ny, nx)
+    xr = (F @ np.cos(ax).T).reshape(-1, ny, len(modes))                     # sum_x f cos
+    xi = -(F @ np.sin(ax).T).reshape(-1, ny, len(modes))                    # -sum_x f sin
+    cy, sy = np.cos(ay).T, np.sin(ay).T                                     # (ny, M)
+    re = np.einsum('pym,ym->pm', xr, cy) + np.einsum('pym,ym->pm', xi, sy)
+    im = np.einsum('pym,ym->pm', xi, cy) - np.einsum('pym,ym->pm', xr, sy)
+    return ((re + 1j * im) / (nx * ny)).reshape(f.shape[:-2] + (len(modes),))
+
+
 def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
-          chunk=256, modes=None):
+          chunk=256, modes=None, direct_dft=True):
     """Strain, stress, displacement and surface u3 of u = M[t] + N[C:eps_p].
 
     grid: dict nx, ny, nz, lx, ly, lz.  eps_p: (6, nz, ny, nx) stored
@@ -127,8 +147,12 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
     C : eps - w, disp (3, nz, ny, nx), surf_u3 (ny, nx).  With ``modes`` (a
     list of (ky, kx) bins) only those bins are computed and the spectral
     coefficients are returned instead (keys strain_hat, stress_hat,
-    disp_hat, each (len(modes), nz, ...)).
+    disp_hat, each (len(modes), nz, ...)); their input coefficients come
+    from sampled_dft, or with direct_dft=False from the full FFT of every
+    plane (the full-field path restricted to those bins).
     """
+    if modes is not None and direct_dft:
+        return apply_modes(grid, E, nu, eps_p, traction, modes, k0_policy)
     nx, ny, nz = grid['nx'], grid['ny'], grid['nz']
     lx, ly, lz = grid['lx'], grid['ly'], grid['lz']
     lam, mu = elastic.lame(E, nu)
@@ -143,10 +167,10 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
     t_hat = np.fft.fft2(t, axes=(-2, -1)) / (nx * ny)        # (3, ny, nx)
     W = elastic.to_full(np.moveaxis(w_hat, 0, -1))           # (nz, ny, nx, 3, 3)
 
-    rows = mode_table(nx, ny, lx, ly)
-    if modes is not None:
-        want = set(modes)
-        rows = [r for r in rows if (r[0], r[1]) in want]
+    if modes is None:
+        rows = mode_table(nx, ny, lx, ly)
+    else:
+        rows = [r for (ky, kx) in modes if (ky, kx) != (0, 0) for r in mode_rows(ky, kx, nx, ny, lx, ly)]
     grad = np.zeros((ny, nx, nz, 3, 3), dtype=complex)
     disp = np.zeros((ny, nx, nz, 3), dtype=complex)
     for s in range(0, len(rows), chunk):
@@ -163,15 +187,7 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
         np.add.at(disp, (ky, kx), wg[:, None, None] * u)
 
     # k = 0: laterally uniform, exact
-    if modes is None or (0, 0) in set(modes):
-        t0 = t_hat[:, 0, 0] if k0_policy == "include" else np.zeros(3, dtype=complex)
-        w0 = W[:, 0, 0]                                          # (nz, 3, 3)
-        g0 = np.zeros((nz, 3, 3), dtype=complex)
-        # strains through grad u: d u_a/d x3 = 2 eps_a3 for a = 1, 2
-        g0[:, 0, 2] = (w0[:, 0, 2] - t0[0]) / mu
-        g0[:, 1, 2] = (w0[:, 1, 2] - t0[1]) / mu
-        g0[:, 2, 2] = (w0[:, 2, 2] - t0[2]) / (lam + 2.0 * mu)
-        grad[0, 0] = g0
+    grad[0, 0] = k0_gradient(W[:, 0, 0], t_hat[:, 0, 0], k0_policy, lam, mu)
 
     eps = sym_grad(grad)                                         # (ny, nx, nz, 3, 3)
     sig = hooke_full(eps, lam, mu) - np.moveaxis(W, 0, 2)
@@ -190,6 +206,57 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
     out = {'strain': back(eps_v), 'stress': back(sig_v), 'disp': back(disp)}
     out['surf_u3'] = out['disp'][2, 0].copy()
     return out
+
+
+def k0_gradient(w0, t0, k0_policy, lam, mu):
+    """Displacement gradient of the laterally uniform mode (exact): the
+    stress vector on horizontal planes equals -t everywhere and there is no
+    in-plane strain.  w0: (nz, 3, 3) mean eigenstress, t0: (3,) mean traction."""
+    if k0_policy != "include":
+        t0 = np.zeros(3, dtype=complex)
+    g0 = np.zeros(w0.shape, dtype=complex)
+    # strains through grad u: d u_a/d x3 = 2 eps_a3 for a = 1, 2
+    g0[:, 0, 2] = (w0[:, 0, 2] - t0[0]) / mu
+    g0[:, 1, 2] = (w0[:, 1, 2] - t0[1]) / mu
+    g0[:, 2, 2] = (w0[:, 2, 2] - t0[2]) / (lam + 2.0 * mu)
+    return g0
+
+
+def apply_modes(grid, E, nu, eps_p, traction, modes, k0_policy="include"):
+    """apply() restricted to the (ky, kx) bins of modes: the spectral
+    coefficients strain_hat, stress_hat (len(modes), nz, 6) and disp_hat
+    (len(modes), nz, 3), with the input coefficients taken by sampled_dft
+    (no full-size arrays)."""
+    nx, ny, nz = grid['nx'], grid['ny'], grid['nz']
+    lx, ly, lz = grid['lx'], grid['ly'], grid['lz']
+    lam, mu = elastic.lame(E, nu)
+    z = depth_nodes(nz, lz)
+    M = len(modes)
+    if eps_p is None:
+        w_hat = np.zeros((6, nz, M), dtype=complex)
+    else:
+        # C : eps_p commutes with the DFT (pointwise, linear)
+        w_hat = elastic.hooke(sampled_dft(np.asarray(eps_p, dtype=float), modes), E, nu)
+    t_hat = np.zeros((3, M), dtype=complex) if traction is None else sampled_dft(traction, modes)
+    W = elastic.to_full(np.moveaxis(w_hat, 0, -1))             # (nz, M, 3, 3)
+    grad = np.zeros((M, nz, 3, 3), dtype=complex)
+    disp = np.zeros((M, nz, 3), dtype=complex)
+    for i, (ky, kx) in enumerate(modes):
+        if ky == 0 and kx == 0:
+            grad[i] = k0_gradient(W[:, i], t_hat[:, i], k0_policy, lam, mu)
+            continue
+        rows = mode_rows(ky, kx, nx, ny, lx, ly)
+        q1 = np.array([r[2] for r in rows])
+        q2 = np.array([r[3] for r in rows])
+        wg = np.array([r[4] for r in rows])
+        wm = np.repeat(W[None, :, i], len(rows), axis=0)        # (R, nz, 3, 3)
+        tm = np.repeat(t_hat[None, :, i], len(rows), axis=0)    # (R, 3)
+        g, u = mode_response(q1, q2, wm, tm, z, E, nu)
+        grad[i] = np.einsum('r,rzab->zab', wg, g)
+        disp[i] = np.einsum('r,rza->za', wg, u)
+    eps = sym_grad(grad)                                         # (M, nz, 3, 3)
+    sig = hooke_full(eps, lam, mu) - np.moveaxis(W, 0, 1)
+    return {'strain_hat': elastic.to_voigt(eps), 'stress_hat': elastic.to_voigt(sig), 'disp_hat': disp}
 
 
 def mindlin_apply(grid, E, nu, eps_p, **kw):

@@ -37,14 +37,23 @@ def _filter_planes(noise, power):
     return np.real(np.fft.ifft2(spec, axes=(-2, -1)))
 
 
-def filtered_eigenstrain(grid, seed=0, decay=0.1, max_abs=1e-3, power=2.0):
-    """(6, nz, ny, nx) float64 plastic strain field."""
+def filtered_eigenstrain(grid, seed=0, decay=0.1, max_abs=1e-3, power=2.0, layers=None):
+    """(6, nz, ny, nx) float64 plastic strain field.  layers: optional list
+    of depth indices that receive the filtered field (others stay zero), for
+    inputs of full-size grids that are cheap to generate."""
     nx, ny, nz, lz = grid["nx"], grid["ny"], grid["nz"], grid["lz"]
     rng = np.random.default_rng(seed)
-    noise = rng.standard_normal((6, nz, ny, nx))
-    f = _filter_planes(noise, power)
     z = np.linspace(0.0, lz, nz)
-    f = f * np.exp(-z / decay)[None, :, None, None]
+    if layers is None:
+        noise = rng.standard_normal((6, nz, ny, nx))
+        f = _filter_planes(noise, power)
+        f = f * np.exp(-z / decay)[None, :, None, None]
+    else:
+        layers = list(layers)
+        part = _filter_planes(rng.standard_normal((6, len(layers), ny, nx)), power)
+        part = part * np.exp(-z[layers] / decay)[None, :, None, None]
+        f = np.zeros((6, nz, ny, nx))
+        f[:, layers] = part
     m = np.max(np.abs(f))
     return np.ascontiguousarray(f * (max_abs / m if m > 0 else 1.0))
 

@@ -251,3 +251,51 @@ def test_batched_operator_more_than_eight_contexts_and_fp32():
         assert worst <= bound
         for c in ctxs:
             c.close()
+
+
+def _sampled_dft_gpu(f, modes):
+    """Fourier coefficients (1/(nx ny)) sum_x f(x) exp(-2 pi i (kx x/nx +
+    ky y/ny)) of a real device tensor (..., ny, nx) at the (ky, kx) bins,
+    evaluated on the device by matrix products (test-side measurement)."""
+    ny, nx = f.shape[-2:]
+    dev = f.device
+    kx = torch.tensor([m[1] for m in modes], dtype=torch.int64, device=dev)
+    ky = torch.tensor([m[0] for m in modes], dtype=torch.int64, device=dev)
+    ax = (2 * np.pi / nx) * ((kx[:, None] * torch.arange(nx, device=dev)[None, :]) % nx).double()
+    ay = (2 * np.pi / ny) * ((ky[:, None] * torch.arange(ny, device=dev)[None, :]) % ny).double()
+    F = f.reshape(-1, nx)
+    xr = (F @ torch.cos(ax).T).reshape(-1, ny, len(modes))
+    xi = -(F @ torch.sin(ax).T).reshape(-1, ny, len(modes))
+    cy, sy = torch.cos(ay).T, torch.sin(ay).T
+    re = (xr * cy).sum(1) + (xi * sy).sum(1)
+    im = (xi * cy).sum(1) - (xr * sy).sum(1)
+    out = torch.complex(re, im) / (nx * ny)
+    return out.reshape(tuple(f.shape[:-2]) + (len(modes),)).cpu().numpy()
+
+
+@pytest.mark.parametrize("nx,ny,nz,prec,bound", [(1024, 1024, 64, "fp64", TOL),
+                                                 (512, 512, 128, "fp32_refined", 2e-6)])
+def test_full_size_sampled_modes(nx, ny, nz, prec, bound):
+    """The rough-contact grid 1024^2 x 64 in float64 and the mixed-precision
+    grid 512^2 x 128 in FP32_REFINED, at the launch configuration of the
+    benchmark: the strain's Fourier coefficients on sampled bins (k = 0,
+    Nyquist lines and corner, edges, random) against the oracle's response on
+    those bins.  Eigenstrain in four layers (the others zero) plus traction."""
+    from paper_1811_11558_amd import Context
+    g = grid_dict(nx, ny, nz, 1.0, 1.0, 0.25)
+    eps = filtered_eigenstrain(g, seed=7, layers=[0, 1, nz // 2, nz - 1])
+    t = filtered_traction(g, seed=1001)
+    rng = np.random.default_rng(2)
+    modes = [(0, 0), (0, 1), (1, 0), (0, nx // 2), (ny // 2, 0), (ny // 2, nx // 2), (ny - 1, 1),
+             (3, nx // 2), (ny // 2, 77)]
+    modes += [(int(rng.integers(0, ny)), int(rng.integers(0, nx))) for _ in range(15)]
+    ref = ora.apply(g, E, NU, eps_p=eps, traction=t, modes=modes)["strain_hat"]     # (M, nz, 6)
+    ctx = Context(g, E, NU, precision=prec)
+    _say("case", nx, ny, nz, prec)
+    out = ctx.operator_apply(torch.from_numpy(eps).cuda(), torch.from_numpy(t).cuda(), want=("strain",))
+    torch.cuda.synchronize()
+    got = np.transpose(_sampled_dft_gpu(out["strain"], modes), (2, 1, 0))          # (M, nz, 6)
+    err = _rel(got, ref)
+    _say("full-size sampled-mode rel err", nx, ny, nz, prec, err)
+    assert err <= bound, err
+    ctx.close()

@@ -11,7 +11,7 @@ import mpmath as mp
 
 from oracle import depth, elastic, operators
 from ode_reference import solve_mode
-from synth import grid_dict
+from synth import filtered_eigenstrain, filtered_traction, grid_dict
 
 E, NU = 1.0, 0.3
 LAM, MU = elastic.lame(E, NU)
@@ -319,3 +319,29 @@ def test_depth_moments_against_quadrature(a):
         for n in range(3):
             ref = float(mp.quad(lambda t: t ** n * mp.exp(a * t), [-1, 0, 1]))
             assert abs(m[n][0] - ref) <= 4e-15 * max(1.0, abs(ref))
+
+
+def test_sampled_dft_matches_fft():
+    """sampled_dft is the DFT of eqn dft at the requested bins: equal to
+    numpy's FFT coefficients (scaled by 1/(nx ny)) on random fields."""
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((2, 3, 8, 16))
+    modes = [(0, 0), (1, 0), (0, 1), (4, 8), (7, 15), (3, 5), (4, 3)]
+    got = operators.sampled_dft(f, modes)
+    ref = np.fft.fft2(f, axes=(-2, -1)) / (8 * 16)
+    want = np.stack([ref[..., ky, kx] for (ky, kx) in modes], axis=-1)
+    assert np.max(np.abs(got - want)) < 1e-14
+
+
+def test_sampled_path_matches_full_path():
+    """apply(modes=...) without full-size arrays gives the full path's
+    spectral coefficients on the same bins (k = 0, Nyquist lines and the
+    Nyquist corner included)."""
+    g = grid_dict(8, 16, 5, 1.0, 2.0, 0.3)
+    eps = filtered_eigenstrain(g, seed=3, decay=0.2)
+    t = filtered_traction(g, seed=4)
+    modes = [(0, 0), (0, 4), (8, 0), (8, 4), (3, 1), (15, 2), (8, 3), (1, 4)]
+    a = operators.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes)
+    b = operators.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes, direct_dft=False)
+    for k in ("strain_hat", "stress_hat", "disp_hat"):
+        assert np.max(np.abs(a[k] - b[k])) <= 1e-13 * np.max(np.abs(b[k])), k
