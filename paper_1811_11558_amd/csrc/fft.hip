@@ -29,10 +29,15 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int idx) {
   return w;
 }
 
-// Complex elements of one block's LDS tile (32 KiB either precision), so
-// several blocks share a CU and keep loads in flight while others compute.
+// Complex elements of one block's LDS tile in the row kernels, chosen per
+// kernel and precision by measurement on 256^2 x 64: a smaller tile lets
+// more blocks share a CU (the forward transform gains: 16 KiB), a larger one
+// gives the inverse transform's strided reads longer runs (32 KiB in
+// float64; 16 KiB in float32).
 template <typename T>
-constexpr int tile_elems() { return sizeof(T) == 8 ? 2048 : 4096; }
+constexpr int r2c_tile_elems() { return sizeof(T) == 8 ? 1024 : 2048; }
+template <typename T>
+constexpr int c2r_tile_elems() { return 2048; }
 // Columns (planes) per block of the column (y) kernels.  The mode-major side
 // S[kx][ky][p] is touched in runs of B consecutive planes, so B is the 32 KiB
 // tile's share unless that makes runs shorter than 64 bytes (ny >= 1024 in
@@ -143,7 +148,7 @@ template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
                                              const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
   constexpr int N = 1 << LOGN;
-  constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
+  constexpr int SEQ = (r2c_tile_elems<T>() / N) > 1 ? r2c_tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
   __shared__ cpx<T> buf[SEQ * ld];
@@ -294,7 +299,7 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
                                              double scale, const cpx<T>* __restrict__ tw,
                                              const double* __restrict__ padd) {
   constexpr int N = 1 << LOGN;
-  constexpr int SEQ = (tile_elems<T>() / N) > 1 ? tile_elems<T>() / N : 1;
+  constexpr int SEQ = (c2r_tile_elems<T>() / N) > 1 ? c2r_tile_elems<T>() / N : 1;
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
   constexpr int nyq = N / 2;
@@ -348,8 +353,8 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
 }
 
 template <typename T>
-int rows_per_block(int nx, int ny) {
-  int seq = tile_elems<T>() / nx;
+int rows_per_block(int tile, int nx, int ny) {
+  int seq = tile / nx;
   if (seq < 1) seq = 1;
   int r = 2 * seq;
   if (r > ny) r = ny;
@@ -383,14 +388,14 @@ int ilog2(int n) { return 31 - __builtin_clz((unsigned)n); }
 
 template <typename T>
 int x_r2c_blocks_per_plane(int nx, int ny) {
-  return ny / rows_per_block<T>(nx, ny);
+  return ny / rows_per_block<T>(r2c_tile_elems<T>(), nx, ny);
 }
 
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum) {
   if (seg.n < 1 || seg.n > 2 || seg.first[0] != 0) return hipErrorInvalidValue;
-  int R = rows_per_block<T>(nx, ny);
+  int R = rows_per_block<T>(r2c_tile_elems<T>(), nx, ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
 #define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
@@ -435,7 +440,7 @@ hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd) {
-  int R = rows_per_block<T>(nx, ny);
+  int R = rows_per_block<T>(c2r_tile_elems<T>(), nx, ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
 #define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
