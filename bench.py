@@ -65,6 +65,10 @@ def parse():
                     help="rough: solve in float64 and in FP32_REFINED and report the differences")
     ap.add_argument("--anderson", type=int, default=0,
                     help="solve/serve: Anderson depth of the outer fixed point (0 = Algorithm 1 relaxation)")
+    ap.add_argument("--warm", type=int, default=0,
+                    help="solve/serve/rough: warm-start each outer pass's plasticity solve from the previous one")
+    ap.add_argument("--inner-rel", type=float, default=0.0,
+                    help="solve/serve/rough: inexact plasticity solves to inner_rel x the outer error (0 = off)")
     return ap.parse_args()
 
 
@@ -227,7 +231,8 @@ def bench_rough(a):
                                        seed=0)).cuda()
     Ws = [a.load * (i + 1) / 5 for i in range(5)]
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
-                     max_plastic=20000, max_contact=50000, anderson_m=a.anderson)
+                     max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
+                     inner_rel=a.inner_rel)
     V = a.nx * a.ny * a.nz
     runs = {}
     for prec in (["fp64", "fp32_refined"] if a.compare else [a.precision]):
@@ -247,7 +252,8 @@ def bench_rough(a):
            "n_gpus": 1, "data": "synthetic",
            "config": {"workload": "rough elastoplastic contact %dx%dx%d" % (a.nx, a.ny, a.nz), "hurst": a.hurst,
                       "k_roll": a.k_roll, "k_cut": kcut, "rms_slope": 0.1, "W": a.load, "load_steps": 5,
-                      "tol_outer": 1e-7, "anderson": a.anderson}}
+                      "tol_outer": 1e-7, "anderson": a.anderson, "warm_start": a.warm,
+                      "inner_rel": a.inner_rel}}
     for prec, r in runs.items():
         out[prec] = {k: v for k, v in r.items() if k != "state"}
         p = r["state"]["traction"][2]
@@ -280,7 +286,7 @@ def bench_solve(a):
     h = torch.from_numpy(paraboloid(g, R=0.5)).cuda()
     Ws = [0.002 * (i + 1) for i in range(10)]
     opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, max_outer=2000,
-                     max_plastic=20000, anderson_m=a.anderson)
+                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel)
     times, infos = [], None
     for _ in range(max(1, a.steps)):
         ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=a.precision)
@@ -295,7 +301,7 @@ def bench_solve(a):
     print(json.dumps({"metric": "elastoplastic solve time", "value": float(np.median(times)), "unit": "s",
                       "higher_is_better": False, "n_gpus": 1, "steps": len(times),
                       "config": {"workload": "paraboloid 32x32x16, W=0.02 in 10 steps", "precision": a.precision,
-                                 "anderson": a.anderson},
+                                 "anderson": a.anderson, "warm_start": a.warm, "inner_rel": a.inner_rel},
                       "outer_iters": [i["outer_iters"] for i in infos], "residual_evals": ev,
                       "voxel_updates_per_s": ev * 32 * 32 * 16 / float(np.median(times))}))
 
@@ -315,7 +321,7 @@ def bench_serve(a):
                           seed=r["seed"])
         prepared.append((r, g, h))
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
-                     max_plastic=20000, anderson_m=a.anderson)
+                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel)
     srv = Server(hbm_budget_bytes=200 << 30, max_slots=a.slots)
     t0 = time.perf_counter()
     ids = []
@@ -349,7 +355,8 @@ def bench_serve(a):
                       "run_s_median_by_grid": {k: float(np.median(v)) for k, v in sorted(by_grid.items())},
                       "failures": [d for d in detail if d["status"] != 0],
                       "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": a.slots,
-                                 "rate_per_s": a.rate, "precision": "fp32_refined", "anderson": a.anderson}}))
+                                 "rate_per_s": a.rate, "precision": "fp32_refined", "anderson": a.anderson,
+                                 "warm_start": a.warm, "inner_rel": a.inner_rel}}))
 
 
 def main():

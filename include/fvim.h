@@ -203,6 +203,15 @@ typedef struct {
                        /* of the same outer fixed point with that history  */
                        /* depth and damping relax (Walker & Ni 2011); the  */
                        /* stopping test is unchanged; ignored if literal   */
+  int warm_start;      /* 1: outer passes after a step's first start the    */
+                       /* plasticity iteration from the previous pass's     */
+                       /* solution plus the change of M[dT] (its plastic    */
+                       /* part kept); 0: from the elastic trial M[dT]       */
+  double inner_rel;    /* > 0: inexact plasticity solves to the relative    */
+                       /* tolerance max(tol_plastic, inner_rel * the        */
+                       /* previous pass's outer error) while that error is  */
+                       /* at least tol_outer; a step is accepted only after */
+                       /* a pass solved to tol_plastic; 0: always tol_plastic*/
 } fvim_ep_opts;
 
 typedef struct {

@@ -860,13 +860,19 @@ static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, 
 // FP32_REFINED mode the iteration first runs on the float32 operator down to
 // a relative residual of 3e-6 (about its rounding floor) and is then
 // continued on the float64 operator to the requested tolerance; the
-// right-hand side grad_s M[dT] is always formed in float64.
-static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb,
-                      int* iters, int* evals, double* res) {
+// right-hand side grad_s M[dT] is always formed in float64.  The iteration
+// starts from the elastic trial x = M[dT], or, with warm set, from
+// x_prev - M[dT_prev] + M[dT], where x_prev and M[dT_prev] are what pb.x and
+// pb.b hold from the previous call: the plastic part of the previous solution
+// is kept and only the elastic part follows the new traction.  The residual
+// target is tol_rel |M[dT]|.
+static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const fvim_ep_opts* o, double tol_rel,
+                      bool warm, PlastBufs& pb, int* iters, int* evals, double* res) {
   SolverWork* w = c->sw;
   const size_t n6 = 6 * w->V;
   hipStream_t st = c->stream;
   int rc;
+  if (warm) axpy(c, pb.x, pb.x, -1.0, pb.b, n6);
   {
     Fp64Scope f64(c, 1);
     rc = operator_apply(c, nullptr, dT, pb.b, nullptr, nullptr, nullptr);
@@ -875,18 +881,23 @@ static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const 
   double d3[3];
   if ((rc = wdots(c, pb.b, nullptr, pb.b, nullptr, d3))) return rc;
   const double bn = std::max(std::sqrt(d3[0]), 1e-300);
-  const double tol_abs = o->tol_plastic * bn;
-  hipError_t e = hipMemcpyAsync(pb.x, pb.b, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+  const double tol_abs = tol_rel * bn;
+  hipError_t e = hipSuccess;
+  if (warm) axpy(c, pb.x, pb.x, 1.0, pb.b, n6);
+  else e = hipMemcpyAsync(pb.x, pb.b, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return fail_hip(e, "copy");
   *iters = 0;
   *evals = 0;
   double f = 0.0;
   const bool mixed = c->precision == FVIM_FP32_REFINED;
   const double tol32 = 3e-6 * bn;
-  if (mixed && tol32 > tol_abs) {
-    if ((rc = fixed_point(c, s, o, pb, tol32, o->max_plastic, iters, evals, &f))) return rc;
+  // an inexact solve (target above tol_plastic) at or above the float32
+  // floor stays in float32; every other solve ends on the float64 operator
+  const bool only32 = mixed && tol_rel > o->tol_plastic && tol_abs >= tol32;
+  if (mixed && (tol32 > tol_abs || only32)) {
+    if ((rc = fixed_point(c, s, o, pb, std::max(tol32, tol_abs), o->max_plastic, iters, evals, &f))) return rc;
   }
-  {
+  if (!only32) {
     Fp64Scope f64(c, mixed ? 1 : c->force_fp64);
     if ((rc = fixed_point(c, s, o, pb, tol_abs, o->max_plastic, iters, evals, &f))) return rc;
   }
@@ -1005,7 +1016,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
   if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
   if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1 || o->anderson_m < 0 ||
-      o->anderson_m > AA_MMAX)
+      o->anderson_m > AA_MMAX || !(o->inner_rel >= 0))
     return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
   int rc = sw_ensure(c);
   if (rc) return rc;
@@ -1055,7 +1066,8 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     // warm start of the pressure: the previous step's normal traction
     if (e == hipSuccess) e = hipMemcpyAsync(pcur, s->traction + 2 * n, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return cleanup(fail_hip(e, "step setup"));
-    double err = INFINITY;
+    double err = INFINITY, err_prev = 1.0;
+    bool conv = false;
     int k;
     int aa_count = 0, aa_head = 0;
     for (k = 1; k <= o->max_outer; ++k) {
@@ -1064,9 +1076,14 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       if (rc) return cleanup(rc);
       inf.contact_iters += ci.iters;
       axpy(c, dT, T, -1.0, s->traction, 3 * n);           // dT = T - T_n
+      // inexact inner solves while the outer error is large; a pass that
+      // may end the step is always solved to tol_plastic
+      double tol_rel = o->tol_plastic;
+      if (o->inner_rel > 0 && !(err_prev < o->tol_outer)) tol_rel = std::max(tol_rel, o->inner_rel * err_prev);
+      const bool exact = tol_rel == o->tol_plastic;
       int it, ne;
       double res;
-      rc = plasticity(c, dT, s, o, pb, &it, &ne, &res);
+      rc = plasticity(c, dT, s, o, tol_rel, o->warm_start && k > 1, pb, &it, &ne, &res);
       if (rc) return cleanup(rc);
       inf.plastic_iters += it;
       inf.r_evals += ne;
@@ -1079,6 +1096,8 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       double an;
       if ((rc = surf_norms(c, dU, dUp, &dn, &an))) return cleanup(rc);
       err = dn / hn;
+      err_prev = err;
+      conv = err < o->tol_outer && exact;
       inf.outer_err = err;
       inf.outer_iters = k;
       if (aam > 0) {
@@ -1093,7 +1112,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
         e = hipMemcpyAsync(xprev, dUp, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(fprev, fres, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
-        if (err < o->tol_outer) break;
+        if (conv) break;
         AACoef co = {};
         int me = aa_count;
         if (me > 0) {
@@ -1115,10 +1134,10 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
         if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
       }
       axpy(c, H, H0, -1.0, H, n);                         // H = H0 - relaxed
-      if (err < o->tol_outer) break;
+      if (conv) break;
     }
     inf.outer_iters = k > o->max_outer ? o->max_outer : k;
-    if (err >= o->tol_outer) return cleanup(fail(FVIM_ENOCONV, "Algorithm 1: outer iteration limit reached"));
+    if (!conv) return cleanup(fail(FVIM_ENOCONV, "Algorithm 1: outer iteration limit reached"));
     // state update: eps_p += d_eps_p, ep += d_ep, sigma <- sigma_(n+1), T_n <- T, U3p += dU
     e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, s->sigma, V, c->lam, c->mu, c->mat.sigma_y0,
                           c->mat.E_h, st);

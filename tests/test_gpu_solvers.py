@@ -144,6 +144,35 @@ def test_anderson_outer_reaches_the_stored_fixed_point():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_warm_inexact_inner_solves_reach_the_stored_fixed_point(precision):
+    """Plasticity solves warm-started from the previous outer pass and solved
+    only to 0.1 x the outer error until the outer error is below tol_outer
+    (then once more to tol_plastic) end on the state of the oracle's relaxed
+    iteration within what the tolerances allow, with fewer residual
+    evaluations than full solves from the elastic trial."""
+    from paper_1811_11558_amd import Context, EPOptions
+    ref = np.load(GOLDEN)
+    g = grid_dict(16, 16, 8, lz=0.25)
+    evals = {}
+    for warm, rel in ((0, 0.0), (1, 0.1)):
+        ctx = Context(g, E, NU, SY, EH, precision=precision)
+        st = ctx.new_state()
+        infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                        EPOptions(tol_outer=1e-12, relax=0.3, tol_plastic=1e-13,
+                                                  tol_contact=1e-15, max_plastic=20000, anderson_m=5,
+                                                  warm_start=warm, inner_rel=rel))
+        torch.cuda.synchronize()
+        evals[warm] = sum(i["r_evals"] for i in infos)
+        _say(precision, "warm", warm, "inner_rel", rel, [(i["outer_iters"], i["r_evals"]) for i in infos])
+        for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+            err = _rel(st[k].cpu().numpy(), ref[k])
+            _say(k, err)
+            assert err < 1e-8, (k, err)
+        ctx.close()
+    assert evals[1] < evals[0], evals
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
 def test_residual_graphs_equal_eager(precision):
     """Algorithm 1 on the stored Hertz case with the plasticity residual
     evaluations replayed from captured HIP graphs gives bitwise the same state
