@@ -369,6 +369,14 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
 
 static bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u); }
 
+int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, double* strain) {
+  OpPlan<double> p64;
+  int rc = op_plan<double>(c, eps_p, traction, strain, nullptr, nullptr, nullptr, p64);
+  if (rc || c->precision != FVIM_FP32_REFINED) return rc;
+  OpPlan<float> p32;
+  return op_plan<float>(c, eps_p, traction, strain, nullptr, nullptr, nullptr, p32);
+}
+
 int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
                    double* disp, double* surf_u3) {
   if (misaligned(eps_p) || misaligned(traction) || misaligned(strain) || misaligned(stress) ||

@@ -123,5 +123,10 @@ hipError_t launch_k0_fields(const double* wsum, int wblocks, const double* tsum,
 hipError_t launch_return_map(const double* d_eps, const double* sig_n, const double* ep_n, double* d_eps_p,
                              double* d_ep, double* sig_np1, size_t nvox, double lam, double mu,
                              double sy0, double eh, hipStream_t st);
+// Return map at the trial point x + cf F (F may be NULL: at x); the trial
+// point is stored in xt when F and xt are given; writes d_eps_p only.
+hipError_t launch_trial_return_map(const double* x, const double* F, double cf, double* xt, const double* sig_n,
+                                   const double* ep_n, double* d_eps_p, size_t nvox, double lam, double mu,
+                                   double sy0, double eh, hipStream_t st);
 
 }  // namespace fvim

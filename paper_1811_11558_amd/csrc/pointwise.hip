@@ -15,7 +15,11 @@ constexpr int NT = 256;
 // (sy0 + eh ep_n) > 0, the consistency condition
 // sigma_eq_trial - 3 mu d_ep = sy0 + eh (ep_n + d_ep) gives
 // d_ep = f / (3 mu + eh), and the flow direction is that of dev sigma_trial.
-__global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de, const double* sn,
+// The strain increment is de + cf F when F is given (a trial point of the
+// plasticity iteration), and is then also stored in xt unless xt is NULL;
+// d_ep and sigma_(n+1) are written only where dp and sn1 are given.
+__global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de, const double* __restrict__ F,
+                                                  double cf, double* __restrict__ xt, const double* sn,
                                                   const double* __restrict__ epn, double* __restrict__ dep,
                                                   double* __restrict__ dp, double* sn1, size_t V, double lam,
                                                   double mu, double sy0, double eh) {
@@ -26,6 +30,13 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
   for (int c = 0; c < 6; ++c) {
     e[c] = de[c * V + v];
     s[c] = sn[c * V + v];
+  }
+  if (F) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      e[c] += cf * F[c * V + v];
+      if (xt) xt[c * V + v] = e[c];
+    }
   }
   const double tre = e[0] + e[1] + e[2];
 #pragma unroll
@@ -40,7 +51,7 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
     dpv = f / (3.0 * mu + eh);
     fac = 1.5 * dpv / seq;
   }
-  dp[v] = dpv;
+  if (dp) dp[v] = dpv;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const double x = fac * d[c];
@@ -112,8 +123,17 @@ hipError_t launch_return_map(const double* d_eps, const double* sig_n, const dou
                              double* d_ep, double* sig_np1, size_t nvox, double lam, double mu, double sy0,
                              double eh, hipStream_t st) {
   unsigned nb = (unsigned)((nvox + NT - 1) / NT);
-  hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, d_eps, sig_n, ep_n, d_eps_p, d_ep, sig_np1, nvox,
-                     lam, mu, sy0, eh);
+  hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, d_eps, nullptr, 0.0, nullptr, sig_n, ep_n, d_eps_p,
+                     d_ep, sig_np1, nvox, lam, mu, sy0, eh);
+  return hipGetLastError();
+}
+
+hipError_t launch_trial_return_map(const double* x, const double* F, double cf, double* xt, const double* sig_n,
+                                   const double* ep_n, double* d_eps_p, size_t nvox, double lam, double mu,
+                                   double sy0, double eh, hipStream_t st) {
+  unsigned nb = (unsigned)((nvox + NT - 1) / NT);
+  hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, x, F, cf, xt, sig_n, ep_n, d_eps_p, nullptr,
+                     nullptr, nvox, lam, mu, sy0, eh);
   return hipGetLastError();
 }
 

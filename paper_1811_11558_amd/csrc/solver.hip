@@ -267,33 +267,49 @@ __global__ __launch_bounds__(NT) void k_axpy(double* __restrict__ y, const doubl
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) y[i] = a[i] + s * b[i];
 }
 
-// R = x - b - w  (residual of the incremental equation) and its weighted square norm
+// Weight of element i of a [6][nz][plane] strain field in the scalar
+// product: 2 for the shear components (each stands for two tensor entries),
+// 1/2 at the first and last depth node (trapezoid rule in depth).  plane is
+// 2^lp.
+__device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz) {
+  const unsigned zc = (unsigned)(i >> lp);      // c * nz + z
+  const unsigned z = zc % nz;
+  return (zc < 3u * nz ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
+}
+
+// R = x - w, the residual of the incremental equation (w = grad_s M applied
+// to the plastic strain increment and to the traction increment), with the
+// weighted sums <R, R> and, when Fo is given, <Fo, R - Fo>.  Two elements per
+// thread (n is even: a plane has at least 16 elements).
 __global__ __launch_bounds__(NT) void k_resid(double* __restrict__ R, const double* __restrict__ x,
-                                             const double* __restrict__ b, const double* __restrict__ w,
-                                             size_t plane, int nz, size_t n, double* part) {
-  double v[1] = {0.0};
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
-    double r = x[i] - b[i] - w[i];
-    R[i] = r;
-    const size_t zc = i / plane;                // c * nz + z
-    const int z = (int)(zc % nz), c = (int)(zc / nz);
-    double wt = (c < 3 ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
-    v[0] += wt * r * r;
+                                             const double* __restrict__ w, const double* __restrict__ Fo,
+                                             int lp, unsigned nz, size_t n, double* part) {
+  double v[2] = {0.0, 0.0};
+  const size_t n2 = n / 2;
+  for (size_t j = (size_t)blockIdx.x * NT + threadIdx.x; j < n2; j += (size_t)gridDim.x * NT) {
+    const double2 a = reinterpret_cast<const double2*>(x)[j];
+    const double2 b = reinterpret_cast<const double2*>(w)[j];
+    const double2 r = make_double2(a.x - b.x, a.y - b.y);
+    reinterpret_cast<double2*>(R)[j] = r;
+    const double wt = field_weight(2 * j, lp, nz);          // both elements lie in one plane
+    v[0] += wt * (r.x * r.x + r.y * r.y);
+    if (Fo) {
+      const double2 f = reinterpret_cast<const double2*>(Fo)[j];
+      v[1] += wt * (f.x * (r.x - f.x) + f.y * (r.y - f.y));
+    }
   }
-  block_sums<1>(v, part);
+  block_sums<2>(v, part);
 }
 
 // weighted sums  <a, a>, <a, b>, <b, b>  with a = a1 - a0, b = b1 - b0 (a0/b0 may be NULL)
 __global__ __launch_bounds__(NT) void k_wdots(const double* __restrict__ a1, const double* a0,
-                                             const double* __restrict__ b1, const double* b0, size_t plane, int nz,
+                                             const double* __restrict__ b1, const double* b0, int lp, unsigned nz,
                                              size_t n, double* part) {
   double v[3] = {0.0, 0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
     double a = a1[i] - (a0 ? a0[i] : 0.0);
     double b = b1[i] - (b0 ? b0[i] : 0.0);
-    const size_t zc = i / plane;
-    const int z = (int)(zc % nz), c = (int)(zc / nz);
-    double wt = (c < 3 ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
+    const double wt = field_weight(i, lp, nz);
     v[0] += wt * a * a;
     v[1] += wt * a * b;
     v[2] += wt * b * b;
@@ -370,7 +386,8 @@ __global__ __launch_bounds__(NT) void k_aa_step(double* __restrict__ x, const do
 
 struct SolverWork {
   size_t ns = 0, V = 0;
-  double* surf = nullptr;       // 8 surface arrays
+  int lp = 0;                   // log2(ns)
+  double* surf = nullptr;       // 15 surface arrays
   void* specA = nullptr;        // complex kxh*ny
   void* specB = nullptr;
   double* part = nullptr;       // 3 * RB partial sums
@@ -394,27 +411,61 @@ struct SolverWork {
   double* aa_part = nullptr;
   double* aa_out = nullptr;     // device view of aa_hout (mapped host memory)
   double* aa_hout = nullptr;
-  // captured residual evaluations R(x) -> F (return map, operator, residual
-  // and its reduction), one per combination of the pointers and settings they
-  // bake in; replayed on the context stream
+  // captured residual evaluations (operator, residual and its reduction),
+  // one per combination of the pointers and settings they bake in; replayed
+  // on the context stream
   struct ResGraph {
     const void* key[10] = {};
     hipGraph_t g = nullptr;
     hipGraphExec_t ex = nullptr;
   };
-  ResGraph rg[4];
+  static constexpr int NRG = 8;    // trial or plain point x two buffer parities x two precisions
+  ResGraph rg[NRG];
   int rg_next = 0;
   int rg_warm[2] = {0, 0};       // an eager evaluation has sized every buffer (per precision)
-  int rg_off = 0;                // capture failed once: evaluate eagerly from now on
+  int cap_fail = 0;              // failed captures; from CAP_TRIES on, launch directly
 };
+
+constexpr int CAP_TRIES = 4;
+
+// The private capture stream and the events that fence it against the
+// context stream.
+static int cap_ensure(SolverWork* w) {
+  if (!w->cap && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess) {
+    w->cap = nullptr;
+    return fail(FVIM_EHIP, "graph stream");
+  }
+  if (!w->ev_in && hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess) {
+    w->ev_in = nullptr;
+    return fail(FVIM_EHIP, "graph event");
+  }
+  if (!w->ev_out && hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess) {
+    w->ev_out = nullptr;
+    return fail(FVIM_EHIP, "graph event");
+  }
+  return FVIM_OK;
+}
+
+// After a capture that failed: drop what it produced and clear the error it
+// left, so that the direct launches that replace it report their own status.
+static void capture_failed(SolverWork* w, hipGraph_t* g, hipGraphExec_t* ex) {
+  if (*ex) hipGraphExecDestroy(*ex);
+  if (*g) hipGraphDestroy(*g);
+  *ex = nullptr;
+  *g = nullptr;
+  (void)hipGetLastError();
+  ++w->cap_fail;
+}
 
 static int sw_ensure(fvim_ctx* c) {
   if (c->sw) return FVIM_OK;
   SolverWork* w = new SolverWork();
   w->ns = (size_t)c->grid.nx * c->grid.ny;
+  w->lp = 0;
+  while (((size_t)1 << w->lp) < w->ns) ++w->lp;
   w->V = w->ns * c->grid.nz;
   const size_t nm = (size_t)(c->grid.nx / 2 + 1) * c->grid.ny;
-  bool ok = hipMalloc((void**)&w->surf, sizeof(double) * w->ns * 12) == hipSuccess &&
+  bool ok = hipMalloc((void**)&w->surf, sizeof(double) * w->ns * 15) == hipSuccess &&
             hipMalloc(&w->specA, sizeof(cpx<double>) * nm) == hipSuccess &&
             hipMalloc(&w->specB, sizeof(cpx<double>) * nm) == hipSuccess &&
             hipMalloc((void**)&w->part, sizeof(double) * 3 * RB) == hipSuccess &&
@@ -458,7 +509,7 @@ void solver_release(fvim_ctx* c) {
 size_t solver_footprint(const fvim_grid* g, size_t V) {
   const size_t ns = (size_t)g->nx * g->ny;
   const size_t nm = (size_t)(g->nx / 2 + 1) * g->ny;
-  // surface arrays (12 + dT 3 + Anderson history 2 AA_MMAX + 3), volume work
+  // surface arrays (15 + Anderson history 2 AA_MMAX + 3), volume work
   // arrays (7 tensors + 1 scalar), compliance spectra, reduction buffers
   return sizeof(double) * (ns * (18 + 2 * AA_MMAX) + 43 * V) + 2 * sizeof(cpx<double>) * nm +
          sizeof(double) * aa_nsums(AA_MMAX) * (RB + 2) + 64 * 1024;
@@ -585,13 +636,9 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   double err = INFINITY;
   const int check = n <= 4096 ? 1 : 4;        // host convergence check period
   hipStream_t run = st;
-  if (c->use_graphs) {
-    if (!w->cap) {
-      if (hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess ||
-          hipEventCreateWithFlags(&w->ev_in, hipEventDisableTiming) != hipSuccess ||
-          hipEventCreateWithFlags(&w->ev_out, hipEventDisableTiming) != hipSuccess)
-        return fail(FVIM_EHIP, "graph stream");
-    }
+  bool graph = c->use_graphs && w->cap_fail < CAP_TRIES;
+  if (graph) {
+    if ((rc = cap_ensure(w))) return rc;
     if ((e = hipEventRecord(w->ev_in, st)) != hipSuccess) return fail_hip(e, "event");
     if ((e = hipStreamWaitEvent(w->cap, w->ev_in, 0)) != hipSuccess) return fail_hip(e, "event wait");
     run = w->cap;
@@ -602,16 +649,21 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
         return fail_hip(e, "graph capture");
       int rc2 = pk_iteration(c, run, h, p);
       e = hipStreamEndCapture(run, &w->pk_graph);
-      if (rc2) return rc2;
-      if (e != hipSuccess) return fail_hip(e, "graph capture end");
-      if ((e = hipGraphInstantiate(&w->pk_exec, w->pk_graph, nullptr, nullptr, 0)) != hipSuccess)
-        return fail_hip(e, "graph instantiate");
-      w->g_h = h;
-      w->g_p = p;
+      if (rc2 || e != hipSuccess || !w->pk_graph ||
+          hipGraphInstantiate(&w->pk_exec, w->pk_graph, nullptr, nullptr, 0) != hipSuccess) {
+        // the capture was invalidated (for instance by a device-wide
+        // synchronisation in another thread): nothing it recorded ran, so
+        // this solve iterates with direct launches
+        capture_failed(w, &w->pk_graph, &w->pk_exec);
+        graph = false;
+      } else {
+        w->g_h = h;
+        w->g_p = p;
+      }
     }
   }
   for (it = 1; it <= max_iter; ++it) {
-    if (c->use_graphs) {
+    if (graph) {
       if ((e = hipGraphLaunch(w->pk_exec, run)) != hipSuccess) return fail_hip(e, "graph launch");
     } else {
       if ((rc = pk_iteration(c, run, h, p))) return rc;
@@ -653,6 +705,7 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
 // --------------------------------------------------------- plasticity
 struct PlastBufs {
   double *x, *F, *xt, *Ft, *b, *dep, *dp, *wk;
+  const double* dT;             // traction increment of the current solve
 };
 
 static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
@@ -680,6 +733,7 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
   pb.dep = q + 30 * V;
   pb.wk = q + 36 * V;
   pb.dp = q + 42 * V;
+  pb.dT = nullptr;
   return FVIM_OK;
 }
 
@@ -689,36 +743,34 @@ static double inner_scale(const fvim_ctx* c) {
   return g.lx * g.ly / ((double)g.nx * g.ny) * g.lz / (g.nz - 1);
 }
 
-// R(x) into F; returns |R|^2 (weighted) in *f
-// Launches of one residual evaluation on the context stream.
-static int residual_launches(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F) {
+// One residual evaluation after the return map: w = grad_s M[dep] +
+// grad_s M[dT] (one operator application with both sources), F = x - w and
+// the sums <F, F>, <Fo, F - Fo> (Fo may be NULL), on the context stream.
+static int residual_launches(fvim_ctx* c, PlastBufs& pb, const double* x, double* F, const double* Fo) {
   SolverWork* w = c->sw;
-  const size_t V = w->V, n6 = 6 * V;
-  hipStream_t st = c->stream;
-  hipError_t e = launch_return_map(x, s->sigma, s->ep, pb.dep, pb.dp, nullptr, V, c->lam, c->mu, c->mat.sigma_y0,
-                                   c->mat.E_h, st);
-  if (e != hipSuccess) return fail_hip(e, "return map");
-  int rc = operator_apply(c, pb.dep, nullptr, pb.wk, nullptr, nullptr, nullptr);
+  const size_t n6 = 6 * w->V;
+  int rc = operator_apply(c, pb.dep, pb.dT, pb.wk, nullptr, nullptr, nullptr);
   if (rc) return rc;
-  const int nb = nblocks(n6);
-  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, st, F, x, pb.b, pb.wk, w->ns, c->grid.nz, n6, w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, st, 6, w->part, nb, w->sc, w->dmap);
+  const int nb = nblocks(n6 / 2);
+  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, c->stream, F, x, pb.wk, Fo, w->lp, (unsigned)c->grid.nz, n6,
+                     w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
   return FVIM_OK;
 }
 
-// The residual evaluation as a replayed HIP graph when the context allows it
+// The launches above as a replayed HIP graph when the context allows it
 // (graphs on, no tuning or stage timing pending, buffers already sized by an
 // eager evaluation in this precision); else launched directly.
-static int residual_enqueue(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F) {
+static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double* F, const double* Fo) {
   SolverWork* w = c->sw;
   const int p64 = (c->precision == FVIM_FP64 || c->force_fp64) ? 1 : 0;
-  if (!c->use_graphs || w->rg_off || c->tune_pending || c->timing || c->use_side)
-    return residual_launches(c, s, pb, x, F);
+  if (!c->use_graphs || w->cap_fail >= CAP_TRIES || c->tune_pending || c->timing || c->use_side)
+    return residual_launches(c, pb, x, F, Fo);
   if (!w->rg_warm[p64]) {
     w->rg_warm[p64] = 1;
-    return residual_launches(c, s, pb, x, F);
+    return residual_launches(c, pb, x, F, Fo);
   }
-  const void* key[10] = {x, F, s->sigma, s->ep, w->vol, c->bufA, c->bufB, c->k0buf,
+  const void* key[10] = {x, F, Fo, pb.dT, w->vol, c->bufA, c->bufB, c->k0buf,
                          (const void*)(intptr_t)(p64 + 2), (const void*)(intptr_t)(c->depth_cfg + 16)};
   for (auto& r : w->rg)
     if (r.ex && std::equal(key, key + 10, r.key)) {
@@ -726,26 +778,24 @@ static int residual_enqueue(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, con
       return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
     }
   // capture on the private stream (the context stream is pointed at it)
-  if (!w->cap && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess)
-    return fail(FVIM_EHIP, "graph stream");
+  int rc = cap_ensure(w);
+  if (rc) return rc;
   SolverWork::ResGraph& r = w->rg[w->rg_next];
-  w->rg_next = (w->rg_next + 1) % 4;
+  w->rg_next = (w->rg_next + 1) % SolverWork::NRG;
   if (r.ex) { hipGraphExecDestroy(r.ex); r.ex = nullptr; }
   if (r.g) { hipGraphDestroy(r.g); r.g = nullptr; }
   hipStream_t saved = c->stream;
   hipError_t e = hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return fail_hip(e, "graph capture");
   c->stream = w->cap;
-  int rc = residual_launches(c, s, pb, x, F);
+  rc = residual_launches(c, pb, x, F, Fo);
   c->stream = saved;
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(w->cap, &g);
   if (rc || e != hipSuccess || !g ||
       hipGraphInstantiate(&r.ex, g, nullptr, nullptr, 0) != hipSuccess) {
-    if (g) hipGraphDestroy(g);
-    r.ex = nullptr;
-    w->rg_off = 1;                     // do not try again; evaluate eagerly
-    return residual_launches(c, s, pb, x, F);
+    capture_failed(w, &g, &r.ex);       // nothing recorded ran: evaluate directly
+    return residual_launches(c, pb, x, F, Fo);
   }
   r.g = g;
   std::copy(key, key + 10, r.key);
@@ -753,12 +803,21 @@ static int residual_enqueue(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, con
   return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
 }
 
-static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, double* F, double* f) {
+// Residual at the trial point xt = x + cf Fo (Fo NULL: at x itself, xt
+// ignored) into F: radial return at xt, then the evaluation above.  Returns
+// the weighted <F, F> in *f and, with Fo, <Fo, F - Fo> in *d.
+static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* x, const double* Fo, double cf,
+                    double* xt, double* F, double* f, double* d = nullptr) {
   SolverWork* w = c->sw;
-  int rc = residual_enqueue(c, s, pb, x, F);
+  hipError_t e = launch_trial_return_map(x, Fo, cf, Fo ? xt : nullptr, s->sigma, s->ep, pb.dep, w->V, c->lam, c->mu,
+                                         c->mat.sigma_y0, c->mat.E_h, c->stream);
+  if (e != hipSuccess) return fail_hip(e, "return map");
+  int rc = residual_enqueue(c, pb, Fo ? xt : x, F, Fo);
   if (rc) return rc;
-  if ((rc = read_scalars(c, S_DOT0, 1))) return rc;
-  *f = w->hsc[S_DOT0] * inner_scale(c);
+  if ((rc = read_scalars(c, S_DOT0, Fo ? 2 : 1))) return rc;
+  const double sc = inner_scale(c);
+  *f = w->hsc[S_DOT0] * sc;
+  if (d) *d = Fo ? w->hsc[S_DOT1] * sc : 0.0;
   if (!std::isfinite(*f)) return fail(FVIM_EINVAL, "plasticity residual is not finite");
   return FVIM_OK;
 }
@@ -767,7 +826,8 @@ static int wdots(fvim_ctx* c, const double* a1, const double* a0, const double* 
   SolverWork* w = c->sw;
   const size_t n6 = 6 * w->V;
   const int nb = nblocks(n6);
-  hipLaunchKernelGGL(k_wdots, dim3(nb), dim3(NT), 0, c->stream, a1, a0, b1, b0, w->ns, c->grid.nz, n6, w->part);
+  hipLaunchKernelGGL(k_wdots, dim3(nb), dim3(NT), 0, c->stream, a1, a0, b1, b0, w->lp, (unsigned)c->grid.nz, n6,
+                     w->part);
   hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
   int rc = read_scalars(c, S_DOT0, 3);
   if (rc) return rc;
@@ -791,16 +851,15 @@ struct Fp64Scope {
 // One DF-SANE / Picard run from the current pb.x to |R| <= tol_abs.
 static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, double tol_abs,
                        int max_it, int* iters, int* evals, double* fout) {
-  const size_t n6 = 6 * c->sw->V;
   double f;
-  int rc = residual(c, s, pb, pb.x, pb.F, &f);
+  int rc = residual(c, s, pb, pb.x, nullptr, 0.0, nullptr, pb.F, &f);
   if (rc) return rc;
   int ne = 1, k = 0;
-  double d3[3];
   if (o->solver == 1) {            // Picard: x <- x - R(x)
     while (std::sqrt(f) > tol_abs && k < max_it) {
-      axpy(c, pb.x, pb.x, -1.0, pb.F, n6);
-      if ((rc = residual(c, s, pb, pb.x, pb.F, &f))) return rc;
+      if ((rc = residual(c, s, pb, pb.x, pb.F, -1.0, pb.xt, pb.Ft, &f))) return rc;
+      std::swap(pb.x, pb.xt);
+      std::swap(pb.F, pb.Ft);
       ++ne;
       ++k;
     }
@@ -814,28 +873,27 @@ static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, 
       const double eta = f0n / ((1.0 + k) * (1.0 + k));
       double fbar = 0.0;
       for (size_t i = hist.size() > (size_t)M ? hist.size() - M : 0; i < hist.size(); ++i) fbar = std::max(fbar, hist[i]);
-      double ap = 1.0, am = 1.0, fn = 0.0;
+      double ap = 1.0, am = 1.0, fn = 0.0, cs = 0.0, dfy = 0.0;
       int guard = 0;
       while (true) {
-        axpy(c, pb.xt, pb.x, -ap * sigma, pb.F, n6);      // x + ap d, d = -sigma F
-        double fp;
-        if ((rc = residual(c, s, pb, pb.xt, pb.Ft, &fp))) return rc;
+        double fp, dp, fm, dm;
+        const double cp = -ap * sigma;                     // x + ap d, d = -sigma F
+        if ((rc = residual(c, s, pb, pb.x, pb.F, cp, pb.xt, pb.Ft, &fp, &dp))) return rc;
         ++ne;
-        if (fp <= fbar + eta - gamma * ap * ap * f) { fn = fp; break; }
-        axpy(c, pb.xt, pb.x, am * sigma, pb.F, n6);       // x - am d
-        double fm;
-        if ((rc = residual(c, s, pb, pb.xt, pb.Ft, &fm))) return rc;
+        if (fp <= fbar + eta - gamma * ap * ap * f) { fn = fp; cs = cp; dfy = dp; break; }
+        const double cm = am * sigma;                      // x - am d
+        if ((rc = residual(c, s, pb, pb.x, pb.F, cm, pb.xt, pb.Ft, &fm, &dm))) return rc;
         ++ne;
-        if (fm <= fbar + eta - gamma * am * am * f) { fn = fm; break; }
+        if (fm <= fbar + eta - gamma * am * am * f) { fn = fm; cs = cm; dfy = dm; break; }
         double at = ap * ap * f / (fp + (2.0 * ap - 1.0) * f);
         ap = std::min(std::max(at, tmin * ap), tmax * ap);
         at = am * am * f / (fm + (2.0 * am - 1.0) * f);
         am = std::min(std::max(at, tmin * am), tmax * am);
         if (++guard > 60) return fail(FVIM_ENOCONV, "DF-SANE line search failed");
       }
-      // spectral coefficient from s = xt - x, y = Ft - F
-      if ((rc = wdots(c, pb.xt, pb.x, pb.Ft, pb.F, d3))) return rc;
-      const double ss = d3[0], sy = d3[1];
+      // spectral coefficient from s = xt - x = cs F and y = Ft - F:
+      // <s, s> = cs^2 <F, F>, <s, y> = cs <F, Ft - F>
+      const double ss = cs * cs * f, sy = cs * dfy;
       if (sy == 0.0) sigma = smax;
       else {
         sigma = ss / sy;
@@ -872,6 +930,7 @@ static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const 
   const size_t n6 = 6 * w->V;
   hipStream_t st = c->stream;
   int rc;
+  pb.dT = dT;
   if (warm) axpy(c, pb.x, pb.x, -1.0, pb.b, n6);
   {
     Fp64Scope f64(c, 1);
@@ -1032,14 +1091,12 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   double* dU = w->surf + 8 * n;
   double* T = w->surf + 9 * n;        // 3 planes: 9, 10, 11
   double* pcur = T + 2 * n;           // normal component of T
-  // dT lives in the traction spectrum workspace? use a dedicated array
-  double* dT = nullptr;
-  if (hipMalloc((void**)&dT, sizeof(double) * 3 * n) != hipSuccess) return fail(FVIM_ENOMEM, "dT");
+  double* dT = w->surf + 12 * n;      // 3 planes: 12, 13, 14
   const int aam = o->literal_alg1 ? 0 : o->anderson_m;
-  if (aam > 0 && (rc = aa_ensure(c))) {
-    hipFree(dT);
-    return rc;
-  }
+  if (aam > 0 && (rc = aa_ensure(c))) return rc;
+  // every buffer the operator applications of the solve use, sized now: no
+  // device memory is freed or allocated while the solve runs
+  if ((rc = operator_reserve(c, pb.dep, dT, pb.wk))) return rc;
   // Anderson history: differences of the iterates and of the residuals
   double* aX = aam ? w->aa : nullptr;
   double* aF = aam ? w->aa + (size_t)AA_MMAX * n : nullptr;
@@ -1048,7 +1105,6 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   double* fres = aam ? fprev + n : nullptr;
   auto cleanup = [&](int r) {
     hipStreamSynchronize(st);
-    hipFree(dT);
     return r;
   };
   hipError_t e;

@@ -62,6 +62,10 @@ int fail_hip(hipError_t e, const char* where);
 int ctx_reserve(fvim_ctx* c, void** p, size_t* have, size_t need);
 int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
                    double* disp, double* surf_u3);
+// Sizes the workspace and builds the mode tables of an application with
+// eigenstrain and traction inputs and strain output, in float64 and, in the
+// FP32_REFINED mode, in float32.
+int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, double* strain);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
 }  // namespace fvim
