@@ -35,9 +35,28 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int idx) {
 // gives the inverse transform's strided reads longer runs (32 KiB in
 // float64; 16 KiB in float32).
 template <typename T>
-constexpr int r2c_tile_elems() { return sizeof(T) == 8 ? 1024 : 2048; }
+__host__ __device__ constexpr int r2c_tile_elems() { return sizeof(T) == 8 ? 1024 : 2048; }
 template <typename T>
-constexpr int c2r_tile_elems() { return 2048; }
+__host__ __device__ constexpr int c2r_tile_elems() { return 2048; }
+// Row pairs per block of a row kernel (R = 2 SEQ rows of length n).  The
+// X[p][kx][y] side is touched in runs of R elements of one kx, so SEQ is the
+// tile's share but at least what gives runs of ROW_RUN bytes, as far as the
+// 160 KiB of LDS a block may use and a tile of 8192 elements (the loads of a
+// whole tile are staged in registers) allow.  (At nx = 1024 in float64 a 16 KiB
+// tile alone gives 2-row blocks, 32-byte runs and 1.5 TB/s.)
+constexpr int ROW_RUN = 128;
+__host__ __device__ constexpr int row_seq(int n, int csize, int tile) {
+  int seq = tile / n;
+  if (seq < 1) seq = 1;
+  const int minseq = ROW_RUN / (2 * csize);
+  if (seq < minseq) seq = minseq;
+  while (seq > 1 && (seq * (n + 1) * csize > 160 * 1024 || seq * n > 8192)) seq /= 2;
+  return seq;
+}
+template <typename T>
+__host__ __device__ constexpr int r2c_seq(int n) { return row_seq(n, (int)sizeof(cpx<T>), r2c_tile_elems<T>()); }
+template <typename T>
+__host__ __device__ constexpr int c2r_seq(int n) { return row_seq(n, (int)sizeof(cpx<T>), c2r_tile_elems<T>()); }
 // Columns (planes) per block of the column (y) kernels.  The mode-major side
 // S[kx][ky][p] is touched in runs of B consecutive planes, so B is the 32 KiB
 // tile's share unless that makes runs shorter than 64 bytes (ny >= 1024 in
@@ -148,7 +167,7 @@ template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
                                              const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
   constexpr int N = 1 << LOGN;
-  constexpr int SEQ = (r2c_tile_elems<T>() / N) > 1 ? r2c_tile_elems<T>() / N : 1;
+  constexpr int SEQ = r2c_seq<T>(N);
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
   __shared__ cpx<T> buf[SEQ * ld];
@@ -208,6 +227,14 @@ __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict
   }
 }
 
+// Logical block index such that the blocks dispatched to one XCD (physical
+// blocks b, b + 8, b + 16, ...) take consecutive logical indices.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int x = b & 7, slot = b >> 3, per = n >> 3, rem = n & 7;
+  return x * per + (x < rem ? x : rem) + slot;
+}
+
 // Forward column transform: X[p][kx][y] -> S[kx][ky][p]; block = up to B
 // planes of one kx (B = tile / ny).  Tile rows past the last plane are filled
 // with copies of it (never stored), so every load is unconditional: with
@@ -222,8 +249,9 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
-  const int kx = blockIdx.x / npb;
-  const int p0 = (blockIdx.x - kx * npb) * B;
+  const int lb = xcd_block();
+  const int kx = lb / npb;
+  const int p0 = (lb - kx * npb) * B;
   const int nb = min(B, NP - p0);
   constexpr int MV = B * N / NT;
   cpx<T> v[MV];
@@ -259,8 +287,9 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
   constexpr int ld = N + 1;
   __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
-  const int kx = blockIdx.x / npb;
-  const int p0 = (blockIdx.x - kx * npb) * B;
+  const int lb = xcd_block();
+  const int kx = lb / npb;
+  const int p0 = (lb - kx * npb) * B;
   const int nb = min(B, NP - p0);
   static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int MV = B * N / NT;
@@ -299,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
                                              double scale, const cpx<T>* __restrict__ tw,
                                              const double* __restrict__ padd) {
   constexpr int N = 1 << LOGN;
-  constexpr int SEQ = (c2r_tile_elems<T>() / N) > 1 ? c2r_tile_elems<T>() / N : 1;
+  constexpr int SEQ = c2r_seq<T>(N);
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
   constexpr int nyq = N / 2;
@@ -352,14 +381,8 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
   }
 }
 
-template <typename T>
-int rows_per_block(int tile, int nx, int ny) {
-  int seq = tile / nx;
-  if (seq < 1) seq = 1;
-  int r = 2 * seq;
-  if (r > ny) r = ny;
-  return r;
-}
+// R of a row kernel launch: 2 SEQ rows, or the whole plane when it is shorter
+int rows_per_block(int seq, int ny) { return 2 * seq < ny ? 2 * seq : ny; }
 
 template <typename T>
 int cols_per_block(int ny) {
@@ -388,14 +411,14 @@ int ilog2(int n) { return 31 - __builtin_clz((unsigned)n); }
 
 template <typename T>
 int x_r2c_blocks_per_plane(int nx, int ny) {
-  return ny / rows_per_block<T>(r2c_tile_elems<T>(), nx, ny);
+  return ny / rows_per_block(r2c_seq<T>(nx), ny);
 }
 
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum) {
   if (seg.n < 1 || seg.n > 2 || seg.first[0] != 0) return hipErrorInvalidValue;
-  int R = rows_per_block<T>(r2c_tile_elems<T>(), nx, ny);
+  int R = rows_per_block(r2c_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
 #define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
@@ -440,7 +463,7 @@ hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd) {
-  int R = rows_per_block<T>(c2r_tile_elems<T>(), nx, ny);
+  int R = rows_per_block(c2r_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
 #define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
