@@ -63,12 +63,14 @@ def parse():
     ap.add_argument("--load", type=float, default=1e-4, help="rough: final total load W (E L^2 units)")
     ap.add_argument("--compare", action="store_true",
                     help="rough: solve in float64 and in FP32_REFINED and report the differences")
-    ap.add_argument("--anderson", type=int, default=0,
-                    help="solve/serve: Anderson depth of the outer fixed point (0 = Algorithm 1 relaxation)")
-    ap.add_argument("--warm", type=int, default=0,
-                    help="solve/serve/rough: warm-start each outer pass's plasticity solve from the previous one")
-    ap.add_argument("--inner-rel", type=float, default=0.0,
-                    help="solve/serve/rough: inexact plasticity solves to inner_rel x the outer error (0 = off)")
+    ap.add_argument("--anderson", type=int, default=5,
+                    help="solve/serve/rough: Anderson depth of the outer fixed point (0 = Algorithm 1 relaxation)")
+    ap.add_argument("--warm", type=int, default=1,
+                    help="solve/serve/rough: warm-start each outer pass's plasticity solve from the previous one "
+                         "(0 = from the elastic trial)")
+    ap.add_argument("--inner-rel", type=float, default=0.1,
+                    help="solve/serve/rough: inexact plasticity solves to inner_rel x the outer error "
+                         "(0 = always to tol_plastic)")
     return ap.parse_args()
 
 
@@ -217,7 +219,9 @@ def bench_rough(a):
     """Elastoplastic contact of a self-affine rough surface (flat PSD below
     k_roll, power law with Hurst exponent H up to k_cut, rms slope 0.1, seed
     0) on nx x ny x nz, lz = 0.25 L, E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1,
-    cumulative loads W/5, ..., W; outer tolerance 1e-7, lambda = 0.3.
+    cumulative loads W/5, ..., W; outer tolerance 1e-7, lambda = 0.3; outer
+    acceleration, warm start and inner tolerance from --anderson, --warm,
+    --inner-rel (defaults 5, on, 0.1).
     Throughput = voxel-updates of the plasticity residual evaluations / solve
     time.  With --compare: float64 and FP32_REFINED on the same problem and
     the relative L2 differences of the final pressure, plastic strain,
@@ -278,7 +282,7 @@ def bench_rough(a):
 def bench_solve(a):
     """Elastoplastic paraboloid solve, 32 x 32 x 16 (R = 0.5 L, lz = 0.25 L,
     E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1), cumulative loads up to
-    W = 0.02 in 10 equal steps."""
+    W = 0.02 in 10 equal steps; --anderson, --warm, --inner-rel as for rough."""
     import torch
     from paper_1811_11558_amd import Context, EPOptions
     from synth import grid_dict, paraboloid
@@ -310,7 +314,8 @@ def bench_serve(a):
     """Seeded Poisson-arrival elastoplastic contact solves of mixed grids
     (64^2 x 32, 128^2 x 64, 256^2 x 64, 512^2 x 96; rough surfaces with Hurst
     exponent in [0.5, 0.9]) through the batching server; one load step each,
-    FP32 kernels with float64 refinement, outer tolerance 1e-7."""
+    FP32 kernels with float64 refinement, outer tolerance 1e-7; --anderson,
+    --warm, --inner-rel as for rough."""
     from paper_1811_11558_amd import Server, EPOptions
     from synth import grid_dict, poisson_requests, rough_surface
     reqs = poisson_requests(n=a.requests, rate=a.rate if a.rate > 0 else 1e9, seed=2024)

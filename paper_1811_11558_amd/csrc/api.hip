@@ -53,8 +53,14 @@ static void* make_twiddles(int n, hipError_t* err) {
   return d;
 }
 
+std::recursive_mutex& device_lock() {
+  static std::recursive_mutex m;
+  return m;
+}
+
 int ctx_reserve(fvim_ctx* c, void** p, size_t* have, size_t need) {
   if (*have >= need) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   if (*p) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
@@ -97,6 +103,7 @@ struct StageTimer {
 
 static int side_ensure(fvim_ctx* c) {
   if (c->side) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   hipEvent_t* evs[] = {&c->ev_spec, &c->ev_nyq};
   for (hipEvent_t* ev : evs)
@@ -233,6 +240,7 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   }
   void*& mt = sizeof(T) == 8 ? c->mt64 : c->mt32;
   if (!mt) {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());
     if (hipMalloc(&mt, sizeof(ModeConst<T>) * nmodes) != hipSuccess) {
       mt = nullptr;
       return fail(FVIM_ENOMEM, "device allocation failed for the mode table");
@@ -419,6 +427,7 @@ int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision, 
   if (k0_policy != FVIM_K0_INCLUDE && k0_policy != FVIM_K0_EXCLUDE) return fail(FVIM_EINVAL, "unknown k0 policy");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(FVIM_ENODEV, "no HIP device");
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   fvim_ctx* c = new fvim_ctx();
   c->grid = *grid;
   c->mat = *mat;
@@ -443,6 +452,7 @@ int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision, 
 
 void fvim_destroy(fvim_ctx* c) {
   if (!c) return;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   if (c->side) hipStreamSynchronize(c->side);

@@ -29,6 +29,7 @@
 
 #include "../../include/fvim.h"
 #include "solver.hpp"
+#include "solver.hpp"
 
 namespace {
 
@@ -82,7 +83,11 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
   if (rc) return rc;
   double* mem = nullptr;
   const size_t nd = 13 * V + 5 * ns;
+  // allocation and the copies from pageable host memory do not overlap
+  // another slot's graph capture
+  std::unique_lock<std::recursive_mutex> dev(fvim::device_lock());
   if (hipMalloc((void**)&mem, sizeof(double) * nd) != hipSuccess) {
+    dev.unlock();
     fvim_destroy(ctx);
     return FVIM_ENOMEM;
   }
@@ -95,9 +100,12 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
   state.u3p = state.traction + 3 * ns;
   double* h = state.u3p + ns;
   if (e == hipSuccess) e = hipMemcpyAsync(h, j->h.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) rc = FVIM_EHIP;
+  dev.unlock();
   std::vector<fvim_ep_info> info(r.n_steps);
   if (!rc) rc = elastoplastic_solve(ctx, h, r.W_steps, r.n_steps, &r.opts, &state, info.data());
+  dev.lock();
   if (!rc) {
     j->res.info = info[r.n_steps - 1];
     j->p_host.resize(ns);
@@ -114,13 +122,16 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
   hipStreamSynchronize(st);
   hipFree(mem);
   fvim_destroy(ctx);
-  return rc;
+  return rc;                            // releases the device lock
 }
 
 void worker(fvim_server* s) {
   hipSetDevice(s->device);
   hipStream_t st = nullptr;
-  hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  {
+    std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
+    hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  }
   for (;;) {
     Job* j = nullptr;
     {
@@ -161,7 +172,10 @@ void worker(fvim_server* s) {
     s->cv_done.notify_all();
     s->cv_work.notify_all();
   }
-  if (st) hipStreamDestroy(st);
+  if (st) {
+    std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
+    hipStreamDestroy(st);
+  }
 }
 
 }  // namespace

@@ -115,8 +115,10 @@ __global__ __launch_bounds__(NT) void k_pk_grad(const double* __restrict__ p, do
 __global__ __launch_bounds__(NT) void k_pk_dir(const double* __restrict__ p, const double* __restrict__ g,
                                               double* __restrict__ t, size_t n, const double* __restrict__ sc) {
   const double beta = sc[S_BETA];
+  // beta = 0 (first iteration, restart) must not read the previous
+  // direction: 0 * t would carry a NaN through
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT)
-    t[i] = (p[i] > 0.0) ? g[i] + beta * t[i] : 0.0;
+    t[i] = (p[i] > 0.0) ? g[i] + (beta != 0.0 ? beta * t[i] : 0.0) : 0.0;
 }
 
 // sums over the contact set of r and 1
@@ -431,6 +433,7 @@ constexpr int CAP_TRIES = 4;
 // The private capture stream and the events that fence it against the
 // context stream.
 static int cap_ensure(SolverWork* w) {
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   if (!w->cap && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess) {
     w->cap = nullptr;
     return fail(FVIM_EHIP, "graph stream");
@@ -459,6 +462,7 @@ static void capture_failed(SolverWork* w, hipGraph_t* g, hipGraphExec_t* ex) {
 
 static int sw_ensure(fvim_ctx* c) {
   if (c->sw) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   SolverWork* w = new SolverWork();
   w->ns = (size_t)c->grid.nx * c->grid.ny;
   w->lp = 0;
@@ -476,12 +480,18 @@ static int sw_ensure(fvim_ctx* c) {
             hipHostGetDevicePointer((void**)&w->dmap, w->hmap, 0) == hipSuccess;
   c->sw = w;
   if (!ok) return fail(FVIM_ENOMEM, "solver workspace allocation failed");
+  // the final reductions always sum three rows of partials; rows a kernel
+  // does not write then read zeros, not whatever the allocation held
+  hipError_t e = hipMemsetAsync(w->part, 0, sizeof(double) * 3 * RB, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e, "solver workspace");
   return FVIM_OK;
 }
 
 void solver_release(fvim_ctx* c) {
   SolverWork* w = c->sw;
   if (!w) return;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   if (w->surf) hipFree(w->surf);
   if (w->specA) hipFree(w->specA);
   if (w->specB) hipFree(w->specB);
@@ -613,6 +623,7 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   const dim3 G(nb), Bk(NT);
   double* u = w->surf;
   double* g = w->surf + n;
+  double* t = w->surf + 2 * n;
   const double dA = c->grid.lx * c->grid.ly / (double)n;
   // scalars: load, area, restart state
   w->hsc[S_W] = W;
@@ -621,6 +632,8 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   w->hsc[S_GOLD] = 1.0;
   hipError_t e = hipMemcpyAsync(w->sc, w->hsc, sizeof(double) * NSCAL, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail_hip(e, "scalar upload");
+  // no previous conjugate direction
+  hipLaunchKernelGGL(k_fill, G, Bk, 0, st, t, n, 0.0);
   // initial pressure: warm start renormalised to W, or uniform
   hipLaunchKernelGGL(k_sum_abs, G, Bk, 0, st, p, n, w->part);
   hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 6, w->part, nb, w->sc, w->dmap);
@@ -645,6 +658,7 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
     if (!w->pk_exec || w->g_h != h || w->g_p != p) {
       if (w->pk_exec) { hipGraphExecDestroy(w->pk_exec); w->pk_exec = nullptr; }
       if (w->pk_graph) { hipGraphDestroy(w->pk_graph); w->pk_graph = nullptr; }
+      std::lock_guard<std::recursive_mutex> lk(device_lock());
       if ((e = hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return fail_hip(e, "graph capture");
       int rc2 = pk_iteration(c, run, h, p);
@@ -713,6 +727,7 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
   const size_t V = w->V;
   const size_t need = 7 * 6 * V + V;
   if (w->vol_count < need) {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());
     if (w->vol) {
       hipStreamSynchronize(c->stream);
       hipFree(w->vol);
@@ -785,6 +800,7 @@ static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double*
   if (r.ex) { hipGraphExecDestroy(r.ex); r.ex = nullptr; }
   if (r.g) { hipGraphDestroy(r.g); r.g = nullptr; }
   hipStream_t saved = c->stream;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   hipError_t e = hipStreamBeginCapture(w->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return fail_hip(e, "graph capture");
   c->stream = w->cap;
@@ -985,6 +1001,7 @@ static int surf_norms(fvim_ctx* c, const double* a, const double* b, double* dno
 static int aa_ensure(fvim_ctx* c) {
   SolverWork* w = c->sw;
   if (w->aa) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
   const int K = aa_nsums(AA_MMAX);
   if (hipMalloc((void**)&w->aa, sizeof(double) * w->ns * (2 * AA_MMAX + 3)) != hipSuccess ||
       hipMalloc((void**)&w->aa_part, sizeof(double) * K * RB) != hipSuccess ||

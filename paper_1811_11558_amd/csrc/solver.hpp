@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <mutex>
 #include <vector>
 
 #include "../../include/fvim.h"
@@ -57,6 +58,13 @@ struct fvim_ctx {
 };
 
 namespace fvim {
+// Held by every graph capture of the library (begin to end) and by every
+// library call that allocates or frees device or pinned memory or copies
+// synchronously.  On HIP such a call made by one thread while another
+// thread captures either invalidates that capture or fails itself, so the
+// library's own threads (server slots, callers solving on several streams)
+// must not overlap the two.
+std::recursive_mutex& device_lock();
 int fail(int code, const char* msg);
 int fail_hip(hipError_t e, const char* where);
 int ctx_reserve(fvim_ctx* c, void** p, size_t* have, size_t need);

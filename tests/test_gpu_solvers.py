@@ -56,6 +56,28 @@ def test_contact_matches_oracle(n, W, seed):
     assert oc.kkt_residual(p, gap, h) < 1e-10
 
 
+def test_contact_solve_on_workspace_that_held_nan():
+    """The solver workspace of a new context is not cleared memory: pages
+    that held NaN are returned to the driver first, then a contact solve on
+    a fresh context (which allocates its workspace then) must stay finite
+    and equal a solve on an ordinary context.  The conjugate direction of the
+    first iteration must not be formed from what the array held."""
+    n, W = 64, 0.01
+    g = grid_dict(n, n, 2)
+    h = torch.from_numpy(rough_surface(n, n, hurst=0.8, k_roll=2, k_cut=n // 4, rms_slope=0.1, seed=2)).cuda()
+    ref, _, _ = _ctx(g).contact_solve(h, W, tol=1e-14, max_iter=20000)
+    torch.cuda.synchronize()
+    junk = torch.full((1 << 26,), float("nan"), dtype=torch.float64, device="cuda")   # 512 MiB
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    p, _, info = _ctx(g).contact_solve(h, W, tol=1e-14, max_iter=20000)
+    torch.cuda.synchronize()
+    _say("contact after NaN pages: iters", info["iters"])
+    assert torch.isfinite(p).all()
+    assert torch.equal(p, ref)
+
+
 def test_contact_full_contact_sinusoid_exact():
     g = grid_dict(32, 16, 2)
     x = np.arange(32) / 32
