@@ -3,6 +3,8 @@ under profiles/ and into profiles/traffic.json (read by bench.py).
 
 Usage (from the repository root):
     python -m paper_1811_11558_amd.profile_summary stats <kernel_stats.csv>
+    python -m paper_1811_11558_amd.profile_summary kernels --title T --stats S.csv \\
+        --trace T.csv --commands commands.txt --out profiles/NAME.md
     python -m paper_1811_11558_amd.profile_summary report --workload 256x256x64/fp64 \\
         --stats S.csv --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
         --copy-bytes 400000000 [--raw-read R1.csv --raw-write R2.csv] \\
@@ -45,7 +47,8 @@ def source_sha(name):
 
 
 def short(name):
-    name = name.replace("void fvim::(anonymous namespace)::", "")
+    name = name.replace("void ", "", 1) if name.startswith("void ") else name
+    name = name.replace("fvim::(anonymous namespace)::", "")
     return re.sub(r"\(.*\)$", "", name).strip()
 
 
@@ -195,9 +198,37 @@ def report(a):
     print("\n".join(doc))
 
 
+def kernels(a):
+    """Kernel-time summary of one profiled run (no counters): the commands,
+    the per-kernel statistics and the per-launch-shape table."""
+    rows = trace_table(a.trace).split("\n")
+    doc = ["# %s" % a.title, "", "Commands (from the repository root on the GPU host):", "", "```"]
+    doc += [l.rstrip("\n") for l in open(a.commands)] + ["```", ""]
+    doc += ["## Kernel durations (`rocprofv3 --kernel-trace --stats`)", "", stats(a.stats), ""]
+    doc += ["Per launch shape (same run, from the kernel trace; the %d with the most time):" % a.top, ""]
+    doc += rows[:2 + a.top] + [""]
+    if a.note:
+        doc += [a.note, ""]
+    with open(a.out, "w") as f:
+        f.write("\n".join(doc))
+    print("\n".join(doc))
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "kernels":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("mode", choices=["kernels"])
+        ap.add_argument("--title", required=True)
+        ap.add_argument("--stats", required=True)
+        ap.add_argument("--trace", required=True)
+        ap.add_argument("--commands", required=True)
+        ap.add_argument("--top", type=int, default=20)
+        ap.add_argument("--note")
+        ap.add_argument("--out", required=True)
+        kernels(ap.parse_args())
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("mode", choices=["report"])
