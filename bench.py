@@ -38,14 +38,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--nx", type=int, default=256)
-    ap.add_argument("--ny", type=int, default=256)
-    ap.add_argument("--nz", type=int, default=64)
+    ap.add_argument("--nx", type=int, default=None, help="grid (default 256 x 256 x 64; area: 512 x 512 x 64)")
+    ap.add_argument("--ny", type=int, default=None)
+    ap.add_argument("--nz", type=int, default=None)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-modes", type=int, default=4096,
                     help="modes of the oracle sample for the CPU baseline")
-    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch", "rough"],
+    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch", "rough", "area"],
                     help="operator: the fused operator (the headline line); serve: Poisson-arrival "
                          "elastoplastic solves of mixed grids through the batching server; solve: the "
                          "32x32x16 paraboloid elastoplastic solve; copy: a plain device copy of known size "
@@ -71,7 +71,16 @@ def parse():
     ap.add_argument("--inner-rel", type=float, default=0.1,
                     help="solve/serve/rough: inexact plasticity solves to inner_rel x the outer error "
                          "(0 = always to tol_plastic)")
-    return ap.parse_args()
+    ap.add_argument("--slopes", default="0.25,0.5,1.0",
+                    help="area: rms slopes of the rough surface to run (comma separated)")
+    ap.add_argument("--load-steps", type=int, default=5, help="area: equal cumulative load steps")
+    ap.add_argument("--seed", type=int, default=0, help="area: seed of the rough surface")
+    a = ap.parse_args()
+    dflt = (512, 512, 64) if a.workload == "area" else (256, 256, 64)
+    a.nx = a.nx or dflt[0]
+    a.ny = a.ny or dflt[1]
+    a.nz = a.nz or dflt[2]
+    return a
 
 
 def stage_bytes(nx, ny, nz, csize=16, rsize=8):
@@ -279,6 +288,74 @@ def bench_rough(a):
     print(json.dumps(out))
 
 
+def bench_area(a):
+    """The paper's rough-surface experiment (its Sec. on rough surface
+    contact and the appendix on the surface): elastic and elastoplastic
+    contact of the same self-affine surface under the same load, compared by
+    contact area.  Domain L x L x 0.4 L on nx x ny x nz nodes (512 x 512 x 64);
+    Hurst exponent 0.8, PSD plateau for 1 <= |k| < 2 (lambda_l = L, lambda_l /
+    lambda_r = 2), power law up to |k| = nx / 4 (lambda_s = 4 dx); E = 1,
+    nu = 0.3, sigma_y = 0.1 E, E_h = 0.01 E; load W = 1e-3 E h'_rms L^2 in
+    --load-steps equal cumulative steps; Algorithm 1 with lambda = 0.3 and
+    outer tolerance 1e-7.  The paper does not give the rms slope h'_rms: the
+    load is proportional to it, but yielding depends on its absolute value
+    against sigma_y, so the run sweeps --slopes.  Reports the contact area
+    fractions, their ratio and the solve times per slope."""
+    import torch
+    from paper_1811_11558_amd import Context, EPOptions
+    from synth import grid_dict, rough_surface
+    E, NU, SY, EH = 1.0, 0.3, 0.1, 0.01
+    g = grid_dict(a.nx, a.ny, a.nz, 1.0, 1.0, 0.4)
+    kcut = a.nx // 4
+    opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=4000,
+                     max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
+                     inner_rel=a.inner_rel)
+    rows = []
+    for slope in [float(x) for x in a.slopes.split(",")]:
+        h = torch.from_numpy(rough_surface(a.nx, a.ny, hurst=0.8, k_roll=2, k_cut=kcut, rms_slope=slope,
+                                           seed=a.seed)).cuda()
+        W = 1e-3 * E * slope
+        ctx = Context(g, E, NU, SY, EH, precision=a.precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_el, _, cinfo = ctx.contact_solve(h, W, tol=1e-12, max_iter=50000)
+        torch.cuda.synchronize()
+        t_el = time.perf_counter() - t0
+        st = ctx.new_state()
+        Ws = [W * (i + 1) / a.load_steps for i in range(a.load_steps)]
+        t0 = time.perf_counter()
+        infos = []
+        for k, Wk in enumerate(Ws):           # one step per call: the state carries over
+            infos += ctx.elastoplastic_solve(h, [Wk], st, opts)
+            torch.cuda.synchronize()
+            print("slope %g step %d/%d: %d outer passes, %.1f s" % (slope, k + 1, len(Ws),
+                  infos[-1]["outer_iters"], time.perf_counter() - t0), file=sys.stderr, flush=True)
+        t_ep = time.perf_counter() - t0
+        a_el = float((p_el > 0).double().mean().item())
+        p_ep = st["traction"][2]
+        a_ep = float((p_ep > 0).double().mean().item())
+        row = {"rms_slope": slope, "W": W, "area_elastic": a_el, "area_elastoplastic": a_ep,
+               "area_ratio": a_ep / a_el if a_el > 0 else None,
+               "max_p_elastic_over_sy": float(p_el.max().item()) / SY,
+               "max_p_elastoplastic_over_sy": float(p_ep.max().item()) / SY,
+               "plastic_voxels": float((st["ep"] > 0).double().mean().item()),
+               "elastic_s": t_el, "elastoplastic_s": t_ep, "contact_iters": cinfo["iters"],
+               "outer_iters": [i["outer_iters"] for i in infos],
+               "residual_evals": sum(i["r_evals"] for i in infos)}
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        rows.append(row)
+        ctx.close()
+    print(json.dumps({"metric": "elastoplastic / elastic contact area", "unit": "ratio",
+                      "value": rows[-1]["area_ratio"], "higher_is_better": None, "n_gpus": 1, "data": "synthetic",
+                      "dtype": "f64" if a.precision == "fp64" else "f32+f64",
+                      "config": {"workload": "rough-surface contact area %dx%dx%d, lz = 0.4 L" % (a.nx, a.ny, a.nz),
+                                 "hurst": 0.8, "k_roll": 2, "k_cut": kcut, "sigma_y": SY, "E_h": EH, "nu": NU,
+                                 "load": "1e-3 E h'_rms", "load_steps": a.load_steps, "tol_outer": 1e-7,
+                                 "relax": 0.3, "anderson": a.anderson, "warm_start": a.warm,
+                                 "inner_rel": a.inner_rel, "seed": a.seed, "precision": a.precision},
+                      "runs": rows}))
+
+
 def bench_solve(a):
     """Elastoplastic paraboloid solve, 32 x 32 x 16 (R = 0.5 L, lz = 0.25 L,
     E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1), cumulative loads up to
@@ -376,6 +453,8 @@ def main():
         return bench_batch(a)
     if a.workload == "rough":
         return bench_rough(a)
+    if a.workload == "area":
+        return bench_area(a)
     if a.workload == "solve":
         return bench_solve(a)
     if a.workload == "serve":

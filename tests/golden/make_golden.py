@@ -15,14 +15,24 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
+from oracle import contact as oc  # noqa: E402
 from oracle import coupling as cp  # noqa: E402
-from synth import grid_dict, paraboloid  # noqa: E402
+from synth import grid_dict, paraboloid, rough_surface  # noqa: E402
 
 CASES = {
     # paraboloid R = 2 L on 16 x 16 x 8 (lz = 0.25 L), E = 1, nu = 0.3,
     # sigma_y0 = 0.01, E_h = 0.1; two cumulative loads with Hertz peak
     # pressures of about 2 and 3 times the first-yield pressure 1.6 sigma_y0
-    "hertz_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3),
+    "hertz_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
+                             mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1)),
+    # the rough-surface experiment's geometry and material (Sec. on rough
+    # surface contact and its appendix: lz = 0.4 L, H = 0.8, PSD plateau for
+    # 1 <= |k| < 2, sigma_y = 0.1 E, E_h = 0.01 E) on 16 x 16 x 8: cut-off
+    # k = 4, rms slope 0.5, seed 3, two cumulative mean pressures up to
+    # 0.01 E (mean contact pressure about 2.5 sigma_y); the elastic contact
+    # solution under the final load is stored as well
+    "rough_ep_16x16x8": dict(grid=(16, 16, 8, 0.4), rough=dict(hurst=0.8, k_roll=2, k_cut=4, rms_slope=0.5, seed=3),
+                             W=[0.005, 0.01], relax=0.3, mat=dict(E=1.0, nu=0.3, sigma_y0=0.1, E_h=0.01)),
 }
 # Standard under-relaxation (the printed overwrite of the relaxed update
 # oscillates on these cases; see the design notes).
@@ -34,8 +44,15 @@ def run(name):
     c = CASES[name]
     nx, ny, nz, lz = c["grid"]
     g = grid_dict(nx, ny, nz, lz=lz)
-    mat = dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1)
-    h = paraboloid(g, R=c["R"])
+    mat = c["mat"]
+    if "rough" in c:
+        h = rough_surface(nx, ny, **c["rough"])
+    else:
+        h = paraboloid(g, R=c["R"])
+    extra = {}
+    if "rough" in c:
+        p_el, _, _ = oc.contact_solve(h, c["W"][-1], g, mat["E"], mat["nu"], tol=1e-15, max_iter=20000)
+        extra["p_elastic"] = p_el
     st = cp.new_state(g)
     t0 = time.time()
     infos = cp.elastoplastic_solve(g, mat, h, c["W"], st, relax=c["relax"], **OPTS)
@@ -45,7 +62,7 @@ def run(name):
                            "outer_err": [i["outer_err"] for i in infos],
                            "plastic": [i["plastic"] for i in infos]})])
     np.savez_compressed(os.path.join(HERE, name + ".npz"), h=h, W=np.array(c["W"]), meta=meta,
-                        **{k: v for k, v in st.items()})
+                        **{k: v for k, v in st.items()}, **extra)
     print(name, "%.1f s" % dt, [i["outer_iters"] for i in infos])
 
 

@@ -165,6 +165,50 @@ def test_anderson_outer_reaches_the_stored_fixed_point():
         assert err < 1e-8, (k, err)
 
 
+ROUGH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rough_ep_16x16x8.npz")
+
+
+@pytest.mark.parametrize("precision,accel", [("fp64", False), ("fp32_refined", True)])
+def test_rough_surface_experiment_setting_matches_stored_oracle(precision, accel):
+    """The rough-surface experiment's geometry and material (lz = 0.4 L,
+    sigma_y = 0.1 E, E_h = 0.01 E, H = 0.8, PSD plateau for 1 <= |k| < 2) on a
+    16 x 16 x 8 grid, stored by tests/golden/make_golden.py: the GPU's
+    elastic contact pressure under the final load and its Algorithm 1 state
+    reproduce the oracle's, and so do both contact areas.  In float64 with
+    the oracle's relaxation the bound is rounding (1e-11); with FP32 kernels
+    and the accelerated outer/inner iteration it is what the tolerances
+    allow (1e-8)."""
+    from paper_1811_11558_amd import Context, EPOptions
+    ref = np.load(ROUGH)
+    g = grid_dict(16, 16, 8, lz=0.4)
+    ctx = Context(g, 1.0, 0.3, 0.1, 0.01, precision=precision)
+    h = torch.from_numpy(ref["h"]).cuda()
+    W = list(ref["W"])
+    p_el, _, _ = ctx.contact_solve(h, W[-1], tol=1e-15, max_iter=20000)
+    torch.cuda.synchronize()
+    p_el = p_el.cpu().numpy()
+    err = _rel(p_el, ref["p_elastic"])
+    _say(precision, "elastic pressure", err)
+    assert err < 1e-11
+    st = ctx.new_state()
+    opts = (EPOptions(tol_outer=1e-12, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000,
+                      anderson_m=5, warm_start=1, inner_rel=0.1) if accel else
+            EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000))
+    infos = ctx.elastoplastic_solve(h, W, st, opts)
+    torch.cuda.synchronize()
+    _say(precision, [(i["outer_iters"], i["r_evals"]) for i in infos])
+    bound = 1e-8 if accel else 1e-11
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < bound, (k, err)
+    a_el, a_ep = int((p_el > 0).sum()), int((st["traction"][2].cpu().numpy() > 0).sum())
+    _say("contact points elastic / elastoplastic", a_el, a_ep)
+    assert a_el == int((ref["p_elastic"] > 0).sum())
+    assert a_ep == int((ref["traction"][2] > 0).sum())
+    ctx.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
 def test_warm_inexact_inner_solves_reach_the_stored_fixed_point(precision):
     """Plasticity solves warm-started from the previous outer pass and solved
