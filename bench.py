@@ -83,27 +83,38 @@ def parse():
     return a
 
 
-def stage_bytes(nx, ny, nz, csize=16, rsize=8):
+def stage_bytes(nx, ny, nz, csize=16, rsize=8, replicas=True):
     """Algorithmic bytes per launch of each stage of the fused application:
     the 6 nz eigenstrain planes and the 3 traction planes are transformed
-    together (pin = 6 nz + 3 planes in), 6 nz strain planes come out."""
+    together (pin = 6 nz + 3 planes in), 6 nz strain planes come out.  With
+    replicas (the default launch), the main depth launch also reads the
+    Nyquist modes' spectra once and writes one record per sign replica, and
+    depth_nyq averages those records into the Nyquist modes; without (side
+    stream), depth_nyq evaluates the Nyquist modes itself."""
     kxh = nx // 2 + 1
     nm = kxh * ny
     nnyq = ny + kxh - 1                    # modes with kx = nx/2 or ky = ny/2
+    nrep = 2 * (ny + kxh)                  # their sign replicas
     pin, pout = 6 * nz + 3, 6 * nz
     per_mode = (pin + pout) * csize        # spectra in, strain spectrum out
+    if replicas:
+        depth = (nm - nnyq) * per_mode + nnyq * pin * csize + nrep * pout * csize
+        nyq = nrep * pout * csize + nnyq * pout * csize
+    else:
+        depth = (nm - nnyq) * per_mode
+        nyq = nnyq * per_mode
     return {
         "x_fwd": pin * nx * ny * rsize + pin * nm * csize,
         "y_fwd": 2 * pin * nm * csize,
-        "depth": (nm - nnyq) * per_mode,
-        "depth_nyq": nnyq * per_mode,
+        "depth": depth,
+        "depth_nyq": nyq,
         "y_inv": 2 * pout * nm * csize,
         "x_inv": pout * nm * csize + pout * nx * ny * rsize,
     }
 
 
 KERNEL_OF_STAGE = {"x_fwd": "k_x_r2c", "y_fwd": "k_y_fwd", "depth": "k_depth",
-                   "depth_nyq": "k_depth (Nyquist modes)", "y_inv": "k_y_inv", "x_inv": "k_x_c2r"}
+                   "depth_nyq": "k_nyq_average", "y_inv": "k_y_inv", "x_inv": "k_x_c2r"}
 
 
 def measured_traffic(stage, nx, ny, nz, precision):
@@ -503,7 +514,7 @@ def main():
     value = V / (ms_per_step * 1e-3)
 
     csize = 16 if a.precision == "fp64" else 8
-    sb = stage_bytes(a.nx, a.ny, a.nz, csize=csize)
+    sb = stage_bytes(a.nx, a.ny, a.nz, csize=csize, replicas=not a.side_stream)
     stages = {}
     for k, (ms, n) in st.items():
         if n:

@@ -224,7 +224,9 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   if (eps_p) { iseg.first[iseg.n] = 0; iseg.ptr[iseg.n++] = eps_p; }
   if (traction) { iseg.first[iseg.n] = prm.off_t; iseg.ptr[iseg.n++] = traction; }
   const size_t planes = (size_t)std::max(prm.ld_out, prm.ld_in);
-  const size_t bytes = planes * nmodes * sizeof(cpx<T>);
+  // the depth pass writes E to A; the Nyquist sign-replica records follow it
+  const size_t nrep = (size_t)depth_replicas(ny, kxh);
+  const size_t bytes = (planes * nmodes + nrep * (size_t)prm.ld_out) * sizeof(cpx<T>);
   int rc = ctx_reserve(c, &c->bufA, &c->bufA_bytes, bytes);
   if (rc) return rc;
   rc = ctx_reserve(c, &c->bufB, &c->bufB_bytes, bytes);
@@ -253,6 +255,9 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   P.twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
   P.A = (cpx<T>*)c->bufA;
   P.B = (cpx<T>*)c->bufB;
+  // with the side stream the Nyquist modes keep a launch of their own, which
+  // can run beside the main one; otherwise their sign replicas join it
+  prm.rep_out = c->use_side ? nullptr : (void*)(P.A + nmodes * (size_t)prm.ld_out);
   return FVIM_OK;
 }
 
@@ -360,6 +365,7 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
     for (int k = 0; k < b.n; ++k) {
       const DepthParams& p = P[i0 + k].prm;
       b.prm[k] = p;
+      b.prm[k].rep_out = nullptr;        // the batched launches keep the Nyquist kernel
       depth_derive(b.prm[k]);
       b.in[k] = P[i0 + k].B;
       b.out[k] = P[i0 + k].A;
@@ -550,7 +556,7 @@ size_t fvim_footprint_bytes(const fvim_grid* g, int precision, int with_solver_s
   // the solvers of the FP32_REFINED mode also apply the float64 operator
   const size_t csz = (precision == FVIM_FP32_REFINED && !with_solver_state) ? 8 : 16;
   const size_t planes = 15 * (size_t)g->nz + 16;   // largest record, padded to 128 B
-  size_t b = 2 * planes * nmodes * csz;
+  size_t b = 2 * planes * (nmodes + (size_t)depth_replicas(g->ny, g->nx / 2 + 1)) * csz;
   b += nmodes * (sizeof(ModeConst<double>) + (precision == FVIM_FP32_REFINED ? sizeof(ModeConst<float>) : 0));
   const size_t V = (size_t)g->nx * g->ny * g->nz;
   if (with_solver_state) b += solver_footprint(g, V);

@@ -150,20 +150,37 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
   const int l = threadIdx.x - g * LPM;
   const int gid = block * GPB + g;
   int kx, ky;
+  // vrep >= 0: this group evaluates sign replica vrep of a Nyquist mode,
+  // unweighted, into replica record vslot of prm.rep_out.  Replica records:
+  // 2 j, 2 j + 1 for Nyquist mode j (the kx = nx/2 column first, then the
+  // ky = ny/2 row), then replicas 2 and 3 of the corner
+  int vrep = -1, vslot = 0;
   if (NYQ) {
     if (gid >= prm.ny + prm.kxh - 1) return;
     if (gid < prm.ny) { kx = prm.nx / 2; ky = gid; }
     else { kx = gid - prm.ny; ky = prm.ny / 2; }
   } else {
-    if (gid >= prm.kxh * prm.ny) return;       // the whole lane group leaves together
-    kx = gid / prm.ny;
-    ky = gid - kx * prm.ny;
-    if (kx * 2 == prm.nx || ky * 2 == prm.ny) return;
+    const int nmain = prm.kxh * prm.ny;
+    if (gid >= nmain) {
+      vslot = gid - nmain;
+      const int mn = prm.ny + prm.kxh - 1;
+      if (!prm.rep_out || vslot >= 2 * mn + 2) return;   // the whole lane group leaves together
+      int j;
+      if (vslot < 2 * mn) { j = vslot >> 1; vrep = vslot & 1; }
+      else { j = prm.ny / 2; vrep = 2 + (vslot - 2 * mn); }
+      if (j < prm.ny) { kx = prm.nx / 2; ky = j; }
+      else { kx = j - prm.ny; ky = prm.ny / 2; }
+    } else {
+      kx = gid / prm.ny;
+      ky = gid - kx * prm.ny;
+      if (kx * 2 == prm.nx || ky * 2 == prm.ny) return;
+    }
   }
   const int mode = kx * prm.ny + ky;
   const int nz = prm.nz;
   const cpx<T>* __restrict__ src = in + (size_t)mode * prm.ld_in;
-  cpx<T>* __restrict__ dst = out + (size_t)mode * prm.ld_out;
+  cpx<T>* __restrict__ dst = vrep >= 0 ? static_cast<cpx<T>*>(prm.rep_out) + (size_t)vslot * prm.ld_out
+                                       : out + (size_t)mode * prm.ld_out;
   const T nrm = (T)prm.norm;
   const T kap = (T)prm.kappa;
   const T mu = (T)prm.mu;
@@ -234,9 +251,10 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     return;
   }
 
-  const int nyqx = NYQ && (kx * 2 == prm.nx);
-  const int nyqy = NYQ && (ky * 2 == prm.ny);
+  const int nyqx = (NYQ || vrep >= 0) && (kx * 2 == prm.nx);
+  const int nyqy = (NYQ || vrep >= 0) && (ky * 2 == prm.ny);
   const int nrep = NYQ ? (nyqx ? 2 : 1) * (nyqy ? 2 : 1) : 1;
+  const int rep0 = vrep >= 0 ? vrep : 0;
   const int k1 = kx;
   const int k2 = (ky * 2 <= prm.ny) ? ky : ky - prm.ny;
   const T wrep = nrep == 1 ? T(1) : (nrep == 2 ? T(0.5) : T(0.25));
@@ -255,7 +273,7 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
   for (int k = 1; k < P; ++k) rP *= r;
   const T G0 = K.G0, G0p = K.G0p, H0 = K.H0, H0p = K.H0p;
 
-  for (int rep = 0; rep < nrep; ++rep) {
+  for (int rep = rep0; rep < rep0 + nrep; ++rep) {
     int bits = rep;
     T s1 = T(1), s2 = T(1);
     if (nyqx) { s1 = (bits & 1) ? T(-1) : T(1); bits >>= 1; }
@@ -430,18 +448,18 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         e[3] = add(scl(exz, n2), scl(eez, n1));
         e[4] = sub(scl(exz, n1), scl(eez, n2));
         e[5] = add(scl(exx, n1 * n2), scl(exe, n1 * n1 - n2 * n2));
-        emit(i, e, rep == 0, wrep);
+        emit(i, e, rep == rep0, wrep);
         if (DISP) {
           cpx<T> c = sub(sub(scl(sub(m2, m0), T(0.5)), scl(m1, ik2)), scl(m3, ik2));
           cpx<T> U = mul_i(scl(a, iq));
           cpx<T> V = scl(v, iq);
           cpx<T> W = scl(c, iq);
           if (prm.off_disp >= 0) {
-            put(dst + prm.off_disp + i, scl(sub(scl(U, n1), scl(V, n2)), wrep), rep == 0);
-            put(dst + prm.off_disp + (size_t)nz + i, scl(add(scl(U, n2), scl(V, n1)), wrep), rep == 0);
-            put(dst + prm.off_disp + (size_t)2 * nz + i, scl(W, wrep), rep == 0);
+            put(dst + prm.off_disp + i, scl(sub(scl(U, n1), scl(V, n2)), wrep), rep == rep0);
+            put(dst + prm.off_disp + (size_t)nz + i, scl(add(scl(U, n2), scl(V, n1)), wrep), rep == rep0);
+            put(dst + prm.off_disp + (size_t)2 * nz + i, scl(W, wrep), rep == rep0);
           }
-          if (prm.off_u3 >= 0 && i == 0) put(dst + prm.off_u3, scl(W, wrep), rep == 0);
+          if (prm.off_u3 >= 0 && i == 0) put(dst + prm.off_u3, scl(W, wrep), rep == rep0);
         }
       }
     }
@@ -464,6 +482,34 @@ __global__ __launch_bounds__(NT) void k_depth_batch(const DepthBatch* __restrict
   while (c + 1 < b->n && (int)blockIdx.x >= first[c + 1]) ++c;
   depth_modes<T, LPM, P, DISP, WANTX, NYQ>(static_cast<const cpx<T>*>(b->in[c]), static_cast<cpx<T>*>(b->out[c]),
                                            b->prm[c], (int)blockIdx.x - first[c]);
+}
+
+// Nyquist mode j (one block each) <- the weighted sum of its sign replicas,
+// in the order and with the weights (1/2, or 1/4 at the corner) of the
+// replica loop of the NYQ kernel.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_nyq_average(cpx<T>* __restrict__ out, const cpx<T>* __restrict__ rep,
+                                                   int nx, int ny, int kxh, int ld, int np) {
+  const int j = blockIdx.x;
+  const int mn = ny + kxh - 1;
+  int kx, ky;
+  if (j < ny) { kx = nx / 2; ky = j; }
+  else { kx = j - ny; ky = ny / 2; }
+  const bool corner = kx * 2 == nx && ky * 2 == ny;
+  const T w = corner ? T(0.25) : T(0.5);
+  const cpx<T>* r0 = rep + (size_t)(2 * j) * ld;
+  const cpx<T>* r1 = r0 + ld;
+  const cpx<T>* r2 = rep + (size_t)(2 * mn) * ld;
+  const cpx<T>* r3 = r2 + ld;
+  cpx<T>* dst = out + (size_t)(kx * ny + ky) * ld;
+  for (int c = threadIdx.x; c < np; c += NT) {
+    cpx<T> v = add(scl(r1[c], w), scl(r0[c], w));
+    if (corner) {
+      v = add(scl(r2[c], w), v);
+      v = add(scl(r3[c], w), v);
+    }
+    dst[c] = v;
+  }
 }
 
 template <typename T>
@@ -497,15 +543,20 @@ template <typename T, int LPM, int P, bool DISP, bool WANTX>
 hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipStream_t st,
                       int part) {
   constexpr int GPB = NT / LPM;
+  const int nnyq = p.ny + p.kxh - 1;
   if (part != 2) {
-    const int nmodes = p.kxh * p.ny;
+    const int nmodes = p.kxh * p.ny + (p.rep_out ? depth_replicas(p.ny, p.kxh) : 0);
     const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
     hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, out, p);
   }
   if (part != 1) {
-    const int nnyq = p.ny + p.kxh - 1;
-    const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
-    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, out, p);
+    if (p.rep_out) {
+      hipLaunchKernelGGL(k_nyq_average<T>, dim3((unsigned)nnyq), dim3(NT), 0, st, out,
+                         static_cast<const cpx<T>*>(p.rep_out), p.nx, p.ny, p.kxh, p.ld_out, p.np_out);
+    } else {
+      const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
+      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, out, p);
+    }
   }
   return hipGetLastError();
 }

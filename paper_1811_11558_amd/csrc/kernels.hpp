@@ -67,6 +67,11 @@ struct DepthParams {
   int np_out, ld_out;
   int off_strain, off_stress, off_disp, off_u3;
   const void* mtab;       // ModeConst<T>[kxh * ny] of this grid (launch_mode_table)
+  // Nyquist modes: NULL -> a second launch averages each mode's 2 or 4 sign
+  // replicas in turn; else the main launch evaluates every replica as a
+  // mode of its own into depth_replicas(ny, kxh) records of stride ld_out
+  // here, and the second launch averages them
+  void* rep_out;
   // ratios of kappa, filled by launch_depth: 1/(kappa+2), (kappa+1)/(kappa+2),
   // 1/(2(kappa+2)), kappa/(kappa+2), (kappa+2)/(2(kappa+1)), 1/(2 kappa+2)
   double ikp2, kk, i2k4, kapkp2, cfac, ik2;
@@ -97,6 +102,9 @@ struct DepthBatch {
   void* out[DEPTH_BATCH_MAX];
 };
 void depth_derive(DepthParams& p);
+// Sign replicas of the Nyquist modes: 2 for each of the ny + kxh - 1 modes on
+// the kx = nx/2 column or the ky = ny/2 row, 2 more for the corner.
+inline int depth_replicas(int ny, int kxh) { return 2 * (ny + kxh); }
 int depth_groups_per_block(int cfg);
 template <typename T>
 hipError_t launch_depth_batch(const DepthBatch& host, DepthBatch* dtab, int cfg, hipStream_t st);

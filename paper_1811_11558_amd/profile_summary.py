@@ -126,7 +126,8 @@ def report(a):
     raw_r = dispatches(a.raw_read) if a.raw_read else None
     raw_w = dispatches(a.raw_write) if a.raw_write else None
 
-    st, depth_keys = stage_keys(fetch.keys())
+    keys = list(fetch.keys())
+    st, depth_keys = stage_keys(keys)
     # depth: the layout with the most launches in the timing run (the trace)
     # is the tuned one (every layout also runs during tuning in the counter
     # runs); Nyquist launches are the instances whose last flag is true
@@ -144,6 +145,10 @@ def report(a):
             ks = [k for k in depth_keys if k[0] == best]
             if ks:
                 st[stage] = ks[0]
+    # the Nyquist stage of the default launch averages the sign replicas
+    avg = [k for k in keys if k[0].startswith("k_nyq_average")]
+    if avg:
+        st["depth_nyq"] = avg[0]
 
     lines = ["Copy reference `%s`: %d bytes read and %d written per launch; FETCH_SIZE reads %.1f and "
              "WRITE_SIZE %.1f, so %.1f bytes per FETCH_SIZE unit and %.1f per WRITE_SIZE unit."

@@ -196,6 +196,35 @@ def test_every_depth_layout_matches_oracle(nz):
     assert 0 <= ctx.get_option(ctx.OPT_DEPTH_CONFIG) < 8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_nyquist_replicas_in_main_launch_equal_separate_launch(precision):
+    """The default launch evaluates each Nyquist mode's sign replicas as
+    modes of the main depth launch and averages them afterwards; with the
+    side stream on, a launch of its own sums them in turn.  Both give the
+    oracle's result, and agree with each other to rounding, on every output
+    (stress and displacement included) and on a grid with the corner mode."""
+    g = grid_dict(32, 16, 12, 1.0, 0.5, 0.3)
+    eps = filtered_eigenstrain(g, seed=7)
+    t = filtered_traction(g, seed=8)
+    ref = ora.apply(g, E, NU, eps_p=eps, traction=t)
+    ctx = _ctx(g, precision=precision)
+    e_d, t_d = torch.from_numpy(eps).cuda(), torch.from_numpy(t).cuda()
+    want = ("strain", "stress", "disp", "surf_u3")
+    outs = {}
+    for side in (0, 1):
+        ctx.set_option(ctx.OPT_SIDE_STREAM, side)
+        outs[side] = {k: v.cpu().numpy() for k, v in ctx.operator_apply(e_d, t_d, want=want).items()}
+        torch.cuda.synchronize()
+    tol = TOL if precision == "fp64" else 2e-6
+    for k in want:
+        for side in (0, 1):
+            err = _rel(outs[side][k], ref[k])
+            assert err <= tol, (side, k, err)
+        d = _rel(outs[0][k], outs[1][k])
+        _say(precision, k, "replicas in main launch vs separate launch", d)
+        assert d <= (1e-14 if precision == "fp64" else 1e-6), (k, d)
+
+
 BATCH = [(16, 16, 9, 1.0, 1.0, 0.3), (32, 16, 16, 1.0, 0.5, 0.25), (64, 64, 33, 1.0, 1.0, 0.25),
          (8, 32, 5, 0.5, 1.0, 0.2)]
 
