@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="serve: concurrent request slots")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrivals per second (0 = all at once)")
+    ap.add_argument("--streaming", type=int, default=2, choices=[0, 1, 2],
+                    help="operator: streaming loads for last-use reads (0 off, 1 on, 2 by spectrum size)")
     ap.add_argument("--side-stream", type=int, default=0,
                     help="operator: 1 runs the traction transforms and Nyquist depth launch on a second stream")
     ap.add_argument("--hurst", type=float, default=0.8, help="rough: Hurst exponent")
@@ -485,6 +487,7 @@ def main():
     ctx = Context(g, 1.0, 0.3, precision=a.precision, stream=stream)
     out = {"strain": strain}
     ctx.set_option(ctx.OPT_SIDE_STREAM, a.side_stream)
+    ctx.set_option(ctx.OPT_STREAMING, a.streaming)
     ctx.tune()                      # first warm-up call times the depth-pass layouts
     for _ in range(a.warmup):
         ctx.operator_apply(eps, trac, out=out)
@@ -546,7 +549,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD if (a.nx, a.ny, a.nz, a.precision) == (256, 256, 64, "fp64") else
                    "operator %dx%dx%d %s" % (a.nx, a.ny, a.nz, a.precision),
-                   "nx": a.nx, "ny": a.ny, "nz": a.nz, "lz": 0.25, "nu": 0.3, "precision": a.precision},
+                   "nx": a.nx, "ny": a.ny, "nz": a.nz, "lz": 0.25, "nu": 0.3, "precision": a.precision, "streaming": a.streaming},
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),
         "operator_hbm_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

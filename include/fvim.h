@@ -263,9 +263,16 @@ int fvim_set_timing(fvim_ctx* ctx, int on);
  * captured once as a HIP graph and replayed (same kernels, same results; 0
  * launches the kernels one by one).  FVIM_OPT_SIDE_STREAM (default 0): 1 runs
  * the Nyquist-mode depth launch on a second library stream beside the main
- * depth launch (same results).
+ * depth launch (same results).  FVIM_OPT_STREAMING (default 2): each operator
+ * launch reads its input spectrum for the last time; 1 does so with streaming
+ * (non-temporal) loads, which keep the previous launch's output in the
+ * caches for the next one; 0 never; 2 when the spectrum buffer of the
+ * application is larger than 64 MiB and at most 256 MiB (it then fits the
+ * last-level cache), where that measured faster on MI355X (same results
+ * either way).
  */
-enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3, FVIM_OPT_SIDE_STREAM = 4 };
+enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3, FVIM_OPT_SIDE_STREAM = 4,
+       FVIM_OPT_STREAMING = 5 };
 int fvim_set_option(fvim_ctx* ctx, int key, int value);
 int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);

@@ -201,7 +201,7 @@ class Context:
 
     STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv", "depth_nyq")
 
-    OPT_DEPTH_CONFIG, OPT_TUNE, OPT_GRAPHS, OPT_SIDE_STREAM = 1, 2, 3, 4
+    OPT_DEPTH_CONFIG, OPT_TUNE, OPT_GRAPHS, OPT_SIDE_STREAM, OPT_STREAMING = 1, 2, 3, 4, 5
 
     def set_option(self, key, value):
         _check(_LIB.fvim_set_option(self._h, int(key), int(value)))

@@ -19,6 +19,39 @@ __device__ __forceinline__ cpx<T> mk(T a, T b) {
   r.y = b;
   return r;
 }
+// Loads that mark the line as streaming (non-temporal): for data a kernel
+// reads for the last time, so that it does not displace what the next kernel
+// will read (the previous kernel's output) from the caches.
+template <typename T>
+struct nt_vec;
+template <>
+struct nt_vec<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <>
+struct nt_vec<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_nt(const cpx<T>* p) {
+  typedef typename nt_vec<T>::type V;
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  cpx<T> r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+// a load that streams when NT is set
+template <bool NT, typename T>
+__device__ __forceinline__ cpx<T> ld_in(const cpx<T>* p) {
+  if constexpr (NT) return ld_nt(p);
+  else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ double2 ld_in(const double2* p) {
+  if constexpr (NT) {
+    const cpx<double> v = ld_nt(reinterpret_cast<const cpx<double>*>(p));
+    return make_double2(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
 template <typename T>
 __device__ __forceinline__ cpx<T> add(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
 template <typename T>

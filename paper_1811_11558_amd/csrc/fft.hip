@@ -163,7 +163,7 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T
 // X[(plane * kxh + k) * ny + y].
 // If bsum is not NULL, block b also writes the float64 sum of its R rows to
 // bsum[b] (the plane means of the mean mode are then formed in float64).
-template <typename T, int LOGN>
+template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
                                              const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
   constexpr int N = 1 << LOGN;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
-    if (i < tot) v[u] = src[i];
+    if (i < tot) v[u] = ld_in<NTL>(src + i);
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -240,7 +240,7 @@ __device__ __forceinline__ int xcd_block() {
 // with copies of it (never stored), so every load is unconditional: with
 // conditional loads the staging array was not kept in registers and went
 // through scratch memory, doubling the kernel's memory traffic.
-template <typename T, int LOGN>
+template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
                                              int NP, int ldp, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
     const int i = threadIdx.x + u * NT;
     const int b = i >> LOGN, y = i & (N - 1);
     const int bc = b < nb ? b : nb - 1;
-    v[u] = in[((size_t)(p0 + bc) * kxh + kx) * N + y];
+    v[u] = ld_in<NTL>(in + ((size_t)(p0 + bc) * kxh + kx) * N + y);
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
 }
 
 // Inverse column transform: S[kx][ky][p] -> X[p][kx][y].
-template <typename T, int LOGN>
+template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
                                              int NP, int ldp, const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
     const int i = threadIdx.x + u * NT;
     const int ky = i / B, b = i - ky * B;
     const int bc = b < nb ? b : nb - 1;
-    v[u] = in[((size_t)kx * N + ky) * ldp + p0 + bc];
+    v[u] = ld_in<NTL>(in + ((size_t)kx * N + ky) * ldp + p0 + bc);
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
 // Plane p of the input goes to the output segment that contains it.
 // If padd is not NULL, padd[plane] (float64) is added to every output value
 // of that plane (the mean mode computed in float64).
-template <typename T, int LOGN>
+template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
                                              double scale, const cpx<T>* __restrict__ tw,
                                              const double* __restrict__ padd) {
@@ -348,8 +348,8 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
     const int i = min((int)threadIdx.x + u * NT, tot - 1);
     const int k = i >> lhp, pr = i - (k << lhp);
     const size_t a = ((size_t)plane * kxh + k) * ny + y0 + 2 * pr;
-    v0[u] = in[a];
-    v1[u] = in[a + 1];
+    v0[u] = ld_in<NTL>(in + a);
+    v1[u] = ld_in<NTL>(in + a + 1);
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -416,11 +416,13 @@ int x_r2c_blocks_per_plane(int nx, int ny) {
 
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum) {
+                        hipStream_t st, double* bsum, bool stream_in) {
   if (seg.n < 1 || seg.n > 2 || seg.first[0] != 0) return hipErrorInvalidValue;
   int R = rows_per_block(r2c_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L) hipLaunchKernelGGL((k_x_r2c<T, L>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum)
+#define CALL(L)                                                                                        \
+  if (stream_in) hipLaunchKernelGGL((k_x_r2c<T, L, true>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum); \
+  else hipLaunchKernelGGL((k_x_r2c<T, L, false>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
@@ -428,21 +430,23 @@ hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size
 
 template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum) {
+                        hipStream_t st, double* bsum, bool stream_in) {
   InSegments seg;
   seg.n = 1;
   seg.first[0] = seg.first[1] = 0;
   seg.ptr[0] = seg.ptr[1] = in;
-  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum);
+  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum, stream_in);
 }
 
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st) {
+                        hipStream_t st, bool stream_in) {
   if (ldp < NP) return hipErrorInvalidValue;
   int B = cols_per_block<T>(ny);
   dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L) hipLaunchKernelGGL((k_y_fwd<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
+#define CALL(L)                                                                                       \
+  if (stream_in) hipLaunchKernelGGL((k_y_fwd<T, L, true>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw); \
+  else hipLaunchKernelGGL((k_y_fwd<T, L, false>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();
@@ -450,11 +454,13 @@ hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st) {
+                        hipStream_t st, bool stream_in) {
   if (ldp < NP) return hipErrorInvalidValue;
   int B = cols_per_block<T>(ny);
   dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L) hipLaunchKernelGGL((k_y_inv<T, L>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
+#define CALL(L)                                                                                       \
+  if (stream_in) hipLaunchKernelGGL((k_y_inv<T, L, true>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw); \
+  else hipLaunchKernelGGL((k_y_inv<T, L, false>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();
@@ -462,36 +468,38 @@ hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
-                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd) {
+                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd, bool stream_in) {
   int R = rows_per_block(c2r_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd)
+#define CALL(L)                                                                                         \
+  if (stream_in) hipLaunchKernelGGL((k_x_c2r<T, L, true>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd); \
+  else hipLaunchKernelGGL((k_x_c2r<T, L, false>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
 }
 
 template hipError_t launch_x_r2c<double>(const double*, cpx<double>*, int, int, size_t, const cpx<double>*,
-                                         hipStream_t, double*);
+                                         hipStream_t, double*, bool);
 template hipError_t launch_x_r2c<double>(const InSegments&, cpx<double>*, int, int, size_t,
-                                         const cpx<double>*, hipStream_t, double*);
+                                         const cpx<double>*, hipStream_t, double*, bool);
 template hipError_t launch_x_r2c<float>(const InSegments&, cpx<float>*, int, int, size_t, const cpx<float>*,
-                                        hipStream_t, double*);
+                                        hipStream_t, double*, bool);
 template hipError_t launch_x_r2c<float>(const double*, cpx<float>*, int, int, size_t, const cpx<float>*,
-                                        hipStream_t, double*);
+                                        hipStream_t, double*, bool);
 template int x_r2c_blocks_per_plane<double>(int, int);
 template int x_r2c_blocks_per_plane<float>(int, int);
 template hipError_t launch_y_fwd<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
-                                         const cpx<double>*, hipStream_t);
+                                         const cpx<double>*, hipStream_t, bool);
 template hipError_t launch_y_fwd<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
-                                        hipStream_t);
+                                        hipStream_t, bool);
 template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
-                                         const cpx<double>*, hipStream_t);
+                                         const cpx<double>*, hipStream_t, bool);
 template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
-                                        hipStream_t);
+                                        hipStream_t, bool);
 template hipError_t launch_x_c2r<double>(const cpx<double>*, const OutSegments&, int, int, size_t, double,
-                                         const cpx<double>*, hipStream_t, const double*);
+                                         const cpx<double>*, hipStream_t, const double*, bool);
 template hipError_t launch_x_c2r<float>(const cpx<float>*, const OutSegments&, int, int, size_t, double,
-                                        const cpx<float>*, hipStream_t, const double*);
+                                        const cpx<float>*, hipStream_t, const double*, bool);
 
 }  // namespace fvim

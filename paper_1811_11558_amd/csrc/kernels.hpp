@@ -21,23 +21,25 @@ struct InSegments {
 };
 
 // bsum (optional): float64 sum of the rows of each block, blocks of a plane
-// consecutive (x_r2c_blocks_per_plane of them).
+// consecutive (x_r2c_blocks_per_plane of them).  stream_in: the launch reads
+// its input for the last time with streaming (non-temporal) loads (see
+// operator_streaming); every launcher below takes the same flag.
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum = nullptr);
+                        hipStream_t st, double* bsum = nullptr, bool stream_in = false);
 template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum = nullptr);
+                        hipStream_t st, double* bsum = nullptr, bool stream_in = false);
 template <typename T>
 int x_r2c_blocks_per_plane(int nx, int ny);
 // Column transforms between X[p][kx][y] (p < NP) and the mode-major
 // S[kx][ky][ldp] (record stride ldp >= NP; the padding is not touched).
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st);
+                        hipStream_t st, bool stream_in = false);
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st);
+                        hipStream_t st, bool stream_in = false);
 // Record stride of a mode-major spectrum of np planes: a whole number of
 // 128-byte lines, so every mode's record starts on a line.
 template <typename T>
@@ -48,7 +50,8 @@ inline int mode_stride(int np) {
 // padd (optional): float64 constant added to each plane of the output.
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
-                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr);
+                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr,
+                        bool stream_in = false);
 
 // Per-mode depth pass.  Input spectra (unnormalised DFTs) in mode-major
 // layout in[mode][ld_in]: the plastic strain as [6][nz] at offset 0 (if

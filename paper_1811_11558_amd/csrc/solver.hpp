@@ -35,6 +35,7 @@ struct fvim_ctx {
   // optional second stream (default priority) for the Nyquist-mode depth
   // launch beside the main one, with its fork/join events
   int use_side = 0;
+  int streaming = 2;            // FVIM_OPT_STREAMING
   hipStream_t side = nullptr;
   hipEvent_t ev_spec = nullptr, ev_nyq = nullptr;
   size_t bufA_bytes = 0, bufB_bytes = 0, k0buf_bytes = 0;

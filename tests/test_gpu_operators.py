@@ -225,6 +225,29 @@ def test_nyquist_replicas_in_main_launch_equal_separate_launch(precision):
         assert d <= (1e-14 if precision == "fp64" else 1e-6), (k, d)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_streaming_loads_do_not_change_results(precision):
+    """Streaming (non-temporal) loads change only how the transforms read
+    their input: every output is bitwise the same with them forced on and
+    off, and matches the oracle."""
+    g = grid_dict(64, 32, 10, 1.0, 0.5, 0.3)
+    eps = filtered_eigenstrain(g, seed=11)
+    t = filtered_traction(g, seed=12)
+    ref = ora.apply(g, E, NU, eps_p=eps, traction=t)
+    ctx = _ctx(g, precision=precision)
+    e_d, t_d = torch.from_numpy(eps).cuda(), torch.from_numpy(t).cuda()
+    want = ("strain", "stress", "disp", "surf_u3")
+    outs = {}
+    for mode in (0, 1):
+        ctx.set_option(ctx.OPT_STREAMING, mode)
+        outs[mode] = {k: v.cpu().numpy() for k, v in ctx.operator_apply(e_d, t_d, want=want).items()}
+        torch.cuda.synchronize()
+    tol = TOL if precision == "fp64" else 2e-6
+    for k in want:
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+        assert _rel(outs[1][k], ref[k]) <= tol, k
+
+
 BATCH = [(16, 16, 9, 1.0, 1.0, 0.3), (32, 16, 16, 1.0, 0.5, 0.25), (64, 64, 33, 1.0, 1.0, 0.25),
          (8, 32, 5, 0.5, 1.0, 0.2)]
 
