@@ -268,6 +268,7 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   const size_t spec_bytes = planes * nmodes * sizeof(cpx<T>);
   P.nt = c->streaming == 1 ||
          (c->streaming == 2 && spec_bytes > ((size_t)64 << 20) && spec_bytes <= ((size_t)256 << 20));
+  prm.nt_in = P.nt ? 1 : 0;
   return FVIM_OK;
 }
 

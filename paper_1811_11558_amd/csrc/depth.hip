@@ -142,7 +142,7 @@ __device__ __forceinline__ void put(cpx<T>* __restrict__ dst, cpx<T> v, bool fir
 // then the ky = ny/2 row without its kx = nx/2 entry).
 // Block `block` of the pass over one grid (prm): GPB = NT / LPM lane groups,
 // one mode each.
-template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL = false>
 __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                             const DepthParams& prm, int block) {
   constexpr int GPB = NT / LPM;
@@ -287,7 +287,7 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
       const int i = i0 + p;
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = (prm.has_w && i < nz) ? src[(size_t)c * nz + i] : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = (prm.has_w && i < nz) ? ld_in<NTL>(src + (size_t)c * nz + i) : zero<T>();
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
       cpx<T> exx = add(add(scl(ep[0], n1 * n1), scl(ep[5], T(2) * n1 * n2)), scl(ep[1], n2 * n2));
       cpx<T> exe = add(add(scl(ep[0], -n1 * n2), scl(ep[5], n1 * n1 - n2 * n2)), scl(ep[1], n1 * n2));
@@ -466,10 +466,11 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
   }
 }
 
-template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ>
+// NTL: the input spectrum is read with streaming loads (last use)
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL>
 __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                              DepthParams prm) {
-  depth_modes<T, LPM, P, DISP, WANTX, NYQ>(in, out, prm, blockIdx.x);
+  depth_modes<T, LPM, P, DISP, WANTX, NYQ, NTL>(in, out, prm, blockIdx.x);
 }
 
 // Several grids in one launch: block b belongs to the grid c with
@@ -547,7 +548,8 @@ hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipSt
   if (part != 2) {
     const int nmodes = p.kxh * p.ny + (p.rep_out ? depth_replicas(p.ny, p.kxh) : 0);
     const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
-    hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false>), dim3(nb), dim3(NT), 0, st, in, out, p);
+    if (p.nt_in) hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, true>), dim3(nb), dim3(NT), 0, st, in, out, p);
+    else hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, false>), dim3(nb), dim3(NT), 0, st, in, out, p);
   }
   if (part != 1) {
     if (p.rep_out) {
@@ -555,7 +557,7 @@ hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipSt
                          static_cast<const cpx<T>*>(p.rep_out), p.nx, p.ny, p.kxh, p.ld_out, p.np_out);
     } else {
       const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
-      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true>), dim3(nb2), dim3(NT), 0, st, in, out, p);
+      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true, false>), dim3(nb2), dim3(NT), 0, st, in, out, p);
     }
   }
   return hipGetLastError();

@@ -75,6 +75,7 @@ struct DepthParams {
   // mode of its own into depth_replicas(ny, kxh) records of stride ld_out
   // here, and the second launch averages them
   void* rep_out;
+  int nt_in;              // the main launch reads the input with streaming loads
   // ratios of kappa, filled by launch_depth: 1/(kappa+2), (kappa+1)/(kappa+2),
   // 1/(2(kappa+2)), kappa/(kappa+2), (kappa+2)/(2(kappa+1)), 1/(2 kappa+2)
   double ikp2, kk, i2k4, kapkp2, cfac, ik2;
