@@ -548,8 +548,18 @@ hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipSt
   if (part != 2) {
     const int nmodes = p.kxh * p.ny + (p.rep_out ? depth_replicas(p.ny, p.kxh) : 0);
     const unsigned nb = (unsigned)((nmodes + GPB - 1) / GPB);
-    if (p.nt_in) hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, true>), dim3(nb), dim3(NT), 0, st, in, out, p);
-    else hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, false>), dim3(nb), dim3(NT), 0, st, in, out, p);
+    // streaming loads only where a load instruction reads whole lines (one
+    // node per lane): with P > 1 the lanes read every P-th element and the
+    // rest of the line would be fetched again
+    bool streamed = false;
+    if constexpr (P == 1) {
+      if (p.nt_in) {
+        hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, true>), dim3(nb), dim3(NT), 0, st, in, out, p);
+        streamed = true;
+      }
+    }
+    if (!streamed)
+      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, false>), dim3(nb), dim3(NT), 0, st, in, out, p);
   }
   if (part != 1) {
     if (p.rep_out) {

@@ -138,8 +138,13 @@ def report(a):
     else:
         for k in depth_keys:
             launches[k[0]] += len(fetch[k]["FETCH_SIZE"])
-    for stage, flag in (("depth", "false>"), ("depth_nyq", "true>")):
-        names = [n for n in launches if n.startswith("k_depth") and n.endswith(flag)]
+    def nyq_flag(name):
+        # k_depth<T, LPM, P, DISP, WANTX, NYQ, streaming>: the sixth argument
+        args = [x.strip() for x in name[name.index("<") + 1:name.rindex(">")].split(",")]
+        return "true" if len(args) > 5 and args[5] == "true" else "false"
+
+    for stage, flag in (("depth", "false"), ("depth_nyq", "true")):
+        names = [n for n in launches if n.startswith("k_depth<") and nyq_flag(n) == flag]
         if names:
             best = max(names, key=lambda n: launches[n])
             ks = [k for k in depth_keys if k[0] == best]
