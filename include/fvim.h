@@ -244,10 +244,13 @@ enum {
   FVIM_STAGE_YFWD = 1,   /* y transform of the same planes               */
   FVIM_STAGE_XFWD_T = 2, /* unused (the traction planes are part of XFWD) */
   FVIM_STAGE_YFWD_T = 3, /* unused (part of YFWD)                        */
-  FVIM_STAGE_DEPTH = 4,  /* per-mode depth pass, all but Nyquist modes   */
+  FVIM_STAGE_DEPTH = 4,  /* per-mode depth pass (with the sign replicas   */
+                         /* of the Nyquist modes unless the side stream  */
+                         /* is on)                                       */
   FVIM_STAGE_YINV = 5,   /* inverse y transform of the output planes     */
   FVIM_STAGE_XINV = 6,   /* inverse x transform of the output planes     */
-  FVIM_STAGE_DEPTH_NYQ = 7, /* depth pass of the Nyquist modes           */
+  FVIM_STAGE_DEPTH_NYQ = 7, /* Nyquist modes: average of their sign      */
+                            /* replicas (side stream: their depth pass)  */
   FVIM_NSTAGES = 8
 };
 int fvim_set_timing(fvim_ctx* ctx, int on);
