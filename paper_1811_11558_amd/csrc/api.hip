@@ -163,6 +163,7 @@ struct OpPlan {
   int np = 0, np_in = 0, wbpp = 0;
   bool k0x = false;
   bool nt = false;              // launches read their input with streaming loads
+  ResidEpilogue ep{};           // residual epilogue of the inverse x transform
   double* wsum = nullptr;
   double* tsum = nullptr;
   double* padd = nullptr;
@@ -300,7 +301,7 @@ int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
     return fail_hip(e, "y_inv");
   tm.end();
   tm.begin(FVIM_STAGE_XINV, st);
-  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.nt)) != hipSuccess)
+  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.nt, P.ep)) != hipSuccess)
     return fail_hip(e, "x_c2r");
   tm.end();
   return FVIM_OK;
@@ -309,10 +310,11 @@ int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
 // u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
 template <typename T>
 int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
-                     double* disp, double* surf_u3) {
+                     double* disp, double* surf_u3, const ResidEpilogue* ep = nullptr) {
   OpPlan<T> P;
   int rc = op_plan<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P);
   if (rc || P.np == 0) return rc;
+  if (ep) P.ep = *ep;
   hipStream_t st = c->stream;
   const bool side = c->use_side != 0;
   if (side && (rc = side_ensure(c))) return rc;
@@ -393,6 +395,25 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
 }
 
 static bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u); }
+
+int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* traction, const double* x,
+                         const double* Fo, double* R, double* part, int* nparts) {
+  if (misaligned(eps_p) || misaligned(traction) || misaligned(x) || misaligned(Fo) || misaligned(R))
+    return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
+  const ResidEpilogue ep = {x, Fo, part, c->grid.nz};
+  const size_t np = (size_t)6 * c->grid.nz;
+  if (c->precision == FVIM_FP32_REFINED && !c->force_fp64) {
+    *nparts = x_c2r_blocks<float>(c->grid.nx, c->grid.ny, np);
+    return operator_apply_t<float>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep);
+  }
+  *nparts = x_c2r_blocks<double>(c->grid.nx, c->grid.ny, np);
+  return operator_apply_t<double>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep);
+}
+
+int operator_resid_parts(const fvim_grid& g) {
+  const size_t np = (size_t)6 * g.nz;
+  return std::max(x_c2r_blocks<float>(g.nx, g.ny, np), x_c2r_blocks<double>(g.nx, g.ny, np));
+}
 
 int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, double* strain) {
   OpPlan<double> p64;

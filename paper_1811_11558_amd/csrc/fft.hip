@@ -326,7 +326,7 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
 template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
                                              double scale, const cpx<T>* __restrict__ tw,
-                                             const double* __restrict__ padd) {
+                                             const double* __restrict__ padd, ResidEpilogue ep) {
   constexpr int N = 1 << LOGN;
   constexpr int SEQ = c2r_seq<T>(N);
   constexpr int ld = N + 1;
@@ -371,13 +371,59 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
   const double add = padd ? padd[plane] : 0.0;
   const int tot2 = R * N / 2;
   double2* d2 = reinterpret_cast<double2*>(dst);
+  if (!ep.x) {
+    for (int i = threadIdx.x; i < tot2; i += NT) {
+      int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
+      const cpx<T>* b = buf + (r >> 1) * ld + x;
+      double2 o;
+      if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
+      else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
+      d2[i] = o;
+    }
+    return;
+  }
+  // residual epilogue (the residual is the first and only segment)
+  const size_t off = ((size_t)plane * ny + y0) * N;
+  const double2* x2 = reinterpret_cast<const double2*>(ep.x + off);
+  const double2* f2 = ep.Fo ? reinterpret_cast<const double2*>(ep.Fo + off) : nullptr;
+  double s0 = 0.0, s1 = 0.0;
   for (int i = threadIdx.x; i < tot2; i += NT) {
     int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
     const cpx<T>* b = buf + (r >> 1) * ld + x;
     double2 o;
     if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
     else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
-    d2[i] = o;
+    const double2 xv = x2[i];
+    const double2 rr = make_double2(xv.x - o.x, xv.y - o.y);
+    d2[i] = rr;
+    s0 += rr.x * rr.x + rr.y * rr.y;
+    if (f2) {
+      const double2 f = f2[i];
+      s1 += f.x * (rr.x - f.x) + f.y * (rr.y - f.y);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s0 += __shfl_down(s0, o, 64);
+    s1 += __shfl_down(s1, o, 64);
+  }
+  __shared__ double red[2][NT / 64];
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s0;
+    red[1][threadIdx.x >> 6] = s1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) {
+      a += red[0][w];
+      c += red[1][w];
+    }
+    const int cp = plane / ep.nz, z = plane - cp * ep.nz;
+    const double wt = (cp < 3 ? 1.0 : 2.0) * ((z == 0 || z == ep.nz - 1) ? 0.5 : 1.0);
+    ep.part[2 * blockIdx.x] = wt * a;
+    ep.part[2 * blockIdx.x + 1] = wt * c;
   }
 }
 
@@ -468,16 +514,28 @@ hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
-                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd, bool stream_in) {
+                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd, bool stream_in,
+                        const ResidEpilogue& ep) {
+  // the epilogue reads its fields at the output's own offsets: one segment
+  // holding the 6 nz strain planes from plane 0
+  if (ep.x && (seg.n != 1 || seg.first[0] != 0 || !ep.part || ep.nz < 1 || nplanes != (size_t)6 * ep.nz))
+    return hipErrorInvalidValue;
   int R = rows_per_block(c2r_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
 #define CALL(L)                                                                                         \
-  if (stream_in) hipLaunchKernelGGL((k_x_c2r<T, L, true>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd); \
-  else hipLaunchKernelGGL((k_x_c2r<T, L, false>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd)
+  if (stream_in) hipLaunchKernelGGL((k_x_c2r<T, L, true>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep); \
+  else hipLaunchKernelGGL((k_x_c2r<T, L, false>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
 }
+
+template <typename T>
+int x_c2r_blocks(int nx, int ny, size_t nplanes) {
+  return (int)(nplanes * (size_t)ny / rows_per_block(c2r_seq<T>(nx), ny));
+}
+template int x_c2r_blocks<double>(int, int, size_t);
+template int x_c2r_blocks<float>(int, int, size_t);
 
 template hipError_t launch_x_r2c<double>(const double*, cpx<double>*, int, int, size_t, const cpx<double>*,
                                          hipStream_t, double*, bool);
@@ -498,8 +556,10 @@ template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, 
 template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
                                         hipStream_t, bool);
 template hipError_t launch_x_c2r<double>(const cpx<double>*, const OutSegments&, int, int, size_t, double,
-                                         const cpx<double>*, hipStream_t, const double*, bool);
+                                         const cpx<double>*, hipStream_t, const double*, bool,
+                                         const ResidEpilogue&);
 template hipError_t launch_x_c2r<float>(const cpx<float>*, const OutSegments&, int, int, size_t, double,
-                                        const cpx<float>*, hipStream_t, const double*, bool);
+                                        const cpx<float>*, hipStream_t, const double*, bool,
+                                         const ResidEpilogue&);
 
 }  // namespace fvim

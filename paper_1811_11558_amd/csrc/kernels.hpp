@@ -47,11 +47,25 @@ inline int mode_stride(int np) {
   const int q = 128 / (int)sizeof(cpx<T>);
   return (np + q - 1) / q * q;
 }
+// Residual epilogue of the inverse x transform (plasticity iteration): with
+// x set, each output value w of the first segment (the 6 nz strain planes)
+// is replaced by r = x - w, and block b writes wt sum r.r to part[2 b] and,
+// with Fo, wt sum Fo.(r - Fo) to part[2 b + 1]; wt = 2 for shear planes
+// (plane / nz >= 3), halved at the first and last depth node.
+struct ResidEpilogue {
+  const double* x;
+  const double* Fo;
+  double* part;
+  int nz;
+};
 // padd (optional): float64 constant added to each plane of the output.
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr,
-                        bool stream_in = false);
+                        bool stream_in = false, const ResidEpilogue& ep = ResidEpilogue{});
+// blocks of a launch_x_c2r over nplanes planes (partial-sum pairs it writes)
+template <typename T>
+int x_c2r_blocks(int nx, int ny, size_t nplanes);
 
 // Per-mode depth pass.  Input spectra (unnormalised DFTs) in mode-major
 // layout in[mode][ld_in]: the plastic strain as [6][nz] at offset 0 (if

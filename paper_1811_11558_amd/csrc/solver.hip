@@ -279,28 +279,31 @@ __device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz) {
   return (zc < 3u * nz ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
 }
 
-// R = x - w, the residual of the incremental equation (w = grad_s M applied
-// to the plastic strain increment and to the traction increment), with the
-// weighted sums <R, R> and, when Fo is given, <Fo, R - Fo>.  Two elements per
-// thread (n is even: a plane has at least 16 elements).
-__global__ __launch_bounds__(NT) void k_resid(double* __restrict__ R, const double* __restrict__ x,
-                                             const double* __restrict__ w, const double* __restrict__ Fo,
-                                             int lp, unsigned nz, size_t n, double* part) {
-  double v[2] = {0.0, 0.0};
-  const size_t n2 = n / 2;
-  for (size_t j = (size_t)blockIdx.x * NT + threadIdx.x; j < n2; j += (size_t)gridDim.x * NT) {
-    const double2 a = reinterpret_cast<const double2*>(x)[j];
-    const double2 b = reinterpret_cast<const double2*>(w)[j];
-    const double2 r = make_double2(a.x - b.x, a.y - b.y);
-    reinterpret_cast<double2*>(R)[j] = r;
-    const double wt = field_weight(2 * j, lp, nz);          // both elements lie in one plane
-    v[0] += wt * (r.x * r.x + r.y * r.y);
-    if (Fo) {
-      const double2 f = reinterpret_cast<const double2*>(Fo)[j];
-      v[1] += wt * (f.x * (r.x - f.x) + f.y * (r.y - f.y));
-    }
+// Sums of the pairs part[2 b], part[2 b + 1] (b < nb), in a fixed order, into
+// the scalar slots S_DOT0 and S_DOT1 and their host mirror (the weighted
+// <F, F> and <Fo, F - Fo> of a residual evaluation).
+__global__ __launch_bounds__(NT) void k_sum_pairs(const double* __restrict__ part, int nb, double* sc,
+                                                 double* mirror) {
+  __shared__ double sh[2][NT];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
   }
-  block_sums<2>(v, part);
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    sc[S_DOT0] = mirror[S_DOT0] = sh[0][0];
+    sc[S_DOT1] = mirror[S_DOT1] = sh[1][0];
+  }
 }
 
 // weighted sums  <a, a>, <a, b>, <b, b>  with a = a1 - a0, b = b1 - b0 (a0/b0 may be NULL)
@@ -399,6 +402,8 @@ struct SolverWork {
   double* dmap = nullptr;       //   (device view)
   double* vol = nullptr;        // volume work arrays (allocated on first plasticity use)
   size_t vol_count = 0;
+  double* rpart = nullptr;      // partial-sum pairs of the fused residual evaluation
+  int rpart_count = 0;
   // one contact iteration captured as a HIP graph, replayed on a private
   // stream fenced by events against the context stream
   hipStream_t cap = nullptr;
@@ -500,6 +505,7 @@ void solver_release(fvim_ctx* c) {
   if (w->hsc) hipHostFree(w->hsc);
   if (w->hmap) hipHostFree(w->hmap);
   if (w->vol) hipFree(w->vol);
+  if (w->rpart) hipFree(w->rpart);
   if (w->aa) hipFree(w->aa);
   if (w->aa_part) hipFree(w->aa_part);
   if (w->aa_hout) hipHostFree(w->aa_hout);
@@ -520,8 +526,10 @@ size_t solver_footprint(const fvim_grid* g, size_t V) {
   const size_t ns = (size_t)g->nx * g->ny;
   const size_t nm = (size_t)(g->nx / 2 + 1) * g->ny;
   // surface arrays (15 + Anderson history 2 AA_MMAX + 3), volume work
-  // arrays (7 tensors + 1 scalar), compliance spectra, reduction buffers
-  return sizeof(double) * (ns * (18 + 2 * AA_MMAX) + 43 * V) + 2 * sizeof(cpx<double>) * nm +
+  // arrays (6 tensors + 1 scalar), residual partial sums, compliance
+  // spectra, reduction buffers
+  return sizeof(double) * (ns * (18 + 2 * AA_MMAX) + 37 * V + 2 * (size_t)operator_resid_parts(*g)) +
+         2 * sizeof(cpx<double>) * nm +
          sizeof(double) * aa_nsums(AA_MMAX) * (RB + 2) + 64 * 1024;
 }
 
@@ -718,14 +726,14 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
 
 // --------------------------------------------------------- plasticity
 struct PlastBufs {
-  double *x, *F, *xt, *Ft, *b, *dep, *dp, *wk;
+  double *x, *F, *xt, *Ft, *b, *dep, *dp;
   const double* dT;             // traction increment of the current solve
 };
 
 static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
   SolverWork* w = c->sw;
   const size_t V = w->V;
-  const size_t need = 7 * 6 * V + V;
+  const size_t need = 6 * 6 * V + V;
   if (w->vol_count < need) {
     std::lock_guard<std::recursive_mutex> lk(device_lock());
     if (w->vol) {
@@ -739,6 +747,20 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
     }
     w->vol_count = need;
   }
+  const int np2 = operator_resid_parts(c->grid);
+  if (w->rpart_count < np2) {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());
+    if (w->rpart) {
+      hipStreamSynchronize(c->stream);
+      hipFree(w->rpart);
+      w->rpart = nullptr;
+    }
+    if (hipMalloc((void**)&w->rpart, sizeof(double) * 2 * np2) != hipSuccess) {
+      w->rpart_count = 0;
+      return fail(FVIM_ENOMEM, "plasticity workspace allocation failed");
+    }
+    w->rpart_count = np2;
+  }
   double* q = w->vol;
   pb.x = q;
   pb.F = q + 6 * V;
@@ -746,8 +768,7 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
   pb.Ft = q + 18 * V;
   pb.b = q + 24 * V;
   pb.dep = q + 30 * V;
-  pb.wk = q + 36 * V;
-  pb.dp = q + 42 * V;
+  pb.dp = q + 36 * V;
   pb.dT = nullptr;
   return FVIM_OK;
 }
@@ -758,18 +779,18 @@ static double inner_scale(const fvim_ctx* c) {
   return g.lx * g.ly / ((double)g.nx * g.ny) * g.lz / (g.nz - 1);
 }
 
-// One residual evaluation after the return map: w = grad_s M[dep] +
-// grad_s M[dT] (one operator application with both sources), F = x - w and
-// the sums <F, F>, <Fo, F - Fo> (Fo may be NULL), on the context stream.
+// One residual evaluation after the return map: one operator application
+// with both sources (grad_s M[dep] + grad_s M[dT]) whose last transform
+// forms F = x - w in place of w, with the block sums of <F, F> and
+// <Fo, F - Fo> (Fo may be NULL); then their fixed-order total, on the
+// context stream.
 static int residual_launches(fvim_ctx* c, PlastBufs& pb, const double* x, double* F, const double* Fo) {
   SolverWork* w = c->sw;
-  const size_t n6 = 6 * w->V;
-  int rc = operator_apply(c, pb.dep, pb.dT, pb.wk, nullptr, nullptr, nullptr);
+  int nb = 0;
+  int rc = operator_apply_resid(c, pb.dep, pb.dT, x, Fo, F, w->rpart, &nb);
   if (rc) return rc;
-  const int nb = nblocks(n6 / 2);
-  hipLaunchKernelGGL(k_resid, dim3(nb), dim3(NT), 0, c->stream, F, x, pb.wk, Fo, w->lp, (unsigned)c->grid.nz, n6,
-                     w->part);
-  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
+  if (nb > w->rpart_count) return fail(FVIM_EINVAL, "residual partial sums: workspace too small");
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(NT), 0, c->stream, w->rpart, nb, w->sc, w->dmap);
   return FVIM_OK;
 }
 
@@ -1113,7 +1134,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (aam > 0 && (rc = aa_ensure(c))) return rc;
   // every buffer the operator applications of the solve use, sized now: no
   // device memory is freed or allocated while the solve runs
-  if ((rc = operator_reserve(c, pb.dep, dT, pb.wk))) return rc;
+  if ((rc = operator_reserve(c, pb.dep, dT, pb.F))) return rc;
   // Anderson history: differences of the iterates and of the residuals
   double* aX = aam ? w->aa : nullptr;
   double* aF = aam ? w->aa + (size_t)AA_MMAX * n : nullptr;

@@ -75,6 +75,12 @@ int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, dou
 // eigenstrain and traction inputs and strain output, in float64 and, in the
 // FP32_REFINED mode, in float32.
 int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, double* strain);
+// R = x - (grad_s M[eps_p] + grad_s M[traction]) with the weighted sums of
+// the residual epilogue (kernels.hpp) written as *nparts pairs to part
+// (at most operator_resid_parts(c) pairs).
+int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* traction, const double* x,
+                         const double* Fo, double* R, double* part, int* nparts);
+int operator_resid_parts(const fvim_grid& g);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
 }  // namespace fvim
