@@ -282,18 +282,20 @@ __device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz) {
 // Sums of the pairs part[2 b], part[2 b + 1] (b < nb), in a fixed order, into
 // the scalar slots S_DOT0 and S_DOT1 and their host mirror (the weighted
 // <F, F> and <Fo, F - Fo> of a residual evaluation).
-__global__ __launch_bounds__(NT) void k_sum_pairs(const double* __restrict__ part, int nb, double* sc,
-                                                 double* mirror) {
-  __shared__ double sh[2][NT];
+constexpr int NTS = 1024;           // threads of the one block of k_sum_pairs
+__global__ __launch_bounds__(NTS) void k_sum_pairs(const double* __restrict__ part, int nb, double* sc,
+                                                  double* mirror) {
+  __shared__ double sh[2][NTS];
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += NT) {
+#pragma unroll 4
+  for (int i = threadIdx.x; i < nb; i += NTS) {
     a += part[2 * i];
     b += part[2 * i + 1];
   }
   sh[0][threadIdx.x] = a;
   sh[1][threadIdx.x] = b;
   __syncthreads();
-  for (int o = NT / 2; o > 0; o >>= 1) {
+  for (int o = NTS / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) {
       sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
       sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
@@ -790,7 +792,7 @@ static int residual_launches(fvim_ctx* c, PlastBufs& pb, const double* x, double
   int rc = operator_apply_resid(c, pb.dep, pb.dT, x, Fo, F, w->rpart, &nb);
   if (rc) return rc;
   if (nb > w->rpart_count) return fail(FVIM_EINVAL, "residual partial sums: workspace too small");
-  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(NT), 0, c->stream, w->rpart, nb, w->sc, w->dmap);
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(NTS), 0, c->stream, w->rpart, nb, w->sc, w->dmap);
   return FVIM_OK;
 }
 
