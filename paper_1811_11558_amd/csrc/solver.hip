@@ -423,8 +423,10 @@ struct SolverWork {
   // captured residual evaluations (operator, residual and its reduction),
   // one per combination of the pointers and settings they bake in; replayed
   // on the context stream
+  // pointers and settings a captured evaluation bakes in
+  static constexpr int NKEY = 12;
   struct ResGraph {
-    const void* key[10] = {};
+    const void* key[NKEY] = {};
     hipGraph_t g = nullptr;
     hipGraphExec_t ex = nullptr;
   };
@@ -808,10 +810,12 @@ static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double*
     w->rg_warm[p64] = 1;
     return residual_launches(c, pb, x, F, Fo);
   }
-  const void* key[10] = {x, F, Fo, pb.dT, w->vol, c->bufA, c->bufB, c->k0buf,
-                         (const void*)(intptr_t)(p64 + 2), (const void*)(intptr_t)(c->depth_cfg + 16)};
+  const void* key[SolverWork::NKEY] = {x, F, Fo, pb.dT, w->vol, w->rpart, c->bufA, c->bufB, c->k0buf,
+                                       (const void*)(intptr_t)(p64 + 2),
+                                       (const void*)(intptr_t)(c->depth_cfg + 16),
+                                       (const void*)(intptr_t)(c->streaming + 8)};
   for (auto& r : w->rg)
-    if (r.ex && std::equal(key, key + 10, r.key)) {
+    if (r.ex && std::equal(key, key + SolverWork::NKEY, r.key)) {
       hipError_t e = hipGraphLaunch(r.ex, c->stream);
       return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
     }
@@ -837,7 +841,7 @@ static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double*
     return residual_launches(c, pb, x, F, Fo);
   }
   r.g = g;
-  std::copy(key, key + 10, r.key);
+  std::copy(key, key + SolverWork::NKEY, r.key);
   e = hipGraphLaunch(r.ex, c->stream);
   return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
 }
