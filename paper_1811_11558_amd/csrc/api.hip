@@ -164,6 +164,7 @@ struct OpPlan {
   bool k0x = false;
   bool nt = false;              // launches read their input with streaming loads
   ResidEpilogue ep{};           // residual epilogue of the inverse x transform
+  LayerSkip skip{};             // eigenstrain layers known to be zero
   double* wsum = nullptr;
   double* tsum = nullptr;
   double* padd = nullptr;
@@ -279,11 +280,11 @@ int op_forward(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
   const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
   hipError_t e;
   tm.begin(FVIM_STAGE_XFWD, st);
-  if ((e = launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum, P.nt)) != hipSuccess)
+  if ((e = launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum, P.nt, P.skip)) != hipSuccess)
     return fail_hip(e, "x_r2c");
   tm.end();
   tm.begin(FVIM_STAGE_YFWD, st);
-  if ((e = launch_y_fwd<T>(P.A, P.B, ny, kxh, P.np_in, P.prm.ld_in, P.twy, st, P.nt)) != hipSuccess)
+  if ((e = launch_y_fwd<T>(P.A, P.B, ny, kxh, P.np_in, P.prm.ld_in, P.twy, st, P.nt, P.skip)) != hipSuccess)
     return fail_hip(e, "y_fwd");
   tm.end();
   return FVIM_OK;
@@ -310,11 +311,16 @@ int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
 // u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
 template <typename T>
 int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
-                     double* disp, double* surf_u3, const ResidEpilogue* ep = nullptr) {
+                     double* disp, double* surf_u3, const ResidEpilogue* ep = nullptr,
+                     const int* zact = nullptr) {
   OpPlan<T> P;
   int rc = op_plan<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P);
   if (rc || P.np == 0) return rc;
   if (ep) P.ep = *ep;
+  if (zact && eps_p) {
+    P.skip = LayerSkip{zact, c->grid.nz, 6 * c->grid.nz};
+    P.prm.zact = zact;
+  }
   hipStream_t st = c->stream;
   const bool side = c->use_side != 0;
   if (side && (rc = side_ensure(c))) return rc;
@@ -397,17 +403,17 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
 static bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u); }
 
 int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* traction, const double* x,
-                         const double* Fo, double* R, double* part, int* nparts) {
+                         const double* Fo, double* R, double* part, int* nparts, const int* zact) {
   if (misaligned(eps_p) || misaligned(traction) || misaligned(x) || misaligned(Fo) || misaligned(R))
     return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
   const ResidEpilogue ep = {x, Fo, part, c->grid.nz};
   const size_t np = (size_t)6 * c->grid.nz;
   if (c->precision == FVIM_FP32_REFINED && !c->force_fp64) {
     *nparts = x_c2r_blocks<float>(c->grid.nx, c->grid.ny, np);
-    return operator_apply_t<float>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep);
+    return operator_apply_t<float>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep, zact);
   }
   *nparts = x_c2r_blocks<double>(c->grid.nx, c->grid.ny, np);
-  return operator_apply_t<double>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep);
+  return operator_apply_t<double>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep, zact);
 }
 
 int operator_resid_parts(const fvim_grid& g) {

@@ -186,6 +186,9 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
   const T mu = (T)prm.mu;
   const int i0 = l * P;
   const bool wantS = prm.off_strain >= 0;
+  // eigenstrain layers z >= za are zero (their spectra were not written)
+  const int za = prm.zact ? min(*prm.zact, nz) : nz;
+  const bool has_w = prm.has_w != 0;
   constexpr bool wantX = WANTX;
 
   cpx<T> tr[3];
@@ -201,7 +204,7 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     if (wantX) {
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? scl(src[(size_t)c * nz + i], nrm) : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = (has_w && i < za) ? scl(src[(size_t)c * nz + i], nrm) : zero<T>();
       cpx<T> tre = add(add(e[0], e[1]), e[2]);
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
 #pragma unroll
@@ -222,7 +225,7 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
       if (i >= nz) continue;
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = prm.has_w ? src[(size_t)c * nz + i] : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = (has_w && i < za) ? src[(size_t)c * nz + i] : zero<T>();
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
       cpx<T> w33 = scl(axpy(scl(trp, kap), T(2), ep[2]), nrm);     // w33 / mu
       cpx<T> e[6] = {zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>(), zero<T>()};
@@ -287,7 +290,7 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
       const int i = i0 + p;
       cpx<T> ep[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ep[c] = (prm.has_w && i < nz) ? ld_in<NTL>(src + (size_t)c * nz + i) : zero<T>();
+      for (int c = 0; c < 6; ++c) ep[c] = (has_w && i < za) ? ld_in<NTL>(src + (size_t)c * nz + i) : zero<T>();
       cpx<T> trp = add(add(ep[0], ep[1]), ep[2]);
       cpx<T> exx = add(add(scl(ep[0], n1 * n1), scl(ep[5], T(2) * n1 * n2)), scl(ep[1], n2 * n2));
       cpx<T> exe = add(add(scl(ep[0], -n1 * n2), scl(ep[5], n1 * n1 - n2 * n2)), scl(ep[1], n1 * n2));

@@ -165,7 +165,8 @@ __device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T
 // bsum[b] (the plane means of the mean mode are then formed in float64).
 template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
-                                             const cpx<T>* __restrict__ tw, double* __restrict__ bsum) {
+                                             const cpx<T>* __restrict__ tw, double* __restrict__ bsum,
+                                             LayerSkip skip) {
   constexpr int N = 1 << LOGN;
   constexpr int SEQ = r2c_seq<T>(N);
   constexpr int ld = N + 1;
@@ -174,6 +175,11 @@ __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict
   const size_t row0 = (size_t)blockIdx.x * R;
   const size_t plane = row0 / ny;
   const int y0 = (int)(row0 - plane * ny);
+  // a layer without plastic strain: its rows sum to zero, nothing to transform
+  if (skip.zact && (int)plane < skip.nw && (int)(plane % skip.nz) >= *skip.zact) {
+    if (bsum && threadIdx.x == 0) bsum[blockIdx.x] = 0.0;
+    return;
+  }
   const int sg = (seg.n > 1 && (int)plane >= seg.first[1]) ? 1 : 0;
   const double* in = seg.ptr[sg] + ((plane - seg.first[sg]) * ny + y0) * (size_t)N;
   // 16-byte loads: two consecutive x of one row
@@ -242,7 +248,7 @@ __device__ __forceinline__ int xcd_block() {
 // through scratch memory, doubling the kernel's memory traffic.
 template <typename T, int LOGN, bool NTL>
 __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
-                                             int NP, int ldp, const cpx<T>* __restrict__ tw) {
+                                             int NP, int ldp, const cpx<T>* __restrict__ tw, LayerSkip skip) {
   constexpr int N = 1 << LOGN;
   constexpr int B = col_batch<T>(N);
   static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
@@ -253,6 +259,15 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
   const int kx = lb / npb;
   const int p0 = (lb - kx * npb) * B;
   const int nb = min(B, NP - p0);
+  if (skip.zact) {                     // every plane of the group in a layer without plastic strain
+    const int za = *skip.zact;
+    bool live = false;
+    for (int b = 0; b < nb; ++b) {
+      const int p = p0 + b;
+      live = live || p >= skip.nw || p % skip.nz < za;
+    }
+    if (!live) return;
+  }
   constexpr int MV = B * N / NT;
   cpx<T> v[MV];
 #pragma unroll
@@ -462,13 +477,13 @@ int x_r2c_blocks_per_plane(int nx, int ny) {
 
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum, bool stream_in) {
+                        hipStream_t st, double* bsum, bool stream_in, const LayerSkip& skip) {
   if (seg.n < 1 || seg.n > 2 || seg.first[0] != 0) return hipErrorInvalidValue;
   int R = rows_per_block(r2c_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
 #define CALL(L)                                                                                        \
-  if (stream_in) hipLaunchKernelGGL((k_x_r2c<T, L, true>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum); \
-  else hipLaunchKernelGGL((k_x_r2c<T, L, false>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum)
+  if (stream_in) hipLaunchKernelGGL((k_x_r2c<T, L, true>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum, skip); \
+  else hipLaunchKernelGGL((k_x_r2c<T, L, false>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum, skip)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
@@ -481,18 +496,18 @@ hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t np
   seg.n = 1;
   seg.first[0] = seg.first[1] = 0;
   seg.ptr[0] = seg.ptr[1] = in;
-  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum, stream_in);
+  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum, stream_in, LayerSkip{});
 }
 
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st, bool stream_in) {
+                        hipStream_t st, bool stream_in, const LayerSkip& skip) {
   if (ldp < NP) return hipErrorInvalidValue;
   int B = cols_per_block<T>(ny);
   dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
 #define CALL(L)                                                                                       \
-  if (stream_in) hipLaunchKernelGGL((k_y_fwd<T, L, true>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw); \
-  else hipLaunchKernelGGL((k_y_fwd<T, L, false>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
+  if (stream_in) hipLaunchKernelGGL((k_y_fwd<T, L, true>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw, skip); \
+  else hipLaunchKernelGGL((k_y_fwd<T, L, false>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw, skip)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
   return hipGetLastError();
@@ -540,17 +555,17 @@ template int x_c2r_blocks<float>(int, int, size_t);
 template hipError_t launch_x_r2c<double>(const double*, cpx<double>*, int, int, size_t, const cpx<double>*,
                                          hipStream_t, double*, bool);
 template hipError_t launch_x_r2c<double>(const InSegments&, cpx<double>*, int, int, size_t,
-                                         const cpx<double>*, hipStream_t, double*, bool);
+                                         const cpx<double>*, hipStream_t, double*, bool, const LayerSkip&);
 template hipError_t launch_x_r2c<float>(const InSegments&, cpx<float>*, int, int, size_t, const cpx<float>*,
-                                        hipStream_t, double*, bool);
+                                        hipStream_t, double*, bool, const LayerSkip&);
 template hipError_t launch_x_r2c<float>(const double*, cpx<float>*, int, int, size_t, const cpx<float>*,
                                         hipStream_t, double*, bool);
 template int x_r2c_blocks_per_plane<double>(int, int);
 template int x_r2c_blocks_per_plane<float>(int, int);
 template hipError_t launch_y_fwd<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
-                                         const cpx<double>*, hipStream_t, bool);
+                                         const cpx<double>*, hipStream_t, bool, const LayerSkip&);
 template hipError_t launch_y_fwd<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
-                                        hipStream_t, bool);
+                                        hipStream_t, bool, const LayerSkip&);
 template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
                                          const cpx<double>*, hipStream_t, bool);
 template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,

@@ -20,13 +20,22 @@ struct InSegments {
   const double* ptr[2];
 };
 
+// Depth layers without plastic strain: with zact set, eigenstrain plane p
+// (p < nw = 6 nz, depth p % nz) is known to be zero when p % nz >= *zact
+// (a device value), and the forward transforms skip it (its spectrum is then
+// not written; the depth pass reads only layers below *zact).
+struct LayerSkip {
+  const int* zact;
+  int nz, nw;
+};
 // bsum (optional): float64 sum of the rows of each block, blocks of a plane
 // consecutive (x_r2c_blocks_per_plane of them).  stream_in: the launch reads
 // its input for the last time with streaming (non-temporal) loads (see
 // operator_streaming); every launcher below takes the same flag.
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum = nullptr, bool stream_in = false);
+                        hipStream_t st, double* bsum = nullptr, bool stream_in = false,
+                        const LayerSkip& skip = LayerSkip{});
 template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum = nullptr, bool stream_in = false);
@@ -36,7 +45,7 @@ int x_r2c_blocks_per_plane(int nx, int ny);
 // S[kx][ky][ldp] (record stride ldp >= NP; the padding is not touched).
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st, bool stream_in = false);
+                        hipStream_t st, bool stream_in = false, const LayerSkip& skip = LayerSkip{});
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
                         hipStream_t st, bool stream_in = false);
@@ -90,6 +99,7 @@ struct DepthParams {
   // here, and the second launch averages them
   void* rep_out;
   int nt_in;              // the main launch reads the input with streaming loads
+  const int* zact;        // if set: eigenstrain layers z >= *zact are zero and not read
   // ratios of kappa, filled by launch_depth: 1/(kappa+2), (kappa+1)/(kappa+2),
   // 1/(2(kappa+2)), kappa/(kappa+2), (kappa+2)/(2(kappa+1)), 1/(2 kappa+2)
   double ikp2, kk, i2k4, kapkp2, cfac, ik2;
@@ -150,9 +160,12 @@ hipError_t launch_return_map(const double* d_eps, const double* sig_n, const dou
                              double* d_ep, double* sig_np1, size_t nvox, double lam, double mu,
                              double sy0, double eh, hipStream_t st);
 // Return map at the trial point x + cf F (F may be NULL: at x); the trial
-// point is stored in xt when F and xt are given; writes d_eps_p only.
+// point is stored in xt when F and xt are given; writes d_eps_p only.  With
+// layer_flags, layer_flags[z] is set to 1 for every depth layer z (voxel v
+// in layer v >> lp) where d_eps_p is not zero (the caller clears them).
 hipError_t launch_trial_return_map(const double* x, const double* F, double cf, double* xt, const double* sig_n,
                                    const double* ep_n, double* d_eps_p, size_t nvox, double lam, double mu,
-                                   double sy0, double eh, hipStream_t st);
+                                   double sy0, double eh, hipStream_t st, int* layer_flags = nullptr,
+                                   int lp = 0);
 
 }  // namespace fvim

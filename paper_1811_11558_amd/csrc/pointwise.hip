@@ -22,7 +22,8 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
                                                   double cf, double* __restrict__ xt, const double* sn,
                                                   const double* __restrict__ epn, double* __restrict__ dep,
                                                   double* __restrict__ dp, double* sn1, size_t V, double lam,
-                                                  double mu, double sy0, double eh) {
+                                                  double mu, double sy0, double eh, int* __restrict__ flags,
+                                                  int lp) {
   size_t v = (size_t)blockIdx.x * NT + threadIdx.x;
   if (v >= V) return;
   double e[6], s[6];
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
     fac = 1.5 * dpv / seq;
   }
   if (dp) dp[v] = dpv;
+  if (flags && fac != 0.0) flags[v >> lp] = 1;   // d_eps_p = fac dev(sigma_trial) is not zero
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const double x = fac * d[c];
@@ -124,16 +126,16 @@ hipError_t launch_return_map(const double* d_eps, const double* sig_n, const dou
                              double eh, hipStream_t st) {
   unsigned nb = (unsigned)((nvox + NT - 1) / NT);
   hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, d_eps, nullptr, 0.0, nullptr, sig_n, ep_n, d_eps_p,
-                     d_ep, sig_np1, nvox, lam, mu, sy0, eh);
+                     d_ep, sig_np1, nvox, lam, mu, sy0, eh, nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_trial_return_map(const double* x, const double* F, double cf, double* xt, const double* sig_n,
                                    const double* ep_n, double* d_eps_p, size_t nvox, double lam, double mu,
-                                   double sy0, double eh, hipStream_t st) {
+                                   double sy0, double eh, hipStream_t st, int* layer_flags, int lp) {
   unsigned nb = (unsigned)((nvox + NT - 1) / NT);
   hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, x, F, cf, xt, sig_n, ep_n, d_eps_p, nullptr,
-                     nullptr, nvox, lam, mu, sy0, eh);
+                     nullptr, nvox, lam, mu, sy0, eh, layer_flags, lp);
   return hipGetLastError();
 }
 

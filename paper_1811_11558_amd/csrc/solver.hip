@@ -282,6 +282,25 @@ __device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz) {
 // Sums of the pairs part[2 b], part[2 b + 1] (b < nb), in a fixed order, into
 // the scalar slots S_DOT0 and S_DOT1 and their host mirror (the weighted
 // <F, F> and <Fo, F - Fo> of a residual evaluation).
+// zact = 1 + the deepest layer z with flags[z] set (0 if none), written to
+// flags[nz]; the flags are cleared for the next evaluation.
+__global__ __launch_bounds__(NT) void k_zact(int* __restrict__ flags, int nz) {
+  __shared__ int sh[NT];
+  int za = 0;
+  for (int z = threadIdx.x; z < nz; z += NT)
+    if (flags[z]) {
+      za = max(za, z + 1);
+      flags[z] = 0;
+    }
+  sh[threadIdx.x] = za;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flags[nz] = sh[0];
+}
+
 constexpr int NTS = 1024;           // threads of the one block of k_sum_pairs
 __global__ __launch_bounds__(NTS) void k_sum_pairs(const double* __restrict__ part, int nb, double* sc,
                                                   double* mirror) {
@@ -406,6 +425,7 @@ struct SolverWork {
   size_t vol_count = 0;
   double* rpart = nullptr;      // partial-sum pairs of the fused residual evaluation
   int rpart_count = 0;
+  int* layers = nullptr;        // [nz] plastic-layer flags of the trial point, then zact
   // one contact iteration captured as a HIP graph, replayed on a private
   // stream fenced by events against the context stream
   hipStream_t cap = nullptr;
@@ -424,7 +444,7 @@ struct SolverWork {
   // one per combination of the pointers and settings they bake in; replayed
   // on the context stream
   // pointers and settings a captured evaluation bakes in
-  static constexpr int NKEY = 12;
+  static constexpr int NKEY = 13;
   struct ResGraph {
     const void* key[NKEY] = {};
     hipGraph_t g = nullptr;
@@ -510,6 +530,7 @@ void solver_release(fvim_ctx* c) {
   if (w->hmap) hipHostFree(w->hmap);
   if (w->vol) hipFree(w->vol);
   if (w->rpart) hipFree(w->rpart);
+  if (w->layers) hipFree(w->layers);
   if (w->aa) hipFree(w->aa);
   if (w->aa_part) hipFree(w->aa_part);
   if (w->aa_hout) hipHostFree(w->aa_hout);
@@ -765,6 +786,18 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
     }
     w->rpart_count = np2;
   }
+  if (!w->layers) {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());
+    const size_t bytes = sizeof(int) * ((size_t)c->grid.nz + 1);
+    hipError_t e = hipMalloc((void**)&w->layers, bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(w->layers, 0, bytes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      if (w->layers) hipFree(w->layers);
+      w->layers = nullptr;
+      return fail_hip(e, "plasticity workspace");
+    }
+  }
   double* q = w->vol;
   pb.x = q;
   pb.F = q + 6 * V;
@@ -791,7 +824,7 @@ static double inner_scale(const fvim_ctx* c) {
 static int residual_launches(fvim_ctx* c, PlastBufs& pb, const double* x, double* F, const double* Fo) {
   SolverWork* w = c->sw;
   int nb = 0;
-  int rc = operator_apply_resid(c, pb.dep, pb.dT, x, Fo, F, w->rpart, &nb);
+  int rc = operator_apply_resid(c, pb.dep, pb.dT, x, Fo, F, w->rpart, &nb, w->layers + c->grid.nz);
   if (rc) return rc;
   if (nb > w->rpart_count) return fail(FVIM_EINVAL, "residual partial sums: workspace too small");
   hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(NTS), 0, c->stream, w->rpart, nb, w->sc, w->dmap);
@@ -810,7 +843,7 @@ static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double*
     w->rg_warm[p64] = 1;
     return residual_launches(c, pb, x, F, Fo);
   }
-  const void* key[SolverWork::NKEY] = {x, F, Fo, pb.dT, w->vol, w->rpart, c->bufA, c->bufB, c->k0buf,
+  const void* key[SolverWork::NKEY] = {x, F, Fo, pb.dT, w->vol, w->rpart, w->layers, c->bufA, c->bufB, c->k0buf,
                                        (const void*)(intptr_t)(p64 + 2),
                                        (const void*)(intptr_t)(c->depth_cfg + 16),
                                        (const void*)(intptr_t)(c->streaming + 8)};
@@ -853,8 +886,10 @@ static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const doubl
                     double* xt, double* F, double* f, double* d = nullptr) {
   SolverWork* w = c->sw;
   hipError_t e = launch_trial_return_map(x, Fo, cf, Fo ? xt : nullptr, s->sigma, s->ep, pb.dep, w->V, c->lam, c->mu,
-                                         c->mat.sigma_y0, c->mat.E_h, c->stream);
+                                         c->mat.sigma_y0, c->mat.E_h, c->stream, w->layers, w->lp);
   if (e != hipSuccess) return fail_hip(e, "return map");
+  // the deepest layer with plastic strain: the operator skips the layers below
+  hipLaunchKernelGGL(k_zact, dim3(1), dim3(NT), 0, c->stream, w->layers, c->grid.nz);
   int rc = residual_enqueue(c, pb, Fo ? xt : x, F, Fo);
   if (rc) return rc;
   if ((rc = read_scalars(c, S_DOT0, Fo ? 2 : 1))) return rc;

@@ -77,9 +77,10 @@ int operator_apply(fvim_ctx* c, const double* eps_p, const double* traction, dou
 int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, double* strain);
 // R = x - (grad_s M[eps_p] + grad_s M[traction]) with the weighted sums of
 // the residual epilogue (kernels.hpp) written as *nparts pairs to part
-// (at most operator_resid_parts(c) pairs).
+// (at most operator_resid_parts(c) pairs).  zact (device, may be NULL): the
+// eigenstrain layers z >= *zact are zero and are skipped.
 int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* traction, const double* x,
-                         const double* Fo, double* R, double* part, int* nparts);
+                         const double* Fo, double* R, double* part, int* nparts, const int* zact);
 int operator_resid_parts(const fvim_grid& g);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
