@@ -338,7 +338,7 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
 // Plane p of the input goes to the output segment that contains it.
 // If padd is not NULL, padd[plane] (float64) is added to every output value
 // of that plane (the mean mode computed in float64).
-template <typename T, int LOGN, bool NTL>
+template <typename T, int LOGN>
 __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
                                              double scale, const cpx<T>* __restrict__ tw,
                                              const double* __restrict__ padd, ResidEpilogue ep) {
@@ -363,8 +363,8 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
     const int i = min((int)threadIdx.x + u * NT, tot - 1);
     const int k = i >> lhp, pr = i - (k << lhp);
     const size_t a = ((size_t)plane * kxh + k) * ny + y0 + 2 * pr;
-    v0[u] = ld_in<NTL>(in + a);
-    v1[u] = ld_in<NTL>(in + a + 1);
+    v0[u] = in[a];
+    v1[u] = in[a + 1];
   }
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -529,7 +529,7 @@ hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, 
 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
-                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd, bool stream_in,
+                        double scale, const cpx<T>* tw, hipStream_t st, const double* padd,
                         const ResidEpilogue& ep) {
   // the epilogue reads its fields at the output's own offsets: one segment
   // holding the 6 nz strain planes from plane 0
@@ -537,9 +537,7 @@ hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny
     return hipErrorInvalidValue;
   int R = rows_per_block(c2r_seq<T>(nx), ny);
   dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L)                                                                                         \
-  if (stream_in) hipLaunchKernelGGL((k_x_c2r<T, L, true>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep); \
-  else hipLaunchKernelGGL((k_x_c2r<T, L, false>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep)
+#define CALL(L) hipLaunchKernelGGL((k_x_c2r<T, L>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
   return hipGetLastError();
@@ -571,10 +569,10 @@ template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, 
 template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
                                         hipStream_t, bool);
 template hipError_t launch_x_c2r<double>(const cpx<double>*, const OutSegments&, int, int, size_t, double,
-                                         const cpx<double>*, hipStream_t, const double*, bool,
+                                         const cpx<double>*, hipStream_t, const double*,
                                          const ResidEpilogue&);
 template hipError_t launch_x_c2r<float>(const cpx<float>*, const OutSegments&, int, int, size_t, double,
-                                        const cpx<float>*, hipStream_t, const double*, bool,
+                                        const cpx<float>*, hipStream_t, const double*,
                                          const ResidEpilogue&);
 
 }  // namespace fvim
