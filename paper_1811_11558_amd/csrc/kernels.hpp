@@ -165,9 +165,11 @@ hipError_t launch_return_map(const double* d_eps, const double* sig_n, const dou
 // point is stored in xt when F and xt are given; writes d_eps_p only.  With
 // layer_flags, layer_flags[z] is set to 1 for every depth layer z (voxel v
 // in layer v >> lp) where d_eps_p is not zero (the caller clears them).
+// With zwrite (device), d_eps_p is known to hold zeros in the layers >=
+// *zwrite, and elastic voxels there are not stored again.
 hipError_t launch_trial_return_map(const double* x, const double* F, double cf, double* xt, const double* sig_n,
                                    const double* ep_n, double* d_eps_p, size_t nvox, double lam, double mu,
                                    double sy0, double eh, hipStream_t st, int* layer_flags = nullptr,
-                                   int lp = 0);
+                                   int lp = 0, const int* zwrite = nullptr);
 
 }  // namespace fvim

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
                                                   const double* __restrict__ epn, double* __restrict__ dep,
                                                   double* __restrict__ dp, double* sn1, size_t V, double lam,
                                                   double mu, double sy0, double eh, int* __restrict__ flags,
-                                                  int lp) {
+                                                  int lp, const int* __restrict__ zwrite) {
   size_t v = (size_t)blockIdx.x * NT + threadIdx.x;
   if (v >= V) return;
   double e[6], s[6];
@@ -54,6 +54,9 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
   }
   if (dp) dp[v] = dpv;
   if (flags && fac != 0.0) flags[v >> lp] = 1;   // d_eps_p = fac dev(sigma_trial) is not zero
+  // with zwrite, dep already holds zeros in the layers >= *zwrite: an elastic
+  // voxel there needs no store
+  if (zwrite && fac == 0.0 && (int)(v >> lp) >= *zwrite) return;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     const double x = fac * d[c];
@@ -126,16 +129,17 @@ hipError_t launch_return_map(const double* d_eps, const double* sig_n, const dou
                              double eh, hipStream_t st) {
   unsigned nb = (unsigned)((nvox + NT - 1) / NT);
   hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, d_eps, nullptr, 0.0, nullptr, sig_n, ep_n, d_eps_p,
-                     d_ep, sig_np1, nvox, lam, mu, sy0, eh, nullptr, 0);
+                     d_ep, sig_np1, nvox, lam, mu, sy0, eh, nullptr, 0, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_trial_return_map(const double* x, const double* F, double cf, double* xt, const double* sig_n,
                                    const double* ep_n, double* d_eps_p, size_t nvox, double lam, double mu,
-                                   double sy0, double eh, hipStream_t st, int* layer_flags, int lp) {
+                                   double sy0, double eh, hipStream_t st, int* layer_flags, int lp,
+                                   const int* zwrite) {
   unsigned nb = (unsigned)((nvox + NT - 1) / NT);
   hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, x, F, cf, xt, sig_n, ep_n, d_eps_p, nullptr,
-                     nullptr, nvox, lam, mu, sy0, eh, layer_flags, lp);
+                     nullptr, nvox, lam, mu, sy0, eh, layer_flags, lp, zwrite);
   return hipGetLastError();
 }
 

@@ -283,7 +283,9 @@ __device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz) {
 // the scalar slots S_DOT0 and S_DOT1 and their host mirror (the weighted
 // <F, F> and <Fo, F - Fo> of a residual evaluation).
 // zact = 1 + the deepest layer z with flags[z] set (0 if none), written to
-// flags[nz]; the flags are cleared for the next evaluation.
+// flags[nz] (the layers the operator reads) and flags[nz + 1] (the layers in
+// which the next trial return map must store every voxel: d_eps_p is zero
+// beyond); the flags are cleared for the next evaluation.
 __global__ __launch_bounds__(NT) void k_zact(int* __restrict__ flags, int nz) {
   __shared__ int sh[NT];
   int za = 0;
@@ -298,7 +300,14 @@ __global__ __launch_bounds__(NT) void k_zact(int* __restrict__ flags, int nz) {
     if (threadIdx.x < o) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) flags[nz] = sh[0];
+  if (threadIdx.x == 0) {
+    flags[nz] = sh[0];
+    flags[nz + 1] = sh[0];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0) p[0] = v;
 }
 
 constexpr int NTS = 1024;           // threads of the one block of k_sum_pairs
@@ -425,7 +434,7 @@ struct SolverWork {
   size_t vol_count = 0;
   double* rpart = nullptr;      // partial-sum pairs of the fused residual evaluation
   int rpart_count = 0;
-  int* layers = nullptr;        // [nz] plastic-layer flags of the trial point, then zact
+  int* layers = nullptr;        // [nz] plastic-layer flags of the trial point, zact, zwrite
   // one contact iteration captured as a HIP graph, replayed on a private
   // stream fenced by events against the context stream
   hipStream_t cap = nullptr;
@@ -771,6 +780,8 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
       return fail(FVIM_ENOMEM, "plasticity workspace allocation failed");
     }
     w->vol_count = need;
+    if (w->layers)                                   // a new d_eps_p holds nothing yet
+      hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->stream, w->layers + c->grid.nz + 1, c->grid.nz);
   }
   const int np2 = operator_resid_parts(c->grid);
   if (w->rpart_count < np2) {
@@ -788,9 +799,12 @@ static int vol_ensure(fvim_ctx* c, PlastBufs& pb) {
   }
   if (!w->layers) {
     std::lock_guard<std::recursive_mutex> lk(device_lock());
-    const size_t bytes = sizeof(int) * ((size_t)c->grid.nz + 1);
+    const size_t bytes = sizeof(int) * ((size_t)c->grid.nz + 2);
     hipError_t e = hipMalloc((void**)&w->layers, bytes);
     if (e == hipSuccess) e = hipMemsetAsync(w->layers, 0, bytes, c->stream);
+    if (e == hipSuccess) hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->stream, w->layers + c->grid.nz + 1,
+                                            c->grid.nz);     // d_eps_p holds nothing yet: store every voxel
+    if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
       if (w->layers) hipFree(w->layers);
@@ -879,6 +893,13 @@ static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double*
   return e == hipSuccess ? FVIM_OK : fail_hip(e, "graph launch");
 }
 
+// After a return map that stored d_eps_p for every voxel, the field may be
+// nonzero in any layer: the next trial return map stores every voxel again.
+static void dep_written_everywhere(fvim_ctx* c) {
+  SolverWork* w = c->sw;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, c->stream, w->layers + c->grid.nz + 1, c->grid.nz);
+}
+
 // Residual at the trial point xt = x + cf Fo (Fo NULL: at x itself, xt
 // ignored) into F: radial return at xt, then the evaluation above.  Returns
 // the weighted <F, F> in *f and, with Fo, <Fo, F - Fo> in *d.
@@ -886,7 +907,8 @@ static int residual(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const doubl
                     double* xt, double* F, double* f, double* d = nullptr) {
   SolverWork* w = c->sw;
   hipError_t e = launch_trial_return_map(x, Fo, cf, Fo ? xt : nullptr, s->sigma, s->ep, pb.dep, w->V, c->lam, c->mu,
-                                         c->mat.sigma_y0, c->mat.E_h, c->stream, w->layers, w->lp);
+                                         c->mat.sigma_y0, c->mat.E_h, c->stream, w->layers, w->lp,
+                                         w->layers + c->grid.nz + 1);
   if (e != hipSuccess) return fail_hip(e, "return map");
   // the deepest layer with plastic strain: the operator skips the layers below
   hipLaunchKernelGGL(k_zact, dim3(1), dim3(NT), 0, c->stream, w->layers, c->grid.nz);
@@ -1042,6 +1064,7 @@ static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const 
   e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, nullptr, w->V, c->lam, c->mu, c->mat.sigma_y0,
                         c->mat.E_h, st);
   if (e != hipSuccess) return fail_hip(e, "return map");
+  dep_written_everywhere(c);
   *res = std::sqrt(f);
   if (std::sqrt(f) > tol_abs) return fail(FVIM_ENOCONV, "plasticity: iteration limit reached");
   return FVIM_OK;
@@ -1277,6 +1300,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, s->sigma, V, c->lam, c->mu, c->mat.sigma_y0,
                           c->mat.E_h, st);
     if (e != hipSuccess) return cleanup(fail_hip(e, "return map"));
+    dep_written_everywhere(c);
     axpy(c, s->eps_p, s->eps_p, 1.0, pb.dep, 6 * V);
     axpy(c, s->ep, s->ep, 1.0, pb.dp, V);
     e = hipMemcpyAsync(s->traction, T, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st);
