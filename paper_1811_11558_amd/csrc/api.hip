@@ -384,12 +384,14 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
     for (int k = 0; k < b.n; ++k) {
       const DepthParams& p = P[i0 + k].prm;
       b.prm[k] = p;
-      b.prm[k].rep_out = nullptr;        // the batched launches keep the Nyquist kernel
+      // the Nyquist sign replicas join the main launch (records after the
+      // spectrum in A, reserved by op_plan), whatever the side-stream option
+      b.prm[k].rep_out = (void*)(P[i0 + k].A + (size_t)p.kxh * p.ny * p.ld_out);
       depth_derive(b.prm[k]);
       b.in[k] = P[i0 + k].B;
       b.out[k] = P[i0 + k].A;
-      b.first_main[k + 1] = b.first_main[k] + (p.kxh * p.ny + gpb - 1) / gpb;
-      b.first_nyq[k + 1] = b.first_nyq[k] + (p.ny + p.kxh - 1 + gpb - 1) / gpb;
+      b.first_main[k + 1] = b.first_main[k] + (p.kxh * p.ny + depth_replicas(p.ny, p.kxh) + gpb - 1) / gpb;
+      b.first_nyq[k + 1] = b.first_nyq[k] + (p.ny + p.kxh - 1);           // one block per Nyquist mode
     }
     tm.begin(FVIM_STAGE_DEPTH, st);
     hipError_t e = launch_depth_batch<T>(b, (DepthBatch*)c0->dbatch, cfg, st);

@@ -488,13 +488,12 @@ __global__ __launch_bounds__(NT) void k_depth_batch(const DepthBatch* __restrict
                                            b->prm[c], (int)blockIdx.x - first[c]);
 }
 
-// Nyquist mode j (one block each) <- the weighted sum of its sign replicas,
-// in the order and with the weights (1/2, or 1/4 at the corner) of the
-// replica loop of the NYQ kernel.
+// Nyquist mode j <- the weighted sum of its sign replicas, in the order and
+// with the weights (1/2, or 1/4 at the corner) of the replica loop of the
+// NYQ kernel; one block per mode.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_nyq_average(cpx<T>* __restrict__ out, const cpx<T>* __restrict__ rep,
-                                                   int nx, int ny, int kxh, int ld, int np) {
-  const int j = blockIdx.x;
+__device__ __forceinline__ void nyq_average(cpx<T>* __restrict__ out, const cpx<T>* __restrict__ rep, int nx,
+                                            int ny, int kxh, int ld, int np, int j) {
   const int mn = ny + kxh - 1;
   int kx, ky;
   if (j < ny) { kx = nx / 2; ky = j; }
@@ -514,6 +513,23 @@ __global__ __launch_bounds__(NT) void k_nyq_average(cpx<T>* __restrict__ out, co
     }
     dst[c] = v;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_nyq_average(cpx<T>* __restrict__ out, const cpx<T>* __restrict__ rep,
+                                                   int nx, int ny, int kxh, int ld, int np) {
+  nyq_average<T>(out, rep, nx, ny, kxh, ld, np, blockIdx.x);
+}
+
+// The same over several grids: block b averages Nyquist mode b - first_nyq[c]
+// of the grid c with first_nyq[c] <= b < first_nyq[c + 1].
+template <typename T>
+__global__ __launch_bounds__(NT) void k_nyq_average_batch(const DepthBatch* __restrict__ b) {
+  int c = 0;
+  while (c + 1 < b->n && (int)blockIdx.x >= b->first_nyq[c + 1]) ++c;
+  const DepthParams& p = b->prm[c];
+  nyq_average<T>(static_cast<cpx<T>*>(b->out[c]), static_cast<const cpx<T>*>(p.rep_out), p.nx, p.ny, p.kxh,
+                 p.ld_out, p.np_out, (int)blockIdx.x - b->first_nyq[c]);
 }
 
 template <typename T>
@@ -637,12 +653,13 @@ void depth_derive(DepthParams& p) {
 
 int depth_groups_per_block(int cfg) { return NT / kCfgs[cfg].lpm; }
 
+// main launch (every mode, and the Nyquist sign replicas as modes of their
+// own), then one block per Nyquist mode averaging its replicas
 template <typename T, int LPM, int P, bool DISP, bool WANTX>
 hipError_t launch_batch_two(const DepthBatch* dtab, int nb_main, int nb_nyq, hipStream_t st) {
   if (nb_main > 0)
     hipLaunchKernelGGL((k_depth_batch<T, LPM, P, DISP, WANTX, false>), dim3(nb_main), dim3(NT), 0, st, dtab);
-  if (nb_nyq > 0)
-    hipLaunchKernelGGL((k_depth_batch<T, LPM, P, DISP, WANTX, true>), dim3(nb_nyq), dim3(NT), 0, st, dtab);
+  if (nb_nyq > 0) hipLaunchKernelGGL(k_nyq_average_batch<T>, dim3(nb_nyq), dim3(NT), 0, st, dtab);
   return hipGetLastError();
 }
 
@@ -662,8 +679,8 @@ hipError_t launch_depth_batch(const DepthBatch& host, DepthBatch* dtab, int cfg,
   const bool wx = p0.off_stress >= 0;
   for (int c = 0; c < host.n; ++c) {
     const DepthParams& p = host.prm[c];
-    if (!p.mtab || p.nz > kCfgs[cfg].lpm * kCfgs[cfg].p || (p.off_disp >= 0 || p.off_u3 >= 0) != disp ||
-        (p.off_stress >= 0) != wx)
+    if (!p.mtab || !p.rep_out || p.nz > kCfgs[cfg].lpm * kCfgs[cfg].p ||
+        (p.off_disp >= 0 || p.off_u3 >= 0) != disp || (p.off_stress >= 0) != wx)
       return hipErrorInvalidValue;
   }
   // pageable source: the copy is staged before the call returns

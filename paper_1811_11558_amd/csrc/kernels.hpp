@@ -116,12 +116,14 @@ struct alignas(16) ModeConst {
   T s, r, G0, G0p, H0, H0p, iq, pad;
 };
 
-// Depth pass over several grids in one launch per part (main, Nyquist): the
-// host table lists each grid's parameters (derived constants filled by
-// depth_derive), input and output spectra, and the prefix counts of blocks
-// of each part (groups per block: depth_groups_per_block(cfg)); dtab is a
-// device copy target.  Every grid must request the same kinds of output and
-// have nz <= the configuration's capacity.
+// Depth pass over several grids in one launch per part: the host table lists
+// each grid's parameters (derived constants filled by depth_derive, rep_out
+// set: the Nyquist sign replicas are modes of the main launch), input and
+// output spectra, and prefix counts of blocks: first_main for the main launch
+// (modes and replicas, depth_groups_per_block(cfg) per block), first_nyq for
+// the averaging launch (one block per Nyquist mode).  dtab is a device copy
+// target.  Every grid must request the same kinds of output and have nz <=
+// the configuration's capacity.
 constexpr int DEPTH_BATCH_MAX = 8;
 struct DepthBatch {
   int n;

@@ -33,19 +33,31 @@ def _requests():
     return out
 
 
-def _run(server, reqs):
+def _opts(accelerated=False):
     from paper_1811_11558_amd import EPOptions
-    opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14)
+    if accelerated:     # the serving benchmark's options
+        return EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, anderson_m=5,
+                         warm_start=1, inner_rel=0.1)
+    return EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14)
+
+
+def _run(server, reqs, opts=None):
+    opts = opts or _opts()
     ids = [server.submit(g, h, W, precision=prec, opts=opts) for (g, h, W, prec) in reqs]
     return [server.wait(i, (g["ny"], g["nx"])) for i, (g, _, _, _) in zip(ids, reqs)]
 
 
-def test_results_identical_alone_and_in_mix():
+@pytest.mark.parametrize("accelerated", [False, True])
+def test_results_identical_alone_and_in_mix(accelerated):
+    """With Algorithm 1's relaxation and with the accelerated options
+    (Anderson, warm-started and inexact inner solves, as the serving
+    benchmark runs them)."""
     assert torch.cuda.is_available()
     from paper_1811_11558_amd import Server
     reqs = _requests()
+    opts = _opts(accelerated)
     srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
-    mixed = _run(srv, reqs)
+    mixed = _run(srv, reqs, opts)
     st = srv.stats()
     srv.close()
     for r in mixed:
@@ -57,7 +69,7 @@ def test_results_identical_alone_and_in_mix():
     assert overlap
     for k, req in enumerate(reqs):
         alone = Server(hbm_budget_bytes=8 << 30, max_slots=1)
-        a = _run(alone, [req])[0]
+        a = _run(alone, [req], opts)[0]
         alone.close()
         assert np.array_equal(a["p"], mixed[k]["p"]), k
         assert np.array_equal(a["u3p"], mixed[k]["u3p"]), k
