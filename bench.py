@@ -77,6 +77,9 @@ def parse():
                     help="area: rms slopes of the rough surface to run (comma separated)")
     ap.add_argument("--load-steps", type=int, default=5, help="area: equal cumulative load steps")
     ap.add_argument("--seed", type=int, default=0, help="area: seed of the rough surface")
+    ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
+                    help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
+    ap.add_argument("--krylov", type=int, default=0, help="Newton-Krylov: Arnoldi steps per Newton step (0 = 20)")
     a = ap.parse_args()
     dflt = (512, 512, 64) if a.workload == "area" else (256, 256, 64)
     a.nx = a.nx or dflt[0]
@@ -258,7 +261,7 @@ def bench_rough(a):
     Ws = [a.load * (i + 1) / 5 for i in range(5)]
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
                      max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
-                     inner_rel=a.inner_rel)
+                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov)
     V = a.nx * a.ny * a.nz
     runs = {}
     for prec in (["fp64", "fp32_refined"] if a.compare else [a.precision]):
@@ -322,7 +325,7 @@ def bench_area(a):
     kcut = a.nx // 4
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=4000,
                      max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
-                     inner_rel=a.inner_rel)
+                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov)
     rows = []
     for slope in [float(x) for x in a.slopes.split(",")]:
         h = torch.from_numpy(rough_surface(a.nx, a.ny, hurst=0.8, k_roll=2, k_cut=kcut, rms_slope=slope,
@@ -380,7 +383,8 @@ def bench_solve(a):
     h = torch.from_numpy(paraboloid(g, R=0.5)).cuda()
     Ws = [0.002 * (i + 1) for i in range(10)]
     opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, max_outer=2000,
-                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel)
+                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel,
+                     solver=a.solver, krylov_dim=a.krylov)
     times, infos = [], None
     for _ in range(max(1, a.steps)):
         ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=a.precision)
@@ -416,7 +420,8 @@ def bench_serve(a):
                           seed=r["seed"])
         prepared.append((r, g, h))
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
-                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel)
+                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel,
+                     solver=a.solver, krylov_dim=a.krylov)
     srv = Server(hbm_budget_bytes=200 << 30, max_slots=a.slots)
     t0 = time.perf_counter()
     ids = []

@@ -196,7 +196,14 @@ typedef struct {
   double tol_plastic;  /* DF-SANE: |R| <= tol * max(|R0|, |grad_s M[dT]|)   */
   double tol_contact;  /* contact_solve tol                                  */
   int max_outer, max_plastic, max_contact;
-  int solver;          /* 0 = DF-SANE (Sec. 4.3), 1 = Picard fixed point     */
+  int solver;          /* 0 = DF-SANE (Sec. 4.3), 1 = Picard fixed point,    */
+                       /* 2 = Newton-Krylov with the consistent tangent of */
+                       /* the radial return (the alternative Sec. 4.3      */
+                       /* names): GMRES without restart for each step,     */
+                       /* Eisenstat-Walker forcing terms, backtracking on  */
+                       /* |R|; residuals in float64, Jacobian products in  */
+                       /* the operator precision; its basis adds           */
+                       /* (krylov_dim + 2) * 6 nvox doubles                */
   int literal_alg1;    /* 1: overwrite the relaxed update as printed; 0:   */
                        /* keep it (plain under-relaxation, same fixed pt) */
   int anderson_m;      /* 0: Alg. 1 relaxation; 1..6: Anderson acceleration */
@@ -212,6 +219,8 @@ typedef struct {
                        /* previous pass's outer error) while that error is  */
                        /* at least tol_outer; a step is accepted only after */
                        /* a pass solved to tol_plastic; 0: always tol_plastic*/
+  int krylov_dim;      /* Newton-Krylov: Arnoldi steps per Newton step,     */
+                       /* 1..30 (0 = 20); ignored by the other solvers      */
 } fvim_ep_opts;
 
 typedef struct {

@@ -16,6 +16,11 @@ Test infrastructure only (see ``oracle/__init__``).
   quadratic interpolation into [0.1, 0.5] of the previous alpha.  The paper
   gives the iteration but none of these constants; these are the published
   defaults.
+* ``newton_krylov``: Newton's method on the same R with the consistent
+  tangent J v = v - grad_s N[C : d(d_eps_p)/d(d_eps) v] (the alternative
+  Sec. 4.3 names): each linear system J delta = -R solved by GMRES (SciPy)
+  to a tight relative tolerance, the step halved until |R| decreases by the
+  Armijo factor 1 - 1e-4 alpha.
 * ``elastoplastic_solve``: Algorithm 1 over cumulative loads.  The printed
   algorithm overwrites the relaxed surface correction with the unrelaxed one
   at the end of each pass (``literal=True``); by default the relaxed value is
@@ -82,6 +87,40 @@ def dfsane(F, x0, inner, tol_abs, max_iter=500, memory=10, gamma=1e-4,
     return x, Fx, {"iters": k, "evals": nevals, "res": float(np.sqrt(f))}
 
 
+def newton_krylov(F, J, x0, inner, tol_abs, max_iter=50, lin_rtol=1e-12):
+    """Root of F by Newton's method.  J(x, v) is the derivative of F at x
+    applied to v; inner(a, b) the scalar product of the stopping test.
+
+    Returns (x, Fx, info) with the residual norm after every iteration in
+    info["history"]."""
+    from scipy.sparse.linalg import LinearOperator, gmres
+    x = x0
+    Fx = F(x)
+    f = np.sqrt(inner(Fx, Fx))
+    hist = [f]
+    nevals, k = 1, 0
+    shape = x.shape
+    while f > tol_abs and k < max_iter:
+        xk = x
+        A = LinearOperator((x.size, x.size), dtype=float,
+                           matvec=lambda v: J(xk, v.reshape(shape)).ravel())
+        d, status = gmres(A, -Fx.ravel(), rtol=lin_rtol, atol=0.0, restart=200, maxiter=20)
+        d = d.reshape(shape)
+        a = 1.0
+        while True:
+            xn = x + a * d
+            Fn = F(xn)
+            nevals += 1
+            fn = np.sqrt(inner(Fn, Fn))
+            if fn <= (1.0 - 1e-4 * a) * f or a < 1e-10:
+                break
+            a *= 0.5
+        x, Fx, f = xn, Fn, fn
+        hist.append(f)
+        k += 1
+    return x, Fx, {"iters": k, "evals": nevals, "res": float(f), "history": hist}
+
+
 def plasticity(grid, mat, dT, state, tol=1e-13, max_iter=500, solver="dfsane", k0_policy="include"):
     """Strain increment of one load increment with tractions increment dT.
 
@@ -101,6 +140,11 @@ def plasticity(grid, mat, dT, state, tol=1e-13, max_iter=500, solver="dfsane", k
     tol_abs = tol * max(np.sqrt(inner(b, b)), 1e-300)
     if solver == "dfsane":
         de, Rv, info = dfsane(R, b.copy(), inner, tol_abs, max_iter=max_iter)
+    elif solver == "newton":
+        def Jv(de, v):
+            t = pl.return_map_tangent(de, state['sigma'], state['ep'], E, nu, mat['sigma_y0'], mat['E_h'], v)
+            return v - ops.mindlin_apply(grid, E, nu, t, k0_policy=k0_policy)['strain']
+        de, Rv, info = newton_krylov(R, Jv, b.copy(), inner, tol_abs, max_iter=max_iter)
     else:
         de = b.copy()
         Rv = R(de)

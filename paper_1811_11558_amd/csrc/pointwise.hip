@@ -65,6 +65,56 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
   }
 }
 
+// Consistent tangent of the radial return above: the derivative of d_eps_p
+// at the strain increment de in the direction u, written to out.  With
+// d = dev sigma_trial, seq = sqrt(3/2)|d|, d_ep = f / (3 mu + eh) and
+// d_eps_p = (3 d_ep / (2 seq)) d, a change u of de changes d by
+// dd = 2 mu dev(u), seq by (3/2) <d, dd> / seq and d_ep by that over
+// (3 mu + eh); the product rule gives the rest.  The trial state is formed
+// with the same operations as the return map, so the voxels with a nonzero
+// tangent are exactly those the return map at de lets flow; elsewhere the
+// tangent is zero.
+__global__ __launch_bounds__(NT) void k_plastic_tangent(const double* __restrict__ de, const double* __restrict__ u,
+                                                       const double* __restrict__ sn, const double* __restrict__ epn,
+                                                       double* __restrict__ out, size_t V, double lam, double mu,
+                                                       double sy0, double eh) {
+  size_t v = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (v >= V) return;
+  double e[6], s[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    e[c] = de[c * V + v];
+    s[c] = sn[c * V + v];
+  }
+  const double tre = e[0] + e[1] + e[2];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s[c] += 2.0 * mu * e[c] + (c < 3 ? lam * tre : 0.0);
+  const double m = (s[0] + s[1] + s[2]) * (1.0 / 3.0);
+  const double d[6] = {s[0] - m, s[1] - m, s[2] - m, s[3], s[4], s[5]};
+  const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0 * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
+  const double seq = sqrt(1.5 * nn);
+  const double f = seq - (sy0 + eh * epn[v]);
+  if (!(f > 0.0)) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[c * V + v] = 0.0;
+    return;
+  }
+  double dd[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) dd[c] = u[c * V + v];
+  const double um = (dd[0] + dd[1] + dd[2]) * (1.0 / 3.0);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) dd[c] = 2.0 * mu * (c < 3 ? dd[c] - um : dd[c]);
+  const double dn = d[0] * dd[0] + d[1] * dd[1] + d[2] * dd[2] + 2.0 * (d[3] * dd[3] + d[4] * dd[4] + d[5] * dd[5]);
+  const double dseq = 1.5 * dn / seq;
+  const double h = 1.0 / (3.0 * mu + eh);
+  const double dp = f * h, ddp = dseq * h;
+  const double fac = 1.5 * dp / seq;
+  const double dfac = 1.5 * (ddp * seq - dp * dseq) / (seq * seq);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[c * V + v] = dfac * d[c] + fac * dd[c];
+}
+
 // Mean-mode fields in float64 (precision FP32_REFINED).  One thread per
 // depth node: sums the block partials of the 6 eigenstrain planes of that
 // node (and of the 3 traction planes) in a fixed order, forms the laterally
@@ -140,6 +190,15 @@ hipError_t launch_trial_return_map(const double* x, const double* F, double cf, 
   unsigned nb = (unsigned)((nvox + NT - 1) / NT);
   hipLaunchKernelGGL(k_return_map, dim3(nb), dim3(NT), 0, st, x, F, cf, xt, sig_n, ep_n, d_eps_p, nullptr,
                      nullptr, nvox, lam, mu, sy0, eh, layer_flags, lp, zwrite);
+  return hipGetLastError();
+}
+
+hipError_t launch_plastic_tangent(const double* d_eps, const double* u, const double* sig_n, const double* ep_n,
+                                  double* out, size_t nvox, double lam, double mu, double sy0, double eh,
+                                  hipStream_t st) {
+  unsigned nb = (unsigned)((nvox + NT - 1) / NT);
+  hipLaunchKernelGGL(k_plastic_tangent, dim3(nb), dim3(NT), 0, st, d_eps, u, sig_n, ep_n, out, nvox, lam, mu, sy0,
+                     eh);
   return hipGetLastError();
 }
 

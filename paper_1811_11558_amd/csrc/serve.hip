@@ -71,7 +71,8 @@ size_t request_bytes(const fvim_request* r) {
   const fvim_grid& g = r->grid;
   const size_t V = (size_t)g.nx * g.ny * g.nz, ns = (size_t)g.nx * g.ny;
   // operator + solver workspace, plus the caller-side state of a solve
-  return fvim_footprint_bytes(&g, r->precision, 1) + sizeof(double) * (13 * V + 4 * ns + 3 * ns);
+  return fvim_footprint_bytes(&g, r->precision, 1) + sizeof(double) * (13 * V + 4 * ns + 3 * ns) +
+         fvim::krylov_footprint(&g, &r->opts);
 }
 
 int run_job(fvim_server* s, Job* j, hipStream_t st) {

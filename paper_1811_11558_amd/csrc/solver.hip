@@ -364,6 +364,56 @@ __global__ __launch_bounds__(NT) void k_sq2(const double* __restrict__ a1, const
   block_sums<2>(v, part);
 }
 
+// ------------------------------------------ Newton-Krylov (Arnoldi) kernels
+// The Krylov basis u_0 .. u_m is stored contiguously, u_i = base + i n6, not
+// normalised (the host keeps the norms); at most KMAX vectors enter one
+// scalar-product or combination launch.
+constexpr int KMAX = 32;
+struct KCoef {
+  double c[KMAX];
+};
+
+// Weighted <u_i, v> for i < n; blockIdx.y takes the four vectors from
+// 4 blockIdx.y on, v is read once per group of four.  Block b writes
+// part[i * RB + b].
+__global__ __launch_bounds__(NT) void k_kdot(const double* __restrict__ base, int n, const double* __restrict__ v,
+                                            int lp, unsigned nz, size_t n6, double* part) {
+  const int i0 = blockIdx.y * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n6; i += (size_t)gridDim.x * NT) {
+    const double vi = v[i] * field_weight(i, lp, nz);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i0 + k < n) acc[k] += base[(size_t)(i0 + k) * n6 + i] * vi;
+  }
+  block_sums<4>(acc, part + (size_t)i0 * RB);
+}
+
+// y = a v + sum_{i<n} c_i u_i (v may be NULL; y may be v), with the block
+// sums of the weighted <y, y> when part is given.
+__global__ __launch_bounds__(NT) void k_kcomb(double* y, const double* v, double a, const double* __restrict__ base,
+                                             int n, KCoef kc, size_t n6, int lp, unsigned nz, double* part) {
+  __shared__ double cs[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (threadIdx.x == j) cs[j] = kc.c[j];
+  __syncthreads();
+  double nn[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n6; i += (size_t)gridDim.x * NT) {
+    double r = v ? a * v[i] : 0.0;
+    for (int j = 0; j < n; ++j) r += cs[j] * base[(size_t)j * n6 + i];
+    y[i] = r;
+    nn[0] += field_weight(i, lp, nz) * r * r;
+  }
+  if (part) block_sums<1>(nn, part);
+}
+
+// out[k] = sum of the nb partials of row k, one block per row, fixed order.
+__global__ __launch_bounds__(NT) void k_kfinal(const double* __restrict__ part, int nb, double* out) {
+  const double r = final_sum(part, blockIdx.x, nb);
+  if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
 // ------------------------------------------- Anderson acceleration (outer)
 constexpr int AA_MMAX = 6;
 constexpr int aa_nsums(int m) { return m * (m + 1) / 2 + m; }
@@ -464,6 +514,13 @@ struct SolverWork {
   int rg_next = 0;
   int rg_warm[2] = {0, 0};       // an eager evaluation has sized every buffer (per precision)
   int cap_fail = 0;              // failed captures; from CAP_TRIES on, launch directly
+  // Newton-Krylov: basis u_0 .. u_m and the Newton step, [kry_m + 2][6 V];
+  // scalar-product partials [KMAX][RB]; their totals (mapped host memory)
+  double* kry = nullptr;
+  int kry_m = 0;
+  double* kry_part = nullptr;
+  double* kry_out = nullptr;     // device view
+  double* kry_hout = nullptr;    // host view
 };
 
 constexpr int CAP_TRIES = 4;
@@ -543,6 +600,9 @@ void solver_release(fvim_ctx* c) {
   if (w->aa) hipFree(w->aa);
   if (w->aa_part) hipFree(w->aa_part);
   if (w->aa_hout) hipHostFree(w->aa_hout);
+  if (w->kry) hipFree(w->kry);
+  if (w->kry_part) hipFree(w->kry_part);
+  if (w->kry_hout) hipHostFree(w->kry_hout);
   for (auto& r : w->rg) {
     if (r.ex) hipGraphExecDestroy(r.ex);
     if (r.g) hipGraphDestroy(r.g);
@@ -1013,6 +1073,214 @@ static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, 
   return FVIM_OK;
 }
 
+// ------------------------------------------------------ Newton-Krylov
+static int krylov_dim(const fvim_ep_opts* o) { return o->krylov_dim > 0 ? o->krylov_dim : 20; }
+
+size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o) {
+  if (!o || o->solver != 2) return 0;
+  const size_t V = (size_t)g->nx * g->ny * g->nz;
+  return sizeof(double) * (6 * V * (size_t)(krylov_dim(o) + 2) + (size_t)KMAX * (RB + 1));
+}
+
+static int kry_ensure(fvim_ctx* c, int m) {
+  SolverWork* w = c->sw;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
+  if (!w->kry || w->kry_m < m) {
+    if (w->kry) {
+      hipStreamSynchronize(c->stream);
+      hipFree(w->kry);
+      w->kry = nullptr;
+      w->kry_m = 0;
+    }
+    if (hipMalloc((void**)&w->kry, sizeof(double) * 6 * w->V * (size_t)(m + 2)) != hipSuccess)
+      return fail(FVIM_ENOMEM, "Krylov basis allocation failed");
+    w->kry_m = m;
+  }
+  if (!w->kry_part && hipMalloc((void**)&w->kry_part, sizeof(double) * KMAX * RB) != hipSuccess) {
+    w->kry_part = nullptr;
+    return fail(FVIM_ENOMEM, "Krylov workspace allocation failed");
+  }
+  if (!w->kry_hout) {
+    if (hipHostMalloc((void**)&w->kry_hout, sizeof(double) * KMAX, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&w->kry_out, w->kry_hout, 0) != hipSuccess) {
+      if (w->kry_hout) hipHostFree(w->kry_hout);
+      w->kry_hout = nullptr;
+      return fail(FVIM_ENOMEM, "Krylov workspace allocation failed");
+    }
+  }
+  return FVIM_OK;
+}
+
+// out[i] = <u_i, v> (weighted, unscaled) for the first n basis vectors.
+static int kdots(fvim_ctx* c, const double* base, int n, const double* v, double* out) {
+  SolverWork* w = c->sw;
+  const size_t n6 = 6 * w->V;
+  const int nb = nblocks(n6);
+  hipLaunchKernelGGL(k_kdot, dim3(nb, (n + 3) / 4), dim3(NT), 0, c->stream, base, n, v, w->lp,
+                     (unsigned)c->grid.nz, n6, w->kry_part);
+  hipLaunchKernelGGL(k_kfinal, dim3(n), dim3(NT), 0, c->stream, w->kry_part, nb, w->kry_out);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e, "Krylov scalar products");
+  for (int i = 0; i < n; ++i) out[i] = w->kry_hout[i];
+  return FVIM_OK;
+}
+
+// y = a v + sum_{i<n} coef_i u_i; with norm2, its weighted (unscaled) <y, y>.
+static int kcomb(fvim_ctx* c, double* y, const double* v, double a, const double* base, int n, const double* coef,
+                 double* norm2) {
+  SolverWork* w = c->sw;
+  const size_t n6 = 6 * w->V;
+  const int nb = nblocks(n6);
+  KCoef kc = {};
+  for (int i = 0; i < n; ++i) kc.c[i] = coef[i];
+  hipLaunchKernelGGL(k_kcomb, dim3(nb), dim3(NT), 0, c->stream, y, v, a, base, n, kc, n6, w->lp,
+                     (unsigned)c->grid.nz, norm2 ? w->kry_part : nullptr);
+  if (!norm2) {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FVIM_OK : fail_hip(e, "Krylov combination");
+  }
+  hipLaunchKernelGGL(k_kfinal, dim3(1), dim3(NT), 0, c->stream, w->kry_part, nb, w->kry_out);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail_hip(e, "Krylov combination");
+  *norm2 = w->kry_hout[0];
+  return FVIM_OK;
+}
+
+// W = J u = u - grad_s N[C : T u], T the consistent tangent of the radial
+// return at the current iterate pb.x (eqn incremental_strain differentiated;
+// the traction term is constant), in the context's operator precision; the
+// tangent vanishes below the deepest plastic layer of the last return map
+// at pb.x, which the operator skips.  The weighted <W, W> goes to the
+// S_DOT0 slot and its host mirror.
+static int jacobian_apply(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* u, double* D, double* W) {
+  SolverWork* w = c->sw;
+  hipError_t e = launch_plastic_tangent(pb.x, u, s->sigma, s->ep, D, w->V, c->lam, c->mu, c->mat.sigma_y0,
+                                        c->mat.E_h, c->stream);
+  if (e != hipSuccess) return fail_hip(e, "plastic tangent");
+  int nb = 0;
+  int rc = operator_apply_resid(c, D, nullptr, u, nullptr, W, w->rpart, &nb, w->layers + c->grid.nz);
+  if (rc) return rc;
+  if (nb > w->rpart_count) return fail(FVIM_EINVAL, "residual partial sums: workspace too small");
+  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(NTS), 0, c->stream, w->rpart, nb, w->sc, w->dmap);
+  return FVIM_OK;
+}
+
+// Inexact Newton on R[d_eps] = 0 from pb.x to |R| <= tol_abs (Sec. 4.3
+// names Newton-Krylov with the consistent tangent as the alternative to
+// DF-SANE).  Each step solves J delta = -R by GMRES without restart, at most
+// m Arnoldi steps (classical Gram-Schmidt, repeated once when it cancels more
+// than 30 % of the new vector), to the relative residual eta of Eisenstat
+// and Walker (1996), choice 2 (gamma 0.9, exponent 2, their safeguard,
+// eta <= 0.5 and not below half the final tolerance over |R|); then
+// x + alpha delta, alpha halved until |R| falls by the factor
+// 1 - 1e-4 alpha (1 - eta).  Residuals are always float64; the
+// Jacobian-vector products use the context's operator precision (float32
+// in the FP32_REFINED mode: an inexact Jacobian slows the last steps, it
+// does not move the root).  evals counts residuals and Jacobian products.
+static int newton_krylov(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, double tol_abs,
+                         int max_it, int* iters, int* evals, double* fout) {
+  SolverWork* w = c->sw;
+  const size_t n6 = 6 * w->V;
+  const int m = krylov_dim(o);
+  if (!w->kry || w->kry_m < m || !w->kry_part || !w->kry_hout)
+    return fail(FVIM_EINVAL, "Newton-Krylov workspace not reserved");
+  double* U = w->kry;
+  double* step = U + (size_t)(m + 1) * n6;
+  const double sc = inner_scale(c);
+  double f;
+  int rc;
+  {
+    Fp64Scope f64(c, 1);
+    if ((rc = residual(c, s, pb, pb.x, nullptr, 0.0, nullptr, pb.F, &f))) return rc;
+  }
+  int ne = 1, k = 0;
+  double eta = 0.5, fprev = f;
+  std::vector<double> H((size_t)(m + 1) * m), gc(m), gs(m), g(m + 1), sv(m + 1), y(m);
+  double d[KMAX], coef[KMAX];
+  auto h = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+  while (std::sqrt(f) > tol_abs && k < max_it) {
+    if (k > 0) {
+      const double e2 = 0.9 * f / fprev, sg = 0.9 * eta * eta;
+      eta = std::min(0.5, sg > 0.1 ? std::max(e2, sg) : e2);
+    }
+    eta = std::max(eta, 0.5 * tol_abs / std::sqrt(f));
+    const double rn = std::sqrt(f / sc);       // |R| in the unscaled weighted norm
+    hipError_t e = hipMemcpyAsync(U, pb.F, sizeof(double) * n6, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "copy");
+    std::fill(g.begin(), g.end(), 0.0);
+    sv[0] = rn;
+    g[0] = -rn;                                // -R = -rn q_0
+    int kd = 0;
+    for (int j = 0; j < m; ++j) {
+      const double* uj = U + (size_t)j * n6;
+      double* un = U + (size_t)(j + 1) * n6;
+      if ((rc = jacobian_apply(c, s, pb, uj, pb.xt, pb.Ft))) return rc;
+      if ((rc = kdots(c, U, j + 1, pb.Ft, d))) return rc;
+      const double jn = std::sqrt(w->hmap[S_DOT0]) / sv[j];     // |J q_j|
+      for (int i = 0; i <= j; ++i) {
+        h(i, j) = d[i] / (sv[i] * sv[j]);
+        coef[i] = -h(i, j) / sv[i];
+      }
+      double n2;
+      if ((rc = kcomb(c, un, pb.Ft, 1.0 / sv[j], U, j + 1, coef, &n2))) return rc;
+      if (std::sqrt(n2) < 0.7 * jn) {
+        if ((rc = kdots(c, U, j + 1, un, d))) return rc;
+        for (int i = 0; i <= j; ++i) {
+          h(i, j) += d[i] / sv[i];
+          coef[i] = -d[i] / (sv[i] * sv[i]);
+        }
+        if ((rc = kcomb(c, un, un, 1.0, U, j + 1, coef, &n2))) return rc;
+      }
+      sv[j + 1] = std::sqrt(n2);
+      h(j + 1, j) = sv[j + 1];
+      for (int i = 0; i < j; ++i) {            // earlier rotations on column j
+        const double a = h(i, j), b = h(i + 1, j);
+        h(i, j) = gc[i] * a + gs[i] * b;
+        h(i + 1, j) = -gs[i] * a + gc[i] * b;
+      }
+      const double a = h(j, j), b = h(j + 1, j), r = std::hypot(a, b);
+      gc[j] = r > 0.0 ? a / r : 1.0;
+      gs[j] = r > 0.0 ? b / r : 0.0;
+      h(j, j) = r;
+      h(j + 1, j) = 0.0;
+      g[j + 1] = -gs[j] * g[j];
+      g[j] = gc[j] * g[j];
+      kd = j + 1;
+      ++ne;
+      if (std::fabs(g[j + 1]) <= eta * rn || !(sv[j + 1] > 1e-13 * jn)) break;
+    }
+    for (int i = kd - 1; i >= 0; --i) {         // H y = g, upper triangular
+      double t = g[i];
+      for (int l = i + 1; l < kd; ++l) t -= h(i, l) * y[l];
+      if (h(i, i) == 0.0) return fail(FVIM_ENOCONV, "Newton-Krylov: singular Hessenberg matrix");
+      y[i] = t / h(i, i);
+    }
+    for (int i = 0; i < kd; ++i) coef[i] = y[i] / sv[i];
+    if ((rc = kcomb(c, step, nullptr, 0.0, U, kd, coef, nullptr))) return rc;
+    double alpha = 1.0, fn;
+    for (int guard = 0;; ++guard) {
+      {
+        Fp64Scope f64(c, 1);
+        if ((rc = residual(c, s, pb, pb.x, step, alpha, pb.xt, pb.Ft, &fn))) return rc;
+      }
+      ++ne;
+      if (std::sqrt(fn) <= (1.0 - 1e-4 * alpha * (1.0 - eta)) * std::sqrt(f)) break;
+      if (guard >= 30) return fail(FVIM_ENOCONV, "Newton-Krylov line search failed");
+      alpha *= 0.5;
+    }
+    std::swap(pb.x, pb.xt);
+    std::swap(pb.F, pb.Ft);
+    fprev = f;
+    f = fn;
+    ++k;
+  }
+  *iters += k;
+  *evals += ne;
+  *fout = f;
+  return FVIM_OK;
+}
+
 // Solves R[d_eps] = 0 for the traction increment dT ([3][ny][nx]); on
 // return pb.x holds d_eps, pb.dep / pb.dp the plastic increments.  In the
 // FP32_REFINED mode the iteration first runs on the float32 operator down to
@@ -1050,15 +1318,19 @@ static int plasticity(fvim_ctx* c, const double* dT, const fvim_state* s, const 
   double f = 0.0;
   const bool mixed = c->precision == FVIM_FP32_REFINED;
   const double tol32 = 3e-6 * bn;
-  // an inexact solve (target above tol_plastic) at or above the float32
-  // floor stays in float32; every other solve ends on the float64 operator
-  const bool only32 = mixed && tol_rel > o->tol_plastic && tol_abs >= tol32;
-  if (mixed && (tol32 > tol_abs || only32)) {
-    if ((rc = fixed_point(c, s, o, pb, std::max(tol32, tol_abs), o->max_plastic, iters, evals, &f))) return rc;
-  }
-  if (!only32) {
-    Fp64Scope f64(c, mixed ? 1 : c->force_fp64);
-    if ((rc = fixed_point(c, s, o, pb, tol_abs, o->max_plastic, iters, evals, &f))) return rc;
+  if (o->solver == 2) {
+    if ((rc = newton_krylov(c, s, o, pb, tol_abs, o->max_plastic, iters, evals, &f))) return rc;
+  } else {
+    // an inexact solve (target above tol_plastic) at or above the float32
+    // floor stays in float32; every other solve ends on the float64 operator
+    const bool only32 = mixed && tol_rel > o->tol_plastic && tol_abs >= tol32;
+    if (mixed && (tol32 > tol_abs || only32)) {
+      if ((rc = fixed_point(c, s, o, pb, std::max(tol32, tol_abs), o->max_plastic, iters, evals, &f))) return rc;
+    }
+    if (!only32) {
+      Fp64Scope f64(c, mixed ? 1 : c->force_fp64);
+      if ((rc = fixed_point(c, s, o, pb, tol_abs, o->max_plastic, iters, evals, &f))) return rc;
+    }
   }
   // plastic increments of the accepted iterate
   e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, nullptr, w->V, c->lam, c->mu, c->mat.sigma_y0,
@@ -1177,7 +1449,8 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
   if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
   if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1 || o->anderson_m < 0 ||
-      o->anderson_m > AA_MMAX || !(o->inner_rel >= 0))
+      o->anderson_m > AA_MMAX || !(o->inner_rel >= 0) || o->solver < 0 || o->solver > 2 || o->krylov_dim < 0 ||
+      o->krylov_dim > KMAX - 2)
     return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
   int rc = sw_ensure(c);
   if (rc) return rc;
@@ -1196,6 +1469,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   double* dT = w->surf + 12 * n;      // 3 planes: 12, 13, 14
   const int aam = o->literal_alg1 ? 0 : o->anderson_m;
   if (aam > 0 && (rc = aa_ensure(c))) return rc;
+  if (o->solver == 2 && (rc = kry_ensure(c, krylov_dim(o)))) return rc;
   // every buffer the operator applications of the solve use, sized now: no
   // device memory is freed or allocated while the solve runs
   if ((rc = operator_reserve(c, pb.dep, dT, pb.F))) return rc;

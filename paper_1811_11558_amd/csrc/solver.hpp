@@ -84,4 +84,11 @@ int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* tractio
 int operator_resid_parts(const fvim_grid& g);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
+// Device bytes the Newton-Krylov solver adds when opts selects it (0 else).
+size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o);
+// out = the directional derivative of the radial return's d_eps_p at the
+// strain increment d_eps in the direction u (all [6][nvox]).
+hipError_t launch_plastic_tangent(const double* d_eps, const double* u, const double* sig_n, const double* ep_n,
+                                  double* out, size_t nvox, double lam, double mu, double sy0, double eh,
+                                  hipStream_t st);
 }  // namespace fvim

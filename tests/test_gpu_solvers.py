@@ -117,12 +117,14 @@ def test_flat_surface_elastoplastic_closed_form():
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hertz_ep_16x16x8.npz")
 
 
-@pytest.mark.parametrize("solver", [0, 1])
-def test_hertz_elastoplastic_matches_stored_oracle(solver):
+@pytest.mark.parametrize("solver,kdim", [(0, 0), (1, 0), (2, 0), (2, 3)])
+def test_hertz_elastoplastic_matches_stored_oracle(solver, kdim):
     """Paraboloid R = 2 L on 16 x 16 x 8 (lz = 0.25 L), two load steps with
     Hertz peak pressures of about 2 and 3 times first yield: the GPU
-    Algorithm 1 (DF-SANE or Picard inside) reproduces the oracle's converged
-    state stored by tests/golden/make_golden.py."""
+    Algorithm 1 (DF-SANE, Picard or Newton-Krylov inside; the last also with
+    a Krylov space of 3, which truncates most linear solves) reproduces the
+    oracle's converged state stored by tests/golden/make_golden.py (computed
+    with DF-SANE: the root, not the iteration, is compared)."""
     from paper_1811_11558_amd import EPOptions
     ref = np.load(GOLDEN)
     g = grid_dict(16, 16, 8, lz=0.25)
@@ -130,9 +132,14 @@ def test_hertz_elastoplastic_matches_stored_oracle(solver):
     st = ctx.new_state()
     infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
                                     EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13,
-                                              tol_contact=1e-15, solver=solver, max_plastic=20000))
+                                              tol_contact=1e-15, solver=solver, max_plastic=20000,
+                                              krylov_dim=kdim))
     torch.cuda.synchronize()
     _say(infos)
+    if solver == 2 and kdim == 0:
+        # Newton: a handful of steps per plasticity solve, not tens
+        for i in infos:
+            assert i["plastic_iters"] <= 12 * i["outer_iters"], i
     for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
         err = _rel(st[k].cpu().numpy(), ref[k])
         _say(k, err)
@@ -168,8 +175,9 @@ def test_anderson_outer_reaches_the_stored_fixed_point():
 ROUGH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "rough_ep_16x16x8.npz")
 
 
-@pytest.mark.parametrize("precision,accel", [("fp64", False), ("fp32_refined", True)])
-def test_rough_surface_experiment_setting_matches_stored_oracle(precision, accel):
+@pytest.mark.parametrize("precision,accel,solver", [("fp64", False, 0), ("fp32_refined", True, 0),
+                                                   ("fp64", False, 2), ("fp32_refined", True, 2)])
+def test_rough_surface_experiment_setting_matches_stored_oracle(precision, accel, solver):
     """The rough-surface experiment's geometry and material (lz = 0.4 L,
     sigma_y = 0.1 E, E_h = 0.01 E, H = 0.8, PSD plateau for 1 <= |k| < 2) on a
     16 x 16 x 8 grid, stored by tests/golden/make_golden.py: the GPU's
@@ -177,7 +185,8 @@ def test_rough_surface_experiment_setting_matches_stored_oracle(precision, accel
     reproduce the oracle's, and so do both contact areas.  In float64 with
     the oracle's relaxation the bound is rounding (1e-11); with FP32 kernels
     and the accelerated outer/inner iteration it is what the tolerances
-    allow (1e-8)."""
+    allow (1e-8).  Solver 2 (Newton-Krylov) replaces DF-SANE inside; its
+    Jacobian products are float32 in the FP32_REFINED mode."""
     from paper_1811_11558_amd import Context, EPOptions
     ref = np.load(ROUGH)
     g = grid_dict(16, 16, 8, lz=0.4)
@@ -192,8 +201,9 @@ def test_rough_surface_experiment_setting_matches_stored_oracle(precision, accel
     assert err < 1e-11
     st = ctx.new_state()
     opts = (EPOptions(tol_outer=1e-12, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000,
-                      anderson_m=5, warm_start=1, inner_rel=0.1) if accel else
-            EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000))
+                      anderson_m=5, warm_start=1, inner_rel=0.1, solver=solver) if accel else
+            EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000,
+                      solver=solver))
     infos = ctx.elastoplastic_solve(h, W, st, opts)
     torch.cuda.synchronize()
     _say(precision, [(i["outer_iters"], i["r_evals"]) for i in infos])
@@ -284,3 +294,18 @@ def test_contact_graph_replay_equals_eager():
     _say("iterations graph / eager", ig, ie)
     assert ig == ie == ig2
     assert np.array_equal(pg, pe) and np.array_equal(pg, pg2)
+
+
+def test_newton_krylov_options_are_checked():
+    """An unknown solver id or a Krylov dimension beyond 30 is rejected
+    before any work; the state is left as it was."""
+    from paper_1811_11558_amd import EPOptions
+    ref = np.load(GOLDEN)
+    g = grid_dict(16, 16, 8, lz=0.25)
+    ctx = _ctx(g)
+    st = ctx.new_state()
+    for bad in (EPOptions(solver=3), EPOptions(solver=2, krylov_dim=31), EPOptions(solver=2, krylov_dim=-1)):
+        with pytest.raises(RuntimeError, match="bad options"):
+            ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), [float(ref["W"][0])], st, bad)
+    assert float(st["ep"].abs().max()) == 0.0
+    ctx.close()

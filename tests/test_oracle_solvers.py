@@ -225,3 +225,84 @@ def test_hertz_elastoplastic_certificates():
     for inf in infos:
         assert inf["outer_err"] < 1e-10
         assert inf["contact"]["kkt_residual"] < 1e-9
+
+
+# ------------------------------------------------- consistent tangent --
+def _plastic_points(rng, n):
+    """Random states, each at least 5 % away from the yield surface in f."""
+    d_eps, sig, ep = _rand_state(rng, (n,), 0.004)
+    sig_tr = sig + elastic.hooke(d_eps, E, NU)
+    f = pl.von_mises(sig_tr) - (SY + EH * ep)
+    keep = np.abs(f) > 0.05 * SY
+    return d_eps[:, keep], sig[:, keep], ep[keep], f[keep] > 0
+
+
+def test_return_map_tangent_matches_central_differences():
+    rng = np.random.default_rng(11)
+    d_eps, sig, ep, flow = _plastic_points(rng, 400)
+    assert 0.2 < flow.mean() < 0.9
+    v = rng.standard_normal(d_eps.shape) * 1e-3
+    h = 1e-5
+    p1, _, _ = pl.return_map(d_eps + h * v, sig, ep, E, NU, SY, EH)
+    p0, _, _ = pl.return_map(d_eps - h * v, sig, ep, E, NU, SY, EH)
+    fd = (p1 - p0) / (2 * h)
+    t = pl.return_map_tangent(d_eps, sig, ep, E, NU, SY, EH, v)
+    assert np.all(t[:, ~flow] == 0.0)
+    err = np.max(np.abs(t - fd), axis=0)[flow] / np.max(np.abs(fd), axis=0)[flow]
+    assert err.max() < 1e-7
+
+
+def test_return_map_tangent_matches_the_algorithmic_modulus():
+    """Closed form of the algorithmic (consistent) tangent modulus of the
+    radial return with linear isotropic hardening (Simo and Taylor 1985;
+    Simo and Hughes, Computational Inelasticity, Box 3.2): with n the unit
+    trial deviator, dg the consistency parameter (|d_eps_p| = dg) and
+    theta = 1 - 2 mu dg / |s_tr|, thetab = 1 / (1 + E_h / (3 mu)) - (1 - theta),
+    C_alg : v = K tr(v) 1 + 2 mu theta dev(v) - 2 mu thetab n <n, v>.  Since
+    sigma = sigma_tr - 2 mu d_eps_p, the tangent of d_eps_p is
+    (C : v - C_alg : v) / (2 mu)."""
+    rng = np.random.default_rng(12)
+    d_eps, sig, ep, flow = _plastic_points(rng, 300)
+    d_eps, sig, ep = d_eps[:, flow], sig[:, flow], ep[flow]
+    v = rng.standard_normal(d_eps.shape)
+    w = elastic.VOIGT_WEIGHT[:, None]
+    sig_tr = sig + elastic.hooke(d_eps, E, NU)
+    mean = (sig_tr[0] + sig_tr[1] + sig_tr[2]) / 3
+    s_tr = sig_tr - mean * np.array([1, 1, 1, 0, 0, 0])[:, None]
+    snorm = np.sqrt(np.sum(w * s_tr ** 2, 0))
+    n = s_tr / snorm
+    dep, dp, _ = pl.return_map(d_eps, sig, ep, E, NU, SY, EH)
+    dg = np.sqrt(np.sum(w * dep ** 2, 0))
+    theta = 1 - 2 * MU * dg / snorm
+    thetab = 1 / (1 + EH / (3 * MU)) - (1 - theta)
+    K = LAM + 2 * MU / 3
+    trv = v[0] + v[1] + v[2]
+    devv = v - trv / 3 * np.array([1, 1, 1, 0, 0, 0])[:, None]
+    calg = (K * trv * np.array([1, 1, 1, 0, 0, 0])[:, None] + 2 * MU * theta * devv
+            - 2 * MU * thetab * n * np.sum(w * n * v, 0))
+    expect = (elastic.hooke(v, E, NU) - calg) / (2 * MU)
+    t = pl.return_map_tangent(d_eps, sig, ep, E, NU, SY, EH, v)
+    assert np.max(np.abs(t - expect)) < 1e-13 * np.max(np.abs(expect))
+
+
+def test_newton_krylov_reaches_the_dfsane_root_superlinearly():
+    """Newton with the consistent tangent and DF-SANE (different algorithms)
+    find the same root; the Newton residuals fall faster than linearly."""
+    g = grid_dict(16, 16, 8, lz=0.25)
+    mat = dict(E=E, nu=NU, sigma_y0=SY, E_h=EH)
+    h = paraboloid(g, R=0.5)
+    p, _, _ = oc.contact_solve(h, 0.002, g, E, NU, tol=1e-14)
+    dT = np.zeros((3, 16, 16))
+    dT[2] = -p
+    st = cp.new_state(g)
+    a = cp.plasticity(g, mat, dT, st, tol=1e-12, solver="dfsane")
+    b = cp.plasticity(g, mat, dT, st, tol=1e-12, solver="newton")
+    assert np.count_nonzero(a['d_ep']) > 20
+    hist = b['info']['history']
+    assert b['info']['iters'] <= 12
+    assert hist[-1] < 1e-12 * hist[0] * 10
+    # the last reductions outpace the first (superlinear tail)
+    assert hist[-1] / hist[-2] < 1e-2
+    scale = np.max(np.abs(a['d_eps']))
+    assert np.max(np.abs(a['d_eps'] - b['d_eps'])) < 1e-10 * scale
+    assert np.max(np.abs(a['d_eps_p'] - b['d_eps_p'])) < 1e-9 * np.max(np.abs(a['d_eps_p']))
