@@ -240,6 +240,9 @@ def bench_batch(a):
                                  ", ".join("%dx%dx%d" % s_ for s_ in shapes)}}))
 
 
+SOLVER_NAMES = {0: "dfsane", 1: "picard", 2: "newton_krylov"}
+
+
 def bench_rough(a):
     """Elastoplastic contact of a self-affine rough surface (flat PSD below
     k_roll, power law with Hurst exponent H up to k_cut, rms slope 0.1, seed
@@ -282,7 +285,7 @@ def bench_rough(a):
            "config": {"workload": "rough elastoplastic contact %dx%dx%d" % (a.nx, a.ny, a.nz), "hurst": a.hurst,
                       "k_roll": a.k_roll, "k_cut": kcut, "rms_slope": 0.1, "W": a.load, "load_steps": 5,
                       "tol_outer": 1e-7, "anderson": a.anderson, "warm_start": a.warm,
-                      "inner_rel": a.inner_rel}}
+                      "inner_rel": a.inner_rel, "solver": SOLVER_NAMES[a.solver], "krylov_dim": a.krylov}}
     for prec, r in runs.items():
         out[prec] = {k: v for k, v in r.items() if k != "state"}
         p = r["state"]["traction"][2]
@@ -399,8 +402,10 @@ def bench_solve(a):
     print(json.dumps({"metric": "elastoplastic solve time", "value": float(np.median(times)), "unit": "s",
                       "higher_is_better": False, "n_gpus": 1, "steps": len(times),
                       "config": {"workload": "paraboloid 32x32x16, W=0.02 in 10 steps", "precision": a.precision,
-                                 "anderson": a.anderson, "warm_start": a.warm, "inner_rel": a.inner_rel},
+                                 "anderson": a.anderson, "warm_start": a.warm, "inner_rel": a.inner_rel,
+                                 "solver": SOLVER_NAMES[a.solver], "krylov_dim": a.krylov},
                       "outer_iters": [i["outer_iters"] for i in infos], "residual_evals": ev,
+                      "plastic_iters": sum(i["plastic_iters"] for i in infos),
                       "voxel_updates_per_s": ev * 32 * 32 * 16 / float(np.median(times))}))
 
 

@@ -65,21 +65,22 @@ __global__ __launch_bounds__(NT) void k_return_map(const double* __restrict__ de
   }
 }
 
-// Consistent tangent of the radial return above: the derivative of d_eps_p
-// at the strain increment de in the direction u, written to out.  With
-// d = dev sigma_trial, seq = sqrt(3/2)|d|, d_ep = f / (3 mu + eh) and
+// Consistent tangent T of the radial return above at the strain increment
+// de: out = base - T (u1 - u2) (base, u2 may be NULL), for the voxels
+// v < na of each component (component stride V).  With d = dev
+// sigma_trial, seq = sqrt(3/2)|d|, d_ep = f / (3 mu + eh) and
 // d_eps_p = (3 d_ep / (2 seq)) d, a change u of de changes d by
 // dd = 2 mu dev(u), seq by (3/2) <d, dd> / seq and d_ep by that over
 // (3 mu + eh); the product rule gives the rest.  The trial state is formed
-// with the same operations as the return map, so the voxels with a nonzero
-// tangent are exactly those the return map at de lets flow; elsewhere the
-// tangent is zero.
-__global__ __launch_bounds__(NT) void k_plastic_tangent(const double* __restrict__ de, const double* __restrict__ u,
+// with the same operations as the return map, so T is nonzero exactly on
+// the voxels the return map at de lets flow.
+__global__ __launch_bounds__(NT) void k_plastic_tangent(const double* __restrict__ de, const double* u1,
+                                                       const double* u2, const double* base,
                                                        const double* __restrict__ sn, const double* __restrict__ epn,
-                                                       double* __restrict__ out, size_t V, double lam, double mu,
+                                                       double* out, size_t na, size_t V, double lam, double mu,
                                                        double sy0, double eh) {
   size_t v = (size_t)blockIdx.x * NT + threadIdx.x;
-  if (v >= V) return;
+  if (v >= na) return;
   double e[6], s[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
@@ -94,14 +95,17 @@ __global__ __launch_bounds__(NT) void k_plastic_tangent(const double* __restrict
   const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + 2.0 * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5]);
   const double seq = sqrt(1.5 * nn);
   const double f = seq - (sy0 + eh * epn[v]);
+  double b[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) b[c] = base ? base[c * V + v] : 0.0;
   if (!(f > 0.0)) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) out[c * V + v] = 0.0;
+    for (int c = 0; c < 6; ++c) out[c * V + v] = b[c];
     return;
   }
   double dd[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) dd[c] = u[c * V + v];
+  for (int c = 0; c < 6; ++c) dd[c] = u1[c * V + v] - (u2 ? u2[c * V + v] : 0.0);
   const double um = (dd[0] + dd[1] + dd[2]) * (1.0 / 3.0);
 #pragma unroll
   for (int c = 0; c < 6; ++c) dd[c] = 2.0 * mu * (c < 3 ? dd[c] - um : dd[c]);
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(NT) void k_plastic_tangent(const double* __restrict
   const double fac = 1.5 * dp / seq;
   const double dfac = 1.5 * (ddp * seq - dp * dseq) / (seq * seq);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) out[c * V + v] = dfac * d[c] + fac * dd[c];
+  for (int c = 0; c < 6; ++c) out[c * V + v] = b[c] - (dfac * d[c] + fac * dd[c]);
 }
 
 // Mean-mode fields in float64 (precision FP32_REFINED).  One thread per
@@ -193,12 +197,13 @@ hipError_t launch_trial_return_map(const double* x, const double* F, double cf, 
   return hipGetLastError();
 }
 
-hipError_t launch_plastic_tangent(const double* d_eps, const double* u, const double* sig_n, const double* ep_n,
-                                  double* out, size_t nvox, double lam, double mu, double sy0, double eh,
-                                  hipStream_t st) {
-  unsigned nb = (unsigned)((nvox + NT - 1) / NT);
-  hipLaunchKernelGGL(k_plastic_tangent, dim3(nb), dim3(NT), 0, st, d_eps, u, sig_n, ep_n, out, nvox, lam, mu, sy0,
-                     eh);
+hipError_t launch_plastic_tangent(const double* d_eps, const double* u1, const double* u2, const double* base,
+                                  const double* sig_n, const double* ep_n, double* out, size_t na, size_t nvox,
+                                  double lam, double mu, double sy0, double eh, hipStream_t st) {
+  if (na == 0) return hipSuccess;
+  unsigned nb = (unsigned)((na + NT - 1) / NT);
+  hipLaunchKernelGGL(k_plastic_tangent, dim3(nb), dim3(NT), 0, st, d_eps, u1, u2, base, sig_n, ep_n, out, na, nvox,
+                     lam, mu, sy0, eh);
   return hipGetLastError();
 }
 

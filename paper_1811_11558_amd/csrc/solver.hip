@@ -365,7 +365,9 @@ __global__ __launch_bounds__(NT) void k_sq2(const double* __restrict__ a1, const
 }
 
 // ------------------------------------------ Newton-Krylov (Arnoldi) kernels
-// The Krylov basis u_0 .. u_m is stored contiguously, u_i = base + i n6, not
+// Krylov vectors are [6][nz][plane] fields of which only the voxels v < na
+// of each component (the layers above the deepest plastic one) take part;
+// the basis u_0 .. u_m is stored contiguously, u_i = base + 6 i V, not
 // normalised (the host keeps the norms); at most KMAX vectors enter one
 // scalar-product or combination launch.
 constexpr int KMAX = 32;
@@ -373,37 +375,48 @@ struct KCoef {
   double c[KMAX];
 };
 
-// Weighted <u_i, v> for i < n; blockIdx.y takes the four vectors from
-// 4 blockIdx.y on, v is read once per group of four.  Block b writes
+// Weighted <u_i, x> for i < n; blockIdx.y takes the four vectors from
+// 4 blockIdx.y on, x is read once per group of four.  Block b writes
 // part[i * RB + b].
-__global__ __launch_bounds__(NT) void k_kdot(const double* __restrict__ base, int n, const double* __restrict__ v,
-                                            int lp, unsigned nz, size_t n6, double* part) {
+__global__ __launch_bounds__(NT) void k_kdot(const double* __restrict__ base, int n, const double* __restrict__ x,
+                                            size_t na, size_t V, int lp, unsigned nz, double* part) {
   const int i0 = blockIdx.y * 4;
+  const size_t n6 = 6 * V;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n6; i += (size_t)gridDim.x * NT) {
-    const double vi = v[i] * field_weight(i, lp, nz);
+  for (size_t v = (size_t)blockIdx.x * NT + threadIdx.x; v < na; v += (size_t)gridDim.x * NT) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i0 + k < n) acc[k] += base[(size_t)(i0 + k) * n6 + i] * vi;
+    for (int c = 0; c < 6; ++c) {
+      const size_t i = c * V + v;
+      const double xi = x[i] * field_weight(i, lp, nz);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i0 + k < n) acc[k] += base[(size_t)(i0 + k) * n6 + i] * xi;
+    }
   }
   block_sums<4>(acc, part + (size_t)i0 * RB);
 }
 
-// y = a v + sum_{i<n} c_i u_i (v may be NULL; y may be v), with the block
+// y = a x + sum_{i<n} c_i u_i (x may be NULL; y may be x), with the block
 // sums of the weighted <y, y> when part is given.
-__global__ __launch_bounds__(NT) void k_kcomb(double* y, const double* v, double a, const double* __restrict__ base,
-                                             int n, KCoef kc, size_t n6, int lp, unsigned nz, double* part) {
+__global__ __launch_bounds__(NT) void k_kcomb(double* y, const double* x, double a, const double* __restrict__ base,
+                                             int n, KCoef kc, size_t na, size_t V, int lp, unsigned nz,
+                                             double* part) {
   __shared__ double cs[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j)
     if (threadIdx.x == j) cs[j] = kc.c[j];
   __syncthreads();
+  const size_t n6 = 6 * V;
   double nn[1] = {0.0};
-  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n6; i += (size_t)gridDim.x * NT) {
-    double r = v ? a * v[i] : 0.0;
-    for (int j = 0; j < n; ++j) r += cs[j] * base[(size_t)j * n6 + i];
-    y[i] = r;
-    nn[0] += field_weight(i, lp, nz) * r * r;
+  for (size_t v = (size_t)blockIdx.x * NT + threadIdx.x; v < na; v += (size_t)gridDim.x * NT) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const size_t i = c * V + v;
+      double r = x ? a * x[i] : 0.0;
+      for (int j = 0; j < n; ++j) r += cs[j] * base[(size_t)j * n6 + i];
+      y[i] = r;
+      nn[0] += field_weight(i, lp, nz) * r * r;
+    }
   }
   if (part) block_sums<1>(nn, part);
 }
@@ -1092,8 +1105,16 @@ static int kry_ensure(fvim_ctx* c, int m) {
       w->kry = nullptr;
       w->kry_m = 0;
     }
-    if (hipMalloc((void**)&w->kry, sizeof(double) * 6 * w->V * (size_t)(m + 2)) != hipSuccess)
+    const size_t bytes = sizeof(double) * 6 * w->V * (size_t)(m + 2);
+    if (hipMalloc((void**)&w->kry, bytes) != hipSuccess) {
+      w->kry = nullptr;
       return fail(FVIM_ENOMEM, "Krylov basis allocation failed");
+    }
+    // the layers below the plastic ones are never written by the iteration;
+    // they are read (and their results ignored) by the residual epilogue
+    hipError_t e = hipMemsetAsync(w->kry, 0, bytes, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail_hip(e, "Krylov basis");
     w->kry_m = m;
   }
   if (!w->kry_part && hipMalloc((void**)&w->kry_part, sizeof(double) * KMAX * RB) != hipSuccess) {
@@ -1112,13 +1133,13 @@ static int kry_ensure(fvim_ctx* c, int m) {
   return FVIM_OK;
 }
 
-// out[i] = <u_i, v> (weighted, unscaled) for the first n basis vectors.
-static int kdots(fvim_ctx* c, const double* base, int n, const double* v, double* out) {
+// out[i] = <u_i, x> (weighted, unscaled) over the na active voxels of each
+// component, for the first n basis vectors.
+static int kdots(fvim_ctx* c, const double* base, int n, const double* x, size_t na, double* out) {
   SolverWork* w = c->sw;
-  const size_t n6 = 6 * w->V;
-  const int nb = nblocks(n6);
-  hipLaunchKernelGGL(k_kdot, dim3(nb, (n + 3) / 4), dim3(NT), 0, c->stream, base, n, v, w->lp,
-                     (unsigned)c->grid.nz, n6, w->kry_part);
+  const int nb = nblocks(na);
+  hipLaunchKernelGGL(k_kdot, dim3(nb, (n + 3) / 4), dim3(NT), 0, c->stream, base, n, x, na, w->V, w->lp,
+                     (unsigned)c->grid.nz, w->kry_part);
   hipLaunchKernelGGL(k_kfinal, dim3(n), dim3(NT), 0, c->stream, w->kry_part, nb, w->kry_out);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail_hip(e, "Krylov scalar products");
@@ -1126,15 +1147,15 @@ static int kdots(fvim_ctx* c, const double* base, int n, const double* v, double
   return FVIM_OK;
 }
 
-// y = a v + sum_{i<n} coef_i u_i; with norm2, its weighted (unscaled) <y, y>.
-static int kcomb(fvim_ctx* c, double* y, const double* v, double a, const double* base, int n, const double* coef,
-                 double* norm2) {
+// y = a x + sum_{i<n} coef_i u_i over the active voxels; with norm2, its
+// weighted (unscaled) <y, y>.
+static int kcomb(fvim_ctx* c, double* y, const double* x, double a, const double* base, int n, const double* coef,
+                 size_t na, double* norm2) {
   SolverWork* w = c->sw;
-  const size_t n6 = 6 * w->V;
-  const int nb = nblocks(n6);
+  const int nb = nblocks(na);
   KCoef kc = {};
   for (int i = 0; i < n; ++i) kc.c[i] = coef[i];
-  hipLaunchKernelGGL(k_kcomb, dim3(nb), dim3(NT), 0, c->stream, y, v, a, base, n, kc, n6, w->lp,
+  hipLaunchKernelGGL(k_kcomb, dim3(nb), dim3(NT), 0, c->stream, y, x, a, base, n, kc, na, w->V, w->lp,
                      (unsigned)c->grid.nz, norm2 ? w->kry_part : nullptr);
   if (!norm2) {
     hipError_t e = hipGetLastError();
@@ -1147,47 +1168,48 @@ static int kcomb(fvim_ctx* c, double* y, const double* v, double a, const double
   return FVIM_OK;
 }
 
-// W = J u = u - grad_s N[C : T u], T the consistent tangent of the radial
-// return at the current iterate pb.x (eqn incremental_strain differentiated;
-// the traction term is constant), in the context's operator precision; the
-// tangent vanishes below the deepest plastic layer of the last return map
-// at pb.x, which the operator skips.  The weighted <W, W> goes to the
-// S_DOT0 slot and its host mirror.
-static int jacobian_apply(fvim_ctx* c, const fvim_state* s, PlastBufs& pb, const double* u, double* D, double* W) {
+// Fo = x - grad_s N[C : y] (no traction), in the context's operator
+// precision; y is read in the layers above *zact only.
+static int op_minus(fvim_ctx* c, const double* y, const double* x, double* Fo) {
   SolverWork* w = c->sw;
-  hipError_t e = launch_plastic_tangent(pb.x, u, s->sigma, s->ep, D, w->V, c->lam, c->mu, c->mat.sigma_y0,
-                                        c->mat.E_h, c->stream);
-  if (e != hipSuccess) return fail_hip(e, "plastic tangent");
   int nb = 0;
-  int rc = operator_apply_resid(c, D, nullptr, u, nullptr, W, w->rpart, &nb, w->layers + c->grid.nz);
+  int rc = operator_apply_resid(c, y, nullptr, x, nullptr, Fo, w->rpart, &nb, w->layers + c->grid.nz);
   if (rc) return rc;
   if (nb > w->rpart_count) return fail(FVIM_EINVAL, "residual partial sums: workspace too small");
-  hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(NTS), 0, c->stream, w->rpart, nb, w->sc, w->dmap);
   return FVIM_OK;
 }
 
 // Inexact Newton on R[d_eps] = 0 from pb.x to |R| <= tol_abs (Sec. 4.3
 // names Newton-Krylov with the consistent tangent as the alternative to
-// DF-SANE).  Each step solves J delta = -R by GMRES without restart, at most
-// m Arnoldi steps (classical Gram-Schmidt, repeated once when it cancels more
-// than 30 % of the new vector), to the relative residual eta of Eisenstat
-// and Walker (1996), choice 2 (gamma 0.9, exponent 2, their safeguard,
-// eta <= 0.5 and not below half the final tolerance over |R|); then
-// x + alpha delta, alpha halved until |R| falls by the factor
-// 1 - 1e-4 alpha (1 - eta).  Residuals are always float64; the
-// Jacobian-vector products use the context's operator precision (float32
+// DF-SANE).  With R = d_eps - grad_s M[dT] - grad_s N[C : d_eps_p(d_eps)],
+// the Jacobian is J = I - A T, A = grad_s N[C : .] and T the consistent
+// tangent of the radial return at the iterate, which vanishes outside the
+// plastic voxels.  J delta = -R is solved on the plastic support: with
+// y = T delta it reads (I - T A) y = -T R, and then delta = -R + A y.  The
+// Krylov vectors thus live in the layers above the deepest plastic one
+// (the operator skips the layers below as sources), and each Arnoldi step
+// costs one operator application and one tangent.  GMRES without restart,
+// at most m Arnoldi steps (classical Gram-Schmidt, repeated once when it
+// cancels more than 30 % of the new vector), to the relative residual eta
+// of Eisenstat and Walker (1996), choice 2 (gamma 0.9, exponent 2, their
+// safeguard, eta <= 0.5 and not below half the final tolerance over |R|);
+// then x + alpha delta, alpha halved until |R| falls by the factor
+// 1 - 1e-4 alpha (1 - eta).  Residuals are always float64; the operator
+// inside the linear solve and in A y uses the context's precision (float32
 // in the FP32_REFINED mode: an inexact Jacobian slows the last steps, it
-// does not move the root).  evals counts residuals and Jacobian products.
+// does not move the root).  evals counts residuals and operator
+// applications of the linear solves.
 static int newton_krylov(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, double tol_abs,
                          int max_it, int* iters, int* evals, double* fout) {
   SolverWork* w = c->sw;
-  const size_t n6 = 6 * w->V;
+  const size_t V = w->V, n6 = 6 * V;
   const int m = krylov_dim(o);
   if (!w->kry || w->kry_m < m || !w->kry_part || !w->kry_hout)
     return fail(FVIM_EINVAL, "Newton-Krylov workspace not reserved");
   double* U = w->kry;
-  double* step = U + (size_t)(m + 1) * n6;
+  double* ystar = U + (size_t)(m + 1) * n6;
   const double sc = inner_scale(c);
+  int* hz = reinterpret_cast<int*>(w->hsc + NSCAL - 1);      // pinned host word
   double f;
   int rc;
   {
@@ -1205,64 +1227,88 @@ static int newton_krylov(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o
       eta = std::min(0.5, sg > 0.1 ? std::max(e2, sg) : e2);
     }
     eta = std::max(eta, 0.5 * tol_abs / std::sqrt(f));
-    const double rn = std::sqrt(f / sc);       // |R| in the unscaled weighted norm
-    hipError_t e = hipMemcpyAsync(U, pb.F, sizeof(double) * n6, hipMemcpyDeviceToDevice, c->stream);
-    if (e != hipSuccess) return fail_hip(e, "copy");
-    std::fill(g.begin(), g.end(), 0.0);
-    sv[0] = rn;
-    g[0] = -rn;                                // -R = -rn q_0
+    // layers with plastic voxels at the iterate (its return map was the last)
+    hipError_t e = hipMemcpyAsync(hz, w->layers + c->grid.nz, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail_hip(e, "active layers");
+    const size_t na = (size_t)std::min(std::max(*hz, 0), c->grid.nz) * w->ns;
+    // u_0 = -T R
+    e = launch_plastic_tangent(pb.x, pb.F, nullptr, nullptr, s->sigma, s->ep, U, na, V, c->lam, c->mu,
+                               c->mat.sigma_y0, c->mat.E_h, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "plastic tangent");
+    double b2 = 0.0;
+    if (na && (rc = kdots(c, U, 1, U, na, &b2))) return rc;
+    const double bn = std::sqrt(b2);
     int kd = 0;
-    for (int j = 0; j < m; ++j) {
-      const double* uj = U + (size_t)j * n6;
-      double* un = U + (size_t)(j + 1) * n6;
-      if ((rc = jacobian_apply(c, s, pb, uj, pb.xt, pb.Ft))) return rc;
-      if ((rc = kdots(c, U, j + 1, pb.Ft, d))) return rc;
-      const double jn = std::sqrt(w->hmap[S_DOT0]) / sv[j];     // |J q_j|
-      for (int i = 0; i <= j; ++i) {
-        h(i, j) = d[i] / (sv[i] * sv[j]);
-        coef[i] = -h(i, j) / sv[i];
-      }
-      double n2;
-      if ((rc = kcomb(c, un, pb.Ft, 1.0 / sv[j], U, j + 1, coef, &n2))) return rc;
-      if (std::sqrt(n2) < 0.7 * jn) {
-        if ((rc = kdots(c, U, j + 1, un, d))) return rc;
+    if (bn > 0.0) {
+      std::fill(g.begin(), g.end(), 0.0);
+      sv[0] = bn;
+      g[0] = bn;
+      for (int j = 0; j < m; ++j) {
+        double* uj = U + (size_t)j * n6;
+        double* un = U + (size_t)(j + 1) * n6;
+        // W = (I - T A) u_j = u_j - T (u_j - (u_j - A u_j)), into pb.xt
+        if ((rc = op_minus(c, uj, uj, pb.Ft))) return rc;
+        e = launch_plastic_tangent(pb.x, uj, pb.Ft, uj, s->sigma, s->ep, pb.xt, na, V, c->lam, c->mu,
+                                   c->mat.sigma_y0, c->mat.E_h, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "plastic tangent");
+        ++ne;
+        if ((rc = kdots(c, U, j + 1, pb.xt, na, d))) return rc;
+        double hh = 0.0;
         for (int i = 0; i <= j; ++i) {
-          h(i, j) += d[i] / sv[i];
-          coef[i] = -d[i] / (sv[i] * sv[i]);
+          h(i, j) = d[i] / (sv[i] * sv[j]);
+          coef[i] = -h(i, j) / sv[i];
+          hh += h(i, j) * h(i, j);
         }
-        if ((rc = kcomb(c, un, un, 1.0, U, j + 1, coef, &n2))) return rc;
+        double n2;
+        if ((rc = kcomb(c, un, pb.xt, 1.0 / sv[j], U, j + 1, coef, na, &n2))) return rc;
+        // |W / s_j|^2 = sum h^2 + |u_(j+1)|^2 when the basis is orthonormal
+        if (std::sqrt(n2) < 0.7 * std::sqrt(hh + n2)) {
+          if ((rc = kdots(c, U, j + 1, un, na, d))) return rc;
+          for (int i = 0; i <= j; ++i) {
+            h(i, j) += d[i] / sv[i];
+            coef[i] = -d[i] / (sv[i] * sv[i]);
+          }
+          if ((rc = kcomb(c, un, un, 1.0, U, j + 1, coef, na, &n2))) return rc;
+        }
+        sv[j + 1] = std::sqrt(n2);
+        h(j + 1, j) = sv[j + 1];
+        for (int i = 0; i < j; ++i) {          // earlier rotations on column j
+          const double a = h(i, j), b = h(i + 1, j);
+          h(i, j) = gc[i] * a + gs[i] * b;
+          h(i + 1, j) = -gs[i] * a + gc[i] * b;
+        }
+        const double a = h(j, j), b = h(j + 1, j), r = std::hypot(a, b);
+        gc[j] = r > 0.0 ? a / r : 1.0;
+        gs[j] = r > 0.0 ? b / r : 0.0;
+        h(j, j) = r;
+        h(j + 1, j) = 0.0;
+        g[j + 1] = -gs[j] * g[j];
+        g[j] = gc[j] * g[j];
+        kd = j + 1;
+        if (std::fabs(g[j + 1]) <= eta * bn || !(sv[j + 1] > 1e-13 * std::sqrt(hh + n2))) break;
       }
-      sv[j + 1] = std::sqrt(n2);
-      h(j + 1, j) = sv[j + 1];
-      for (int i = 0; i < j; ++i) {            // earlier rotations on column j
-        const double a = h(i, j), b = h(i + 1, j);
-        h(i, j) = gc[i] * a + gs[i] * b;
-        h(i + 1, j) = -gs[i] * a + gc[i] * b;
+      for (int i = kd - 1; i >= 0; --i) {       // H y = g, upper triangular
+        double t = g[i];
+        for (int l = i + 1; l < kd; ++l) t -= h(i, l) * y[l];
+        if (h(i, i) == 0.0) return fail(FVIM_ENOCONV, "Newton-Krylov: singular Hessenberg matrix");
+        y[i] = t / h(i, i);
       }
-      const double a = h(j, j), b = h(j + 1, j), r = std::hypot(a, b);
-      gc[j] = r > 0.0 ? a / r : 1.0;
-      gs[j] = r > 0.0 ? b / r : 0.0;
-      h(j, j) = r;
-      h(j + 1, j) = 0.0;
-      g[j + 1] = -gs[j] * g[j];
-      g[j] = gc[j] * g[j];
-      kd = j + 1;
+      for (int i = 0; i < kd; ++i) coef[i] = y[i] / sv[i];
+      if ((rc = kcomb(c, ystar, nullptr, 0.0, U, kd, coef, na, nullptr))) return rc;
+    }
+    // -delta = R - A y (= R where nothing flows)
+    const double* mdel = pb.F;
+    if (kd > 0) {
+      if ((rc = op_minus(c, ystar, pb.F, U))) return rc;
       ++ne;
-      if (std::fabs(g[j + 1]) <= eta * rn || !(sv[j + 1] > 1e-13 * jn)) break;
+      mdel = U;
     }
-    for (int i = kd - 1; i >= 0; --i) {         // H y = g, upper triangular
-      double t = g[i];
-      for (int l = i + 1; l < kd; ++l) t -= h(i, l) * y[l];
-      if (h(i, i) == 0.0) return fail(FVIM_ENOCONV, "Newton-Krylov: singular Hessenberg matrix");
-      y[i] = t / h(i, i);
-    }
-    for (int i = 0; i < kd; ++i) coef[i] = y[i] / sv[i];
-    if ((rc = kcomb(c, step, nullptr, 0.0, U, kd, coef, nullptr))) return rc;
     double alpha = 1.0, fn;
     for (int guard = 0;; ++guard) {
       {
         Fp64Scope f64(c, 1);
-        if ((rc = residual(c, s, pb, pb.x, step, alpha, pb.xt, pb.Ft, &fn))) return rc;
+        if ((rc = residual(c, s, pb, pb.x, mdel, -alpha, pb.xt, pb.Ft, &fn))) return rc;
       }
       ++ne;
       if (std::sqrt(fn) <= (1.0 - 1e-4 * alpha * (1.0 - eta)) * std::sqrt(f)) break;

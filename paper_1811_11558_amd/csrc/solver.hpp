@@ -86,9 +86,10 @@ void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
 // Device bytes the Newton-Krylov solver adds when opts selects it (0 else).
 size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o);
-// out = the directional derivative of the radial return's d_eps_p at the
-// strain increment d_eps in the direction u (all [6][nvox]).
-hipError_t launch_plastic_tangent(const double* d_eps, const double* u, const double* sig_n, const double* ep_n,
-                                  double* out, size_t nvox, double lam, double mu, double sy0, double eh,
-                                  hipStream_t st);
+// out = base - T (u1 - u2) for the voxels v < na of each component
+// (stride nvox; base and u2 may be NULL), T the consistent tangent of the
+// radial return's d_eps_p at the strain increment d_eps.
+hipError_t launch_plastic_tangent(const double* d_eps, const double* u1, const double* u2, const double* base,
+                                  const double* sig_n, const double* ep_n, double* out, size_t na, size_t nvox,
+                                  double lam, double mu, double sy0, double eh, hipStream_t st);
 }  // namespace fvim
