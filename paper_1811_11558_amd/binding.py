@@ -412,10 +412,10 @@ def make_request(grid, h, W_steps, E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1, precis
     return r, h
 
 
-def request_bytes(grid, precision="fp64"):
+def request_bytes(grid, precision="fp64", opts=None):
     import numpy as np
     lib = load_library()
-    r, _ = make_request(grid, np.zeros((grid["ny"], grid["nx"])), [1.0], precision=precision)
+    r, _ = make_request(grid, np.zeros((grid["ny"], grid["nx"])), [1.0], precision=precision, opts=opts)
     return lib.fvim_request_bytes(ctypes.byref(r))
 
 

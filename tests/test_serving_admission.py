@@ -24,3 +24,17 @@ def test_footprint_grows_with_grid():
     assert all(a < b for a, b in zip(sizes, sizes[1:]))
     # the state and work arrays of a solve: at least 56 float64 tensors-worth per voxel
     assert sizes[-1] >= 56 * 8 * 512 * 512 * 96
+
+
+def test_newton_krylov_footprint_counts_its_basis():
+    """Solver 2 keeps krylov_dim + 2 strain fields (6 float64 per voxel each)
+    beyond what the other solvers need; the others ignore krylov_dim."""
+    from paper_1811_11558_amd import EPOptions, request_bytes
+    g = dict(nx=128, ny=128, nz=64, lx=1.0, ly=1.0, lz=0.25)
+    V = 128 * 128 * 64
+    base = request_bytes(g, opts=EPOptions(solver=0))
+    assert request_bytes(g, opts=EPOptions(solver=0, krylov_dim=30)) == base
+    for m, md in ((0, 20), (5, 5), (30, 30)):
+        extra = request_bytes(g, opts=EPOptions(solver=2, krylov_dim=m)) - base
+        basis = 8 * 6 * V * (md + 2)
+        assert basis <= extra < basis + (1 << 20), (m, extra, basis)
