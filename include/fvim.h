@@ -84,6 +84,17 @@ int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision,
 void fvim_destroy(fvim_ctx* ctx);
 /* Replace the stream used by later calls on this context. */
 int fvim_set_stream(fvim_ctx* ctx, void* hip_stream);
+/* Depth nodes (Sec. 3.1 leaves their spacing free).  z: HOST array of nz
+ * node depths, z[0] = 0, strictly increasing, z[nz-1] = lz (to 1e-12
+ * relative), copied; NULL restores the uniform nodes z_i = i lz / (nz - 1).
+ * The depth pass then integrates the P1 eigenstress exactly on these
+ * elements.  Scalar products of the solvers keep the uniform trapezoid
+ * weights (a different but equivalent norm: the roots do not change).
+ * Contexts with non-uniform nodes are rejected by
+ * fvim_operator_apply_batch.  Drops the solver workspace (captured
+ * evaluations bake the node table in).  Blocking.  FVIM_EINVAL for nodes
+ * that break the rules above. */
+int fvim_set_depth_nodes(fvim_ctx* ctx, const double* z);
 /* Device bytes a context of this grid holds at most (workspace for the
  * fused operator with every output, plus solver state if asked).  Used by
  * admission control. */

@@ -39,6 +39,16 @@ def depth_nodes(nz, lz):
     return np.linspace(0.0, lz, nz)
 
 
+def grid_nodes(grid):
+    """The grid's depth nodes: grid['z'] when given (Sec. 3.1 leaves the
+    spacing free), else uniform on [0, lz]."""
+    if grid.get('z') is not None:
+        z = np.asarray(grid['z'], dtype=float)
+        assert z.shape == (grid['nz'],) and z[0] == 0.0 and np.all(np.diff(z) > 0)
+        return z
+    return depth_nodes(grid['nz'], grid['lz'])
+
+
 def sym_grad(g):
     return 0.5 * (g + np.swapaxes(g, -1, -2))
 
@@ -141,7 +151,7 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
           chunk=256, modes=None, direct_dft=True):
     """Strain, stress, displacement and surface u3 of u = M[t] + N[C:eps_p].
 
-    grid: dict nx, ny, nz, lx, ly, lz.  eps_p: (6, nz, ny, nx) stored
+    grid: dict nx, ny, nz, lx, ly, lz (and optionally z, the depth nodes).  eps_p: (6, nz, ny, nx) stored
     components or None.  traction: (3, ny, nx) or None.  Returns a dict of
     physical fields: strain (6, nz, ny, nx), stress (6, nz, ny, nx) =
     C : eps - w, disp (3, nz, ny, nx), surf_u3 (ny, nx).  With ``modes`` (a
@@ -156,7 +166,7 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
     nx, ny, nz = grid['nx'], grid['ny'], grid['nz']
     lx, ly, lz = grid['lx'], grid['ly'], grid['lz']
     lam, mu = elastic.lame(E, nu)
-    z = depth_nodes(nz, lz)
+    z = grid_nodes(grid)
     if eps_p is None:
         w = np.zeros((6, nz, ny, nx))
     else:
@@ -230,7 +240,7 @@ def apply_modes(grid, E, nu, eps_p, traction, modes, k0_policy="include"):
     nx, ny, nz = grid['nx'], grid['ny'], grid['nz']
     lx, ly, lz = grid['lx'], grid['ly'], grid['lz']
     lam, mu = elastic.lame(E, nu)
-    z = depth_nodes(nz, lz)
+    z = grid_nodes(grid)
     M = len(modes)
     if eps_p is None:
         w_hat = np.zeros((6, nz, M), dtype=complex)

@@ -101,8 +101,14 @@ def von_mises(sigma):
     return np.sqrt(1.5 * np.sum(w * s * s, axis=0))
 
 
-def depth_weights(nz, lz):
-    """Trapezoid weights of the depth nodes."""
+def depth_weights(nz, lz, z=None):
+    """Trapezoid weights of the depth nodes (uniform, or the nodes z)."""
+    if z is not None:
+        h = np.diff(np.asarray(z, dtype=float))
+        w = np.zeros(nz)
+        w[:-1] += 0.5 * h
+        w[1:] += 0.5 * h
+        return w
     h = lz / (nz - 1)
     w = np.full(nz, h)
     w[0] = w[-1] = 0.5 * h
@@ -113,7 +119,7 @@ def inner(a, b, grid):
     """<a, b>: Frobenius over stored components, trapezoid in depth,
     cell area per in-plane point."""
     nz = grid['nz']
-    wz = depth_weights(nz, grid['lz'])
+    wz = depth_weights(nz, grid['lz'], grid.get('z'))
     da = grid['lx'] * grid['ly'] / (grid['nx'] * grid['ny'])
     wc = elastic.VOIGT_WEIGHT[:, None, None, None]
     return float(np.sum(wc * wz[None, :, None, None] * a * b) * da)

@@ -108,6 +108,7 @@ def load_library(path=None):
     lib.fvim_destroy.argtypes = [_P]
     lib.fvim_destroy.restype = None
     lib.fvim_set_stream.argtypes = [_P, _P]
+    lib.fvim_set_depth_nodes.argtypes = [_P, _P]
     lib.fvim_footprint_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.c_int]
     lib.fvim_footprint_bytes.restype = ctypes.c_size_t
     lib.fvim_last_error.restype = ctypes.c_char_p
@@ -230,6 +231,18 @@ class Context:
 
     def set_stream(self, stream):
         _check(_LIB.fvim_set_stream(self._h, _stream_handle(stream)))
+
+    def set_depth_nodes(self, z=None):
+        """Non-uniform depth nodes (nz values, 0 ... lz, increasing); None
+        restores the uniform ones."""
+        if z is None:
+            _check(_LIB.fvim_set_depth_nodes(self._h, None))
+            return
+        import numpy as np
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        if z.shape != (self.nz,):
+            raise FvimError(FVIM_EINVAL, "depth nodes: need %d values" % self.nz)
+        _check(_LIB.fvim_set_depth_nodes(self._h, z.ctypes.data))
 
     # shapes
     @property

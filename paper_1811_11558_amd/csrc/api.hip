@@ -254,6 +254,7 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
     if (e0 != hipSuccess) return fail_hip(e0, "mode table");
   }
   prm.mtab = mt;
+  prm.hz = c->hz;
   P.twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
   P.twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
   P.A = (cpx<T>*)c->bufA;
@@ -502,7 +503,8 @@ void fvim_destroy(fvim_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   if (c->side) hipStreamSynchronize(c->side);
-  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32, c->dbatch};
+  void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32, c->dbatch,
+                  c->hz};
   for (void* p : ptrs)
     if (p) hipFree(p);
   hipEvent_t evs[] = {c->ev_spec, c->ev_nyq};
@@ -597,6 +599,42 @@ int fvim_set_stream(fvim_ctx* c, void* hip_stream) {
   return FVIM_OK;
 }
 
+int fvim_set_depth_nodes(fvim_ctx* c, const double* z) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  const int nz = c->grid.nz;
+  std::vector<double> h;
+  if (z) {
+    const double lz = c->grid.lz;
+    if (!(z[0] == 0.0) || !(std::fabs(z[nz - 1] - lz) <= 1e-12 * lz))
+      return fail(FVIM_EINVAL, "depth nodes: need z[0] = 0 and z[nz-1] = lz");
+    h.resize(nz - 1);
+    for (int e = 0; e + 1 < nz; ++e) {
+      h[e] = z[e + 1] - z[e];
+      if (!(h[e] > 0.0) || !std::isfinite(h[e])) return fail(FVIM_EINVAL, "depth nodes: need strictly increasing finite z");
+    }
+  }
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
+  hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return fail_hip(e, "depth nodes");
+  solver_release(c);             // captured evaluations hold the previous node table
+  if (c->hz) {
+    hipFree(c->hz);
+    c->hz = nullptr;
+  }
+  if (!z) return FVIM_OK;
+  if (hipMalloc((void**)&c->hz, sizeof(double) * h.size()) != hipSuccess) {
+    c->hz = nullptr;
+    return fail(FVIM_ENOMEM, "depth nodes: allocation failed");
+  }
+  e = hipMemcpy(c->hz, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(c->hz);
+    c->hz = nullptr;
+    return fail_hip(e, "depth nodes");
+  }
+  return FVIM_OK;
+}
+
 size_t fvim_footprint_bytes(const fvim_grid* g, int precision, int with_solver_state) {
   if (check_grid(g)) return 0;
   const size_t nmodes = (size_t)(g->nx / 2 + 1) * g->ny;
@@ -641,6 +679,7 @@ int fvim_operator_apply_batch(fvim_ctx* const* ctxs, int n, const double* const*
     if (!c) return fail(FVIM_EINVAL, "batch: NULL context");
     if (c->device != c0->device || c->precision != c0->precision || c->force_fp64 != c0->force_fp64)
       return fail(FVIM_EINVAL, "batch: contexts must share the device and the precision");
+    if (c->hz) return fail(FVIM_EINVAL, "batch: contexts with non-uniform depth nodes are not supported");
     const double* ptrs[] = {eps_p ? eps_p[i] : nullptr, traction ? traction[i] : nullptr};
     double* outs[] = {strain ? strain[i] : nullptr, stress ? stress[i] : nullptr, disp ? disp[i] : nullptr,
                       surf_u3 ? surf_u3[i] : nullptr};

@@ -142,7 +142,12 @@ __device__ __forceinline__ void put(cpx<T>* __restrict__ dst, cpx<T> v, bool fir
 // then the ky = ny/2 row without its kx = nx/2 entry).
 // Block `block` of the pass over one grid (prm): GPB = NT / LPM lane groups,
 // one mode each.
-template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL = false>
+// NU: non-uniform depth nodes (prm.hz): every element has its own scaled
+// length s_e = |q| h_e, propagator exp(-s_e) [[1, +/-s_e], [0, 1]] and
+// element functions; since these propagators commute and compose by adding
+// the s_e, the scans carry each lane's (product of exp(-s_e), sum of s_e)
+// instead of powers of one per-mode constant.
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL = false, bool NU = false>
 __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                             const DepthParams& prm, int block) {
   constexpr int GPB = NT / LPM;
@@ -275,6 +280,31 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
 #pragma unroll
   for (int k = 1; k < P; ++k) rP *= r;
   const T G0 = K.G0, G0p = K.G0p, H0 = K.H0, H0p = K.H0p;
+  // NU: per element e = i0 + p (nodes e, e + 1; length 0 past the last
+  // node) and the lane's totals
+  T se[NU ? P : 1], re[NU ? P : 1], eg0[NU ? P : 1], eg0p[NU ? P : 1], eh0[NU ? P : 1], eh0p[NU ? P : 1];
+  T SL = T(0), RL = T(1);
+  if constexpr (NU) {
+    const double q1d = twopi * k1 / prm.lx, q2d = twopi * k2 / prm.ly;
+    const double qd = sqrt(q1d * q1d + q2d * q2d);
+    double S = 0.0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int e = i0 + p;
+      const double sd = (e + 1 < nz) ? qd * prm.hz[e] : 0.0;
+      double a, b, c, d;
+      elem_coeffs(sd, a, b, c, d);
+      se[p] = (T)sd;
+      re[p] = (T)exp(-sd);
+      eg0[p] = (T)a;
+      eg0p[p] = (T)b;
+      eh0[p] = (T)c;
+      eh0p[p] = (T)d;
+      S += sd;
+    }
+    SL = (T)S;
+    RL = (T)exp(-S);
+  }
 
   for (int rep = rep0; rep < rep0 + nrep; ++rep) {
     int bits = rep;
@@ -317,14 +347,17 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         const int e = i0 + p;                    // element e joins nodes e, e+1
         Loads<T> L = modal_loads<T>(o[p], mc);
         cpx<T> b2 = zero<T>(), b3 = zero<T>(), bp = zero<T>();
+        const T g0 = NU ? eg0[NU ? p : 0] : G0, g0p = NU ? eg0p[NU ? p : 0] : G0p;
+        const T h0 = NU ? eh0[NU ? p : 0] : H0, h0p = NU ? eh0p[NU ? p : 0] : H0p;
+        const T se_ = NU ? se[NU ? p : 0] : s, re_ = NU ? re[NU ? p : 0] : r;
         if (e + 1 < nz) {
-          b3 = add(scl(L.f3, G0), scl(Ln.f3, G0p));
-          b2 = sub(add(scl(L.f2, G0), scl(Ln.f2, G0p)), add(scl(L.f3, H0), scl(Ln.f3, H0p)));
-          bp = add(scl(L.fp, G0), scl(Ln.fp, G0p));
+          b3 = add(scl(L.f3, g0), scl(Ln.f3, g0p));
+          b2 = sub(add(scl(L.f2, g0), scl(Ln.f2, g0p)), add(scl(L.f3, h0), scl(Ln.f3, h0p)));
+          bp = add(scl(L.fp, g0), scl(Ln.fp, g0p));
         }
-        x2 = sub(scl(axpy(x2, -s, x3), r), b2);
-        x3 = sub(scl(x3, r), b3);
-        xp = sub(scl(xp, r), bp);
+        x2 = sub(scl(axpy(x2, -se_, x3), re_), b2);
+        x3 = sub(scl(x3, re_), b3);
+        xp = sub(scl(xp, re_), bp);
         M2[p] = x2;
         M3[p] = x3;
         MP[p] = xp;
@@ -334,7 +367,7 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     // ---- reverse scan across lanes: Y_l = A_l + Rb^P Y_(l+1) ----
     cpx<T> Y2 = M2[0], Y3 = M3[0], YP = MP[0];
     {
-      T rk = rP, ks = (T)P * s;
+      T rk = NU ? RL : rP, ks = NU ? SL : (T)P * s;
 #pragma unroll
       for (int d = 1; d < LPM; d <<= 1) {
         cpx<T> o2 = sh_down<T, LPM>(Y2, d), o3 = sh_down<T, LPM>(Y3, d), op = sh_down<T, LPM>(YP, d);
@@ -342,21 +375,34 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         Y2 = add(Y2, scl(axpy(o2, -ks, o3), wk));
         Y3 = add(Y3, scl(o3, wk));
         YP = add(YP, scl(op, wk));
-        rk = rk * rk;
-        ks = ks + ks;
+        if constexpr (NU) {                        // lanes l .. l + 2d - 1
+          const T prk = __shfl_down(rk, d, LPM), pks = __shfl_down(ks, d, LPM);
+          rk = rk * prk;
+          ks = ks + pks;
+        } else {
+          rk = rk * rk;
+          ks = ks + ks;
+        }
       }
     }
     {
       cpx<T> C2 = sh_down<T, LPM>(Y2, 1), C3 = sh_down<T, LPM>(Y3, 1), CP = sh_down<T, LPM>(YP, 1);
       if (l == LPM - 1) { C2 = zero<T>(); C3 = zero<T>(); CP = zero<T>(); }
-      T rk = r, ks = s;            // Rb^(P-p) applied to the carry, p from P-1 down
+      T rk = NU ? re[NU ? P - 1 : 0] : r, ks = NU ? se[NU ? P - 1 : 0] : s;   // Rb^(P-p) on the carry
 #pragma unroll
       for (int p = P - 1; p >= 0; --p) {
         M2[p] = add(M2[p], scl(axpy(C2, -ks, C3), rk));
         M3[p] = add(M3[p], scl(C3, rk));
         MP[p] = add(MP[p], scl(CP, rk));
-        rk = rk * r;
-        ks = ks + s;
+        if constexpr (NU) {
+          if (p > 0) {
+            rk = rk * re[p - 1];
+            ks = ks + se[p - 1];
+          }
+        } else {
+          rk = rk * r;
+          ks = ks + s;
+        }
       }
     }
     // ---- surface condition: sigma . e3 = -t at z = 0 ----
@@ -383,16 +429,19 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         ZM[p] = zm;
         const int e = i0 + p;
         cpx<T> a0 = zero<T>(), a1 = zero<T>(), am = zero<T>();
+        const T g0 = NU ? eg0[NU ? p : 0] : G0, g0p = NU ? eg0p[NU ? p : 0] : G0p;
+        const T h0 = NU ? eh0[NU ? p : 0] : H0, h0p = NU ? eh0p[NU ? p : 0] : H0p;
+        const T se_ = NU ? se[NU ? p : 0] : s, re_ = NU ? re[NU ? p : 0] : r;
         if (e + 1 < nz) {
           Loads<T> L = modal_loads<T>(o[p], mc);
           Loads<T> Ln = modal_loads<T>(p + 1 < P ? o[(p + 1) % P] : on, mc);
-          a1 = add(scl(L.f1, G0p), scl(Ln.f1, G0));
-          a0 = add(add(scl(L.f0, G0p), scl(Ln.f0, G0)), add(scl(L.f1, H0p), scl(Ln.f1, H0)));
-          am = add(scl(L.fm, G0p), scl(Ln.fm, G0));
+          a1 = add(scl(L.f1, g0p), scl(Ln.f1, g0));
+          a0 = add(add(scl(L.f0, g0p), scl(Ln.f0, g0)), add(scl(L.f1, h0p), scl(Ln.f1, h0)));
+          am = add(scl(L.fm, g0p), scl(Ln.fm, g0));
         }
-        z0 = add(scl(axpy(z0, s, z1), r), a0);
-        z1 = add(scl(z1, r), a1);
-        zm = add(scl(zm, r), am);
+        z0 = add(scl(axpy(z0, se_, z1), re_), a0);
+        z1 = add(scl(z1, re_), a1);
+        zm = add(scl(zm, re_), am);
       }
       F0 = z0;
       F1 = z1;
@@ -400,13 +449,13 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     }
     // ---- forward scan across lanes with the surface value on lane 0 ----
     if (l == 0) {
-      T ps = (T)P * s;
-      F0 = add(F0, scl(axpy(bc0, ps, bc1), rP));
-      F1 = add(F1, scl(bc1, rP));
-      FM = add(FM, scl(bcm, rP));
+      const T ps = NU ? SL : (T)P * s, rl = NU ? RL : rP;
+      F0 = add(F0, scl(axpy(bc0, ps, bc1), rl));
+      F1 = add(F1, scl(bc1, rl));
+      FM = add(FM, scl(bcm, rl));
     }
     {
-      T rk = rP, ks = (T)P * s;
+      T rk = NU ? RL : rP, ks = NU ? SL : (T)P * s;
 #pragma unroll
       for (int d = 1; d < LPM; d <<= 1) {
         cpx<T> o0 = sh_up<T, LPM>(F0, d), o1 = sh_up<T, LPM>(F1, d), om = sh_up<T, LPM>(FM, d);
@@ -414,8 +463,14 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         F0 = add(F0, scl(axpy(o0, ks, o1), wk));
         F1 = add(F1, scl(o1, wk));
         FM = add(FM, scl(om, wk));
-        rk = rk * rk;
-        ks = ks + ks;
+        if constexpr (NU) {                        // lanes l - 2d + 1 .. l
+          const T prk = __shfl_up(rk, d, LPM), pks = __shfl_up(ks, d, LPM);
+          rk = rk * prk;
+          ks = ks + pks;
+        } else {
+          rk = rk * rk;
+          ks = ks + ks;
+        }
       }
     }
     cpx<T> D0 = sh_up<T, LPM>(F0, 1), D1 = sh_up<T, LPM>(F1, 1), DM = sh_up<T, LPM>(FM, 1);
@@ -430,8 +485,13 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         cpx<T> m0 = add(Z0[p], scl(axpy(D0, ks, D1), rk));
         cpx<T> m1 = add(Z1[p], scl(D1, rk));
         cpx<T> mm = add(ZM[p], scl(DM, rk));
-        rk = rk * r;
-        ks = ks + s;
+        if constexpr (NU) {
+          rk = rk * re[NU ? p : 0];
+          ks = ks + se[NU ? p : 0];
+        } else {
+          rk = rk * r;
+          ks = ks + s;
+        }
         if (i >= nz) continue;
         cpx<T> m2 = M2[p], m3 = M3[p], mpp = MP[p];
         cpx<T> a = add(sub(scl(add(m0, m2), T(0.5)), scl(m1, cfac)), scl(m3, cfac));
@@ -469,11 +529,12 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
   }
 }
 
-// NTL: the input spectrum is read with streaming loads (last use)
-template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL>
+// NTL: the input spectrum is read with streaming loads (last use); NU:
+// non-uniform depth nodes (prm.hz)
+template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL, bool NU = false>
 __global__ __launch_bounds__(NT) void k_depth(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                              DepthParams prm) {
-  depth_modes<T, LPM, P, DISP, WANTX, NYQ, NTL>(in, out, prm, blockIdx.x);
+  depth_modes<T, LPM, P, DISP, WANTX, NYQ, NTL, NU>(in, out, prm, blockIdx.x);
 }
 
 // Several grids in one launch: block b belongs to the grid c with
@@ -571,8 +632,13 @@ hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipSt
     // node per lane): with P > 1 the lanes read every P-th element and the
     // rest of the line would be fetched again
     bool streamed = false;
+    if (p.hz) {
+      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, false, true>), dim3(nb), dim3(NT), 0, st, in, out,
+                         p);
+      streamed = true;
+    }
     if constexpr (P == 1) {
-      if (p.nt_in) {
+      if (p.nt_in && !streamed) {
         hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, true>), dim3(nb), dim3(NT), 0, st, in, out, p);
         streamed = true;
       }
@@ -586,7 +652,11 @@ hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipSt
                          static_cast<const cpx<T>*>(p.rep_out), p.nx, p.ny, p.kxh, p.ld_out, p.np_out);
     } else {
       const unsigned nb2 = (unsigned)((nnyq + GPB - 1) / GPB);
-      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true, false>), dim3(nb2), dim3(NT), 0, st, in, out, p);
+      if (p.hz)
+        hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true, false, true>), dim3(nb2), dim3(NT), 0, st, in, out,
+                           p);
+      else
+        hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, true, false>), dim3(nb2), dim3(NT), 0, st, in, out, p);
     }
   }
   return hipGetLastError();
@@ -679,7 +749,7 @@ hipError_t launch_depth_batch(const DepthBatch& host, DepthBatch* dtab, int cfg,
   const bool wx = p0.off_stress >= 0;
   for (int c = 0; c < host.n; ++c) {
     const DepthParams& p = host.prm[c];
-    if (!p.mtab || !p.rep_out || p.nz > kCfgs[cfg].lpm * kCfgs[cfg].p ||
+    if (!p.mtab || !p.rep_out || p.hz || p.nz > kCfgs[cfg].lpm * kCfgs[cfg].p ||
         (p.off_disp >= 0 || p.off_u3 >= 0) != disp || (p.off_stress >= 0) != wx)
       return hipErrorInvalidValue;
   }

@@ -102,6 +102,9 @@ struct DepthParams {
   void* rep_out;
   int nt_in;              // the main launch reads the input with streaming loads
   const int* zact;        // if set: eigenstrain layers z >= *zact are zero and not read
+  const double* hz;       // if set (device, nz - 1): non-uniform element lengths
+                          // z_(e+1) - z_e; h and the mode table's s, r, G0..H0p
+                          // are then unused.  Not in batched launches
   // ratios of kappa, filled by launch_depth: 1/(kappa+2), (kappa+1)/(kappa+2),
   // 1/(2(kappa+2)), kappa/(kappa+2), (kappa+2)/(2(kappa+1)), 1/(2 kappa+2)
   double ikp2, kk, i2k4, kapkp2, cfac, ik2;

@@ -44,6 +44,44 @@ def test_mode_matches_state_space_ode(q1, q2, nz, lz):
     assert np.linalg.norm(u[0] - uref) <= 1e-13 * np.linalg.norm(uref)
 
 
+@pytest.mark.parametrize("q1,q2,z", [
+    (2 * np.pi, 2 * np.pi * 2, [0.0, 0.01, 0.03, 0.07, 0.15, 0.25]),      # graded toward the surface
+    (40.0, 13.0, [0.0, 0.002, 0.1, 0.11, 0.5]),                            # q dz on both branches
+    (0.05, 0.03, [0.0, 0.3, 0.31, 0.9]),
+])
+def test_mode_matches_state_space_ode_non_uniform_nodes(q1, q2, z):
+    """Free node spacing (Sec. 3.1): the oracle's element integrals on
+    unequal elements == the exact ODE solve on the same nodes."""
+    z = np.array(z)
+    nz = z.size
+    rng = np.random.default_rng(int(1000 * (q1 + 3 * q2)) % 2**31)
+    wv = rng.standard_normal((nz, 6)) + 1j * rng.standard_normal((nz, 6))
+    t = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+    gref, uref = solve_mode(q1, q2, z, wv, t, E, NU)
+    g, u = operators.mode_response(np.array([q1]), np.array([q2]),
+                                   elastic.to_full(wv)[None], t[None], z, E, NU)
+    assert np.linalg.norm(g[0] - gref) <= 1e-13 * np.linalg.norm(gref)
+    assert np.linalg.norm(u[0] - uref) <= 1e-13 * np.linalg.norm(uref)
+
+
+def test_grid_nodes_feed_the_full_operator():
+    """apply() with grid['z'] equals the per-mode response on those nodes
+    for every bin (plumbing of the node table through the transforms)."""
+    from synth import grid_dict
+    g = grid_dict(4, 6, 5, lz=0.4)
+    g['z'] = np.array([0.0, 0.02, 0.08, 0.2, 0.4])
+    rng = np.random.default_rng(9)
+    eps_p = rng.standard_normal((6, 5, 6, 4))
+    full = operators.apply(g, E, NU, eps_p=eps_p)['strain']
+    modes = [(1, 1), (0, 2), (3, 1)]
+    spec = operators.apply(g, E, NU, eps_p=eps_p, modes=modes)['strain_hat']
+    fhat = np.fft.fft2(full, axes=(2, 3)) / (4 * 6)
+    for m, (ky, kx) in enumerate(modes):
+        assert np.allclose(spec[m].T, fhat[:, :, ky, kx], rtol=0, atol=1e-13 * np.abs(fhat).max())
+    uni = operators.apply(grid_dict(4, 6, 5, lz=0.4), E, NU, eps_p=eps_p)['strain']
+    assert np.linalg.norm(uni - full) > 1e-3 * np.linalg.norm(full)
+
+
 def test_mode_eigenstress_only_and_traction_only_are_additive():
     rng = np.random.default_rng(7)
     z = np.linspace(0, 0.3, 7)
