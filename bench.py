@@ -77,6 +77,8 @@ def parse():
                     help="area: rms slopes of the rough surface to run (comma separated)")
     ap.add_argument("--load-steps", type=int, default=5, help="area: equal cumulative load steps")
     ap.add_argument("--seed", type=int, default=0, help="area: seed of the rough surface")
+    ap.add_argument("--graded", type=float, default=0.0,
+                    help="operator: non-uniform depth nodes z_i = lz (i / (nz - 1))^GRADED (0 = uniform)")
     ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
                     help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
     ap.add_argument("--krylov", type=int, default=0, help="Newton-Krylov: Arnoldi steps per Newton step (0 = 20)")
@@ -498,6 +500,11 @@ def main():
     out = {"strain": strain}
     ctx.set_option(ctx.OPT_SIDE_STREAM, a.side_stream)
     ctx.set_option(ctx.OPT_STREAMING, a.streaming)
+    if a.graded > 0:
+        z = 0.25 * (np.arange(a.nz) / (a.nz - 1)) ** a.graded
+        z[-1] = 0.25
+        ctx.set_depth_nodes(z)
+        g = dict(g, z=z)
     ctx.tune()                      # first warm-up call times the depth-pass layouts
     for _ in range(a.warmup):
         ctx.operator_apply(eps, trac, out=out)
@@ -537,7 +544,8 @@ def main():
     dom = max(stages, key=lambda k: stages[k]["avg_ms"])
     avg_s = stages[dom]["avg_ms"] * 1e-3
     achieved = sb[dom] / avg_s / 1e9
-    traffic = measured_traffic(dom, a.nx, a.ny, a.nz, a.precision)
+    # the counters were taken on uniform nodes
+    traffic = measured_traffic(dom, a.nx, a.ny, a.nz, a.precision) if a.graded <= 0 else None
     depth_cfg = ctx.get_option(ctx.OPT_DEPTH_CONFIG)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -557,9 +565,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD if (a.nx, a.ny, a.nz, a.precision) == (256, 256, 64, "fp64") else
-                   "operator %dx%dx%d %s" % (a.nx, a.ny, a.nz, a.precision),
-                   "nx": a.nx, "ny": a.ny, "nz": a.nz, "lz": 0.25, "nu": 0.3, "precision": a.precision, "streaming": a.streaming},
+        "config": {"workload": WORKLOAD if (a.nx, a.ny, a.nz, a.precision, a.graded) == (256, 256, 64, "fp64", 0.0)
+                   else "operator %dx%dx%d %s%s" % (a.nx, a.ny, a.nz, a.precision,
+                                                    " graded depth nodes" if a.graded > 0 else ""),
+                   "nx": a.nx, "ny": a.ny, "nz": a.nz, "lz": 0.25, "nu": 0.3, "precision": a.precision,
+                   "streaming": a.streaming, "graded": a.graded},
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),
         "operator_hbm_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -633,9 +633,18 @@ hipError_t launch_two(const cpx<T>* in, cpx<T>* out, const DepthParams& p, hipSt
     // rest of the line would be fetched again
     bool streamed = false;
     if (p.hz) {
-      hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, false, true>), dim3(nb), dim3(NT), 0, st, in, out,
-                         p);
-      streamed = true;
+      bool done = false;
+      if constexpr (P == 1) {
+        if (p.nt_in) {
+          hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, true, true>), dim3(nb), dim3(NT), 0, st, in,
+                             out, p);
+          done = true;
+        }
+      }
+      if (!done)
+        hipLaunchKernelGGL((k_depth<T, LPM, P, DISP, WANTX, false, false, true>), dim3(nb), dim3(NT), 0, st, in,
+                           out, p);
+      streamed = true;                 // launched
     }
     if constexpr (P == 1) {
       if (p.nt_in && !streamed) {

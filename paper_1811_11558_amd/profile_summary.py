@@ -139,7 +139,7 @@ def report(a):
         for k in depth_keys:
             launches[k[0]] += len(fetch[k]["FETCH_SIZE"])
     def nyq_flag(name):
-        # k_depth<T, LPM, P, DISP, WANTX, NYQ, streaming>: the sixth argument
+        # k_depth<T, LPM, P, DISP, WANTX, NYQ, streaming, non-uniform>: the sixth argument
         args = [x.strip() for x in name[name.index("<") + 1:name.rindex(">")].split(",")]
         return "true" if len(args) > 5 and args[5] == "true" else "false"
 
