@@ -25,7 +25,12 @@ The oracle is written to be read against the paper, not to be fast:
                       point on the incremental residual (Sec. 4.2-4.3).
 * ``contact``      -- Polonsky-Keer projected CG on the Kalker dual with
                       the total-load constraint (Sec. 5.1).
-* ``coupling``     -- Algorithm 1 (Sec. 5.2).
+* ``coupling``     -- Algorithm 1 (Sec. 5.2), and Newton's method with the
+                      consistent tangent (the alternative of Sec. 4.3).
+* ``friction``     -- tangential (Coulomb, partial-slip) contact under a
+                      given pressure, the friction Sec. 5.1 says can be
+                      added: projected gradient with momentum on the
+                      complementary energy.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against things the
 oracle does not compute itself: an independent high-precision state-space
