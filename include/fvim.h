@@ -189,6 +189,33 @@ typedef struct {
 int contact_solve(fvim_ctx* ctx, const double* h, double W, double tol, int max_iter,
                   double* p, double* gap, fvim_contact_info* info);
 
+typedef struct {
+  int iters;
+  double rel_change;      /* last dA * sum |q_k - q_(k-1)| / (mu_f W)           */
+  double stick_fraction;  /* of the contact points (p > 0)                       */
+  double shift[2];        /* rigid tangential shift: u_t on the stick zone       */
+} fvim_tangential_info;
+
+/*
+ * Tangential contact with Coulomb friction under the normal pressure p
+ * ([ny][nx], device, e.g. from contact_solve): the friction Sec. 5.1 says
+ * the contact step can include, here with normal and tangential problems
+ * uncoupled (Goodman's approximation).  The tangential surface traction q
+ * ([2][ny][nx], device, output; the tangential part of the traction input
+ * of boussinesq_apply) minimises the complementary energy 1/2 <q, C q> over
+ * |q| <= mu_f p pointwise with dA * sum q = (Qx, Qy), C the tangential block
+ * of the surface compliance: (2 (1 + nu) / (E |k|)) (I - nu n n^T) per mode,
+ * mode 0 dropped.  Optimality is partial slip: one rigid shift (info.shift)
+ * of the stick zone, slip against q on the friction limit.  Accelerated
+ * projected gradient with restart; stops when info.rel_change < tol
+ * (checked every 8 iterations) or after max_iter (FVIM_ENOCONV, q holds
+ * the last iterate).  Needs |Q| < mu_f W, W = dA * sum p (FVIM_EINVAL
+ * otherwise; full sliding is q = mu_f p Q / |Q|).  Blocking; info (may be
+ * NULL) on host.
+ */
+int tangential_solve(fvim_ctx* ctx, const double* p, double mu_f, double Qx, double Qy, double tol,
+                     int max_iter, double* q, fvim_tangential_info* info);
+
 /* Elastoplastic state S_n kept between load steps (Sec. 4.2, Alg. 1):
  * device pointers, caller-owned.  eps_p, sigma: tensor fields; ep: scalar
  * field; traction: surface vector [3][ny][nx]; u3p: surface residual

@@ -41,6 +41,11 @@ class _ContactInfo(ctypes.Structure):
                 ("mean_gap", ctypes.c_double)]
 
 
+class _TangentialInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("rel_change", ctypes.c_double),
+                ("stick_fraction", ctypes.c_double), ("shift", ctypes.c_double * 2)]
+
+
 class _State(ctypes.Structure):
     _fields_ = [("eps_p", ctypes.c_void_p), ("ep", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("traction", ctypes.c_void_p), ("u3p", ctypes.c_void_p)]
@@ -124,6 +129,8 @@ def load_library(path=None):
     lib.return_map.argtypes = [_P, _P, _P, _P, _P, _P, _P]
     lib.contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P,
                                   ctypes.POINTER(_ContactInfo)]
+    lib.tangential_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, _P, ctypes.POINTER(_TangentialInfo)]
     lib.elastoplastic_solve.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(EPOptions), ctypes.POINTER(_State),
                                         ctypes.POINTER(_EPInfo)]
@@ -318,6 +325,18 @@ class Context:
                                   _ptr(p, sh, "p"), _ptr(gap, sh, "gap"), ctypes.byref(info)))
         return p, gap, contact_info_dict(info)
 
+    def tangential_solve(self, p, mu_f, Q, tol=1e-12, max_iter=100000, q=None):
+        """Partial-slip tangential traction (2, ny, nx) under the normal
+        pressure p for the total tangential force Q = (Qx, Qy)."""
+        sh = self.surface_shape
+        if q is None:
+            q = torch.empty((2,) + sh, dtype=torch.float64, device=p.device)
+        info = _TangentialInfo()
+        _check(_LIB.tangential_solve(self._h, _ptr(p, sh, "p"), float(mu_f), float(Q[0]), float(Q[1]),
+                                     float(tol), int(max_iter), _ptr(q, (2,) + sh, "q"), ctypes.byref(info)))
+        return q, {"iters": info.iters, "rel_change": info.rel_change, "stick_fraction": info.stick_fraction,
+                   "shift": (info.shift[0], info.shift[1])}
+
     def new_state(self, device="cuda"):
         z = lambda s: torch.zeros(s, dtype=torch.float64, device=device)
         return {"eps_p": z(self.tensor_shape), "ep": z(self.scalar_shape), "sigma": z(self.tensor_shape),
@@ -391,6 +410,10 @@ def return_map(ctx, d_eps, sigma_n, ep_n, **kw):
 
 def contact_solve(ctx, h, W, **kw):
     return ctx.contact_solve(h, W, **kw)
+
+
+def tangential_solve(ctx, p, mu_f, Q, **kw):
+    return ctx.tangential_solve(p, mu_f, Q, **kw)
 
 
 def elastoplastic_solve(ctx, h, W_steps, state, opts=None):

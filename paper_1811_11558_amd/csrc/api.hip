@@ -512,6 +512,7 @@ void fvim_destroy(fvim_ctx* c) {
     if (ev) hipEventDestroy(ev);
   if (c->side) hipStreamDestroy(c->side);
   solver_release(c);
+  friction_release(c);
   for (auto& ev : c->evs) {
     hipEventDestroy(ev.a);
     hipEventDestroy(ev.b);

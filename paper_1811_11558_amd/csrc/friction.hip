@@ -1,0 +1,434 @@
+// Tangential (Coulomb, partial-slip) contact under a given normal pressure:
+// the friction Sec. 5.1 says the contact step can include.  Normal and
+// tangential problems are uncoupled (Goodman's approximation); the
+// tangential surface traction q = (q1, q2) minimises the complementary
+// energy 1/2 <q, C q> over |q_i| <= mu_f p_i with the total tangential force
+// dA sum q = Q prescribed, C the tangential block of the half-space surface
+// compliance: per mode, (2 (1 + nu) / (E |k|)) (I - nu n n^T), n = k / |k|,
+// k = 0 dropped, n1 n2 averaged to 0 over the sign replicas of a Nyquist
+// line.  Its optimality conditions are the stick/slip conditions (one rigid
+// shift of the stick zone; slip against the traction where it is on the
+// friction limit).
+//
+// Accelerated projected gradient (FISTA) with gradient restart, step 1 / L,
+// L the largest eigenvalue of C.  One iteration, all on the device with no
+// host round trip:
+//   u = C y            2-plane forward transforms, 2x2 multiplier, inverse
+//   v = y - u / L;     q_new = P(v + lam): P the projection onto the disks
+//                      |.| <= mu_f p_i, lam (2 values) the root of
+//                      dA sum P(v + lam) = Q by Newton steps (block sums of
+//                      P and of its 2x2 Jacobian, then one block solves)
+//   restart test <y - q_new, q_new - q> > 0, momentum, y and q updated.
+// The host reads the change measure dA sum |q_new - q| / (mu_f W) every few
+// iterations.  Reductions use a fixed block partition and order.
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "solver.hpp"
+
+namespace fvim {
+namespace {
+
+constexpr int NT = 256;
+constexpr int RB = 1024;               // max reduction blocks
+constexpr int NEWTON = 4;              // projection Newton steps per iteration
+constexpr int CHECK = 8;               // iterations between host checks
+
+// device scalars
+enum { F_LAM0 = 0, F_LAM1, F_T, F_BETA, F_CHANGE, F_DOT, F_SUMP, F_STICK, F_CONTACT, F_NSC = 16 };
+
+template <int NS>
+__device__ __forceinline__ void fblock_sums(double (&v)[NS], double* part) {
+  __shared__ double sh[NS][NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) sh[k][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s += sh[k][i];
+      part[k * RB + blockIdx.x] = s;
+    }
+  }
+}
+
+// total of the nb partials of row k, one block, fixed order
+__device__ double ffinal(const double* part, int k, int nb) {
+  __shared__ double sh[NT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) s += part[k * RB + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// projection of w onto the disk |.| <= rho: P and its Jacobian (a, b, c) =
+// [[a, b], [b, c]]
+__device__ __forceinline__ void disk(double w0, double w1, double rho, double& p0, double& p1, double& ja,
+                                     double& jb, double& jc) {
+  const double r = sqrt(w0 * w0 + w1 * w1);
+  if (r <= rho) {
+    p0 = w0;
+    p1 = w1;
+    ja = 1.0;
+    jb = 0.0;
+    jc = 1.0;
+    return;
+  }
+  const double s = rho / r, a = s / (r * r);
+  p0 = s * w0;
+  p1 = s * w1;
+  ja = s - a * w0 * w0;
+  jb = -a * w0 * w1;
+  jc = s - a * w1 * w1;
+}
+
+// rho = mu_f p; block sums of p
+__global__ __launch_bounds__(NT) void k_f_rho(const double* __restrict__ p, double mu, double* __restrict__ rho,
+                                             size_t n, double* part) {
+  double v[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double pi = p[i];
+    rho[i] = mu * pi;
+    v[0] += pi;
+  }
+  fblock_sums<1>(v, part);
+}
+
+// q = y = (c0, c1) rho (the full-slip field scaled to the load)
+__global__ __launch_bounds__(NT) void k_f_init(const double* __restrict__ rho, double* __restrict__ q,
+                                              double* __restrict__ y, size_t n, double c0, double c1) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double r = rho[i];
+    q[i] = y[i] = c0 * r;
+    q[n + i] = y[n + i] = c1 * r;
+  }
+}
+
+// 2x2 tangential compliance per mode of the mode-major spectrum s[mode][ld]
+// (planes 0, 1), with the 1 / (nx ny) of the inverse transform
+__global__ __launch_bounds__(NT) void k_f_compliance(cpx<double>* __restrict__ s, int ld, int nx, int ny, double lx,
+                                                    double ly, double fac, double nu) {
+  const int kxh = nx / 2 + 1;
+  const int m = blockIdx.x * NT + threadIdx.x;
+  if (m >= kxh * ny) return;
+  const int kx = m / ny, ky = m - kx * ny;
+  const int k2 = (ky * 2 <= ny) ? ky : ky - ny;
+  const double twopi = 6.283185307179586476925286766559;
+  const double q1 = twopi * kx / lx, q2 = twopi * k2 / ly;
+  const double q = sqrt(q1 * q1 + q2 * q2);
+  cpx<double>* r = s + (size_t)m * ld;
+  if (m == 0) {
+    r[0] = mk(0.0, 0.0);
+    r[1] = mk(0.0, 0.0);
+    return;
+  }
+  const double f = fac / q, n1 = q1 / q, n2 = q2 / q;
+  const bool nyq = (kx * 2 == nx) || (ky * 2 == ny);
+  const double c11 = f * (1.0 - nu * n1 * n1), c22 = f * (1.0 - nu * n2 * n2);
+  const double c12 = nyq ? 0.0 : -f * nu * n1 * n2;
+  const cpx<double> a = r[0], b = r[1];
+  r[0] = mk(c11 * a.x + c12 * b.x, c11 * a.y + c12 * b.y);
+  r[1] = mk(c12 * a.x + c22 * b.x, c12 * a.y + c22 * b.y);
+}
+
+// block sums of P(v + lam) and of its Jacobian, v = y - u / L
+__global__ __launch_bounds__(NT) void k_f_sums(const double* __restrict__ y, const double* __restrict__ u,
+                                              double invL, const double* __restrict__ rho,
+                                              const double* __restrict__ sc, size_t n, double* part) {
+  const double l0 = sc[F_LAM0], l1 = sc[F_LAM1];
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double w0 = y[i] - invL * u[i] + l0, w1 = y[n + i] - invL * u[n + i] + l1;
+    double p0, p1, ja, jb, jc;
+    disk(w0, w1, rho[i], p0, p1, ja, jb, jc);
+    v[0] += p0;
+    v[1] += p1;
+    v[2] += ja;
+    v[3] += jb;
+    v[4] += jc;
+  }
+  fblock_sums<5>(v, part);
+}
+
+// one Newton step on lam: g = sum P - S, J = sum of Jacobians (regularised)
+__global__ __launch_bounds__(NT) void k_f_newton(const double* __restrict__ part, int nb, double* sc, double S0,
+                                                double S1) {
+  const double g0 = ffinal(part, 0, nb) - S0, g1 = ffinal(part, 1, nb) - S1;
+  double a = ffinal(part, 2, nb), b = ffinal(part, 3, nb), c = ffinal(part, 4, nb);
+  if (threadIdx.x == 0) {
+    const double reg = 1e-14 * (a + c + 1.0);
+    a += reg;
+    c += reg;
+    const double det = a * c - b * b;
+    if (det > 0.0) {
+      sc[F_LAM0] -= (c * g0 - b * g1) / det;
+      sc[F_LAM1] -= (a * g1 - b * g0) / det;
+    }
+  }
+}
+
+// q_new = P(v + lam); block sums of |q_new - q| and <y - q_new, q_new - q>
+__global__ __launch_bounds__(NT) void k_f_apply(const double* __restrict__ y, const double* __restrict__ u,
+                                               double invL, const double* __restrict__ rho,
+                                               const double* __restrict__ sc, const double* __restrict__ q,
+                                               double* __restrict__ qn, size_t n, double* part) {
+  const double l0 = sc[F_LAM0], l1 = sc[F_LAM1];
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double y0 = y[i], y1 = y[n + i];
+    const double w0 = y0 - invL * u[i] + l0, w1 = y1 - invL * u[n + i] + l1;
+    double p0, p1, ja, jb, jc;
+    disk(w0, w1, rho[i], p0, p1, ja, jb, jc);
+    qn[i] = p0;
+    qn[n + i] = p1;
+    const double d0 = p0 - q[i], d1 = p1 - q[n + i];
+    v[0] += fabs(d0) + fabs(d1);
+    v[1] += (y0 - p0) * d0 + (y1 - p1) * d1;
+  }
+  fblock_sums<2>(v, part);
+}
+
+// change measure, restart decision and momentum coefficient
+__global__ __launch_bounds__(NT) void k_f_momentum(const double* __restrict__ part, int nb, double* sc,
+                                                  double* mirror, double cscale) {
+  const double ch = ffinal(part, 0, nb), dot = ffinal(part, 1, nb);
+  if (threadIdx.x == 0) {
+    const double t = sc[F_T];
+    double beta = 0.0, tn = 1.0;
+    if (!(dot > 0.0)) {
+      tn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+      beta = (t - 1.0) / tn;
+    }
+    sc[F_T] = tn;
+    sc[F_BETA] = beta;
+    sc[F_CHANGE] = mirror[F_CHANGE] = ch * cscale;
+    sc[F_DOT] = dot;
+  }
+}
+
+// y = q_new + beta (q_new - q); q = q_new
+__global__ __launch_bounds__(NT) void k_f_update(double* __restrict__ q, const double* __restrict__ qn,
+                                                double* __restrict__ y, const double* __restrict__ sc, size_t n2) {
+  const double beta = sc[F_BETA];
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n2; i += (size_t)gridDim.x * NT) {
+    const double a = qn[i];
+    y[i] = a + beta * (a - q[i]);
+    q[i] = a;
+  }
+}
+
+// block sums of stick points (|q| < rho (1 - 1e-9)) and contact points (rho > 0)
+__global__ __launch_bounds__(NT) void k_f_stick(const double* __restrict__ q, const double* __restrict__ rho,
+                                               size_t n, double* part) {
+  double v[2] = {0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double r = rho[i];
+    if (r > 0.0) {
+      v[1] += 1.0;
+      const double a = sqrt(q[i] * q[i] + q[n + i] * q[n + i]);
+      if (a < r * (1.0 - 1e-9)) v[0] += 1.0;
+    }
+  }
+  fblock_sums<2>(v, part);
+}
+
+__global__ __launch_bounds__(NT) void k_f_totals(const double* __restrict__ part, int nb, int k, double* sc,
+                                                double* mirror, int slot) {
+  double s[3];
+  for (int j = 0; j < k; ++j) s[j] = ffinal(part, j, nb);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < k; ++j) sc[slot + j] = mirror[slot + j] = s[j];
+}
+
+int fblocks(size_t n) { return (int)std::min<size_t>((n + NT - 1) / NT, RB); }
+
+}  // namespace
+
+struct FricWork {
+  size_t n = 0;
+  int ld = 0;
+  double* vec = nullptr;          // q, y, u, q_new (2 planes each), rho
+  cpx<double>* specX = nullptr;   // [2][kxh][ny]
+  cpx<double>* specM = nullptr;   // [kxh][ny][ld]
+  double* part = nullptr;         // [5][RB]
+  double* sc = nullptr;           // device scalars
+  double* hmap = nullptr;         // mapped host mirror (host view)
+  double* dmap = nullptr;         //   (device view)
+};
+
+void friction_release(fvim_ctx* c) {
+  FricWork* w = c->fric;
+  if (!w) return;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
+  if (w->vec) hipFree(w->vec);
+  if (w->specX) hipFree(w->specX);
+  if (w->specM) hipFree(w->specM);
+  if (w->part) hipFree(w->part);
+  if (w->sc) hipFree(w->sc);
+  if (w->hmap) hipHostFree(w->hmap);
+  delete w;
+  c->fric = nullptr;
+}
+
+static int fric_ensure(fvim_ctx* c) {
+  if (c->fric) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
+  FricWork* w = new FricWork();
+  c->fric = w;
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  w->n = (size_t)nx * ny;
+  w->ld = mode_stride<double>(2);
+  const bool ok = hipMalloc((void**)&w->vec, sizeof(double) * 9 * w->n) == hipSuccess &&
+                  hipMalloc((void**)&w->specX, sizeof(cpx<double>) * 2 * kxh * ny) == hipSuccess &&
+                  hipMalloc((void**)&w->specM, sizeof(cpx<double>) * (size_t)kxh * ny * w->ld) == hipSuccess &&
+                  hipMalloc((void**)&w->part, sizeof(double) * 5 * RB) == hipSuccess &&
+                  hipMalloc((void**)&w->sc, sizeof(double) * F_NSC) == hipSuccess &&
+                  hipHostMalloc((void**)&w->hmap, sizeof(double) * F_NSC,
+                                hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+                  hipHostGetDevicePointer((void**)&w->dmap, w->hmap, 0) == hipSuccess;
+  if (!ok) {
+    friction_release(c);
+    return fail(FVIM_ENOMEM, "tangential contact workspace allocation failed");
+  }
+  return FVIM_OK;
+}
+
+// u = C y (2 planes)
+static int tangential_compliance(fvim_ctx* c, const double* y, double* u, hipStream_t st) {
+  FricWork* w = c->fric;
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  const cpx<double>* twx = (const cpx<double>*)c->twx64;
+  const cpx<double>* twy = (const cpx<double>*)c->twy64;
+  hipError_t e;
+  if ((e = launch_x_r2c<double>(y, w->specX, nx, ny, 2, twx, st)) != hipSuccess) return fail_hip(e, "tangential x");
+  if ((e = launch_y_fwd<double>(w->specX, w->specM, ny, kxh, 2, w->ld, twy, st)) != hipSuccess)
+    return fail_hip(e, "tangential y");
+  const double G = c->mat.E / (2.0 * (1.0 + c->mat.nu));
+  const double fac = 1.0 / G / ((double)nx * ny);
+  const int nm = kxh * ny;
+  hipLaunchKernelGGL(k_f_compliance, dim3((nm + NT - 1) / NT), dim3(NT), 0, st, w->specM, w->ld, nx, ny,
+                     c->grid.lx, c->grid.ly, fac, c->mat.nu);
+  if ((e = launch_y_inv<double>(w->specM, w->specX, ny, kxh, 2, w->ld, twy, st)) != hipSuccess)
+    return fail_hip(e, "tangential y^-1");
+  OutSegments seg;
+  seg.n = 1;
+  seg.first[0] = 0;
+  seg.ptr[0] = u;
+  if ((e = launch_x_c2r<double>(w->specX, seg, nx, ny, 2, 1.0, twx, st)) != hipSuccess)
+    return fail_hip(e, "tangential x^-1");
+  return FVIM_OK;
+}
+
+int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
+                   double* q_out, fvim_tangential_info* info) {
+  if (!(mu_f > 0.0) || !std::isfinite(Qx) || !std::isfinite(Qy) || !(tol > 0.0) || max_iter < 1)
+    return fail(FVIM_EINVAL, "tangential_solve: bad arguments");
+  int rc = fric_ensure(c);
+  if (rc) return rc;
+  FricWork* w = c->fric;
+  hipStream_t st = c->stream;
+  const size_t n = w->n;
+  double* q = w->vec;
+  double* y = q + 2 * n;
+  double* u = y + 2 * n;
+  double* qn = u + 2 * n;
+  double* rho = qn + 2 * n;
+  const int nb = fblocks(n);
+  const double dA = c->grid.lx * c->grid.ly / (double)n;
+  hipLaunchKernelGGL(k_f_rho, dim3(nb), dim3(NT), 0, st, p, mu_f, rho, n, w->part);
+  hipLaunchKernelGGL(k_f_totals, dim3(1), dim3(NT), 0, st, w->part, nb, 1, w->sc, w->dmap, (int)F_SUMP);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail_hip(e, "tangential_solve");
+  const double W = dA * w->hmap[F_SUMP];
+  if (!(std::hypot(Qx, Qy) < mu_f * W))
+    return fail(FVIM_EINVAL, "tangential_solve: partial slip needs |Q| < mu_f W (full sliding: q = mu_f p Q/|Q|)");
+  // largest eigenvalue of C: the lowest wavenumber, along the direction
+  // where I - nu n n^T is 1 (the coupling only lowers it)
+  const double G = c->mat.E / (2.0 * (1.0 + c->mat.nu));
+  const double twopi = 6.283185307179586476925286766559;
+  double kmin = INFINITY;
+  if (c->grid.nx > 1) kmin = std::min(kmin, twopi / c->grid.lx);
+  if (c->grid.ny > 1) kmin = std::min(kmin, twopi / c->grid.ly);
+  const double L = 1.0 / (G * kmin);
+  const double invL = 1.0 / L;
+  const double S0 = Qx / dA, S1 = Qy / dA;
+  hipLaunchKernelGGL(k_f_init, dim3(nb), dim3(NT), 0, st, rho, q, y, n, Qx / (mu_f * W), Qy / (mu_f * W));
+  double init[F_NSC] = {};
+  init[F_T] = 1.0;
+  {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());     // pageable copy
+    e = hipMemcpyAsync(w->sc, init, sizeof(init), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  if (e != hipSuccess) return fail_hip(e, "tangential_solve");
+  const double cscale = dA / (mu_f * W);
+  int k = 0;
+  double change = INFINITY;
+  bool conv = false;
+  while (k < max_iter) {
+    if ((rc = tangential_compliance(c, y, u, st))) return rc;
+    for (int j = 0; j < NEWTON; ++j) {
+      hipLaunchKernelGGL(k_f_sums, dim3(nb), dim3(NT), 0, st, y, u, invL, rho, w->sc, n, w->part);
+      hipLaunchKernelGGL(k_f_newton, dim3(1), dim3(NT), 0, st, w->part, nb, w->sc, S0, S1);
+    }
+    hipLaunchKernelGGL(k_f_apply, dim3(nb), dim3(NT), 0, st, y, u, invL, rho, w->sc, q, qn, n, w->part);
+    hipLaunchKernelGGL(k_f_momentum, dim3(1), dim3(NT), 0, st, w->part, nb, w->sc, w->dmap, cscale);
+    hipLaunchKernelGGL(k_f_update, dim3(fblocks(2 * n)), dim3(NT), 0, st, q, qn, y, w->sc, 2 * n);
+    ++k;
+    if (k % CHECK == 0 || k == max_iter) {
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail_hip(e, "tangential_solve");
+      change = w->hmap[F_CHANGE];
+      if (!std::isfinite(change)) return fail(FVIM_EINVAL, "tangential_solve: iterate is not finite");
+      if (change < tol) {
+        conv = true;
+        break;
+      }
+    }
+  }
+  // outputs: q, stick fraction, the rigid shift L lam of the stick zone
+  e = hipMemcpyAsync(q_out, q, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return fail_hip(e, "tangential_solve");
+  hipLaunchKernelGGL(k_f_stick, dim3(nb), dim3(NT), 0, st, q, rho, n, w->part);
+  hipLaunchKernelGGL(k_f_totals, dim3(1), dim3(NT), 0, st, w->part, nb, 2, w->sc, w->dmap, (int)F_STICK);
+  double lam[2];
+  {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());     // pageable copy
+    e = hipMemcpyAsync(lam, w->sc + F_LAM0, sizeof(lam), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
+  if (e != hipSuccess) return fail_hip(e, "tangential_solve");
+  if (info) {
+    info->iters = k;
+    info->rel_change = change;
+    info->stick_fraction = w->hmap[F_CONTACT] > 0 ? w->hmap[F_STICK] / w->hmap[F_CONTACT] : 0.0;
+    info->shift[0] = L * lam[0];
+    info->shift[1] = L * lam[1];
+  }
+  if (!conv) return fail(FVIM_ENOCONV, "tangential_solve: iteration limit reached");
+  return FVIM_OK;
+}
+
+}  // namespace fvim
+
+int tangential_solve(fvim_ctx* ctx, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
+                     double* q, fvim_tangential_info* info) {
+  if (!ctx || !p || !q) return fvim::fail(FVIM_EINVAL, "tangential_solve: NULL argument");
+  return fvim::friction_solve(ctx, p, mu_f, Qx, Qy, tol, max_iter, q, info);
+}

@@ -11,6 +11,7 @@
 
 namespace fvim {
 struct SolverWork;
+struct FricWork;
 }
 
 struct fvim_ctx {
@@ -41,6 +42,7 @@ struct fvim_ctx {
   hipEvent_t ev_spec = nullptr, ev_nyq = nullptr;
   size_t bufA_bytes = 0, bufB_bytes = 0, k0buf_bytes = 0;
   fvim::SolverWork* sw = nullptr;
+  fvim::FricWork* fric = nullptr;   // tangential contact workspace (first use)
   // tuning: depth-pass configuration id (-1 = default for nz), and a request
   // to time every candidate on the next operator call
   int depth_cfg = -1;
@@ -85,6 +87,9 @@ int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* tractio
 int operator_resid_parts(const fvim_grid& g);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
+void friction_release(fvim_ctx* c);
+int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
+                   double* q_out, fvim_tangential_info* info);
 // Device bytes the Newton-Krylov solver adds when opts selects it (0 else).
 size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o);
 // out = base - T (u1 - u2) for the voxels v < na of each component

@@ -86,7 +86,8 @@ def test_binding_structures_match_the_header():
     from paper_1811_11558_amd import binding as b
     pairs = {"fvim_grid": b._Grid, "fvim_material": b._Material, "fvim_contact_info": b._ContactInfo,
              "fvim_ep_opts": b.EPOptions, "fvim_ep_info": b._EPInfo, "fvim_request": b._Request,
-             "fvim_result": b._Result, "fvim_server_stats": b._ServerStats}
+             "fvim_result": b._Result, "fvim_server_stats": b._ServerStats,
+             "fvim_tangential_info": b._TangentialInfo}
     consts = header_constants()
     hs = header_structs()
     for cname, py in pairs.items():
