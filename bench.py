@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-modes", type=int, default=4096,
                     help="modes of the oracle sample for the CPU baseline")
-    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch", "rough", "area"],
+    ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch", "rough", "area",
+                                                                   "friction"],
                     help="operator: the fused operator (the headline line); serve: Poisson-arrival "
                          "elastoplastic solves of mixed grids through the batching server; solve: the "
                          "32x32x16 paraboloid elastoplastic solve; copy: a plain device copy of known size "
@@ -79,6 +80,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=0, help="area: seed of the rough surface")
     ap.add_argument("--graded", type=float, default=0.0,
                     help="operator: non-uniform depth nodes z_i = lz (i / (nz - 1))^GRADED (0 = uniform)")
+    ap.add_argument("--mu-f", type=float, default=0.3, help="friction: Coulomb coefficient")
+    ap.add_argument("--q-ratio", type=float, default=0.5, help="friction: tangential load Q / (mu_f W) along x")
     ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
                     help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
     ap.add_argument("--krylov", type=int, default=0, help="Newton-Krylov: Arnoldi steps per Newton step (0 = 20)")
@@ -377,6 +380,44 @@ def bench_area(a):
                       "runs": rows}))
 
 
+def bench_friction(a):
+    """Partial-slip tangential contact (Coulomb mu_f, Q = q_ratio mu_f W along
+    x) under the frictionless pressure of a rough surface (Hurst --hurst,
+    PSD plateau below --k-roll, cut-off nx / 4, rms slope 0.1, seed 0) at
+    total load --load on nx x ny (default 512 x 512), tolerance 1e-12.  The
+    normal solve is untimed; each timed step is one tangential_solve."""
+    import torch
+    from paper_1811_11558_amd import Context
+    from synth import grid_dict, rough_surface
+    nx, ny = a.nx or 512, a.ny or 512
+    g = grid_dict(nx, ny, 2, 1.0, 1.0, 0.25)
+    h = torch.from_numpy(rough_surface(nx, ny, hurst=a.hurst, k_roll=a.k_roll, k_cut=a.k_cut or nx // 4,
+                                       rms_slope=0.1, seed=0)).cuda()
+    ctx = Context(g, 1.0, 0.3)
+    p, _, cinfo = ctx.contact_solve(h, a.load, tol=1e-12, max_iter=50000)
+    Q = (a.q_ratio * a.mu_f * a.load, 0.0)
+    info = None
+    for _ in range(max(1, a.warmup)):
+        _, info = ctx.tangential_solve(p, a.mu_f, Q, tol=1e-12)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, a.steps)):
+        t0 = time.perf_counter()
+        _, info = ctx.tangential_solve(p, a.mu_f, Q, tol=1e-12)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ctx.close()
+    t = float(np.median(times))
+    print(json.dumps({"metric": "tangential contact solve time", "value": t, "unit": "s", "higher_is_better": False,
+                      "n_gpus": 1, "steps": len(times), "data": "synthetic",
+                      "config": {"workload": "partial-slip tangential contact %dx%d" % (nx, ny), "mu_f": a.mu_f,
+                                 "q_ratio": a.q_ratio, "W": a.load, "hurst": a.hurst, "tol": 1e-12},
+                      "iters": info["iters"], "stick_fraction": info["stick_fraction"],
+                      "contact_fraction": cinfo["contact_fraction"],
+                      "ms_per_iteration": 1e3 * t / info["iters"],
+                      "point_updates_per_s": info["iters"] * nx * ny / t}))
+
+
 def bench_solve(a):
     """Elastoplastic paraboloid solve, 32 x 32 x 16 (R = 0.5 L, lz = 0.25 L,
     E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1), cumulative loads up to
@@ -482,6 +523,8 @@ def main():
         return bench_area(a)
     if a.workload == "solve":
         return bench_solve(a)
+    if a.workload == "friction":
+        return bench_friction(a)
     if a.workload == "serve":
         return bench_serve(a)
     import torch

@@ -259,6 +259,13 @@ typedef struct {
                        /* a pass solved to tol_plastic; 0: always tol_plastic*/
   int krylov_dim;      /* Newton-Krylov: Arnoldi steps per Newton step,     */
                        /* 1..30 (0 = 20); ignored by the other solvers      */
+  double mu_f;         /* > 0: Coulomb friction in the contact step: after  */
+                       /* each normal solve, tangential_solve for the total */
+                       /* tangential force q_ratio * mu_f * W (|q_ratio|<1) */
+                       /* to the tolerance max(tol_contact, 1e-13) (its    */
+                       /* iterations count in contact_iters), and the     */
+                       /* traction T carries it; 0: frictionless            */
+  double q_ratio[2];
 } fvim_ep_opts;
 
 typedef struct {

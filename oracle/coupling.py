@@ -30,6 +30,7 @@ Test infrastructure only (see ``oracle/__init__``).
 import numpy as np
 
 from . import contact as oc
+from . import friction as fr
 from . import operators as ops
 from . import plasticity as pl
 
@@ -168,8 +169,16 @@ def new_state(grid):
 def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3,
                         tol_plastic=1e-13, tol_contact=1e-14, max_outer=500,
                         max_plastic=500, max_contact=5000, solver="dfsane", literal=False,
-                        k0_policy="include"):
+                        k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0), tol_friction=1e-13):
     """Algorithm 1 for each cumulative load in W_steps; state updated in place.
+
+    With mu_f > 0 the contact step also carries Coulomb friction: after the
+    normal solve, the partial-slip tangential traction for the total
+    tangential force Q = q_ratio mu_f W (``friction.tangential_solve``,
+    normal and tangential problems uncoupled) joins the traction T, so the
+    plasticity sees it through the Boussinesq-Cerruti operator.  The
+    tangential problem is solved in total form at each load, which is the
+    Cattaneo-Mindlin reading for monotonic proportional loading.
 
     Returns a list of per-step info dicts."""
     E, nu = mat['E'], mat['nu']
@@ -191,6 +200,9 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
             p, _, cinfo = oc.contact_solve(H, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p)
             T = np.zeros_like(T_n)
             T[2] = p
+            if mu_f > 0.0:
+                Q = np.asarray(q_ratio, dtype=float) * mu_f * W
+                T[:2], _ = fr.tangential_solve(grid, E, nu, p, Q, mu_f, tol=tol_friction)
             res = plasticity(grid, mat, T - T_n, state, tol=tol_plastic, max_iter=max_plastic,
                              solver=solver, k0_policy=k0_policy)
             dU = ops.mindlin_apply(grid, E, nu, res['d_eps_p'], k0_policy=k0_policy)['surf_u3']

@@ -34,7 +34,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int RB = 1024;               // max reduction blocks
-constexpr int NEWTON = 4;              // projection Newton steps per iteration
+constexpr int NEWTON = 2;              // projection Newton steps per iteration (warm-started)
 constexpr int CHECK = 8;               // iterations between host checks
 
 // device scalars
@@ -76,6 +76,36 @@ __device__ double ffinal(const double* part, int k, int nb) {
   double r = sh[0];
   __syncthreads();
   return r;
+}
+
+// totals of the nb partials of rows 0 .. K-1 in one pass: every thread sums
+// its strided share of each row, then wave shuffles and one cross-wave step
+// (fixed order); the totals are valid in thread 0
+template <int K>
+__device__ __forceinline__ void ffinal_rows(const double* part, int nb, double (&out)[K]) {
+  __shared__ double sh[K][NT / 64];
+  double s[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) s[k] = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT)
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] += part[k * RB + i];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = s[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    if (lane == 0) sh[k][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double t = 0.0;
+      for (int j = 0; j < NT / 64; ++j) t += sh[k][j];
+      out[k] = t;
+    }
 }
 
 // projection of w onto the disk |.| <= rho: P and its Jacobian (a, b, c) =
@@ -170,9 +200,11 @@ __global__ __launch_bounds__(NT) void k_f_sums(const double* __restrict__ y, con
 // one Newton step on lam: g = sum P - S, J = sum of Jacobians (regularised)
 __global__ __launch_bounds__(NT) void k_f_newton(const double* __restrict__ part, int nb, double* sc, double S0,
                                                 double S1) {
-  const double g0 = ffinal(part, 0, nb) - S0, g1 = ffinal(part, 1, nb) - S1;
-  double a = ffinal(part, 2, nb), b = ffinal(part, 3, nb), c = ffinal(part, 4, nb);
+  double t[5];
+  ffinal_rows<5>(part, nb, t);
   if (threadIdx.x == 0) {
+    const double g0 = t[0] - S0, g1 = t[1] - S1;
+    double a = t[2], b = t[3], c = t[4];
     const double reg = 1e-14 * (a + c + 1.0);
     a += reg;
     c += reg;
@@ -208,8 +240,10 @@ __global__ __launch_bounds__(NT) void k_f_apply(const double* __restrict__ y, co
 // change measure, restart decision and momentum coefficient
 __global__ __launch_bounds__(NT) void k_f_momentum(const double* __restrict__ part, int nb, double* sc,
                                                   double* mirror, double cscale) {
-  const double ch = ffinal(part, 0, nb), dot = ffinal(part, 1, nb);
+  double t2[2];
+  ffinal_rows<2>(part, nb, t2);
   if (threadIdx.x == 0) {
+    const double ch = t2[0], dot = t2[1];
     const double t = sc[F_T];
     double beta = 0.0, tn = 1.0;
     if (!(dot > 0.0)) {
@@ -308,6 +342,13 @@ static int fric_ensure(fvim_ctx* c) {
     return fail(FVIM_ENOMEM, "tangential contact workspace allocation failed");
   }
   return FVIM_OK;
+}
+
+int friction_reserve(fvim_ctx* c) { return fric_ensure(c); }
+
+size_t friction_footprint(const fvim_grid* g) {
+  const size_t n = (size_t)g->nx * g->ny, nm = (size_t)(g->nx / 2 + 1) * g->ny;
+  return sizeof(double) * (9 * n + 5 * RB + F_NSC) + sizeof(cpx<double>) * nm * (2 + mode_stride<double>(2));
 }
 
 // u = C y (2 planes)

@@ -72,7 +72,7 @@ size_t request_bytes(const fvim_request* r) {
   const size_t V = (size_t)g.nx * g.ny * g.nz, ns = (size_t)g.nx * g.ny;
   // operator + solver workspace, plus the caller-side state of a solve
   return fvim_footprint_bytes(&g, r->precision, 1) + sizeof(double) * (13 * V + 4 * ns + 3 * ns) +
-         fvim::krylov_footprint(&g, &r->opts);
+         fvim::krylov_footprint(&g, &r->opts) + (r->opts.mu_f > 0 ? fvim::friction_footprint(&g) : 0);
 }
 
 int run_job(fvim_server* s, Job* j, hipStream_t st) {

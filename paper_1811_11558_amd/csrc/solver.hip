@@ -1496,7 +1496,8 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
   if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1 || o->anderson_m < 0 ||
       o->anderson_m > AA_MMAX || !(o->inner_rel >= 0) || o->solver < 0 || o->solver > 2 || o->krylov_dim < 0 ||
-      o->krylov_dim > KMAX - 2)
+      o->krylov_dim > KMAX - 2 || !(o->mu_f >= 0) || !std::isfinite(o->mu_f) ||
+      (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)))
     return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
   int rc = sw_ensure(c);
   if (rc) return rc;
@@ -1516,6 +1517,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   const int aam = o->literal_alg1 ? 0 : o->anderson_m;
   if (aam > 0 && (rc = aa_ensure(c))) return rc;
   if (o->solver == 2 && (rc = kry_ensure(c, krylov_dim(o)))) return rc;
+  if (o->mu_f > 0 && (rc = friction_reserve(c))) return rc;
   // every buffer the operator applications of the solve use, sized now: no
   // device memory is freed or allocated while the solve runs
   if ((rc = operator_reserve(c, pb.dep, dT, pb.F))) return rc;
@@ -1553,6 +1555,13 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
       if (rc) return cleanup(rc);
       inf.contact_iters += ci.iters;
+      if (o->mu_f > 0) {                                   // tangential traction into T[0], T[1]
+        fvim_tangential_info fi;
+        rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * Wn, o->q_ratio[1] * o->mu_f * Wn,
+                            std::max(o->tol_contact, 1e-13), o->max_contact, T, &fi);
+        if (rc) return cleanup(rc);
+        inf.contact_iters += fi.iters;
+      }
       axpy(c, dT, T, -1.0, s->traction, 3 * n);           // dT = T - T_n
       // inexact inner solves while the outer error is large; a pass that
       // may end the step is always solved to tol_plastic

@@ -88,6 +88,9 @@ int operator_resid_parts(const fvim_grid& g);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
 void friction_release(fvim_ctx* c);
+// Allocates the tangential contact workspace now (not inside a solve).
+int friction_reserve(fvim_ctx* c);
+size_t friction_footprint(const fvim_grid* g);
 int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
                    double* q_out, fvim_tangential_info* info);
 // Device bytes the Newton-Krylov solver adds when opts selects it (0 else).

@@ -33,6 +33,11 @@ CASES = {
     # solution under the final load is stored as well
     "rough_ep_16x16x8": dict(grid=(16, 16, 8, 0.4), rough=dict(hurst=0.8, k_roll=2, k_cut=4, rms_slope=0.5, seed=3),
                              W=[0.005, 0.01], relax=0.3, mat=dict(E=1.0, nu=0.3, sigma_y0=0.1, E_h=0.01)),
+    # the Hertz case with Coulomb friction in the contact step: mu_f = 0.3,
+    # tangential force 0.5 mu_f W along x and 0.2 mu_f W along y at each load
+    "hertz_friction_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
+                                      mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1),
+                                      friction=dict(mu_f=0.3, q_ratio=(0.5, 0.2))),
 }
 # Standard under-relaxation (the printed overwrite of the relaxed update
 # oscillates on these cases; see the design notes).
@@ -55,7 +60,7 @@ def run(name):
         extra["p_elastic"] = p_el
     st = cp.new_state(g)
     t0 = time.time()
-    infos = cp.elastoplastic_solve(g, mat, h, c["W"], st, relax=c["relax"], **OPTS)
+    infos = cp.elastoplastic_solve(g, mat, h, c["W"], st, relax=c["relax"], **OPTS, **c.get("friction", {}))
     dt = time.time() - t0
     meta = np.array([repr({"case": c, "opts": OPTS, "seconds": dt,
                            "outer": [i["outer_iters"] for i in infos],

@@ -96,3 +96,34 @@ def test_tangential_arguments_are_checked():
     with pytest.raises(FvimError, match="iteration limit"):
         ctx.tangential_solve(pd, 0.3, (0.2 * W, 0.0), tol=1e-15, max_iter=8)
     ctx.close()
+
+
+FRICTION_GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)),
+                                             "golden", "hertz_friction_ep_16x16x8.npz")
+
+
+@pytest.mark.parametrize("solver", [0, 2])
+def test_elastoplastic_with_friction_matches_stored_oracle(solver):
+    """Algorithm 1 with Coulomb friction in the contact step (mu_f = 0.3,
+    tangential force (0.5, 0.2) mu_f W at each load) on the Hertz case:
+    the GPU state (plastic strain, stresses, the three traction components,
+    surface correction) reproduces the oracle's stored by
+    tests/golden/make_golden.py.  Friction moves the plastic zone (the
+    cumulated plastic strain differs from the frictionless case by about
+    45 %), so the comparison exercises the tangential traction inside the
+    plasticity solves."""
+    from paper_1811_11558_amd import Context, EPOptions
+    ref = np.load(FRICTION_GOLDEN)
+    g = grid_dict(16, 16, 8, lz=0.25)
+    ctx = Context(g, 1.0, 0.3, 0.01, 0.1)
+    st = ctx.new_state()
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                    EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15,
+                                              max_plastic=20000, solver=solver, mu_f=0.3, q_ratio=(0.5, 0.2)))
+    torch.cuda.synchronize()
+    _say([(i["outer_iters"], i["contact_iters"]) for i in infos])
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < 1e-10, (k, err)
+    ctx.close()
