@@ -198,7 +198,8 @@ typedef struct {
 
 /*
  * Tangential contact with Coulomb friction under the normal pressure p
- * ([ny][nx], device, e.g. from contact_solve): the friction Sec. 5.1 says
+ * ([ny][nx], device, >= 0 (negative values count as 0), e.g. from
+ * contact_solve): the friction Sec. 5.1 says
  * the contact step can include, here with normal and tangential problems
  * uncoupled (Goodman's approximation).  The tangential surface traction q
  * ([2][ny][nx], device, output; the tangential part of the traction input

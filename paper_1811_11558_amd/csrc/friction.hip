@@ -129,12 +129,13 @@ __device__ __forceinline__ void disk(double w0, double w1, double rho, double& p
   jc = s - a * w1 * w1;
 }
 
-// rho = mu_f p; block sums of p
+// rho = mu_f p; block sums of p (negative pressures, which a contact
+// solution does not hold, count as 0)
 __global__ __launch_bounds__(NT) void k_f_rho(const double* __restrict__ p, double mu, double* __restrict__ rho,
                                              size_t n, double* part) {
   double v[1] = {0.0};
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
-    const double pi = p[i];
+    const double pi = fmax(p[i], 0.0);
     rho[i] = mu * pi;
     v[0] += pi;
   }
