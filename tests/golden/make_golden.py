@@ -38,6 +38,10 @@ CASES = {
     "hertz_friction_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
                                       mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1),
                                       friction=dict(mu_f=0.3, q_ratio=(0.5, 0.2))),
+    # the Hertz case on depth nodes graded toward the surface,
+    # z_i = lz (i / (nz - 1))^2
+    "hertz_graded_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
+                                    mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1), graded=2.0),
 }
 # Standard under-relaxation (the printed overwrite of the relaxed update
 # oscillates on these cases; see the design notes).
@@ -49,6 +53,10 @@ def run(name):
     c = CASES[name]
     nx, ny, nz, lz = c["grid"]
     g = grid_dict(nx, ny, nz, lz=lz)
+    if "graded" in c:
+        z = lz * (np.arange(nz) / (nz - 1)) ** c["graded"]
+        z[-1] = lz
+        g["z"] = z
     mat = c["mat"]
     if "rough" in c:
         h = rough_surface(nx, ny, **c["rough"])
@@ -66,6 +74,8 @@ def run(name):
                            "outer": [i["outer_iters"] for i in infos],
                            "outer_err": [i["outer_err"] for i in infos],
                            "plastic": [i["plastic"] for i in infos]})])
+    if "z" in g:
+        extra["z"] = g["z"]
     np.savez_compressed(os.path.join(HERE, name + ".npz"), h=h, W=np.array(c["W"]), meta=meta,
                         **{k: v for k, v in st.items()}, **extra)
     print(name, "%.1f s" % dt, [i["outer_iters"] for i in infos])

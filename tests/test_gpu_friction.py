@@ -127,3 +127,25 @@ def test_elastoplastic_with_friction_matches_stored_oracle(solver):
         _say(k, err)
         assert err < 1e-10, (k, err)
     ctx.close()
+
+
+def test_elastoplastic_with_friction_fp32_refined():
+    """The same case in the FP32-refined mode with the accelerated outer
+    iteration (Anderson 5, warm-started inexact inner solves): within what
+    the tolerances allow (1e-8) of the stored float64 oracle state."""
+    from paper_1811_11558_amd import Context, EPOptions
+    ref = np.load(FRICTION_GOLDEN)
+    g = grid_dict(16, 16, 8, lz=0.25)
+    ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision="fp32_refined")
+    st = ctx.new_state()
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                    EPOptions(tol_outer=1e-12, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15,
+                                              max_plastic=20000, anderson_m=5, warm_start=1, inner_rel=0.1,
+                                              mu_f=0.3, q_ratio=(0.5, 0.2)))
+    torch.cuda.synchronize()
+    _say([(i["outer_iters"], i["r_evals"]) for i in infos])
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < 1e-8, (k, err)
+    ctx.close()
