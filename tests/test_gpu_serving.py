@@ -33,12 +33,13 @@ def _requests():
     return out
 
 
-def _opts(accelerated=False, solver=0):
+def _opts(accelerated=False, solver=0, mu_f=0.0):
     from paper_1811_11558_amd import EPOptions
+    fr = dict(mu_f=mu_f, q_ratio=(0.4, 0.1)) if mu_f > 0 else {}
     if accelerated:     # the serving benchmark's options
         return EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, anderson_m=5,
-                         warm_start=1, inner_rel=0.1, solver=solver)
-    return EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, solver=solver)
+                         warm_start=1, inner_rel=0.1, solver=solver, **fr)
+    return EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, solver=solver, **fr)
 
 
 def _run(server, reqs, opts=None):
@@ -47,16 +48,19 @@ def _run(server, reqs, opts=None):
     return [server.wait(i, (g["ny"], g["nx"])) for i, (g, _, _, _) in zip(ids, reqs)]
 
 
-@pytest.mark.parametrize("accelerated,solver", [(False, 0), (True, 0), (True, 2)])
-def test_results_identical_alone_and_in_mix(accelerated, solver):
+@pytest.mark.parametrize("accelerated,solver,mu_f", [(False, 0, 0.0), (True, 0, 0.0), (True, 2, 0.0),
+                                                     (True, 0, 0.3)])
+def test_results_identical_alone_and_in_mix(accelerated, solver, mu_f):
     """With Algorithm 1's relaxation and with the accelerated options
     (Anderson, warm-started and inexact inner solves, as the serving
     benchmark runs them), the latter also with Newton-Krylov plasticity
-    solves (whose host decisions and Krylov workspace are per request)."""
+    solves (whose host decisions and Krylov workspace are per request) and
+    with Coulomb friction in the contact step (per-request tangential
+    workspace)."""
     assert torch.cuda.is_available()
     from paper_1811_11558_amd import Server
     reqs = _requests()
-    opts = _opts(accelerated, solver)
+    opts = _opts(accelerated, solver, mu_f)
     srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
     mixed = _run(srv, reqs, opts)
     st = srv.stats()

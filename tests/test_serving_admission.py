@@ -38,3 +38,13 @@ def test_newton_krylov_footprint_counts_its_basis():
         extra = request_bytes(g, opts=EPOptions(solver=2, krylov_dim=m)) - base
         basis = 8 * 6 * V * (md + 2)
         assert basis <= extra < basis + (1 << 20), (m, extra, basis)
+
+
+def test_friction_footprint_counts_its_workspace():
+    """mu_f > 0 adds the tangential contact workspace (9 surface fields and
+    two 2-plane spectra) to a request's footprint."""
+    from paper_1811_11558_amd import EPOptions, request_bytes
+    g = dict(nx=256, ny=256, nz=32, lx=1.0, ly=1.0, lz=0.25)
+    base = request_bytes(g, opts=EPOptions())
+    extra = request_bytes(g, opts=EPOptions(mu_f=0.3, q_ratio=(0.5, 0.0))) - base
+    assert 9 * 8 * 256 * 256 <= extra < 9 * 8 * 256 * 256 + 16 * 129 * 256 * 16 + (1 << 20)
