@@ -70,7 +70,7 @@ __device__ double ffinal(const double* part, int k, int nb) {
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = NT / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
   double r = sh[0];

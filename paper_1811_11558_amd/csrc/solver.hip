@@ -68,7 +68,7 @@ __device__ double final_sum(const double* part, int k, int nb) {
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = NT / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
     __syncthreads();
   }
   double r = sh[0];
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_zact(int* __restrict__ flags, int nz) {
   sh[threadIdx.x] = za;
   __syncthreads();
   for (int o = NT / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(NTS) void k_sum_pairs(const double* __restrict__ pa
   sh[1][threadIdx.x] = b;
   __syncthreads();
   for (int o = NTS / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
+    if ((int)threadIdx.x < o) {
       sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
       sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
     }
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(NT) void k_kcomb(double* y, const double* x, double
   __shared__ double cs[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j)
-    if (threadIdx.x == j) cs[j] = kc.c[j];
+    if ((int)threadIdx.x == j) cs[j] = kc.c[j];
   __syncthreads();
   const size_t n6 = 6 * V;
   double nn[1] = {0.0};
@@ -1208,7 +1208,6 @@ static int newton_krylov(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o
     return fail(FVIM_EINVAL, "Newton-Krylov workspace not reserved");
   double* U = w->kry;
   double* ystar = U + (size_t)(m + 1) * n6;
-  const double sc = inner_scale(c);
   int* hz = reinterpret_cast<int*>(w->hsc + NSCAL - 1);      // pinned host word
   double f;
   int rc;
