@@ -379,7 +379,7 @@ static int tangential_compliance(fvim_ctx* c, const double* y, double* u, hipStr
 }
 
 int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
-                   double* q_out, fvim_tangential_info* info) {
+                   double* q_out, fvim_tangential_info* info, bool warm) {
   if (!(mu_f > 0.0) || !std::isfinite(Qx) || !std::isfinite(Qy) || !(tol > 0.0) || max_iter < 1)
     return fail(FVIM_EINVAL, "tangential_solve: bad arguments");
   int rc = fric_ensure(c);
@@ -421,6 +421,21 @@ int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double 
   }
   if (e != hipSuccess) return fail_hip(e, "tangential_solve");
   const double cscale = dA / (mu_f * W);
+  if (warm) {
+    // start from the projection of the caller's q (the previous solution
+    // under a nearby pressure) onto the new constraint set: Newton steps on
+    // lam with v = q (step length 0), then q = y = P(q + lam)
+    e = hipMemcpyAsync(y, q_out, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "tangential_solve");
+    for (int j = 0; j < 2 * NEWTON + 4; ++j) {
+      hipLaunchKernelGGL(k_f_sums, dim3(nb), dim3(NT), 0, st, y, y, 0.0, rho, w->sc, n, w->part);
+      hipLaunchKernelGGL(k_f_newton, dim3(1), dim3(NT), 0, st, w->part, nb, w->sc, S0, S1);
+    }
+    hipLaunchKernelGGL(k_f_apply, dim3(nb), dim3(NT), 0, st, y, y, 0.0, rho, w->sc, q, qn, n, w->part);
+    e = hipMemcpyAsync(q, qn, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(y, qn, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "tangential_solve");
+  }
   int k = 0;
   double change = INFINITY;
   bool conv = false;

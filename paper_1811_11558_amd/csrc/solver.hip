@@ -1556,8 +1556,9 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       inf.contact_iters += ci.iters;
       if (o->mu_f > 0) {                                   // tangential traction into T[0], T[1]
         fvim_tangential_info fi;
+        // from the second pass on, T holds the previous pass's traction
         rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * Wn, o->q_ratio[1] * o->mu_f * Wn,
-                            std::max(o->tol_contact, 1e-13), o->max_contact, T, &fi);
+                            std::max(o->tol_contact, 1e-13), o->max_contact, T, &fi, k > 1);
         if (rc) return cleanup(rc);
         inf.contact_iters += fi.iters;
       }

@@ -91,8 +91,10 @@ void friction_release(fvim_ctx* c);
 // Allocates the tangential contact workspace now (not inside a solve).
 int friction_reserve(fvim_ctx* c);
 size_t friction_footprint(const fvim_grid* g);
+// warm: q_out holds a previous solution to start from (projected onto the
+// new constraint set); else the start is the scaled full-slip field.
 int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
-                   double* q_out, fvim_tangential_info* info);
+                   double* q_out, fvim_tangential_info* info, bool warm = false);
 // Device bytes the Newton-Krylov solver adds when opts selects it (0 else).
 size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o);
 // out = base - T (u1 - u2) for the voxels v < na of each component
