@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--graded", type=float, default=0.0,
                     help="operator: non-uniform depth nodes z_i = lz (i / (nz - 1))^GRADED (0 = uniform)")
     ap.add_argument("--mu-f", type=float, default=0.3, help="friction: Coulomb coefficient")
+    ap.add_argument("--friction", action="store_true",
+                    help="solve/rough/area/serve: Coulomb friction (--mu-f, --q-ratio along x) in the contact step")
     ap.add_argument("--q-ratio", type=float, default=0.5, help="friction: tangential load Q / (mu_f W) along x")
     ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
                     help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
@@ -248,6 +250,10 @@ def bench_batch(a):
 SOLVER_NAMES = {0: "dfsane", 1: "picard", 2: "newton_krylov"}
 
 
+def friction_opts(a):
+    return dict(mu_f=a.mu_f, q_ratio=(a.q_ratio, 0.0)) if a.friction else {}
+
+
 def bench_rough(a):
     """Elastoplastic contact of a self-affine rough surface (flat PSD below
     k_roll, power law with Hurst exponent H up to k_cut, rms slope 0.1, seed
@@ -269,7 +275,7 @@ def bench_rough(a):
     Ws = [a.load * (i + 1) / 5 for i in range(5)]
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
                      max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
-                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov)
+                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
     V = a.nx * a.ny * a.nz
     runs = {}
     for prec in (["fp64", "fp32_refined"] if a.compare else [a.precision]):
@@ -290,7 +296,8 @@ def bench_rough(a):
            "config": {"workload": "rough elastoplastic contact %dx%dx%d" % (a.nx, a.ny, a.nz), "hurst": a.hurst,
                       "k_roll": a.k_roll, "k_cut": kcut, "rms_slope": 0.1, "W": a.load, "load_steps": 5,
                       "tol_outer": 1e-7, "anderson": a.anderson, "warm_start": a.warm,
-                      "inner_rel": a.inner_rel, "solver": SOLVER_NAMES[a.solver], "krylov_dim": a.krylov}}
+                      "inner_rel": a.inner_rel, "solver": SOLVER_NAMES[a.solver], "krylov_dim": a.krylov,
+                      "friction": friction_opts(a)}}
     for prec, r in runs.items():
         out[prec] = {k: v for k, v in r.items() if k != "state"}
         p = r["state"]["traction"][2]
@@ -333,7 +340,7 @@ def bench_area(a):
     kcut = a.nx // 4
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=4000,
                      max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
-                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov)
+                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
     rows = []
     for slope in [float(x) for x in a.slopes.split(",")]:
         h = torch.from_numpy(rough_surface(a.nx, a.ny, hurst=0.8, k_roll=2, k_cut=kcut, rms_slope=slope,
@@ -430,7 +437,7 @@ def bench_solve(a):
     Ws = [0.002 * (i + 1) for i in range(10)]
     opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, max_outer=2000,
                      max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel,
-                     solver=a.solver, krylov_dim=a.krylov)
+                     solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
     times, infos = [], None
     for _ in range(max(1, a.steps)):
         ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=a.precision)
@@ -469,7 +476,7 @@ def bench_serve(a):
         prepared.append((r, g, h))
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
                      max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel,
-                     solver=a.solver, krylov_dim=a.krylov)
+                     solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
     srv = Server(hbm_budget_bytes=200 << 30, max_slots=a.slots)
     t0 = time.perf_counter()
     ids = []

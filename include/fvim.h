@@ -256,8 +256,10 @@ typedef struct {
   double inner_rel;    /* > 0: inexact plasticity solves to the relative    */
                        /* tolerance max(tol_plastic, inner_rel * the        */
                        /* previous pass's outer error) while that error is  */
-                       /* at least tol_outer; a step is accepted only after */
-                       /* a pass solved to tol_plastic; 0: always tol_plastic*/
+                       /* at least tol_outer (with friction, the tangential */
+                       /* solves likewise); a step is accepted only after a */
+                       /* pass solved to the full tolerances; 0: always     */
+                       /* tol_plastic                                      */
   int krylov_dim;      /* Newton-Krylov: Arnoldi steps per Newton step,     */
                        /* 1..30 (0 = 20); ignored by the other solvers      */
   double mu_f;         /* > 0: Coulomb friction in the contact step: after  */

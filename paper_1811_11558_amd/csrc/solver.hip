@@ -1554,20 +1554,25 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
       if (rc) return cleanup(rc);
       inf.contact_iters += ci.iters;
+      // inexact inner solves (plasticity, and the tangential contact with
+      // friction) while the outer error is large; a pass that may end the
+      // step is always solved to the full tolerances
+      const bool loose = o->inner_rel > 0 && !(err_prev < o->tol_outer);
+      const double tol_f_full = std::max(o->tol_contact, 1e-13);
+      double tol_f = tol_f_full;
       if (o->mu_f > 0) {                                   // tangential traction into T[0], T[1]
+        if (loose) tol_f = std::max(tol_f, o->inner_rel * err_prev);
         fvim_tangential_info fi;
         // from the second pass on, T holds the previous pass's traction
-        rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * Wn, o->q_ratio[1] * o->mu_f * Wn,
-                            std::max(o->tol_contact, 1e-13), o->max_contact, T, &fi, k > 1);
+        rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * Wn, o->q_ratio[1] * o->mu_f * Wn, tol_f,
+                            o->max_contact, T, &fi, k > 1);
         if (rc) return cleanup(rc);
         inf.contact_iters += fi.iters;
       }
       axpy(c, dT, T, -1.0, s->traction, 3 * n);           // dT = T - T_n
-      // inexact inner solves while the outer error is large; a pass that
-      // may end the step is always solved to tol_plastic
       double tol_rel = o->tol_plastic;
-      if (o->inner_rel > 0 && !(err_prev < o->tol_outer)) tol_rel = std::max(tol_rel, o->inner_rel * err_prev);
-      const bool exact = tol_rel == o->tol_plastic;
+      if (loose) tol_rel = std::max(tol_rel, o->inner_rel * err_prev);
+      const bool exact = tol_rel == o->tol_plastic && tol_f == tol_f_full;
       int it, ne;
       double res;
       rc = plasticity(c, dT, s, o, tol_rel, o->warm_start && k > 1, pb, &it, &ne, &res);
