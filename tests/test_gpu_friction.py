@@ -95,6 +95,10 @@ def test_tangential_arguments_are_checked():
             ctx.tangential_solve(pd, mu, Q)
     with pytest.raises(FvimError, match="iteration limit"):
         ctx.tangential_solve(pd, 0.3, (0.2 * W, 0.0), tol=1e-15, max_iter=8)
+    # no tangential force: no traction (the minimiser of the energy with
+    # zero resultant), from the first check on
+    q, info = ctx.tangential_solve(pd, 0.3, (0.0, 0.0))
+    assert float(q.abs().max()) == 0.0 and info["iters"] == 8
     ctx.close()
 
 
