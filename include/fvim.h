@@ -362,6 +362,8 @@ typedef struct {
   double W_steps[FVIM_MAX_STEPS];
   fvim_ep_opts opts;
   const double* h;           /* HOST pointer [ny][nx], copied at submission */
+  const double* z;           /* HOST [nz] depth nodes (fvim_set_depth_nodes  */
+                             /* rules) or NULL (uniform), copied            */
 } fvim_request;
 
 typedef struct {

@@ -82,7 +82,7 @@ MAX_STEPS = 16
 class _Request(ctypes.Structure):
     _fields_ = [("grid", _Grid), ("mat", _Material), ("precision", ctypes.c_int),
                 ("n_steps", ctypes.c_int), ("W_steps", ctypes.c_double * MAX_STEPS),
-                ("opts", EPOptions), ("h", ctypes.c_void_p)]
+                ("opts", EPOptions), ("h", ctypes.c_void_p), ("z", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):
@@ -429,7 +429,8 @@ def admit_index(pending_bytes, budget, in_use):
     return lib.fvim_admit_index(arr, len(pending_bytes), int(budget), int(in_use))
 
 
-def make_request(grid, h, W_steps, E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1, precision="fp64", opts=None):
+def make_request(grid, h, W_steps, E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1, precision="fp64", opts=None,
+                 z=None):
     import numpy as np
     h = np.ascontiguousarray(h, dtype=np.float64)
     if h.shape != (grid["ny"], grid["nx"]):
@@ -446,7 +447,12 @@ def make_request(grid, h, W_steps, E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1, precis
         r.W_steps[i] = float(w)
     r.opts = opts or EPOptions()
     r.h = h.ctypes.data
-    return r, h
+    if z is not None:
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        if z.shape != (grid["nz"],):
+            raise FvimError(FVIM_EINVAL, "depth nodes: need %d values" % grid["nz"])
+        r.z = z.ctypes.data
+    return r, (h, z)
 
 
 def request_bytes(grid, precision="fp64", opts=None):

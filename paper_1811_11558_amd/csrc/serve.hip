@@ -42,6 +42,7 @@ struct Job {
   uint64_t id = 0;
   fvim_request req;
   std::vector<double> h;       // host copy of the surface
+  std::vector<double> z;       // host copy of the depth nodes (empty: uniform)
   size_t bytes = 0;            // admission footprint
   fvim_result res;
   std::vector<double> p_host, u3_host;
@@ -82,6 +83,10 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
   fvim_ctx* ctx = nullptr;
   int rc = fvim_create(&g, &r.mat, r.precision, FVIM_K0_INCLUDE, st, &ctx);
   if (rc) return rc;
+  if (!j->z.empty() && (rc = fvim_set_depth_nodes(ctx, j->z.data()))) {
+    fvim_destroy(ctx);
+    return rc;
+  }
   double* mem = nullptr;
   const size_t nd = 13 * V + 5 * ns;
   // allocation and the copies from pageable host memory do not overlap
@@ -214,6 +219,8 @@ int fvim_server_submit(fvim_server* s, const fvim_request* r, uint64_t* id) {
   const size_t ns = (size_t)g.nx * g.ny;
   j->h.assign(r->h, r->h + ns);
   j->req.h = nullptr;
+  if (r->z) j->z.assign(r->z, r->z + g.nz);
+  j->req.z = nullptr;
   j->bytes = request_bytes(r);
   if (j->bytes > s->budget) return FVIM_ENOMEM;
   memset(&j->res, 0, sizeof(j->res));

@@ -98,3 +98,41 @@ def test_admission_respects_budget():
     with pytest.raises(FvimError):
         srv.submit(big, np.zeros((512, 512)), [0.001])
     srv.close()
+
+
+def test_requests_with_depth_nodes_identical_alone_and_in_mix():
+    """Requests may carry their own depth nodes (copied at submission): two
+    graded-node requests among uniform ones give the same result alone and
+    in the mix, and differ from the same request on uniform nodes."""
+    from paper_1811_11558_amd import Server
+    assert torch.cuda.is_available()
+    reqs = _requests()[:4]
+    zs = []
+    for k, (g, h, W, prec) in enumerate(reqs):
+        nz = g["nz"]
+        z = None
+        if k % 2 == 0:
+            z = g["lz"] * (np.arange(nz) / (nz - 1)) ** 2
+            z[-1] = g["lz"]
+        zs.append(z)
+    opts = _opts(True)
+
+    def run(server, items):
+        ids = [server.submit(g, h, W, precision=prec, opts=opts, z=z) for (g, h, W, prec), z in items]
+        return [server.wait(i, (g["ny"], g["nx"])) for i, ((g, _, _, _), _) in zip(ids, items)]
+
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=4)
+    mixed = run(srv, list(zip(reqs, zs)))
+    srv.close()
+    for r in mixed:
+        assert r["status"] == 0, r
+    for k in range(len(reqs)):
+        alone = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+        a = run(alone, [(reqs[k], zs[k])])[0]
+        alone.close()
+        assert np.array_equal(a["p"], mixed[k]["p"]), k
+        assert np.array_equal(a["u3p"], mixed[k]["u3p"]), k
+    uni = Server(hbm_budget_bytes=8 << 30, max_slots=1)
+    u0 = run(uni, [(reqs[0], None)])[0]
+    uni.close()
+    assert not np.array_equal(u0["u3p"], mixed[0]["u3p"])
