@@ -88,8 +88,8 @@ int fvim_set_stream(fvim_ctx* ctx, void* hip_stream);
  * node depths, z[0] = 0, strictly increasing, z[nz-1] = lz (to 1e-12
  * relative), copied; NULL restores the uniform nodes z_i = i lz / (nz - 1).
  * The depth pass then integrates the P1 eigenstress exactly on these
- * elements.  Scalar products of the solvers keep the uniform trapezoid
- * weights (a different but equivalent norm: the roots do not change).
+ * elements, and the solvers' scalar products use the trapezoid weights of
+ * these nodes.
  * Contexts with non-uniform nodes are rejected by
  * fvim_operator_apply_batch.  Drops the solver workspace (captured
  * evaluations bake the node table in).  Blocking.  FVIM_EINVAL for nodes

@@ -409,7 +409,7 @@ int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* tractio
                          const double* Fo, double* R, double* part, int* nparts, const int* zact) {
   if (misaligned(eps_p) || misaligned(traction) || misaligned(x) || misaligned(Fo) || misaligned(R))
     return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
-  const ResidEpilogue ep = {x, Fo, part, c->grid.nz};
+  const ResidEpilogue ep = {x, Fo, part, c->grid.nz, c->wz};
   const size_t np = (size_t)6 * c->grid.nz;
   if (c->precision == FVIM_FP32_REFINED && !c->force_fp64) {
     *nparts = x_c2r_blocks<float>(c->grid.nx, c->grid.ny, np);
@@ -504,7 +504,7 @@ void fvim_destroy(fvim_ctx* c) {
   else hipDeviceSynchronize();
   if (c->side) hipStreamSynchronize(c->side);
   void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32, c->dbatch,
-                  c->hz};
+                  c->hz, c->wz};
   for (void* p : ptrs)
     if (p) hipFree(p);
   hipEvent_t evs[] = {c->ev_spec, c->ev_nyq};
@@ -622,15 +622,32 @@ int fvim_set_depth_nodes(fvim_ctx* c, const double* z) {
     hipFree(c->hz);
     c->hz = nullptr;
   }
+  if (c->wz) {
+    hipFree(c->wz);
+    c->wz = nullptr;
+  }
   if (!z) return FVIM_OK;
-  if (hipMalloc((void**)&c->hz, sizeof(double) * h.size()) != hipSuccess) {
+  // trapezoid weights of the nodes in units of the uniform spacing
+  const double hu = c->grid.lz / (nz - 1);
+  std::vector<double> wz(nz, 0.0);
+  for (int i = 0; i + 1 < nz; ++i) {
+    wz[i] += 0.5 * h[i] / hu;
+    wz[i + 1] += 0.5 * h[i] / hu;
+  }
+  if (hipMalloc((void**)&c->hz, sizeof(double) * h.size()) != hipSuccess ||
+      hipMalloc((void**)&c->wz, sizeof(double) * nz) != hipSuccess) {
+    if (c->hz) hipFree(c->hz);
     c->hz = nullptr;
+    c->wz = nullptr;
     return fail(FVIM_ENOMEM, "depth nodes: allocation failed");
   }
   e = hipMemcpy(c->hz, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->wz, wz.data(), sizeof(double) * nz, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     hipFree(c->hz);
+    hipFree(c->wz);
     c->hz = nullptr;
+    c->wz = nullptr;
     return fail_hip(e, "depth nodes");
   }
   return FVIM_OK;

@@ -436,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
       c += red[1][w];
     }
     const int cp = plane / ep.nz, z = plane - cp * ep.nz;
-    const double wt = (cp < 3 ? 1.0 : 2.0) * ((z == 0 || z == ep.nz - 1) ? 0.5 : 1.0);
+    const double wt = (cp < 3 ? 1.0 : 2.0) * (ep.wz ? ep.wz[z] : ((z == 0 || z == ep.nz - 1) ? 0.5 : 1.0));
     ep.part[2 * blockIdx.x] = wt * a;
     ep.part[2 * blockIdx.x + 1] = wt * c;
   }

@@ -60,12 +60,14 @@ inline int mode_stride(int np) {
 // x set, each output value w of the first segment (the 6 nz strain planes)
 // is replaced by r = x - w, and block b writes wt sum r.r to part[2 b] and,
 // with Fo, wt sum Fo.(r - Fo) to part[2 b + 1]; wt = 2 for shear planes
-// (plane / nz >= 3), halved at the first and last depth node.
+// (plane / nz >= 3) times the depth weight of the plane's node: wz[z] if
+// given (device, nz), else 1/2 at the first and last node and 1 between.
 struct ResidEpilogue {
   const double* x;
   const double* Fo;
   double* part;
   int nz;
+  const double* wz;
 };
 // padd (optional): float64 constant added to each plane of the output.  No
 // streaming loads here: keeping its input cached measured faster (the next

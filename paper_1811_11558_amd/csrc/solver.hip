@@ -270,13 +270,14 @@ __global__ __launch_bounds__(NT) void k_axpy(double* __restrict__ y, const doubl
 }
 
 // Weight of element i of a [6][nz][plane] strain field in the scalar
-// product: 2 for the shear components (each stands for two tensor entries),
-// 1/2 at the first and last depth node (trapezoid rule in depth).  plane is
-// 2^lp.
-__device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz) {
+// product: 2 for the shear components (each stands for two tensor entries)
+// times the trapezoid weight of its depth node in units of the uniform
+// spacing: wz[z] on non-uniform nodes, else 1/2 at the first and last node
+// and 1 between.  plane is 2^lp.
+__device__ __forceinline__ double field_weight(size_t i, int lp, unsigned nz, const double* wz) {
   const unsigned zc = (unsigned)(i >> lp);      // c * nz + z
   const unsigned z = zc % nz;
-  return (zc < 3u * nz ? 1.0 : 2.0) * ((z == 0 || z == nz - 1) ? 0.5 : 1.0);
+  return (zc < 3u * nz ? 1.0 : 2.0) * (wz ? wz[z] : ((z == 0 || z == nz - 1) ? 0.5 : 1.0));
 }
 
 // Sums of the pairs part[2 b], part[2 b + 1] (b < nb), in a fixed order, into
@@ -339,12 +340,12 @@ __global__ __launch_bounds__(NTS) void k_sum_pairs(const double* __restrict__ pa
 // weighted sums  <a, a>, <a, b>, <b, b>  with a = a1 - a0, b = b1 - b0 (a0/b0 may be NULL)
 __global__ __launch_bounds__(NT) void k_wdots(const double* __restrict__ a1, const double* a0,
                                              const double* __restrict__ b1, const double* b0, int lp, unsigned nz,
-                                             size_t n, double* part) {
+                                             const double* __restrict__ wz, size_t n, double* part) {
   double v[3] = {0.0, 0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
     double a = a1[i] - (a0 ? a0[i] : 0.0);
     double b = b1[i] - (b0 ? b0[i] : 0.0);
-    const double wt = field_weight(i, lp, nz);
+    const double wt = field_weight(i, lp, nz, wz);
     v[0] += wt * a * a;
     v[1] += wt * a * b;
     v[2] += wt * b * b;
@@ -379,7 +380,8 @@ struct KCoef {
 // 4 blockIdx.y on, x is read once per group of four.  Block b writes
 // part[i * RB + b].
 __global__ __launch_bounds__(NT) void k_kdot(const double* __restrict__ base, int n, const double* __restrict__ x,
-                                            size_t na, size_t V, int lp, unsigned nz, double* part) {
+                                            size_t na, size_t V, int lp, unsigned nz, const double* __restrict__ wz,
+                                            double* part) {
   const int i0 = blockIdx.y * 4;
   const size_t n6 = 6 * V;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -387,7 +389,7 @@ __global__ __launch_bounds__(NT) void k_kdot(const double* __restrict__ base, in
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       const size_t i = c * V + v;
-      const double xi = x[i] * field_weight(i, lp, nz);
+      const double xi = x[i] * field_weight(i, lp, nz, wz);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (i0 + k < n) acc[k] += base[(size_t)(i0 + k) * n6 + i] * xi;
@@ -400,7 +402,7 @@ __global__ __launch_bounds__(NT) void k_kdot(const double* __restrict__ base, in
 // sums of the weighted <y, y> when part is given.
 __global__ __launch_bounds__(NT) void k_kcomb(double* y, const double* x, double a, const double* __restrict__ base,
                                              int n, KCoef kc, size_t na, size_t V, int lp, unsigned nz,
-                                             double* part) {
+                                             const double* __restrict__ wz, double* part) {
   __shared__ double cs[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j)
@@ -415,7 +417,7 @@ __global__ __launch_bounds__(NT) void k_kcomb(double* y, const double* x, double
       double r = x ? a * x[i] : 0.0;
       for (int j = 0; j < n; ++j) r += cs[j] * base[(size_t)j * n6 + i];
       y[i] = r;
-      nn[0] += field_weight(i, lp, nz) * r * r;
+      nn[0] += field_weight(i, lp, nz, wz) * r * r;
     }
   }
   if (part) block_sums<1>(nn, part);
@@ -999,8 +1001,8 @@ static int wdots(fvim_ctx* c, const double* a1, const double* a0, const double* 
   SolverWork* w = c->sw;
   const size_t n6 = 6 * w->V;
   const int nb = nblocks(n6);
-  hipLaunchKernelGGL(k_wdots, dim3(nb), dim3(NT), 0, c->stream, a1, a0, b1, b0, w->lp, (unsigned)c->grid.nz, n6,
-                     w->part);
+  hipLaunchKernelGGL(k_wdots, dim3(nb), dim3(NT), 0, c->stream, a1, a0, b1, b0, w->lp, (unsigned)c->grid.nz, c->wz,
+                     n6, w->part);
   hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
   int rc = read_scalars(c, S_DOT0, 3);
   if (rc) return rc;
@@ -1139,7 +1141,7 @@ static int kdots(fvim_ctx* c, const double* base, int n, const double* x, size_t
   SolverWork* w = c->sw;
   const int nb = nblocks(na);
   hipLaunchKernelGGL(k_kdot, dim3(nb, (n + 3) / 4), dim3(NT), 0, c->stream, base, n, x, na, w->V, w->lp,
-                     (unsigned)c->grid.nz, w->kry_part);
+                     (unsigned)c->grid.nz, c->wz, w->kry_part);
   hipLaunchKernelGGL(k_kfinal, dim3(n), dim3(NT), 0, c->stream, w->kry_part, nb, w->kry_out);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail_hip(e, "Krylov scalar products");
@@ -1156,7 +1158,7 @@ static int kcomb(fvim_ctx* c, double* y, const double* x, double a, const double
   KCoef kc = {};
   for (int i = 0; i < n; ++i) kc.c[i] = coef[i];
   hipLaunchKernelGGL(k_kcomb, dim3(nb), dim3(NT), 0, c->stream, y, x, a, base, n, kc, na, w->V, w->lp,
-                     (unsigned)c->grid.nz, norm2 ? w->kry_part : nullptr);
+                     (unsigned)c->grid.nz, c->wz, norm2 ? w->kry_part : nullptr);
   if (!norm2) {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FVIM_OK : fail_hip(e, "Krylov combination");

@@ -32,6 +32,7 @@ struct fvim_ctx {
   void* mt64 = nullptr;        // per-mode depth-pass constants (built on first use)
   void* mt32 = nullptr;
   double* hz = nullptr;        // non-uniform depth nodes: element lengths (device), else NULL
+  double* wz = nullptr;        //   and their trapezoid weights / the uniform spacing (device)
   void* dbatch = nullptr;      // device copy of a batched depth-pass table
   size_t dbatch_bytes = 0;
   // optional second stream (default priority) for the Nyquist-mode depth

@@ -136,11 +136,9 @@ GRADED_GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__impor
 @pytest.mark.parametrize("solver", [0, 2])
 def test_elastoplastic_on_graded_nodes_matches_stored_oracle(solver):
     """Algorithm 1 on the Hertz case with depth nodes z_i = lz (i/7)^2: the
-    GPU state reproduces the oracle's (tests/golden/make_golden.py).  The
-    oracle's scalar products use the trapezoid weights of these nodes and
-    the GPU's the uniform ones (an equivalent norm), so the two could stop
-    at different iterates of the same fixed point; at these tolerances they
-    agree to about 1e-13 in the same outer pass counts (51, 58)."""
+    GPU state reproduces the oracle's (tests/golden/make_golden.py), whose
+    scalar products, like the GPU's, use the trapezoid weights of these
+    nodes."""
     from paper_1811_11558_amd import Context, EPOptions
     ref = np.load(GRADED_GOLDEN)
     g = grid_dict(16, 16, 8, lz=0.25)
