@@ -18,9 +18,10 @@ def declared_functions():
     return sorted(set(n for n in names if n not in ("if", "while", "for", "sizeof")))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_operator_and_solver_calls():
     names = declared_functions()
-    for n in ("mindlin_apply", "boussinesq_apply", "return_map", "contact_solve", "elastoplastic_solve"):
+    for n in ("mindlin_apply", "boussinesq_apply", "return_map", "contact_solve", "elastoplastic_solve",
+              "tangential_solve", "fvim_set_depth_nodes"):
         assert n in names
 
 

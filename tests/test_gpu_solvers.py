@@ -58,7 +58,7 @@ def test_contact_matches_oracle(n, W, seed):
 
 def test_contact_solve_on_workspace_that_held_nan():
     """The solver workspace of a new context is not cleared memory: pages
-    that held NaN are returned to the driver first, then a contact solve on
+    that held NaN are freed first, then a contact solve on
     a fresh context (which allocates its workspace then) must stay finite
     and equal a solve on an ordinary context.  The conjugate direction of the
     first iteration must not be formed from what the array held."""
