@@ -267,7 +267,8 @@ typedef struct {
                        /* tangential force q_ratio * mu_f * W (|q_ratio|<1) */
                        /* to the tolerance max(tol_contact, 1e-13) (its    */
                        /* iterations count in contact_iters), and the     */
-                       /* traction T carries it; 0: frictionless            */
+                       /* traction T carries it (none at a zero load); 0: */
+                       /* frictionless                                      */
   double q_ratio[2];
 } fvim_ep_opts;
 

@@ -1562,7 +1562,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       const bool loose = o->inner_rel > 0 && !(err_prev < o->tol_outer);
       const double tol_f_full = std::max(o->tol_contact, 1e-13);
       double tol_f = tol_f_full;
-      if (o->mu_f > 0) {                                   // tangential traction into T[0], T[1]
+      if (o->mu_f > 0 && Wn > 0) {                         // tangential traction into T[0], T[1]
         if (loose) tol_f = std::max(tol_f, o->inner_rel * err_prev);
         fvim_tangential_info fi;
         // from the second pass on, T holds the previous pass's traction
