@@ -306,3 +306,36 @@ def test_newton_krylov_reaches_the_dfsane_root_superlinearly():
     scale = np.max(np.abs(a['d_eps']))
     assert np.max(np.abs(a['d_eps'] - b['d_eps'])) < 1e-10 * scale
     assert np.max(np.abs(a['d_eps_p'] - b['d_eps_p'])) < 1e-9 * np.max(np.abs(a['d_eps_p']))
+
+
+def test_newton_system_on_the_plastic_support_is_exact():
+    """The Newton step can be found on the plastic support: with J = I - A T
+    (A = grad_s N[C : .], T the consistent tangent), solving
+    (I - T A) y = -T R and taking delta = -R + A y gives the delta of
+    J delta = -R.  Checked with dense matrices built from the oracle's
+    operator and tangent on a 4 x 4 x 3 grid (288 unknowns)."""
+    from oracle import operators as ops
+    g = grid_dict(4, 4, 3, lz=0.2)
+    rng = np.random.default_rng(21)
+    shape = (6, 3, 4, 4)
+    d_eps, sig, ep = _rand_state(rng, shape[1:], 0.004)
+    n = int(np.prod(shape))
+    _, dp, _ = pl.return_map(d_eps, sig, ep, E, NU, SY, EH)
+    assert 0 < np.count_nonzero(dp) < dp.size
+    A = np.zeros((n, n))
+    T = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        v = e.reshape(shape)
+        A[:, k] = ops.mindlin_apply(g, E, NU, v)['strain'].ravel()
+        T[:, k] = pl.return_map_tangent(d_eps, sig, ep, E, NU, SY, EH, v).ravel()
+    R = rng.standard_normal(n)
+    J = np.eye(n) - A @ T
+    delta = np.linalg.solve(J, -R)
+    y = np.linalg.solve(np.eye(n) - T @ A, -T @ R)
+    delta2 = -R + A @ y
+    assert np.linalg.norm(delta2 - delta) <= 1e-10 * np.linalg.norm(delta)
+    # y lives on the plastic voxels only
+    plastic = np.broadcast_to(dp > 0, shape).ravel()
+    assert np.all(y[~plastic] == 0.0)
