@@ -155,3 +155,34 @@ def test_elastoplastic_on_graded_nodes_matches_stored_oracle(solver):
         _say(k, err)
         assert err < 1e-11, (k, err)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL), ("fp32_refined", 2e-6)])
+def test_graded_nodes_benchmark_size_sampled_modes(precision, tol):
+    """256 x 256 x 64 on the graded nodes of the benchmark's --graded 2 run,
+    in its launch configuration (tuned layout, streaming loads): the GPU
+    output's DFT on sampled modes (k = 0, Nyquist lines, edges, random) is
+    the oracle's spectral response on those modes and nodes."""
+    from paper_1811_11558_amd import Context
+    g = grid_dict(256, 256, 64, 1.0, 1.0, 0.25)
+    z = graded_nodes(64, 0.25, 2.0)
+    eps = filtered_eigenstrain(g, seed=0)
+    t = filtered_traction(g, seed=1000)
+    ctx = Context(g, E, NU, precision=precision)
+    ctx.set_depth_nodes(z)
+    ctx.tune()
+    e_d, t_d = torch.from_numpy(eps).cuda(), torch.from_numpy(t).cuda()
+    ctx.operator_apply(e_d, t_d, want=("strain",))
+    out = ctx.operator_apply(e_d, t_d, want=("strain",))
+    torch.cuda.synchronize()
+    strain = out["strain"].cpu().numpy()
+    spec = np.fft.fft2(strain, axes=(-2, -1)) / (256 * 256)
+    rng = np.random.default_rng(2)
+    modes = [(0, 0), (0, 1), (1, 0), (0, 128), (128, 0), (128, 128), (255, 1), (3, 128), (128, 77)]
+    modes += [tuple(int(v) for v in rng.integers(0, 256, 2)) for _ in range(15)]
+    ref = ora.apply(dict(g, z=z), E, NU, eps_p=eps, traction=t, modes=modes)["strain_hat"]
+    got = np.stack([spec[:, :, ky, kx].T for (ky, kx) in modes])
+    err = _rel(got, ref)
+    _say(precision, "graded sampled-mode rel err", err, "layout", ctx.get_option(ctx.OPT_DEPTH_CONFIG))
+    assert err <= tol, err
+    ctx.close()
