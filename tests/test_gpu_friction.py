@@ -153,3 +153,25 @@ def test_elastoplastic_with_friction_fp32_refined():
         _say(k, err)
         assert err < 1e-8, (k, err)
     ctx.close()
+
+
+def test_tangential_matches_oracle_at_benchmark_size():
+    """256 x 256 (the smallest size of the tangential-contact benchmark; the
+    oracle needs about 90 s at 512 x 512), mu_f 0.3, Q = 0.5 mu_f W along x,
+    on a seeded rough-surface pressure: the GPU's minimiser is the
+    oracle's."""
+    from paper_1811_11558_amd import Context
+    n = 256
+    g = grid_dict(n, n, 2, 1.0, 1.0, 0.25)
+    p = _rough_pressure(n, n, seed=7, frac=0.95)
+    W = p.sum() / n ** 2
+    mu = 0.3
+    Q = (0.5 * mu * W, 0.0)
+    ref, rinfo = fr.tangential_solve(g, E, NU, p, Q, mu, tol=1e-13)
+    ctx = Context(g, E, NU)
+    q, info = ctx.tangential_solve(torch.from_numpy(p).cuda(), mu, Q, tol=1e-13)
+    torch.cuda.synchronize()
+    err = _rel(q.cpu().numpy(), ref)
+    _say("256^2 iters gpu/oracle", info["iters"], rinfo["iters"], "err", err)
+    assert err <= 1e-9
+    ctx.close()
