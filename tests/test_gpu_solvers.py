@@ -117,12 +117,13 @@ def test_flat_surface_elastoplastic_closed_form():
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hertz_ep_16x16x8.npz")
 
 
-@pytest.mark.parametrize("solver,kdim", [(0, 0), (1, 0), (2, 0), (2, 3)])
+@pytest.mark.parametrize("solver,kdim", [(0, 0), (1, 0), (2, 0), (2, 3), (2, 30)])
 def test_hertz_elastoplastic_matches_stored_oracle(solver, kdim):
     """Paraboloid R = 2 L on 16 x 16 x 8 (lz = 0.25 L), two load steps with
     Hertz peak pressures of about 2 and 3 times first yield: the GPU
     Algorithm 1 (DF-SANE, Picard or Newton-Krylov inside; the last also with
-    a Krylov space of 3, which truncates most linear solves) reproduces the
+    a Krylov space of 3, which truncates most linear solves, and with the
+    largest one, 30) reproduces the
     oracle's converged state stored by tests/golden/make_golden.py (computed
     with DF-SANE: the root, not the iteration, is compared)."""
     from paper_1811_11558_amd import EPOptions

@@ -97,3 +97,27 @@ def test_load_beyond_the_friction_limit_is_rejected():
     W = p.sum() / 32 ** 2
     with pytest.raises(ValueError):
         fr.tangential_solve(g, E, NU, p, np.array([0.31 * W, 0.0]), 0.3)
+
+
+def test_tangential_compliance_is_symmetric_positive_definite_per_mode():
+    """Per nonzero mode the 2x2 compliance is symmetric with eigenvalues
+    2 (1 + nu) / (E |k|) times 1 and 1 - nu (along and across n), the
+    coupling term vanishing on the Nyquist lines; mode 0 is dropped."""
+    g = grid_dict(8, 6, 2, 1.0, 1.5, 0.2)
+    C = fr.tangential_compliance_symbol(g, E, NU)
+    assert np.array_equal(C[0, 1], C[1, 0])
+    assert np.all(C[:, :, 0, 0] == 0.0)
+    k1 = np.fft.fftfreq(8, d=1.0 / 8) * 2 * np.pi / 1.0
+    k2 = np.fft.fftfreq(6, d=1.0 / 6) * 2 * np.pi / 1.5
+    for iy in range(6):
+        for ix in range(8):
+            if ix == 0 and iy == 0:
+                continue
+            q = np.hypot(k1[ix], k2[iy])
+            f = 2 * (1 + NU) / (E * q)
+            ev = np.linalg.eigvalsh(C[:, :, iy, ix])
+            if ix == 4 or iy == 3:          # Nyquist: diagonal, entries f (1 - nu n_a^2)
+                n1, n2 = k1[ix] / q, k2[iy] / q
+                assert np.allclose(sorted(ev), sorted([f * (1 - NU * n1 * n1), f * (1 - NU * n2 * n2)]))
+            else:
+                assert np.allclose(ev, [f * (1 - NU), f], rtol=1e-14)
