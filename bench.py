@@ -449,6 +449,15 @@ def bench_solve(a):
         times.append(time.perf_counter() - t0)
         ctx.close()
     ev = sum(i["r_evals"] for i in infos)
+    # final contact against the elastic Hertz solution of the same load
+    # (E* = E / (1 - nu^2), a = (3 W R / (4 E*))^(1/3), p0 = 3 W / (2 pi a^2))
+    p_fin = st["traction"][2].cpu().numpy()
+    area = float((p_fin > 0).sum()) / (32 * 32)
+    W, R, estar = Ws[-1], 0.5, 1.0 / (1.0 - 0.09)
+    a_h = (3 * W * R / (4 * estar)) ** (1.0 / 3.0)
+    contact = {"radius_equivalent": float(np.sqrt(area / np.pi)), "peak_pressure": float(p_fin.max()),
+               "hertz_radius": a_h, "hertz_peak_pressure": 3 * W / (2 * np.pi * a_h ** 2),
+               "max_ep": float(st["ep"].max().item())}
     print(json.dumps({"metric": "elastoplastic solve time", "value": float(np.median(times)), "unit": "s",
                       "higher_is_better": False, "n_gpus": 1, "steps": len(times),
                       "config": {"workload": "paraboloid 32x32x16, W=0.02 in 10 steps", "precision": a.precision,
@@ -456,7 +465,8 @@ def bench_solve(a):
                                  "solver": SOLVER_NAMES[a.solver], "krylov_dim": a.krylov},
                       "outer_iters": [i["outer_iters"] for i in infos], "residual_evals": ev,
                       "plastic_iters": sum(i["plastic_iters"] for i in infos),
-                      "voxel_updates_per_s": ev * 32 * 32 * 16 / float(np.median(times))}))
+                      "voxel_updates_per_s": ev * 32 * 32 * 16 / float(np.median(times)),
+                      "final_contact": contact}))
 
 
 def bench_serve(a):
