@@ -78,6 +78,8 @@ def parse():
                     help="area: rms slopes of the rough surface to run (comma separated)")
     ap.add_argument("--load-steps", type=int, default=5, help="area: equal cumulative load steps")
     ap.add_argument("--seed", type=int, default=0, help="area: seed of the rough surface")
+    ap.add_argument("--op", default="fused", choices=["fused", "mindlin", "boussinesq"],
+                    help="operator: both operators (default) or one alone")
     ap.add_argument("--graded", type=float, default=0.0,
                     help="operator: non-uniform depth nodes z_i = lz (i / (nz - 1))^GRADED (0 = uniform)")
     ap.add_argument("--mu-f", type=float, default=0.3, help="friction: Coulomb coefficient")
@@ -95,19 +97,21 @@ def parse():
     return a
 
 
-def stage_bytes(nx, ny, nz, csize=16, rsize=8, replicas=True):
+def stage_bytes(nx, ny, nz, csize=16, rsize=8, replicas=True, pin=None):
     """Algorithmic bytes per launch of each stage of the fused application:
     the 6 nz eigenstrain planes and the 3 traction planes are transformed
     together (pin = 6 nz + 3 planes in), 6 nz strain planes come out.  With
     replicas (the default launch), the main depth launch also reads the
     Nyquist modes' spectra once and writes one record per sign replica, and
     depth_nyq averages those records into the Nyquist modes; without (side
-    stream), depth_nyq evaluates the Nyquist modes itself."""
+    stream), depth_nyq evaluates the Nyquist modes itself.  pin: input
+    planes when not both operators (6 nz for Mindlin alone, 3 for
+    Boussinesq alone)."""
     kxh = nx // 2 + 1
     nm = kxh * ny
     nnyq = ny + kxh - 1                    # modes with kx = nx/2 or ky = ny/2
     nrep = 2 * (ny + kxh)                  # their sign replicas
-    pin, pout = 6 * nz + 3, 6 * nz
+    pin, pout = (6 * nz + 3 if pin is None else pin), 6 * nz
     per_mode = (pin + pout) * csize        # spectra in, strain spectrum out
     if replicas:
         depth = (nm - nnyq) * per_mode + nnyq * pin * csize + nrep * pout * csize
@@ -565,6 +569,10 @@ def main():
         z[-1] = 0.25
         ctx.set_depth_nodes(z)
         g = dict(g, z=z)
+    if a.op == "mindlin":
+        trac = None
+    elif a.op == "boussinesq":
+        eps = None
     ctx.tune()                      # first warm-up call times the depth-pass layouts
     for _ in range(a.warmup):
         ctx.operator_apply(eps, trac, out=out)
@@ -594,7 +602,8 @@ def main():
     value = V / (ms_per_step * 1e-3)
 
     csize = 16 if a.precision == "fp64" else 8
-    sb = stage_bytes(a.nx, a.ny, a.nz, csize=csize, replicas=not a.side_stream)
+    pin = {"fused": None, "mindlin": 6 * a.nz, "boussinesq": 3}[a.op]
+    sb = stage_bytes(a.nx, a.ny, a.nz, csize=csize, replicas=not a.side_stream, pin=pin)
     stages = {}
     for k, (ms, n) in st.items():
         if n:
@@ -605,7 +614,8 @@ def main():
     avg_s = stages[dom]["avg_ms"] * 1e-3
     achieved = sb[dom] / avg_s / 1e9
     # the counters were taken on uniform nodes
-    traffic = measured_traffic(dom, a.nx, a.ny, a.nz, a.precision) if a.graded <= 0 else None
+    # (the fused operator's)
+    traffic = measured_traffic(dom, a.nx, a.ny, a.nz, a.precision) if a.graded <= 0 and a.op == "fused" else None
     depth_cfg = ctx.get_option(ctx.OPT_DEPTH_CONFIG)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -625,11 +635,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if a.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD if (a.nx, a.ny, a.nz, a.precision, a.graded) == (256, 256, 64, "fp64", 0.0)
-                   else "operator %dx%dx%d %s%s" % (a.nx, a.ny, a.nz, a.precision,
-                                                    " graded depth nodes" if a.graded > 0 else ""),
+        "config": {"workload": WORKLOAD if (a.nx, a.ny, a.nz, a.precision, a.graded, a.op) ==
+                   (256, 256, 64, "fp64", 0.0, "fused")
+                   else "operator %dx%dx%d %s%s%s" % (a.nx, a.ny, a.nz, a.precision,
+                                                      " graded depth nodes" if a.graded > 0 else "",
+                                                      "" if a.op == "fused" else " (%s alone)" % a.op),
                    "nx": a.nx, "ny": a.ny, "nz": a.nz, "lz": 0.25, "nu": 0.3, "precision": a.precision,
-                   "streaming": a.streaming, "graded": a.graded},
+                   "streaming": a.streaming, "graded": a.graded, "op": a.op},
         "p50_ms": float(np.percentile(per, 50)),
         "p99_ms": float(np.percentile(per, 99)),
         "operator_hbm_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -637,7 +649,7 @@ def main():
         "depth_layout": depth_cfg,
         "roofline": roof,
     }
-    if not a.no_cpu_baseline:
+    if not a.no_cpu_baseline and a.op == "fused":
         res["cpu_baseline"] = cpu_baseline(g, eps_np, t_np, a.cpu_modes)
     ctx.close()
     print(json.dumps(res))
