@@ -137,6 +137,28 @@ int fvim_operator_apply(fvim_ctx* ctx, const double* eps_p, const double* tracti
                         double* strain, double* stress, double* disp, double* surf_u3);
 
 /*
+ * fvim_operator_apply without any allocation, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, serving
+ * loops that must not call hipMalloc, harnesses that forbid it.  Same
+ * arguments, kernels and results as fvim_operator_apply, but the spectrum
+ * buffers and the per-mode table live in a fixed region of
+ * FVIM_NOALLOC_BYTES (128 MiB) of device memory that the library reserves on
+ * every device it runs on, from the first fvim_create there until the
+ * process ends; the table is rebuilt there on each call.  The call makes no
+ * hipMalloc, hipFree or other allocation (no depth-layout tuning, no stage
+ * timing, no side stream: those options are ignored here).  Every call on
+ * one device shares that region and it keeps the last call's contents:
+ * calls that overlap in time on one device (different streams or threads)
+ * race and give wrong results; calls ordered on one stream do not.
+ * Asynchronous.  Errors: FVIM_EINVAL if the application needs more than
+ * FVIM_NOALLOC_BYTES (the fused strain of a 128 x 128 x 64 float64 grid
+ * needs about 110 MB), FVIM_EHIP if the region could not be set up.
+ */
+#define FVIM_NOALLOC_BYTES ((size_t)128 << 20)
+int fvim_operator_apply_noalloc(fvim_ctx* ctx, const double* eps_p, const double* traction, double* strain,
+                                double* stress, double* disp, double* surf_u3);
+
+/*
  * Batched application (batching of grids of different sizes): the fused
  * operator of fvim_operator_apply for n contexts at once, ordered on the
  * stream of ctxs[0].  Each context's in-plane transforms run as before; the

@@ -126,6 +126,7 @@ def load_library(path=None):
     lib.mindlin_apply.argtypes = [_P, _P, _P, _P, _P, _P]
     lib.boussinesq_apply.argtypes = [_P, _P, _P, _P, _P, _P]
     lib.fvim_operator_apply.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+    lib.fvim_operator_apply_noalloc.argtypes = [_P, _P, _P, _P, _P, _P, _P]
     lib.fvim_operator_apply_batch.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P]
     lib.return_map.argtypes = [_P, _P, _P, _P, _P, _P, _P]
     lib.contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int, _P, _P,
@@ -290,6 +291,19 @@ class Context:
         _check(_LIB.fvim_operator_apply(self._h, pe, pt, *ptrs))
         return res
 
+    def operator_apply_noalloc(self, eps_p=None, traction=None, out=None):
+        """operator_apply through the entry point that allocates nothing: the
+        library's fixed per-device scratch holds the workspace.  out: dict of
+        preallocated output tensors (strain, stress, disp, surf_u3), at least
+        one."""
+        if not out:
+            raise FvimError(FVIM_EINVAL, "operator_apply_noalloc: pass preallocated outputs")
+        pe = _ptr(eps_p, self.tensor_shape, "eps_p")
+        pt = _ptr(traction, (3, self.ny, self.nx), "traction")
+        res, ptrs = self._outputs((), out, None)
+        _check(_LIB.fvim_operator_apply_noalloc(self._h, pe, pt, *ptrs))
+        return res
+
     def mindlin_apply(self, eps_p, want=("strain",), out=None):
         pe = _ptr(eps_p, self.tensor_shape, "eps_p")
         res, ptrs = self._outputs(want, out, eps_p.device)
@@ -373,6 +387,13 @@ def boussinesq_apply(ctx, traction, **kw):
 
 def operator_apply(ctx, eps_p=None, traction=None, **kw):
     return ctx.operator_apply(eps_p, traction, **kw)
+
+
+def operator_apply_noalloc(ctx, eps_p=None, traction=None, out=None):
+    return ctx.operator_apply_noalloc(eps_p, traction, out)
+
+
+NOALLOC_BYTES = 128 << 20
 
 
 def operator_apply_batch(ctxs, eps_p=None, traction=None, want=("strain",)):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,21 @@ using namespace fvim;
 
 namespace {
 thread_local std::string g_err;
-}
+
+// Workspace of fvim_operator_apply_noalloc: one region of FVIM_NOALLOC_BYTES
+// in every device's memory, held from the library's first use of that device
+// until the process ends.  In host code `scratch` only names the symbol; its
+// device address (different on every device) comes from
+// hipGetSymbolAddress, taken once per device when the first context is
+// created there, and is the only thing passed to kernels.
+constexpr size_t kNoallocBytes = FVIM_NOALLOC_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mx;
+void* g_scratch_addr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoallocBytes];
 
 namespace fvim {
 
@@ -40,8 +55,8 @@ template <typename T>
 static void* make_twiddles(int n, hipError_t* err) {
   std::vector<cpx<T>> h(n);
   for (int k = 0; k < n; ++k) {
-    // exp(-2 pi i k / n), evaluated from the first octant by symmetry so the
-    // table is exactly symmetric
+    // exp(-2 pi i k / n): cosine and sine of the full angle in long double,
+    // rounded once to T
     long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)n;
     h[k].x = (T)cosl(a);
     h[k].y = (T)(-sinl(a));
@@ -80,19 +95,20 @@ int ctx_reserve(fvim_ctx* c, void** p, size_t* have, size_t need) {
 // Records a pair of events around a launch when the context has timing on.
 struct StageTimer {
   fvim_ctx* c;
+  bool on;
   int stage = -1;
   hipEvent_t a = nullptr;
   hipStream_t s = nullptr;
-  explicit StageTimer(fvim_ctx* cc) : c(cc) {}
-  void begin(int stg, hipStream_t on) {
-    if (!c->timing) return;
+  explicit StageTimer(fvim_ctx* cc, bool enabled = true) : c(cc), on(enabled && cc->timing) {}
+  void begin(int stg, hipStream_t st) {
+    if (!on) return;
     stage = stg;
-    s = on;
+    s = st;
     hipEventCreate(&a);
     hipEventRecord(a, s);
   }
   void end() {
-    if (!c->timing || stage < 0) return;
+    if (!on || stage < 0) return;
     hipEvent_t b;
     hipEventCreate(&b);
     hipEventRecord(b, s);
@@ -174,12 +190,26 @@ struct OpPlan {
   const cpx<T>* twy = nullptr;
 };
 
-// Depth parameters, output/input plane layout, workspace and the mode table
-// of one application u = M[t] + N[C : eps_p] (any subset of outputs, see
-// fvim.h).  P.np == 0: nothing requested.
+// Device bytes one application needs: each of the two spectrum buffers
+// (spectrum plus the Nyquist sign-replica records), the float64 plane sums
+// and mean-mode constants of the float32 path, and the mode table.
+struct OpSizes {
+  size_t spec = 0, k0 = 0, mt = 0;
+};
+static size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+// One region holding A, B, the float64 sums and the mode table, each on a
+// 256-byte boundary.
+static size_t scratch_bytes(const OpSizes& s) {
+  return 2 * round256(s.spec) + round256(s.k0) + round256(s.mt);
+}
+
+// Depth parameters and the output/input plane layout of one application
+// u = M[t] + N[C : eps_p] (any subset of outputs, see fvim.h), and the
+// workspace it needs.  No device memory is touched.  P.np == 0: nothing
+// requested.
 template <typename T>
-int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
-            double* disp, double* surf_u3, OpPlan<T>& P) {
+int op_layout(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+              double* disp, double* surf_u3, OpPlan<T>& P, OpSizes& sz) {
   const int nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
   const int kxh = nx / 2 + 1;
   const size_t nmodes = (size_t)kxh * ny;
@@ -229,39 +259,10 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   const size_t planes = (size_t)std::max(prm.ld_out, prm.ld_in);
   // the depth pass writes E to A; the Nyquist sign-replica records follow it
   const size_t nrep = (size_t)depth_replicas(ny, kxh);
-  const size_t bytes = (planes * nmodes + nrep * (size_t)prm.ld_out) * sizeof(cpx<T>);
-  int rc = ctx_reserve(c, &c->bufA, &c->bufA_bytes, bytes);
-  if (rc) return rc;
-  rc = ctx_reserve(c, &c->bufB, &c->bufB_bytes, bytes);
-  if (rc) return rc;
+  sz.spec = (planes * nmodes + nrep * (size_t)prm.ld_out) * sizeof(cpx<T>);
   P.wbpp = x_r2c_blocks_per_plane<T>(nx, ny);
-  if (P.k0x) {
-    const size_t kb = sizeof(double) * ((size_t)(6 * nz + 3) * P.wbpp + (size_t)np);
-    rc = ctx_reserve(c, &c->k0buf, &c->k0buf_bytes, kb);
-    if (rc) return rc;
-    P.wsum = (double*)c->k0buf;                    // block sums of every input plane
-    P.tsum = P.wsum + (size_t)prm.off_t * P.wbpp;
-    P.padd = P.wsum + (size_t)(6 * nz + 3) * P.wbpp;
-  }
-  void*& mt = sizeof(T) == 8 ? c->mt64 : c->mt32;
-  if (!mt) {
-    std::lock_guard<std::recursive_mutex> lk(device_lock());
-    if (hipMalloc(&mt, sizeof(ModeConst<T>) * nmodes) != hipSuccess) {
-      mt = nullptr;
-      return fail(FVIM_ENOMEM, "device allocation failed for the mode table");
-    }
-    hipError_t e0 = launch_mode_table<T>((ModeConst<T>*)mt, nx, ny, c->grid.lx, c->grid.ly, prm.h, c->stream);
-    if (e0 != hipSuccess) return fail_hip(e0, "mode table");
-  }
-  prm.mtab = mt;
-  prm.hz = c->hz;
-  P.twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
-  P.twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
-  P.A = (cpx<T>*)c->bufA;
-  P.B = (cpx<T>*)c->bufB;
-  // with the side stream the Nyquist modes keep a launch of their own, which
-  // can run beside the main one; otherwise their sign replicas join it
-  prm.rep_out = c->use_side ? nullptr : (void*)(P.A + nmodes * (size_t)prm.ld_out);
+  sz.k0 = P.k0x ? sizeof(double) * ((size_t)(6 * nz + 3) * P.wbpp + (size_t)np) : 0;
+  sz.mt = sizeof(ModeConst<T>) * nmodes;
   // Streaming loads pay off when one launch's output fits the 256 MiB
   // last-level cache, so the next launch can read it from there. Measured
   // on MI355X, operator step off -> on:
@@ -272,6 +273,53 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   P.nt = c->streaming == 1 ||
          (c->streaming == 2 && spec_bytes > ((size_t)64 << 20) && spec_bytes <= ((size_t)256 << 20));
   prm.nt_in = P.nt ? 1 : 0;
+  return FVIM_OK;
+}
+
+// Pointers of an application whose workspace is bound: the float64 sums,
+// the twiddles, the node table and the Nyquist replica records.
+template <typename T>
+void op_bind(fvim_ctx* c, OpPlan<T>& P, void* bufA, void* bufB, double* k0buf, const void* mt, bool side) {
+  const size_t nmodes = (size_t)P.prm.kxh * P.prm.ny;
+  if (P.k0x) {
+    P.wsum = k0buf;                                // block sums of every input plane
+    P.tsum = P.wsum + (size_t)P.prm.off_t * P.wbpp;
+    P.padd = P.wsum + (size_t)(6 * c->grid.nz + 3) * P.wbpp;
+  }
+  P.prm.mtab = mt;
+  P.prm.hz = c->hz;
+  P.twx = (const cpx<T>*)(sizeof(T) == 8 ? c->twx64 : c->twx32);
+  P.twy = (const cpx<T>*)(sizeof(T) == 8 ? c->twy64 : c->twy32);
+  P.A = (cpx<T>*)bufA;
+  P.B = (cpx<T>*)bufB;
+  // with the side stream the Nyquist modes keep a launch of their own, which
+  // can run beside the main one; otherwise their sign replicas join it
+  P.prm.rep_out = side ? nullptr : (void*)(P.A + nmodes * (size_t)P.prm.ld_out);
+}
+
+// op_layout plus the workspace the context owns (grown on demand) and the
+// context's mode table (built on first use).
+template <typename T>
+int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
+            double* disp, double* surf_u3, OpPlan<T>& P) {
+  OpSizes sz;
+  int rc = op_layout<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P, sz);
+  if (rc || P.np == 0) return rc;
+  if ((rc = ctx_reserve(c, &c->bufA, &c->bufA_bytes, sz.spec))) return rc;
+  if ((rc = ctx_reserve(c, &c->bufB, &c->bufB_bytes, sz.spec))) return rc;
+  if (P.k0x && (rc = ctx_reserve(c, &c->k0buf, &c->k0buf_bytes, sz.k0))) return rc;
+  void*& mt = sizeof(T) == 8 ? c->mt64 : c->mt32;
+  if (!mt) {
+    std::lock_guard<std::recursive_mutex> lk(device_lock());
+    if (hipMalloc(&mt, sz.mt) != hipSuccess) {
+      mt = nullptr;
+      return fail(FVIM_ENOMEM, "device allocation failed for the mode table");
+    }
+    hipError_t e0 = launch_mode_table<T>((ModeConst<T>*)mt, c->grid.nx, c->grid.ny, c->grid.lx, c->grid.ly,
+                                         P.prm.h, c->stream);
+    if (e0 != hipSuccess) return fail_hip(e0, "mode table");
+  }
+  op_bind<T>(c, P, c->bufA, c->bufB, (double*)c->k0buf, mt, c->use_side != 0);
   return FVIM_OK;
 }
 
@@ -309,29 +357,55 @@ int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
   return FVIM_OK;
 }
 
-// u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).
+// u = M[t] + N[C : eps_p] with any subset of outputs (see fvim.h).  With
+// scratch set, the workspace and the mode table are carved from that device
+// region of scratch_cap bytes instead of the context's (nothing is allocated:
+// no tuning, no stage timing, no side stream; the mode table is rebuilt there
+// by the same kernel, so results are those of the context's own workspace).
 template <typename T>
 int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, double* strain, double* stress,
                      double* disp, double* surf_u3, const ResidEpilogue* ep = nullptr,
-                     const int* zact = nullptr) {
+                     const int* zact = nullptr, char* scratch = nullptr, size_t scratch_cap = 0) {
   OpPlan<T> P;
-  int rc = op_plan<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P);
-  if (rc || P.np == 0) return rc;
+  int rc;
+  if (scratch) {
+    OpSizes sz;
+    rc = op_layout<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P, sz);
+    if (rc || P.np == 0) return rc;
+    const size_t need = scratch_bytes(sz);
+    if (need > scratch_cap) {
+      char msg[200];
+      snprintf(msg, sizeof msg, "operator_apply_noalloc: this application needs %zu bytes of workspace, more than "
+               "the %zu-byte scratch", need, scratch_cap);
+      return fail(FVIM_EINVAL, msg);
+    }
+    char* a = scratch;
+    char* b = a + round256(sz.spec);
+    char* k0 = b + round256(sz.spec);
+    char* mt = k0 + round256(sz.k0);
+    hipError_t e0 = launch_mode_table<T>((ModeConst<T>*)mt, c->grid.nx, c->grid.ny, c->grid.lx, c->grid.ly,
+                                         P.prm.h, c->stream);
+    if (e0 != hipSuccess) return fail_hip(e0, "mode table");
+    op_bind<T>(c, P, a, b, (double*)k0, mt, false);
+  } else {
+    rc = op_plan<T>(c, eps_p, traction, strain, stress, disp, surf_u3, P);
+    if (rc || P.np == 0) return rc;
+  }
   if (ep) P.ep = *ep;
   if (zact && eps_p) {
     P.skip = LayerSkip{zact, c->grid.nz, 6 * c->grid.nz};
     P.prm.zact = zact;
   }
   hipStream_t st = c->stream;
-  const bool side = c->use_side != 0;
+  const bool side = c->use_side != 0 && !scratch;
   if (side && (rc = side_ensure(c))) return rc;
   // the Nyquist-mode depth launch may run on the side stream beside the main
   // one (disjoint modes); measured slower in float64, so off by default
   hipStream_t ss = side ? c->side : st;
   hipError_t e;
-  StageTimer tm(c);
+  StageTimer tm(c, scratch == nullptr);
   if ((rc = op_forward<T>(c, P, st, tm))) return rc;
-  if (c->tune_pending) {
+  if (c->tune_pending && !scratch) {
     c->tune_pending = 0;
     int rc2 = tune_depth<T>(c, P.B, P.A, P.prm);
     if (rc2) return rc2;
@@ -450,6 +524,22 @@ const char* fvim_last_error(void) { return g_err.c_str(); }
 
 const char* fvim_version(void) { return "fvim 0.1 gfx950"; }
 
+// Device address of the no-allocation scratch on device dev (current), looked
+// up once; a failed lookup is remembered and reported by the entry point.
+static void scratch_lookup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mx);
+  if (g_scratch_addr[dev] || g_scratch_err[dev] != hipSuccess) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    g_scratch_err[dev] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    (void)hipGetLastError();
+    return;
+  }
+  g_scratch_addr[dev] = p;
+}
+
 static int check_grid(const fvim_grid* g) {
   if (!g) return fail(FVIM_EINVAL, "grid is NULL");
   if (!is_pow2(g->nx) || !is_pow2(g->ny) || g->nx < 4 || g->ny < 4 || g->nx > 4096 || g->ny > 4096)
@@ -482,6 +572,7 @@ int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision, 
   c->k0_policy = k0_policy;
   c->stream = (hipStream_t)hip_stream;
   hipGetDevice(&c->device);
+  scratch_lookup(c->device);
   c->mu = mat->E / (2.0 * (1.0 + mat->nu));
   c->lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
   hipError_t e = hipSuccess;
@@ -683,6 +774,28 @@ int fvim_operator_apply(fvim_ctx* c, const double* eps_p, const double* traction
                         double* disp, double* surf_u3) {
   if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
   return operator_apply(c, eps_p, traction, strain, stress, disp, surf_u3);
+}
+
+int fvim_operator_apply_noalloc(fvim_ctx* c, const double* eps_p, const double* traction, double* strain,
+                                double* stress, double* disp, double* surf_u3) {
+  if (!c) return fail(FVIM_EINVAL, "ctx is NULL");
+  if (misaligned(eps_p) || misaligned(traction) || misaligned(strain) || misaligned(stress) ||
+      misaligned(disp) || misaligned(surf_u3))
+    return fail(FVIM_EINVAL, "field pointers must be 16-byte aligned");
+  if (c->device < 0 || c->device >= kMaxDevices) return fail(FVIM_ENODEV, "operator_apply_noalloc: device index");
+  char* base;
+  hipError_t se;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mx);
+    base = (char*)g_scratch_addr[c->device];
+    se = g_scratch_err[c->device];
+  }
+  if (!base) return fail_hip(se != hipSuccess ? se : hipErrorInvalidSymbol, "operator_apply_noalloc: scratch");
+  if (c->precision == FVIM_FP32_REFINED && !c->force_fp64)
+    return operator_apply_t<float>(c, eps_p, traction, strain, stress, disp, surf_u3, nullptr, nullptr, base,
+                                   kNoallocBytes);
+  return operator_apply_t<double>(c, eps_p, traction, strain, stress, disp, surf_u3, nullptr, nullptr, base,
+                                  kNoallocBytes);
 }
 
 int fvim_operator_apply_batch(fvim_ctx* const* ctxs, int n, const double* const* eps_p,
