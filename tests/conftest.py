@@ -12,14 +12,4 @@ for p in (ROOT, HERE):
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
-
-
-def pytest_collection_modifyitems(config, items):
-    """Tests marked slow (minutes of CPU) run only with FVIM_SLOW=1."""
-    if os.environ.get("FVIM_SLOW") == "1":
-        return
-    skip = pytest.mark.skip(reason="slow CPU test; set FVIM_SLOW=1 to run")
-    for it in items:
-        if "slow" in it.keywords:
-            it.add_marker(skip)
+    config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds (runs by default)")

@@ -42,6 +42,14 @@ CASES = {
     # z_i = lz (i / (nz - 1))^2
     "hertz_graded_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
                                     mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1), graded=2.0),
+    # the plain FP64 elastoplastic configuration: 32 x 32 x 16, lz = 0.25 L,
+    # paraboloid R = 0.5 L centred on node (16, 16), E = 1, nu = 0.3,
+    # sigma_y0 = 0.01, E_h = 0.1, total load W = 0.02 E L^2 in 10 equal
+    # cumulative increments, lambda = 0.3, k = 0 traction included.  The file
+    # is rewritten after every increment; "steps_done" says how many of the
+    # loads the stored state has taken.
+    "c1_32x32x16": dict(grid=(32, 32, 16, 0.25), R=0.5, W=[0.002 * (i + 1) for i in range(10)], relax=0.3,
+                        mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1), checkpoint=True),
 }
 # Standard under-relaxation (the printed overwrite of the relaxed update
 # oscillates on these cases; see the design notes).
@@ -67,18 +75,33 @@ def run(name):
         p_el, _, _ = oc.contact_solve(h, c["W"][-1], g, mat["E"], mat["nu"], tol=1e-15, max_iter=20000)
         extra["p_elastic"] = p_el
     st = cp.new_state(g)
+    if "z" in g:
+        extra["z"] = g["z"]
     t0 = time.time()
+    if c.get("checkpoint"):
+        # one increment at a time (the state carries over, as inside one call)
+        infos = []
+        for k, W in enumerate(c["W"]):
+            infos += cp.elastoplastic_solve(g, mat, h, [W], st, relax=c["relax"], **OPTS, **c.get("friction", {}))
+            save(name, c, g, h, st, infos, time.time() - t0, extra, k + 1)
+            print(name, "step %d: %.1f s, %d outer passes" % (k + 1, time.time() - t0, infos[-1]["outer_iters"]),
+                  flush=True)
+        return
     infos = cp.elastoplastic_solve(g, mat, h, c["W"], st, relax=c["relax"], **OPTS, **c.get("friction", {}))
-    dt = time.time() - t0
+    save(name, c, g, h, st, infos, time.time() - t0, extra, len(c["W"]))
+    print(name, "%.1f s" % (time.time() - t0), [i["outer_iters"] for i in infos])
+
+
+def save(name, c, g, h, st, infos, dt, extra, steps_done):
     meta = np.array([repr({"case": c, "opts": OPTS, "seconds": dt,
                            "outer": [i["outer_iters"] for i in infos],
                            "outer_err": [i["outer_err"] for i in infos],
                            "plastic": [i["plastic"] for i in infos]})])
-    if "z" in g:
-        extra["z"] = g["z"]
+    more = dict(extra)
+    if c.get("checkpoint"):
+        more["steps_done"] = np.array(steps_done)
     np.savez_compressed(os.path.join(HERE, name + ".npz"), h=h, W=np.array(c["W"]), meta=meta,
-                        **{k: v for k, v in st.items()}, **extra)
-    print(name, "%.1f s" % dt, [i["outer_iters"] for i in infos])
+                        **{k: v for k, v in st.items()}, **more)
 
 
 if __name__ == "__main__":

@@ -204,29 +204,6 @@ def test_flat_surface_uniaxial_strain_closed_form(steps):
         assert inf["outer_err"] < 1e-12
 
 
-@pytest.mark.slow
-def test_hertz_elastoplastic_certificates():
-    """Paraboloid beyond first yield: the converged state satisfies yield
-    consistency where the last step flowed, stays inside the yield surface
-    elsewhere, and the contact KKT conditions hold (certificates; the field
-    has no closed form, so parity here is certificate-only)."""
-    g = grid_dict(16, 16, 8, lz=0.25)
-    mat = dict(E=E, nu=NU, sigma_y0=SY, E_h=EH)
-    h = paraboloid(g, R=0.5)
-    st = cp.new_state(g)
-    cp.elastoplastic_solve(g, mat, h, [0.0005], st, tol_outer=1e-10, relax=0.3)
-    ep1 = st['ep'].copy()
-    infos = cp.elastoplastic_solve(g, mat, h, [0.001], st, tol_outer=1e-10, relax=0.3)
-    fy = pl.von_mises(st['sigma'])
-    assert np.all(fy <= SY + EH * st['ep'] + 1e-12)
-    flowed = st['ep'] > ep1
-    assert flowed.any()
-    assert np.max(np.abs(fy[flowed] - (SY + EH * st['ep'][flowed]))) < 1e-10
-    for inf in infos:
-        assert inf["outer_err"] < 1e-10
-        assert inf["contact"]["kkt_residual"] < 1e-9
-
-
 # ------------------------------------------------- consistent tangent --
 def _plastic_points(rng, n):
     """Random states, each at least 5 % away from the yield surface in f."""
