@@ -504,8 +504,10 @@ def bench_serve(a):
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    lat = np.array([x["t_done"] - x["t_submit"] for x in res])
     ok = [x["status"] == 0 for x in res]
+    # solve latency over the requests that succeeded; failures are listed
+    # with their own latencies
+    lat = np.array([x["t_done"] - x["t_submit"] for x, k in zip(res, ok) if k] or [float("nan")])
     detail = [{"grid": "%dx%dx%d" % (r["nx"], r["ny"], r["nz"]), "pbar": round(r["pbar"], 5),
                "hurst": round(r["hurst"], 3), "status": x["status"], "error": x["error"],
                "outer": x["info"]["outer_iters"], "r_evals": x["info"]["r_evals"],
@@ -523,6 +525,7 @@ def bench_serve(a):
                       "voxel_updates_per_s": vox / wall, "wall_s": wall, "peak_bytes": st["peak_bytes"],
                       "run_s_median_by_grid": {k: float(np.median(v)) for k, v in sorted(by_grid.items())},
                       "failures": [d for d in detail if d["status"] != 0],
+                      "failure_latency_s": [d["latency_s"] for d in detail if d["status"] != 0],
                       "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": a.slots,
                                  "rate_per_s": a.rate, "precision": "fp32_refined", "anderson": a.anderson,
                                  "warm_start": a.warm, "inner_rel": a.inner_rel}}))

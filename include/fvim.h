@@ -30,7 +30,10 @@
  *
  * Errors: every int-returning call returns FVIM_OK (0) or a negative
  * FVIM_E* code; on error the outputs are unspecified and no state passed by
- * the caller is modified.  fvim_last_error() gives a thread-local message.
+ * the caller is modified, with one exception: elastoplastic_solve commits
+ * each converged load step to the caller's state before it starts the next
+ * (fvim_ep_info.committed says which steps were).  fvim_last_error() gives a
+ * thread-local message.
  */
 #ifndef FVIM_H
 #define FVIM_H
@@ -192,7 +195,8 @@ int return_map(fvim_ctx* ctx, const double* d_eps, const double* sigma_n, const 
 typedef struct {
   int iters;
   double rel_change;      /* last dA * sum |p_k - p_(k-1)| / W                 */
-  double kkt_residual;    /* max(|gap| on the contact set, -min gap) / max|h|  */
+  double kkt_residual;    /* max(|gap| on the contact set, -min gap) / max|h|, */
+                          /* gap = u3 - h minus its mean on the contact set    */
   double contact_fraction;
   double mean_gap;        /* rigid approach (mean of u3 - h on the contact set) */
 } fvim_contact_info;
@@ -296,7 +300,13 @@ typedef struct {
 
 typedef struct {
   int outer_iters, plastic_iters, contact_iters, r_evals;
-  double outer_err, plastic_res, kkt;
+  double outer_err, plastic_res;
+  double kkt;          /* KKT certificate of the step's last contact solve   */
+                       /* (fvim_contact_info.kkt_residual, on the surface   */
+                       /* that solve saw: h - U3p_n - the relaxed correction) */
+  int committed;       /* 1: the step converged and its state update was     */
+                       /* applied to the caller's state; 0: not (the step   */
+                       /* that failed, and every later one, is not run)     */
 } fvim_ep_info;
 
 /*
@@ -306,7 +316,11 @@ typedef struct {
  * plasticity fixed point R[d_eps] = 0 (eqn incremental_strain) solved by
  * DF-SANE or Picard, the surface residual displacement of N[C:d_eps_p],
  * relaxation, until the outer error is below tol_outer; then the state is
- * updated in place.  info: host array of n_steps records.  Blocking.
+ * updated in place.  info: host array of n_steps records (all cleared on
+ * entry).  Each converged step is committed to the state before the next
+ * starts: on an error (e.g. FVIM_ENOCONV at step k) the state holds the
+ * result of steps 0 .. k-1, and info[j].committed is 1 exactly for those.
+ * Blocking.
  */
 int elastoplastic_solve(fvim_ctx* ctx, const double* h, const double* W_steps, int n_steps,
                         const fvim_ep_opts* opts, fvim_state* state, fvim_ep_info* info);
@@ -392,7 +406,8 @@ typedef struct {
 typedef struct {
   int status;                /* FVIM_OK or the solve's error code           */
   double t_submit, t_admit, t_done;
-  fvim_ep_info info;         /* of the last load step                       */
+  fvim_ep_info info;         /* of the last load step; of the failing step   */
+                             /* when status is not FVIM_OK                  */
   double contact_fraction;   /* of the final pressure                       */
   const double* p;           /* HOST [ny][nx] final contact pressure        */
   const double* u3p;         /* HOST [ny][nx] final surface residual disp.  */

@@ -73,7 +73,7 @@ class _EPInfo(ctypes.Structure):
     _fields_ = [("outer_iters", ctypes.c_int), ("plastic_iters", ctypes.c_int),
                 ("contact_iters", ctypes.c_int), ("r_evals", ctypes.c_int),
                 ("outer_err", ctypes.c_double), ("plastic_res", ctypes.c_double),
-                ("kkt", ctypes.c_double)]
+                ("kkt", ctypes.c_double), ("committed", ctypes.c_int)]
 
 
 MAX_STEPS = 16
@@ -367,9 +367,16 @@ class Context:
         n = len(W_steps)
         ws = (ctypes.c_double * n)(*[float(w) for w in W_steps])
         infos = (_EPInfo * n)()
-        _check(_LIB.elastoplastic_solve(self._h, _ptr(h, sf, "h"), ws, n, ctypes.byref(opts),
-                                        ctypes.byref(st), infos))
-        return [{f: getattr(i, f) for f, _ in _EPInfo._fields_} for i in infos]
+        rc = _LIB.elastoplastic_solve(self._h, _ptr(h, sf, "h"), ws, n, ctypes.byref(opts),
+                                      ctypes.byref(st), infos)
+        out = [{f: getattr(i, f) for f, _ in _EPInfo._fields_} for i in infos]
+        if rc != FVIM_OK:
+            # the steps before the failing one are committed to the state;
+            # the records say which (committed == 1)
+            err = FvimError(rc, _LIB.fvim_last_error().decode())
+            err.infos = out
+            raise err
+        return out
 
 
 def contact_info_dict(info):

@@ -112,7 +112,14 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
   std::vector<fvim_ep_info> info(r.n_steps);
   if (!rc) rc = elastoplastic_solve(ctx, h, r.W_steps, r.n_steps, &r.opts, &state, info.data());
   dev.lock();
-  if (!rc) {
+  if (rc) {
+    // the record of the step that failed (the first one not committed)
+    for (const fvim_ep_info& i : info)
+      if (!i.committed) {
+        j->res.info = i;
+        break;
+      }
+  } else {
     j->res.info = info[r.n_steps - 1];
     j->p_host.resize(ns);
     j->u3_host.resize(ns);

@@ -33,7 +33,7 @@ constexpr int NSCAL = 32;
 // device scalar slots
 enum {
   S_GBAR = 0, S_G, S_GOLD, S_BETA, S_RBAR, S_TAU, S_DELTA, S_SCALE, S_ERR, S_NIOL, S_SUMP, S_CNT, S_W, S_DA,
-  S_DOT0, S_DOT1, S_DOT2
+  S_DOT0, S_DOT1, S_DOT2, S_KKT
 };
 
 // ---------------------------------------------------------------- reductions
@@ -69,6 +69,45 @@ __device__ double final_sum(const double* part, int k, int nb) {
   __syncthreads();
   for (int o = NT / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Block maxima of NS quantities (all >= 0); block b writes part[k * RB + b].
+template <int NS>
+__device__ __forceinline__ void block_max(double (&v)[NS], double* part) {
+  __shared__ double sh[NS][NT / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_down(x, o, 64));
+    if (lane == 0) sh[k][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < NT / 64; ++i) s = fmax(s, sh[k][i]);
+      part[k * RB + blockIdx.x] = s;
+    }
+  }
+}
+
+// Maximum of nb partials of quantity k (all >= 0), by one block.
+__device__ double final_max(const double* part, int k, int nb) {
+  __shared__ double sh[NT];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) s = fmax(s, part[k * RB + i]);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = NT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
     __syncthreads();
   }
   double r = sh[0];
@@ -181,6 +220,21 @@ __global__ __launch_bounds__(NT) void k_pk_scale(double* __restrict__ p, const d
   block_sums<1>(v, part);
 }
 
+// KKT certificate of a contact solution: with g the gap (u3 - h minus its
+// mean on the contact set), the maxima of |g| on the contact set, of -g
+// anywhere (a negative gap is an overlap) and of |h|
+__global__ __launch_bounds__(NT) void k_pk_kkt(const double* __restrict__ p, const double* __restrict__ g,
+                                              const double* __restrict__ h, size_t n, double* part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double gi = g[i];
+    if (p[i] > 0.0) v[0] = fmax(v[0], fabs(gi));
+    v[1] = fmax(v[1], -gi);
+    v[2] = fmax(v[2], fabs(h[i]));
+  }
+  block_max<3>(v, part);
+}
+
 // One-block finishing steps of the PK iteration: turn partial sums into the
 // scalars the next kernel needs.
 // Final reductions into the device scalars; the slots the host reads after
@@ -223,6 +277,9 @@ __global__ __launch_bounds__(NT) void k_pk_final(int stage, const double* part, 
       sc[S_ERR] = err;
       mirror[S_ERR] = err;
     }
+  } else if (stage == 7) {     // KKT certificate max(on, off) / max |h|
+    double on = final_max(part, 0, nb), off = final_max(part, 1, nb), hm = final_max(part, 2, nb);
+    if (threadIdx.x == 0) sc[S_KKT] = fmax(on, off) / (hm > 0.0 ? hm : 1e-300);
   } else if (stage == 6) {     // generic: sums of up to three quantities
     double a = final_sum(part, 0, nb), b = final_sum(part, 1, nb), c = final_sum(part, 2, nb);
     if (threadIdx.x == 0) {
@@ -817,6 +874,8 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   hipLaunchKernelGGL(k_pk_gap, G, Bk, 0, st, u, h, p, g, n, w->part);
   hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 0, w->part, nb, w->sc, w->dmap);
   hipLaunchKernelGGL(k_pk_grad, G, Bk, 0, st, p, g, n, w->sc, w->part);
+  hipLaunchKernelGGL(k_pk_kkt, G, Bk, 0, st, p, g, h, n, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), Bk, 0, st, 7, w->part, nb, w->sc, w->dmap);
   if (gap) {
     e = hipMemcpyAsync(gap, g, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return fail_hip(e, "gap copy");
@@ -827,7 +886,7 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
     info->rel_change = err;
     info->contact_fraction = w->hsc[S_CNT] / (double)n;
     info->mean_gap = w->hsc[S_GBAR];
-    info->kkt_residual = -1.0;   // filled by the caller when it needs it
+    info->kkt_residual = w->hsc[S_KKT];
   }
   if (!conv) return fail(FVIM_ENOCONV, "contact_solve: iteration limit reached");
   return FVIM_OK;
@@ -1533,10 +1592,10 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     return r;
   };
   hipError_t e;
+  memset(info, 0, sizeof(fvim_ep_info) * (size_t)n_steps);
   for (int step = 0; step < n_steps; ++step) {
     const double Wn = W_steps[step];
     fvim_ep_info& inf = info[step];
-    memset(&inf, 0, sizeof(inf));
     axpy(c, H0, h, -1.0, s->u3p, n);                      // H0 = h - U3p
     double dn, hn;
     if ((rc = surf_norms(c, H0, nullptr, &dn, &hn))) return cleanup(rc);
@@ -1556,6 +1615,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
       if (rc) return cleanup(rc);
       inf.contact_iters += ci.iters;
+      inf.kkt = ci.kkt_residual;
       // inexact inner solves (plasticity, and the tangential contact with
       // friction) while the outer error is large; a pass that may end the
       // step is always solved to the full tolerances
@@ -1642,6 +1702,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     e = hipMemcpyAsync(s->traction, T, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
     axpy(c, s->u3p, s->u3p, 1.0, dU, n);
+    inf.committed = 1;
   }
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return cleanup(fail_hip(e, "elastoplastic_solve"));

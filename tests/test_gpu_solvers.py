@@ -54,6 +54,37 @@ def test_contact_matches_oracle(n, W, seed):
     assert abs(p.sum() / n ** 2 - W) < 1e-14 * W * n
     gap = gap.cpu().numpy()
     assert oc.kkt_residual(p, gap, h) < 1e-10
+    # the certificate the C ABI reports is formed on the device from the same
+    # final gap: the oracle's definition applied to the returned p and gap
+    kkt = oc.kkt_residual(p, gap, h)
+    assert abs(info["kkt_residual"] - kkt) <= 1e-12 * max(kkt, 1e-300), (info["kkt_residual"], kkt)
+
+
+def test_contact_matches_oracle_rough_1024():
+    """The rough-surface workload's contact solve at its full size: 1024^2,
+    Hurst 0.8, PSD plateau for 1 <= |k| < 4, cut-off |k| = 256, rms slope
+    0.1, first of 5 load increments to W = 1e-4 (W = 2e-5).  The oracle's
+    Polonsky-Keer solve (13 s on 4 host cores) against the GPU's, both to
+    tol 1e-15: pressures to 1e-11, identical contact sets, KKT below 1e-12."""
+    n, W = 1024, 2e-5
+    g = grid_dict(n, n, 64, lz=0.25)
+    h = rough_surface(n, n, hurst=0.8, k_roll=4, k_cut=256, rms_slope=0.1, seed=0)
+    _say("contact 1024^2: oracle")
+    ref, rgap, rinfo = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=20000)
+    ctx = _ctx(g)
+    p, gap, info = ctx.contact_solve(torch.from_numpy(h).cuda(), W, tol=1e-15, max_iter=20000, want_gap=True)
+    torch.cuda.synchronize()
+    p = p.cpu().numpy()
+    err = _rel(p, ref)
+    _say("contact 1024^2 iters gpu/oracle", info["iters"], rinfo["iters"], "rel err", err, "frac",
+         info["contact_fraction"], "kkt", info["kkt_residual"])
+    assert err < 1e-11
+    assert np.array_equal(p > 0, ref > 0)
+    assert abs(p.sum() / n ** 2 - W) < 1e-14 * W * n
+    assert info["kkt_residual"] < 1e-12
+    kkt = oc.kkt_residual(p, gap.cpu().numpy(), h)
+    assert abs(info["kkt_residual"] - kkt) <= 1e-12 * max(kkt, 1e-300)
+    ctx.close()
 
 
 def test_contact_solve_on_workspace_that_held_nan():
@@ -309,4 +340,33 @@ def test_newton_krylov_options_are_checked():
         with pytest.raises(RuntimeError, match="bad options"):
             ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), [float(ref["W"][0])], st, bad)
     assert float(st["ep"].abs().max()) == 0.0
+    ctx.close()
+
+
+def test_elastoplastic_reports_committed_steps_on_failure():
+    """elastoplastic_solve commits each converged load step before the next:
+    when step 2 cannot converge within max_outer, the call fails with
+    FVIM_ENOCONV, info says step 1 was committed and step 2 was not, and the
+    state equals that of step 1 solved alone."""
+    from paper_1811_11558_amd import EPOptions, FvimError
+    from paper_1811_11558_amd import binding as b
+    from synth import paraboloid
+    g = grid_dict(16, 16, 8, lz=0.25)
+    h = torch.from_numpy(paraboloid(g, R=0.5)).cuda()
+    opts = EPOptions(tol_outer=1e-10, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14, max_outer=6)
+    ctx = _ctx(g)
+    ref = ctx.new_state()
+    ok = ctx.elastoplastic_solve(h, [1e-6], ref, opts)
+    assert ok[0]["committed"] == 1 and ok[0]["outer_iters"] <= 6
+    st = ctx.new_state()
+    with pytest.raises(FvimError) as ei:
+        ctx.elastoplastic_solve(h, [1e-6, 0.002], st, opts)
+    assert ei.value.code == b.FVIM_ENOCONV
+    infos = ei.value.infos
+    assert [i["committed"] for i in infos] == [1, 0]
+    assert infos[1]["outer_iters"] == 6
+    torch.cuda.synchronize()
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        assert torch.equal(st[k], ref[k]), k
+    assert ok[0]["kkt"] >= 0.0 and ok[0]["kkt"] < 1e-10
     ctx.close()
