@@ -351,7 +351,7 @@ int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
     return fail_hip(e, "y_inv");
   tm.end();
   tm.begin(FVIM_STAGE_XINV, st);
-  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.ep)) != hipSuccess)
+  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.ep, true)) != hipSuccess)
     return fail_hip(e, "x_c2r");
   tm.end();
   return FVIM_OK;

@@ -71,11 +71,12 @@ struct ResidEpilogue {
 };
 // padd (optional): float64 constant added to each plane of the output.  No
 // streaming loads here: keeping its input cached measured faster (the next
-// application's y_inv writes the same buffer).
+// application's y_inv writes the same buffer).  stream_out: the outputs
+// (without the epilogue) are stored as streaming writes.
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr,
-                        const ResidEpilogue& ep = ResidEpilogue{});
+                        const ResidEpilogue& ep = ResidEpilogue{}, bool stream_out = false);
 // blocks of a launch_x_c2r over nplanes planes (partial-sum pairs it writes)
 template <typename T>
 int x_c2r_blocks(int nx, int ny, size_t nplanes);
