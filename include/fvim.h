@@ -384,9 +384,14 @@ int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);
  * hbm_budget_bytes; the first pending request in submission order that fits
  * is taken.  Each slot runs on its own HIP stream (default priority), so
  * admitted requests overlap on the device while others keep arriving.  State
- * stays in device memory from admission to completion.  A request's result
- * does not depend on the other requests in flight (same kernels, own context,
- * default depth-pass layout, deterministic reductions).
+ * stays in device memory from admission to completion.  A slot keeps the
+ * context and state memory of its last request and reuses them for a later
+ * request with the same grid, material, precision and depth nodes (nothing
+ * is allocated then); kept memory counts against the budget and is given
+ * back when a pending request does not fit otherwise.  A request's result
+ * does not depend on the other requests in flight nor on the slot's previous
+ * request (same kernels, default depth-pass layout, deterministic
+ * reductions, state cleared).
  * Times are seconds since the server was created.  Results stay owned by the
  * server until fvim_server_release.  Thread-safe.
  */
@@ -417,7 +422,9 @@ typedef struct {
 typedef struct {
   int pending, running;
   uint64_t completed;
-  size_t bytes_in_use, peak_bytes, budget;
+  size_t bytes_in_use;       /* footprints of running requests and of the   */
+                             /* contexts idle slots keep                    */
+  size_t peak_bytes, budget;
 } fvim_server_stats;
 
 typedef struct fvim_server fvim_server;

@@ -9,9 +9,16 @@
 // priority), so admitted requests run concurrently on the device while new
 // ones keep arriving.  A request's state lives in device memory from
 // admission until its result has been copied back; the slot then frees the
-// memory for the next admission.  Every request runs the same deterministic
-// kernels in its own context with the default depth-pass layout, so its
-// result does not depend on what else is running.
+// memory for the next admission, unless the slot keeps it: each slot
+// retains the context and state memory of its last request and reuses them
+// for a later request of the same grid, material, precision and depth nodes
+// (the operator and solver workspaces, mode tables and captured graphs carry
+// over; the state is cleared), so a stream of same-sized requests allocates
+// nothing after its first.  Retained memory counts against the budget and is
+// dropped when a pending request cannot be admitted otherwise.  Every request
+// runs the same deterministic kernels with the default depth-pass layout, so
+// its result depends neither on what else is running nor on which request
+// the slot served before.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +56,39 @@ struct Job {
   bool done = false;
 };
 
+// The context and state memory a slot keeps from its last request.
+struct SlotCache {
+  fvim_ctx* ctx = nullptr;
+  double* mem = nullptr;
+  size_t held = 0;             // budget bytes it holds (0: nothing kept)
+  fvim_grid grid{};
+  fvim_material mat{};
+  int precision = -1;
+  std::vector<double> z;
+};
+
+bool cache_matches(const SlotCache& c, const Job* j) {
+  const fvim_request& r = j->req;
+  return c.ctx && c.precision == r.precision && memcmp(&c.grid, &r.grid, sizeof(fvim_grid)) == 0 &&
+         memcmp(&c.mat, &r.mat, sizeof(fvim_material)) == 0 && c.z == j->z;
+}
+
+// Budget bytes the slot holds once it has taken job j.
+size_t held_after(const SlotCache& c, const Job* j) {
+  return cache_matches(c, j) ? std::max(c.held, j->bytes) : j->bytes;
+}
+
+void cache_drop(SlotCache& c, hipStream_t st) {
+  if (!c.ctx) return;
+  std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
+  hipStreamSynchronize(st);
+  if (c.mem) hipFree(c.mem);
+  fvim_destroy(c.ctx);
+  c.ctx = nullptr;
+  c.mem = nullptr;
+  c.z.clear();
+}
+
 }  // namespace
 
 struct fvim_server {
@@ -76,27 +116,39 @@ size_t request_bytes(const fvim_request* r) {
          fvim::krylov_footprint(&g, &r->opts) + (r->opts.mu_f > 0 ? fvim::friction_footprint(&g) : 0);
 }
 
-int run_job(fvim_server* s, Job* j, hipStream_t st) {
+int run_job(fvim_server* s, Job* j, hipStream_t st, SlotCache& cache) {
   const fvim_request& r = j->req;
   const fvim_grid& g = r.grid;
   const size_t V = (size_t)g.nx * g.ny * g.nz, ns = (size_t)g.nx * g.ny;
-  fvim_ctx* ctx = nullptr;
-  int rc = fvim_create(&g, &r.mat, r.precision, FVIM_K0_INCLUDE, st, &ctx);
-  if (rc) return rc;
-  if (!j->z.empty() && (rc = fvim_set_depth_nodes(ctx, j->z.data()))) {
-    fvim_destroy(ctx);
-    return rc;
-  }
-  double* mem = nullptr;
   const size_t nd = 13 * V + 5 * ns;
-  // allocation and the copies from pageable host memory do not overlap
-  // another slot's graph capture
-  std::unique_lock<std::recursive_mutex> dev(fvim::device_lock());
-  if (hipMalloc((void**)&mem, sizeof(double) * nd) != hipSuccess) {
-    dev.unlock();
-    fvim_destroy(ctx);
-    return FVIM_ENOMEM;
+  int rc = FVIM_OK;
+  if (!cache_matches(cache, j)) {
+    cache_drop(cache, st);
+    fvim_ctx* ctx = nullptr;
+    rc = fvim_create(&g, &r.mat, r.precision, FVIM_K0_INCLUDE, st, &ctx);
+    if (rc) return rc;
+    if (!j->z.empty() && (rc = fvim_set_depth_nodes(ctx, j->z.data()))) {
+      fvim_destroy(ctx);
+      return rc;
+    }
+    double* mem = nullptr;
+    {
+      // allocation does not overlap another slot's graph capture
+      std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
+      if (hipMalloc((void**)&mem, sizeof(double) * nd) != hipSuccess) {
+        fvim_destroy(ctx);
+        return FVIM_ENOMEM;
+      }
+    }
+    cache.ctx = ctx;
+    cache.mem = mem;
+    cache.grid = g;
+    cache.mat = r.mat;
+    cache.precision = r.precision;
+    cache.z = j->z;
   }
+  fvim_ctx* ctx = cache.ctx;
+  double* mem = cache.mem;
   hipError_t e = hipMemsetAsync(mem, 0, sizeof(double) * nd, st);
   fvim_state state;
   state.eps_p = mem;
@@ -105,13 +157,15 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
   state.traction = mem + 13 * V;
   state.u3p = state.traction + 3 * ns;
   double* h = state.u3p + ns;
-  if (e == hipSuccess) e = hipMemcpyAsync(h, j->h.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  {
+    // copies from pageable host memory do not overlap a graph capture
+    std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
+    if (e == hipSuccess) e = hipMemcpyAsync(h, j->h.data(), sizeof(double) * ns, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+  }
   if (e != hipSuccess) rc = FVIM_EHIP;
-  dev.unlock();
   std::vector<fvim_ep_info> info(r.n_steps);
   if (!rc) rc = elastoplastic_solve(ctx, h, r.W_steps, r.n_steps, &r.opts, &state, info.data());
-  dev.lock();
   if (rc) {
     // the record of the step that failed (the first one not committed)
     for (const fvim_ep_info& i : info)
@@ -120,6 +174,7 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
         break;
       }
   } else {
+    std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
     j->res.info = info[r.n_steps - 1];
     j->p_host.resize(ns);
     j->u3_host.resize(ns);
@@ -133,9 +188,9 @@ int run_job(fvim_server* s, Job* j, hipStream_t st) {
     j->res.contact_fraction = (double)nc / (double)ns;
   }
   hipStreamSynchronize(st);
-  hipFree(mem);
-  fvim_destroy(ctx);
-  return rc;                            // releases the device lock
+  // a failed solve does not leave its context to the next request
+  if (rc) cache_drop(cache, st);
+  return rc;
 }
 
 void worker(fvim_server* s) {
@@ -145,31 +200,54 @@ void worker(fvim_server* s) {
     std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
     hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
   }
+  SlotCache cache;
   for (;;) {
     Job* j = nullptr;
+    bool drop = false;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       for (;;) {
         if (s->stop && s->pending.empty()) break;
-        // first pending request that fits in the remaining budget
+        // first pending request that fits in the remaining budget, counting
+        // the slot's retained memory as reusable (same grid) or freed
         std::vector<size_t> sizes;
         sizes.reserve(s->pending.size());
-        for (Job* q : s->pending) sizes.push_back(q->bytes);
-        int k = fvim_admit_index(sizes.data(), (int)sizes.size(), s->budget, s->in_use);
+        for (Job* q : s->pending) sizes.push_back(held_after(cache, q));
+        int k = fvim_admit_index(sizes.data(), (int)sizes.size(), s->budget, s->in_use - cache.held);
         if (k >= 0) {
           j = s->pending[k];
           s->pending.erase(s->pending.begin() + k);
-          s->in_use += j->bytes;
+          const size_t held = sizes[k];
+          if (!cache_matches(cache, j) && cache.ctx) {
+            // the slot frees its context outside the lock; its bytes are
+            // released now and the new request's counted
+            drop = true;
+          }
+          s->in_use = s->in_use - cache.held + held;
+          cache.held = held;
           s->peak = std::max(s->peak, s->in_use);
           s->running++;
+          break;
+        }
+        if (!s->pending.empty() && cache.held > 0) {
+          // nothing fits: give the retained memory back so that some slot
+          // can admit a pending request
+          s->in_use -= cache.held;
+          cache.held = 0;
+          drop = true;
           break;
         }
         s->cv_work.wait(lk);
       }
     }
+    if (drop) {
+      cache_drop(cache, st);
+      s->cv_work.notify_all();
+      if (!j) continue;
+    }
     if (!j) break;
     j->res.t_admit = now_s() - s->t0;
-    int rc = run_job(s, j, st);
+    int rc = run_job(s, j, st, cache);
     {
       std::lock_guard<std::mutex> lk(s->mu);
       j->res.status = rc;
@@ -178,13 +256,22 @@ void worker(fvim_server* s) {
       j->res.p = j->p_host.empty() ? nullptr : j->p_host.data();
       j->res.u3p = j->u3_host.empty() ? nullptr : j->u3_host.data();
       j->done = true;
-      s->in_use -= j->bytes;
+      if (!cache.ctx) {              // nothing kept (a failed solve)
+        s->in_use -= cache.held;
+        cache.held = 0;
+      }
       s->running--;
       s->completed++;
     }
     s->cv_done.notify_all();
     s->cv_work.notify_all();
   }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->in_use -= cache.held;
+    cache.held = 0;
+  }
+  cache_drop(cache, st);
   if (st) {
     std::lock_guard<std::recursive_mutex> dev(fvim::device_lock());
     hipStreamDestroy(st);

@@ -136,3 +136,45 @@ def test_requests_with_depth_nodes_identical_alone_and_in_mix():
     u0 = run(uni, [(reqs[0], None)])[0]
     uni.close()
     assert not np.array_equal(u0["u3p"], mixed[0]["u3p"])
+
+
+def test_served_results_match_the_stored_oracle_cases():
+    """The stored oracle cases (Hertz, the rough-surface experiment's setting,
+    graded depth nodes, Coulomb friction; written by
+    tests/golden/make_golden.py from the oracle alone) submitted to the
+    server in one mix with rough requests of other grids, the Hertz case
+    twice so that a slot reuses its context: the served pressure and
+    plastic surface displacement equal the oracle's within 1e-11."""
+    import os
+    from paper_1811_11558_amd import EPOptions, Server
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gold)
+    from make_golden import CASES
+    cases = ["hertz_ep_16x16x8", "rough_ep_16x16x8", "hertz_graded_ep_16x16x8", "hertz_friction_ep_16x16x8",
+             "hertz_ep_16x16x8"]
+    srv = Server(hbm_budget_bytes=8 << 30, max_slots=3)
+    ids = []
+    for i, name in enumerate(cases):
+        c = CASES[name]
+        ref = np.load(os.path.join(gold, name + ".npz"))
+        nx, ny, nz, lz = c["grid"]
+        g = grid_dict(nx, ny, nz, lz=lz)
+        fr = dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"]) if "friction" in c else {}
+        opts = EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000, **fr)
+        m = c["mat"]
+        ids.append((name, ref, g, srv.submit(g, ref["h"], list(ref["W"]), E=m["E"], nu=m["nu"],
+                                             sigma_y0=m["sigma_y0"], E_h=m["E_h"], opts=opts,
+                                             z=ref["z"] if "z" in ref else None)))
+        # other traffic between the stored cases
+        n = 32 * (1 + i % 2)
+        go = grid_dict(n, n, 16, lz=0.25)
+        ho = rough_surface(n, n, hurst=0.7, k_roll=2, k_cut=n // 4, rms_slope=0.05, seed=100 + i)
+        srv.submit(go, ho, [0.002], opts=_opts(True))
+    for name, ref, g, rid in ids:
+        r = srv.wait(rid, (g["ny"], g["nx"]))
+        assert r["status"] == 0, (name, r)
+        ep = np.linalg.norm(r["p"] - ref["traction"][2]) / np.linalg.norm(ref["traction"][2])
+        eu = np.linalg.norm(r["u3p"] - ref["u3p"]) / np.linalg.norm(ref["u3p"])
+        _say("served", name, "p", ep, "u3p", eu, "outer", r["info"]["outer_iters"])
+        assert ep < 1e-11 and eu < 1e-11, (name, ep, eu)
+    srv.close()
