@@ -670,6 +670,7 @@ def main():
         "operator_hbm_frac": round(total_alg / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "stages": stages,
         "depth_layout": depth_cfg,
+        "fft_config": [list(x) for x in ctx.fft_config()],
         "roofline": roof,
     }
     if not a.no_cpu_baseline and a.op == "fused":

@@ -164,16 +164,20 @@ int fvim_operator_apply_noalloc(fvim_ctx* ctx, const double* eps_p, const double
 /*
  * Batched application (batching of grids of different sizes): the fused
  * operator of fvim_operator_apply for n contexts at once, ordered on the
- * stream of ctxs[0].  Each context's in-plane transforms run as before; the
- * depth pass of up to 8 contexts runs as one launch for their regular modes
- * and one for their Nyquist modes, a table mapping each block to its grid
- * (the layout is the default one for the largest nz, so results agree with
- * separate applications up to the summation order of that layout, bitwise
- * when the contexts use the same layout).  The arrays hold one device
- * pointer per context (eps_p[i] [6][nz][ny][nx], ...); an array that is NULL
- * is not requested for any context, and every requested pointer must be
- * non-NULL.  All contexts must share the device and the precision.
- * Asynchronous.  Errors: FVIM_EINVAL for mismatched contexts or arguments.
+ * stream of ctxs[0].  Contexts whose transform lengths nx and ny are both at
+ * most 512 share one launch per in-plane transform stage (up to 8 grids per
+ * launch, each with its length's default transform choice); longer ones run
+ * their own transform launches with their own choices.  The depth pass of
+ * up to 8 contexts runs as one launch for their regular modes and one for
+ * their Nyquist modes, a table mapping each block to its grid (the layout is
+ * the default one for the largest nz).  A context's results are therefore
+ * the same in any batch (bitwise), and agree with its separate application
+ * up to the summation order of the depth layout and transform choices
+ * (bitwise when both are the defaults).  The arrays hold one device pointer
+ * per context (eps_p[i] [6][nz][ny][nx], ...); an array that is NULL is not
+ * requested for any context, and every requested pointer must be non-NULL.
+ * All contexts must share the device and the precision.  Asynchronous.
+ * Errors: FVIM_EINVAL for mismatched contexts or arguments.
  */
 int fvim_operator_apply_batch(fvim_ctx* const* ctxs, int n, const double* const* eps_p,
                               const double* const* traction, double* const* strain, double* const* stress,
@@ -366,10 +370,21 @@ int fvim_set_timing(fvim_ctx* ctx, int on);
  * caches for the next one; 0 never; 2 when the spectrum buffer of the
  * application is larger than 64 MiB and at most 256 MiB (it then fits the
  * last-level cache), where that measured faster on MI355X (same results
- * either way).
+ * either way).  FVIM_OPT_FFT_CONFIG: launch choices of the four in-plane
+ * transform kernels for the context's operator precision, 3 bits each
+ * (bits 3k .. 3k+2 for k = 0 forward row, 1 forward column, 2 inverse
+ * column, 3 inverse row transform): tile (0: half the default LDS tile,
+ * 1: default, 2: twice) | 4 for radix-8 stages (else radix 4); 0x249 is
+ * the default.  Alternatives exist for transform lengths 32 .. 1024; other
+ * lengths run the default.  FVIM_OPT_TUNE also times these (6 choices per
+ * kernel, on the next operator call's own data) and keeps the fastest; the
+ * result is recorded for the process under (nx, ny, nz, input and output
+ * planes, precision, device architecture) and reused by later contexts
+ * that ask for tuning.  Choices change only the summation order of the
+ * transforms.
  */
 enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3, FVIM_OPT_SIDE_STREAM = 4,
-       FVIM_OPT_STREAMING = 5 };
+       FVIM_OPT_STREAMING = 5, FVIM_OPT_FFT_CONFIG = 6 };
 int fvim_set_option(fvim_ctx* ctx, int key, int value);
 int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);

@@ -213,7 +213,15 @@ class Context:
 
     STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv", "depth_nyq")
 
-    OPT_DEPTH_CONFIG, OPT_TUNE, OPT_GRAPHS, OPT_SIDE_STREAM, OPT_STREAMING = 1, 2, 3, 4, 5
+    OPT_DEPTH_CONFIG, OPT_TUNE, OPT_GRAPHS, OPT_SIDE_STREAM, OPT_STREAMING, OPT_FFT_CONFIG = 1, 2, 3, 4, 5, 6
+
+    def fft_config(self):
+        """[(tile, radix)] of the forward row, forward column, inverse column
+        and inverse row transforms (the operator's precision)."""
+        return unpack_fft_config(self.get_option(self.OPT_FFT_CONFIG))
+
+    def set_fft_config(self, cfg):
+        self.set_option(self.OPT_FFT_CONFIG, pack_fft_config(cfg))
 
     def set_option(self, key, value):
         _check(_LIB.fvim_set_option(self._h, int(key), int(value)))
@@ -377,6 +385,18 @@ class Context:
             err.infos = out
             raise err
         return out
+
+
+def pack_fft_config(cfg):
+    """FVIM_OPT_FFT_CONFIG value of four (tile, radix) choices."""
+    v = 0
+    for k, (tile, radix) in enumerate(cfg):
+        v |= ((tile & 3) | (4 if radix == 8 else 0)) << (3 * k)
+    return v
+
+
+def unpack_fft_config(v):
+    return [((v >> (3 * k)) & 3, 8 if (v >> (3 * k)) & 4 else 4) for k in range(4)]
 
 
 def contact_info_dict(info):

@@ -8,8 +8,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/fvim.h"
@@ -170,13 +172,77 @@ int tune_depth(fvim_ctx* c, const cpx<T>* in, cpx<T>* out, const DepthParams& pr
   return FVIM_OK;
 }
 
+// Times launch(choice) for every candidate choice of a transform of length
+// 2^logn (one launch to warm up, then three timed) and returns the fastest in
+// *best; lengths without alternatives keep the default.
+template <typename F>
+static int time_choices(fvim_ctx* c, int logn, F&& launch, FftChoice* best) {
+  *best = FftChoice{};
+  if (logn < FFT_TUNE_MIN_LOGN || logn > FFT_TUNE_MAX_LOGN) return FVIM_OK;
+  hipStream_t st = c->stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return fail(FVIM_EHIP, "events");
+  float best_ms = 1e30f;
+  hipError_t e = hipSuccess;
+  for (int radix = 4; radix <= 8 && e == hipSuccess; radix += 4)
+    for (int tile = 0; tile < 3 && e == hipSuccess; ++tile) {
+      const FftChoice ch{tile, radix};
+      e = launch(ch);
+      if (e == hipSuccess) e = hipEventRecord(a, st);
+      for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch(ch);
+      if (e == hipSuccess) e = hipEventRecord(b, st);
+      if (e == hipSuccess) e = hipEventSynchronize(b);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        *best = ch;
+      }
+    }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return e == hipSuccess ? FVIM_OK : fail_hip(e, "transform tuning");
+}
+
+// Tuned launch choices kept for the process, keyed by the grid, the planes
+// of the application, the precision and the device architecture: a context
+// that asks for tuning takes an earlier context's result for the same key
+// instead of timing again.
+struct TuneKey {
+  int nx, ny, nz, np_in, np_out, tsize;
+  std::string arch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(nx, ny, nz, np_in, np_out, tsize, arch) <
+           std::tie(o.nx, o.ny, o.nz, o.np_in, o.np_out, o.tsize, o.arch);
+  }
+};
+struct TuneRec {
+  FftChoice ch[4];
+  int depth_cfg;
+};
+static std::mutex g_tune_mx;
+static std::map<TuneKey, TuneRec>& tune_records() {
+  static std::map<TuneKey, TuneRec> m;
+  return m;
+}
+
+int fft_pack(const fvim_ctx* c, int prec) {
+  int v = 0;
+  for (int k = 0; k < 4; ++k) {
+    const FftChoice ch = c->fft[prec][k];
+    v |= ((ch.tile & 3) | (ch.radix == 8 ? 4 : 0)) << (3 * k);
+  }
+  return v;
+}
+int fft_pack_all(const fvim_ctx* c) { return fft_pack(c, 0) | (fft_pack(c, 1) << 12); }
+
 // One operator application on one grid: parameters, buffers, launches.
 template <typename T>
 struct OpPlan {
   DepthParams prm{};
   OutSegments seg{};
   InSegments iseg{};
-  int np = 0, np_in = 0, wbpp = 0;
+  int np = 0, np_in = 0, wbpp = 0, wbmax = 0;
   bool k0x = false;
   bool nt = false;              // launches read their input with streaming loads
   ResidEpilogue ep{};           // residual epilogue of the inverse x transform
@@ -188,7 +254,11 @@ struct OpPlan {
   cpx<T>* B = nullptr;
   const cpx<T>* twx = nullptr;
   const cpx<T>* twy = nullptr;
+  FftChoice ch[4];              // x_r2c, y_fwd, y_inv, x_c2r
 };
+
+template <typename T>
+constexpr int prec_index() { return sizeof(T) == 8 ? 0 : 1; }
 
 // Device bytes one application needs: each of the two spectrum buffers
 // (spectrum plus the Nyquist sign-replica records), the float64 plane sums
@@ -260,8 +330,12 @@ int op_layout(fvim_ctx* c, const double* eps_p, const double* traction, double* 
   // the depth pass writes E to A; the Nyquist sign-replica records follow it
   const size_t nrep = (size_t)depth_replicas(ny, kxh);
   sz.spec = (planes * nmodes + nrep * (size_t)prm.ld_out) * sizeof(cpx<T>);
-  P.wbpp = x_r2c_blocks_per_plane<T>(nx, ny);
-  sz.k0 = P.k0x ? sizeof(double) * ((size_t)(6 * nz + 3) * P.wbpp + (size_t)np) : 0;
+  for (int k = 0; k < 4; ++k) P.ch[k] = c->fft[prec_index<T>()][k];
+  P.wbpp = x_r2c_blocks_per_plane<T>(nx, ny, P.ch[0]);
+  // block sums of every input plane for the most blocks any tile choice
+  // gives (the tuner runs them all), then the mean-mode constants
+  P.wbmax = x_r2c_max_blocks_per_plane<T>(nx, ny);
+  sz.k0 = P.k0x ? sizeof(double) * ((size_t)(6 * nz + 3) * P.wbmax + (size_t)np) : 0;
   sz.mt = sizeof(ModeConst<T>) * nmodes;
   // Streaming loads pay off when one launch's output fits the 256 MiB
   // last-level cache, so the next launch can read it from there. Measured
@@ -284,7 +358,7 @@ void op_bind(fvim_ctx* c, OpPlan<T>& P, void* bufA, void* bufB, double* k0buf, c
   if (P.k0x) {
     P.wsum = k0buf;                                // block sums of every input plane
     P.tsum = P.wsum + (size_t)P.prm.off_t * P.wbpp;
-    P.padd = P.wsum + (size_t)(6 * c->grid.nz + 3) * P.wbpp;
+    P.padd = P.wsum + (size_t)(6 * c->grid.nz + 3) * P.wbmax;
   }
   P.prm.mtab = mt;
   P.prm.hz = c->hz;
@@ -323,17 +397,68 @@ int op_plan(fvim_ctx* c, const double* eps_p, const double* traction, double* st
   return FVIM_OK;
 }
 
+// Block count of the forward row transform after a change of its choice:
+// the float64 plane sums of the float32 path follow it.
+template <typename T>
+void op_refresh_sums(fvim_ctx* c, OpPlan<T>& P) {
+  P.wbpp = x_r2c_blocks_per_plane<T>(c->grid.nx, c->grid.ny, P.ch[0]);
+  if (P.k0x) P.tsum = P.wsum + (size_t)P.prm.off_t * P.wbpp;
+}
+
+static int ilog2i(int n) { return 31 - __builtin_clz((unsigned)n); }
+
+// Tuning of the forward transforms on the live input: the row transform's
+// choices (its output then recomputed with the fastest), then the column
+// transform's on that output.
+template <typename T>
+int tune_forward(fvim_ctx* c, OpPlan<T>& P) {
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  hipStream_t st = c->stream;
+  int rc = time_choices(c, ilog2i(nx), [&](FftChoice ch) {
+    return launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum, P.nt, P.skip, ch);
+  }, &P.ch[0]);
+  if (rc) return rc;
+  op_refresh_sums<T>(c, P);
+  hipError_t e = launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum, P.nt, P.skip, P.ch[0]);
+  if (e != hipSuccess) return fail_hip(e, "x_r2c");
+  return time_choices(c, ilog2i(ny), [&](FftChoice ch) {
+    return launch_y_fwd<T>(P.A, P.B, ny, kxh, P.np_in, P.prm.ld_in, P.twy, st, P.nt, P.skip, ch);
+  }, &P.ch[1]);
+}
+
+// Tuning of the inverse transforms on the depth pass's output (the outputs
+// are written again by the application's own inverse afterwards).
+template <typename T>
+int tune_inverse(fvim_ctx* c, OpPlan<T>& P) {
+  const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
+  hipStream_t st = c->stream;
+  hipError_t e;
+  if (P.k0x && (e = launch_k0_fields(P.wsum, P.wbpp, P.tsum, P.wbpp, P.padd, P.prm, st)) != hipSuccess)
+    return fail_hip(e, "k0");
+  int rc = time_choices(c, ilog2i(ny), [&](FftChoice ch) {
+    return launch_y_inv<T>(P.A, P.B, ny, kxh, P.np, P.prm.ld_out, P.twy, st, P.nt, ch);
+  }, &P.ch[2]);
+  if (rc) return rc;
+  if ((e = launch_y_inv<T>(P.A, P.B, ny, kxh, P.np, P.prm.ld_out, P.twy, st, P.nt, P.ch[2])) != hipSuccess)
+    return fail_hip(e, "y_inv");
+  return time_choices(c, ilog2i(nx), [&](FftChoice ch) {
+    return launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.ep, true, ch);
+  }, &P.ch[3]);
+}
+
 // Forward transforms of the input planes: real fields -> mode-major B.
 template <typename T>
 int op_forward(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
   const int nx = c->grid.nx, ny = c->grid.ny, kxh = nx / 2 + 1;
   hipError_t e;
   tm.begin(FVIM_STAGE_XFWD, st);
-  if ((e = launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum, P.nt, P.skip)) != hipSuccess)
+  if ((e = launch_x_r2c<T>(P.iseg, P.A, nx, ny, (size_t)P.np_in, P.twx, st, P.wsum, P.nt, P.skip, P.ch[0])) !=
+      hipSuccess)
     return fail_hip(e, "x_r2c");
   tm.end();
   tm.begin(FVIM_STAGE_YFWD, st);
-  if ((e = launch_y_fwd<T>(P.A, P.B, ny, kxh, P.np_in, P.prm.ld_in, P.twy, st, P.nt, P.skip)) != hipSuccess)
+  if ((e = launch_y_fwd<T>(P.A, P.B, ny, kxh, P.np_in, P.prm.ld_in, P.twy, st, P.nt, P.skip, P.ch[1])) !=
+      hipSuccess)
     return fail_hip(e, "y_fwd");
   tm.end();
   return FVIM_OK;
@@ -347,11 +472,12 @@ int op_inverse(fvim_ctx* c, OpPlan<T>& P, hipStream_t st, StageTimer& tm) {
   if (P.k0x && (e = launch_k0_fields(P.wsum, P.wbpp, P.tsum, P.wbpp, P.padd, P.prm, st)) != hipSuccess)
     return fail_hip(e, "k0");
   tm.begin(FVIM_STAGE_YINV, st);
-  if ((e = launch_y_inv<T>(P.A, P.B, ny, kxh, P.np, P.prm.ld_out, P.twy, st, P.nt)) != hipSuccess)
+  if ((e = launch_y_inv<T>(P.A, P.B, ny, kxh, P.np, P.prm.ld_out, P.twy, st, P.nt, P.ch[2])) != hipSuccess)
     return fail_hip(e, "y_inv");
   tm.end();
   tm.begin(FVIM_STAGE_XINV, st);
-  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.ep, true)) != hipSuccess)
+  if ((e = launch_x_c2r<T>(P.B, P.seg, nx, ny, (size_t)P.np, 1.0, P.twx, st, P.padd, P.ep, true, P.ch[3])) !=
+      hipSuccess)
     return fail_hip(e, "x_c2r");
   tm.end();
   return FVIM_OK;
@@ -404,8 +530,34 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
   hipStream_t ss = side ? c->side : st;
   hipError_t e;
   StageTimer tm(c, scratch == nullptr);
+  // tuning (plain applications only): take the process record for this
+  // shape, else time every transform choice and depth layout on this call
+  const bool tune = c->tune_pending && !scratch && !ep;
+  bool timed = false;
+  if (tune) {
+    const TuneKey key{c->grid.nx, c->grid.ny, c->grid.nz, P.np_in, P.np, (int)sizeof(T), c->arch};
+    TuneRec rec{};
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mx);
+      auto it = tune_records().find(key);
+      if (it != tune_records().end()) {
+        rec = it->second;
+        have = true;
+      }
+    }
+    if (have) {
+      for (int k = 0; k < 4; ++k) P.ch[k] = c->fft[prec_index<T>()][k] = rec.ch[k];
+      c->depth_cfg = rec.depth_cfg;
+      c->tune_pending = 0;
+      op_refresh_sums<T>(c, P);
+    } else {
+      if ((rc = tune_forward<T>(c, P))) return rc;
+      timed = true;
+    }
+  }
   if ((rc = op_forward<T>(c, P, st, tm))) return rc;
-  if (c->tune_pending && !scratch) {
+  if (timed) {
     c->tune_pending = 0;
     int rc2 = tune_depth<T>(c, P.B, P.A, P.prm);
     if (rc2) return rc2;
@@ -419,6 +571,16 @@ int operator_apply_t(fvim_ctx* c, const double* eps_p, const double* traction, d
     return fail_hip(e, "depth (Nyquist modes)");
   tm.end();
   if (ss != st && (e = join(c->ev_nyq, ss, st)) != hipSuccess) return fail_hip(e, "join");
+  if (timed) {
+    if ((rc = tune_inverse<T>(c, P))) return rc;
+    for (int k = 0; k < 4; ++k) c->fft[prec_index<T>()][k] = P.ch[k];
+    const TuneKey key{c->grid.nx, c->grid.ny, c->grid.nz, P.np_in, P.np, (int)sizeof(T), c->arch};
+    TuneRec rec{};
+    for (int k = 0; k < 4; ++k) rec.ch[k] = P.ch[k];
+    rec.depth_cfg = c->depth_cfg;
+    std::lock_guard<std::mutex> lk(g_tune_mx);
+    tune_records()[key] = rec;
+  }
   return op_inverse<T>(c, P, st, tm);
 }
 
@@ -449,8 +611,64 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
   fvim_ctx* c0 = cs[0];
   if ((rc = ctx_reserve(c0, &c0->dbatch, &c0->dbatch_bytes, sizeof(DepthBatch)))) return restore(rc);
   StageTimer tm(c0);
-  for (int i = 0; i < n && !rc; ++i) rc = op_forward<T>(cs[i], P[i], st, tm);
-  if (rc) return restore(rc);
+  // Grids whose transform lengths are both at most 2^XFORM_BATCH_MAX_LOGN
+  // share one launch per transform stage (up to XFORM_BATCH_MAX grids each,
+  // the default choices); longer ones keep launches of their own.
+  std::vector<int> bat;
+  for (int i = 0; i < n; ++i) {
+    if (ilog2i(cs[i]->grid.nx) <= XFORM_BATCH_MAX_LOGN && ilog2i(cs[i]->grid.ny) <= XFORM_BATCH_MAX_LOGN) {
+      bat.push_back(i);
+      for (int k = 0; k < 4; ++k) P[i].ch[k] = FftChoice{};
+      P[i].wbpp = x_r2c_batch_blocks_per_plane<T>(cs[i]->grid.nx, cs[i]->grid.ny);
+      if (P[i].k0x) P[i].tsum = P[i].wsum + (size_t)P[i].prm.off_t * P[i].wbpp;
+    } else if ((rc = op_forward<T>(cs[i], P[i], st, tm))) {
+      return restore(rc);
+    }
+  }
+  // one stage of the batched grids, XFORM_BATCH_MAX at a time
+  auto xform = [&](int kind, int stage) -> int {
+    for (size_t i0 = 0; i0 < bat.size(); i0 += XFORM_BATCH_MAX) {
+      XformBatch b{};
+      b.n = (int)std::min<size_t>(XFORM_BATCH_MAX, bat.size() - i0);
+      for (int k = 0; k < b.n; ++k) {
+        const int i = bat[i0 + k];
+        const OpPlan<T>& p = P[i];
+        const int nx = cs[i]->grid.nx, ny = cs[i]->grid.ny;
+        b.ny[k] = ny;
+        b.kxh[k] = nx / 2 + 1;
+        b.logn[k] = ilog2i(kind == 0 || kind == 3 ? nx : ny);
+        b.tw[k] = kind == 0 || kind == 3 ? (const void*)p.twx : (const void*)p.twy;
+        if (kind == 0) {
+          b.NP[k] = p.np_in;
+          b.iseg[k] = p.iseg;
+          b.out[k] = p.A;
+          b.bsum[k] = p.wsum;
+        } else if (kind == 1) {
+          b.NP[k] = p.np_in;
+          b.ldp[k] = p.prm.ld_in;
+          b.in[k] = p.A;
+          b.out[k] = p.B;
+        } else if (kind == 2) {
+          b.NP[k] = p.np;
+          b.ldp[k] = p.prm.ld_out;
+          b.in[k] = p.A;
+          b.out[k] = p.B;
+        } else {
+          b.NP[k] = p.np;
+          b.in[k] = p.B;
+          b.oseg[k] = p.seg;
+          b.padd[k] = p.padd;
+          b.nts[k] = 1;
+        }
+      }
+      tm.begin(stage, st);
+      hipError_t e = launch_xform_batch<T>(kind, b, st);
+      tm.end();
+      if (e != hipSuccess) return fail_hip(e, "batched transform");
+    }
+    return FVIM_OK;
+  };
+  if ((rc = xform(0, FVIM_STAGE_XFWD)) || (rc = xform(1, FVIM_STAGE_YFWD))) return restore(rc);
   const int cfg = depth_default_config(maxnz);
   const int gpb = depth_groups_per_block(cfg);
   for (int i0 = 0; i0 < n; i0 += DEPTH_BATCH_MAX) {
@@ -473,8 +691,18 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
     tm.end();
     if (e != hipSuccess) return restore(fail_hip(e, "batched depth pass"));
   }
-  for (int i = 0; i < n && !rc; ++i) rc = op_inverse<T>(cs[i], P[i], st, tm);
-  return restore(rc);
+  for (int i = 0; i < n && !rc; ++i) {
+    const bool in_batch = std::find(bat.begin(), bat.end(), i) != bat.end();
+    if (!in_batch) {
+      rc = op_inverse<T>(cs[i], P[i], st, tm);
+    } else if (P[i].k0x) {
+      hipError_t e = launch_k0_fields(P[i].wsum, P[i].wbpp, P[i].tsum, P[i].wbpp, P[i].padd, P[i].prm, st);
+      if (e != hipSuccess) rc = fail_hip(e, "k0");
+    }
+  }
+  if (rc) return restore(rc);
+  if ((rc = xform(2, FVIM_STAGE_YINV)) || (rc = xform(3, FVIM_STAGE_XINV))) return restore(rc);
+  return restore(FVIM_OK);
 }
 
 static bool misaligned(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u); }
@@ -486,16 +714,16 @@ int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* tractio
   const ResidEpilogue ep = {x, Fo, part, c->grid.nz, c->wz};
   const size_t np = (size_t)6 * c->grid.nz;
   if (c->precision == FVIM_FP32_REFINED && !c->force_fp64) {
-    *nparts = x_c2r_blocks<float>(c->grid.nx, c->grid.ny, np);
+    *nparts = x_c2r_blocks<float>(c->grid.nx, c->grid.ny, np, c->fft[1][3]);
     return operator_apply_t<float>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep, zact);
   }
-  *nparts = x_c2r_blocks<double>(c->grid.nx, c->grid.ny, np);
+  *nparts = x_c2r_blocks<double>(c->grid.nx, c->grid.ny, np, c->fft[0][3]);
   return operator_apply_t<double>(c, eps_p, traction, R, nullptr, nullptr, nullptr, &ep, zact);
 }
 
 int operator_resid_parts(const fvim_grid& g) {
   const size_t np = (size_t)6 * g.nz;
-  return std::max(x_c2r_blocks<float>(g.nx, g.ny, np), x_c2r_blocks<double>(g.nx, g.ny, np));
+  return std::max(x_c2r_max_blocks<float>(g.nx, g.ny, np), x_c2r_max_blocks<double>(g.nx, g.ny, np));
 }
 
 int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, double* strain) {
@@ -573,6 +801,10 @@ int fvim_create(const fvim_grid* grid, const fvim_material* mat, int precision, 
   c->stream = (hipStream_t)hip_stream;
   hipGetDevice(&c->device);
   scratch_lookup(c->device);
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) c->arch = prop.gcnArchName;
+  }
   c->mu = mat->E / (2.0 * (1.0 + mat->nu));
   c->lam = mat->E * mat->nu / ((1.0 + mat->nu) * (1.0 - 2.0 * mat->nu));
   hipError_t e = hipSuccess;
@@ -632,6 +864,18 @@ int fvim_set_option(fvim_ctx* c, int key, int value) {
       if (value < 0 || value > 2) return fail(FVIM_EINVAL, "streaming: 0, 1 or 2");
       c->streaming = value;
       return FVIM_OK;
+    case FVIM_OPT_FFT_CONFIG: {
+      if (value < 0 || value >= (1 << 12)) return fail(FVIM_EINVAL, "fft config: 12 bits");
+      const int prec = c->precision == FVIM_FP32_REFINED ? 1 : 0;
+      FftChoice ch[4];
+      for (int k = 0; k < 4; ++k) {
+        const int v = (value >> (3 * k)) & 7;
+        ch[k] = FftChoice{v & 3, (v & 4) ? 8 : 4};
+        if (ch[k].tile > 2) return fail(FVIM_EINVAL, "fft config: tile 0, 1 or 2");
+      }
+      for (int k = 0; k < 4; ++k) c->fft[prec][k] = ch[k];
+      return FVIM_OK;
+    }
   }
   return fail(FVIM_EINVAL, "unknown option");
 }
@@ -653,6 +897,9 @@ int fvim_get_option(fvim_ctx* c, int key, int* value) {
       return FVIM_OK;
     case FVIM_OPT_STREAMING:
       *value = c->streaming;
+      return FVIM_OK;
+    case FVIM_OPT_FFT_CONFIG:
+      *value = fft_pack(c, c->precision == FVIM_FP32_REFINED ? 1 : 0);
       return FVIM_OK;
   }
   return fail(FVIM_EINVAL, "unknown option");

@@ -1,8 +1,9 @@
 // In-plane transforms of the layered fields (the DFT of Sec. 3.1, eqn dft),
 // written for gfx950: every kernel stages a batch of 1D transforms through
-// LDS and runs a self-sorting (Stockham) radix-4 FFT with one radix-2 stage
-// when log2(n) is odd.  Global memory is touched once on the way in and once
-// on the way out, with the layouts chosen so both sides are contiguous runs:
+// LDS and runs a self-sorting (Stockham) FFT of radix 4 (one radix-2 stage
+// when log2(n) is odd) or radix 8 (one radix-2 or radix-4 stage first).
+// Global memory is touched once on the way in and once on the way out, with
+// the layouts chosen so both sides are contiguous runs:
 //
 //   real field        [P][ny][nx]          (P planes = components x layers)
 //   x-spectrum   X    [P][nx/2+1][ny]      written by x_r2c, read by y_fwd
@@ -13,6 +14,13 @@
 // and the mirror images for the inverse.  Real transforms of length nx are
 // done two rows at a time as one complex transform (z = a + i b).
 // Forward transforms are unnormalised; the depth pass applies 1/(nx ny).
+//
+// The LDS tile (half, default or twice the default) and the radix are
+// choices of each launch (FftChoice), timed by the context's tuner for
+// lengths 2^5 .. 2^10; other lengths use the default.  Kernels over several
+// grids (XformBatch) run the default choice of each grid's length.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -29,15 +37,19 @@ __device__ __forceinline__ cpx<T> twid(const cpx<T>* __restrict__ tw, int idx) {
   return w;
 }
 
-// Complex elements of one block's LDS tile in the row kernels, chosen per
+// Complex elements of one block's LDS tile in the row kernels.  TILE picks
+// half (0), the default (1) or twice (2) the default, which was chosen per
 // kernel and precision by measurement on 256^2 x 64: a smaller tile lets
-// more blocks share a CU (the forward transform gains: 16 KiB), a larger one
-// gives the inverse transform's strided reads longer runs (32 KiB in
-// float64; 16 KiB in float32).
+// more blocks share a CU (the forward transform gains: 16 KiB in float64),
+// a larger one gives the inverse transform's strided reads longer runs
+// (32 KiB in float64; 16 KiB in float32).  The tuner times the three.
+__host__ __device__ constexpr int tile_scale(int base, int tile) {
+  return tile == 0 ? base / 2 : (tile == 2 ? base * 2 : base);
+}
 template <typename T>
-__host__ __device__ constexpr int r2c_tile_elems() { return sizeof(T) == 8 ? 1024 : 2048; }
+__host__ __device__ constexpr int r2c_tile_elems(int tile) { return tile_scale(sizeof(T) == 8 ? 1024 : 2048, tile); }
 template <typename T>
-__host__ __device__ constexpr int c2r_tile_elems() { return 2048; }
+__host__ __device__ constexpr int c2r_tile_elems(int tile) { return tile_scale(2048, tile); }
 // Row pairs per block of a row kernel (R = 2 SEQ rows of length n).  The
 // X[p][kx][y] side is touched in runs of R elements of one kx, so SEQ is the
 // tile's share but at least what gives runs of ROW_RUN bytes, as far as the
@@ -54,130 +66,204 @@ __host__ __device__ constexpr int row_seq(int n, int csize, int tile) {
   return seq;
 }
 template <typename T>
-__host__ __device__ constexpr int r2c_seq(int n) { return row_seq(n, (int)sizeof(cpx<T>), r2c_tile_elems<T>()); }
+__host__ __device__ constexpr int r2c_seq(int n, int tile) {
+  return row_seq(n, (int)sizeof(cpx<T>), r2c_tile_elems<T>(tile));
+}
 template <typename T>
-__host__ __device__ constexpr int c2r_seq(int n) { return row_seq(n, (int)sizeof(cpx<T>), c2r_tile_elems<T>()); }
+__host__ __device__ constexpr int c2r_seq(int n, int tile) {
+  return row_seq(n, (int)sizeof(cpx<T>), c2r_tile_elems<T>(tile));
+}
 // Columns (planes) per block of the column (y) kernels.  The mode-major side
-// S[kx][ky][p] is touched in runs of B consecutive planes, so B is the 32 KiB
-// tile's share unless that makes runs shorter than 64 bytes (ny >= 1024 in
-// float64, >= 1024 in float32), in which case the tile grows up to the
-// 160 KiB of LDS a block may use (powers of two).  Measured: 32-byte runs ran
-// at 1.5 TB/s, 64-byte runs at 4.4 TB/s, and 64 KiB tiles with 256-byte runs
-// were slower than 32 KiB ones at ny = 256.
-__host__ __device__ constexpr int col_batch_bytes(int n, int csize) {
-  int b = (32768 / csize) / n;
+// S[kx][ky][p] is touched in runs of B consecutive planes, so B is the tile's
+// share (32 KiB by default; half or twice with TILE 0 or 2) unless that makes
+// runs shorter than 64 bytes (ny >= 1024 in float64, >= 1024 in float32), in
+// which case the tile grows up to the 160 KiB of LDS a block may use (powers
+// of two).  Measured: 32-byte runs ran at 1.5 TB/s, 64-byte runs at 4.4 TB/s,
+// and 64 KiB tiles with 256-byte runs were slower than 32 KiB ones at
+// ny = 256.
+__host__ __device__ constexpr int col_batch_bytes(int n, int csize, int tile) {
+  int b = (tile_scale(32768, tile) / csize) / n;
   if (b < 1) b = 1;
   const int minb = 64 / csize;
   int maxb = 1;
   while (2 * maxb * (n + 1) * csize <= 160 * 1024) maxb *= 2;
   if (b < minb) b = minb < maxb ? minb : maxb;
+  if (b > maxb) b = maxb;
   return b;
 }
 template <typename T>
-__host__ __device__ constexpr int col_batch(int n) { return col_batch_bytes(n, (int)sizeof(cpx<T>)); }
+__host__ __device__ constexpr int col_batch(int n, int tile) { return col_batch_bytes(n, (int)sizeof(cpx<T>), tile); }
 
-// NB transforms of length N = 2^LOGN held at buf[b * ld + k] (NB <= NBMAX),
-// Stockham autosort: one radix-2 stage first when LOGN is odd, then radix-4
-// stages.  All index arithmetic is shifts and masks.  Called by all NT threads.
-template <typename T, int LOGN, int NBMAX, bool INV>
-__device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T>* __restrict__ tw) {
-  constexpr int N = 1 << LOGN;
-  const int tid = threadIdx.x;
-  if constexpr (LOGN & 1) {
-    constexpr int H = N / 2;
-    constexpr int MB = (NBMAX * H + NT - 1) / NT;
-    const int nb = NB * H;
-    cpx<T> v0[MB], v1[MB];
-#pragma unroll
-    for (int u = 0; u < MB; ++u) {
-      int j = tid + u * NT;
-      if (j < nb) {
-        int b = j >> (LOGN - 1), jj = j & (H - 1);
-        v0[u] = buf[b * ld + jj];
-        v1[u] = buf[b * ld + jj + H];
-      }
+__host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+// Radix-R butterfly (R = 2, 4, 8) of the DFT with kernel exp(-2 pi i / R)
+// (its conjugate for INV), in place on a[0 .. R).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void butterfly(cpx<T>* a) {
+  if constexpr (R == 2) {
+    const cpx<T> a0 = a[0], a1 = a[1];
+    a[0] = add(a0, a1);
+    a[1] = sub(a0, a1);
+  } else if constexpr (R == 4) {
+    const cpx<T> s02 = add(a[0], a[2]), d02 = sub(a[0], a[2]);
+    const cpx<T> s13 = add(a[1], a[3]), d13 = sub(a[1], a[3]);
+    // forward: y1 = d02 - i d13, y3 = d02 + i d13 (conjugate for inverse)
+    const cpx<T> id13 = INV ? mul_i(d13) : mul_mi(d13);
+    a[0] = add(s02, s13);
+    a[1] = add(d02, id13);
+    a[2] = sub(s02, s13);
+    a[3] = sub(d02, id13);
+  } else {
+    static_assert(R == 8, "radix 2, 4 or 8");
+    // two length-4 transforms (even and odd inputs), then the odd ones
+    // turned by w^p, w = exp(-+ 2 pi i / 8), and combined
+    cpx<T> e[4] = {a[0], a[2], a[4], a[6]};
+    cpx<T> o[4] = {a[1], a[3], a[5], a[7]};
+    butterfly<T, 4, INV>(e);
+    butterfly<T, 4, INV>(o);
+    const T c = T(0.70710678118654752440084436210485);
+    cpx<T> t1, t3;
+    if (INV) {
+      t1 = mk((o[1].x - o[1].y) * c, (o[1].x + o[1].y) * c);      // (1 + i)/sqrt2
+      t3 = mk(-(o[3].x + o[3].y) * c, (o[3].x - o[3].y) * c);     // (-1 + i)/sqrt2
+    } else {
+      t1 = mk((o[1].x + o[1].y) * c, (o[1].y - o[1].x) * c);      // (1 - i)/sqrt2
+      t3 = mk((o[3].y - o[3].x) * c, -(o[3].x + o[3].y) * c);     // (-1 - i)/sqrt2
     }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MB; ++u) {
-      int j = tid + u * NT;
-      if (j < nb) {
-        int b = j >> (LOGN - 1), jj = j & (H - 1);
-        buf[b * ld + 2 * jj] = add(v0[u], v1[u]);
-        buf[b * ld + 2 * jj + 1] = sub(v0[u], v1[u]);
-      }
-    }
-    __syncthreads();
-  }
-  constexpr int Q = N / 4;
-  constexpr int MB4 = (NBMAX * Q + NT - 1) / NT;
-  const int nb4 = NB * Q;
-#pragma unroll
-  for (int ls = (LOGN & 1); ls < LOGN; ls += 2) {
-    const int ns = 1 << ls;
-    const int tstep = N >> (ls + 2);
-    cpx<T> v[MB4][4];
-#pragma unroll
-    for (int u = 0; u < MB4; ++u) {
-      int j = tid + u * NT;
-      if (j < nb4) {
-        int b = j >> (LOGN - 2), jj = j & (Q - 1);
-        const cpx<T>* src = buf + b * ld + jj;
-        v[u][0] = src[0];
-        v[u][1] = src[Q];
-        v[u][2] = src[2 * Q];
-        v[u][3] = src[3 * Q];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MB4; ++u) {
-      int j = tid + u * NT;
-      if (j < nb4) {
-        int b = j >> (LOGN - 2), jj = j & (Q - 1);
-        int k = jj & (ns - 1);
-        cpx<T> a0 = v[u][0];
-        cpx<T> a1 = v[u][1], a2 = v[u][2], a3 = v[u][3];
-        if (ls > 0) {
-          a1 = mul(a1, twid<T, INV>(tw, k * tstep));
-          a2 = mul(a2, twid<T, INV>(tw, 2 * k * tstep));
-          a3 = mul(a3, twid<T, INV>(tw, 3 * k * tstep));
-        }
-        cpx<T> s02 = add(a0, a2), d02 = sub(a0, a2);
-        cpx<T> s13 = add(a1, a3), d13 = sub(a1, a3);
-        // forward: y1 = d02 - i d13, y3 = d02 + i d13 (conjugate for inverse)
-        cpx<T> id13 = INV ? mul_i(d13) : mul_mi(d13);
-        int o = b * ld + ((jj >> ls) << (ls + 2)) + k;
-        buf[o] = add(s02, s13);
-        buf[o + ns] = add(d02, id13);
-        buf[o + 2 * ns] = sub(s02, s13);
-        buf[o + 3 * ns] = sub(d02, id13);
-      }
-    }
-    __syncthreads();
+    const cpx<T> t2 = INV ? mul_i(o[2]) : mul_mi(o[2]);
+    a[0] = add(e[0], o[0]);
+    a[4] = sub(e[0], o[0]);
+    a[1] = add(e[1], t1);
+    a[5] = sub(e[1], t1);
+    a[2] = add(e[2], t2);
+    a[6] = sub(e[2], t2);
+    a[3] = add(e[3], t3);
+    a[7] = sub(e[3], t3);
   }
 }
+
+// One self-sorting (Stockham) radix-R stage of NB transforms of length
+// N = 2^LOGN held at buf[b * ld + k] (NB <= NBMAX), for sub-transforms of
+// length ns = 2^LS: butterfly j of a transform takes elements j + m N/R,
+// turned by w^(m k N/(R ns)) with k = j mod ns, and writes them to
+// (j / ns) ns R + k + m ns.  Called by all NT threads.
+template <typename T, int LOGN, int NBMAX, bool INV, int R, int LS>
+__device__ __forceinline__ void stockham_stage(cpx<T>* buf, int ld, int NB, const cpx<T>* __restrict__ tw) {
+  constexpr int N = 1 << LOGN;
+  constexpr int LR = ilog2c(R);
+  constexpr int M = N / R;
+  constexpr int ns = 1 << LS;
+  constexpr int tstep = M >> LS;
+  constexpr int MB = (NBMAX * M + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  const int nb = NB * M;
+  cpx<T> v[MB][R];
+#pragma unroll
+  for (int u = 0; u < MB; ++u) {
+    const int j = tid + u * NT;
+    if (j < nb) {
+      const int b = j >> (LOGN - LR), jj = j & (M - 1);
+      const cpx<T>* src = buf + b * ld + jj;
+#pragma unroll
+      for (int m = 0; m < R; ++m) v[u][m] = src[m * M];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < MB; ++u) {
+    const int j = tid + u * NT;
+    if (j < nb) {
+      const int b = j >> (LOGN - LR), jj = j & (M - 1);
+      const int k = jj & (ns - 1);
+      if constexpr (LS > 0) {
+#pragma unroll
+        for (int m = 1; m < R; ++m) v[u][m] = mul(v[u][m], twid<T, INV>(tw, m * k * tstep));
+      }
+      butterfly<T, R, INV>(v[u]);
+      const int o = b * ld + ((jj >> LS) << (LS + LR)) + k;
+#pragma unroll
+      for (int m = 0; m < R; ++m) buf[o + m * ns] = v[u][m];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int LOGN, int NBMAX, bool INV, int R, int LS>
+__device__ __forceinline__ void stockham_from(cpx<T>* buf, int ld, int NB, const cpx<T>* __restrict__ tw) {
+  if constexpr (LS < LOGN) {
+    stockham_stage<T, LOGN, NBMAX, INV, R, LS>(buf, ld, NB, tw);
+    stockham_from<T, LOGN, NBMAX, INV, R, LS + ilog2c(R)>(buf, ld, NB, tw);
+  }
+}
+
+// NB transforms of length N = 2^LOGN held at buf[b * ld + k] (NB <= NBMAX),
+// Stockham autosort.  RADIX 4: one radix-2 stage first when LOGN is odd,
+// then radix-4 stages; RADIX 8: one radix-2 or radix-4 stage first when
+// LOGN mod 3 is 1 or 2, then radix-8 stages.  All index arithmetic is shifts
+// and masks.  Called by all NT threads.
+template <typename T, int LOGN, int NBMAX, bool INV, int RADIX>
+__device__ __forceinline__ void lds_fft(cpx<T>* buf, int ld, int NB, const cpx<T>* __restrict__ tw) {
+  if constexpr (RADIX == 4) {
+    if constexpr (LOGN & 1) {
+      stockham_stage<T, LOGN, NBMAX, INV, 2, 0>(buf, ld, NB, tw);
+      stockham_from<T, LOGN, NBMAX, INV, 4, 1>(buf, ld, NB, tw);
+    } else {
+      stockham_from<T, LOGN, NBMAX, INV, 4, 0>(buf, ld, NB, tw);
+    }
+  } else {
+    static_assert(RADIX == 8, "radix 4 or 8");
+    if constexpr (LOGN % 3 == 1) {
+      stockham_stage<T, LOGN, NBMAX, INV, 2, 0>(buf, ld, NB, tw);
+      stockham_from<T, LOGN, NBMAX, INV, 8, 1>(buf, ld, NB, tw);
+    } else if constexpr (LOGN % 3 == 2) {
+      stockham_stage<T, LOGN, NBMAX, INV, 4, 0>(buf, ld, NB, tw);
+      stockham_from<T, LOGN, NBMAX, INV, 8, 2>(buf, ld, NB, tw);
+    } else {
+      stockham_from<T, LOGN, NBMAX, INV, 8, 0>(buf, ld, NB, tw);
+    }
+  }
+}
+
+// Sum of v over the block (fixed order: waves by shuffles, then the waves in
+// turn); red: NT / 64 doubles of LDS.  Every thread gets the total.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------------------------ bodies
+// Each transform is a device body over one block's tile (logical block lb of
+// one grid) using the LDS tile buf (and red, NT/64 doubles), shared by the
+// single-grid kernels and by the kernels that serve several grids in one
+// launch.
 
 // Rows of nx = 2^LOGN reals -> half spectra.  Block = R consecutive rows of
 // one plane (R even, R | ny), two rows per complex sequence.  Output
 // X[(plane * kxh + k) * ny + y].
-// If bsum is not NULL, block b also writes the float64 sum of its R rows to
-// bsum[b] (the plane means of the mean mode are then formed in float64).
-template <typename T, int LOGN, bool NTL>
-__global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
-                                             const cpx<T>* __restrict__ tw, double* __restrict__ bsum,
-                                             LayerSkip skip) {
+// If bsum is not NULL, block lb also writes the float64 sum of its R rows to
+// bsum[lb] (the plane means of the mean mode are then formed in float64).
+template <typename T, int LOGN, bool NTL, int TILE, int RADIX>
+__device__ __forceinline__ void x_r2c_body(cpx<T>* buf, double* red, int lb, const InSegments& seg,
+                                           cpx<T>* __restrict__ out, int ny, int R,
+                                           const cpx<T>* __restrict__ tw, double* __restrict__ bsum,
+                                           const LayerSkip& skip) {
   constexpr int N = 1 << LOGN;
-  constexpr int SEQ = r2c_seq<T>(N);
+  constexpr int SEQ = r2c_seq<T>(N, TILE);
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
-  __shared__ cpx<T> buf[SEQ * ld];
-  const size_t row0 = (size_t)blockIdx.x * R;
+  const size_t row0 = (size_t)lb * R;
   const size_t plane = row0 / ny;
   const int y0 = (int)(row0 - plane * ny);
   // a layer without plastic strain: its rows sum to zero, nothing to transform
   if (skip.zact && (int)plane < skip.nw && (int)(plane % skip.nz) >= *skip.zact) {
-    if (bsum && threadIdx.x == 0) bsum[blockIdx.x] = 0.0;
+    if (bsum && threadIdx.x == 0) bsum[lb] = 0.0;
     return;
   }
   const int sg = (seg.n > 1 && (int)plane >= seg.first[1]) ? 1 : 0;
@@ -203,23 +289,17 @@ __global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict
     }
   }
   if (bsum) {
-    __shared__ double red[NT];
     double acc = 0.0;
 #pragma unroll
     for (int u = 0; u < MV; ++u) {
       int i = threadIdx.x + u * NT;
       if (i < tot) acc += v[u].x + v[u].y;
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = NT / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) bsum[lb] = acc;
   }
   __syncthreads();
-  lds_fft<T, LOGN, SEQ, false>(buf, ld, R / 2, tw);
+  lds_fft<T, LOGN, SEQ, false, RADIX>(buf, ld, R / 2, tw);
   const int tot2 = kxh * R;
   for (int i = threadIdx.x; i < tot2; i += NT) {
     int k = i / R, yl = i - k * R;
@@ -246,16 +326,15 @@ __device__ __forceinline__ int xcd_block() {
 // with copies of it (never stored), so every load is unconditional: with
 // conditional loads the staging array was not kept in registers and went
 // through scratch memory, doubling the kernel's memory traffic.
-template <typename T, int LOGN, bool NTL>
-__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
-                                             int NP, int ldp, const cpx<T>* __restrict__ tw, LayerSkip skip) {
+template <typename T, int LOGN, bool NTL, int TILE, int RADIX>
+__device__ __forceinline__ void y_fwd_body(cpx<T>* buf, int lb, const cpx<T>* __restrict__ in,
+                                           cpx<T>* __restrict__ out, int kxh, int NP, int ldp,
+                                           const cpx<T>* __restrict__ tw, const LayerSkip& skip) {
   constexpr int N = 1 << LOGN;
-  constexpr int B = col_batch<T>(N);
+  constexpr int B = col_batch<T>(N, TILE);
   static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int ld = N + 1;
-  __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
-  const int lb = xcd_block();
   const int kx = lb / npb;
   const int p0 = (lb - kx * npb) * B;
   const int nb = min(B, NP - p0);
@@ -283,7 +362,7 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
     buf[(i >> LOGN) * ld + (i & (N - 1))] = v[u];
   }
   __syncthreads();
-  lds_fft<T, LOGN, B, false>(buf, ld, nb, tw);
+  lds_fft<T, LOGN, B, false, RADIX>(buf, ld, nb, tw);
   // consecutive lanes take consecutive planes of one ky: runs of nb elements
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
@@ -294,19 +373,18 @@ __global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx
 }
 
 // Inverse column transform: S[kx][ky][p] -> X[p][kx][y].
-template <typename T, int LOGN, bool NTL>
-__global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
-                                             int NP, int ldp, const cpx<T>* __restrict__ tw) {
+template <typename T, int LOGN, bool NTL, int TILE, int RADIX>
+__device__ __forceinline__ void y_inv_body(cpx<T>* buf, int lb, const cpx<T>* __restrict__ in,
+                                           cpx<T>* __restrict__ out, int kxh, int NP, int ldp,
+                                           const cpx<T>* __restrict__ tw) {
   constexpr int N = 1 << LOGN;
-  constexpr int B = col_batch<T>(N);
+  constexpr int B = col_batch<T>(N, TILE);
+  static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int ld = N + 1;
-  __shared__ cpx<T> buf[B * ld];
   const int npb = (NP + B - 1) / B;
-  const int lb = xcd_block();
   const int kx = lb / npb;
   const int p0 = (lb - kx * npb) * B;
   const int nb = min(B, NP - p0);
-  static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int MV = B * N / NT;
   // consecutive lanes read consecutive planes of one ky (runs of nb
   // elements); lanes past the last plane repeat it into unused tile rows
@@ -325,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
     buf[b * ld + ky] = v[u];
   }
   __syncthreads();
-  lds_fft<T, LOGN, B, true>(buf, ld, nb, tw);
+  lds_fft<T, LOGN, B, true, RADIX>(buf, ld, nb, tw);
 #pragma unroll
   for (int u = 0; u < MV; ++u) {
     int i = threadIdx.x + u * NT;
@@ -337,19 +415,19 @@ __global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx
 // Half spectra -> rows of nx = 2^LOGN reals, two rows per complex transform.
 // Plane p of the input goes to the output segment that contains it.
 // If padd is not NULL, padd[plane] (float64) is added to every output value
-// of that plane (the mean mode computed in float64).
-// NTS: the outputs (without the epilogue) are stored as streaming writes.
-template <typename T, int LOGN, bool NTS>
-__global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
-                                             double scale, const cpx<T>* __restrict__ tw,
-                                             const double* __restrict__ padd, ResidEpilogue ep) {
+// of that plane (the mean mode computed in float64).  nts: the outputs
+// (without the epilogue) are stored as streaming writes.
+template <typename T, int LOGN, int TILE, int RADIX>
+__device__ __forceinline__ void x_c2r_body(cpx<T>* buf, double* red, int lb, const cpx<T>* __restrict__ in,
+                                           const OutSegments& seg, int ny, int R, double scale,
+                                           const cpx<T>* __restrict__ tw, const double* __restrict__ padd,
+                                           const ResidEpilogue& ep, bool nts) {
   constexpr int N = 1 << LOGN;
-  constexpr int SEQ = c2r_seq<T>(N);
+  constexpr int SEQ = c2r_seq<T>(N, TILE);
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
   constexpr int nyq = N / 2;
-  __shared__ cpx<T> buf[SEQ * ld];
-  const size_t row0 = (size_t)blockIdx.x * R;
+  const size_t row0 = (size_t)lb * R;
   const int plane = (int)(row0 / ny);
   const int y0 = (int)(row0 - (size_t)plane * ny);
   const int hp = R / 2;                  // a power of two (R = ny or 2 SEQ)
@@ -380,7 +458,7 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
     }
   }
   __syncthreads();
-  lds_fft<T, LOGN, SEQ, true>(buf, ld, hp, tw);
+  lds_fft<T, LOGN, SEQ, true, RADIX>(buf, ld, hp, tw);
   int s = 0;
   while (s + 1 < seg.n && plane >= seg.first[s + 1]) ++s;
   double* dst = seg.ptr[s] + ((size_t)(plane - seg.first[s]) * ny + y0) * N;
@@ -403,7 +481,7 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
       v2d o;
       if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
       else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
-      if constexpr (NTS) __builtin_nontemporal_store(o, reinterpret_cast<v2d*>(d2 + i));
+      if (nts) __builtin_nontemporal_store(o, reinterpret_cast<v2d*>(d2 + i));
       else *reinterpret_cast<v2d*>(d2 + i) = o;
     }
     return;
@@ -428,37 +506,160 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
       s1 += f.x * (rr.x - f.x) + f.y * (rr.y - f.y);
     }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    s0 += __shfl_down(s0, o, 64);
-    s1 += __shfl_down(s1, o, 64);
-  }
-  __shared__ double red[2][NT / 64];
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = s0;
-    red[1][threadIdx.x >> 6] = s1;
-  }
-  __syncthreads();
+  const double a = block_sum(s0, red);
+  const double c = block_sum(s1, red);
   if (threadIdx.x == 0) {
-    double a = 0.0, c = 0.0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; ++w) {
-      a += red[0][w];
-      c += red[1][w];
-    }
     const int cp = plane / ep.nz, z = plane - cp * ep.nz;
     const double wt = (cp < 3 ? 1.0 : 2.0) * (ep.wz ? ep.wz[z] : ((z == 0 || z == ep.nz - 1) ? 0.5 : 1.0));
-    ep.part[2 * blockIdx.x] = wt * a;
-    ep.part[2 * blockIdx.x + 1] = wt * c;
+    ep.part[2 * lb] = wt * a;
+    ep.part[2 * lb + 1] = wt * c;
   }
 }
 
+// ---------------------------------------------------- single-grid kernels
+template <typename T, int LOGN, int TILE>
+__host__ __device__ constexpr int r2c_lds_elems() {
+  return r2c_seq<T>(1 << LOGN, TILE) * ((1 << LOGN) + 1);
+}
+template <typename T, int LOGN, int TILE>
+__host__ __device__ constexpr int c2r_lds_elems() {
+  return c2r_seq<T>(1 << LOGN, TILE) * ((1 << LOGN) + 1);
+}
+template <typename T, int LOGN, int TILE>
+__host__ __device__ constexpr int col_lds_elems() {
+  return col_batch<T>(1 << LOGN, TILE) * ((1 << LOGN) + 1);
+}
+
+template <typename T, int LOGN, bool NTL, int TILE, int RADIX>
+__global__ __launch_bounds__(NT) void k_x_r2c(InSegments seg, cpx<T>* __restrict__ out, int ny, int R,
+                                             const cpx<T>* __restrict__ tw, double* __restrict__ bsum,
+                                             LayerSkip skip) {
+  __shared__ cpx<T> buf[r2c_lds_elems<T, LOGN, TILE>()];
+  __shared__ double red[NT / 64];
+  x_r2c_body<T, LOGN, NTL, TILE, RADIX>(buf, red, blockIdx.x, seg, out, ny, R, tw, bsum, skip);
+}
+
+template <typename T, int LOGN, bool NTL, int TILE, int RADIX>
+__global__ __launch_bounds__(NT) void k_y_fwd(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
+                                             int NP, int ldp, const cpx<T>* __restrict__ tw, LayerSkip skip) {
+  __shared__ cpx<T> buf[col_lds_elems<T, LOGN, TILE>()];
+  y_fwd_body<T, LOGN, NTL, TILE, RADIX>(buf, xcd_block(), in, out, kxh, NP, ldp, tw, skip);
+}
+
+template <typename T, int LOGN, bool NTL, int TILE, int RADIX>
+__global__ __launch_bounds__(NT) void k_y_inv(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int kxh,
+                                             int NP, int ldp, const cpx<T>* __restrict__ tw) {
+  __shared__ cpx<T> buf[col_lds_elems<T, LOGN, TILE>()];
+  y_inv_body<T, LOGN, NTL, TILE, RADIX>(buf, xcd_block(), in, out, kxh, NP, ldp, tw);
+}
+
+template <typename T, int LOGN, int TILE, int RADIX>
+__global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, OutSegments seg, int ny, int R,
+                                             double scale, const cpx<T>* __restrict__ tw,
+                                             const double* __restrict__ padd, ResidEpilogue ep, int nts) {
+  __shared__ cpx<T> buf[c2r_lds_elems<T, LOGN, TILE>()];
+  __shared__ double red[NT / 64];
+  x_c2r_body<T, LOGN, TILE, RADIX>(buf, red, blockIdx.x, in, seg, ny, R, scale, tw, padd, ep, nts != 0);
+}
+
+// --------------------------------------------- kernels over several grids
+// One launch serves the grids of an XformBatch (transform lengths up to
+// 2^XFORM_BATCH_MAX_LOGN, default tile and radix 4): block b belongs to grid
+// c with first[c] <= b < first[c + 1] and runs that grid's body with the
+// block index b - first[c]; the tile lives in dynamic LDS sized by the host
+// for the largest grid.  A grid's results are those of its own launch.
+extern __shared__ double2 fvim_dyn_lds[];
+
+__device__ __forceinline__ int batch_grid(const XformBatch& b, int blk) {
+  int c = 0;
+  while (c + 1 < b.n && blk >= b.first[c + 1]) ++c;
+  return c;
+}
+
+#define FVIM_BATCH_LOGN_SWITCH(logn, CALL) \
+  switch (logn) {                          \
+    case 2: CALL(2); break;                \
+    case 3: CALL(3); break;                \
+    case 4: CALL(4); break;                \
+    case 5: CALL(5); break;                \
+    case 6: CALL(6); break;                \
+    case 7: CALL(7); break;                \
+    case 8: CALL(8); break;                \
+    case 9: CALL(9); break;                \
+  }
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_x_r2c_batch(XformBatch b) {
+  __shared__ double red[NT / 64];
+  const int c = batch_grid(b, blockIdx.x);
+  const int lb = blockIdx.x - b.first[c];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(fvim_dyn_lds);
+  cpx<T>* out = static_cast<cpx<T>*>(b.out[c]);
+  const cpx<T>* tw = static_cast<const cpx<T>*>(b.tw[c]);
+#define CALL(L) x_r2c_body<T, L, false, 1, 4>(buf, red, lb, b.iseg[c], out, b.ny[c], b.R[c], tw, b.bsum[c], LayerSkip{})
+  FVIM_BATCH_LOGN_SWITCH(b.logn[c], CALL)
+#undef CALL
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_y_fwd_batch(XformBatch b) {
+  const int g = xcd_block();
+  const int c = batch_grid(b, g);
+  const int lb = g - b.first[c];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(fvim_dyn_lds);
+  const cpx<T>* in = static_cast<const cpx<T>*>(b.in[c]);
+  cpx<T>* out = static_cast<cpx<T>*>(b.out[c]);
+  const cpx<T>* tw = static_cast<const cpx<T>*>(b.tw[c]);
+#define CALL(L) y_fwd_body<T, L, false, 1, 4>(buf, lb, in, out, b.kxh[c], b.NP[c], b.ldp[c], tw, LayerSkip{})
+  FVIM_BATCH_LOGN_SWITCH(b.logn[c], CALL)
+#undef CALL
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_y_inv_batch(XformBatch b) {
+  const int g = xcd_block();
+  const int c = batch_grid(b, g);
+  const int lb = g - b.first[c];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(fvim_dyn_lds);
+  const cpx<T>* in = static_cast<const cpx<T>*>(b.in[c]);
+  cpx<T>* out = static_cast<cpx<T>*>(b.out[c]);
+  const cpx<T>* tw = static_cast<const cpx<T>*>(b.tw[c]);
+#define CALL(L) y_inv_body<T, L, false, 1, 4>(buf, lb, in, out, b.kxh[c], b.NP[c], b.ldp[c], tw)
+  FVIM_BATCH_LOGN_SWITCH(b.logn[c], CALL)
+#undef CALL
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_x_c2r_batch(XformBatch b) {
+  __shared__ double red[NT / 64];
+  const int c = batch_grid(b, blockIdx.x);
+  const int lb = blockIdx.x - b.first[c];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(fvim_dyn_lds);
+  const cpx<T>* in = static_cast<const cpx<T>*>(b.in[c]);
+  const cpx<T>* tw = static_cast<const cpx<T>*>(b.tw[c]);
+#define CALL(L) \
+  x_c2r_body<T, L, 1, 4>(buf, red, lb, in, b.oseg[c], b.ny[c], b.R[c], 1.0, tw, b.padd[c], ResidEpilogue{}, b.nts[c] != 0)
+  FVIM_BATCH_LOGN_SWITCH(b.logn[c], CALL)
+#undef CALL
+}
+
+// -------------------------------------------------------------- launches
 // R of a row kernel launch: 2 SEQ rows, or the whole plane when it is shorter
 int rows_per_block(int seq, int ny) { return 2 * seq < ny ? 2 * seq : ny; }
 
-template <typename T>
-int cols_per_block(int ny) {
-  return col_batch<T>(ny);
+int ilog2(int n) { return 31 - __builtin_clz((unsigned)n); }
+
+bool fft_tunable(int logn) { return logn >= FFT_TUNE_MIN_LOGN && logn <= FFT_TUNE_MAX_LOGN; }
+
+// Runtime tile -> compile-time tile of a row kernel's SEQ (or a column
+// kernel's B) for a length 2^L.
+template <typename T, int L>
+int r2c_seq_rt(int tile) {
+  return tile == 0 ? r2c_seq<T>(1 << L, 0) : (tile == 2 ? r2c_seq<T>(1 << L, 2) : r2c_seq<T>(1 << L, 1));
+}
+template <typename T, int L>
+int c2r_seq_rt(int tile) {
+  return tile == 0 ? c2r_seq<T>(1 << L, 0) : (tile == 2 ? c2r_seq<T>(1 << L, 2) : c2r_seq<T>(1 << L, 1));
 }
 
 #define FVIM_LOGN_SWITCH(logn, CALL) \
@@ -477,27 +678,147 @@ int cols_per_block(int ny) {
     default: return hipErrorInvalidValue; \
   }
 
-int ilog2(int n) { return 31 - __builtin_clz((unsigned)n); }
+// Calls GO<TILE, RADIX>() of the launcher struct for the effective choice:
+// the six (tile, radix) variants exist for tunable lengths only.
+template <int L, typename F>
+hipError_t with_choice(FftChoice ch, F& f) {
+  if constexpr (L >= FFT_TUNE_MIN_LOGN && L <= FFT_TUNE_MAX_LOGN) {
+    if (ch.radix == 8) {
+      if (ch.tile == 0) return f.template go<L, 0, 8>();
+      if (ch.tile == 2) return f.template go<L, 2, 8>();
+      return f.template go<L, 1, 8>();
+    }
+    if (ch.tile == 0) return f.template go<L, 0, 4>();
+    if (ch.tile == 2) return f.template go<L, 2, 4>();
+  }
+  return f.template go<L, 1, 4>();
+}
+
+template <typename T>
+struct R2CLaunch {
+  const InSegments& seg;
+  cpx<T>* out;
+  int ny;
+  size_t nplanes;
+  const cpx<T>* tw;
+  hipStream_t st;
+  double* bsum;
+  bool stream_in;
+  const LayerSkip& skip;
+  template <int L, int TILE, int RADIX>
+  hipError_t go() {
+    const int R = rows_per_block(r2c_seq<T>(1 << L, TILE), ny);
+    const dim3 grid((unsigned)(nplanes * (size_t)ny / R));
+    if (stream_in)
+      hipLaunchKernelGGL((k_x_r2c<T, L, true, TILE, RADIX>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum, skip);
+    else
+      hipLaunchKernelGGL((k_x_r2c<T, L, false, TILE, RADIX>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum, skip);
+    return hipGetLastError();
+  }
+};
+
+template <typename T, bool FWD>
+struct ColLaunch {
+  const cpx<T>* in;
+  cpx<T>* out;
+  int kxh, NP, ldp;
+  const cpx<T>* tw;
+  hipStream_t st;
+  bool stream_in;
+  const LayerSkip& skip;
+  template <int L, int TILE, int RADIX>
+  hipError_t go() {
+    constexpr int B = col_batch<T>(1 << L, TILE);
+    const dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
+    if (FWD) {
+      if (stream_in)
+        hipLaunchKernelGGL((k_y_fwd<T, L, true, TILE, RADIX>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw, skip);
+      else
+        hipLaunchKernelGGL((k_y_fwd<T, L, false, TILE, RADIX>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw,
+                           skip);
+    } else {
+      if (stream_in)
+        hipLaunchKernelGGL((k_y_inv<T, L, true, TILE, RADIX>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw);
+      else
+        hipLaunchKernelGGL((k_y_inv<T, L, false, TILE, RADIX>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw);
+    }
+    return hipGetLastError();
+  }
+};
+
+template <typename T>
+struct C2RLaunch {
+  const cpx<T>* in;
+  const OutSegments& seg;
+  int ny;
+  size_t nplanes;
+  double scale;
+  const cpx<T>* tw;
+  hipStream_t st;
+  const double* padd;
+  const ResidEpilogue& ep;
+  bool stream_out;
+  template <int L, int TILE, int RADIX>
+  hipError_t go() {
+    const int R = rows_per_block(c2r_seq<T>(1 << L, TILE), ny);
+    const dim3 grid((unsigned)(nplanes * (size_t)ny / R));
+    hipLaunchKernelGGL((k_x_c2r<T, L, TILE, RADIX>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep,
+                       stream_out ? 1 : 0);
+    return hipGetLastError();
+  }
+};
+
+template <typename T, bool R2C>
+struct SeqOf {
+  template <int L, int TILE, int RADIX>
+  hipError_t go() {
+    seq = R2C ? r2c_seq<T>(1 << L, TILE) : c2r_seq<T>(1 << L, TILE);
+    return hipSuccess;
+  }
+  int seq = 0;
+};
+
+template <typename T, bool R2C>
+int row_seq_of(int nx, FftChoice ch) {
+  SeqOf<T, R2C> f;
+  auto run = [&]() -> hipError_t {
+#define CALL(L) return with_choice<L>(ch, f)
+    FVIM_LOGN_SWITCH(ilog2(nx), CALL)
+#undef CALL
+    return hipErrorInvalidValue;
+  };
+  run();
+  return f.seq;
+}
 
 }  // namespace
 
+FftChoice fft_effective(int logn, FftChoice ch) {
+  if (!fft_tunable(logn) || (ch.radix != 4 && ch.radix != 8) || ch.tile < 0 || ch.tile > 2) return FftChoice{};
+  return ch;
+}
+
 template <typename T>
-int x_r2c_blocks_per_plane(int nx, int ny) {
-  return ny / rows_per_block(r2c_seq<T>(nx), ny);
+int x_r2c_blocks_per_plane(int nx, int ny, FftChoice ch) {
+  return ny / rows_per_block(row_seq_of<T, true>(nx, fft_effective(ilog2(nx), ch)), ny);
+}
+
+template <typename T>
+int x_r2c_max_blocks_per_plane(int nx, int ny) {
+  int m = 0;
+  for (int t = 0; t < 3; ++t) m = std::max(m, x_r2c_blocks_per_plane<T>(nx, ny, FftChoice{t, 4}));
+  return m;
 }
 
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
-                        hipStream_t st, double* bsum, bool stream_in, const LayerSkip& skip) {
+                        hipStream_t st, double* bsum, bool stream_in, const LayerSkip& skip, FftChoice ch) {
   if (seg.n < 1 || seg.n > 2 || seg.first[0] != 0) return hipErrorInvalidValue;
-  int R = rows_per_block(r2c_seq<T>(nx), ny);
-  dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L)                                                                                        \
-  if (stream_in) hipLaunchKernelGGL((k_x_r2c<T, L, true>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum, skip); \
-  else hipLaunchKernelGGL((k_x_r2c<T, L, false>), grid, dim3(NT), 0, st, seg, out, ny, R, tw, bsum, skip)
+  R2CLaunch<T> f{seg, out, ny, nplanes, tw, st, bsum, stream_in, skip};
+  ch = fft_effective(ilog2(nx), ch);
+#define CALL(L) return with_choice<L>(ch, f)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
-  return hipGetLastError();
 }
 
 template <typename T>
@@ -507,85 +828,156 @@ hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t np
   seg.n = 1;
   seg.first[0] = seg.first[1] = 0;
   seg.ptr[0] = seg.ptr[1] = in;
-  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum, stream_in, LayerSkip{});
+  return launch_x_r2c<T>(seg, out, nx, ny, nplanes, tw, st, bsum, stream_in, LayerSkip{}, FftChoice{});
 }
 
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st, bool stream_in, const LayerSkip& skip) {
+                        hipStream_t st, bool stream_in, const LayerSkip& skip, FftChoice ch) {
   if (ldp < NP) return hipErrorInvalidValue;
-  int B = cols_per_block<T>(ny);
-  dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L)                                                                                       \
-  if (stream_in) hipLaunchKernelGGL((k_y_fwd<T, L, true>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw, skip); \
-  else hipLaunchKernelGGL((k_y_fwd<T, L, false>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw, skip)
+  ColLaunch<T, true> f{in, out, kxh, NP, ldp, tw, st, stream_in, skip};
+  ch = fft_effective(ilog2(ny), ch);
+#define CALL(L) return with_choice<L>(ch, f)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
-  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st, bool stream_in) {
+                        hipStream_t st, bool stream_in, FftChoice ch) {
   if (ldp < NP) return hipErrorInvalidValue;
-  int B = cols_per_block<T>(ny);
-  dim3 grid((unsigned)(kxh * ((NP + B - 1) / B)));
-#define CALL(L)                                                                                       \
-  if (stream_in) hipLaunchKernelGGL((k_y_inv<T, L, true>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw); \
-  else hipLaunchKernelGGL((k_y_inv<T, L, false>), grid, dim3(NT), 0, st, in, out, kxh, NP, ldp, tw)
+  const LayerSkip none{};
+  ColLaunch<T, false> f{in, out, kxh, NP, ldp, tw, st, stream_in, none};
+  ch = fft_effective(ilog2(ny), ch);
+#define CALL(L) return with_choice<L>(ch, f)
   FVIM_LOGN_SWITCH(ilog2(ny), CALL)
 #undef CALL
-  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd,
-                        const ResidEpilogue& ep, bool stream_out) {
+                        const ResidEpilogue& ep, bool stream_out, FftChoice ch) {
   // the epilogue reads its fields at the output's own offsets: one segment
   // holding the 6 nz strain planes from plane 0
   if (ep.x && (seg.n != 1 || seg.first[0] != 0 || !ep.part || ep.nz < 1 || nplanes != (size_t)6 * ep.nz))
     return hipErrorInvalidValue;
-  int R = rows_per_block(c2r_seq<T>(nx), ny);
-  dim3 grid((unsigned)(nplanes * (size_t)ny / R));
-#define CALL(L)                                                                                          \
-  if (stream_out) hipLaunchKernelGGL((k_x_c2r<T, L, true>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep); \
-  else hipLaunchKernelGGL((k_x_c2r<T, L, false>), grid, dim3(NT), 0, st, in, seg, ny, R, scale, tw, padd, ep)
+  C2RLaunch<T> f{in, seg, ny, nplanes, scale, tw, st, padd, ep, stream_out};
+  ch = fft_effective(ilog2(nx), ch);
+#define CALL(L) return with_choice<L>(ch, f)
   FVIM_LOGN_SWITCH(ilog2(nx), CALL)
 #undef CALL
-  return hipGetLastError();
 }
 
 template <typename T>
-int x_c2r_blocks(int nx, int ny, size_t nplanes) {
-  return (int)(nplanes * (size_t)ny / rows_per_block(c2r_seq<T>(nx), ny));
+int x_c2r_blocks(int nx, int ny, size_t nplanes, FftChoice ch) {
+  return (int)(nplanes * (size_t)ny / rows_per_block(row_seq_of<T, false>(nx, fft_effective(ilog2(nx), ch)), ny));
 }
-template int x_c2r_blocks<double>(int, int, size_t);
-template int x_c2r_blocks<float>(int, int, size_t);
 
-template hipError_t launch_x_r2c<double>(const double*, cpx<double>*, int, int, size_t, const cpx<double>*,
-                                         hipStream_t, double*, bool);
-template hipError_t launch_x_r2c<double>(const InSegments&, cpx<double>*, int, int, size_t,
-                                         const cpx<double>*, hipStream_t, double*, bool, const LayerSkip&);
-template hipError_t launch_x_r2c<float>(const InSegments&, cpx<float>*, int, int, size_t, const cpx<float>*,
-                                        hipStream_t, double*, bool, const LayerSkip&);
-template hipError_t launch_x_r2c<float>(const double*, cpx<float>*, int, int, size_t, const cpx<float>*,
-                                        hipStream_t, double*, bool);
-template int x_r2c_blocks_per_plane<double>(int, int);
-template int x_r2c_blocks_per_plane<float>(int, int);
-template hipError_t launch_y_fwd<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
-                                         const cpx<double>*, hipStream_t, bool, const LayerSkip&);
-template hipError_t launch_y_fwd<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
-                                        hipStream_t, bool, const LayerSkip&);
-template hipError_t launch_y_inv<double>(const cpx<double>*, cpx<double>*, int, int, int, int,
-                                         const cpx<double>*, hipStream_t, bool);
-template hipError_t launch_y_inv<float>(const cpx<float>*, cpx<float>*, int, int, int, int, const cpx<float>*,
-                                        hipStream_t, bool);
-template hipError_t launch_x_c2r<double>(const cpx<double>*, const OutSegments&, int, int, size_t, double,
-                                         const cpx<double>*, hipStream_t, const double*,
-                                         const ResidEpilogue&, bool);
-template hipError_t launch_x_c2r<float>(const cpx<float>*, const OutSegments&, int, int, size_t, double,
-                                        const cpx<float>*, hipStream_t, const double*,
-                                         const ResidEpilogue&, bool);
+template <typename T>
+int x_c2r_max_blocks(int nx, int ny, size_t nplanes) {
+  int m = 0;
+  for (int t = 0; t < 3; ++t) m = std::max(m, x_c2r_blocks<T>(nx, ny, nplanes, FftChoice{t, 4}));
+  return m;
+}
+
+// ------------------------------------------------- launches over grids
+namespace {
+
+// block count and LDS bytes of one grid's part of a batched launch (the
+// default tile), and its rows per block (row kernels)
+template <typename T>
+struct BatchGeom {
+  int blocks = 0, R = 0;
+  size_t lds = 0;
+};
+
+template <typename T>
+BatchGeom<T> geom_r2c(int logn, int ny, int nplanes) {
+  BatchGeom<T> g;
+  const int n = 1 << logn;
+  const int seq = r2c_seq<T>(n, 1);
+  g.R = rows_per_block(seq, ny);
+  g.blocks = nplanes * ny / g.R;
+  g.lds = (size_t)seq * (n + 1) * sizeof(cpx<T>);
+  return g;
+}
+template <typename T>
+BatchGeom<T> geom_c2r(int logn, int ny, int nplanes) {
+  BatchGeom<T> g;
+  const int n = 1 << logn;
+  const int seq = c2r_seq<T>(n, 1);
+  g.R = rows_per_block(seq, ny);
+  g.blocks = nplanes * ny / g.R;
+  g.lds = (size_t)seq * (n + 1) * sizeof(cpx<T>);
+  return g;
+}
+template <typename T>
+BatchGeom<T> geom_col(int logn, int kxh, int NP) {
+  BatchGeom<T> g;
+  const int n = 1 << logn;
+  const int B = col_batch<T>(n, 1);
+  g.blocks = kxh * ((NP + B - 1) / B);
+  g.lds = (size_t)B * (n + 1) * sizeof(cpx<T>);
+  return g;
+}
+
+}  // namespace
+
+// kind: 0 x_r2c, 1 y_fwd, 2 y_inv, 3 x_c2r.  The host fills every grid's
+// fields but first[]; logn is the transform length of the kernel (nx for
+// the row kernels, ny for the column kernels), nplanes[c] its plane count.
+template <typename T>
+hipError_t launch_xform_batch(int kind, XformBatch& b, hipStream_t st) {
+  if (b.n < 1 || b.n > XFORM_BATCH_MAX) return hipErrorInvalidValue;
+  size_t lds = 0;
+  b.first[0] = 0;
+  for (int c = 0; c < b.n; ++c) {
+    if (b.logn[c] < 2 || b.logn[c] > XFORM_BATCH_MAX_LOGN) return hipErrorInvalidValue;
+    BatchGeom<T> g = kind == 0 ? geom_r2c<T>(b.logn[c], b.ny[c], b.NP[c])
+                     : kind == 3 ? geom_c2r<T>(b.logn[c], b.ny[c], b.NP[c])
+                                 : geom_col<T>(b.logn[c], b.kxh[c], b.NP[c]);
+    b.R[c] = g.R;
+    b.first[c + 1] = b.first[c] + g.blocks;
+    lds = std::max(lds, g.lds);
+  }
+  const dim3 grid((unsigned)b.first[b.n]);
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(k_x_r2c_batch<T>, grid, dim3(NT), lds, st, b); break;
+    case 1: hipLaunchKernelGGL(k_y_fwd_batch<T>, grid, dim3(NT), lds, st, b); break;
+    case 2: hipLaunchKernelGGL(k_y_inv_batch<T>, grid, dim3(NT), lds, st, b); break;
+    case 3: hipLaunchKernelGGL(k_x_c2r_batch<T>, grid, dim3(NT), lds, st, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// blocks per plane of the batched x_r2c (the float32 mean-mode sums)
+template <typename T>
+int x_r2c_batch_blocks_per_plane(int nx, int ny) {
+  return ny / rows_per_block(r2c_seq<T>(nx, 1), ny);
+}
+
+#define FVIM_INST(T)                                                                                            \
+  template int x_r2c_blocks_per_plane<T>(int, int, FftChoice);                                                  \
+  template int x_r2c_max_blocks_per_plane<T>(int, int);                                                         \
+  template int x_r2c_batch_blocks_per_plane<T>(int, int);                                                       \
+  template hipError_t launch_x_r2c<T>(const InSegments&, cpx<T>*, int, int, size_t, const cpx<T>*, hipStream_t, \
+                                      double*, bool, const LayerSkip&, FftChoice);                              \
+  template hipError_t launch_x_r2c<T>(const double*, cpx<T>*, int, int, size_t, const cpx<T>*, hipStream_t,     \
+                                      double*, bool);                                                           \
+  template hipError_t launch_y_fwd<T>(const cpx<T>*, cpx<T>*, int, int, int, int, const cpx<T>*, hipStream_t,   \
+                                      bool, const LayerSkip&, FftChoice);                                       \
+  template hipError_t launch_y_inv<T>(const cpx<T>*, cpx<T>*, int, int, int, int, const cpx<T>*, hipStream_t,   \
+                                      bool, FftChoice);                                                         \
+  template hipError_t launch_x_c2r<T>(const cpx<T>*, const OutSegments&, int, int, size_t, double,              \
+                                      const cpx<T>*, hipStream_t, const double*, const ResidEpilogue&, bool,    \
+                                      FftChoice);                                                               \
+  template int x_c2r_blocks<T>(int, int, size_t, FftChoice);                                                    \
+  template int x_c2r_max_blocks<T>(int, int, size_t);                                                           \
+  template hipError_t launch_xform_batch<T>(int, XformBatch&, hipStream_t);
+FVIM_INST(double)
+FVIM_INST(float)
+#undef FVIM_INST
 
 }  // namespace fvim

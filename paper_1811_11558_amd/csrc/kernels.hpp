@@ -28,6 +28,17 @@ struct LayerSkip {
   const int* zact;
   int nz, nw;
 };
+// Launch choice of a transform kernel: the LDS tile (0: half the default,
+// 1: the default, 2: twice) and the radix of the Stockham stages (4 or 8).
+// Only lengths 2^FFT_TUNE_MIN_LOGN .. 2^FFT_TUNE_MAX_LOGN have the
+// alternatives; fft_effective gives what a launch of length 2^logn runs.
+struct FftChoice {
+  int tile = 1;
+  int radix = 4;
+};
+constexpr int FFT_TUNE_MIN_LOGN = 5, FFT_TUNE_MAX_LOGN = 10;
+FftChoice fft_effective(int logn, FftChoice ch);
+
 // bsum (optional): float64 sum of the rows of each block, blocks of a plane
 // consecutive (x_r2c_blocks_per_plane of them).  stream_in: the launch reads
 // its input for the last time with streaming (non-temporal) loads (see
@@ -35,20 +46,24 @@ struct LayerSkip {
 template <typename T>
 hipError_t launch_x_r2c(const InSegments& seg, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum = nullptr, bool stream_in = false,
-                        const LayerSkip& skip = LayerSkip{});
+                        const LayerSkip& skip = LayerSkip{}, FftChoice ch = FftChoice{});
 template <typename T>
 hipError_t launch_x_r2c(const double* in, cpx<T>* out, int nx, int ny, size_t nplanes, const cpx<T>* tw,
                         hipStream_t st, double* bsum = nullptr, bool stream_in = false);
 template <typename T>
-int x_r2c_blocks_per_plane(int nx, int ny);
+int x_r2c_blocks_per_plane(int nx, int ny, FftChoice ch = FftChoice{});
+// the most blocks per plane any choice gives (buffers sized for tuning)
+template <typename T>
+int x_r2c_max_blocks_per_plane(int nx, int ny);
 // Column transforms between X[p][kx][y] (p < NP) and the mode-major
 // S[kx][ky][ldp] (record stride ldp >= NP; the padding is not touched).
 template <typename T>
 hipError_t launch_y_fwd(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st, bool stream_in = false, const LayerSkip& skip = LayerSkip{});
+                        hipStream_t st, bool stream_in = false, const LayerSkip& skip = LayerSkip{},
+                        FftChoice ch = FftChoice{});
 template <typename T>
 hipError_t launch_y_inv(const cpx<T>* in, cpx<T>* out, int ny, int kxh, int NP, int ldp, const cpx<T>* tw,
-                        hipStream_t st, bool stream_in = false);
+                        hipStream_t st, bool stream_in = false, FftChoice ch = FftChoice{});
 // Record stride of a mode-major spectrum of np planes: a whole number of
 // 128-byte lines, so every mode's record starts on a line.
 template <typename T>
@@ -76,10 +91,43 @@ struct ResidEpilogue {
 template <typename T>
 hipError_t launch_x_c2r(const cpx<T>* in, const OutSegments& seg, int nx, int ny, size_t nplanes,
                         double scale, const cpx<T>* tw, hipStream_t st, const double* padd = nullptr,
-                        const ResidEpilogue& ep = ResidEpilogue{}, bool stream_out = false);
+                        const ResidEpilogue& ep = ResidEpilogue{}, bool stream_out = false,
+                        FftChoice ch = FftChoice{});
 // blocks of a launch_x_c2r over nplanes planes (partial-sum pairs it writes)
 template <typename T>
-int x_c2r_blocks(int nx, int ny, size_t nplanes);
+int x_c2r_blocks(int nx, int ny, size_t nplanes, FftChoice ch = FftChoice{});
+template <typename T>
+int x_c2r_max_blocks(int nx, int ny, size_t nplanes);
+
+// One launch of a transform kernel over several grids (up to
+// XFORM_BATCH_MAX, lengths up to 2^XFORM_BATCH_MAX_LOGN), each with the
+// default choice of its length: the grids' parameters travel as the kernel
+// argument.  logn: log2 of the kernel's transform length (nx for the row
+// kernels, ny for the column kernels); NP: planes (row kernels: planes of
+// ny rows; column kernels: planes NP with record stride ldp); R and first
+// are filled by launch_xform_batch.  Row kernels use ny, iseg / oseg, tw,
+// bsum (x_r2c, may be NULL), padd and nts (x_c2r); column kernels use in,
+// out, kxh, NP, ldp, tw.
+constexpr int XFORM_BATCH_MAX = 8, XFORM_BATCH_MAX_LOGN = 9;
+struct XformBatch {
+  int n;
+  int first[XFORM_BATCH_MAX + 1];
+  int logn[XFORM_BATCH_MAX];
+  int ny[XFORM_BATCH_MAX], R[XFORM_BATCH_MAX], NP[XFORM_BATCH_MAX];
+  int kxh[XFORM_BATCH_MAX], ldp[XFORM_BATCH_MAX], nts[XFORM_BATCH_MAX];
+  const void* in[XFORM_BATCH_MAX];
+  void* out[XFORM_BATCH_MAX];
+  const void* tw[XFORM_BATCH_MAX];
+  double* bsum[XFORM_BATCH_MAX];
+  const double* padd[XFORM_BATCH_MAX];
+  InSegments iseg[XFORM_BATCH_MAX];
+  OutSegments oseg[XFORM_BATCH_MAX];
+};
+// kind: 0 x_r2c, 1 y_fwd, 2 y_inv, 3 x_c2r
+template <typename T>
+hipError_t launch_xform_batch(int kind, XformBatch& b, hipStream_t st);
+template <typename T>
+int x_r2c_batch_blocks_per_plane(int nx, int ny);
 
 // Per-mode depth pass.  Input spectra (unnormalised DFTs) in mode-major
 // layout in[mode][ld_in]: the plastic strain as [6][nz] at offset 0 (if

@@ -993,7 +993,7 @@ static int residual_enqueue(fvim_ctx* c, PlastBufs& pb, const double* x, double*
   }
   const void* key[SolverWork::NKEY] = {x, F, Fo, pb.dT, w->vol, w->rpart, w->layers, c->bufA, c->bufB, c->k0buf,
                                        (const void*)(intptr_t)(p64 + 2),
-                                       (const void*)(intptr_t)(c->depth_cfg + 16),
+                                       (const void*)(intptr_t)(c->depth_cfg + 16 + ((intptr_t)fft_pack_all(c) << 8)),
                                        (const void*)(intptr_t)(c->streaming + 8)};
   for (auto& r : w->rg)
     if (r.ex && std::equal(key, key + SolverWork::NKEY, r.key)) {

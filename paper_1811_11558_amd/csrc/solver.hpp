@@ -5,9 +5,11 @@
 
 #include <cstddef>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/fvim.h"
+#include "kernels.hpp"
 
 namespace fvim {
 struct SolverWork;
@@ -47,6 +49,11 @@ struct fvim_ctx {
   // tuning: depth-pass configuration id (-1 = default for nz), and a request
   // to time every candidate on the next operator call
   int depth_cfg = -1;
+  // launch choices of the four transform kernels (x_r2c, y_fwd, y_inv,
+  // x_c2r) in float64 [0] and float32 [1] (default tile, radix 4 unless
+  // tuned or set)
+  fvim::FftChoice fft[2][4];
+  std::string arch;              // gcnArchName of the device (tuning records)
   // set by the solvers of the FP32_REFINED mode for the applications that
   // must be float64 (refinement phase, right-hand sides, surface corrections)
   int force_fp64 = 0;
@@ -86,6 +93,11 @@ int operator_reserve(fvim_ctx* c, const double* eps_p, const double* traction, d
 int operator_apply_resid(fvim_ctx* c, const double* eps_p, const double* traction, const double* x,
                          const double* Fo, double* R, double* part, int* nparts, const int* zact);
 int operator_resid_parts(const fvim_grid& g);
+// The context's transform choices of precision index prec (0 float64, 1
+// float32) packed as FVIM_OPT_FFT_CONFIG encodes them; fft_pack_all packs
+// both precisions (a key that changes whenever any choice does).
+int fft_pack(const fvim_ctx* c, int prec);
+int fft_pack_all(const fvim_ctx* c);
 void solver_release(fvim_ctx* c);
 size_t solver_footprint(const fvim_grid* g, size_t V);
 void friction_release(fvim_ctx* c);

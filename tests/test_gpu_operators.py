@@ -267,9 +267,10 @@ BATCH = [(16, 16, 9, 1.0, 1.0, 0.3), (32, 16, 16, 1.0, 0.5, 0.25), (64, 64, 33, 
 
 
 def test_batched_operator_uneven_grids():
-    """Four grids of different sizes in one batched application: each result
-    matches the oracle and the context's own application (the batch uses one
-    depth layout for all, so only the order of the depth sums can differ)."""
+    """Four grids of different sizes in one batched application (their
+    transforms in shared launches): each result matches the oracle and the
+    context's own application (the batch uses one depth layout for all, so
+    only the order of the depth sums can differ)."""
     from paper_1811_11558_amd import operator_apply_batch
     dev = torch.device("cuda")
     ctxs, eps, ts, refs, own = [], [], [], [], []
@@ -365,3 +366,93 @@ def test_full_size_sampled_modes(nx, ny, nz, prec, bound):
     _say("full-size sampled-mode rel err", nx, ny, nz, prec, err)
     assert err <= bound, err
     ctx.close()
+
+
+FFT_GRIDS = [(32, 64, 6, 1.0, 1.0, 0.25), (256, 128, 4, 1.0, 0.5, 0.2), (1024, 32, 3, 2.0, 1.0, 0.25),
+             (64, 1024, 3, 1.0, 2.0, 0.25), (512, 512, 2, 1.0, 1.0, 0.25)]
+FFT_CHOICES = [(t, r) for r in (4, 8) for t in (0, 1, 2)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,lx,ly,lz", FFT_GRIDS)
+def test_every_fft_choice_matches_oracle(nx, ny, nz, lx, ly, lz):
+    """Every launch choice of the four transform kernels (half, default and
+    double LDS tile; radix-4 and radix-8 stages), uniform and mixed, gives
+    the oracle's fields (float64 to 1e-11, float32 to 2e-6) on grids whose
+    lengths span the tunable range 32 .. 1024."""
+    g = grid_dict(nx, ny, nz, lx, ly, lz)
+    e = filtered_eigenstrain(g, seed=nx + ny, decay=0.5 * lz)
+    t = filtered_traction(g, seed=nz + 5)
+    ref = ora.apply(g, E, NU, eps_p=e, traction=t)
+    dev = torch.device("cuda")
+    ed, td = torch.from_numpy(e).to(dev), torch.from_numpy(t).to(dev)
+    cfgs = [[ch] * 4 for ch in FFT_CHOICES] + [[(0, 8), (2, 4), (1, 8), (2, 8)], [(2, 8), (0, 8), (0, 4), (1, 8)]]
+    for prec, bound in (("fp64", TOL), ("fp32_refined", 2e-6)):
+        c = _ctx(g, precision=prec)
+        for cfg in cfgs:
+            c.set_fft_config(cfg)
+            out = c.operator_apply(ed, td, want=("strain", "surf_u3"))
+            torch.cuda.synchronize()
+            errs = [_rel(out[k].cpu().numpy(), ref[k]) for k in ("strain", "surf_u3")]
+            _say("fft choice", (nx, ny, nz), prec, cfg, errs)
+            assert max(errs) <= bound, (cfg, errs)
+        c.close()
+
+
+def test_fft_tuner_picks_and_records_a_choice():
+    """FVIM_OPT_TUNE times the transform choices on the call's own data: the
+    result matches the oracle, and a second context of the same shape that
+    asks for tuning takes the recorded choices (and depth layout) and gives
+    bitwise the same fields."""
+    g = grid_dict(256, 128, 8, 1.0, 1.0, 0.25)
+    e = filtered_eigenstrain(g, seed=3)
+    t = filtered_traction(g, seed=4)
+    ref = ora.apply(g, E, NU, eps_p=e, traction=t)
+    dev = torch.device("cuda")
+    ed, td = torch.from_numpy(e).to(dev), torch.from_numpy(t).to(dev)
+    c1 = _ctx(g)
+    c1.tune()
+    o1 = c1.operator_apply(ed, td, want=("strain",))["strain"]
+    cfg1, d1 = c1.fft_config(), c1.get_option(c1.OPT_DEPTH_CONFIG)
+    c2 = _ctx(g)
+    c2.tune()
+    o2 = c2.operator_apply(ed, td, want=("strain",))["strain"]
+    torch.cuda.synchronize()
+    _say("tuned", cfg1, d1)
+    assert c2.fft_config() == cfg1 and c2.get_option(c2.OPT_DEPTH_CONFIG) == d1
+    assert all(t_ in (0, 1, 2) and r in (4, 8) for t_, r in cfg1)
+    assert torch.equal(o1, o2)
+    assert _rel(o1.cpu().numpy(), ref["strain"]) <= TOL
+    c1.close()
+    c2.close()
+
+
+def test_batched_transforms_same_alone_and_in_a_batch():
+    """Eight small grids of different sizes share one launch per transform
+    stage, a ninth grid (1024 x 16) keeps its own transform launches: every
+    grid's fields are bitwise those of the same grid batched alone, and
+    match the oracle."""
+    from paper_1811_11558_amd import operator_apply_batch
+    dev = torch.device("cuda")
+    shapes = [(64, 64, 12), (32, 32, 8), (128, 128, 6), (64, 32, 8), (32, 64, 10), (64, 64, 4), (128, 64, 6),
+              (16, 16, 5), (1024, 16, 3)]
+    ctxs, eps, ts, refs = [], [], [], []
+    for i, (nx, ny, nz) in enumerate(shapes):
+        g = grid_dict(nx, ny, nz, 1.0, 1.0, 0.25)
+        e = filtered_eigenstrain(g, seed=40 + i)
+        t = filtered_traction(g, seed=60 + i)
+        refs.append(ora.apply(g, E, NU, eps_p=e, traction=t))
+        ctxs.append(_ctx(g))
+        eps.append(torch.from_numpy(e).to(dev))
+        ts.append(torch.from_numpy(t).to(dev))
+    got = operator_apply_batch(ctxs, eps, ts, want=("strain", "surf_u3"))
+    torch.cuda.synchronize()
+    for i in range(len(shapes)):
+        alone = operator_apply_batch([ctxs[i]], [eps[i]], [ts[i]], want=("strain", "surf_u3"))[0]
+        torch.cuda.synchronize()
+        for k in ("strain", "surf_u3"):
+            err = _rel(got[i][k].cpu().numpy(), refs[i][k])
+            _say("batched", shapes[i], k, err)
+            assert err <= TOL, (shapes[i], k, err)
+            assert torch.equal(got[i][k], alone[k]), (shapes[i], k)
+    for c in ctxs:
+        c.close()
