@@ -300,10 +300,23 @@ typedef struct {
                        /* traction T carries it (none at a zero load); 0: */
                        /* frictionless                                      */
   double q_ratio[2];
+  int coupling;        /* 0: Algorithm 1 (relaxation, or Anderson with      */
+                       /* anderson_m); 1: its fixed point G(x) = x on the   */
+                       /* surface correction x by Newton-Krylov: GMRES on   */
+                       /* (J_G - I) d = x - G(x) with J_G v formed by       */
+                       /* forward differences of G (one full pass each,     */
+                       /* started from the pass at x), steps halved until   */
+                       /* |G(x) - x| decreases; same stopping test and      */
+                       /* fixed point; inner solves always to tol_plastic   */
+                       /* and tol_contact; max_outer bounds Newton steps;   */
+                       /* adds 12 nx ny nz + (coupling_krylov + 10) nx ny   */
+                       /* doubles                                           */
+  int coupling_krylov; /* GMRES steps per Newton step, 1..30 (0 = 10)       */
 } fvim_ep_opts;
 
 typedef struct {
-  int outer_iters, plastic_iters, contact_iters, r_evals;
+  int outer_iters;     /* Algorithm 1 passes, or Newton steps (coupling 1)  */
+  int plastic_iters, contact_iters, r_evals;
   double outer_err, plastic_res;
   double kkt;          /* KKT certificate of the step's last contact solve   */
                        /* (fvim_contact_info.kkt_residual, on the surface   */

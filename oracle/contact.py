@@ -50,6 +50,9 @@ def contact_solve(h, W, grid, E, nu, tol=1e-14, max_iter=5000, p0=None):
     n = nx * ny
     dA = grid['lx'] * grid['ly'] / n
     sym = surface_compliance_symbol(grid, E, nu)
+    # diagonal of the compliance matrix: the surface displacement under a
+    # unit point force at its own point, the mean of the symbol over modes
+    m_diag = float(np.mean(sym))
     if p0 is None or not np.any(p0):
         p = np.full((ny, nx), W / (n * dA))
     else:
@@ -65,7 +68,8 @@ def contact_solve(h, W, grid, E, nu, tol=1e-14, max_iter=5000, p0=None):
         g = apply_compliance(p, sym) - h
         g = g - g[Ic].mean()
         G = np.sum(g[Ic] ** 2)
-        t = np.where(Ic, g + (delta * G / G_old) * t, 0.0)
+        beta = delta * G / G_old if G_old > 0 else 0.0
+        t = np.where(Ic, g + beta * t, 0.0)
         G_old = G
         r = apply_compliance(t, sym)
         r = r - r[Ic].mean()
@@ -77,7 +81,13 @@ def contact_solve(h, W, grid, E, nu, tol=1e-14, max_iter=5000, p0=None):
         Iol = (p == 0) & (g < 0)
         if np.any(Iol):
             delta = 0.0
-            p[Iol] = p[Iol] - tau * g[Iol]
+            # points that overlap the surface re-enter with a pressure
+            # proportional to their overlap; when the conjugate-gradient
+            # step vanishes (the gap is already uniform on the contact set,
+            # e.g. a set of one point) the published update would re-admit
+            # nothing, and the step of a point load, 1 / M_ii, is taken
+            step = tau if tau != 0.0 else 1.0 / m_diag
+            p[Iol] = p[Iol] - step * g[Iol]
         else:
             delta = 1.0
         p = p * (W / (dA * p.sum()))

@@ -221,3 +221,95 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
         infos.append({"outer_iters": k, "outer_err": float(err), "plastic": res['info'],
                       "contact": cinfo, "p": p, "history": hist})
     return infos
+
+
+def outer_map(grid, mat, H0, W, state, x, p0=None, tol_plastic=1e-13, tol_contact=1e-14, max_plastic=500,
+              max_contact=5000, solver="dfsane", k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0),
+              tol_friction=1e-13):
+    """One pass of Algorithm 1 as a map of the surface correction x: the
+    contact step on the modified surface H0 - x (warm-started from p0),
+    with friction the tangential step, the plasticity step for the traction
+    increment, and the surface displacement of N[C : d_eps_p] it produces.
+    Returns (G(x), aux) with aux the pass's pressure, traction, plasticity
+    result and contact record."""
+    E, nu = mat['E'], mat['nu']
+    p, _, cinfo = oc.contact_solve(H0 - x, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p0)
+    T = np.zeros_like(state['traction'])
+    T[2] = p
+    if mu_f > 0.0:
+        Q = np.asarray(q_ratio, dtype=float) * mu_f * W
+        T[:2], _ = fr.tangential_solve(grid, E, nu, p, Q, mu_f, tol=tol_friction)
+    res = plasticity(grid, mat, T - state['traction'], state, tol=tol_plastic, max_iter=max_plastic,
+                     solver=solver, k0_policy=k0_policy)
+    dU = ops.mindlin_apply(grid, E, nu, res['d_eps_p'], k0_policy=k0_policy)['surf_u3']
+    return dU, {"p": p, "T": T, "res": res, "contact": cinfo}
+
+
+def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd_rel=1e-7, krylov=20,
+                               max_newton=50, tol_plastic=1e-13, tol_contact=1e-14, max_plastic=500,
+                               max_contact=5000, solver="dfsane", k0_policy="include", mu_f=0.0,
+                               q_ratio=(0.0, 0.0), tol_friction=1e-13):
+    """The fixed point of Algorithm 1 by Newton's method instead of relaxed
+    alternation: for each cumulative load, F(x) = G(x) - x = 0 with G the
+    pass map ``outer_map`` of the surface correction x, each Newton system
+    (J_G - I) d = -F solved by GMRES (SciPy) with the products J_G v formed
+    by a forward difference (G(x + h v) - G(x)) / h, h = fd_rel (1 + |x|)
+    / |v| (Jacobian-free Newton-Krylov, Knoll and Keyes 2004), and the step
+    halved until |F| decreases by the Armijo factor 1 - 1e-4 alpha.  The
+    stopping test is Algorithm 1's: |G(x) - x| / |H0| < tol_outer.  The
+    state is committed from the pass at the final x, as in Algorithm 1.
+    Returns per-step records (newton steps, pass-map evaluations, error)."""
+    from scipy.sparse.linalg import LinearOperator, gmres
+    kw = dict(tol_plastic=tol_plastic, tol_contact=tol_contact, max_plastic=max_plastic,
+              max_contact=max_contact, solver=solver, k0_policy=k0_policy, mu_f=mu_f, q_ratio=q_ratio,
+              tol_friction=tol_friction)
+    infos = []
+    for W in W_steps:
+        H0 = h - state['u3p']
+        hnorm = np.linalg.norm(H0)
+        if hnorm == 0.0:
+            hnorm = 1.0
+        shape = H0.shape
+        x = np.zeros_like(H0)
+        Gx, aux = outer_map(grid, mat, H0, W, state, x, **kw)
+        nevals = 1
+        F = Gx - x
+        fn = np.linalg.norm(F)
+        k = 0
+        while fn / hnorm >= tol_outer and k < max_newton:
+            xb, Gb, pb = x, Gx, aux["p"]
+
+            def jv(v, xb=xb, Gb=Gb, pb=pb):
+                nonlocal nevals
+                v = v.reshape(shape)
+                nv = np.linalg.norm(v)
+                if nv == 0.0:
+                    return np.zeros(v.size)
+                hs = fd_rel * (1.0 + np.linalg.norm(xb)) / nv
+                Gv, _ = outer_map(grid, mat, H0, W, state, xb + hs * v, p0=pb, **kw)
+                nevals += 1
+                return ((Gv - Gb) / hs - v).ravel()
+
+            A = LinearOperator((x.size, x.size), dtype=float, matvec=jv)
+            d, _ = gmres(A, -F.ravel(), rtol=1e-3, atol=0.0, restart=krylov, maxiter=1)
+            d = d.reshape(shape)
+            a = 1.0
+            while True:
+                xn = xb + a * d
+                Gn, auxn = outer_map(grid, mat, H0, W, state, xn, p0=pb, **kw)
+                nevals += 1
+                Fn = Gn - xn
+                if np.linalg.norm(Fn) <= (1.0 - 1e-4 * a) * fn or a < 1e-4:
+                    break
+                a *= 0.5
+            x, Gx, aux, F, fn = xn, Gn, auxn, Fn, np.linalg.norm(Fn)
+            k += 1
+        res = aux["res"]
+        state['eps_p'] = state['eps_p'] + res['d_eps_p']
+        state['ep'] = state['ep'] + res['d_ep']
+        state['sigma'] = res['sigma']
+        state['traction'] = aux["T"]
+        state['u3p'] = state['u3p'] + Gx
+        infos.append({"newton": k, "evals": nevals, "outer_err": float(fn / hnorm), "p": aux["p"],
+                      "contact": aux["contact"]})
+    return infos

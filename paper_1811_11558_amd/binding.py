@@ -59,14 +59,15 @@ class EPOptions(ctypes.Structure):
                 ("literal_alg1", ctypes.c_int), ("anderson_m", ctypes.c_int),
                 ("warm_start", ctypes.c_int), ("inner_rel", ctypes.c_double),
                 ("krylov_dim", ctypes.c_int), ("mu_f", ctypes.c_double),
-                ("q_ratio", ctypes.c_double * 2)]
+                ("q_ratio", ctypes.c_double * 2), ("coupling", ctypes.c_int), ("coupling_krylov", ctypes.c_int)]
 
     def __init__(self, tol_outer=1e-9, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14,
                  max_outer=400, max_plastic=2000, max_contact=20000, solver=0, literal_alg1=0,
-                 anderson_m=0, warm_start=0, inner_rel=0.0, krylov_dim=0, mu_f=0.0, q_ratio=(0.0, 0.0)):
+                 anderson_m=0, warm_start=0, inner_rel=0.0, krylov_dim=0, mu_f=0.0, q_ratio=(0.0, 0.0),
+                 coupling=0, coupling_krylov=0):
         super().__init__(tol_outer, relax, tol_plastic, tol_contact, max_outer, max_plastic,
                          max_contact, solver, literal_alg1, anderson_m, warm_start, inner_rel,
-                         krylov_dim, mu_f, (ctypes.c_double * 2)(*q_ratio))
+                         krylov_dim, mu_f, (ctypes.c_double * 2)(*q_ratio), coupling, coupling_krylov)
 
 
 class _EPInfo(ctypes.Structure):

@@ -33,7 +33,7 @@ constexpr int NSCAL = 32;
 // device scalar slots
 enum {
   S_GBAR = 0, S_G, S_GOLD, S_BETA, S_RBAR, S_TAU, S_DELTA, S_SCALE, S_ERR, S_NIOL, S_SUMP, S_CNT, S_W, S_DA,
-  S_DOT0, S_DOT1, S_DOT2, S_KKT
+  S_DOT0, S_DOT1, S_DOT2, S_KKT, S_TAU0
 };
 
 // ---------------------------------------------------------------- reductions
@@ -186,11 +186,15 @@ __global__ __launch_bounds__(NT) void k_pk_tau(const double* __restrict__ p, con
   block_sums<2>(v, part);
 }
 
-// step, projection onto p >= 0, re-admission of the overlap set
+// step, projection onto p >= 0, re-admission of the overlap set (points of
+// negative gap enter with a pressure proportional to the overlap; when the
+// conjugate-gradient step vanishes -- the gap already uniform on the contact
+// set, e.g. a set of one point -- with the step of a point load, 1 / M_ii)
 __global__ __launch_bounds__(NT) void k_pk_update(double* __restrict__ p, double* __restrict__ pold,
                                                  const double* __restrict__ g, const double* __restrict__ t,
                                                  size_t n, const double* __restrict__ sc, double* part) {
   const double tau = sc[S_TAU];
+  const double tre = tau != 0.0 ? tau : sc[S_TAU0];
   double v[2] = {0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
     double po = p[i];
@@ -198,7 +202,7 @@ __global__ __launch_bounds__(NT) void k_pk_update(double* __restrict__ p, double
     double pn = po - tau * t[i];
     if (pn < 0.0) pn = 0.0;
     if (pn == 0.0 && g[i] < 0.0) {
-      pn = -tau * g[i];
+      pn = -tre * g[i];
       v[1] += 1.0;
     }
     p[i] = pn;
@@ -422,6 +426,18 @@ __global__ __launch_bounds__(NT) void k_sq2(const double* __restrict__ a1, const
   block_sums<2>(v, part);
 }
 
+// plain sums of a.b, a.a and b.b (surfaces)
+__global__ __launch_bounds__(NT) void k_sdot3(const double* __restrict__ a, const double* __restrict__ b, size_t n,
+                                             double* part) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    v[0] += a[i] * b[i];
+    v[1] += a[i] * a[i];
+    v[2] += b[i] * b[i];
+  }
+  block_sums<3>(v, part);
+}
+
 // ------------------------------------------ Newton-Krylov (Arnoldi) kernels
 // Krylov vectors are [6][nz][plane] fields of which only the voxels v < na
 // of each component (the layers above the deepest plastic one) take part;
@@ -593,6 +609,12 @@ struct SolverWork {
   double* kry_part = nullptr;
   double* kry_out = nullptr;     // device view
   double* kry_hout = nullptr;    // host view
+  // outer Newton-Krylov (coupling = 1): base strain and right-hand side
+  // [2][6 V], base traction [3][ns], then surface vectors (x, G(x), F, step,
+  // trial, work and the Krylov basis)
+  double* cpl = nullptr;
+  size_t cpl_count = 0;
+  double mdiag = 0.0;           // diagonal of the surface compliance (contact)
 };
 
 constexpr int CAP_TRIES = 4;
@@ -675,6 +697,7 @@ void solver_release(fvim_ctx* c) {
   if (w->kry) hipFree(w->kry);
   if (w->kry_part) hipFree(w->kry_part);
   if (w->kry_hout) hipHostFree(w->kry_hout);
+  if (w->cpl) hipFree(w->cpl);
   for (auto& r : w->rg) {
     if (r.ex) hipGraphExecDestroy(r.ex);
     if (r.g) hipGraphDestroy(r.g);
@@ -799,11 +822,27 @@ int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, d
   double* g = w->surf + n;
   double* t = w->surf + 2 * n;
   const double dA = c->grid.lx * c->grid.ly / (double)n;
-  // scalars: load, area, restart state
+  // scalars: load, area, restart state, the point-load step 1 / M_ii
+  if (!(w->mdiag > 0.0)) {
+    // M_ii: the mean over the nx x ny modes of 2 / (E* |q|), mode 0 dropped
+    const int nx = c->grid.nx, ny = c->grid.ny;
+    const double estar = c->mat.E / (1.0 - c->mat.nu * c->mat.nu);
+    const double twopi = 6.283185307179586476925286766559;
+    double sum = 0.0;
+    for (int ky = 0; ky < ny; ++ky)
+      for (int kx = 0; kx < nx; ++kx) {
+        if (kx == 0 && ky == 0) continue;
+        const int k1 = 2 * kx <= nx ? kx : kx - nx, k2 = 2 * ky <= ny ? ky : ky - ny;
+        const double q1 = twopi * k1 / c->grid.lx, q2 = twopi * k2 / c->grid.ly;
+        sum += 2.0 / (estar * std::sqrt(q1 * q1 + q2 * q2));
+      }
+    w->mdiag = sum / ((double)nx * ny);
+  }
   w->hsc[S_W] = W;
   w->hsc[S_DA] = dA;
   w->hsc[S_DELTA] = 0.0;
   w->hsc[S_GOLD] = 1.0;
+  w->hsc[S_TAU0] = 1.0 / w->mdiag;
   hipError_t e = hipMemcpyAsync(w->sc, w->hsc, sizeof(double) * NSCAL, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail_hip(e, "scalar upload");
   // no previous conjugate direction
@@ -1150,10 +1189,19 @@ static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, 
 // ------------------------------------------------------ Newton-Krylov
 static int krylov_dim(const fvim_ep_opts* o) { return o->krylov_dim > 0 ? o->krylov_dim : 20; }
 
+// outer Newton-Krylov: Krylov steps per Newton step, and its workspace
+static int coupling_dim(const fvim_ep_opts* o) { return o->coupling_krylov > 0 ? o->coupling_krylov : 10; }
+static size_t coupling_count(size_t V, size_t ns, const fvim_ep_opts* o) {
+  return 12 * V + 3 * ns + ns * (size_t)(6 + coupling_dim(o) + 1);
+}
+
 size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o) {
-  if (!o || o->solver != 2) return 0;
-  const size_t V = (size_t)g->nx * g->ny * g->nz;
-  return sizeof(double) * (6 * V * (size_t)(krylov_dim(o) + 2) + (size_t)KMAX * (RB + 1));
+  if (!o) return 0;
+  const size_t V = (size_t)g->nx * g->ny * g->nz, ns = (size_t)g->nx * g->ny;
+  size_t b = 0;
+  if (o->solver == 2) b += sizeof(double) * (6 * V * (size_t)(krylov_dim(o) + 2) + (size_t)KMAX * (RB + 1));
+  if (o->coupling == 1) b += sizeof(double) * coupling_count(V, ns, o);
+  return b;
 }
 
 static int kry_ensure(fvim_ctx* c, int m) {
@@ -1536,6 +1584,234 @@ static bool aa_solve(int m, const double* sums, double* g) {
   return true;
 }
 
+// ------------------------------------------------ outer Newton-Krylov
+// Algorithm 1's fixed point solved by Newton's method (coupling = 1): with
+// G(x) the surface displacement of N[C : d_eps_p] that one pass (contact on
+// H0 - x, friction, plasticity) produces, F(x) = G(x) - x = 0 is solved by
+// GMRES on (J_G - I) d = -F, the products J_G v formed by forward
+// differences of G from the pass at x (Jacobian-free Newton-Krylov, Knoll
+// and Keyes 2004), the step halved until |F| decreases.  Every pass solves
+// to the full tolerances and starts from the pass at the current x (its
+// pressure, traction and strain), so a difference pass starts next to its
+// solution.  The stopping test is Algorithm 1's, |G(x) - x| / |H0| <
+// tol_outer, and the state is committed from the pass at the final x.
+
+static int cpl_ensure(fvim_ctx* c, const fvim_ep_opts* o) {
+  SolverWork* w = c->sw;
+  const size_t need = coupling_count(w->V, w->ns, o);
+  if (w->cpl_count >= need) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
+  if (w->cpl) {
+    hipStreamSynchronize(c->stream);
+    hipFree(w->cpl);
+    w->cpl = nullptr;
+  }
+  if (hipMalloc((void**)&w->cpl, sizeof(double) * need) != hipSuccess) {
+    w->cpl_count = 0;
+    return fail(FVIM_ENOMEM, "outer Newton-Krylov workspace allocation failed");
+  }
+  w->cpl_count = need;
+  return FVIM_OK;
+}
+
+// a.b, |a|, |b| of surface arrays
+static int sdot(fvim_ctx* c, const double* a, const double* b, double out[3]) {
+  SolverWork* w = c->sw;
+  const int nb = nblocks(w->ns);
+  hipLaunchKernelGGL(k_sdot3, dim3(nb), dim3(NT), 0, c->stream, a, b, w->ns, w->part);
+  hipLaunchKernelGGL(k_pk_final, dim3(1), dim3(NT), 0, c->stream, 6, w->part, nb, w->sc, w->dmap);
+  int rc = read_scalars(c, S_DOT0, 3);
+  if (rc) return rc;
+  out[0] = w->hsc[S_DOT0];
+  out[1] = std::sqrt(w->hsc[S_DOT1]);
+  out[2] = std::sqrt(w->hsc[S_DOT2]);
+  return FVIM_OK;
+}
+
+struct PassBufs {
+  const double* H0;
+  double* H;          // modified surface of the pass
+  double* T;          // traction [3][ns] (the pressure is T + 2 ns)
+  double* dT;         // traction increment [3][ns]
+  double Wn;
+};
+
+// One pass of Algorithm 1 at the surface correction x: G(x) into dU.  warm:
+// the contact, friction and plasticity iterations start from what the
+// buffers hold (else the plasticity starts from the elastic trial).
+static int pass_map(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, PassBufs& q,
+                    const double* x, double* dU, bool warm, fvim_ep_info& inf) {
+  SolverWork* w = c->sw;
+  const size_t n = w->ns;
+  double* pcur = q.T + 2 * n;
+  axpy(c, q.H, q.H0, -1.0, x, n);                       // H = H0 - x
+  fvim_contact_info ci;
+  int rc = pk_solve(c, q.H, q.Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
+  if (rc) return rc;
+  inf.contact_iters += ci.iters;
+  inf.kkt = ci.kkt_residual;
+  if (o->mu_f > 0 && q.Wn > 0) {
+    fvim_tangential_info fi;
+    rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * q.Wn, o->q_ratio[1] * o->mu_f * q.Wn,
+                        std::max(o->tol_contact, 1e-13), o->max_contact, q.T, &fi, warm);
+    if (rc) return rc;
+    inf.contact_iters += fi.iters;
+  }
+  axpy(c, q.dT, q.T, -1.0, s->traction, 3 * n);           // dT = T - T_n
+  int it, ne;
+  double res;
+  rc = plasticity(c, q.dT, s, o, o->tol_plastic, warm, pb, &it, &ne, &res);
+  if (rc) return rc;
+  inf.plastic_iters += it;
+  inf.r_evals += ne;
+  inf.plastic_res = res;
+  Fp64Scope f64(c, 1);                                  // surface correction in float64
+  return operator_apply(c, pb.dep, nullptr, nullptr, nullptr, nullptr, dU);
+}
+
+// One load step by outer Newton-Krylov.  On return dU holds G(x) of the
+// final pass and pb, T its state (for the commit); inf.outer_iters counts
+// Newton steps, inf.outer_err is |G(x) - x| / |H0|.  *conv: converged.
+static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, PassBufs& q,
+                        double hn, double* dU, fvim_ep_info& inf, bool* conv) {
+  SolverWork* w = c->sw;
+  const size_t n = w->ns, V = w->V, n6 = 6 * V;
+  hipStream_t st = c->stream;
+  const int m = coupling_dim(o);
+  double* bx = w->cpl;                 // base strain and right-hand side of the plasticity solve
+  double* bb = bx + n6;
+  double* bT = bb + n6;                // base traction [3][n]
+  double* x = bT + 3 * n;
+  double* Gx = x + n;
+  double* F = Gx + n;
+  double* d = F + n;
+  double* xt = d + n;                  // trial / perturbed point
+  double* wv = xt + n;
+  double* Vb = wv + n;                 // Krylov basis [m + 1][n]
+  hipError_t e;
+  auto save_base = [&]() -> int {
+    e = hipMemcpyAsync(bx, pb.x, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bb, pb.b, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bT, q.T, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? FVIM_OK : fail_hip(e, "copy");
+  };
+  auto restore_base = [&]() -> int {
+    e = hipMemcpyAsync(pb.x, bx, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(pb.b, bb, sizeof(double) * n6, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(q.T, bT, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? FVIM_OK : fail_hip(e, "copy");
+  };
+  // G(x) at x = 0
+  hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(NT), 0, st, x, n, 0.0);
+  int rc = pass_map(c, s, o, pb, q, x, Gx, false, inf);
+  if (rc) return rc;
+  axpy(c, F, Gx, -1.0, x, n);
+  double t3[3];
+  if ((rc = sdot(c, F, Gx, t3))) return rc;
+  double fn = t3[1], gn = t3[2], xn = 0.0;
+  *conv = fn / hn < o->tol_outer;
+  int k = 0;
+  const double fd_rel = 3e-7;
+  while (!*conv && k < o->max_outer) {
+    if ((rc = save_base())) return rc;
+    // GMRES on (J_G - I) d = -F from d = 0, classical Gram-Schmidt applied
+    // twice, Givens rotations on the host; relative tolerance 1e-3
+    std::vector<double> Hh((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), gv(m + 1, 0.0);
+    gv[0] = fn;
+    // v_0 = -F / |F| (the right-hand side -F = |F| v_0)
+    hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, Vb, F, -1.0 / fn - 1.0, F, n);
+    int j = 0;
+    const double hs_scale = fd_rel * std::max(xn, gn);
+    for (; j < m; ++j) {
+      double* vj = Vb + (size_t)j * n;
+      double* vn = Vb + (size_t)(j + 1) * n;
+      // w = (G(x + h v_j) - G(x)) / h - v_j, |v_j| = 1
+      const double hs = hs_scale > 0 ? hs_scale : fd_rel;
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, xt, x, hs, vj, n);
+      if ((rc = restore_base())) return rc;
+      if ((rc = pass_map(c, s, o, pb, q, xt, wv, true, inf))) return rc;
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, wv, wv, -1.0, Gx, n);   // G - G(x)
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, wv, vj, 1.0 / hs, wv, n); // v + (G - G(x)) / h
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, wv, wv, -2.0, vj, n);     // (G - G(x)) / h - v
+      // modified Gram-Schmidt, applied twice
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i <= j; ++i) {
+          double dd[3];
+          if ((rc = sdot(c, wv, Vb + (size_t)i * n, dd))) return rc;
+          Hh[(size_t)i * m + j] += dd[0];
+          hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, wv, wv, -dd[0], Vb + (size_t)i * n, n);
+        }
+      }
+      double dd[3];
+      if ((rc = sdot(c, wv, wv, dd))) return rc;
+      const double hnext = dd[1];
+      Hh[(size_t)(j + 1) * m + j] = hnext;
+      // Givens rotations on column j
+      for (int i = 0; i < j; ++i) {
+        const double a = Hh[(size_t)i * m + j], b = Hh[(size_t)(i + 1) * m + j];
+        Hh[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        Hh[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = Hh[(size_t)j * m + j], b = Hh[(size_t)(j + 1) * m + j];
+      const double r = std::hypot(a, b);
+      cs[j] = r > 0 ? a / r : 1.0;
+      sn[j] = r > 0 ? b / r : 0.0;
+      Hh[(size_t)j * m + j] = r;
+      Hh[(size_t)(j + 1) * m + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      const bool done = std::fabs(gv[j + 1]) <= 1e-3 * fn || !(hnext > 1e-14 * fn);
+      if (!done) hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, vn, wv, 1.0 / hnext - 1.0, wv, n);
+      if (done) {
+        ++j;
+        break;
+      }
+    }
+    // d = sum y_i v_i with R y = g (back substitution): the least-squares
+    // solution of (J_G - I) d = -F over the Krylov space
+    std::vector<double> y(j, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int l = i + 1; l < j; ++l) t -= Hh[(size_t)i * m + l] * y[l];
+      y[i] = t / Hh[(size_t)i * m + i];
+    }
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(NT), 0, st, d, n, 0.0);
+    for (int i = 0; i < j; ++i)
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, d, d, y[i], Vb + (size_t)i * n, n);
+    // backtracking on |F|
+    double alpha = 1.0, fnew = 0.0;
+    for (;;) {
+      hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, xt, x, alpha, d, n);
+      if ((rc = restore_base())) return rc;
+      if ((rc = pass_map(c, s, o, pb, q, xt, dU, true, inf))) return rc;
+      axpy(c, wv, dU, -1.0, xt, n);
+      double f3[3];
+      if ((rc = sdot(c, wv, dU, f3))) return rc;
+      fnew = f3[1];
+      if (fnew <= (1.0 - 1e-4 * alpha) * fn || alpha < 1e-3) {
+        gn = f3[2];
+        break;
+      }
+      alpha *= 0.5;
+    }
+    e = hipMemcpyAsync(x, xt, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(Gx, dU, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(F, wv, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "copy");
+    double xx[3];
+    if ((rc = sdot(c, x, x, xx))) return rc;
+    xn = xx[1];
+    fn = fnew;
+    ++k;
+    *conv = fn / hn < o->tol_outer;
+  }
+  e = hipMemcpyAsync(dU, Gx, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return fail_hip(e, "copy");
+  inf.outer_iters = k;
+  inf.outer_err = fn / hn;
+  return FVIM_OK;
+}
+
 }  // namespace fvim
 
 using namespace fvim;
@@ -1555,6 +1831,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
   if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
   if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1 || o->anderson_m < 0 ||
+      o->coupling < 0 || o->coupling > 1 || o->coupling_krylov < 0 || o->coupling_krylov > 30 ||
       o->anderson_m > AA_MMAX || !(o->inner_rel >= 0) || o->solver < 0 || o->solver > 2 || o->krylov_dim < 0 ||
       o->krylov_dim > KMAX - 2 || !(o->mu_f >= 0) || !std::isfinite(o->mu_f) ||
       (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)))
@@ -1578,6 +1855,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (aam > 0 && (rc = aa_ensure(c))) return rc;
   if (o->solver == 2 && (rc = kry_ensure(c, krylov_dim(o)))) return rc;
   if (o->mu_f > 0 && (rc = friction_reserve(c))) return rc;
+  if (o->coupling == 1 && (rc = cpl_ensure(c, o))) return rc;
   // every buffer the operator applications of the solve use, sized now: no
   // device memory is freed or allocated while the solve runs
   if ((rc = operator_reserve(c, pb.dep, dT, pb.F))) return rc;
@@ -1610,7 +1888,13 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     bool conv = false;
     int k;
     int aa_count = 0, aa_head = 0;
-    for (k = 1; k <= o->max_outer; ++k) {
+    if (o->coupling == 1) {
+      PassBufs q{H0, H, T, dT, Wn};
+      rc = outer_newton(c, s, o, pb, q, hn, dU, inf, &conv);
+      if (rc) return cleanup(rc);
+      if (!conv) return cleanup(fail(FVIM_ENOCONV, "outer Newton-Krylov: iteration limit reached"));
+    }
+    for (k = 1; k <= o->max_outer && o->coupling != 1; ++k) {
       fvim_contact_info ci;
       rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
       if (rc) return cleanup(rc);
@@ -1690,7 +1974,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       axpy(c, H, H0, -1.0, H, n);                         // H = H0 - relaxed
       if (conv) break;
     }
-    inf.outer_iters = k > o->max_outer ? o->max_outer : k;
+    if (o->coupling != 1) inf.outer_iters = k > o->max_outer ? o->max_outer : k;
     if (!conv) return cleanup(fail(FVIM_ENOCONV, "Algorithm 1: outer iteration limit reached"));
     // state update: eps_p += d_eps_p, ep += d_ep, sigma <- sigma_(n+1), T_n <- T, U3p += dU
     e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, s->sigma, V, c->lam, c->mu, c->mat.sigma_y0,

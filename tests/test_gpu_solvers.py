@@ -87,6 +87,27 @@ def test_contact_matches_oracle_rough_1024():
     ctx.close()
 
 
+def test_contact_from_a_one_point_start_reaches_the_minimiser():
+    """A warm start with the whole load on one point far from the contact
+    zone (zero conjugate-gradient step on a one-point contact set): the GPU
+    still re-admits the overlapping points and ends on the oracle's
+    minimiser from the uniform start."""
+    from synth import paraboloid
+    g = grid_dict(16, 16, 2)
+    h = paraboloid(g, R=0.5)
+    W = 0.002
+    ref, _, _ = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=5000)
+    p0 = torch.zeros((16, 16), dtype=torch.float64, device="cuda")
+    p0[0, 0] = 1.0
+    p, gap, info = _ctx(g).contact_solve(torch.from_numpy(h).cuda(), W, tol=1e-15, max_iter=5000, p=p0,
+                                         want_gap=True)
+    torch.cuda.synchronize()
+    p = p.cpu().numpy()
+    _say("one-point start: iters", info["iters"], "kkt", info["kkt_residual"])
+    assert info["kkt_residual"] < 1e-13
+    assert _rel(p, ref) < 1e-11
+
+
 def test_contact_solve_on_workspace_that_held_nan():
     """The solver workspace of a new context is not cleared memory: pages
     that held NaN are freed first, then a contact solve on
@@ -369,4 +390,98 @@ def test_elastoplastic_reports_committed_steps_on_failure():
     for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
         assert torch.equal(st[k], ref[k]), k
     assert ok[0]["kkt"] >= 0.0 and ok[0]["kkt"] < 1e-10
+    ctx.close()
+
+
+C1 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_32x32x16.npz")
+
+
+@pytest.mark.parametrize("solver", [0, 2])
+def test_c1_paraboloid_matches_stored_oracle(solver):
+    """The plain FP64 elastoplastic configuration: 32 x 32 x 16 (lz = 0.25 L),
+    paraboloid R = 0.5 L, E = 1, nu = 0.3, sigma_y0 = 0.01, E_h = 0.1, total
+    load 0.02 E L^2 in 10 equal cumulative increments, lambda = 0.3, k = 0
+    traction included (far beyond first yield: Hertz peak pressure 26
+    sigma_y0 at the full load).  The oracle's state after the increments it
+    has stored (tests/golden/make_golden.py writes the file after every
+    increment) is reproduced by Algorithm 1 with DF-SANE and with
+    Newton-Krylov inside, to 1e-11.  The contact solves stop at 1e-14
+    (the change of the pressure, relative to the load): at the oracle's
+    1e-15 the pressure iteration reaches its rounding floor first on some
+    passes of the Newton-Krylov path."""
+    from paper_1811_11558_amd import EPOptions
+    if not os.path.exists(C1):
+        pytest.skip("stored case not written")
+    ref = np.load(C1)
+    steps = int(ref["steps_done"])
+    g = grid_dict(32, 32, 16, lz=0.25)
+    ctx = _ctx(g)
+    st = ctx.new_state()
+    _say("c1: %d increments, solver %d" % (steps, solver))
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"][:steps]), st,
+                                    EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-14,
+                                              max_outer=400, max_plastic=20000, solver=solver))
+    torch.cuda.synchronize()
+    _say([(i["outer_iters"], i["r_evals"]) for i in infos])
+    assert all(i["committed"] == 1 for i in infos)
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < 1e-11, (k, err)
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,bound", [("hertz_ep_16x16x8", 1e-11), ("hertz_graded_ep_16x16x8", 1e-11),
+                                        ("hertz_friction_ep_16x16x8", 1e-11), ("rough_ep_16x16x8", 1e-10)])
+def test_newton_coupling_reaches_the_stored_fixed_point(name, bound):
+    """The outer Newton-Krylov coupling (coupling = 1) ends on the fixed point
+    of Algorithm 1 stored by tests/golden/make_golden.py (the oracle's
+    relaxed alternation stopped at |dU3p - dU3p_prev| / |H0| < 1e-11), in far
+    fewer passes.  The rough case's stored state lies 2.8e-11 from the
+    fixed point (the oracle's own Newton coupling finds that distance), so
+    its bound is 1e-10."""
+    import ast
+    from paper_1811_11558_amd import Context, EPOptions
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gold)
+    from make_golden import CASES
+    c = CASES[name]
+    ref = np.load(os.path.join(gold, name + ".npz"))
+    meta = ast.literal_eval(str(ref["meta"][0]))
+    nx, ny, nz, lz = c["grid"]
+    g = grid_dict(nx, ny, nz, lz=lz)
+    m = c["mat"]
+    ctx = Context(g, m["E"], m["nu"], m["sigma_y0"], m["E_h"])
+    if "z" in ref:
+        ctx.set_depth_nodes(ref["z"])
+    fr = dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"]) if "friction" in c else {}
+    st = ctx.new_state()
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                    EPOptions(tol_outer=1e-13, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15,
+                                              max_plastic=20000, coupling=1, **fr))
+    torch.cuda.synchronize()
+    _say(name, "newton steps", [i["outer_iters"] for i in infos], "oracle passes", meta["outer"],
+         "kkt", [i["kkt"] for i in infos])
+    for i, passes in zip(infos, meta["outer"]):
+        assert i["outer_err"] < 1e-13 and i["outer_iters"] < passes
+        assert i["kkt"] < 1e-10
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < bound, (k, err)
+    ctx.close()
+
+
+def test_newton_coupling_options_are_checked():
+    from paper_1811_11558_amd import EPOptions, FvimError
+    g = grid_dict(8, 8, 4, lz=0.2)
+    ctx = _ctx(g)
+    st = ctx.new_state()
+    h = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
+    for bad in (dict(coupling=2), dict(coupling=1, coupling_krylov=31), dict(coupling=-1)):
+        with pytest.raises(FvimError):
+            ctx.elastoplastic_solve(h, [0.01], st, EPOptions(**bad))
+    # the flat surface: converged at the first pass, no Newton step
+    infos = ctx.elastoplastic_solve(h, [0.01, 0.02], st, EPOptions(tol_outer=1e-12, coupling=1))
+    assert [i["outer_iters"] for i in infos] == [0, 0]
     ctx.close()

@@ -120,3 +120,28 @@ def test_stored_oracle_state_satisfies_the_certificates(name):
     assert cert["stress"] < 1e-11, cert
     assert cert["outside"] < 1e-13, cert
     assert np.count_nonzero(d["ep"]) > 0
+
+
+def test_newton_coupling_reaches_the_algorithm1_fixed_point():
+    """Newton-Krylov on Algorithm 1's fixed point (a different iteration)
+    ends on Algorithm 1's state and on the certificates of the coupled
+    solution, in fewer passes than the relaxed alternation."""
+    g = grid_dict(16, 16, 4, lz=0.2)
+    mat = dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1)
+    h = paraboloid(g, R=0.5)
+    Ws = [0.0005, 0.001]
+    a = cp.new_state(g)
+    ia = cp.elastoplastic_solve(g, mat, h, Ws, a, tol_outer=1e-12, relax=0.6, tol_contact=1e-15)
+    b = cp.new_state(g)
+    ib = cp.elastoplastic_solve_newton(g, mat, h, Ws, b, tol_outer=1e-13, tol_contact=1e-15)
+    for inf in ib:
+        assert inf["outer_err"] < 1e-13
+    passes_a = sum(i["outer_iters"] for i in ia)
+    passes_b = sum(i["evals"] for i in ib)
+    assert passes_b < passes_a, (passes_b, passes_a)
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = np.linalg.norm(a[k] - b[k]) / np.linalg.norm(a[k])
+        assert err < 1e-9, (k, err)
+    c, fy, lim = certificates(g, mat, h, 0.001, b)
+    assert c["kkt"] < 1e-12 and c["load"] < 1e-14 and c["u3p"] < 1e-13, c
+    assert c["stress"] < 1e-11 and c["outside"] < 1e-13, c

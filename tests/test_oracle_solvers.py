@@ -146,6 +146,24 @@ def test_contact_kkt_certificate_rough():
     assert 0.01 < info["contact_fraction"] < 0.9
 
 
+def test_contact_from_a_one_point_start_reaches_the_minimiser():
+    """Warm start with the whole load on one point far from the contact zone:
+    the gap is uniform on that one-point set, the conjugate-gradient step is
+    zero, and the overlapping points must still re-enter (with the
+    point-load step); the solution is the one from the uniform start and
+    passes the KKT certificate."""
+    g = grid_dict(16, 16, 2)
+    h = paraboloid(g, R=0.5)
+    W = 0.002
+    ref, _, rinfo = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=5000)
+    p0 = np.zeros((16, 16))
+    p0[0, 0] = 1.0
+    p, gap, info = oc.contact_solve(h, W, g, E, NU, tol=1e-15, max_iter=5000, p0=p0)
+    assert info["kkt_residual"] < 1e-13, info
+    assert p[0, 0] == 0.0
+    assert np.max(np.abs(p - ref)) < 1e-12 * ref.max()
+
+
 @pytest.mark.slow
 def test_contact_hertz_within_discretisation_error():
     """Paraboloid, a/L ~ 0.1, a/dx ~ 25: Hertz radius and peak pressure."""
