@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--cpu-modes", type=int, default=4096,
                     help="modes of the oracle sample for the CPU baseline")
     ap.add_argument("--workload", default="operator", choices=["operator", "serve", "solve", "copy", "batch", "rough", "area",
-                                                                   "friction"],
+                                                                   "friction", "request"],
                     help="operator: the fused operator (the headline line); serve: Poisson-arrival "
                          "elastoplastic solves of mixed grids through the batching server; solve: the "
                          "32x32x16 paraboloid elastoplastic solve; copy: a plain device copy of known size "
@@ -83,6 +83,9 @@ def parse():
                     help="area: rms slopes of the rough surface to run (comma separated)")
     ap.add_argument("--load-steps", type=int, default=5, help="area: equal cumulative load steps")
     ap.add_argument("--seed", type=int, default=0, help="area: seed of the rough surface")
+    ap.add_argument("--tune", action="store_true",
+                    help="operator: tune the depth layout and transform choices on the first warm-up call "
+                         "(the headline workload otherwise runs the pinned tuned choices)")
     ap.add_argument("--op", default="fused", choices=["fused", "mindlin", "boussinesq"],
                     help="operator: both operators (default) or one alone")
     ap.add_argument("--graded", type=float, default=0.0,
@@ -94,6 +97,10 @@ def parse():
     ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
                     help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
     ap.add_argument("--krylov", type=int, default=0, help="Newton-Krylov: Arnoldi steps per Newton step (0 = 20)")
+    ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
+                    help="solve/rough/serve/request: 0 Algorithm 1 (relaxation or Anderson), 1 outer Newton-Krylov")
+    ap.add_argument("--request-id", type=int, default=10,
+                    help="request: index of the request of the serving stream (seed 2024) to solve alone")
     a = ap.parse_args()
     dflt = (512, 512, 64) if a.workload == "area" else (256, 256, 64)
     a.nx = a.nx or dflt[0]
@@ -284,7 +291,8 @@ def bench_rough(a):
     Ws = [a.load * (i + 1) / 5 for i in range(5)]
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
                      max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
-                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
+                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov, coupling=a.coupling,
+                     **friction_opts(a))
     V = a.nx * a.ny * a.nz
     runs = {}
     for prec in (["fp64", "fp32_refined"] if a.compare else [a.precision]):
@@ -349,7 +357,8 @@ def bench_area(a):
     kcut = a.nx // 4
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=4000,
                      max_plastic=20000, max_contact=50000, anderson_m=a.anderson, warm_start=a.warm,
-                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
+                     inner_rel=a.inner_rel, solver=a.solver, krylov_dim=a.krylov, coupling=a.coupling,
+                     **friction_opts(a))
     rows = []
     for slope in [float(x) for x in a.slopes.split(",")]:
         h = torch.from_numpy(rough_surface(a.nx, a.ny, hurst=0.8, k_roll=2, k_cut=kcut, rms_slope=slope,
@@ -446,7 +455,7 @@ def bench_solve(a):
     Ws = [0.002 * (i + 1) for i in range(10)]
     opts = EPOptions(tol_outer=1e-9, relax=0.3, tol_plastic=1e-11, tol_contact=1e-14, max_outer=2000,
                      max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel,
-                     solver=a.solver, krylov_dim=a.krylov, **friction_opts(a))
+                     solver=a.solver, krylov_dim=a.krylov, coupling=a.coupling, **friction_opts(a))
     times, infos = [], None
     for _ in range(max(1, a.steps)):
         ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision=a.precision)
@@ -479,7 +488,7 @@ def bench_solve(a):
 
 
 def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver=0, krylov=0, friction=None,
-              verbose=False):
+              verbose=False, coupling=0):
     """Seeded Poisson-arrival elastoplastic contact solves of mixed grids
     (64^2 x 32, 128^2 x 64, 256^2 x 64, 512^2 x 96; rough surfaces with Hurst
     exponent in [0.5, 0.9], mean pressure in [0.005, 0.05] E) through the
@@ -498,7 +507,7 @@ def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver
         prepared.append((r, g, h))
     opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
                      max_plastic=20000, anderson_m=anderson, warm_start=warm, inner_rel=inner_rel,
-                     solver=solver, krylov_dim=krylov, **(friction or {}))
+                     solver=solver, krylov_dim=krylov, coupling=coupling, **(friction or {}))
     srv = Server(hbm_budget_bytes=200 << 30, max_slots=slots)
     t0 = time.perf_counter()
     ids = []
@@ -536,7 +545,43 @@ def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver
             "failure_latency_s": [d["latency_s"] for d in detail if d["status"] != 0],
             "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": slots, "rate_per_s": rate,
                        "precision": "fp32_refined", "anderson": anderson, "warm_start": warm,
-                       "inner_rel": inner_rel, "solver": SOLVER_NAMES[solver]}}
+                       "inner_rel": inner_rel, "solver": SOLVER_NAMES[solver], "coupling": coupling}}
+
+
+def bench_request(a):
+    """One request of the serving stream (seed 2024, --request-id) solved
+    alone on a context: grid, rough surface and mean pressure as served,
+    FP32 kernels with float64 refinement, outer tolerance 1e-7, the outer
+    iteration of --coupling (Algorithm 1 with --anderson / --warm /
+    --inner-rel, or outer Newton-Krylov), --friction.  Reports the outer
+    passes or Newton steps, the residual evaluations (operator
+    applications of the plasticity solves) and the time."""
+    import torch
+    from paper_1811_11558_amd import Context, EPOptions
+    from synth import grid_dict, poisson_requests, rough_surface
+    r = poisson_requests(n=max(64, a.request_id + 1), rate=1e9, seed=2024)[a.request_id]
+    g = grid_dict(r["nx"], r["ny"], r["nz"], 1.0, 1.0, 0.25)
+    h = torch.from_numpy(rough_surface(r["nx"], r["ny"], hurst=r["hurst"], k_roll=4, k_cut=r["nx"] // 4,
+                                       rms_slope=0.1, seed=r["seed"])).cuda()
+    opts = EPOptions(tol_outer=1e-7, relax=0.3, tol_plastic=1e-9, tol_contact=1e-12, max_outer=2000,
+                     max_plastic=20000, anderson_m=a.anderson, warm_start=a.warm, inner_rel=a.inner_rel,
+                     solver=a.solver, krylov_dim=a.krylov, coupling=a.coupling, **friction_opts(a))
+    ctx = Context(g, 1.0, 0.3, 0.01, 0.1, precision="fp32_refined")
+    st = ctx.new_state()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = ctx.elastoplastic_solve(h, [r["pbar"]], st, opts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i = infos[0]
+    print(json.dumps({"metric": "request solve time", "value": dt, "unit": "s", "higher_is_better": False,
+                      "request": {k: r[k] for k in ("id", "nx", "ny", "nz", "hurst", "pbar")},
+                      "outer_iters": i["outer_iters"], "residual_evals": i["r_evals"],
+                      "contact_iters": i["contact_iters"], "outer_err": i["outer_err"],
+                      "config": {"coupling": a.coupling, "anderson": a.anderson, "warm_start": a.warm,
+                                 "inner_rel": a.inner_rel, "solver": SOLVER_NAMES[a.solver],
+                                 "friction": friction_opts(a)}}))
+    ctx.close()
 
 
 def bench_serve(a):
@@ -544,7 +589,7 @@ def bench_serve(a):
     --requests, --rate, --slots, --anderson, --warm, --inner-rel, --solver,
     --friction."""
     r = serve_run(a.requests, a.rate, a.slots, a.anderson, a.warm, a.inner_rel, a.solver, a.krylov,
-                  friction_opts(a), verbose=True)
+                  friction_opts(a), verbose=True, coupling=a.coupling)
     out = {"metric": "served solves/s", "value": r["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
            "n_gpus": 1}
     out.update(r)
@@ -561,6 +606,8 @@ def main():
         return bench_copy(a)
     if a.workload == "batch":
         return bench_batch(a)
+    if a.workload == "request":
+        return bench_request(a)
     if a.workload == "rough":
         return bench_rough(a)
     if a.workload == "area":
@@ -596,7 +643,16 @@ def main():
         trac = None
     elif a.op == "boussinesq":
         eps = None
-    ctx.tune()                      # first warm-up call times the depth-pass layouts
+    if (a.nx, a.ny, a.nz, a.precision, a.graded, a.op) == (256, 256, 64, "fp64", 0.0, "fused") and not a.tune:
+        # the headline workload runs the launch choices the tuner picks for
+        # it on MI355X (depth layout 64 lanes x 1 node; transforms: forward
+        # half tiles radix 4, inverse default tiles radix 8), pinned so that
+        # every run and its profile time the same kernels (the tuner's
+        # timings of near-equal candidates vary from run to run)
+        ctx.set_option(ctx.OPT_DEPTH_CONFIG, 4)
+        ctx.set_fft_config([(0, 4), (0, 4), (1, 8), (1, 8)])
+    else:
+        ctx.tune()                  # first warm-up call times the depth layouts and transform choices
     for _ in range(a.warmup):
         ctx.operator_apply(eps, trac, out=out)
     torch.cuda.synchronize()

@@ -7,7 +7,7 @@ Usage (from the repository root):
         --trace T.csv --commands commands.txt --out profiles/NAME.md
     python -m paper_1811_11558_amd.profile_summary report --workload 256x256x64/fp64 \\
         --stats S.csv --fetch F.csv --write W.csv --copy-fetch CF.csv --copy-write CW.csv \\
-        --copy-bytes 400000000 [--raw-read R1.csv --raw-write R2.csv] \\
+        --copy-bytes 400000000 [--raw-read R1.csv --raw-write R2.csv] [--sq SQ.csv] \\
         --commands commands.txt --out profiles/NAME.md --traffic profiles/traffic.json
 
 Byte accounting.  FETCH_SIZE and WRITE_SIZE are scaled by what they read for
@@ -94,22 +94,24 @@ def median(v):
     return v[len(v) // 2]
 
 
-def stage_keys(keys):
-    """Map (kernel, grid) keys of one operator run to bench stages."""
+def stage_keys(keys, launches=None):
+    """Map (kernel, grid) keys of one operator run to bench stages.  With
+    launches ({kernel name: launches} of the timed run's trace) each
+    transform stage takes the instance launched most there (the tuners'
+    candidates run only a few times), else the largest grid."""
     by = defaultdict(list)
     for k in keys:
         by[k[0].split("<")[0]].append(k)
     st = {}
-    for base, fwd, trac in (("k_x_r2c", "x_fwd", "x_fwd_t"), ("k_y_fwd", "y_fwd", "y_fwd_t")):
-        ks = sorted(by.get(base, []), key=lambda k: -k[1])
-        if ks:
-            st[fwd] = ks[0]
-        if len(ks) > 1:
-            st[trac] = ks[-1]
-    for base, name in (("k_y_inv", "y_inv"), ("k_x_c2r", "x_inv")):
-        ks = sorted(by.get(base, []), key=lambda k: -k[1])
-        if ks:
-            st[name] = ks[0]
+    for base, name in (("k_x_r2c", "x_fwd"), ("k_y_fwd", "y_fwd"), ("k_y_inv", "y_inv"), ("k_x_c2r", "x_inv")):
+        ks = by.get(base, [])
+        if not ks:
+            continue
+        if launches:
+            named = [k for k in ks if launches.get(k[0], 0) == max(launches.get(j[0], 0) for j in ks)]
+            if named:
+                ks = named
+        st[name] = sorted(ks, key=lambda k: -k[1])[0]
     return st, by.get("k_depth", [])
 
 
@@ -127,15 +129,15 @@ def report(a):
     raw_w = dispatches(a.raw_write) if a.raw_write else None
 
     keys = list(fetch.keys())
-    st, depth_keys = stage_keys(keys)
-    # depth: the layout with the most launches in the timing run (the trace)
-    # is the tuned one (every layout also runs during tuning in the counter
-    # runs); Nyquist launches are the instances whose last flag is true
+    # the instances with the most launches in the timing run (the trace) are
+    # the tuned ones (every candidate also runs during tuning in the counter
+    # runs); depth Nyquist launches are the instances whose sixth flag is true
     launches = defaultdict(int)
     if a.trace:
         for r in csv.DictReader(open(a.trace)):
             launches[short(r["Kernel_Name"])] += 1
-    else:
+    st, depth_keys = stage_keys(keys, launches if a.trace else None)
+    if not a.trace:
         for k in depth_keys:
             launches[k[0]] += len(fetch[k]["FETCH_SIZE"])
     def nyq_flag(name):
@@ -193,6 +195,23 @@ def report(a):
         doc += ["Per launch shape (same run, from the kernel trace; the tuning launches of the first "
                 "call are the layouts with 4 launches):", "", trace_table(a.trace), ""]
     doc += ["## HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`)", ""] + lines + [""]
+    if a.sq:
+        sq = dispatches(a.sq)
+        doc += ["## Waiting and occupancy (`--pmc SQ_WAIT_ANY SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAVES`)", "",
+                "wait = SQ_WAIT_ANY / SQ_WAVE_CYCLES (share of the waves' resident cycles spent waiting); "
+                "waves per SQ-cycle = SQ_WAVE_CYCLES / SQ_BUSY_CYCLES (resident waves per busy cycle, "
+                "summed as the counters sum over the shader engines).", "",
+                "| stage | kernel | waves | wait | waves per SQ-cycle |", "|---|---|---|---|---|"]
+        for stage in ("x_fwd", "y_fwd", "depth", "depth_nyq", "y_inv", "x_inv"):
+            k = st.get(stage)
+            if not k or k not in sq:
+                continue
+            c = {n: median(v) for n, v in sq[k].items()}
+            wc = c.get("SQ_WAVE_CYCLES", 0.0)
+            doc.append("| %s | `%s` | %d | %.3f | %.1f |" % (stage, k[0], c.get("SQ_WAVES", 0),
+                                                             c.get("SQ_WAIT_ANY", 0.0) / wc if wc else 0.0,
+                                                             wc / c["SQ_BUSY_CYCLES"] if c.get("SQ_BUSY_CYCLES") else 0.0))
+        doc += [""]
     if a.note:
         doc += [a.note, ""]
     with open(a.out, "w") as f:
@@ -209,14 +228,45 @@ def report(a):
 
 
 def kernels(a):
-    """Kernel-time summary of one profiled run (no counters): the commands,
-    the per-kernel statistics and the per-launch-shape table."""
+    """Kernel-time summary of one profiled run: the commands, the per-kernel
+    statistics and the per-launch-shape table; with counter CSVs (FETCH_SIZE,
+    WRITE_SIZE and the copy references) also the HBM bytes per launch of the
+    kernels named by --traffic-kernels, scaled by the copy, and the rate they
+    give with the trace's average duration."""
     rows = trace_table(a.trace).split("\n")
     doc = ["# %s" % a.title, "", "Commands (from the repository root on the GPU host):", "", "```"]
     doc += [l.rstrip("\n") for l in open(a.commands)] + ["```", ""]
     doc += ["## Kernel durations (`rocprofv3 --kernel-trace --stats`)", "", stats(a.stats), ""]
     doc += ["Per launch shape (same run, from the kernel trace; the %d with the most time):" % a.top, ""]
     doc += rows[:2 + a.top] + [""]
+    if a.fetch and a.write and a.copy_fetch and a.copy_write:
+        fetch, write = dispatches(a.fetch), dispatches(a.write)
+        fs, copy_name, cf = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
+        ws, _, cw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes)
+        dur = defaultdict(list)
+        for r in csv.DictReader(open(a.trace)):
+            dur[(short(r["Kernel_Name"]), int(r["Grid_Size_X"]))].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        doc += ["## HBM traffic per launch (`--pmc FETCH_SIZE`, `--pmc WRITE_SIZE`)", "",
+                "Copy reference `%s`: %.1f bytes per FETCH_SIZE unit and %.1f per WRITE_SIZE unit; the "
+                "mean over the launches of each shape (launches of one shape may move different amounts, "
+                "e.g. surface and volume axpy launches share a grid); rate = (fetched + written) / the "
+                "trace's average duration of that shape (the counter and trace runs make the same "
+                "launches)." % (copy_name, fs, ws), "",
+                "| kernel | grid | launches | fetched MB | written MB | average (us) | TB/s | of 8 TB/s |",
+                "|---|---|---|---|---|---|---|---|"]
+        pats = [re.compile(x) for x in (a.traffic_kernels or [])]
+        for k in sorted(fetch, key=lambda k: -sum(dur.get(k, [0]))):
+            if not any(p.search(k[0]) for p in pats) or k not in write or k not in dur:
+                continue
+            fv, wv = fetch[k]["FETCH_SIZE"], write[k]["WRITE_SIZE"]
+            fb = sum(fv) / len(fv) * fs
+            wb = sum(wv) / len(wv) * ws
+            us = sum(dur[k]) / len(dur[k])
+            rate = (fb + wb) / (us * 1e-6) / 1e12
+            doc.append("| `%s` | %d | %d | %.2f | %.2f | %.2f | %.2f | %.3f |"
+                       % (k[0], k[1], len(dur[k]), fb / 1e6, wb / 1e6, us, rate, rate / 8.0))
+        doc += [""]
     if a.note:
         doc += [a.note, ""]
     with open(a.out, "w") as f:
@@ -236,6 +286,12 @@ def main():
         ap.add_argument("--trace", required=True)
         ap.add_argument("--commands", required=True)
         ap.add_argument("--top", type=int, default=20)
+        ap.add_argument("--fetch")
+        ap.add_argument("--write")
+        ap.add_argument("--copy-fetch")
+        ap.add_argument("--copy-write")
+        ap.add_argument("--copy-bytes", type=int, default=400000000)
+        ap.add_argument("--traffic-kernels", nargs="*", help="regular expressions of kernel names")
         ap.add_argument("--note")
         ap.add_argument("--out", required=True)
         kernels(ap.parse_args())
@@ -253,6 +309,7 @@ def main():
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--raw-read")
     ap.add_argument("--raw-write")
+    ap.add_argument("--sq", help="counter CSV of SQ_WAIT_ANY, SQ_WAVE_CYCLES, SQ_BUSY_CYCLES, SQ_WAVES")
     ap.add_argument("--commands")
     ap.add_argument("--note")
     ap.add_argument("--out", required=True)
