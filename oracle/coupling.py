@@ -169,7 +169,7 @@ def new_state(grid):
 def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3,
                         tol_plastic=1e-13, tol_contact=1e-14, max_outer=500,
                         max_plastic=500, max_contact=5000, solver="dfsane", literal=False,
-                        k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0), tol_friction=1e-13):
+                        k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0), tol_friction=1e-13, cerruti=False):
     """Algorithm 1 for each cumulative load in W_steps; state updated in place.
 
     With mu_f > 0 the contact step also carries Coulomb friction: after the
@@ -178,7 +178,10 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
     normal and tangential problems uncoupled) joins the traction T, so the
     plasticity sees it through the Boussinesq-Cerruti operator.  The
     tangential problem is solved in total form at each load, which is the
-    Cattaneo-Mindlin reading for monotonic proportional loading.
+    Cattaneo-Mindlin reading for monotonic proportional loading.  With
+    cerruti=True the normal and tangential solves are coupled through the
+    Boussinesq-Cerruti cross terms (``friction.frictional_contact_solve``,
+    warm-started from the previous pass's traction within a step).
 
     Returns a list of per-step info dicts."""
     E, nu = mat['E'], mat['nu']
@@ -196,11 +199,21 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
         err = np.inf
         k = 0
         hist = []
+        q_prev = None
         for k in range(1, max_outer + 1):
-            p, _, cinfo = oc.contact_solve(H, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p)
             T = np.zeros_like(T_n)
-            T[2] = p
-            if mu_f > 0.0:
+            if mu_f > 0.0 and cerruti:
+                Q = np.asarray(q_ratio, dtype=float) * mu_f * W
+                p, T[:2], finfo = fr.frictional_contact_solve(
+                    grid, E, nu, H, W, Q, mu_f, coupled=True, tol=tol_friction, tol_contact=tol_contact,
+                    tol_friction=tol_friction, max_contact=max_contact, p0=p, q0=q_prev)
+                cinfo = finfo["contact"]
+                q_prev = T[:2].copy()
+                T[2] = p
+            else:
+                p, _, cinfo = oc.contact_solve(H, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p)
+                T[2] = p
+            if mu_f > 0.0 and not cerruti:
                 Q = np.asarray(q_ratio, dtype=float) * mu_f * W
                 T[:2], _ = fr.tangential_solve(grid, E, nu, p, Q, mu_f, tol=tol_friction)
             res = plasticity(grid, mat, T - T_n, state, tol=tol_plastic, max_iter=max_plastic,
@@ -225,18 +238,27 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
 
 def outer_map(grid, mat, H0, W, state, x, p0=None, tol_plastic=1e-13, tol_contact=1e-14, max_plastic=500,
               max_contact=5000, solver="dfsane", k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0),
-              tol_friction=1e-13):
+              tol_friction=1e-13, cerruti=False, q0=None):
     """One pass of Algorithm 1 as a map of the surface correction x: the
     contact step on the modified surface H0 - x (warm-started from p0),
     with friction the tangential step, the plasticity step for the traction
     increment, and the surface displacement of N[C : d_eps_p] it produces.
     Returns (G(x), aux) with aux the pass's pressure, traction, plasticity
-    result and contact record."""
+    result and contact record.  With cerruti=True and friction the contact
+    step is the coupled normal-tangential solve, warm-started from (p0, q0)."""
     E, nu = mat['E'], mat['nu']
-    p, _, cinfo = oc.contact_solve(H0 - x, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p0)
     T = np.zeros_like(state['traction'])
-    T[2] = p
-    if mu_f > 0.0:
+    if mu_f > 0.0 and cerruti:
+        Q = np.asarray(q_ratio, dtype=float) * mu_f * W
+        p, T[:2], finfo = fr.frictional_contact_solve(
+            grid, E, nu, H0 - x, W, Q, mu_f, coupled=True, tol=tol_friction, tol_contact=tol_contact,
+            tol_friction=tol_friction, max_contact=max_contact, p0=p0, q0=q0)
+        cinfo = finfo["contact"]
+        T[2] = p
+    else:
+        p, _, cinfo = oc.contact_solve(H0 - x, W, grid, E, nu, tol=tol_contact, max_iter=max_contact, p0=p0)
+        T[2] = p
+    if mu_f > 0.0 and not cerruti:
         Q = np.asarray(q_ratio, dtype=float) * mu_f * W
         T[:2], _ = fr.tangential_solve(grid, E, nu, p, Q, mu_f, tol=tol_friction)
     res = plasticity(grid, mat, T - state['traction'], state, tol=tol_plastic, max_iter=max_plastic,
@@ -248,7 +270,7 @@ def outer_map(grid, mat, H0, W, state, x, p0=None, tol_plastic=1e-13, tol_contac
 def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd_rel=1e-7, krylov=20,
                                max_newton=50, tol_plastic=1e-13, tol_contact=1e-14, max_plastic=500,
                                max_contact=5000, solver="dfsane", k0_policy="include", mu_f=0.0,
-                               q_ratio=(0.0, 0.0), tol_friction=1e-13):
+                               q_ratio=(0.0, 0.0), tol_friction=1e-13, cerruti=False):
     """The fixed point of Algorithm 1 by Newton's method instead of relaxed
     alternation: for each cumulative load, F(x) = G(x) - x = 0 with G the
     pass map ``outer_map`` of the surface correction x, each Newton system
@@ -262,7 +284,7 @@ def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd
     from scipy.sparse.linalg import LinearOperator, gmres
     kw = dict(tol_plastic=tol_plastic, tol_contact=tol_contact, max_plastic=max_plastic,
               max_contact=max_contact, solver=solver, k0_policy=k0_policy, mu_f=mu_f, q_ratio=q_ratio,
-              tol_friction=tol_friction)
+              tol_friction=tol_friction, cerruti=cerruti)
     infos = []
     for W in W_steps:
         H0 = h - state['u3p']
@@ -277,16 +299,16 @@ def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd
         fn = np.linalg.norm(F)
         k = 0
         while fn / hnorm >= tol_outer and k < max_newton:
-            xb, Gb, pb = x, Gx, aux["p"]
+            xb, Gb, pb, qb = x, Gx, aux["p"], aux["T"][:2].copy()
 
-            def jv(v, xb=xb, Gb=Gb, pb=pb):
+            def jv(v, xb=xb, Gb=Gb, pb=pb, qb=qb):
                 nonlocal nevals
                 v = v.reshape(shape)
                 nv = np.linalg.norm(v)
                 if nv == 0.0:
                     return np.zeros(v.size)
                 hs = fd_rel * (1.0 + np.linalg.norm(xb)) / nv
-                Gv, _ = outer_map(grid, mat, H0, W, state, xb + hs * v, p0=pb, **kw)
+                Gv, _ = outer_map(grid, mat, H0, W, state, xb + hs * v, p0=pb, q0=qb if cerruti else None, **kw)
                 nevals += 1
                 return ((Gv - Gb) / hs - v).ravel()
 
@@ -296,7 +318,7 @@ def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd
             a = 1.0
             while True:
                 xn = xb + a * d
-                Gn, auxn = outer_map(grid, mat, H0, W, state, xn, p0=pb, **kw)
+                Gn, auxn = outer_map(grid, mat, H0, W, state, xn, p0=pb, q0=qb if cerruti else None, **kw)
                 nevals += 1
                 Fn = Gn - xn
                 if np.linalg.norm(Fn) <= (1.0 - 1e-4 * a) * fn or a < 1e-4:

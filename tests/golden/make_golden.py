@@ -4,7 +4,11 @@ Calls only ``oracle/`` and ``synth/``.  Run from the repository root:
     python tests/golden/make_golden.py [name ...]
 Each case is the FP64 oracle's Algorithm 1 (Sec. 5.2) on a seeded
 synthetic input; the GPU solver must reproduce the stored state.
+    python tests/golden/make_golden.py --resume c1_32x32x16
+continues a checkpointed case from the increments its file already holds
+(the state carries over exactly as inside one run).
 """
+import ast
 import os
 import sys
 import time
@@ -38,6 +42,11 @@ CASES = {
     "hertz_friction_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
                                       mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1),
                                       friction=dict(mu_f=0.3, q_ratio=(0.5, 0.2))),
+    # the friction case with the normal and tangential contact problems
+    # coupled through the Boussinesq-Cerruti cross terms
+    "hertz_cerruti_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
+                                     mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1),
+                                     friction=dict(mu_f=0.3, q_ratio=(0.5, 0.2), cerruti=True)),
     # the Hertz case on depth nodes graded toward the surface,
     # z_i = lz (i / (nz - 1))^2
     "hertz_graded_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
@@ -57,7 +66,7 @@ OPTS = dict(tol_outer=1e-11, tol_plastic=1e-13, tol_contact=1e-15, max_outer=400
             max_contact=20000, literal=False)
 
 
-def run(name):
+def run(name, resume=False):
     c = CASES[name]
     nx, ny, nz, lz = c["grid"]
     g = grid_dict(nx, ny, nz, lz=lz)
@@ -81,7 +90,20 @@ def run(name):
     if c.get("checkpoint"):
         # one increment at a time (the state carries over, as inside one call)
         infos = []
+        first = 0
+        path = os.path.join(HERE, name + ".npz")
+        if resume and os.path.exists(path):
+            d = np.load(path)
+            first = int(d["steps_done"])
+            for key in st:
+                st[key] = np.array(d[key])
+            m = ast.literal_eval(str(d["meta"][0]))
+            t0 -= m["seconds"]
+            infos = [{"outer_iters": o, "outer_err": e, "plastic": pl}
+                     for o, e, pl in zip(m["outer"], m["outer_err"], m["plastic"])]
         for k, W in enumerate(c["W"]):
+            if k < first:
+                continue
             infos += cp.elastoplastic_solve(g, mat, h, [W], st, relax=c["relax"], **OPTS, **c.get("friction", {}))
             save(name, c, g, h, st, infos, time.time() - t0, extra, k + 1)
             print(name, "step %d: %.1f s, %d outer passes" % (k + 1, time.time() - t0, infos[-1]["outer_iters"]),
@@ -100,10 +122,15 @@ def save(name, c, g, h, st, infos, dt, extra, steps_done):
     more = dict(extra)
     if c.get("checkpoint"):
         more["steps_done"] = np.array(steps_done)
-    np.savez_compressed(os.path.join(HERE, name + ".npz"), h=h, W=np.array(c["W"]), meta=meta,
-                        **{k: v for k, v in st.items()}, **more)
+    path = os.path.join(HERE, name + ".npz")
+    tmp = path + ".tmp.npz"
+    np.savez_compressed(tmp, h=h, W=np.array(c["W"]), meta=meta, **{k: v for k, v in st.items()}, **more)
+    os.replace(tmp, path)        # readers never see a half-written file
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or list(CASES)):
-        run(n)
+    args = sys.argv[1:]
+    resume = "--resume" in args
+    args = [a for a in args if a != "--resume"]
+    for n in (args or list(CASES)):
+        run(n, resume=resume)

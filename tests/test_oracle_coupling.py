@@ -26,6 +26,7 @@ import pytest
 
 from oracle import contact as oc
 from oracle import coupling as cp
+from oracle import friction as fr
 from oracle import operators as ops
 from oracle import plasticity as pl
 from synth import grid_dict, paraboloid
@@ -36,13 +37,18 @@ sys.path.insert(0, GOLDEN)
 from make_golden import CASES  # noqa: E402
 
 
-def certificates(g, mat, h, W, st):
-    """The residuals of the list above for a state st (dict of arrays)."""
+def certificates(g, mat, h, W, st, cerruti=False):
+    """The residuals of the list above for a state st (dict of arrays).
+    cerruti: the normal surface displacement includes the one of the
+    tangential traction (taken from boussinesq_apply)."""
     E, nu = mat["E"], mat["nu"]
     nx, ny = g["nx"], g["ny"]
     p = st["traction"][2]
     Hm = h - st["u3p"]
-    u = oc.apply_compliance(p, oc.surface_compliance_symbol(g, E, nu))
+    if cerruti:
+        u = ops.boussinesq_apply(g, E, nu, st["traction"])["disp"][2, 0]
+    else:
+        u = oc.apply_compliance(p, oc.surface_compliance_symbol(g, E, nu))
     gap = u - Hm
     gap = gap - gap[p > 0].mean()
     dA = g["lx"] * g["ly"] / (nx * ny)
@@ -95,7 +101,37 @@ def test_algorithm1_fresh_run_certificates_on_a_paraboloid():
 # outer tolerance (1e-11 of |H0|_2) -- visible on the rough case, whose
 # profile has a small max|h| against its L2 norm; Hertz cases reach 1e-12.
 STORED = {"hertz_ep_16x16x8": 1e-12, "rough_ep_16x16x8": 1e-10, "hertz_graded_ep_16x16x8": 1e-12,
-          "hertz_friction_ep_16x16x8": 1e-12, "c1_32x32x16": 1e-12}
+          "hertz_friction_ep_16x16x8": 1e-12, "hertz_cerruti_ep_16x16x8": 1e-12, "c1_32x32x16": 1e-12}
+
+
+def friction_certificates(g, mat, W, st, mu_f, q_ratio, cerruti):
+    """Coulomb partial slip of the stored tangential traction: |q| <= mu_f p,
+    total force q_ratio mu_f W, one rigid shift of the stick zone and slip
+    against q on the friction limit, the tangential surface displacement
+    taken from boussinesq_apply (of q alone for Goodman's uncoupled form,
+    of the whole traction with the Cerruti cross terms)."""
+    E, nu = mat["E"], mat["nu"]
+    T = np.array(st["traction"])
+    if not cerruti:
+        T[2] = 0.0
+    ut = ops.boussinesq_apply(g, E, nu, T)["disp"][:2, 0]
+    q, p = st["traction"][:2], st["traction"][2]
+    dA = g["lx"] * g["ly"] / (g["nx"] * g["ny"])
+    qa = np.hypot(q[0], q[1])
+    rho = mu_f * p
+    c = p > 0
+    stick = c & (qa < rho * (1 - 1e-6))
+    slip = c & ~stick
+    scale = np.abs(ut[:, c]).max()
+    delta = ut[:, stick].mean(axis=1)
+    sv = ut[:, slip] - delta[:, None]
+    qs = q[:, slip]
+    return {"outside": float(np.max(qa - rho * (1 + 1e-12))),
+            "force": float(np.max(np.abs(dA * q.sum(axis=(1, 2)) - np.array(q_ratio) * mu_f * W)) / (mu_f * W)),
+            "stick": float(np.max(np.abs(ut[:, stick] - delta[:, None])) / scale),
+            "along": float(np.max(np.sum(sv * qs, axis=0) / np.hypot(qs[0], qs[1])) / scale),
+            "across": float(np.max(np.abs(sv[0] * qs[1] - sv[1] * qs[0]) / np.hypot(qs[0], qs[1])) / scale),
+            "n_stick": int(stick.sum()), "n_slip": int(slip.sum())}
 
 
 @pytest.mark.parametrize("name", sorted(STORED))
@@ -111,15 +147,23 @@ def test_stored_oracle_state_satisfies_the_certificates(name):
         g["z"] = d["z"]
     steps = int(d["steps_done"]) if "steps_done" in d else len(c["W"])
     st = {k: d[k] for k in ("eps_p", "ep", "sigma", "traction", "u3p")}
-    cert, fy, lim = certificates(g, c["mat"], d["h"], c["W"][steps - 1], st)
-    # with friction the normal problem is uncoupled from the tangential one
-    # (Goodman), so the normal certificate applies unchanged
+    fric = c.get("friction")
+    cerruti = bool(fric and fric.get("cerruti"))
+    # with Goodman's friction the normal problem is uncoupled from the
+    # tangential one, so the frictionless normal certificate applies; with
+    # the Cerruti terms the gap includes the tangential traction's u3
+    cert, fy, lim = certificates(g, c["mat"], d["h"], c["W"][steps - 1], st, cerruti=cerruti)
     assert cert["kkt"] < STORED[name], cert
     assert cert["neg_p"] == 0.0 and cert["load"] < 1e-13, cert
     assert cert["u3p"] < 1e-13, cert
     assert cert["stress"] < 1e-11, cert
     assert cert["outside"] < 1e-13, cert
     assert np.count_nonzero(d["ep"]) > 0
+    if fric:
+        f = friction_certificates(g, c["mat"], c["W"][steps - 1], st, fric["mu_f"], fric["q_ratio"], cerruti)
+        assert f["outside"] <= 0.0 and f["force"] < 1e-12, f
+        assert f["n_stick"] > 0 and f["n_slip"] > 0, f
+        assert f["stick"] < 1e-9 and f["along"] < 1e-9 and f["across"] < 1e-9, f
 
 
 def test_newton_coupling_reaches_the_algorithm1_fixed_point():
