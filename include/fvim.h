@@ -247,6 +247,48 @@ typedef struct {
 int tangential_solve(fvim_ctx* ctx, const double* p, double mu_f, double Qx, double Qy, double tol,
                      int max_iter, double* q, fvim_tangential_info* info);
 
+typedef struct {
+  int iters;              /* alternations of the normal and tangential solves */
+                          /* (1 with coupled = 0)                             */
+  int contact_iters;      /* Polonsky-Keer iterations over all alternations   */
+  int tangential_iters;   /* tangential iterations over all alternations      */
+  double rel_change;      /* last dA sum |dp| / W + dA sum |dq| / (mu_f W)    */
+                          /* between alternations (coupled = 1; else inf)     */
+  double kkt_residual;    /* of the last normal solve, on the surface it saw  */
+                          /* (h - u3 of the tangential traction)              */
+  double stick_fraction;  /* of the last tangential solve                     */
+  double shift[2];        /* rigid tangential shift of the stick zone         */
+} fvim_frictional_info;
+
+/*
+ * Normal contact under total load W with Coulomb friction and total
+ * tangential force (Qx, Qy), |Q| < mu_f W: the friction Sec. 5.1 says the
+ * contact step can include, with the normal and tangential problems coupled
+ * through the Boussinesq-Cerruti surface response (eqn B:fourier: the
+ * off-diagonal normal/tangential terms of B_00 and B_10, nonzero for
+ * nu < 1/2).  Per in-plane mode the tangential surface displacement of a
+ * pressure is u_a = K_a p and the normal displacement of a tangential
+ * traction u3 = sum_a conj(K_a) q_a, K_a = i (1 - 2 nu) k_a / (2 mu |k|^2)
+ * (zero at k = 0 and on the Nyquist line of axis a).
+ * coupled = 1: the pressure solves contact_solve's problem on h - u3[q],
+ * q solves tangential_solve's problem with the extra displacement u_t[p];
+ * the two solves alternate (each warm-started from the last) until
+ * dA sum |dp| / W + dA sum |dq| / (mu_f W) < tol (the normal solves run to
+ * max(tol / 10, 1e-15), the tangential ones to tol), at most max_iter
+ * alternations (FVIM_ENOCONV; traction then holds the last one).
+ * coupled = 0: Goodman's approximation, contact_solve then tangential_solve
+ * under its pressure (max_iter unused).
+ * h: [ny][nx] device, as for contact_solve.  traction: [3][ny][nx] device,
+ * (q1, q2, p), overwritten with the solution; warm != 0: it holds a
+ * traction to start from (e.g. the solution under a nearby load), else only
+ * its pressure plane is read, as contact_solve's warm start.  FVIM_EINVAL
+ * for mu_f <= 0, W <= 0, |Q| >= mu_f W or bad tolerances.  Blocking; info
+ * (may be NULL) on host.
+ */
+int frictional_contact_solve(fvim_ctx* ctx, const double* h, double W, double mu_f, double Qx, double Qy,
+                             int coupled, double tol, int max_iter, int warm, double* traction,
+                             fvim_frictional_info* info);
+
 /* Elastoplastic state S_n kept between load steps (Sec. 4.2, Alg. 1):
  * device pointers, caller-owned.  eps_p, sigma: tensor fields; ep: scalar
  * field; traction: surface vector [3][ny][nx]; u3p: surface residual
@@ -312,6 +354,13 @@ typedef struct {
                        /* adds 12 nx ny nz + (coupling_krylov + 10) nx ny   */
                        /* doubles                                           */
   int coupling_krylov; /* GMRES steps per Newton step, 1..30 (0 = 10)       */
+  int cerruti;         /* 1 (with mu_f > 0): the contact step couples the   */
+                       /* normal and tangential problems through the        */
+                       /* Boussinesq-Cerruti cross terms, as                */
+                       /* frictional_contact_solve with coupled = 1 and its */
+                       /* tolerance the tangential one above (alternations  */
+                       /* warm-started from the previous pass's traction,   */
+                       /* at most 200); 0: Goodman's uncoupled sequence     */
 } fvim_ep_opts;
 
 typedef struct {

@@ -46,6 +46,12 @@ class _TangentialInfo(ctypes.Structure):
                 ("stick_fraction", ctypes.c_double), ("shift", ctypes.c_double * 2)]
 
 
+class _FrictionalInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("contact_iters", ctypes.c_int), ("tangential_iters", ctypes.c_int),
+                ("rel_change", ctypes.c_double), ("kkt_residual", ctypes.c_double),
+                ("stick_fraction", ctypes.c_double), ("shift", ctypes.c_double * 2)]
+
+
 class _State(ctypes.Structure):
     _fields_ = [("eps_p", ctypes.c_void_p), ("ep", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("traction", ctypes.c_void_p), ("u3p", ctypes.c_void_p)]
@@ -59,15 +65,17 @@ class EPOptions(ctypes.Structure):
                 ("literal_alg1", ctypes.c_int), ("anderson_m", ctypes.c_int),
                 ("warm_start", ctypes.c_int), ("inner_rel", ctypes.c_double),
                 ("krylov_dim", ctypes.c_int), ("mu_f", ctypes.c_double),
-                ("q_ratio", ctypes.c_double * 2), ("coupling", ctypes.c_int), ("coupling_krylov", ctypes.c_int)]
+                ("q_ratio", ctypes.c_double * 2), ("coupling", ctypes.c_int), ("coupling_krylov", ctypes.c_int),
+                ("cerruti", ctypes.c_int)]
 
     def __init__(self, tol_outer=1e-9, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14,
                  max_outer=400, max_plastic=2000, max_contact=20000, solver=0, literal_alg1=0,
                  anderson_m=0, warm_start=0, inner_rel=0.0, krylov_dim=0, mu_f=0.0, q_ratio=(0.0, 0.0),
-                 coupling=0, coupling_krylov=0):
+                 coupling=0, coupling_krylov=0, cerruti=0):
         super().__init__(tol_outer, relax, tol_plastic, tol_contact, max_outer, max_plastic,
                          max_contact, solver, literal_alg1, anderson_m, warm_start, inner_rel,
-                         krylov_dim, mu_f, (ctypes.c_double * 2)(*q_ratio), coupling, coupling_krylov)
+                         krylov_dim, mu_f, (ctypes.c_double * 2)(*q_ratio), coupling, coupling_krylov,
+                         cerruti)
 
 
 class _EPInfo(ctypes.Structure):
@@ -134,6 +142,9 @@ def load_library(path=None):
                                   ctypes.POINTER(_ContactInfo)]
     lib.tangential_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, _P, ctypes.POINTER(_TangentialInfo)]
+    lib.frictional_contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                             ctypes.c_int, _P, ctypes.POINTER(_FrictionalInfo)]
     lib.elastoplastic_solve.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(EPOptions), ctypes.POINTER(_State),
                                         ctypes.POINTER(_EPInfo)]
@@ -361,6 +372,25 @@ class Context:
         return q, {"iters": info.iters, "rel_change": info.rel_change, "stick_fraction": info.stick_fraction,
                    "shift": (info.shift[0], info.shift[1])}
 
+    def frictional_contact_solve(self, h, W, mu_f, Q, coupled=True, tol=1e-13, max_iter=200, traction=None,
+                                 warm=False):
+        """Normal contact with Coulomb friction: the surface traction
+        (3, ny, nx) = (q1, q2, p) for the load W and tangential force Q,
+        coupled through the Cerruti cross terms or (coupled=False) in
+        Goodman's sequence.  traction: warm start when warm, else its
+        pressure plane is contact_solve's warm start (zeros: uniform)."""
+        sh = self.surface_shape
+        if traction is None:
+            traction = torch.zeros((3,) + sh, dtype=torch.float64, device=h.device)
+        info = _FrictionalInfo()
+        _check(_LIB.frictional_contact_solve(self._h, _ptr(h, sh, "h"), float(W), float(mu_f), float(Q[0]),
+                                             float(Q[1]), int(bool(coupled)), float(tol), int(max_iter),
+                                             int(bool(warm)), _ptr(traction, (3,) + sh, "traction"),
+                                             ctypes.byref(info)))
+        out = {f: getattr(info, f) for f, _ in _FrictionalInfo._fields_ if f != "shift"}
+        out["shift"] = (info.shift[0], info.shift[1])
+        return traction, out
+
     def new_state(self, device="cuda"):
         z = lambda s: torch.zeros(s, dtype=torch.float64, device=device)
         return {"eps_p": z(self.tensor_shape), "ep": z(self.scalar_shape), "sigma": z(self.tensor_shape),
@@ -464,6 +494,10 @@ def contact_solve(ctx, h, W, **kw):
 
 def tangential_solve(ctx, p, mu_f, Q, **kw):
     return ctx.tangential_solve(p, mu_f, Q, **kw)
+
+
+def frictional_contact_solve(ctx, h, W, mu_f, Q, **kw):
+    return ctx.frictional_contact_solve(h, W, mu_f, Q, **kw)
 
 
 def elastoplastic_solve(ctx, h, W_steps, state, opts=None):

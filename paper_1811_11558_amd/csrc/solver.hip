@@ -677,6 +677,8 @@ static int sw_ensure(fvim_ctx* c) {
   return FVIM_OK;
 }
 
+int solver_reserve(fvim_ctx* c) { return sw_ensure(c); }
+
 void solver_release(fvim_ctx* c) {
   SolverWork* w = c->sw;
   if (!w) return;
@@ -1628,6 +1630,46 @@ static int sdot(fvim_ctx* c, const double* a, const double* b, double out[3]) {
   return FVIM_OK;
 }
 
+// Alternations of the coupled normal-tangential contact step (each one a
+// normal and a tangential solve); the coupling contracts fast (the cross
+// compliance is a fraction (1 - 2 nu) / (2 - 2 nu) of the normal one).
+constexpr int CERRUTI_MAX = 200;
+
+// The contact step of one outer pass on the surface H under the load Wn:
+// the pressure into T[2] (warm-started from what it holds) and, with
+// friction, the tangential traction into T[0], T[1]: Goodman's sequence
+// (the normal solve, then the tangential one under its pressure) or, with
+// o->cerruti, the alternation coupled through the Boussinesq-Cerruti cross
+// terms.  warm: T[0], T[1] hold the previous pass's tangential traction.
+static int contact_step(fvim_ctx* c, const fvim_ep_opts* o, const double* H, double Wn, double* T, bool warm,
+                        double tol_f, fvim_ep_info& inf) {
+  const size_t n = c->sw->ns;
+  const double Qx = o->q_ratio[0] * o->mu_f * Wn, Qy = o->q_ratio[1] * o->mu_f * Wn;
+  int rc;
+  if (o->cerruti && o->mu_f > 0 && Wn > 0) {
+    fvim_frictional_info fi{};
+    rc = frictional_solve(c, H, Wn, o->mu_f, Qx, Qy, 1, tol_f, o->tol_contact, tol_f, o->max_contact, CERRUTI_MAX,
+                          T, warm, &fi);
+    if (rc) return rc;
+    inf.contact_iters += fi.contact_iters + fi.tangential_iters;
+    inf.kkt = fi.kkt_residual;
+    return FVIM_OK;
+  }
+  double* pcur = T + 2 * n;
+  fvim_contact_info ci;
+  rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
+  if (rc) return rc;
+  inf.contact_iters += ci.iters;
+  inf.kkt = ci.kkt_residual;
+  if (o->mu_f > 0 && Wn > 0) {
+    fvim_tangential_info fi;
+    rc = friction_solve(c, pcur, o->mu_f, Qx, Qy, tol_f, o->max_contact, T, &fi, warm);
+    if (rc) return rc;
+    inf.contact_iters += fi.iters;
+  }
+  return FVIM_OK;
+}
+
 struct PassBufs {
   const double* H0;
   double* H;          // modified surface of the pass
@@ -1643,20 +1685,9 @@ static int pass_map(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, Pla
                     const double* x, double* dU, bool warm, fvim_ep_info& inf) {
   SolverWork* w = c->sw;
   const size_t n = w->ns;
-  double* pcur = q.T + 2 * n;
   axpy(c, q.H, q.H0, -1.0, x, n);                       // H = H0 - x
-  fvim_contact_info ci;
-  int rc = pk_solve(c, q.H, q.Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
+  int rc = contact_step(c, o, q.H, q.Wn, q.T, warm, std::max(o->tol_contact, 1e-13), inf);
   if (rc) return rc;
-  inf.contact_iters += ci.iters;
-  inf.kkt = ci.kkt_residual;
-  if (o->mu_f > 0 && q.Wn > 0) {
-    fvim_tangential_info fi;
-    rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * q.Wn, o->q_ratio[1] * o->mu_f * q.Wn,
-                        std::max(o->tol_contact, 1e-13), o->max_contact, q.T, &fi, warm);
-    if (rc) return rc;
-    inf.contact_iters += fi.iters;
-  }
   axpy(c, q.dT, q.T, -1.0, s->traction, 3 * n);           // dT = T - T_n
   int it, ne;
   double res;
@@ -1834,7 +1865,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       o->coupling < 0 || o->coupling > 1 || o->coupling_krylov < 0 || o->coupling_krylov > 30 ||
       o->anderson_m > AA_MMAX || !(o->inner_rel >= 0) || o->solver < 0 || o->solver > 2 || o->krylov_dim < 0 ||
       o->krylov_dim > KMAX - 2 || !(o->mu_f >= 0) || !std::isfinite(o->mu_f) ||
-      (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)))
+      (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)) || o->cerruti < 0 || o->cerruti > 1)
     return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
   int rc = sw_ensure(c);
   if (rc) return rc;
@@ -1895,26 +1926,17 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       if (!conv) return cleanup(fail(FVIM_ENOCONV, "outer Newton-Krylov: iteration limit reached"));
     }
     for (k = 1; k <= o->max_outer && o->coupling != 1; ++k) {
-      fvim_contact_info ci;
-      rc = pk_solve(c, H, Wn, o->tol_contact, o->max_contact, pcur, nullptr, &ci);
-      if (rc) return cleanup(rc);
-      inf.contact_iters += ci.iters;
-      inf.kkt = ci.kkt_residual;
       // inexact inner solves (plasticity, and the tangential contact with
       // friction) while the outer error is large; a pass that may end the
       // step is always solved to the full tolerances
       const bool loose = o->inner_rel > 0 && !(err_prev < o->tol_outer);
       const double tol_f_full = std::max(o->tol_contact, 1e-13);
       double tol_f = tol_f_full;
-      if (o->mu_f > 0 && Wn > 0) {                         // tangential traction into T[0], T[1]
-        if (loose) tol_f = std::max(tol_f, o->inner_rel * err_prev);
-        fvim_tangential_info fi;
-        // from the second pass on, T holds the previous pass's traction
-        rc = friction_solve(c, pcur, o->mu_f, o->q_ratio[0] * o->mu_f * Wn, o->q_ratio[1] * o->mu_f * Wn, tol_f,
-                            o->max_contact, T, &fi, k > 1);
-        if (rc) return cleanup(rc);
-        inf.contact_iters += fi.iters;
-      }
+      if (o->mu_f > 0 && Wn > 0 && loose) tol_f = std::max(tol_f, o->inner_rel * err_prev);
+      // the pressure into T[2]; with friction the tangential traction into
+      // T[0], T[1] (from the second pass on, T holds the previous pass's)
+      rc = contact_step(c, o, H, Wn, T, k > 1, tol_f, inf);
+      if (rc) return cleanup(rc);
       axpy(c, dT, T, -1.0, s->traction, 3 * n);           // dT = T - T_n
       double tol_rel = o->tol_plastic;
       if (loose) tol_rel = std::max(tol_rel, o->inner_rel * err_prev);

@@ -106,8 +106,29 @@ int friction_reserve(fvim_ctx* c);
 size_t friction_footprint(const fvim_grid* g);
 // warm: q_out holds a previous solution to start from (projected onto the
 // new constraint set); else the start is the scaled full-slip field.
+// ue: when not NULL, a tangential displacement [2][nx ny] of other loads
+// added to C q (the pressure's, with the Cerruti cross terms).
 int friction_solve(fvim_ctx* c, const double* p, double mu_f, double Qx, double Qy, double tol, int max_iter,
-                   double* q_out, fvim_tangential_info* info, bool warm = false);
+                   double* q_out, fvim_tangential_info* info, bool warm = false, const double* ue = nullptr);
+// Polonsky-Keer on the context stream.  p: in warm start (all zero ->
+// uniform), out solution.  gap may be NULL.
+int pk_solve(fvim_ctx* c, const double* h, double W, double tol, int max_iter, double* p, double* gap,
+             fvim_contact_info* info);
+// Allocates the contact solver's workspace now (not inside a solve).
+int solver_reserve(fvim_ctx* c);
+// Normal contact with Coulomb friction into T = (q0, q1, p) [3][nx ny]:
+// Goodman's sequence (coupled 0: the normal solve, then the tangential one)
+// or the alternation coupled through the Cerruti cross terms (coupled 1)
+// until dA sum |dp| / W + dA sum |dq| / (mu_f W) < tol.  Normal solves to
+// tol_contact, tangential ones to tol_f, each at most max_contact
+// iterations; at most max_iter alternations.  warm: T holds a traction to
+// start from (else the pressure is still read as contact_solve's warm start
+// and q is ignored).
+int frictional_solve(fvim_ctx* c, const double* h, double W, double mu_f, double Qx, double Qy, int coupled,
+                     double tol, double tol_contact, double tol_f, int max_contact, int max_iter, double* T,
+                     bool warm, fvim_frictional_info* info);
+// frictional_solve's workspaces, allocated now.
+int frictional_reserve(fvim_ctx* c);
 // Device bytes the Newton-Krylov solver adds when opts selects it (0 else).
 size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o);
 // out = base - T (u1 - u2) for the voxels v < na of each component

@@ -432,7 +432,8 @@ def test_c1_paraboloid_matches_stored_oracle(solver):
 
 
 @pytest.mark.parametrize("name,bound", [("hertz_ep_16x16x8", 1e-11), ("hertz_graded_ep_16x16x8", 1e-11),
-                                        ("hertz_friction_ep_16x16x8", 1e-11), ("rough_ep_16x16x8", 1e-10)])
+                                        ("hertz_friction_ep_16x16x8", 1e-11), ("hertz_cerruti_ep_16x16x8", 1e-11),
+                                        ("rough_ep_16x16x8", 1e-10)])
 def test_newton_coupling_reaches_the_stored_fixed_point(name, bound):
     """The outer Newton-Krylov coupling (coupling = 1) ends on the fixed point
     of Algorithm 1 stored by tests/golden/make_golden.py (the oracle's
@@ -454,7 +455,8 @@ def test_newton_coupling_reaches_the_stored_fixed_point(name, bound):
     ctx = Context(g, m["E"], m["nu"], m["sigma_y0"], m["E_h"])
     if "z" in ref:
         ctx.set_depth_nodes(ref["z"])
-    fr = dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"]) if "friction" in c else {}
+    fr = (dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"],
+               cerruti=int(c["friction"].get("cerruti", False))) if "friction" in c else {})
     st = ctx.new_state()
     infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
                                     EPOptions(tol_outer=1e-13, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15,
