@@ -86,4 +86,47 @@ struct FftPlan1D {
   void* tw;              // device twiddle table exp(-2 pi i k / n), k < n
 };
 
+// Lane moves that stay in the vector unit (DPP, no LDS round trip): within
+// rows of 16 lanes, lane i takes lane i + d (DOWN) or i - d (UP) of its row,
+// 0 when that lane is outside the row; WAVE_DOWN1 / WAVE_UP1 move by one
+// lane across the whole wave (0 past either end); SWAP1 exchanges the
+// values of lanes 2j and 2j + 1.  readlane broadcasts one lane's value.
+// Doubles move as two 32-bit halves.
+enum : int {
+  DPP_ROW_DOWN = 0x100,
+  DPP_ROW_UP = 0x110,
+  DPP_WAVE_DOWN1 = 0x130,
+  DPP_WAVE_UP1 = 0x138,
+  DPP_SWAP1 = 0xB1          // quad_perm (1, 0, 3, 2)
+};
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL, typename T>
+__device__ __forceinline__ cpx<T> dpp_move(cpx<T> v) {
+  return mk(dpp_move<CTRL>(v.x), dpp_move<CTRL>(v.y));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> lane_value(cpx<T> v, int lane) {
+  return mk(lane_value(v.x, lane), lane_value(v.y, lane));
+}
+
 }  // namespace fvim

@@ -101,6 +101,112 @@ __device__ __forceinline__ cpx<T> sh_idx(cpx<T> v, int src) {
   return mk(__shfl(v.x, src, LPM), __shfl(v.y, src, LPM));
 }
 
+// x^e for 1 <= e <= 31 by squaring
+template <typename T>
+__device__ __forceinline__ T powi(T x, int e) {
+  T p = T(1);
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    if (e & 1) p *= x;
+    x *= x;
+    e >>= 1;
+  }
+  return p;
+}
+
+// The two scans of the depth pass over a 64-lane group (one wave) on
+// uniform nodes, each lane holding P nodes: per lane step the propagator is
+// rl = r^P with Jordan shift sl = P s.  Reverse (growing coordinates): the
+// suffix Y(l) = sum over j >= l of Rb^(j - l) A_j with Rb = rl [[1, -sl],
+// [0, 1]] on (Y2, Y3) and rl on YP; forward (decaying): the prefix
+// F(l) = sum over j <= l of Rf^(l - j) a_j with Rf = rl [[1, sl], [0, 1]].
+// Kogge-Stone within each row of 16 lanes by DPP moves, then the rows'
+// totals combined in order from broadcast lane values (3 sequential steps)
+// and carried into every lane with the power of the propagator for its
+// distance to the neighbouring row.
+template <int D, typename T>
+__device__ __forceinline__ void rev_row_step(cpx<T>& Y2, cpx<T>& Y3, cpx<T>& YP, T rk, T ks, int lr) {
+  const cpx<T> o2 = dpp_move<DPP_ROW_DOWN + D>(Y2), o3 = dpp_move<DPP_ROW_DOWN + D>(Y3);
+  const cpx<T> op = dpp_move<DPP_ROW_DOWN + D>(YP);
+  const T wk = (lr + D < 16) ? rk : T(0);
+  Y2 = add(Y2, scl(axpy(o2, -ks, o3), wk));
+  Y3 = add(Y3, scl(o3, wk));
+  YP = add(YP, scl(op, wk));
+}
+template <int D, typename T>
+__device__ __forceinline__ void fwd_row_step(cpx<T>& F0, cpx<T>& F1, cpx<T>& FM, T rk, T ks, int lr) {
+  const cpx<T> o0 = dpp_move<DPP_ROW_UP + D>(F0), o1 = dpp_move<DPP_ROW_UP + D>(F1);
+  const cpx<T> om = dpp_move<DPP_ROW_UP + D>(FM);
+  const T wk = (lr >= D) ? rk : T(0);
+  F0 = add(F0, scl(axpy(o0, ks, o1), wk));
+  F1 = add(F1, scl(o1, wk));
+  FM = add(FM, scl(om, wk));
+}
+
+template <typename T>
+__device__ __forceinline__ void reverse_scan64(cpx<T>& Y2, cpx<T>& Y3, cpx<T>& YP, T rl, T sl, int l) {
+  const int lr = l & 15, row = l >> 4;
+  T rk = rl, ks = sl;
+  rev_row_step<1>(Y2, Y3, YP, rk, ks, lr);
+  rk *= rk; ks += ks;
+  rev_row_step<2>(Y2, Y3, YP, rk, ks, lr);
+  rk *= rk; ks += ks;
+  rev_row_step<4>(Y2, Y3, YP, rk, ks, lr);
+  rk *= rk; ks += ks;
+  rev_row_step<8>(Y2, Y3, YP, rk, ks, lr);
+  rk *= rk; ks += ks;                       // rl^16, 16 sl: one row
+  // complete suffixes at the starts of rows 3, 2, 1
+  cpx<T> t2 = lane_value(Y2, 48), t3 = lane_value(Y3, 48), tp = lane_value(YP, 48);
+  cpx<T> c2 = t2, c3 = t3, cp = tp;        // carry for row 2
+  t2 = add(lane_value(Y2, 32), scl(axpy(t2, -ks, t3), rk));
+  t3 = add(lane_value(Y3, 32), scl(t3, rk));
+  tp = add(lane_value(YP, 32), scl(tp, rk));
+  if (row == 1) { c2 = t2; c3 = t3; cp = tp; }
+  t2 = add(lane_value(Y2, 16), scl(axpy(t2, -ks, t3), rk));
+  t3 = add(lane_value(Y3, 16), scl(t3, rk));
+  tp = add(lane_value(YP, 16), scl(tp, rk));
+  if (row == 0) { c2 = t2; c3 = t3; cp = tp; }
+  if (row < 3) {
+    const int dist = 16 - lr;
+    const T wk = powi(rl, dist), kd = (T)dist * sl;
+    Y2 = add(Y2, scl(axpy(c2, -kd, c3), wk));
+    Y3 = add(Y3, scl(c3, wk));
+    YP = add(YP, scl(cp, wk));
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void forward_scan64(cpx<T>& F0, cpx<T>& F1, cpx<T>& FM, T rl, T sl, int l) {
+  const int lr = l & 15, row = l >> 4;
+  T rk = rl, ks = sl;
+  fwd_row_step<1>(F0, F1, FM, rk, ks, lr);
+  rk *= rk; ks += ks;
+  fwd_row_step<2>(F0, F1, FM, rk, ks, lr);
+  rk *= rk; ks += ks;
+  fwd_row_step<4>(F0, F1, FM, rk, ks, lr);
+  rk *= rk; ks += ks;
+  fwd_row_step<8>(F0, F1, FM, rk, ks, lr);
+  rk *= rk; ks += ks;
+  // complete prefixes at the ends of rows 0, 1, 2
+  cpx<T> t0 = lane_value(F0, 15), t1 = lane_value(F1, 15), tm = lane_value(FM, 15);
+  cpx<T> c0 = t0, c1 = t1, cm = tm;        // carry for row 1
+  t0 = add(lane_value(F0, 31), scl(axpy(t0, ks, t1), rk));
+  t1 = add(lane_value(F1, 31), scl(t1, rk));
+  tm = add(lane_value(FM, 31), scl(tm, rk));
+  if (row == 2) { c0 = t0; c1 = t1; cm = tm; }
+  t0 = add(lane_value(F0, 47), scl(axpy(t0, ks, t1), rk));
+  t1 = add(lane_value(F1, 47), scl(t1, rk));
+  tm = add(lane_value(FM, 47), scl(tm, rk));
+  if (row == 3) { c0 = t0; c1 = t1; cm = tm; }
+  if (row > 0) {
+    const int dist = lr + 1;
+    const T wk = powi(rl, dist), kd = (T)dist * sl;
+    F0 = add(F0, scl(axpy(c0, kd, c1), wk));
+    F1 = add(F1, scl(c1, wk));
+    FM = add(FM, scl(cm, wk));
+  }
+}
+
 // Modal loads of one node from the rotated eigenstress/mu (in-plane part
 // (f0, f1) decaying, (f2, f3) growing; antiplane fm decaying, fp growing).
 template <typename T>
@@ -151,6 +257,8 @@ template <typename T, int LPM, int P, bool DISP, bool WANTX, bool NYQ, bool NTL 
 __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out,
                                             const DepthParams& prm, int block) {
   constexpr int GPB = NT / LPM;
+  // one wave per mode on uniform nodes: the scans and lane moves use DPP
+  constexpr bool DPPS = LPM == 64 && !NU;
   const int g = threadIdx.x / LPM;
   const int l = threadIdx.x - g * LPM;
   const int gid = block * GPB + g;
@@ -335,7 +443,10 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     // rotated loads of the next lane's first node (zero past the last node)
     cpx<T> on[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) on[c] = sh_down<T, LPM>(o[0][c], 1);
+    for (int c = 0; c < 5; ++c) {
+      if constexpr (DPPS) on[c] = dpp_move<DPP_WAVE_DOWN1>(o[0][c]);
+      else on[c] = sh_down<T, LPM>(o[0][c], 1);
+    }
 
     // ---- backward (growing) recurrence inside the lane, zero carry ----
     cpx<T> M2[P], M3[P], MP[P];
@@ -366,7 +477,9 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     }
     // ---- reverse scan across lanes: Y_l = A_l + Rb^P Y_(l+1) ----
     cpx<T> Y2 = M2[0], Y3 = M3[0], YP = MP[0];
-    {
+    if constexpr (DPPS) {
+      reverse_scan64<T>(Y2, Y3, YP, rP, (T)P * s, l);
+    } else {
       T rk = NU ? RL : rP, ks = NU ? SL : (T)P * s;
 #pragma unroll
       for (int d = 1; d < LPM; d <<= 1) {
@@ -386,7 +499,16 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
       }
     }
     {
-      cpx<T> C2 = sh_down<T, LPM>(Y2, 1), C3 = sh_down<T, LPM>(Y3, 1), CP = sh_down<T, LPM>(YP, 1);
+      cpx<T> C2, C3, CP;
+      if constexpr (DPPS) {
+        C2 = dpp_move<DPP_WAVE_DOWN1>(Y2);
+        C3 = dpp_move<DPP_WAVE_DOWN1>(Y3);
+        CP = dpp_move<DPP_WAVE_DOWN1>(YP);
+      } else {
+        C2 = sh_down<T, LPM>(Y2, 1);
+        C3 = sh_down<T, LPM>(Y3, 1);
+        CP = sh_down<T, LPM>(YP, 1);
+      }
       if (l == LPM - 1) { C2 = zero<T>(); C3 = zero<T>(); CP = zero<T>(); }
       T rk = NU ? re[NU ? P - 1 : 0] : r, ks = NU ? se[NU ? P - 1 : 0] : s;   // Rb^(P-p) on the carry
 #pragma unroll
@@ -408,7 +530,16 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
     // ---- surface condition: sigma . e3 = -t at z = 0 ----
     cpx<T> bc0, bc1, bcm;
     {
-      cpx<T> g20 = sh_idx<T, LPM>(M2[0], 0), g30 = sh_idx<T, LPM>(M3[0], 0), gp0 = sh_idx<T, LPM>(MP[0], 0);
+      cpx<T> g20, g30, gp0;
+      if constexpr (DPPS) {
+        g20 = lane_value(M2[0], 0);
+        g30 = lane_value(M3[0], 0);
+        gp0 = lane_value(MP[0], 0);
+      } else {
+        g20 = sh_idx<T, LPM>(M2[0], 0);
+        g30 = sh_idx<T, LPM>(M3[0], 0);
+        gp0 = sh_idx<T, LPM>(MP[0], 0);
+      }
       cpx<T> Txi = add(scl(tr[0], n1), scl(tr[1], n2));
       cpx<T> t1bc = mul_i(Txi);                          // -(T_n / i) = i T_n
       cpx<T> t2bc = scl(tr[2], T(-1));
@@ -454,7 +585,9 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
       F1 = add(F1, scl(bc1, rl));
       FM = add(FM, scl(bcm, rl));
     }
-    {
+    if constexpr (DPPS) {
+      forward_scan64<T>(F0, F1, FM, rP, (T)P * s, l);
+    } else {
       T rk = NU ? RL : rP, ks = NU ? SL : (T)P * s;
 #pragma unroll
       for (int d = 1; d < LPM; d <<= 1) {
@@ -473,7 +606,16 @@ __device__ __forceinline__ void depth_modes(const cpx<T>* __restrict__ in, cpx<T
         }
       }
     }
-    cpx<T> D0 = sh_up<T, LPM>(F0, 1), D1 = sh_up<T, LPM>(F1, 1), DM = sh_up<T, LPM>(FM, 1);
+    cpx<T> D0, D1, DM;
+    if constexpr (DPPS) {
+      D0 = dpp_move<DPP_WAVE_UP1>(F0);
+      D1 = dpp_move<DPP_WAVE_UP1>(F1);
+      DM = dpp_move<DPP_WAVE_UP1>(FM);
+    } else {
+      D0 = sh_up<T, LPM>(F0, 1);
+      D1 = sh_up<T, LPM>(F1, 1);
+      DM = sh_up<T, LPM>(FM, 1);
+    }
     if (l == 0) { D0 = bc0; D1 = bc1; DM = bcm; }
 
     // ---- nodal fields, strains, outputs ----

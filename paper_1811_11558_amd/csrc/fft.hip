@@ -427,92 +427,111 @@ __device__ __forceinline__ void x_c2r_body(cpx<T>* buf, double* red, int lb, con
   constexpr int ld = N + 1;
   constexpr int kxh = N / 2 + 1;
   constexpr int nyq = N / 2;
+  const int hp = R / 2;                  // a power of two (R = ny or 2 SEQ)
+  const int lr = __builtin_ctz(R);
+  // one element per lane, consecutive lanes on consecutive rows y of one kx
+  // (runs of R elements); slots past the end repeat the last row pair, which
+  // writes the same values again.  The rows 2 pr, 2 pr + 1 of a pair sit in
+  // lanes 2 j, 2 j + 1 and are exchanged by a DPP lane swap.
+  const int totr = kxh * R;
+  const bool odd = threadIdx.x & 1;
+  const int last = totr - (odd ? 1 : 2);
+  constexpr int MV = (kxh * 2 * SEQ + NT - 1) / NT;
   const size_t row0 = (size_t)lb * R;
   const int plane = (int)(row0 / ny);
   const int y0 = (int)(row0 - (size_t)plane * ny);
-  const int hp = R / 2;                  // a power of two (R = ny or 2 SEQ)
-  const int lhp = __builtin_ctz(hp);
-  const int tot = kxh * hp;
-  // all loads first (slots past the end repeat the last pair, which writes
-  // the same values again), then the LDS writes
-  constexpr int MV = (kxh * SEQ + NT - 1) / NT;
-  cpx<T> v0[MV], v1[MV];
+  cpx<T> v[MV];
+  {
+    const cpx<T>* src = in + (size_t)plane * kxh * ny + y0;
 #pragma unroll
-  for (int u = 0; u < MV; ++u) {
-    const int i = min((int)threadIdx.x + u * NT, tot - 1);
-    const int k = i >> lhp, pr = i - (k << lhp);
-    const size_t a = ((size_t)plane * kxh + k) * ny + y0 + 2 * pr;
-    v0[u] = in[a];
-    v1[u] = in[a + 1];
-  }
-#pragma unroll
-  for (int u = 0; u < MV; ++u) {
-    const int i = min((int)threadIdx.x + u * NT, tot - 1);
-    const int k = i >> lhp, pr = i - (k << lhp);
-    const cpx<T> X0 = v0[u], X1 = v1[u];
-    if (k == 0 || k == nyq) {
-      buf[pr * ld + k] = mk(X0.x, X1.x);
-    } else {
-      buf[pr * ld + k] = mk(X0.x - X1.y, X0.y + X1.x);
-      buf[pr * ld + N - k] = mk(X0.x + X1.y, X1.x - X0.y);
+    for (int u = 0; u < MV; ++u) {
+      const int i = min((int)threadIdx.x + u * NT, last);
+      const int k = i >> lr, y = i & (R - 1);
+      v[u] = src[(size_t)k * ny + y];
     }
   }
-  __syncthreads();
-  lds_fft<T, LOGN, SEQ, true, RADIX>(buf, ld, hp, tw);
-  int s = 0;
-  while (s + 1 < seg.n && plane >= seg.first[s + 1]) ++s;
-  double* dst = seg.ptr[s] + ((size_t)(plane - seg.first[s]) * ny + y0) * N;
-  const double add = padd ? padd[plane] : 0.0;
-  const int tot2 = R * N / 2;
-  double2* d2 = reinterpret_cast<double2*>(dst);
-  if (!ep.x) {
-    // The operator's outputs are not read again by the operator, so they
-    // are stored as streaming (non-temporal) writes, which do not displace
-    // the spectrum buffers from the last-level cache.  Measured at
-    // 256^2 x 64 float64: this kernel 92.8 -> 71.7 us, the whole
-    // application 0.427 -> 0.421 ms (the column transforms, whose buffers
-    // the cache then holds differently, lose part of the gain).  The
-    // contact solver's compliance, read at once by the next kernel, keeps
-    // ordinary stores.
+  {
+#pragma unroll
+    for (int u = 0; u < MV; ++u) {
+      const int i = min((int)threadIdx.x + u * NT, last);
+      const int k = i >> lr, pr = (i & (R - 1)) >> 1;
+      const cpx<T> o = dpp_move<DPP_SWAP1>(v[u]);
+      const cpx<T> X0 = odd ? o : v[u], X1 = odd ? v[u] : o;
+      if (k == 0 || k == nyq) {
+        if (!odd) buf[pr * ld + k] = mk(X0.x, X1.x);
+      } else if (!odd) {
+        buf[pr * ld + k] = mk(X0.x - X1.y, X0.y + X1.x);
+      } else {
+        buf[pr * ld + N - k] = mk(X0.x + X1.y, X1.x - X0.y);
+      }
+    }
+    __syncthreads();
+    lds_fft<T, LOGN, SEQ, true, RADIX>(buf, ld, hp, tw);
+    int s = 0;
+    while (s + 1 < seg.n && plane >= seg.first[s + 1]) ++s;
+    double* dst = seg.ptr[s] + ((size_t)(plane - seg.first[s]) * ny + y0) * N;
+    const double add = padd ? padd[plane] : 0.0;
     typedef double v2d __attribute__((ext_vector_type(2)));
-    for (int i = threadIdx.x; i < tot2; i += NT) {
-      int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
-      const cpx<T>* b = buf + (r >> 1) * ld + x;
-      v2d o;
-      if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
-      else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
-      if (nts) __builtin_nontemporal_store(o, reinterpret_cast<v2d*>(d2 + i));
-      else *reinterpret_cast<v2d*>(d2 + i) = o;
+    if (!ep.x) {
+      // Each thread stores one x pair of a row pair: the real parts of the
+      // two LDS elements it reads go to row 2 pr, their imaginary parts to
+      // row 2 pr + 1.  The operator's outputs are not read again by the
+      // operator, so they are stored as streaming (non-temporal) writes,
+      // which do not displace the spectrum buffers from the last-level
+      // cache; the contact solver's compliance, read at once by the next
+      // kernel, keeps ordinary stores.
+      const int tot4 = hp * (N / 2);
+      for (int i = threadIdx.x; i < tot4; i += NT) {
+        const int pr = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
+        const cpx<T>* b = buf + pr * ld + x;
+        const cpx<T> b0 = b[0], b1 = b[1];
+        v2d o0, o1;
+        o0.x = (double)b0.x * scale + add;
+        o0.y = (double)b1.x * scale + add;
+        o1.x = (double)b0.y * scale + add;
+        o1.y = (double)b1.y * scale + add;
+        v2d* q0 = reinterpret_cast<v2d*>(dst) + (size_t)(2 * pr) * (N / 2) + (x >> 1);
+        v2d* q1 = q0 + (N / 2);
+        if (nts) {
+          __builtin_nontemporal_store(o0, q0);
+          __builtin_nontemporal_store(o1, q1);
+        } else {
+          *q0 = o0;
+          *q1 = o1;
+        }
+      }
+    } else {
+      // residual epilogue (the residual is the first and only segment)
+      const int tot2 = R * N / 2;
+      double2* d2 = reinterpret_cast<double2*>(dst);
+      const size_t off = ((size_t)plane * ny + y0) * N;
+      const double2* x2 = reinterpret_cast<const double2*>(ep.x + off);
+      const double2* f2 = ep.Fo ? reinterpret_cast<const double2*>(ep.Fo + off) : nullptr;
+      double s0 = 0.0, s1 = 0.0;
+      for (int i = threadIdx.x; i < tot2; i += NT) {
+        int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
+        const cpx<T>* b = buf + (r >> 1) * ld + x;
+        double2 o;
+        if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
+        else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
+        const double2 xv = x2[i];
+        const double2 rr = make_double2(xv.x - o.x, xv.y - o.y);
+        d2[i] = rr;
+        s0 += rr.x * rr.x + rr.y * rr.y;
+        if (f2) {
+          const double2 f = f2[i];
+          s1 += f.x * (rr.x - f.x) + f.y * (rr.y - f.y);
+        }
+      }
+      const double a = block_sum(s0, red);
+      const double c = block_sum(s1, red);
+      if (threadIdx.x == 0) {
+        const int cp = plane / ep.nz, z = plane - cp * ep.nz;
+        const double wt = (cp < 3 ? 1.0 : 2.0) * (ep.wz ? ep.wz[z] : ((z == 0 || z == ep.nz - 1) ? 0.5 : 1.0));
+        ep.part[2 * lb] = wt * a;
+        ep.part[2 * lb + 1] = wt * c;
+      }
     }
-    return;
-  }
-  // residual epilogue (the residual is the first and only segment)
-  const size_t off = ((size_t)plane * ny + y0) * N;
-  const double2* x2 = reinterpret_cast<const double2*>(ep.x + off);
-  const double2* f2 = ep.Fo ? reinterpret_cast<const double2*>(ep.Fo + off) : nullptr;
-  double s0 = 0.0, s1 = 0.0;
-  for (int i = threadIdx.x; i < tot2; i += NT) {
-    int r = (2 * i) >> LOGN, x = (2 * i) & (N - 1);
-    const cpx<T>* b = buf + (r >> 1) * ld + x;
-    double2 o;
-    if (r & 1) { o.x = (double)b[0].y * scale + add; o.y = (double)b[1].y * scale + add; }
-    else { o.x = (double)b[0].x * scale + add; o.y = (double)b[1].x * scale + add; }
-    const double2 xv = x2[i];
-    const double2 rr = make_double2(xv.x - o.x, xv.y - o.y);
-    d2[i] = rr;
-    s0 += rr.x * rr.x + rr.y * rr.y;
-    if (f2) {
-      const double2 f = f2[i];
-      s1 += f.x * (rr.x - f.x) + f.y * (rr.y - f.y);
-    }
-  }
-  const double a = block_sum(s0, red);
-  const double c = block_sum(s1, red);
-  if (threadIdx.x == 0) {
-    const int cp = plane / ep.nz, z = plane - cp * ep.nz;
-    const double wt = (cp < 3 ? 1.0 : 2.0) * (ep.wz ? ep.wz[z] : ((z == 0 || z == ep.nz - 1) ? 0.5 : 1.0));
-    ep.part[2 * lb] = wt * a;
-    ep.part[2 * lb + 1] = wt * c;
   }
 }
 
@@ -638,7 +657,8 @@ __global__ __launch_bounds__(NT) void k_x_c2r_batch(XformBatch b) {
   const cpx<T>* in = static_cast<const cpx<T>*>(b.in[c]);
   const cpx<T>* tw = static_cast<const cpx<T>*>(b.tw[c]);
 #define CALL(L) \
-  x_c2r_body<T, L, 1, 4>(buf, red, lb, in, b.oseg[c], b.ny[c], b.R[c], 1.0, tw, b.padd[c], ResidEpilogue{}, b.nts[c] != 0)
+  x_c2r_body<T, L, 1, 4>(buf, red, lb, in, b.oseg[c], b.ny[c], b.R[c], 1.0, tw, b.padd[c], ResidEpilogue{}, \
+                         b.nts[c] != 0)
   FVIM_BATCH_LOGN_SWITCH(b.logn[c], CALL)
 #undef CALL
 }
