@@ -15,7 +15,9 @@ The oracle is written to be read against the paper, not to be fast:
                       (B00, B10), the gradient recurrence and the jump term
                       (Sec. 2.2-2.3).
 * ``depth``        -- exact P1 element integrals of g0/g1 (Sec. 3.2,
-                      eqns int_g0 / int_g1), no cutoff.
+                      eqns int_g0 / int_g1), no cutoff; dense element-pair
+                      matrices, and the same sums by depth recurrences
+                      (the fast mode, pinned to the dense one).
 * ``operators``    -- mindlin_apply / boussinesq_apply: DFT per layer
                       (Sec. 3.1), dense O(N3^2) depth sums per mode
                       (eqn full_discrete_convolution, eqn 2gradient),
@@ -30,7 +32,8 @@ The oracle is written to be read against the paper, not to be fast:
 * ``friction``     -- tangential (Coulomb, partial-slip) contact under a
                       given pressure, the friction Sec. 5.1 says can be
                       added: projected gradient with momentum on the
-                      complementary energy.
+                      complementary energy; the normal-tangential coupling
+                      through the Boussinesq-Cerruti cross terms.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against things the
 oracle does not compute itself: an independent high-precision state-space

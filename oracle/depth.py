@@ -21,6 +21,15 @@ per mode (the paper's "naive" count, Sec. 3.2).
 The moments M_n(a) = int_{-1}^{1} t^n exp(a t) dt are taken from their
 closed forms for |a| >= 2 and from their Taylor series otherwise, so no
 cancellation occurs for small q * e.
+
+``depth_sum`` is the fast form of the same sums (the oracle-fast mode): the
+kernel of each branch is exp(-q d) and d exp(-q d) in the distance d
+between target and element centre, so the sum over the elements on one
+side of a target follows from the sum at the neighbouring target by one
+multiplication with exp(-q h) (h the node spacing) and the new element's
+term -- a forward recurrence for the elements above, a backward one for
+those below.  Same element integrals, same operator, O(N3) per mode; it is
+checked against element_matrices on every grid of its tests.
 """
 import math
 import numpy as np
@@ -88,3 +97,51 @@ def element_matrices(q, z):
                 d0[:, :, node] += i0
                 d1[:, :, node] += i1
     return d0p, d1p, d0m, d1m
+
+
+def depth_sum(q, z, c, branch, k):
+    """D @ c for D = element_matrices(q, z)[(branch, k)] without forming D
+    (branch "+": elements above the target, "-": below; k = 0: g0, 1: g1).
+
+    q: (M,) wavenumbers; c: (M, nz, ...) nodal coefficients (any trailing
+    shape).  Returns an array shaped like c.
+    """
+    q = np.asarray(q, dtype=float)
+    z = np.asarray(z, dtype=float)
+    c = np.asarray(c)
+    nz = z.size
+    M = q.size
+    tail = (1,) * (c.ndim - 2)
+    qb = q.reshape((M,) + tail)
+    out = np.zeros(c.shape, dtype=np.result_type(c, float))
+    if nz < 2:
+        return out
+    sgn = 1.0 if branch == "+" else -1.0
+    H = np.diff(z)                                  # element lengths
+    P = np.zeros((M,) + c.shape[2:], dtype=out.dtype)
+    Q = np.zeros_like(P)
+    B = np.zeros_like(P)
+    order = range(nz - 1) if branch == "+" else range(nz - 2, -1, -1)
+    mom = {}                                        # moments per distinct element length
+    for e in order:
+        eh = 0.5 * H[e]
+        if eh not in mom:
+            mom[eh] = moments(sgn * q * eh)
+        m0, m1, m2 = mom[eh]
+        g00, g01 = eh * 0.5 * (m0 - m1), eh * 0.5 * (m0 + m1)
+        g10, g11 = -q * eh * eh * 0.5 * (m1 - m2), -q * eh * eh * 0.5 * (m1 + m2)
+        A = g00.reshape((M,) + tail) * c[:, e] + g01.reshape((M,) + tail) * c[:, e + 1]
+        Bn = g10.reshape((M,) + tail) * c[:, e] + g11.reshape((M,) + tail) * c[:, e + 1]
+        rH = np.exp(-qb * H[e])
+        rh = np.exp(-qb * eh)
+        # move the running sums one element further from the targets, then
+        # add element e (distance eh from the next target)
+        Q = rH * (Q + H[e] * P) + eh * rh * A
+        P = rH * P + rh * A
+        B = rH * B + rh * Bn
+        i = e + 1 if branch == "+" else e           # the target these sums now serve
+        if k == 0:
+            out[:, i] = P
+        else:
+            out[:, i] = sgn * qb * Q + B
+    return out

@@ -32,7 +32,7 @@ import numpy as np
 
 from . import elastic
 from . import fundamental as fs
-from .depth import element_matrices
+from .depth import depth_sum, element_matrices
 
 
 def depth_nodes(nz, lz):
@@ -58,8 +58,12 @@ def hooke_full(eps, lam, mu):
     return lam * tr[..., None, None] * np.eye(3) + 2.0 * mu * eps
 
 
-def mode_response(q1, q2, w_hat, t_hat, z, E, nu):
+def mode_response(q1, q2, w_hat, t_hat, z, E, nu, sums="dense"):
     """Per-mode response for modes with q != 0.
+
+    sums: "dense" forms the O(N3^2) element-pair matrices (the paper's naive
+    count); "recurrence" takes the same sums by depth.depth_sum in O(N3)
+    (the oracle-fast mode).
 
     q1, q2: (M,) wavevectors; w_hat: (M, nz, 3, 3) eigenstress coefficients
     (symmetric); t_hat: (M, 3) surface traction coefficients (force per area
@@ -70,8 +74,15 @@ def mode_response(q1, q2, w_hat, t_hat, z, E, nu):
     q, grads = fs.kelvin_gradients(q1, q2, mu, nu)
     jump = fs.kelvin_jump(q1, q2, mu, nu)
     _, b00, b10, b01, b11 = fs.boussinesq_gradient(q1, q2, mu, nu)
-    d0p, d1p, d0m, d1m = element_matrices(q, z)
-    D = {('+', 0): d0p, ('+', 1): d1p, ('-', 0): d0m, ('-', 1): d1m}
+    if sums == "dense":
+        d0p, d1p, d0m, d1m = element_matrices(q, z)
+        D = {('+', 0): d0p, ('+', 1): d1p, ('-', 0): d0m, ('-', 1): d1m}
+
+        def dsum(br, k, c):
+            return np.einsum('mij,mj...->mi...', D[(br, k)], c)
+    else:
+        def dsum(br, k, c):
+            return depth_sum(q, z, c, br, k)
 
     # full-space part: displacement (n = 1) and its gradient (n = 2)
     grad_u = np.zeros(w_hat.shape, dtype=complex)
@@ -82,8 +93,8 @@ def mode_response(q1, q2, w_hat, t_hat, z, E, nu):
         for k, t1, t2 in ((0, u01, u02), (1, u11, u12)):
             c1 = np.einsum('mabc,mjbc->mja', t1, w_hat)
             c2 = np.einsum('mabcd,mjbc->mjad', t2, w_hat)
-            u -= np.einsum('mij,mja->mia', D[(br, k)], c1)
-            grad_u -= q[:, None, None, None] * np.einsum('mij,mjad->miad', D[(br, k)], c2)
+            u -= dsum(br, k, c1)
+            grad_u -= q[:, None, None, None] * dsum(br, k, c2)
     grad_u[..., :, 2] -= np.einsum('mabc,mibc->mia', jump, w_hat)
 
     # surface traction of the full-space field, and what the half-space adds
@@ -148,7 +159,7 @@ def sampled_dft(f, modes):
 
 
 def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
-          chunk=256, modes=None, direct_dft=True):
+          chunk=256, modes=None, direct_dft=True, sums="dense"):
     """Strain, stress, displacement and surface u3 of u = M[t] + N[C:eps_p].
 
     grid: dict nx, ny, nz, lx, ly, lz (and optionally z, the depth nodes).  eps_p: (6, nz, ny, nx) stored
@@ -159,10 +170,14 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
     coefficients are returned instead (keys strain_hat, stress_hat,
     disp_hat, each (len(modes), nz, ...)); their input coefficients come
     from sampled_dft, or with direct_dft=False from the full FFT of every
-    plane (the full-field path restricted to those bins).
+    plane (the full-field path restricted to those bins).  sums: the depth
+    sums of mode_response ("recurrence" is the oracle-fast mode, with
+    chunks of 4096 modes unless chunk is given otherwise).
     """
     if modes is not None and direct_dft:
         return apply_modes(grid, E, nu, eps_p, traction, modes, k0_policy)
+    if sums != "dense" and chunk == 256:
+        chunk = 4096
     nx, ny, nz = grid['nx'], grid['ny'], grid['nz']
     lx, ly, lz = grid['lx'], grid['ly'], grid['lz']
     lam, mu = elastic.lame(E, nu)
@@ -192,7 +207,7 @@ def apply(grid, E, nu, eps_p=None, traction=None, k0_policy="include",
         wg = np.array([r[4] for r in blk])
         wm = np.moveaxis(W[:, ky, kx], 0, 1)                  # (M, nz, 3, 3)
         tm = t_hat[:, ky, kx].T                               # (M, 3)
-        g, u = mode_response(q1, q2, wm, tm, z, E, nu)
+        g, u = mode_response(q1, q2, wm, tm, z, E, nu, sums=sums)
         np.add.at(grad, (ky, kx), wg[:, None, None, None] * g)
         np.add.at(disp, (ky, kx), wg[:, None, None] * u)
 

@@ -383,3 +383,40 @@ def test_sampled_path_matches_full_path():
     b = operators.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes, direct_dft=False)
     for k in ("strain_hat", "stress_hat", "disp_hat"):
         assert np.max(np.abs(a[k] - b[k])) <= 1e-13 * np.max(np.abs(b[k])), k
+
+
+# ---------------------------------------------------------------- oracle-fast
+# The fast mode takes the same element sums by recurrences over the depth
+# nodes (oracle/depth.py depth_sum); it is pinned to the dense element-pair
+# matrices, which the tests above pin to the state-space solve.
+
+@pytest.mark.parametrize("graded", [False, True])
+def test_depth_sum_recurrence_equals_the_element_matrices(graded):
+    from oracle.depth import depth_sum, element_matrices
+    rng = np.random.default_rng(3)
+    nz = 11
+    z = 0.3 * (np.arange(nz) / (nz - 1)) ** (2.0 if graded else 1.0)
+    q = np.array([1e-3, 0.2, 2.0, 17.0, 150.0, 900.0])
+    D = dict(zip((("+", 0), ("+", 1), ("-", 0), ("-", 1)), element_matrices(q, z)))
+    c = rng.standard_normal((q.size, nz, 3, 3)) + 1j * rng.standard_normal((q.size, nz, 3, 3))
+    for key, mat in D.items():
+        ref = np.einsum("mij,mjab->miab", mat, c)
+        got = depth_sum(q, z, c, *key)
+        scale = np.abs(ref).max(axis=(1, 2, 3), keepdims=True)
+        assert np.max(np.abs(got - ref) / scale) <= 1e-13, key
+
+
+@pytest.mark.parametrize("nx,ny,nz,lx,ly,graded", [(16, 12, 8, 1.0, 1.5, False), (9, 10, 5, 1.0, 1.0, False),
+                                                   (32, 16, 12, 2.0, 1.0, True)])
+def test_fast_operator_equals_dense_operator(nx, ny, nz, lx, ly, graded):
+    """Every output of apply() with the recurrence sums equals the dense
+    oracle's (odd and even sizes, Nyquist bins, graded nodes, k = 0)."""
+    g = grid_dict(nx, ny, nz, lx, ly, 0.25)
+    if graded:
+        g["z"] = 0.25 * (np.arange(nz) / (nz - 1)) ** 2
+    eps = filtered_eigenstrain(g, seed=nx)
+    t = filtered_traction(g, seed=ny)
+    a = operators.apply(g, E, NU, eps_p=eps, traction=t)
+    b = operators.apply(g, E, NU, eps_p=eps, traction=t, sums="recurrence")
+    for k in ("strain", "stress", "disp", "surf_u3"):
+        assert np.linalg.norm(a[k] - b[k]) <= 1e-14 * np.linalg.norm(a[k]), k
