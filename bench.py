@@ -94,6 +94,9 @@ def parse():
     ap.add_argument("--friction", action="store_true",
                     help="solve/rough/area/serve: Coulomb friction (--mu-f, --q-ratio along x) in the contact step")
     ap.add_argument("--q-ratio", type=float, default=0.5, help="friction: tangential load Q / (mu_f W) along x")
+    ap.add_argument("--cerruti", action="store_true",
+                    help="friction: couple the normal and tangential problems through the Boussinesq-Cerruti "
+                         "cross terms (else Goodman's uncoupled form)")
     ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
                     help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
     ap.add_argument("--krylov", type=int, default=0, help="Newton-Krylov: Arnoldi steps per Newton step (0 = 20)")
@@ -267,7 +270,9 @@ SOLVER_NAMES = {0: "dfsane", 1: "picard", 2: "newton_krylov"}
 
 
 def friction_opts(a):
-    return dict(mu_f=a.mu_f, q_ratio=(a.q_ratio, 0.0)) if a.friction else {}
+    if not a.friction:
+        return {}
+    return dict(mu_f=a.mu_f, q_ratio=(a.q_ratio, 0.0), cerruti=1 if a.cerruti else 0)
 
 
 def bench_rough(a):

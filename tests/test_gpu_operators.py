@@ -139,6 +139,30 @@ def test_benchmark_size_sampled_modes():
     ctx.close()
 
 
+def test_benchmark_size_full_field_matches_oracle_fast():
+    """256 x 256 x 64 in the benchmark's pinned launch configuration (depth
+    layout 64 lanes x 1 node, transform choices (0,4) (0,4) (1,8) (1,8),
+    streaming loads): every one of the 4.2M voxels of the fused strain
+    against the oracle's fast mode (the same operator with its depth sums
+    taken by recurrences; about a minute of CPU)."""
+    nx = ny = 256
+    g = grid_dict(nx, ny, 64, 1.0, 1.0, 0.25)
+    eps = filtered_eigenstrain(g, seed=0, decay=0.1, max_abs=1e-3)
+    t = filtered_traction(g, seed=1000, max_abs=1e-2)
+    ctx = _ctx(g)
+    ctx.set_option(ctx.OPT_DEPTH_CONFIG, 4)
+    ctx.set_fft_config([(0, 4), (0, 4), (1, 8), (1, 8)])
+    out = ctx.operator_apply(torch.from_numpy(eps).cuda(), torch.from_numpy(t).cuda(), want=("strain",))
+    torch.cuda.synchronize()
+    got = out["strain"].cpu().numpy()
+    ctx.close()
+    ref = ora.apply(g, E, NU, eps_p=eps, traction=t, sums="recurrence")["strain"]
+    err = _rel(got, ref)
+    worst = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("full-field rel err", err, "max abs err / max abs", worst)
+    assert err <= TOL and worst <= TOL, (err, worst)
+
+
 def test_return_map_matches_oracle():
     g = grid_dict(16, 8, 5)
     rng = np.random.default_rng(12)
