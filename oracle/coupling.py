@@ -30,6 +30,7 @@ Test infrastructure only (see ``oracle/__init__``).
 import numpy as np
 
 from . import contact as oc
+from . import adhesion as ad
 from . import friction as fr
 from . import operators as ops
 from . import plasticity as pl
@@ -169,7 +170,8 @@ def new_state(grid):
 def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3,
                         tol_plastic=1e-13, tol_contact=1e-14, max_outer=500,
                         max_plastic=500, max_contact=5000, solver="dfsane", literal=False,
-                        k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0), tol_friction=1e-13, cerruti=False):
+                        k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0), tol_friction=1e-13, cerruti=False,
+                        adhesion=None):
     """Algorithm 1 for each cumulative load in W_steps; state updated in place.
 
     With mu_f > 0 the contact step also carries Coulomb friction: after the
@@ -182,6 +184,10 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
     cerruti=True the normal and tangential solves are coupled through the
     Boussinesq-Cerruti cross terms (``friction.frictional_contact_solve``,
     warm-started from the previous pass's traction within a step).
+    With adhesion = (sigma0, h0) the contact step is the adhesive contact of
+    ``adhesion.adhesive_contact_solve`` (Dugdale cohesive zone, solved
+    afresh at each pass) and T3 is its total traction (negative in the
+    cohesive zone); not combined with friction.
 
     Returns a list of per-step info dicts."""
     E, nu = mat['E'], mat['nu']
@@ -202,7 +208,14 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
         q_prev = None
         for k in range(1, max_outer + 1):
             T = np.zeros_like(T_n)
-            if mu_f > 0.0 and cerruti:
+            if adhesion is not None:
+                if mu_f > 0.0:
+                    raise ValueError("adhesion with friction is not supported")
+                p, _, ainfo = ad.adhesive_contact_solve(grid, E, nu, H, W, adhesion[0], adhesion[1], tol=tol_contact,
+                                                        max_contact=max_contact)
+                cinfo = ainfo["contact"]
+                T[2] = p
+            elif mu_f > 0.0 and cerruti:
                 Q = np.asarray(q_ratio, dtype=float) * mu_f * W
                 p, T[:2], finfo = fr.frictional_contact_solve(
                     grid, E, nu, H, W, Q, mu_f, coupled=True, tol=tol_friction, tol_contact=tol_contact,
@@ -238,7 +251,7 @@ def elastoplastic_solve(grid, mat, h, W_steps, state, tol_outer=1e-12, relax=0.3
 
 def outer_map(grid, mat, H0, W, state, x, p0=None, tol_plastic=1e-13, tol_contact=1e-14, max_plastic=500,
               max_contact=5000, solver="dfsane", k0_policy="include", mu_f=0.0, q_ratio=(0.0, 0.0),
-              tol_friction=1e-13, cerruti=False, q0=None):
+              tol_friction=1e-13, cerruti=False, q0=None, adhesion=None):
     """One pass of Algorithm 1 as a map of the surface correction x: the
     contact step on the modified surface H0 - x (warm-started from p0),
     with friction the tangential step, the plasticity step for the traction
@@ -248,7 +261,14 @@ def outer_map(grid, mat, H0, W, state, x, p0=None, tol_plastic=1e-13, tol_contac
     step is the coupled normal-tangential solve, warm-started from (p0, q0)."""
     E, nu = mat['E'], mat['nu']
     T = np.zeros_like(state['traction'])
-    if mu_f > 0.0 and cerruti:
+    if adhesion is not None:
+        if mu_f > 0.0:
+            raise ValueError("adhesion with friction is not supported")
+        p, _, ainfo = ad.adhesive_contact_solve(grid, E, nu, H0 - x, W, adhesion[0], adhesion[1], tol=tol_contact,
+                                                max_contact=max_contact)
+        cinfo = ainfo["contact"]
+        T[2] = p
+    elif mu_f > 0.0 and cerruti:
         Q = np.asarray(q_ratio, dtype=float) * mu_f * W
         p, T[:2], finfo = fr.frictional_contact_solve(
             grid, E, nu, H0 - x, W, Q, mu_f, coupled=True, tol=tol_friction, tol_contact=tol_contact,
@@ -270,7 +290,7 @@ def outer_map(grid, mat, H0, W, state, x, p0=None, tol_plastic=1e-13, tol_contac
 def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd_rel=1e-7, krylov=20,
                                max_newton=50, tol_plastic=1e-13, tol_contact=1e-14, max_plastic=500,
                                max_contact=5000, solver="dfsane", k0_policy="include", mu_f=0.0,
-                               q_ratio=(0.0, 0.0), tol_friction=1e-13, cerruti=False):
+                               q_ratio=(0.0, 0.0), tol_friction=1e-13, cerruti=False, adhesion=None):
     """The fixed point of Algorithm 1 by Newton's method instead of relaxed
     alternation: for each cumulative load, F(x) = G(x) - x = 0 with G the
     pass map ``outer_map`` of the surface correction x, each Newton system
@@ -284,7 +304,7 @@ def elastoplastic_solve_newton(grid, mat, h, W_steps, state, tol_outer=1e-12, fd
     from scipy.sparse.linalg import LinearOperator, gmres
     kw = dict(tol_plastic=tol_plastic, tol_contact=tol_contact, max_plastic=max_plastic,
               max_contact=max_contact, solver=solver, k0_policy=k0_policy, mu_f=mu_f, q_ratio=q_ratio,
-              tol_friction=tol_friction, cerruti=cerruti)
+              tol_friction=tol_friction, cerruti=cerruti, adhesion=adhesion)
     infos = []
     for W in W_steps:
         H0 = h - state['u3p']

@@ -47,6 +47,11 @@ CASES = {
     "hertz_cerruti_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
                                      mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1),
                                      friction=dict(mu_f=0.3, q_ratio=(0.5, 0.2), cerruti=True)),
+    # the Hertz case with adhesion in the contact step: Dugdale cohesive
+    # zone of stress sigma0 = 0.01 E (the yield stress) and range h0 = 0.003 L
+    "hertz_adhesion_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
+                                      mat=dict(E=1.0, nu=0.3, sigma_y0=0.01, E_h=0.1),
+                                      adhesion=(0.01, 0.003)),
     # the Hertz case on depth nodes graded toward the surface,
     # z_i = lz (i / (nz - 1))^2
     "hertz_graded_ep_16x16x8": dict(grid=(16, 16, 8, 0.25), R=2.0, W=[0.001, 0.002], relax=0.3,
@@ -64,6 +69,14 @@ CASES = {
 # oscillates on these cases; see the design notes).
 OPTS = dict(tol_outer=1e-11, tol_plastic=1e-13, tol_contact=1e-15, max_outer=400, max_plastic=2000,
             max_contact=20000, literal=False)
+
+
+def contact_options(c):
+    """Friction and adhesion settings of a case, as elastoplastic_solve takes them."""
+    out = dict(c.get("friction", {}))
+    if "adhesion" in c:
+        out["adhesion"] = c["adhesion"]
+    return out
 
 
 def run(name, resume=False):
@@ -104,12 +117,12 @@ def run(name, resume=False):
         for k, W in enumerate(c["W"]):
             if k < first:
                 continue
-            infos += cp.elastoplastic_solve(g, mat, h, [W], st, relax=c["relax"], **OPTS, **c.get("friction", {}))
+            infos += cp.elastoplastic_solve(g, mat, h, [W], st, relax=c["relax"], **OPTS, **contact_options(c))
             save(name, c, g, h, st, infos, time.time() - t0, extra, k + 1)
             print(name, "step %d: %.1f s, %d outer passes" % (k + 1, time.time() - t0, infos[-1]["outer_iters"]),
                   flush=True)
         return
-    infos = cp.elastoplastic_solve(g, mat, h, c["W"], st, relax=c["relax"], **OPTS, **c.get("friction", {}))
+    infos = cp.elastoplastic_solve(g, mat, h, c["W"], st, relax=c["relax"], **OPTS, **contact_options(c))
     save(name, c, g, h, st, infos, time.time() - t0, extra, len(c["W"]))
     print(name, "%.1f s" % (time.time() - t0), [i["outer_iters"] for i in infos])
 

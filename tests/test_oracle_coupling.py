@@ -101,7 +101,33 @@ def test_algorithm1_fresh_run_certificates_on_a_paraboloid():
 # outer tolerance (1e-11 of |H0|_2) -- visible on the rough case, whose
 # profile has a small max|h| against its L2 norm; Hertz cases reach 1e-12.
 STORED = {"hertz_ep_16x16x8": 1e-12, "rough_ep_16x16x8": 1e-10, "hertz_graded_ep_16x16x8": 1e-12,
-          "hertz_friction_ep_16x16x8": 1e-12, "hertz_cerruti_ep_16x16x8": 1e-12, "c1_32x32x16": 1e-12}
+          "hertz_friction_ep_16x16x8": 1e-12, "hertz_cerruti_ep_16x16x8": 1e-12, "hertz_adhesion_ep_16x16x8": 1e-12,
+          "c1_32x32x16": 1e-12}
+
+
+def adhesion_certificates(g, mat, h, W, st, sigma0, h0):
+    """Dugdale cohesive-zone contact on the surface h - U3p for the stored
+    total traction p: with the gap from boussinesq_apply, the cohesive set
+    C = {gap <= h0}, p = -sigma0 off contact in C, p = 0 outside C, the
+    repulsive part p_c = p + sigma0 1_C >= 0, gap = 0 where p_c > 0 and
+    >= 0 everywhere, the load.  The contact set is where p is neither 0 nor
+    -sigma0."""
+    E, nu = mat["E"], mat["nu"]
+    p = st["traction"][2]
+    Hm = h - st["u3p"]
+    u3 = ops.boussinesq_apply(g, E, nu, st["traction"])["disp"][2, 0]
+    tiny = 1e-12 * sigma0
+    Ic = (np.abs(p) > tiny) & (np.abs(p + sigma0) > tiny)
+    gap = u3 - Hm
+    gap -= gap[Ic].mean()
+    C = gap <= h0
+    pc = p + sigma0 * C
+    scale = np.max(np.abs(Hm))
+    dA = g["lx"] * g["ly"] / (g["nx"] * g["ny"])
+    return {"kkt_on": float(np.max(np.abs(gap[Ic])) / scale), "kkt_off": float(max(0.0, -np.min(gap)) / scale),
+            "pc_min": float(np.min(pc) / sigma0), "pc_contact_min": float(np.min(pc[Ic]) / sigma0), "cohesive_off": float(np.max(np.abs(p[C & ~Ic] + sigma0)) / sigma0),
+            "outside": float(np.max(np.abs(p[~C])) / sigma0), "load": abs(dA * p.sum() - W) / W,
+            "n_contact": int(Ic.sum()), "n_cohesive_off": int((C & ~Ic).sum())}
 
 
 def friction_certificates(g, mat, W, st, mu_f, q_ratio, cerruti):
@@ -149,6 +175,16 @@ def test_stored_oracle_state_satisfies_the_certificates(name):
     st = {k: d[k] for k in ("eps_p", "ep", "sigma", "traction", "u3p")}
     fric = c.get("friction")
     cerruti = bool(fric and fric.get("cerruti"))
+    if "adhesion" in c:
+        # the normal certificate of adhesive contact replaces the
+        # frictionless one
+        a = adhesion_certificates(g, c["mat"], d["h"], c["W"][steps - 1], st, *c["adhesion"])
+        assert a["kkt_on"] < 1e-12 and a["kkt_off"] < 1e-12, a
+        assert a["pc_min"] >= 0 and a["pc_contact_min"] > 0 and a["cohesive_off"] < 1e-12 and a["outside"] < 1e-12 and a["load"] < 1e-12, a
+        assert a["n_contact"] > 0 and a["n_cohesive_off"] > 0, a
+        cert, fy, lim = certificates(g, c["mat"], d["h"], c["W"][steps - 1], st)
+        assert cert["u3p"] < 1e-13 and cert["stress"] < 1e-11 and cert["outside"] < 1e-13, cert
+        return
     # with Goodman's friction the normal problem is uncoupled from the
     # tangential one, so the frictionless normal certificate applies; with
     # the Cerruti terms the gap includes the tangential traction's u3
