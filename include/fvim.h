@@ -289,6 +289,34 @@ int frictional_contact_solve(fvim_ctx* ctx, const double* h, double W, double mu
                              int coupled, double tol, int max_iter, int warm, double* traction,
                              fvim_frictional_info* info);
 
+typedef struct {
+  int iters;               /* contact solves (cohesive-set updates)            */
+  int contact_iters;       /* Polonsky-Keer iterations over all solves         */
+  double cohesive_fraction;/* of the surface points: gap <= h0                 */
+  double contact_fraction; /* of the surface points: repulsive pressure > 0    */
+  double adhesive_force;   /* sigma0 dA |C|                                    */
+  double kkt_residual;     /* of the last contact solve                        */
+} fvim_adhesive_info;
+
+/*
+ * Adhesive normal contact under total load W: the adhesion Sec. 5.1 says
+ * the contact step can include, as a Dugdale cohesive zone.  The surfaces
+ * attract with the stress sigma0 wherever the gap is at most the range h0
+ * (the contact zone included; work of adhesion sigma0 h0); where they touch,
+ * a repulsive pressure p_c >= 0 acts (Hertz-Signorini-Moreau conditions on
+ * p_c).  The traction on the body is p = p_c - sigma0 1[gap <= h0] and
+ * dA sum p = W.  Solved by fixed point on the cohesive set C from C = {}:
+ * contact_solve's problem on h + sigma0 M[1_C] under W + sigma0 dA |C| (to
+ * tol, warm-started from the previous solve), then C = {gap <= h0}, until
+ * the set repeats (at most max_iter solves; FVIM_ENOCONV otherwise, p then
+ * holding the last solve's traction).  sigma0 = 0 is frictionless contact.
+ * h, p (output), gap (output, may be NULL): [ny][nx] device.  FVIM_EINVAL
+ * for negative sigma0 or h0, and when W + sigma0 dA |C| is not positive.
+ * Blocking; info (may be NULL) on host.
+ */
+int adhesive_contact_solve(fvim_ctx* ctx, const double* h, double W, double sigma0, double h0, double tol,
+                           int max_iter, double* p, double* gap, fvim_adhesive_info* info);
+
 /* Elastoplastic state S_n kept between load steps (Sec. 4.2, Alg. 1):
  * device pointers, caller-owned.  eps_p, sigma: tensor fields; ep: scalar
  * field; traction: surface vector [3][ny][nx]; u3p: surface residual
@@ -361,6 +389,12 @@ typedef struct {
                        /* tolerance the tangential one above (alternations  */
                        /* warm-started from the previous pass's traction,   */
                        /* at most 200); 0: Goodman's uncoupled sequence     */
+  double adh_sigma0;   /* > 0: adhesion in the contact step: the Dugdale    */
+  double adh_h0;       /* cohesive zone of adhesive_contact_solve (stress   */
+                       /* adh_sigma0, range adh_h0; cohesive set from {} at */
+                       /* each pass, contact solves to tol_contact, at most */
+                       /* 200 set updates); T3 is its total traction.  Not  */
+                       /* with friction (FVIM_EINVAL); 0: no adhesion       */
 } fvim_ep_opts;
 
 typedef struct {

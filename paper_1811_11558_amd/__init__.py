@@ -10,12 +10,12 @@ not been built (``python -m paper_1811_11558_amd.build``).
 """
 from .binding import (Context, FvimError, load_library, contact_info_dict,
                       EPOptions, mindlin_apply, boussinesq_apply, operator_apply,
-                      return_map, contact_solve, tangential_solve, frictional_contact_solve,
+                      return_map, contact_solve, tangential_solve, frictional_contact_solve, adhesive_contact_solve,
                       elastoplastic_solve, Server,
                       admit_index, request_bytes, operator_apply_batch,
                       operator_apply_noalloc, NOALLOC_BYTES)
 
 __all__ = ["Context", "FvimError", "load_library", "contact_info_dict", "EPOptions",
            "mindlin_apply", "boussinesq_apply", "operator_apply", "return_map",
-           "contact_solve", "tangential_solve", "frictional_contact_solve", "elastoplastic_solve", "Server", "admit_index", "request_bytes",
+           "contact_solve", "tangential_solve", "frictional_contact_solve", "adhesive_contact_solve", "elastoplastic_solve", "Server", "admit_index", "request_bytes",
            "operator_apply_batch", "operator_apply_noalloc", "NOALLOC_BYTES"]

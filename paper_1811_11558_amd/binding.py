@@ -52,6 +52,12 @@ class _FrictionalInfo(ctypes.Structure):
                 ("stick_fraction", ctypes.c_double), ("shift", ctypes.c_double * 2)]
 
 
+class _AdhesiveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("contact_iters", ctypes.c_int), ("cohesive_fraction", ctypes.c_double),
+                ("contact_fraction", ctypes.c_double), ("adhesive_force", ctypes.c_double),
+                ("kkt_residual", ctypes.c_double)]
+
+
 class _State(ctypes.Structure):
     _fields_ = [("eps_p", ctypes.c_void_p), ("ep", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("traction", ctypes.c_void_p), ("u3p", ctypes.c_void_p)]
@@ -66,16 +72,16 @@ class EPOptions(ctypes.Structure):
                 ("warm_start", ctypes.c_int), ("inner_rel", ctypes.c_double),
                 ("krylov_dim", ctypes.c_int), ("mu_f", ctypes.c_double),
                 ("q_ratio", ctypes.c_double * 2), ("coupling", ctypes.c_int), ("coupling_krylov", ctypes.c_int),
-                ("cerruti", ctypes.c_int)]
+                ("cerruti", ctypes.c_int), ("adh_sigma0", ctypes.c_double), ("adh_h0", ctypes.c_double)]
 
     def __init__(self, tol_outer=1e-9, relax=0.3, tol_plastic=1e-12, tol_contact=1e-14,
                  max_outer=400, max_plastic=2000, max_contact=20000, solver=0, literal_alg1=0,
                  anderson_m=0, warm_start=0, inner_rel=0.0, krylov_dim=0, mu_f=0.0, q_ratio=(0.0, 0.0),
-                 coupling=0, coupling_krylov=0, cerruti=0):
+                 coupling=0, coupling_krylov=0, cerruti=0, adhesion=None):
         super().__init__(tol_outer, relax, tol_plastic, tol_contact, max_outer, max_plastic,
                          max_contact, solver, literal_alg1, anderson_m, warm_start, inner_rel,
                          krylov_dim, mu_f, (ctypes.c_double * 2)(*q_ratio), coupling, coupling_krylov,
-                         cerruti)
+                         cerruti, *(adhesion if adhesion is not None else (0.0, 0.0)))
 
 
 class _EPInfo(ctypes.Structure):
@@ -145,6 +151,8 @@ def load_library(path=None):
     lib.frictional_contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                              ctypes.c_int, _P, ctypes.POINTER(_FrictionalInfo)]
+    lib.adhesive_contact_solve.argtypes = [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, _P, _P, ctypes.POINTER(_AdhesiveInfo)]
     lib.elastoplastic_solve.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(EPOptions), ctypes.POINTER(_State),
                                         ctypes.POINTER(_EPInfo)]
@@ -391,6 +399,17 @@ class Context:
         out["shift"] = (info.shift[0], info.shift[1])
         return traction, out
 
+    def adhesive_contact_solve(self, h, W, sigma0, h0, tol=1e-14, max_iter=200, want_gap=False):
+        """Adhesive contact (Dugdale cohesive zone): the total traction p
+        (ny, nx) = p_c - sigma0 1[gap <= h0] for the load W."""
+        sh = self.surface_shape
+        p = torch.empty(sh, dtype=torch.float64, device=h.device)
+        gap = torch.empty(sh, dtype=torch.float64, device=h.device) if want_gap else None
+        info = _AdhesiveInfo()
+        _check(_LIB.adhesive_contact_solve(self._h, _ptr(h, sh, "h"), float(W), float(sigma0), float(h0), float(tol),
+                                           int(max_iter), _ptr(p, sh, "p"), _ptr(gap, sh, "gap"), ctypes.byref(info)))
+        return p, gap, {f: getattr(info, f) for f, _ in _AdhesiveInfo._fields_}
+
     def new_state(self, device="cuda"):
         z = lambda s: torch.zeros(s, dtype=torch.float64, device=device)
         return {"eps_p": z(self.tensor_shape), "ep": z(self.scalar_shape), "sigma": z(self.tensor_shape),
@@ -498,6 +517,10 @@ def tangential_solve(ctx, p, mu_f, Q, **kw):
 
 def frictional_contact_solve(ctx, h, W, mu_f, Q, **kw):
     return ctx.frictional_contact_solve(h, W, mu_f, Q, **kw)
+
+
+def adhesive_contact_solve(ctx, h, W, sigma0, h0, **kw):
+    return ctx.adhesive_contact_solve(h, W, sigma0, h0, **kw)
 
 
 def elastoplastic_solve(ctx, h, W_steps, state, opts=None):

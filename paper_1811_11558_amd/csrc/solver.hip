@@ -314,6 +314,51 @@ __global__ __launch_bounds__(NT) void k_fill(double* x, size_t n, double v) {
 }
 
 // sum of x and of |x|
+// Adhesive contact (Dugdale cohesive zone): h2 = h + s0 u (u = M[1_C])
+__global__ __launch_bounds__(NT) void k_adh_surface(const double* __restrict__ h, const double* __restrict__ u,
+                                                   double s0, double* __restrict__ h2, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) h2[i] = h[i] + s0 * u[i];
+}
+
+// the cohesive set from the gap: C = 1 where gap <= h0; cnt[0] += points
+// whose membership changed, cnt[1] += members (one atomic per block)
+__global__ __launch_bounds__(NT) void k_adh_set(const double* __restrict__ gap, double h0, double* __restrict__ C,
+                                               size_t n, unsigned long long* cnt) {
+  __shared__ unsigned int sh[2][NT / 64];
+  unsigned int ch = 0, in = 0;
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
+    const double c = gap[i] <= h0 ? 1.0 : 0.0;
+    ch += c != C[i];
+    in += c != 0.0;
+    C[i] = c;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    ch += __shfl_down(ch, o, 64);
+    in += __shfl_down(in, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = ch;
+    sh[1][threadIdx.x >> 6] = in;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      a += sh[0][w];
+      b += sh[1][w];
+    }
+    atomicAdd(cnt, a);
+    atomicAdd(cnt + 1, b);
+  }
+}
+
+// total traction p = p_c - s0 C
+__global__ __launch_bounds__(NT) void k_adh_total(const double* __restrict__ pc, const double* __restrict__ C,
+                                                 double s0, double* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) p[i] = pc[i] - s0 * C[i];
+}
+
 __global__ __launch_bounds__(NT) void k_sum_abs(const double* __restrict__ x, size_t n, double* part) {
   double v[2] = {0.0, 0.0};
   for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += (size_t)gridDim.x * NT) {
@@ -615,6 +660,11 @@ struct SolverWork {
   double* cpl = nullptr;
   size_t cpl_count = 0;
   double mdiag = 0.0;           // diagonal of the surface compliance (contact)
+  // adhesive contact: cohesive set, repulsive pressure, modified surface,
+  // compliance and gap [5][ns]; set counters (device) and their host copy
+  double* adh = nullptr;
+  unsigned long long* adh_cnt = nullptr;
+  unsigned long long* adh_hcnt = nullptr;
 };
 
 constexpr int CAP_TRIES = 4;
@@ -700,6 +750,9 @@ void solver_release(fvim_ctx* c) {
   if (w->kry_part) hipFree(w->kry_part);
   if (w->kry_hout) hipHostFree(w->kry_hout);
   if (w->cpl) hipFree(w->cpl);
+  if (w->adh) hipFree(w->adh);
+  if (w->adh_cnt) hipFree(w->adh_cnt);
+  if (w->adh_hcnt) hipHostFree(w->adh_hcnt);
   for (auto& r : w->rg) {
     if (r.ex) hipGraphExecDestroy(r.ex);
     if (r.g) hipGraphDestroy(r.g);
@@ -716,10 +769,10 @@ void solver_release(fvim_ctx* c) {
 size_t solver_footprint(const fvim_grid* g, size_t V) {
   const size_t ns = (size_t)g->nx * g->ny;
   const size_t nm = (size_t)(g->nx / 2 + 1) * g->ny;
-  // surface arrays (15 + Anderson history 2 AA_MMAX + 3), volume work
+  // surface arrays (15 + Anderson history 2 AA_MMAX + 3 + adhesion 5), volume work
   // arrays (6 tensors + 1 scalar), residual partial sums, compliance
   // spectra, reduction buffers
-  return sizeof(double) * (ns * (18 + 2 * AA_MMAX) + 37 * V + 2 * (size_t)operator_resid_parts(*g)) +
+  return sizeof(double) * (ns * (23 + 2 * AA_MMAX) + 37 * V + 2 * (size_t)operator_resid_parts(*g)) +
          2 * sizeof(cpx<double>) * nm +
          sizeof(double) * aa_nsums(AA_MMAX) * (RB + 2) + 64 * 1024;
 }
@@ -1634,6 +1687,11 @@ static int sdot(fvim_ctx* c, const double* a, const double* b, double out[3]) {
 // normal and a tangential solve); the coupling contracts fast (the cross
 // compliance is a fraction (1 - 2 nu) / (2 - 2 nu) of the normal one).
 constexpr int CERRUTI_MAX = 200;
+// Cohesive-set updates of the adhesive contact step.
+constexpr int ADH_MAX = 200;
+static int adhesion_solve(fvim_ctx* c, const double* h, double W, double sigma0, double h0, double tol,
+                          int max_contact, int max_iter, double* p, double* gap_out, fvim_adhesive_info* info);
+static int adh_ensure(fvim_ctx* c);
 
 // The contact step of one outer pass on the surface H under the load Wn:
 // the pressure into T[2] (warm-started from what it holds) and, with
@@ -1646,6 +1704,18 @@ static int contact_step(fvim_ctx* c, const fvim_ep_opts* o, const double* H, dou
   const size_t n = c->sw->ns;
   const double Qx = o->q_ratio[0] * o->mu_f * Wn, Qy = o->q_ratio[1] * o->mu_f * Wn;
   int rc;
+  if (o->adh_sigma0 > 0) {
+    // the total traction of the adhesive contact (no tangential part)
+    fvim_adhesive_info ai{};
+    hipError_t e = hipMemsetAsync(T, 0, sizeof(double) * 2 * n, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "contact step");
+    rc = adhesion_solve(c, H, Wn, o->adh_sigma0, o->adh_h0, o->tol_contact, o->max_contact, ADH_MAX, T + 2 * n,
+                        nullptr, &ai);
+    if (rc) return rc;
+    inf.contact_iters += ai.contact_iters;
+    inf.kkt = ai.kkt_residual;
+    return FVIM_OK;
+  }
   if (o->cerruti && o->mu_f > 0 && Wn > 0) {
     fvim_frictional_info fi{};
     rc = frictional_solve(c, H, Wn, o->mu_f, Qx, Qy, 1, tol_f, o->tol_contact, tol_f, o->max_contact, CERRUTI_MAX,
@@ -1843,6 +1913,95 @@ static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o,
   return FVIM_OK;
 }
 
+static int adh_ensure(fvim_ctx* c) {
+  SolverWork* w = c->sw;
+  if (w->adh) return FVIM_OK;
+  std::lock_guard<std::recursive_mutex> lk(device_lock());
+  if (hipMalloc((void**)&w->adh, sizeof(double) * 5 * w->ns) != hipSuccess ||
+      hipMalloc((void**)&w->adh_cnt, 2 * sizeof(unsigned long long)) != hipSuccess ||
+      hipHostMalloc((void**)&w->adh_hcnt, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess) {
+    if (w->adh) hipFree(w->adh);
+    if (w->adh_cnt) hipFree(w->adh_cnt);
+    w->adh = nullptr;
+    w->adh_cnt = nullptr;
+    w->adh_hcnt = nullptr;
+    return fail(FVIM_ENOMEM, "adhesive contact workspace allocation failed");
+  }
+  return FVIM_OK;
+}
+
+// Adhesive contact (Dugdale cohesive zone of stress sigma0 and range h0):
+// the cohesive set C by fixed point from C = {} -- the frictionless contact
+// on h + sigma0 M[1_C] under W + sigma0 dA |C| (Polonsky-Keer, warm-started
+// from the previous solve), then C <- {gap <= h0} -- until the set repeats;
+// p = p_c - sigma0 1_C.  gap_out may be NULL.
+static int adhesion_solve(fvim_ctx* c, const double* h, double W, double sigma0, double h0, double tol,
+                          int max_contact, int max_iter, double* p, double* gap_out, fvim_adhesive_info* info) {
+  if (!std::isfinite(W) || !(sigma0 >= 0) || !std::isfinite(sigma0) || !(h0 >= 0) || !std::isfinite(h0) ||
+      !(tol > 0) || max_iter < 1 || max_contact < 1)
+    return fail(FVIM_EINVAL, "adhesive_contact_solve: bad arguments");
+  int rc = sw_ensure(c);
+  if (rc) return rc;
+  if ((rc = adh_ensure(c))) return rc;
+  SolverWork* w = c->sw;
+  hipStream_t st = c->stream;
+  const size_t n = w->ns;
+  const int nb = nblocks(n);
+  const double dA = c->grid.lx * c->grid.ly / (double)n;
+  double* C = w->adh;
+  double* pc = C + n;
+  double* h2 = pc + n;
+  double* u = h2 + n;
+  double* gp = u + n;
+  hipError_t e = hipMemsetAsync(C, 0, sizeof(double) * 2 * n, st);   // C = {}, p_c = 0 (uniform start)
+  if (e != hipSuccess) return fail_hip(e, "adhesive_contact_solve");
+  unsigned long long members = 0;
+  int k = 0, cit = 0;
+  bool conv = false;
+  fvim_contact_info ci{};
+  for (k = 1; k <= max_iter; ++k) {
+    const double* hk = h;
+    if (members > 0) {
+      if ((rc = compliance(c, C, u, st))) return rc;
+      hipLaunchKernelGGL(k_adh_surface, dim3(nb), dim3(NT), 0, st, h, u, sigma0, h2, n);
+      hk = h2;
+    }
+    const double W2 = W + sigma0 * dA * (double)members;
+    if (!(W2 > 0)) return fail(FVIM_EINVAL, "adhesive_contact_solve: the repulsive load W + sigma0 dA |C| must be positive");
+    if ((rc = pk_solve(c, hk, W2, tol, max_contact, pc, gp, &ci))) return rc;
+    cit += ci.iters;
+    e = hipMemsetAsync(w->adh_cnt, 0, 2 * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return fail_hip(e, "adhesive_contact_solve");
+    hipLaunchKernelGGL(k_adh_set, dim3(nb), dim3(NT), 0, st, gp, h0, C, n, w->adh_cnt);
+    {
+      std::lock_guard<std::recursive_mutex> lk(device_lock());     // pinned copy
+      e = hipMemcpyAsync(w->adh_hcnt, w->adh_cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess) return fail_hip(e, "adhesive_contact_solve");
+    const unsigned long long changed = w->adh_hcnt[0];
+    members = w->adh_hcnt[1];
+    if (changed == 0) {
+      conv = true;
+      break;
+    }
+  }
+  if (k > max_iter) k = max_iter;
+  hipLaunchKernelGGL(k_adh_total, dim3(nb), dim3(NT), 0, st, pc, C, sigma0, p, n);
+  if (gap_out && (e = hipMemcpyAsync(gap_out, gp, sizeof(double) * n, hipMemcpyDeviceToDevice, st)) != hipSuccess)
+    return fail_hip(e, "adhesive_contact_solve");
+  if (info) {
+    info->iters = k;
+    info->contact_iters = cit;
+    info->cohesive_fraction = (double)members / (double)n;
+    info->contact_fraction = ci.contact_fraction;
+    info->adhesive_force = sigma0 * dA * (double)members;
+    info->kkt_residual = ci.kkt_residual;
+  }
+  if (!conv) return fail(FVIM_ENOCONV, "adhesive_contact_solve: the cohesive set did not settle");
+  return FVIM_OK;
+}
+
 }  // namespace fvim
 
 using namespace fvim;
@@ -1857,6 +2016,13 @@ int contact_solve(fvim_ctx* c, const double* h, double W, double tol, int max_it
   return pk_solve(c, h, W, tol, max_iter, p, gap, info);
 }
 
+int adhesive_contact_solve(fvim_ctx* c, const double* h, double W, double sigma0, double h0, double tol,
+                           int max_iter, double* p, double* gap, fvim_adhesive_info* info) {
+  if (!c || !h || !p) return fail(FVIM_EINVAL, "NULL argument");
+  if (info) *info = fvim_adhesive_info{};
+  return adhesion_solve(c, h, W, sigma0, h0, tol, 100000, max_iter, p, gap, info);
+}
+
 int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int n_steps, const fvim_ep_opts* o,
                         fvim_state* s, fvim_ep_info* info) {
   if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
@@ -1865,7 +2031,9 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       o->coupling < 0 || o->coupling > 1 || o->coupling_krylov < 0 || o->coupling_krylov > 30 ||
       o->anderson_m > AA_MMAX || !(o->inner_rel >= 0) || o->solver < 0 || o->solver > 2 || o->krylov_dim < 0 ||
       o->krylov_dim > KMAX - 2 || !(o->mu_f >= 0) || !std::isfinite(o->mu_f) ||
-      (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)) || o->cerruti < 0 || o->cerruti > 1)
+      (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)) || o->cerruti < 0 || o->cerruti > 1 ||
+      !(o->adh_sigma0 >= 0) || !std::isfinite(o->adh_sigma0) || !(o->adh_h0 >= 0) || !std::isfinite(o->adh_h0) ||
+      (o->adh_sigma0 > 0 && o->mu_f > 0))
     return fail(FVIM_EINVAL, "elastoplastic_solve: bad options");
   int rc = sw_ensure(c);
   if (rc) return rc;
@@ -1886,6 +2054,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (aam > 0 && (rc = aa_ensure(c))) return rc;
   if (o->solver == 2 && (rc = kry_ensure(c, krylov_dim(o)))) return rc;
   if (o->mu_f > 0 && (rc = friction_reserve(c))) return rc;
+  if (o->adh_sigma0 > 0 && (rc = adh_ensure(c))) return rc;
   if (o->coupling == 1 && (rc = cpl_ensure(c, o))) return rc;
   // every buffer the operator applications of the solve use, sized now: no
   // device memory is freed or allocated while the solve runs
