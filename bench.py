@@ -223,7 +223,9 @@ def bench_copy(a):
 def bench_batch(a):
     """The fused operator (float64) on eight grids of different sizes
     (32^2 x 8 ... 128^2 x 64): one application per context in turn against
-    one batched application that shares the depth-pass launches."""
+    one batched application (one launch per stage for all grids) and against
+    the persistent batched application (one cooperative launch for every
+    stage; FVIM_OPT_PERSISTENT)."""
     import torch
     from paper_1811_11558_amd import Context, operator_apply_batch
     from synth import filtered_eigenstrain, filtered_traction, grid_dict
@@ -246,8 +248,13 @@ def bench_batch(a):
     def batched():
         operator_apply_batch(ctxs, eps, ts)
 
+    def persistent():
+        ctxs[0].set_option(ctxs[0].OPT_PERSISTENT, 1)
+        operator_apply_batch(ctxs, eps, ts)
+        ctxs[0].set_option(ctxs[0].OPT_PERSISTENT, 0)
+
     res = {}
-    for name, fn in (("sequential", sequential), ("batched", batched)):
+    for name, fn in (("sequential", sequential), ("batched", batched), ("persistent", persistent)):
         for _ in range(a.warmup):
             fn()
         torch.cuda.synchronize()
@@ -261,7 +268,8 @@ def bench_batch(a):
     print(json.dumps({"metric": "batched operator voxel-updates/s", "value": vox / (res["batched"] * 1e-3),
                       "unit": "voxel-updates/s", "higher_is_better": True, "n_gpus": 1, "steps": a.steps,
                       "ms_per_batch": res["batched"], "ms_sequential": res["sequential"],
-                      "speedup": res["sequential"] / res["batched"], "dtype": "f64", "data": "synthetic",
+                      "ms_persistent": res["persistent"], "speedup": res["sequential"] / res["batched"],
+                      "speedup_persistent": res["sequential"] / res["persistent"], "dtype": "f64", "data": "synthetic",
                       "config": {"workload": "fused operator on 8 grids: " +
                                  ", ".join("%dx%dx%d" % s_ for s_ in shapes)}}))
 

@@ -477,10 +477,15 @@ int fvim_set_timing(fvim_ctx* ctx, int on);
  * result is recorded for the process under (nx, ny, nz, input and output
  * planes, precision, device architecture) and reused by later contexts
  * that ask for tuning.  Choices change only the summation order of the
- * transforms.
+ * transforms.  FVIM_OPT_PERSISTENT (default 0; read from the first context
+ * of fvim_operator_apply_batch): 1 runs a qualifying batch (float64, strain
+ * output only, every transform length <= 512, at most 8 grids, nz <= 128)
+ * as ONE cooperative persistent launch whose blocks loop over every stage
+ * with a grid barrier between stages; results are bitwise those of the
+ * multi-launch batch, and other batches take the multi-launch path.
  */
 enum { FVIM_OPT_DEPTH_CONFIG = 1, FVIM_OPT_TUNE = 2, FVIM_OPT_GRAPHS = 3, FVIM_OPT_SIDE_STREAM = 4,
-       FVIM_OPT_STREAMING = 5, FVIM_OPT_FFT_CONFIG = 6 };
+       FVIM_OPT_STREAMING = 5, FVIM_OPT_FFT_CONFIG = 6, FVIM_OPT_PERSISTENT = 7 };
 int fvim_set_option(fvim_ctx* ctx, int key, int value);
 int fvim_get_option(fvim_ctx* ctx, int key, int* value);
 int fvim_stage_times(fvim_ctx* ctx, double* ms, int* count);

@@ -233,7 +233,7 @@ class Context:
 
     STAGES = ("x_fwd", "y_fwd", "x_fwd_t", "y_fwd_t", "depth", "y_inv", "x_inv", "depth_nyq")
 
-    OPT_DEPTH_CONFIG, OPT_TUNE, OPT_GRAPHS, OPT_SIDE_STREAM, OPT_STREAMING, OPT_FFT_CONFIG = 1, 2, 3, 4, 5, 6
+    OPT_DEPTH_CONFIG, OPT_TUNE, OPT_GRAPHS, OPT_SIDE_STREAM, OPT_STREAMING, OPT_FFT_CONFIG, OPT_PERSISTENT = 1, 2, 3, 4, 5, 6, 7
 
     def fft_config(self):
         """[(tile, radix)] of the forward row, forward column, inverse column

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfvim.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["fft.hip", "depth.hip", "pointwise.hip", "solver.hip", "friction.hip", "api.hip", "serve.hip"]
+SOURCES = ["fft.hip", "depth.hip", "persist.hip", "pointwise.hip", "solver.hip", "friction.hip", "api.hip", "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -611,6 +612,13 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
   fvim_ctx* c0 = cs[0];
   if ((rc = ctx_reserve(c0, &c0->dbatch, &c0->dbatch_bytes, sizeof(DepthBatch)))) return restore(rc);
   StageTimer tm(c0);
+  // the persistent single-launch form (FVIM_OPT_PERSISTENT): float64, strain
+  // only, every grid within the batched transform lengths, one table each
+  bool persist = c0->persistent && std::is_same<T, double>::value && !stress && !disp && !surf_u3 &&
+                 n <= XFORM_BATCH_MAX && n <= DEPTH_BATCH_MAX;
+  for (int i = 0; i < n && persist; ++i)
+    persist = ilog2i(cs[i]->grid.nx) <= XFORM_BATCH_MAX_LOGN && ilog2i(cs[i]->grid.ny) <= XFORM_BATCH_MAX_LOGN &&
+              !P[i].k0x;
   // Grids whose transform lengths are both at most 2^XFORM_BATCH_MAX_LOGN
   // share one launch per transform stage (up to XFORM_BATCH_MAX grids each,
   // the default choices); longer ones keep launches of their own.
@@ -625,10 +633,10 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
       return restore(rc);
     }
   }
-  // one stage of the batched grids, XFORM_BATCH_MAX at a time
-  auto xform = [&](int kind, int stage) -> int {
-    for (size_t i0 = 0; i0 < bat.size(); i0 += XFORM_BATCH_MAX) {
-      XformBatch b{};
+  // the table of one stage of the batched grids bat[i0 ..], at most
+  // XFORM_BATCH_MAX of them
+  auto fill_xform = [&](int kind, size_t i0, XformBatch& b) {
+      b = XformBatch{};
       b.n = (int)std::min<size_t>(XFORM_BATCH_MAX, bat.size() - i0);
       for (int k = 0; k < b.n; ++k) {
         const int i = bat[i0 + k];
@@ -661,6 +669,12 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
           b.nts[k] = 1;
         }
       }
+  };
+  // one stage of the batched grids, XFORM_BATCH_MAX at a time
+  auto xform = [&](int kind, int stage) -> int {
+    for (size_t i0 = 0; i0 < bat.size(); i0 += XFORM_BATCH_MAX) {
+      XformBatch b;
+      fill_xform(kind, i0, b);
       tm.begin(stage, st);
       hipError_t e = launch_xform_batch<T>(kind, b, st);
       tm.end();
@@ -668,11 +682,11 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
     }
     return FVIM_OK;
   };
-  if ((rc = xform(0, FVIM_STAGE_XFWD)) || (rc = xform(1, FVIM_STAGE_YFWD))) return restore(rc);
   const int cfg = depth_default_config(maxnz);
   const int gpb = depth_groups_per_block(cfg);
-  for (int i0 = 0; i0 < n; i0 += DEPTH_BATCH_MAX) {
-    DepthBatch b{};
+  // the depth table of grids i0 .. i0 + DEPTH_BATCH_MAX - 1
+  auto fill_depth = [&](int i0, DepthBatch& b) {
+    b = DepthBatch{};
     b.n = std::min(DEPTH_BATCH_MAX, n - i0);
     for (int k = 0; k < b.n; ++k) {
       const DepthParams& p = P[i0 + k].prm;
@@ -686,6 +700,23 @@ int operator_apply_batch_t(fvim_ctx* const* cs, int n, const double* const* eps,
       b.first_main[k + 1] = b.first_main[k] + (p.kxh * p.ny + depth_replicas(p.ny, p.kxh) + gpb - 1) / gpb;
       b.first_nyq[k + 1] = b.first_nyq[k] + (p.ny + p.kxh - 1);           // one block per Nyquist mode
     }
+  };
+  if (persist) {
+    // every stage in one cooperative launch (falls through to the launches
+    // below if this batch does not qualify after all)
+    if ((rc = ctx_reserve(c0, &c0->pbatch, &c0->pbatch_bytes, sizeof(OpBatch)))) return restore(rc);
+    OpBatch ob;
+    for (int k = 0; k < 4; ++k) fill_xform(k, 0, ob.x[k]);
+    fill_depth(0, ob.d);
+    hipError_t e = launch_operator_persistent<T>(ob, (OpBatch*)c0->pbatch, cfg, false, false, st);
+    if (e == hipSuccess) return restore(FVIM_OK);
+    if (e != hipErrorNotSupported) return restore(fail_hip(e, "persistent batched operator"));
+    (void)hipGetLastError();
+  }
+  if ((rc = xform(0, FVIM_STAGE_XFWD)) || (rc = xform(1, FVIM_STAGE_YFWD))) return restore(rc);
+  for (int i0 = 0; i0 < n; i0 += DEPTH_BATCH_MAX) {
+    DepthBatch b;
+    fill_depth(i0, b);
     tm.begin(FVIM_STAGE_DEPTH, st);
     hipError_t e = launch_depth_batch<T>(b, (DepthBatch*)c0->dbatch, cfg, st);
     tm.end();
@@ -827,7 +858,7 @@ void fvim_destroy(fvim_ctx* c) {
   else hipDeviceSynchronize();
   if (c->side) hipStreamSynchronize(c->side);
   void* ptrs[] = {c->twx64, c->twy64, c->twx32, c->twy32, c->bufA, c->bufB, c->k0buf, c->mt64, c->mt32, c->dbatch,
-                  c->hz, c->wz};
+                  c->pbatch, c->hz, c->wz};
   for (void* p : ptrs)
     if (p) hipFree(p);
   hipEvent_t evs[] = {c->ev_spec, c->ev_nyq};
@@ -864,6 +895,9 @@ int fvim_set_option(fvim_ctx* c, int key, int value) {
       if (value < 0 || value > 2) return fail(FVIM_EINVAL, "streaming: 0, 1 or 2");
       c->streaming = value;
       return FVIM_OK;
+    case FVIM_OPT_PERSISTENT:
+      c->persistent = value ? 1 : 0;
+      return FVIM_OK;
     case FVIM_OPT_FFT_CONFIG: {
       if (value < 0 || value >= (1 << 12)) return fail(FVIM_EINVAL, "fft config: 12 bits");
       const int prec = c->precision == FVIM_FP32_REFINED ? 1 : 0;
@@ -897,6 +931,9 @@ int fvim_get_option(fvim_ctx* c, int key, int* value) {
       return FVIM_OK;
     case FVIM_OPT_STREAMING:
       *value = c->streaming;
+      return FVIM_OK;
+    case FVIM_OPT_PERSISTENT:
+      *value = c->persistent;
       return FVIM_OK;
     case FVIM_OPT_FFT_CONFIG:
       *value = fft_pack(c, c->precision == FVIM_FP32_REFINED ? 1 : 0);

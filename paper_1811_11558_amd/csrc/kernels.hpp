@@ -126,6 +126,10 @@ struct XformBatch {
 // kind: 0 x_r2c, 1 y_fwd, 2 y_inv, 3 x_c2r
 template <typename T>
 hipError_t launch_xform_batch(int kind, XformBatch& b, hipStream_t st);
+// Fills b.R and b.first of a batched transform (as launch_xform_batch does)
+// and returns the dynamic LDS bytes it needs (0 for an invalid table).
+template <typename T>
+size_t xform_batch_prepare(int kind, XformBatch& b);
 template <typename T>
 int x_r2c_batch_blocks_per_plane(int nx, int ny);
 
@@ -188,6 +192,21 @@ struct DepthBatch {
   void* out[DEPTH_BATCH_MAX];
 };
 void depth_derive(DepthParams& p);
+
+// The whole fused operator application over several grids: the four
+// batched transform tables (x_r2c, y_fwd, y_inv, x_c2r) and the depth table.
+struct OpBatch {
+  XformBatch x[4];
+  DepthBatch d;
+};
+// One cooperative launch runs every stage of the batched application, the
+// blocks looping over each stage's blocks and meeting at a grid barrier
+// between stages (float64, strain output only, depth configurations of
+// nz <= 128).  dev: device copy of the table (sizeof(OpBatch)).  Returns
+// hipErrorNotSupported when the batch does not qualify.
+template <typename T>
+hipError_t launch_operator_persistent(OpBatch& host, OpBatch* dev, int depth_cfg, bool disp, bool wx,
+                                      hipStream_t st);
 // Sign replicas of the Nyquist modes: 2 for each of the ny + kxh - 1 modes on
 // the kx = nx/2 column or the ky = ny/2 row, 2 more for the corner.
 inline int depth_replicas(int ny, int kxh) { return 2 * (ny + kxh); }

@@ -37,10 +37,13 @@ struct fvim_ctx {
   double* wz = nullptr;        //   and their trapezoid weights / the uniform spacing (device)
   void* dbatch = nullptr;      // device copy of a batched depth-pass table
   size_t dbatch_bytes = 0;
+  void* pbatch = nullptr;      // device copy of a persistent batched operator's table
+  size_t pbatch_bytes = 0;
   // optional second stream (default priority) for the Nyquist-mode depth
   // launch beside the main one, with its fork/join events
   int use_side = 0;
   int streaming = 2;            // FVIM_OPT_STREAMING
+  int persistent = 0;           // FVIM_OPT_PERSISTENT (batched applications)
   hipStream_t side = nullptr;
   hipEvent_t ev_spec = nullptr, ev_nyq = nullptr;
   size_t bufA_bytes = 0, bufB_bytes = 0, k0buf_bytes = 0;

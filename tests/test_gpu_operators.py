@@ -320,6 +320,40 @@ def test_batched_operator_uneven_grids():
         c.close()
 
 
+def test_persistent_batched_operator_equals_batched_launches():
+    """The persistent batched operator (FVIM_OPT_PERSISTENT: every stage in
+    one cooperative launch, blocks looping over each stage with a grid
+    barrier between stages) on eight grids of different sizes, nz from 8
+    to 64: bitwise the multi-launch batched application, which matches the
+    oracle."""
+    from paper_1811_11558_amd import Context, operator_apply_batch
+    dev = torch.device("cuda")
+    shapes = [(64, 64, 32), (32, 32, 16), (128, 128, 64), (64, 32, 16), (32, 64, 32), (64, 64, 16),
+              (128, 64, 32), (32, 32, 8)]
+    ctxs, eps, ts = [], [], []
+    for i, (nx, ny, nz) in enumerate(shapes):
+        g = grid_dict(nx, ny, nz, 1.0, 1.0, 0.25)
+        ctxs.append(Context(g, E, NU))
+        eps.append(torch.from_numpy(filtered_eigenstrain(g, seed=i)).to(dev))
+        ts.append(torch.from_numpy(filtered_traction(g, seed=1000 + i)).to(dev))
+    multi = [o["strain"].clone() for o in operator_apply_batch(ctxs, eps, ts)]
+    ctxs[0].set_option(ctxs[0].OPT_PERSISTENT, 1)
+    for rep in range(2):             # the second call reuses the table buffer
+        pers = operator_apply_batch(ctxs, eps, ts)
+        torch.cuda.synchronize()
+        for i, (m, p) in enumerate(zip(multi, pers)):
+            assert torch.equal(m, p["strain"]), (rep, shapes[i])
+    g = grid_dict(*shapes[7], 1.0, 1.0, 0.25)
+    ref = ora.apply(g, E, NU, eps_p=eps[7].cpu().numpy(), traction=ts[7].cpu().numpy())["strain"]
+    assert _rel(pers[7]["strain"].cpu().numpy(), ref) <= TOL
+    # a batch that does not qualify (stress requested) takes the launches
+    out = operator_apply_batch(ctxs[:2], eps[:2], ts[:2], want=("strain", "stress"))
+    torch.cuda.synchronize()
+    assert torch.equal(out[0]["strain"], multi[0])
+    for c in ctxs:
+        c.close()
+
+
 def test_batched_operator_more_than_eight_contexts_and_fp32():
     """Eleven contexts (two depth launches of at most eight grids each) in
     float64, and the same grids in the FP32-refined precision against their
