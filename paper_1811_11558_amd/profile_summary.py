@@ -33,14 +33,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1811_11558_amd", "csrc")
 
 # kernel source of each stage; the hash also covers the shared headers
-SOURCE_OF_STAGE = {"x_fwd": "fft.hip", "y_fwd": "fft.hip", "x_fwd_t": "fft.hip", "y_fwd_t": "fft.hip",
-                   "depth": "depth.hip", "depth_nyq": "depth.hip", "y_inv": "fft.hip", "x_inv": "fft.hip"}
+FFT_SOURCES = ("fft.hip", "fft_dev.hpp")
+DEPTH_SOURCES = ("depth.hip", "depth_dev.hpp")
+SOURCE_OF_STAGE = {"x_fwd": FFT_SOURCES, "y_fwd": FFT_SOURCES, "x_fwd_t": FFT_SOURCES, "y_fwd_t": FFT_SOURCES,
+                   "depth": DEPTH_SOURCES, "depth_nyq": DEPTH_SOURCES, "y_inv": FFT_SOURCES, "x_inv": FFT_SOURCES}
 HEADERS = ("common.hpp", "kernels.hpp")
 
 
-def source_sha(name):
+def source_sha(names):
+    """Hash of the files that hold a stage's kernels (the launching
+    translation unit and its device bodies) and of the shared headers."""
     h = hashlib.sha256()
-    for f in (name,) + HEADERS:
+    for f in tuple(names) + HEADERS:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
