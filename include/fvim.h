@@ -373,7 +373,8 @@ typedef struct {
   int coupling;        /* 0: Algorithm 1 (relaxation, or Anderson with      */
                        /* anderson_m); 1: its fixed point G(x) = x on the   */
                        /* surface correction x by Newton-Krylov: GMRES on   */
-                       /* (J_G - I) d = x - G(x) with J_G v formed by       */
+                       /* (J_G - I) d = x - G(x) to the Eisenstat-Walker    */
+                       /* forcing term (in [1e-3, 0.5]), J_G v formed by   */
                        /* forward differences of G (one full pass each,     */
                        /* started from the pass at x), steps halved until   */
                        /* |G(x) - x| decreases; same stopping test and      */

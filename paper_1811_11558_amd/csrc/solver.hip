@@ -1813,10 +1813,24 @@ static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o,
   *conv = fn / hn < o->tol_outer;
   int k = 0;
   const double fd_rel = 3e-7;
+  // Forcing term eta of the inexact Newton steps (Eisenstat and Walker 1996,
+  // their second choice: eta = 0.9 (|F_k| / |F_k-1|)^2, kept at least
+  // 0.9 eta_prev^2 when that exceeds 0.1), between 1e-3 (about the accuracy
+  // of a forward-difference product) and 0.5, and no smaller than the outer
+  // tolerance asks for at the last steps.
+  double eta = 0.5, fprev = fn;
   while (!*conv && k < o->max_outer) {
+    if (k > 0) {
+      const double r = fn / fprev;
+      double en = 0.9 * r * r;
+      const double sg = 0.9 * eta * eta;
+      if (sg > 0.1) en = std::max(en, sg);
+      eta = std::min(0.5, std::max(1e-3, en));
+    }
+    eta = std::min(0.5, std::max(eta, 0.5 * o->tol_outer * hn / fn));
     if ((rc = save_base())) return rc;
     // GMRES on (J_G - I) d = -F from d = 0, classical Gram-Schmidt applied
-    // twice, Givens rotations on the host; relative tolerance 1e-3
+    // twice, Givens rotations on the host; relative tolerance eta
     std::vector<double> Hh((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), gv(m + 1, 0.0);
     gv[0] = fn;
     // v_0 = -F / |F| (the right-hand side -F = |F| v_0)
@@ -1861,7 +1875,7 @@ static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o,
       Hh[(size_t)(j + 1) * m + j] = 0.0;
       gv[j + 1] = -sn[j] * gv[j];
       gv[j] = cs[j] * gv[j];
-      const bool done = std::fabs(gv[j + 1]) <= 1e-3 * fn || !(hnext > 1e-14 * fn);
+      const bool done = std::fabs(gv[j + 1]) <= eta * fn || !(hnext > 1e-14 * fn);
       if (!done) hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(NT), 0, st, vn, wv, 1.0 / hnext - 1.0, wv, n);
       if (done) {
         ++j;
@@ -1902,6 +1916,7 @@ static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o,
     double xx[3];
     if ((rc = sdot(c, x, x, xx))) return rc;
     xn = xx[1];
+    fprev = fn;
     fn = fnew;
     ++k;
     *conv = fn / hn < o->tol_outer;
