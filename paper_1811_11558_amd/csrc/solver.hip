@@ -1717,9 +1717,12 @@ static int contact_step(fvim_ctx* c, const fvim_ep_opts* o, const double* H, dou
     return FVIM_OK;
   }
   if (o->cerruti && o->mu_f > 0 && Wn > 0) {
+    // the normal solves to a tenth of the alternation's tolerance (not below
+    // 1e-15), as frictional_contact_solve does: solved only to that
+    // tolerance, their pressure changes by about it between alternations
     fvim_frictional_info fi{};
-    rc = frictional_solve(c, H, Wn, o->mu_f, Qx, Qy, 1, tol_f, o->tol_contact, tol_f, o->max_contact, CERRUTI_MAX,
-                          T, warm, &fi);
+    const double tc = std::min(o->tol_contact, std::max(0.1 * tol_f, 1e-15));
+    rc = frictional_solve(c, H, Wn, o->mu_f, Qx, Qy, 1, tol_f, tc, tol_f, o->max_contact, CERRUTI_MAX, T, warm, &fi);
     if (rc) return rc;
     inf.contact_iters += fi.contact_iters + fi.tangential_iters;
     inf.kkt = fi.kkt_residual;
