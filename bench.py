@@ -530,7 +530,13 @@ def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver
             if dt > 0:
                 time.sleep(dt)
         ids.append(srv.submit(g, h, [r["pbar"]], precision="fp32_refined", opts=opts))
-    res = [srv.wait(i, (g["ny"], g["nx"])) for i, (_, g, _) in zip(ids, prepared)]
+    res = []
+    for k, (i, (r, g, _)) in enumerate(zip(ids, prepared)):
+        res.append(srv.wait(i, (g["ny"], g["nx"])))
+        if verbose:          # progress: one line per request, in submission order
+            print("request %d (%dx%dx%d) status %d at %.1f s" % (k, r["nx"], r["ny"], r["nz"], res[-1]["status"],
+                                                                  time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
