@@ -100,8 +100,9 @@ def parse():
     ap.add_argument("--solver", type=int, default=0, choices=[0, 1, 2],
                     help="solve/rough/area/serve: plasticity solver (0 DF-SANE, 1 Picard, 2 Newton-Krylov)")
     ap.add_argument("--krylov", type=int, default=0, help="Newton-Krylov: Arnoldi steps per Newton step (0 = 20)")
-    ap.add_argument("--coupling", type=int, default=0, choices=[0, 1],
-                    help="solve/rough/serve/request: 0 Algorithm 1 (relaxation or Anderson), 1 outer Newton-Krylov")
+    ap.add_argument("--coupling", type=int, default=0, choices=[0, 1, 2],
+                    help="solve/rough/serve/request: 0 Algorithm 1 (relaxation or Anderson), 1 outer Newton-Krylov, "
+                         "2 Algorithm 1 for 40 passes, then outer Newton-Krylov")
     ap.add_argument("--request-id", type=int, default=10,
                     help="request: index of the request of the serving stream (seed 2024) to solve alone")
     a = ap.parse_args()

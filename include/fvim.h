@@ -380,8 +380,11 @@ typedef struct {
                        /* |G(x) - x| decreases; same stopping test and      */
                        /* fixed point; inner solves always to tol_plastic   */
                        /* and tol_contact; max_outer bounds Newton steps;   */
-                       /* adds 12 nx ny nz + (coupling_krylov + 10) nx ny   */
-                       /* doubles                                           */
+                       /* 2: Algorithm 1 for at most 40 passes, then the    */
+                       /* Newton coupling from its last iterate (warm from  */
+                       /* its last pass); outer_iters counts both;          */
+                       /* 1 and 2 add 12 nx ny nz + (coupling_krylov + 10)  */
+                       /* nx ny doubles                                     */
   int coupling_krylov; /* GMRES steps per Newton step, 1..30 (0 = 10)       */
   int cerruti;         /* 1 (with mu_f > 0): the contact step couples the   */
                        /* normal and tangential problems through the        */

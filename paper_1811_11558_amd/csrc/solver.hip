@@ -1244,6 +1244,9 @@ static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, 
 // ------------------------------------------------------ Newton-Krylov
 static int krylov_dim(const fvim_ep_opts* o) { return o->krylov_dim > 0 ? o->krylov_dim : 20; }
 
+// coupling = 2: passes of Algorithm 1 before the outer Newton-Krylov
+// coupling takes over (most requests converge within them)
+constexpr int SWITCH_PASSES = 40;
 // outer Newton-Krylov: Krylov steps per Newton step, and its workspace
 static int coupling_dim(const fvim_ep_opts* o) { return o->coupling_krylov > 0 ? o->coupling_krylov : 10; }
 static size_t coupling_count(size_t V, size_t ns, const fvim_ep_opts* o) {
@@ -1255,7 +1258,7 @@ size_t krylov_footprint(const fvim_grid* g, const fvim_ep_opts* o) {
   const size_t V = (size_t)g->nx * g->ny * g->nz, ns = (size_t)g->nx * g->ny;
   size_t b = 0;
   if (o->solver == 2) b += sizeof(double) * (6 * V * (size_t)(krylov_dim(o) + 2) + (size_t)KMAX * (RB + 1));
-  if (o->coupling == 1) b += sizeof(double) * coupling_count(V, ns, o);
+  if (o->coupling >= 1) b += sizeof(double) * coupling_count(V, ns, o);
   return b;
 }
 
@@ -1777,7 +1780,7 @@ static int pass_map(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, Pla
 // final pass and pb, T its state (for the commit); inf.outer_iters counts
 // Newton steps, inf.outer_err is |G(x) - x| / |H0|.  *conv: converged.
 static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, PlastBufs& pb, PassBufs& q,
-                        double hn, double* dU, fvim_ep_info& inf, bool* conv) {
+                        double hn, const double* x0, double* dU, fvim_ep_info& inf, bool* conv) {
   SolverWork* w = c->sw;
   const size_t n = w->ns, V = w->V, n6 = 6 * V;
   hipStream_t st = c->stream;
@@ -1805,14 +1808,25 @@ static int outer_newton(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o,
     if (e == hipSuccess) e = hipMemcpyAsync(q.T, bT, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? FVIM_OK : fail_hip(e, "copy");
   };
-  // G(x) at x = 0
-  hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(NT), 0, st, x, n, 0.0);
-  int rc = pass_map(c, s, o, pb, q, x, Gx, false, inf);
+  // G(x) at x = x0 (warm from the pass that produced x0), else at x = 0
+  if (x0) {
+    e = hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail_hip(e, "copy");
+  } else {
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(NT), 0, st, x, n, 0.0);
+  }
+  int rc = pass_map(c, s, o, pb, q, x, Gx, x0 != nullptr, inf);
   if (rc) return rc;
+  double xn = 0.0;
+  if (x0) {
+    double xx[3];
+    if ((rc = sdot(c, x, x, xx))) return rc;
+    xn = xx[1];
+  }
   axpy(c, F, Gx, -1.0, x, n);
   double t3[3];
   if ((rc = sdot(c, F, Gx, t3))) return rc;
-  double fn = t3[1], gn = t3[2], xn = 0.0;
+  double fn = t3[1], gn = t3[2];
   *conv = fn / hn < o->tol_outer;
   int k = 0;
   const double fd_rel = 3e-7;
@@ -2046,7 +2060,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (!c || !h || !W_steps || !o || !s || !info) return fail(FVIM_EINVAL, "NULL argument");
   if (!s->eps_p || !s->ep || !s->sigma || !s->traction || !s->u3p) return fail(FVIM_EINVAL, "NULL state field");
   if (n_steps < 1 || !(o->relax > 0 && o->relax <= 1) || o->max_outer < 1 || o->anderson_m < 0 ||
-      o->coupling < 0 || o->coupling > 1 || o->coupling_krylov < 0 || o->coupling_krylov > 30 ||
+      o->coupling < 0 || o->coupling > 2 || o->coupling_krylov < 0 || o->coupling_krylov > 30 ||
       o->anderson_m > AA_MMAX || !(o->inner_rel >= 0) || o->solver < 0 || o->solver > 2 || o->krylov_dim < 0 ||
       o->krylov_dim > KMAX - 2 || !(o->mu_f >= 0) || !std::isfinite(o->mu_f) ||
       (o->mu_f > 0 && !(std::hypot(o->q_ratio[0], o->q_ratio[1]) < 1.0)) || o->cerruti < 0 || o->cerruti > 1 ||
@@ -2073,7 +2087,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
   if (o->solver == 2 && (rc = kry_ensure(c, krylov_dim(o)))) return rc;
   if (o->mu_f > 0 && (rc = friction_reserve(c))) return rc;
   if (o->adh_sigma0 > 0 && (rc = adh_ensure(c))) return rc;
-  if (o->coupling == 1 && (rc = cpl_ensure(c, o))) return rc;
+  if (o->coupling >= 1 && (rc = cpl_ensure(c, o))) return rc;
   // every buffer the operator applications of the solve use, sized now: no
   // device memory is freed or allocated while the solve runs
   if ((rc = operator_reserve(c, pb.dep, dT, pb.F))) return rc;
@@ -2108,11 +2122,14 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
     int aa_count = 0, aa_head = 0;
     if (o->coupling == 1) {
       PassBufs q{H0, H, T, dT, Wn};
-      rc = outer_newton(c, s, o, pb, q, hn, dU, inf, &conv);
+      rc = outer_newton(c, s, o, pb, q, hn, nullptr, dU, inf, &conv);
       if (rc) return cleanup(rc);
       if (!conv) return cleanup(fail(FVIM_ENOCONV, "outer Newton-Krylov: iteration limit reached"));
     }
-    for (k = 1; k <= o->max_outer && o->coupling != 1; ++k) {
+    // passes of the alternation: max_outer, or with coupling = 2 at most
+    // SWITCH_PASSES before the Newton coupling takes over
+    const int kmax = o->coupling == 1 ? 0 : o->coupling == 2 ? std::min(o->max_outer, SWITCH_PASSES) : o->max_outer;
+    for (k = 1; k <= kmax; ++k) {
       // inexact inner solves (plasticity, and the tangential contact with
       // friction) while the outer error is large; a pass that may end the
       // step is always solved to the full tolerances
@@ -2183,7 +2200,17 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       axpy(c, H, H0, -1.0, H, n);                         // H = H0 - relaxed
       if (conv) break;
     }
-    if (o->coupling != 1) inf.outer_iters = k > o->max_outer ? o->max_outer : k;
+    if (o->coupling != 1) inf.outer_iters = k > kmax ? kmax : k;
+    if (!conv && o->coupling == 2) {
+      // the Newton coupling from the alternation's next iterate (dUp),
+      // warm from its last pass; outer_iters counts passes and Newton steps
+      const int passes = inf.outer_iters;
+      PassBufs q{H0, H, T, dT, Wn};
+      rc = outer_newton(c, s, o, pb, q, hn, dUp, dU, inf, &conv);
+      if (rc) return cleanup(rc);
+      inf.outer_iters += passes;
+      if (!conv) return cleanup(fail(FVIM_ENOCONV, "outer Newton-Krylov: iteration limit reached"));
+    }
     if (!conv) return cleanup(fail(FVIM_ENOCONV, "Algorithm 1: outer iteration limit reached"));
     // state update: eps_p += d_eps_p, ep += d_ep, sigma <- sigma_(n+1), T_n <- T, U3p += dU
     e = launch_return_map(pb.x, s->sigma, s->ep, pb.dep, pb.dp, s->sigma, V, c->lam, c->mu, c->mat.sigma_y0,

@@ -474,13 +474,47 @@ def test_newton_coupling_reaches_the_stored_fixed_point(name, bound):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,bound", [("hertz_ep_16x16x8", 1e-11), ("hertz_friction_ep_16x16x8", 1e-11),
+                                        ("rough_ep_16x16x8", 1e-10)])
+def test_switched_coupling_reaches_the_stored_fixed_point(name, bound):
+    """coupling = 2: relaxed Algorithm 1 passes (these cases need 45-58 of
+    them) and, after 40, the outer Newton-Krylov coupling from the last
+    iterate, warm from the last pass, ending on the stored fixed point."""
+    import ast
+    from paper_1811_11558_amd import Context, EPOptions
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    sys.path.insert(0, gold)
+    from make_golden import CASES
+    c = CASES[name]
+    ref = np.load(os.path.join(gold, name + ".npz"))
+    meta = ast.literal_eval(str(ref["meta"][0]))
+    nx, ny, nz, lz = c["grid"]
+    g = grid_dict(nx, ny, nz, lz=lz)
+    m = c["mat"]
+    ctx = Context(g, m["E"], m["nu"], m["sigma_y0"], m["E_h"])
+    fr = (dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"]) if "friction" in c else {})
+    st = ctx.new_state()
+    infos = ctx.elastoplastic_solve(torch.from_numpy(ref["h"]).cuda(), list(ref["W"]), st,
+                                    EPOptions(tol_outer=1e-13, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15,
+                                              max_plastic=20000, coupling=2, **fr))
+    torch.cuda.synchronize()
+    _say(name, "passes + newton steps", [i["outer_iters"] for i in infos], "oracle passes", meta["outer"])
+    for i, passes in zip(infos, meta["outer"]):
+        assert i["outer_err"] < 1e-13 and 40 < i["outer_iters"] < passes + 10
+    for k in ("eps_p", "ep", "sigma", "traction", "u3p"):
+        err = _rel(st[k].cpu().numpy(), ref[k])
+        _say(k, err)
+        assert err < bound, (k, err)
+    ctx.close()
+
+
 def test_newton_coupling_options_are_checked():
     from paper_1811_11558_amd import EPOptions, FvimError
     g = grid_dict(8, 8, 4, lz=0.2)
     ctx = _ctx(g)
     st = ctx.new_state()
     h = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
-    for bad in (dict(coupling=2), dict(coupling=1, coupling_krylov=31), dict(coupling=-1)):
+    for bad in (dict(coupling=3), dict(coupling=1, coupling_krylov=31), dict(coupling=-1)):
         with pytest.raises(FvimError):
             ctx.elastoplastic_solve(h, [0.01], st, EPOptions(**bad))
     # the flat surface: converged at the first pass, no Newton step
