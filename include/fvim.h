@@ -380,8 +380,10 @@ typedef struct {
                        /* |G(x) - x| decreases; same stopping test and      */
                        /* fixed point; inner solves always to tol_plastic   */
                        /* and tol_contact; max_outer bounds Newton steps;   */
-                       /* 2: Algorithm 1 for at most 40 passes, then the    */
-                       /* Newton coupling from its last iterate (warm from  */
+                       /* 2: Algorithm 1 until the passes it still needs,   */
+                       /* extrapolated from its error's rate over the last  */
+                       /* 10 passes (from pass 20 on), exceed 100; then the */
+                       /* Newton coupling from its next iterate (warm from  */
                        /* its last pass); outer_iters counts both;          */
                        /* 1 and 2 add 12 nx ny nz + (coupling_krylov + 10)  */
                        /* nx ny doubles                                     */

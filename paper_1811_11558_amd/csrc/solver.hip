@@ -1244,9 +1244,12 @@ static int fixed_point(fvim_ctx* c, const fvim_state* s, const fvim_ep_opts* o, 
 // ------------------------------------------------------ Newton-Krylov
 static int krylov_dim(const fvim_ep_opts* o) { return o->krylov_dim > 0 ? o->krylov_dim : 20; }
 
-// coupling = 2: passes of Algorithm 1 before the outer Newton-Krylov
-// coupling takes over (most requests converge within them)
-constexpr int SWITCH_PASSES = 40;
+// coupling = 2: Algorithm 1 hands over to the outer Newton-Krylov coupling
+// once the passes it still needs, extrapolated from the error's rate over
+// the last SWITCH_WINDOW passes, exceed SWITCH_LEFT (about what the Newton
+// phase costs in passes); checked from pass SWITCH_FIRST on
+constexpr int SWITCH_FIRST = 20, SWITCH_WINDOW = 10;
+constexpr double SWITCH_LEFT = 100.0;
 // outer Newton-Krylov: Krylov steps per Newton step, and its workspace
 static int coupling_dim(const fvim_ep_opts* o) { return o->coupling_krylov > 0 ? o->coupling_krylov : 10; }
 static size_t coupling_count(size_t V, size_t ns, const fvim_ep_opts* o) {
@@ -2126,9 +2129,10 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       if (rc) return cleanup(rc);
       if (!conv) return cleanup(fail(FVIM_ENOCONV, "outer Newton-Krylov: iteration limit reached"));
     }
-    // passes of the alternation: max_outer, or with coupling = 2 at most
-    // SWITCH_PASSES before the Newton coupling takes over
-    const int kmax = o->coupling == 1 ? 0 : o->coupling == 2 ? std::min(o->max_outer, SWITCH_PASSES) : o->max_outer;
+    // passes of the alternation (none with coupling = 1)
+    const int kmax = o->coupling == 1 ? 0 : o->max_outer;
+    std::vector<double> errs;
+    bool to_newton = false;
     for (k = 1; k <= kmax; ++k) {
       // inexact inner solves (plasticity, and the tangential contact with
       // friction) while the outer error is large; a pass that may end the
@@ -2164,6 +2168,14 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
       conv = err < o->tol_outer && exact;
       inf.outer_err = err;
       inf.outer_iters = k;
+      if (o->coupling == 2 && !conv) {
+        errs.push_back(err);
+        if (k >= SWITCH_FIRST) {
+          const double r = err / errs[errs.size() - 1 - SWITCH_WINDOW];
+          const double left = r < 1.0 ? SWITCH_WINDOW * std::log(o->tol_outer / err) / std::log(r) : INFINITY;
+          to_newton = left > SWITCH_LEFT;
+        }
+      }
       if (aam > 0) {
         // x = dUp, f = G(x) - x; history update, least squares, step
         axpy(c, fres, dU, -1.0, dUp, n);
@@ -2185,6 +2197,7 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
         }
         hipLaunchKernelGGL(k_aa_step, dim3(nblocks(n)), dim3(NT), 0, st, dUp, fres, aX, aF, co, me, o->relax, n);
         axpy(c, H, H0, -1.0, dUp, n);                     // H = H0 - x_(k+1)
+        if (to_newton) break;
         continue;
       }
       // relaxed surface correction, H = H0 - relaxed
@@ -2198,10 +2211,10 @@ int elastoplastic_solve(fvim_ctx* c, const double* h, const double* W_steps, int
         if (e != hipSuccess) return cleanup(fail_hip(e, "copy"));
       }
       axpy(c, H, H0, -1.0, H, n);                         // H = H0 - relaxed
-      if (conv) break;
+      if (conv || to_newton) break;
     }
     if (o->coupling != 1) inf.outer_iters = k > kmax ? kmax : k;
-    if (!conv && o->coupling == 2) {
+    if (to_newton) {
       // the Newton coupling from the alternation's next iterate (dUp),
       // warm from its last pass; outer_iters counts passes and Newton steps
       const int passes = inf.outer_iters;
