@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--k-cut", type=int, default=0, help="rough: cut-off wavenumber (0 = nx / 4)")
     ap.add_argument("--load", type=float, default=1e-4, help="rough: final total load W (E L^2 units)")
     ap.add_argument("--compare", action="store_true",
-                    help="rough: solve in float64 and in FP32_REFINED and report the differences")
+                    help="rough, serve: solve in float64 and in FP32_REFINED and report the differences")
     ap.add_argument("--anderson", type=int, default=5,
                     help="solve/serve/rough: Anderson depth of the outer fixed point (0 = Algorithm 1 relaxation)")
     ap.add_argument("--warm", type=int, default=1,
@@ -222,7 +222,7 @@ def bench_copy(a):
 
 
 def bench_batch(a):
-    """The fused operator (float64) on eight grids of different sizes
+    """The fused operator (float64, or --precision) on eight grids of different sizes
     (32^2 x 8 ... 128^2 x 64): one application per context in turn against
     one batched application (one launch per stage for all grids) and against
     the persistent batched application (one cooperative launch for every
@@ -237,7 +237,7 @@ def bench_batch(a):
     ctxs, eps, ts = [], [], []
     for i, (nx, ny, nz) in enumerate(shapes):
         g = grid_dict(nx, ny, nz, 1.0, 1.0, 0.25)
-        ctxs.append(Context(g, 1.0, 0.3, stream=stream))
+        ctxs.append(Context(g, 1.0, 0.3, stream=stream, precision=a.precision))
         eps.append(torch.from_numpy(filtered_eigenstrain(g, seed=i)).to(dev))
         ts.append(torch.from_numpy(filtered_traction(g, seed=1000 + i)).to(dev))
     vox = sum(nx * ny * nz for nx, ny, nz in shapes)
@@ -270,7 +270,8 @@ def bench_batch(a):
                       "unit": "voxel-updates/s", "higher_is_better": True, "n_gpus": 1, "steps": a.steps,
                       "ms_per_batch": res["batched"], "ms_sequential": res["sequential"],
                       "ms_persistent": res["persistent"], "speedup": res["sequential"] / res["batched"],
-                      "speedup_persistent": res["sequential"] / res["persistent"], "dtype": "f64", "data": "synthetic",
+                      "speedup_persistent": res["sequential"] / res["persistent"],
+                      "dtype": "f64" if a.precision == "fp64" else "f32 (float64 mean mode)", "data": "synthetic",
                       "config": {"workload": "fused operator on 8 grids: " +
                                  ", ".join("%dx%dx%d" % s_ for s_ in shapes)}}))
 
@@ -502,14 +503,15 @@ def bench_solve(a):
 
 
 def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver=0, krylov=0, friction=None,
-              verbose=False, coupling=0):
+              verbose=False, coupling=0, precision="fp32_refined", keep=None):
     """Seeded Poisson-arrival elastoplastic contact solves of mixed grids
     (64^2 x 32, 128^2 x 64, 256^2 x 64, 512^2 x 96; rough surfaces with Hurst
     exponent in [0.5, 0.9], mean pressure in [0.005, 0.05] E) through the
     batching server; one load step each, FP32 kernels with float64
-    refinement, outer tolerance 1e-7.  rate = arrivals per second (0: all
-    at once).  Returns the result record (latencies over the requests that
-    succeeded; failures listed apart)."""
+    refinement (or precision), outer tolerance 1e-7.  rate = arrivals per
+    second (0: all at once).  Returns the result record (latencies over the
+    requests that succeeded; failures listed apart); keep, a list, receives
+    each request's (p, u3p) host arrays (None where it failed)."""
     from paper_1811_11558_amd import Server, EPOptions
     from synth import grid_dict, poisson_requests, rough_surface
     reqs = poisson_requests(n=n_requests, rate=rate if rate > 0 else 1e9, seed=2024)
@@ -530,10 +532,12 @@ def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver
             dt = r["arrival"] - (time.perf_counter() - t0)
             if dt > 0:
                 time.sleep(dt)
-        ids.append(srv.submit(g, h, [r["pbar"]], precision="fp32_refined", opts=opts))
+        ids.append(srv.submit(g, h, [r["pbar"]], precision=precision, opts=opts))
     res = []
     for k, (i, (r, g, _)) in enumerate(zip(ids, prepared)):
         res.append(srv.wait(i, (g["ny"], g["nx"])))
+        if keep is not None:
+            keep.append((res[-1]["p"], res[-1]["u3p"]) if res[-1]["status"] == 0 else None)
         if verbose:          # progress: one line per request, in submission order
             print("request %d (%dx%dx%d) status %d at %.1f s" % (k, r["nx"], r["ny"], r["nz"], res[-1]["status"],
                                                                   time.perf_counter() - t0),
@@ -564,7 +568,7 @@ def serve_run(n_requests, rate, slots, anderson=5, warm=1, inner_rel=0.1, solver
             "failures": [d for d in detail if d["status"] != 0],
             "failure_latency_s": [d["latency_s"] for d in detail if d["status"] != 0],
             "config": {"workload": "Poisson-arrival mixed-grid solves", "slots": slots, "rate_per_s": rate,
-                       "precision": "fp32_refined", "anderson": anderson, "warm_start": warm,
+                       "precision": precision, "anderson": anderson, "warm_start": warm,
                        "inner_rel": inner_rel, "solver": SOLVER_NAMES[solver], "coupling": coupling}}
 
 
@@ -607,19 +611,48 @@ def bench_request(a):
 def bench_serve(a):
     """The serving workload (serve_run) with the command-line settings:
     --requests, --rate, --slots, --anderson, --warm, --inner-rel, --solver,
-    --friction."""
-    r = serve_run(a.requests, a.rate, a.slots, a.anderson, a.warm, a.inner_rel, a.solver, a.krylov,
-                  friction_opts(a), verbose=True, coupling=a.coupling)
-    out = {"metric": "served solves/s", "value": r["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
-           "n_gpus": 1}
-    out.update(r)
-    print(json.dumps(out))
+    --friction, --coupling.  With --compare: the same stream served in
+    float64 and in FP32_REFINED, and the relative L2 difference of each
+    request's pressure and U3p between the two."""
+    kw = dict(verbose=True, coupling=a.coupling)
+    if not a.compare:
+        r = serve_run(a.requests, a.rate, a.slots, a.anderson, a.warm, a.inner_rel, a.solver, a.krylov,
+                      friction_opts(a), **kw)
+        out = {"metric": "served solves/s", "value": r["solves_per_s"], "unit": "solves/s", "higher_is_better": True,
+               "n_gpus": 1}
+        out.update(r)
+        print(json.dumps(out))
+        return
+    runs, arrays = {}, {}
+    for prec in ("fp64", "fp32_refined"):
+        arrays[prec] = []
+        runs[prec] = serve_run(a.requests, a.rate, a.slots, a.anderson, a.warm, a.inner_rel, a.solver, a.krylov,
+                               friction_opts(a), precision=prec, keep=arrays[prec], **kw)
+        print("%s: %.3f solves/s" % (prec, runs[prec]["solves_per_s"]), file=sys.stderr, flush=True)
+    dp, du = [], []
+    for x, y in zip(arrays["fp64"], arrays["fp32_refined"]):
+        if x is None or y is None:
+            continue
+        dp.append(float(np.linalg.norm(y[0] - x[0]) / max(np.linalg.norm(x[0]), 1e-300)))
+        du.append(float(np.linalg.norm(y[1] - x[1]) / max(np.linalg.norm(x[1]), 1e-300)))
+    same_area = sum(int(np.array_equal(x[0] > 0, y[0] > 0)) for x, y in zip(arrays["fp64"], arrays["fp32_refined"])
+                    if x is not None and y is not None)
+    print(json.dumps({"metric": "served solves/s, float64 against FP32_REFINED", "unit": "solves/s",
+                      "higher_is_better": True, "n_gpus": 1,
+                      "fp64": {k: v for k, v in runs["fp64"].items() if k != "failures"},
+                      "fp32_refined": {k: v for k, v in runs["fp32_refined"].items() if k != "failures"},
+                      "speedup": runs["fp32_refined"]["solves_per_s"] / runs["fp64"]["solves_per_s"],
+                      "compared": len(dp), "p_rel_l2_max": max(dp or [float("nan")]),
+                      "p_rel_l2_median": float(np.median(dp)) if dp else float("nan"),
+                      "u3p_rel_l2_max": max(du or [float("nan")]),
+                      "u3p_rel_l2_median": float(np.median(du)) if du else float("nan"),
+                      "same_contact_set": same_area}))
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it "
+        print("bench.py measures one GPU; runs on several GPUs are not supported "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     if a.workload == "copy":
