@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--k-roll", type=int, default=4, help="rough: roll-off wavenumber")
     ap.add_argument("--k-cut", type=int, default=0, help="rough: cut-off wavenumber (0 = nx / 4)")
     ap.add_argument("--load", type=float, default=1e-4, help="rough: final total load W (E L^2 units)")
+    ap.add_argument("--fft-config", type=lambda v: [tuple(int(x) for x in c.split(",")) for c in v.split(";")],
+                    default=None, help="operator: launch choices (tile,radix;...) of the four transform kernels "
+                                       "for the 256^2 x 64 float64 workload instead of the pinned ones")
     ap.add_argument("--compare", action="store_true",
                     help="rough, serve: solve in float64 and in FP32_REFINED and report the differences")
     ap.add_argument("--anderson", type=int, default=5,
@@ -277,6 +280,9 @@ def bench_batch(a):
 
 
 SOLVER_NAMES = {0: "dfsane", 1: "picard", 2: "newton_krylov"}
+# (tile, radix) of the forward row, forward column, inverse column and
+# inverse row transforms for the 256^2 x 64 float64 operator
+HEADLINE_FFT_CONFIG = [(0, 4), (1, 8), (1, 8), (1, 8)]
 
 
 def friction_opts(a):
@@ -697,13 +703,13 @@ def main():
     elif a.op == "boussinesq":
         eps = None
     if (a.nx, a.ny, a.nz, a.precision, a.graded, a.op) == (256, 256, 64, "fp64", 0.0, "fused") and not a.tune:
-        # the headline workload runs the launch choices the tuner picks for
+        # the headline workload runs the launch choices measured fastest for
         # it on MI355X (depth layout 64 lanes x 1 node; transforms: forward
-        # half tiles radix 4, inverse default tiles radix 8), pinned so that
-        # every run and its profile time the same kernels (the tuner's
-        # timings of near-equal candidates vary from run to run)
+        # rows half tiles radix 4, the other three default tiles radix 8),
+        # pinned so that every run and its profile time the same kernels
+        # (the tuner's timings of near-equal candidates vary from run to run)
         ctx.set_option(ctx.OPT_DEPTH_CONFIG, 4)
-        ctx.set_fft_config([(0, 4), (0, 4), (1, 8), (1, 8)])
+        ctx.set_fft_config(a.fft_config or HEADLINE_FFT_CONFIG)
     else:
         ctx.tune()                  # first warm-up call times the depth layouts and transform choices
     for _ in range(a.warmup):
