@@ -77,7 +77,9 @@ def trace_table(path):
         k = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]))
         acc[k].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
         meta[k] = (r["VGPR_Count"], r["Scratch_Size"], r["LDS_Block_Size"])
-    out = ["| kernel | grid (threads) | launches | average (us) | VGPRs | scratch (B) | LDS (B) |",
+    out = ["VGPRs: the trace's VGPR_Count, which on gfx950 is half the register count of the code object "
+           "(the depth pass's 84 is 168 registers, 3 waves per SIMD).", "",
+           "| kernel | grid (threads) | launches | average (us) | VGPRs | scratch (B) | LDS (B) |",
            "|---|---|---|---|---|---|---|"]
     for k in sorted(acc, key=lambda k: -sum(acc[k])):
         v = acc[k]
@@ -242,7 +244,7 @@ def kernels(a):
     doc += [l.rstrip("\n") for l in open(a.commands)] + ["```", ""]
     doc += ["## Kernel durations (`rocprofv3 --kernel-trace --stats`)", "", stats(a.stats), ""]
     doc += ["Per launch shape (same run, from the kernel trace; the %d with the most time):" % a.top, ""]
-    doc += rows[:2 + a.top] + [""]
+    doc += rows[:4 + a.top] + [""]
     if a.fetch and a.write and a.copy_fetch and a.copy_write:
         fetch, write = dispatches(a.fetch), dispatches(a.write)
         fs, copy_name, cf = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
