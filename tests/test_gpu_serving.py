@@ -140,27 +140,37 @@ def test_requests_with_depth_nodes_identical_alone_and_in_mix():
 
 def test_served_results_match_the_stored_oracle_cases():
     """The stored oracle cases (Hertz, the rough-surface experiment's setting,
-    graded depth nodes, Coulomb friction; written by
-    tests/golden/make_golden.py from the oracle alone) submitted to the
-    server in one mix with rough requests of other grids, the Hertz case
-    twice so that a slot reuses its context: the served pressure and
-    plastic surface displacement equal the oracle's within 1e-11."""
+    graded depth nodes, Coulomb friction, Cerruti-coupled friction under the
+    outer Newton coupling, Goodman friction under the switched coupling
+    with a slow relaxation, adhesion; written by tests/golden/make_golden.py
+    from the oracle alone) submitted to the server in one mix with rough
+    requests of other grids, the Hertz case twice so that a slot reuses its
+    context: the served pressure and plastic surface displacement equal the
+    oracle's within 1e-11."""
     import os
     from paper_1811_11558_amd import EPOptions, Server
     gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
     sys.path.insert(0, gold)
     from make_golden import CASES
-    cases = ["hertz_ep_16x16x8", "rough_ep_16x16x8", "hertz_graded_ep_16x16x8", "hertz_friction_ep_16x16x8",
-             "hertz_ep_16x16x8"]
+    cases = [("hertz_ep_16x16x8", {}), ("rough_ep_16x16x8", {}), ("hertz_graded_ep_16x16x8", {}),
+             ("hertz_friction_ep_16x16x8", {}), ("hertz_ep_16x16x8", {}),
+             ("hertz_cerruti_ep_16x16x8", dict(coupling=1, tol_outer=1e-13)),
+             ("hertz_friction_ep_16x16x8", dict(coupling=2, relax=0.05, tol_outer=1e-13)),
+             ("hertz_adhesion_ep_16x16x8", dict(tol_contact=1e-14))]
     srv = Server(hbm_budget_bytes=8 << 30, max_slots=3)
     ids = []
-    for i, name in enumerate(cases):
+    for i, (name, extra) in enumerate(cases):
         c = CASES[name]
         ref = np.load(os.path.join(gold, name + ".npz"))
         nx, ny, nz, lz = c["grid"]
         g = grid_dict(nx, ny, nz, lz=lz)
-        fr = dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"]) if "friction" in c else {}
-        opts = EPOptions(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000, **fr)
+        fr = (dict(mu_f=c["friction"]["mu_f"], q_ratio=c["friction"]["q_ratio"],
+                   cerruti=int(c["friction"].get("cerruti", False))) if "friction" in c else {})
+        if "adhesion" in c:
+            fr["adhesion"] = tuple(c["adhesion"])
+        kw = dict(tol_outer=1e-11, relax=0.3, tol_plastic=1e-13, tol_contact=1e-15, max_plastic=20000, **fr)
+        kw.update(extra)
+        opts = EPOptions(**kw)
         m = c["mat"]
         ids.append((name, ref, g, srv.submit(g, ref["h"], list(ref["W"]), E=m["E"], nu=m["nu"],
                                              sigma_y0=m["sigma_y0"], E_h=m["E_h"], opts=opts,
