@@ -71,7 +71,9 @@ __global__ __launch_bounds__(NT) void k_x_c2r(const cpx<T>* __restrict__ in, Out
                                              const double* __restrict__ padd, ResidEpilogue ep, int nts) {
   __shared__ cpx<T> buf[c2r_lds_elems<T, LOGN, TILE>()];
   __shared__ double red[NT / 64];
-  x_c2r_body<T, LOGN, TILE, RADIX>(buf, red, blockIdx.x, in, seg, ny, R, scale, tw, padd, ep, nts != 0);
+  // the last planes first: the inverse column transform wrote them last
+  x_c2r_body<T, LOGN, TILE, RADIX>(buf, red, (int)(gridDim.x - 1 - blockIdx.x), in, seg, ny, R, scale, tw, padd, ep,
+                                   nts != 0);
 }
 
 template <typename T>

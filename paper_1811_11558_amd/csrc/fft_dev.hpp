@@ -367,8 +367,11 @@ __device__ __forceinline__ void y_inv_body(cpx<T>* buf, int lb, const cpx<T>* __
   static_assert((B * N) % NT == 0, "tile must be a multiple of the block");
   constexpr int ld = N + 1;
   const int npb = (NP + B - 1) / B;
-  const int kx = lb / npb;
-  const int p0 = (lb - kx * npb) * B;
+  // blocks run plane group by plane group (kx fastest), so the inverse row
+  // transform, which runs its blocks from the last plane back, finds the
+  // planes written last still in the last-level cache
+  const int kx = lb % kxh;
+  const int p0 = (lb / kxh) * B;
   const int nb = min(B, NP - p0);
   constexpr int MV = B * N / NT;
   // consecutive lanes read consecutive planes of one ky (runs of nb
