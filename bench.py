@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--fft-config", type=lambda v: [tuple(int(x) for x in c.split(",")) for c in v.split(";")],
                     default=None, help="operator: launch choices (tile,radix;...) of the four transform kernels "
                                        "for the 256^2 x 64 float64 workload instead of the pinned ones")
+    ap.add_argument("--depth-config", type=int, default=None,
+                    help="operator: depth-pass layout id for the 256^2 x 64 float64 workload instead of the pinned one")
     ap.add_argument("--compare", action="store_true",
                     help="rough, serve: solve in float64 and in FP32_REFINED and report the differences")
     ap.add_argument("--anderson", type=int, default=5,
@@ -708,7 +710,7 @@ def main():
         # rows half tiles radix 4, the other three default tiles radix 8),
         # pinned so that every run and its profile time the same kernels
         # (the tuner's timings of near-equal candidates vary from run to run)
-        ctx.set_option(ctx.OPT_DEPTH_CONFIG, 4)
+        ctx.set_option(ctx.OPT_DEPTH_CONFIG, 4 if a.depth_config is None else a.depth_config)
         ctx.set_fft_config(a.fft_config or HEADLINE_FFT_CONFIG)
     else:
         ctx.tune()                  # first warm-up call times the depth layouts and transform choices
