@@ -170,13 +170,13 @@ def measured_traffic(stage, nx, ny, nz, precision):
     return r["bytes_per_launch"]
 
 
-def cpu_baseline(g, eps, t, nmodes_sample):
+def cpu_baseline(g, eps, t, nmodes_sample, repeats=3):
     """The oracle, as it stands, on two samples of the in-plane modes.
 
     One oracle call costs a fixed part (full-field forward DFT, output
     arrays) plus a part linear in the number of modes evaluated; the two
-    samples fix both and the full application time is extrapolated to all
-    modes."""
+    samples (each timed repeats times, the median kept) fix both and the
+    full application time is extrapolated to all modes."""
     from oracle import operators as ora
     try:
         from threadpoolctl import threadpool_info
@@ -191,9 +191,12 @@ def cpu_baseline(g, eps, t, nmodes_sample):
     for n in sizes:
         pick = rng.choice(len(allm), size=min(n, len(allm)), replace=False)
         modes = [allm[i] for i in sorted(pick)]
-        t0 = time.perf_counter()
-        ora.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes, direct_dft=False)
-        times.append(time.perf_counter() - t0)
+        rep = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            ora.apply(g, 1.0, 0.3, eps_p=eps, traction=t, modes=modes, direct_dft=False)
+            rep.append(time.perf_counter() - t0)
+        times.append(float(np.median(rep)))
     per_mode = max((times[1] - times[0]) / (sizes[1] - sizes[0]), 0.0)
     fixed = max(times[0] - per_mode * sizes[0], 0.0)
     t_full = fixed + per_mode * len(allm)
@@ -201,9 +204,9 @@ def cpu_baseline(g, eps, t, nmodes_sample):
             "kind": "oracle",
             "sample": "oracle fused application on %d and %d of the %d in-plane modes of the same "
                       "%dx%dx%d workload (dense O(nz^2) depth sums per mode; full-field forward DFT "
-                      "included) took %.1f s and %.1f s; full application extrapolated linearly in the "
-                      "mode count: %.1f s" % (sizes[0], sizes[1], len(allm), nx, ny, nz, times[0],
-                                               times[1], t_full)}
+                      "included) took %.1f s and %.1f s (medians of %d runs each); full application "
+                      "extrapolated linearly in the mode count: %.1f s"
+                      % (sizes[0], sizes[1], len(allm), nx, ny, nz, times[0], times[1], repeats, t_full)}
 
 
 def bench_copy(a):
